@@ -1,0 +1,121 @@
+"""Pins of the oracle's greedy policy: brute-force argmax, tie rule on mirror-symmetric
+grids, monotone FOM (Sec. IV), T1 = T2 trajectories, rank-k selection rules."""
+import numpy as np
+import pytest
+
+from oracle import greens, greedy, state
+import workloads as W
+
+
+def test_greedy_matches_brute_force_argmax():
+    p = W.tiny(4, 5, n_mon=3, cand_mask=W.MASK_BOTH, steps=6)
+    G0 = greens.build_G0(p)
+    traj = greedy.greedy(p, tier="T1")
+    idx = np.zeros(p.n, np.uint8)
+    for s in traj.steps:
+        F = state.brute_force_scores(p, idx, G0)
+        _, E = state.dense_state(p, state.eps_of(p, idx), G0)
+        fom = state.fom_of_state(p, E)
+        Fstar = F.max()
+        assert Fstar > fom
+        # chosen candidate is within the tie band of the brute-force max and is its lowest index
+        band = np.flatnonzero(F.ravel() >= Fstar * (1 - p.tau))
+        assert band[0] == s.pixel * F.shape[1] + s.eps_idx
+        idx[s.pixel] = s.eps_idx
+        _, E = state.dense_state(p, state.eps_of(p, idx), G0)
+        assert abs(state.fom_of_state(p, E) - s.fom) <= 1e-12 * s.fom
+
+
+def test_greedy_fom_monotone_and_prediction_exact():
+    p = W.tiny(6, 6, n_mon=4, cand_mask=W.MASK_BOTH, steps=25)
+    traj = greedy.greedy(p, tier="T1")
+    foms = [traj.fom0] + [s.fom for s in traj.steps]
+    assert all(b > a for a, b in zip(foms, foms[1:]))
+    for s in traj.steps:
+        assert abs(s.fom_pred - s.fom) <= 1e-11 * s.fom
+
+
+def test_mirror_symmetry_gives_exact_ties_and_lowest_index_wins():
+    p = W.tiny(4, 6, n_mon=4, cand_mask=W.MASK_BOTH)
+    N = p.n
+    idx = W.mirror_symmetric_eps_idx(p, 0.3, seed=2)
+    G, E = state.dense_state(p, state.eps_of(p, idx))
+    F = greedy.scores_closed_form(p, E, np.diagonal(G[:N]), G[N + p.fom_monitor], idx)
+    # mirror symmetry x -> -x maps pixel (iy, ix) to (iy, nx-1-ix); scores are equal up to rounding
+    Fm = F.reshape(p.ny, p.nx, -1)[:, ::-1, :].reshape(N, -1)
+    fin = np.isfinite(F)
+    assert np.array_equal(fin, np.isfinite(Fm))
+    assert np.allclose(F[fin], Fm[fin], rtol=1e-12, atol=0)
+    pick = greedy.select_greedy(F, state.fom_of_state(p, E), p.tau)
+    assert pick is not None and pick.n_tied >= 2
+    assert pick.pixel % p.nx < p.nx / 2          # lowest index of the mirror pair
+
+
+def test_select_greedy_tie_band_and_stop_rule():
+    F = np.array([[-np.inf, 1.0], [-np.inf, 1.0 + 5e-10], [-np.inf, 0.5]])
+    pk = greedy.select_greedy(F, 0.9, 1e-9)
+    assert (pk.pixel, pk.eps_idx, pk.n_tied) == (0, 1, 2)
+    assert greedy.select_greedy(F, 1.0 + 5e-10, 1e-9) is None     # no strict improvement
+    assert greedy.select_greedy(np.full((3, 2), -np.inf), 0.1, 1e-9) is None
+
+
+def test_T1_and_T2_trajectories_agree():
+    p = W.tiny(8, 8, n_mon=4, cand_mask=W.MASK_BOTH, steps=12)
+    t1 = greedy.greedy(p, tier="T1")
+    t2 = greedy.greedy(p, tier="T2")
+    assert t1.pixels() == t2.pixels()
+    for a, b in zip(t1.steps, t2.steps):
+        assert abs(a.fom - b.fom) <= 1e-11 * a.fom
+    assert np.allclose(t1.E, t2.E, rtol=0, atol=1e-11)
+
+
+def test_rank_k_selection_rules():
+    p = W.tiny(12, 12, n_mon=4, cand_mask=W.MASK_BOTH, rank_k=5, min_spacing=3)
+    N = p.n
+    idx = W.random_eps_idx(p, 0.2, seed=3)
+    G, E = state.dense_state(p, state.eps_of(p, idx))
+    fom = state.fom_of_state(p, E)
+    F = greedy.scores_closed_form(p, E, np.diagonal(G[:N]), G[N + p.fom_monitor], idx)
+    picks = greedy.select_rank_k(F, fom, p.tau, 5, 3, p.nx)
+    assert 1 <= len(picks) <= 5
+    assert picks[0].pixel == greedy.select_greedy(F, fom, p.tau).pixel
+    for i, a in enumerate(picks):
+        assert a.fom_new > fom
+        for b in picks[:i]:
+            d = max(abs(a.pixel // p.nx - b.pixel // p.nx), abs(a.pixel % p.nx - b.pixel % p.nx))
+            assert d >= 3
+    # scores are non-increasing along the picks (each is the best still eligible)
+    vals = [pk.fom_new for pk in picks]
+    assert all(b <= a * (1 + p.tau) for a, b in zip(vals, vals[1:]))
+
+
+def test_rank_k_trajectory_joint_state_is_exact():
+    p = W.tiny(10, 10, n_mon=4, cand_mask=W.MASK_BOTH, rank_k=4, min_spacing=3, steps=3)
+    tr = greedy.rank_k_trajectory(p, tier="T1")
+    idx = np.zeros(p.n, np.uint8)
+    for group in tr.steps:
+        for s in group:
+            idx[s.pixel] = s.eps_idx
+    _, E = state.dense_state(p, state.eps_of(p, idx))
+    assert abs(state.fom_of_state(p, E) - tr.steps[-1][0].fom) <= 1e-12 * state.fom_of_state(p, E)
+
+
+def test_replay_certifies_own_sequence():
+    p = W.tiny(6, 6, n_mon=4, cand_mask=W.MASK_BOTH, steps=8)
+    tr = greedy.greedy(p, tier="T1")
+    rep = greedy.replay(p, [(s.pixel, s.eps_idx) for s in tr.steps], tier="T2")
+    for r, s in zip(rep, tr.steps):
+        assert r["oracle_pixel"] == s.pixel
+        assert abs(r["F_taken"] - r["Fstar"]) <= 1e-9 * r["Fstar"]
+
+
+def test_stored_square32_trajectory_reproduced_by_flipped_set_tier():
+    """The stored 32x32 trajectory (written by tier T1) is reproduced by tier T2."""
+    import json, os
+    path = os.path.join(os.path.dirname(__file__), "golden", "square32_fp64.json")
+    gold = json.load(open(path))
+    p = W.SMALL_32
+    tr = greedy.greedy(p, tier="T2")
+    assert [s.pixel for s in tr.steps] == [s["pixel"] for s in gold["steps"]]
+    for a, b in zip(tr.steps, gold["steps"]):
+        assert abs(a.fom - b["fom"]) <= 1e-11 * b["fom"]

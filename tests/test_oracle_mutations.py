@@ -1,0 +1,115 @@
+"""Plant plausible mistakes in the oracle (on the CPU) and check that a pin catches each.
+
+Each case patches one oracle function with a typical slip (dropped term, wrong
+sign, transposed operand, wrong tie direction) and re-runs the relevant pin
+body; the pin must fail.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from oracle import greens, greedy, state
+import workloads as W
+
+
+def _self_term_pin_holds():
+    k0 = 2 * math.pi
+    h = 0.05
+    a = h / math.sqrt(math.pi)
+    re = integrate.quad(lambda r: 2 * math.pi * r * greens.g2d(r, k0).real, 0, a, limit=200)[0]
+    im = integrate.quad(lambda r: 2 * math.pi * r * greens.g2d(r, k0).imag, 0, a, limit=200)[0]
+    st = greens.self_term(h, k0)
+    return abs(st - complex(re, im)) <= 1e-8 * abs(st)
+
+
+def _dense_pins_hold():
+    p = W.tiny(4, 5, n_mon=2)
+    eps = state.eps_of(p, W.random_eps_idx(p, 0.4, 1))
+    N = p.n
+    G0 = greens.build_G0(p)
+    G, _ = state.dense_state(p, eps, G0)
+    a = greens.alpha_of(p, eps)
+    res = (np.eye(N) - G0[:N] * a[None, :]) @ G[:N] - G0[:N]
+    ok_res = np.linalg.norm(res) <= 1e-12 * np.linalg.norm(G0[:N])
+    ok_sym = np.linalg.norm(G[:N] - G[:N].T) <= 1e-12 * np.linalg.norm(G[:N])
+    return ok_res and ok_sym
+
+
+def _score_pin_holds():
+    p = W.tiny(3, 4, n_mon=2)
+    idx = W.random_eps_idx(p, 0.4, 2)
+    G, E = state.dense_state(p, state.eps_of(p, idx))
+    N = p.n
+    F0 = state.brute_force_scores(p, idx)
+    F1 = greedy.scores_closed_form(p, E, np.diagonal(G[:N]), G[N + p.fom_monitor], idx)
+    fin = np.isfinite(F0)
+    return np.allclose(F1[fin], F0[fin], rtol=1e-10, atol=0)
+
+
+def _mirror_tie_pin_holds():
+    p = W.tiny(4, 6, n_mon=4)
+    idx = W.mirror_symmetric_eps_idx(p, 0.3, seed=2)
+    G, E = state.dense_state(p, state.eps_of(p, idx))
+    N = p.n
+    F = greedy.scores_closed_form(p, E, np.diagonal(G[:N]), G[N + p.fom_monitor], idx)
+    pick = greedy.select_greedy(F, state.fom_of_state(p, E), p.tau)
+    return pick.pixel % p.nx < p.nx / 2
+
+
+def test_unpatched_pins_hold():
+    assert _self_term_pin_holds() and _dense_pins_hold() and _score_pin_holds()
+    assert _mirror_tie_pin_holds()
+
+
+def test_pin_catches_dropped_static_term(monkeypatch):
+    def bad(h, k0):
+        a = h / np.sqrt(np.pi)
+        return complex(1j * np.pi * a / (2 * k0) * special.hankel1(1, k0 * a))   # "-1/k0^2" dropped
+    monkeypatch.setattr(greens, "self_term", bad)
+    assert not _self_term_pin_holds()
+
+
+def test_pin_catches_transposed_contrast_product(monkeypatch):
+    orig = state.dense_state
+
+    def bad(problem, eps, G0=None):
+        if G0 is None:
+            G0 = greens.build_G0(problem)
+        N = problem.n
+        a = greens.alpha_of(problem, eps)
+        A = np.eye(N) - a[:, None] * G0[:N]          # B G0 instead of G0 B
+        G_D = np.linalg.solve(A, G0[:N])
+        return np.concatenate([G_D, G0[N:]]), None
+    monkeypatch.setattr(state, "dense_state", bad)
+    assert not _dense_pins_hold()
+    monkeypatch.setattr(state, "dense_state", orig)
+
+
+def test_pin_catches_wrong_contrast_sign(monkeypatch):
+    orig = greens.k0_of
+
+    def scores_bad(problem, E, diag, g_mon_row, eps_idx):
+        N = problem.n
+        k0 = orig(problem)
+        table = np.asarray(problem.eps_table)
+        eps_cur = table[np.asarray(eps_idx, np.int64)]
+        out = np.full((N, table.size), -np.inf)
+        for e in range(table.size):
+            alpha = k0**2 * (eps_cur - table[e])        # sign slip
+            En = E[N + problem.fom_monitor] + alpha * g_mon_row * E[:N] / (1 - alpha * diag)
+            out[:, e] = np.where(np.asarray(eps_idx) == e, -np.inf, np.abs(En) ** 2)
+        return out
+    monkeypatch.setattr(greedy, "scores_closed_form", scores_bad)
+    assert not _score_pin_holds()
+
+
+def test_pin_catches_highest_index_tie_break(monkeypatch):
+    def bad(F, fom_now, tau):
+        Fstar = float(np.max(F))
+        tied = np.flatnonzero(F.ravel() >= Fstar - tau * Fstar)
+        flat = int(tied[-1])
+        return greedy.Pick(flat // F.shape[1], flat % F.shape[1], float(F.ravel()[flat]))
+    monkeypatch.setattr(greedy, "select_greedy", bad)
+    assert not _mirror_tie_pin_holds()
