@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Greedy-step throughput of the Green's-function pixel-by-pixel optimiser on one MI355X.
+
+A step is one pass of the hot path: score every candidate flip + select the
+argmax (score_candidates) + rank-1 Dyson update of G, E and the FP64
+diagonal (apply_flip).  The default workload is the 128x128-pixel grid with 64
+monitors, complex64 storage and an FP64 refresh every 256 accepted moves.  The
+greedy trajectory of that problem ends after 190 accepted moves (no move
+improves the FOM any more), so the benchmark restarts the job (init_G0, inside
+the timed region) whenever it stops, and counts accepted moves only.
+
+Prints one JSON line.  The streaming rank-1 kernel is timed alone with HIP
+events recorded on its own stream around every launch of the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_steps(job, target, poll, events=None, refresh_every=0):
+    """Issue greedy steps until `target` accepted moves; re-init a job that stopped.
+
+    Returns (accepted, calls, restarts, accepted_flags) where accepted_flags[i]
+    tells whether step call i made a move.
+    """
+    from paper_2202_05388_amd import _lib as L
+
+    accepted = 0
+    calls = 0
+    restarts = 0
+    flags = []
+    in_run_issued = 0
+    in_run_acc = job.n_flips()
+    while accepted < target:
+        chunk = min(poll, target - accepted)
+        if refresh_every:
+            chunk = min(chunk, refresh_every - in_run_acc % refresh_every)
+        for _ in range(chunk):
+            if events is not None:
+                a, b = events.next()
+                L.time_next_k1(a, b)
+            job.step()
+        calls += chunk
+        n = job.n_flips()                     # host sync
+        new = n - in_run_acc
+        flags.extend([True] * new + [False] * (chunk - new))
+        accepted += new
+        in_run_acc = n
+        in_run_issued += chunk
+        if new < chunk:                        # the trajectory ended: restart the job
+            job.init()
+            restarts += 1
+            in_run_issued = 0
+            in_run_acc = 0
+        elif refresh_every and in_run_acc % refresh_every == 0:
+            job.refresh()
+    return accepted, calls, restarts, flags
+
+
+def time_workload(problem, steps, warmup, poll, with_events=True):
+    import torch
+    from paper_2202_05388_amd.hiprt import EventPool
+    from paper_2202_05388_amd.job import Job
+
+    kmax = max(problem.refresh_every, 0) * 2 if problem.refresh_every else 0
+    job = Job(problem, device="cuda:0", kmax=kmax)
+    job.init()
+    if warmup:
+        run_steps(job, warmup, poll, refresh_every=problem.refresh_every)
+    job.init()
+    torch.cuda.synchronize()
+    events = EventPool(steps + poll + 8) if with_events else None
+    t0 = time.perf_counter()
+    acc, calls, restarts, flags = run_steps(job, steps, poll, events, problem.refresh_every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    k1_ms = None
+    if events is not None:
+        d = events.elapsed_ms()
+        sel = [x for x, f in zip(d, flags) if f]
+        k1_ms = sum(sel) / len(sel)
+        events.close()
+    st = job.status()
+    fom = job.fom()
+    hist = job.history()
+    del job
+    torch.cuda.empty_cache()
+    return dict(accepted=acc, calls=calls, restarts=restarts, seconds=t1 - t0, k1_ms=k1_ms,
+                status=st, fom_last=fom, last_run_pixels=[int(x) for x in hist[:, 0]])
+
+
+def cpu_baseline(problem, max_steps):
+    """The FP64 oracle (flipped-set tier) on the same workload, host cores."""
+    import numpy as np
+    from oracle import greedy as og
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    t0 = time.perf_counter()
+    tr = og.greedy(problem.replace(tau=1e-9), steps=max_steps, tier="T2")
+    dt = time.perf_counter() - t0
+    n = len(tr.steps)
+    return dict(value=n / dt, unit="steps/s", cores=int(threads), kind="oracle",
+                sample=f"oracle greedy trajectory, flipped-set tier (FP64), {n} steps "
+                       f"({'to termination' if tr.stopped else 'capped'}) of {problem.name}, "
+                       f"{dt:.1f} s"), [s.pixel for s in tr.steps], tr
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--poll", type=int, default=32)
+    ap.add_argument("--workload", default="square128_c64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU row sharding "
+                                   "is a design, not a build (see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import workloads as W
+
+    problem = W.WORKLOADS[args.workload]
+    _log(f"[bench] {problem.name}: {problem.ny}x{problem.nx}, {problem.n_mon} monitors, "
+         f"{problem.dtype}, steps={args.steps} warmup={args.warmup}")
+    res = time_workload(problem, args.steps, args.warmup, args.poll)
+    N, R = problem.n, problem.rows
+    elem = 8 if problem.dtype == "c64" else 16
+    bytes_per_launch = 2 * elem * N * R            # one read + one write of every stored entry
+    k1_s = res["k1_ms"] / 1e3
+    achieved = bytes_per_launch / k1_s / 1e9
+    value = res["accepted"] / res["seconds"]
+    _log(f"[bench] {res['accepted']} moves, {res['restarts']} restarts, {res['seconds']:.3f} s, "
+         f"K1 {res['k1_ms'] * 1e3:.1f} us = {achieved:.0f} GB/s")
+
+    plain = None
+    if not args.no_fp64_plain and problem.dtype == "c64" and problem.name.startswith("square128"):
+        pp = W.SQUARE_128_FP64
+        _log(f"[bench] plain FP64 loop {pp.name}")
+        r2 = time_workload(pp, args.steps, args.warmup, args.poll)
+        plain = dict(workload=pp.name, value=r2["accepted"] / r2["seconds"], unit="steps/s",
+                     ms_per_step=1e3 * r2["seconds"] / r2["accepted"],
+                     k1_us=r2["k1_ms"] * 1e3,
+                     k1_gbs=2 * 16 * N * R / (r2["k1_ms"] / 1e3) / 1e9)
+
+    cpu = None
+    accuracy = None
+    if not args.no_cpu_baseline:
+        _log("[bench] cpu baseline (oracle)")
+        cpu, ref_pixels, tr = cpu_baseline(problem, max_steps=200)
+        gpu_pixels = res["last_run_pixels"]
+        n = min(len(ref_pixels), len(gpu_pixels))
+        match = sum(1 for a, b in zip(ref_pixels, gpu_pixels) if a == b)
+        if tr.stopped and len(gpu_pixels) == len(ref_pixels):
+            fom_ref = tr.steps[-1].fom
+            accuracy = dict(trajectory_steps=len(ref_pixels), pixels_matching=match,
+                            fom_gpu=res["fom_last"], fom_oracle=fom_ref,
+                            fom_rel_err=abs(res["fom_last"] - fom_ref) / fom_ref)
+        else:
+            accuracy = dict(pixels_matching=match, compared=n)
+
+    out = {
+        "metric": "greedy steps/s at 128^2 px (% HBM peak) vs FP64 plain; served p50/p99 latency",
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * res["seconds"] / res["accepted"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": problem.dtype,
+        "data": "synthetic",
+        "config": {"workload": problem.name, "grid": f"{problem.ny}x{problem.nx}",
+                   "monitors": problem.n_mon, "storage": problem.dtype,
+                   "refresh_every": problem.refresh_every, "candidates": "eps {1, 12.25}",
+                   "restarts_in_timed_region": res["restarts"], "step_calls": res["calls"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_rank1 (streaming rank-1 update)",
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": res["k1_ms"] * 1e3},
+        "fp64_plain": plain,
+        "cpu_baseline": cpu,
+        "accuracy": accuracy,
+        "device_status": res["status"],
+    }
+    if plain:
+        out["speedup_vs_fp64_plain"] = value / plain["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * gfo.h - C ABI of libgfo, the MI355X (gfx950) Green's-function pixel-by-pixel
+ * greedy optimiser.
+ *
+ * Problem (paper Sec. II, eq. form1): N design pixels of area h^2 on an
+ * ny x nx grid, a table of permittivities, n_mon monitor points, and a figure
+ * of merit FOM = |E(r_m0)|^2 at one monitor.  2-D TM (scalar E_z) reduction of
+ * the paper's 3-D dyadic formalism; background vacuum.
+ *
+ * Stored state of the current structure (all in caller-owned DEVICE memory):
+ *   G      R x N complex matrix, R = N + n_mon, row-major with leading
+ *          dimension ldG (elements).  Rows: design pixels p = iy*nx + ix, then
+ *          monitors.  Columns: design pixels.  G is "area included": entry
+ *          (r, q) is h^2 times the two-point Green's function (diagonal: its
+ *          integral over the pixel), so a contrast alpha = k0^2 (eps' - eps)
+ *          plays the role of the paper's b = k0^2 d_eps dV (eq. form4).
+ *   E      R complex field values, same element type as G.
+ *   diag64 N complex128 values: FP64 copy of diag(G) used for every
+ *          denominator 1 - alpha G_pp (the only FP64 state besides refresh).
+ *   eps_idx N uint8: material index of each pixel into the permittivity table.
+ *   flips  (pixel, eps_idx) history of accepted moves, 2*flip_cap int32.
+ * Complex numbers are interleaved {re, im}: float2 for GFO_C64, double2 for
+ * GFO_C128.
+ *
+ * Conventions common to every entry point:
+ *   - Pointers are device pointers unless their name starts with h_ (host).
+ *   - The library never allocates or frees caller memory and keeps no pointer
+ *     after a call returns.  Scratch lives in the caller's workspace
+ *     (gfo_workspace_size).
+ *   - Calls only enqueue work on `stream` and return; results are visible
+ *     after the stream is synchronised.  Exceptions are stated per function.
+ *   - Return value: GFO_OK (0) or a negative error detected on the host:
+ *     GFO_EINVAL (bad sizes or null pointers), GFO_EHIP (a HIP call failed),
+ *     GFO_ENOSPC (workspace too small).  Conditions met on the device are OR-ed
+ *     into *state->status (GFO_STATUS_*), to be read by the caller when it
+ *     synchronises.  The library never aborts the process.
+ */
+#ifndef GFO_H
+#define GFO_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { GFO_C64 = 0, GFO_C128 = 1 };            /* storage type of G and E */
+enum { GFO_FP32 = 0, GFO_BF16 = 1 };           /* MFMA input type of the rank-k update */
+enum { GFO_OK = 0, GFO_EINVAL = -1, GFO_EHIP = -2, GFO_ENOSPC = -3 };
+enum {                                         /* bits of the device status word */
+  GFO_STATUS_SINGULAR = 1,      /* |1 - alpha G_jj| < 1e-12: move refused */
+  GFO_STATUS_NONFINITE = 2,     /* a candidate score was NaN or infinite */
+  GFO_STATUS_HISTORY_FULL = 4,  /* flip history at capacity: later moves not recorded */
+  GFO_STATUS_REFRESH_OVERFLOW = 8 /* more flipped pixels than the refresh workspace holds */
+};
+#define GFO_MAX_EPS 8                          /* permittivity table entries */
+#define GFO_MAX_RANK_K 32                      /* largest k of apply_flips_rank_k */
+
+/* Problem description, read during a call, not retained. */
+typedef struct {
+  int32_t ny, nx, n_mon;        /* design rows (along y, the propagation axis), columns, monitors */
+  int32_t dtype;                /* GFO_C64 or GFO_C128 */
+  double wavelength, pitch;     /* lambda and pixel side h (same length unit) */
+  double eps_bg;                /* background permittivity; must appear in the table */
+  const double* h_mon_xy;       /* 2*n_mon monitor coordinates {x, y} (host) */
+  int32_t fom_monitor;          /* index m0 of the FOM monitor */
+  int32_t n_eps;                /* entries of the permittivity table, 2..GFO_MAX_EPS */
+  const double* h_eps_table;    /* permittivity table (host) */
+} gfo_problem;
+
+/* Caller-owned device buffers of one optimisation job. */
+typedef struct {
+  void* G; int64_t ldG;         /* R x N, ldG >= N and a multiple of 64 */
+  void* E;                      /* R */
+  double* diag64;               /* 2*N doubles */
+  uint8_t* eps_idx;             /* N */
+  int32_t* flips;               /* 2*flip_cap int32: (pixel, eps_idx) per accepted move */
+  int32_t flip_cap;
+  int32_t* n_flips;             /* 1 int32: moves accepted so far */
+  int32_t kmax;                 /* largest flipped set refresh_G supports */
+  void* work; size_t work_bytes;/* scratch, at least gfo_workspace_size() bytes, 256-B aligned */
+  int32_t* status;              /* 1 int32 device status word (GFO_STATUS_* bits) */
+} gfo_state;
+
+/* One selected move.  pixel = -1 is the sentinel "no move improves the FOM". */
+typedef struct {
+  int32_t pixel, eps_idx;       /* flipped pixel and its new material index */
+  double fom_new;               /* predicted FOM after the move */
+  double dfom;                  /* fom_new minus the FOM before the move */
+} gfo_pick;
+
+/* Library version string. */
+const char* gfo_version(void);
+
+/* Human-readable text of a return code. */
+const char* gfo_strerror(int code);
+
+/* Bytes of workspace that a job of this problem needs when refresh_G must
+ * support up to kmax flipped pixels (kmax = 0: no refresh).  Host only. */
+int gfo_workspace_size(const gfo_problem* prob, int32_t kmax, size_t* h_bytes);
+
+/* Smallest valid leading dimension of G for this problem (N rounded up to 64). */
+int64_t gfo_min_ld(const gfo_problem* prob);
+
+/* Byte offset, inside the workspace, of the FP64 score array that
+ * score_candidates fills: N x n_eps values in (pixel, eps_idx) row-major
+ * order, -inf where (pixel, eps_idx) is not a candidate (and, after a call
+ * with topk > 1, where the spacing rule excluded it).  Host only; for
+ * inspection and tests. */
+int gfo_scores_offset(const gfo_problem* prob, int32_t kmax, size_t* h_offset);
+
+/* init_G0 - Green's matrix and field of the vacuum reference structure
+ * (paper Sec. II: an analytic G0 is the starting point; Sec. IV starts from
+ * vacuum).  Writes
+ *   G[p, q] = h^2 (i/4) H0^(1)(k0 |r_p - r_q|)  (p != q; p a pixel or monitor)
+ *   G[q, q] = (i pi a / (2 k0)) H1^(1)(k0 a) - 1/k0^2,  a = h / sqrt(pi)
+ * (the kernel integrated over the equal-area disk), E = exp(i k0 y),
+ * diag64 = diag(G) in FP64, eps_idx = index of eps_bg, n_flips = 0,
+ * status = 0, and the FP64 offset table in the workspace that refresh_G
+ * reuses.  Pixel centres: x = (ix - (nx-1)/2) h, y = (iy - (ny-1)/2) h.
+ * All Hankel values are evaluated in FP64 and rounded once to the storage
+ * type. */
+int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
+
+/* score_candidates - score every candidate move and select (paper Sec. II A:
+ * eqs. form4-form9 with a one-pixel region, evaluated at the monitor as in
+ * eq. para1; selection as in Sec. IV/V: largest FOM increase, stop when none).
+ * For every pixel p and every table entry e with bit e set in cand_mask and
+ * e != eps_idx[p]:
+ *   alpha = k0^2 (eps[e] - eps[eps_idx[p]]),  c = alpha / (1 - alpha diag64[p]) (FP64)
+ *   FOM'  = |E[m0] + c G[m0, p] E[p]|^2     (m0 = row N + fom_monitor).
+ * topk = 1: greedy rule.  With F* the largest FOM', the candidates with
+ * FOM' >= F* - tau F* are tied and the lowest (pixel, eps_idx) wins; the move
+ * is accepted iff F* > FOM (1 + tau), else d_out[0].pixel = -1.
+ * topk = k > 1 (k <= GFO_MAX_RANK_K): the greedy rule applied k times, each
+ * time to the candidates that still improve the FOM, whose pixel is not yet
+ * chosen and whose Chebyshev distance to every chosen pixel is at least
+ * min_spacing; unused records get pixel = -1.
+ * d_out: topk device records.  A NaN/Inf score sets GFO_STATUS_NONFINITE. */
+int score_candidates(const gfo_problem* prob, const gfo_state* st, uint32_t cand_mask,
+                     double tau, int32_t topk, int32_t min_spacing, gfo_pick* d_out,
+                     hipStream_t stream);
+
+/* apply_flip - apply one move as a rank-1 Dyson update (paper Sec. II B,
+ * eqs. form10-form14 with a one-pixel region; field by eqs. form4-form9).
+ * With j = d_pick->pixel, alpha = k0^2 (eps_new - eps_j), c = alpha/(1 - alpha G_jj)
+ * (FP64, from diag64):
+ *   G[r, q] += c G[r, j] G[j, q]  for all rows r < R and columns q < N (in place),
+ *   E[r]    += c G[r, j] E[j],     diag64[q] += c G[q, j] G[j, q] (FP64),
+ *   diag64[j] = G_jj / (1 - alpha G_jj),  eps_idx[j] = eps_new, history appended.
+ * The pick is read from DEVICE memory, so score -> apply needs no host round
+ * trip.  A sentinel pick (pixel < 0) makes the call a no-op; a singular
+ * denominator sets GFO_STATUS_SINGULAR and skips the move. */
+int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick,
+               hipStream_t stream);
+
+/* apply_flips_rank_k - apply k moves jointly by the Woodbury form of the
+ * paper's region update (eqs. form10-form14 with V = the k pixels):
+ *   M = (I - B_S G[S,S])^-1 B_S  (k x k, FP64, B_S = diag(alpha)),
+ *   G += G[:, S] M G[S, :],  E += G[:, S] M E[S],  diag64 updated in FP64.
+ * The R x N update is a rank-k product on the matrix cores with FP32 or BF16
+ * inputs (gemm_precision) and FP32 accumulation; requires GFO_C64 storage.
+ * Sentinel records (pixel < 0) are skipped; 1 <= k <= GFO_MAX_RANK_K. */
+int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_picks,
+                       int32_t k, int32_t gemm_precision, hipStream_t stream);
+
+/* refresh_G - recompute G, E and diag64 of the current structure in FP64
+ * from G0 and the flipped set V = {p : eps_idx[p] != background} (the
+ * discretised Dyson equation, eq. form2, solved on V):
+ *   G = G0 + G0[:, V] (I - B_V G0[V, V])^-1 B_V G0[V, :],
+ *   E = Einc + G0[:, V] (I - B_V G0[V, V])^-1 B_V Einc[V],
+ * then rounds G and E once to the storage type.  Removes the rounding drift
+ * of repeated rank-1 updates.  Requires init_G0 on this workspace and
+ * |V| <= kmax (else GFO_STATUS_REFRESH_OVERFLOW and nothing is changed).
+ * Synchronises `stream` once to read |V|. */
+int refresh_G(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
+
+/* Autotuner hooks for the streaming rank-1 kernel of apply_flip: the kernel
+ * exists in several tile shapes (rows per workgroup x rows in flight, plain or
+ * non-temporal memory operations), all computing bit-identical results.
+ * Selection is process-wide per storage type; host only. */
+int gfo_k1_variant_count(int32_t dtype);
+const char* gfo_k1_variant_name(int32_t dtype, int32_t idx);   /* NULL if out of range */
+int gfo_k1_set_variant(int32_t dtype, int32_t idx);           /* GFO_EINVAL if out of range */
+int gfo_k1_get_variant(int32_t dtype);
+
+/* Timing hook: the next apply_flip (on any stream) records `before` on its
+ * stream immediately before its streaming rank-1 kernel and `after`
+ * immediately after it, then forgets both events.  Lets a caller time that
+ * kernel alone with hipEventElapsedTime.  Both NULL cancels a pending pair.
+ * Host only; one pending pair per process. */
+int gfo_time_next_k1(hipEvent_t before, hipEvent_t after);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GFO_H */

@@ -1,0 +1,152 @@
+"""ctypes binding of libgfo (include/gfo.h).  Argument marshalling only.
+
+Every function here forwards to the C ABI of the same name; all arithmetic of
+the optimiser runs in the library's HIP kernels.  Loading fails loudly when
+the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgfo.so")
+
+GFO_C64, GFO_C128 = 0, 1
+GFO_FP32, GFO_BF16 = 0, 1
+GFO_OK, GFO_EINVAL, GFO_EHIP, GFO_ENOSPC = 0, -1, -2, -3
+GFO_STATUS_SINGULAR, GFO_STATUS_NONFINITE = 1, 2
+GFO_STATUS_HISTORY_FULL, GFO_STATUS_REFRESH_OVERFLOW = 4, 8
+GFO_MAX_EPS = 8
+GFO_MAX_RANK_K = 32
+
+# every entry point that include/gfo.h declares
+EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "gfo_scores_offset",
+           "init_G0", "score_candidates", "apply_flip", "apply_flips_rank_k", "refresh_G",
+           "gfo_k1_variant_count", "gfo_k1_variant_name", "gfo_k1_set_variant",
+           "gfo_k1_get_variant", "gfo_time_next_k1")
+
+
+class Problem(C.Structure):
+    _fields_ = [("ny", C.c_int32), ("nx", C.c_int32), ("n_mon", C.c_int32), ("dtype", C.c_int32),
+                ("wavelength", C.c_double), ("pitch", C.c_double), ("eps_bg", C.c_double),
+                ("h_mon_xy", C.POINTER(C.c_double)), ("fom_monitor", C.c_int32),
+                ("n_eps", C.c_int32), ("h_eps_table", C.POINTER(C.c_double))]
+
+
+class State(C.Structure):
+    _fields_ = [("G", C.c_void_p), ("ldG", C.c_int64), ("E", C.c_void_p),
+                ("diag64", C.c_void_p), ("eps_idx", C.c_void_p), ("flips", C.c_void_p),
+                ("flip_cap", C.c_int32), ("n_flips", C.c_void_p), ("kmax", C.c_int32),
+                ("work", C.c_void_p), ("work_bytes", C.c_size_t), ("status", C.c_void_p)]
+
+
+class Pick(C.Structure):
+    _fields_ = [("pixel", C.c_int32), ("eps_idx", C.c_int32), ("fom_new", C.c_double),
+                ("dfom", C.c_double)]
+
+
+PICK_BYTES = C.sizeof(Pick)
+_lib = None
+
+
+class GfoError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libgfo.so; raises if it is missing (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise GfoError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    P, S, V = C.POINTER(Problem), C.POINTER(State), C.c_void_p
+    L.gfo_version.restype = C.c_char_p
+    L.gfo_strerror.restype = C.c_char_p
+    L.gfo_strerror.argtypes = [C.c_int]
+    L.gfo_workspace_size.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
+    L.gfo_min_ld.argtypes = [P]
+    L.gfo_min_ld.restype = C.c_int64
+    L.gfo_scores_offset.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
+    L.init_G0.argtypes = [P, S, V]
+    L.score_candidates.argtypes = [P, S, C.c_uint32, C.c_double, C.c_int32, C.c_int32, V, V]
+    L.apply_flip.argtypes = [P, S, V, V]
+    L.apply_flips_rank_k.argtypes = [P, S, V, C.c_int32, C.c_int32, V]
+    L.refresh_G.argtypes = [P, S, V]
+    L.gfo_k1_variant_count.argtypes = [C.c_int32]
+    L.gfo_k1_variant_name.argtypes = [C.c_int32, C.c_int32]
+    L.gfo_k1_variant_name.restype = C.c_char_p
+    L.gfo_k1_set_variant.argtypes = [C.c_int32, C.c_int32]
+    L.gfo_k1_get_variant.argtypes = [C.c_int32]
+    L.gfo_time_next_k1.argtypes = [C.c_void_p, C.c_void_p]
+    _lib = L
+    return L
+
+
+def check(rc: int, what: str) -> None:
+    if rc != GFO_OK:
+        raise GfoError(f"{what} failed: {rc} ({lib().gfo_strerror(rc).decode()})")
+
+
+def version() -> str:
+    return lib().gfo_version().decode()
+
+
+def workspace_size(prob: Problem, kmax: int) -> int:
+    out = C.c_size_t(0)
+    check(lib().gfo_workspace_size(C.byref(prob), kmax, C.byref(out)), "gfo_workspace_size")
+    return out.value
+
+
+def scores_offset(prob: Problem, kmax: int) -> int:
+    out = C.c_size_t(0)
+    check(lib().gfo_scores_offset(C.byref(prob), kmax, C.byref(out)), "gfo_scores_offset")
+    return out.value
+
+
+def min_ld(prob: Problem) -> int:
+    ld = lib().gfo_min_ld(C.byref(prob))
+    if ld < 0:
+        raise GfoError("invalid problem")
+    return ld
+
+
+def init_G0(prob: Problem, st: State, stream: int) -> None:
+    check(lib().init_G0(C.byref(prob), C.byref(st), stream), "init_G0")
+
+
+def score_candidates(prob, st, cand_mask, tau, topk, min_spacing, d_out, stream) -> None:
+    check(lib().score_candidates(C.byref(prob), C.byref(st), cand_mask, tau, topk, min_spacing,
+                                 d_out, stream), "score_candidates")
+
+
+def apply_flip(prob, st, d_pick, stream) -> None:
+    check(lib().apply_flip(C.byref(prob), C.byref(st), d_pick, stream), "apply_flip")
+
+
+def apply_flips_rank_k(prob, st, d_picks, k, gemm_precision, stream) -> None:
+    check(lib().apply_flips_rank_k(C.byref(prob), C.byref(st), d_picks, k, gemm_precision, stream),
+          "apply_flips_rank_k")
+
+
+def refresh_G(prob, st, stream) -> None:
+    check(lib().refresh_G(C.byref(prob), C.byref(st), stream), "refresh_G")
+
+
+def k1_variants(dtype: int):
+    L = lib()
+    return [L.gfo_k1_variant_name(dtype, i).decode() for i in range(L.gfo_k1_variant_count(dtype))]
+
+
+def k1_set_variant(dtype: int, idx: int) -> None:
+    check(lib().gfo_k1_set_variant(dtype, idx), "gfo_k1_set_variant")
+
+
+def k1_get_variant(dtype: int) -> int:
+    return lib().gfo_k1_get_variant(dtype)
+
+
+def time_next_k1(before: int, after: int) -> None:
+    check(lib().gfo_time_next_k1(before, after), "gfo_time_next_k1")

@@ -1,0 +1,222 @@
+// Host side of the C ABI declared in include/gfo.h: argument validation,
+// workspace layout and dispatch to the kernel launchers.
+#include "gfo_internal.hpp"
+
+#include <math.h>
+#include <string.h>
+
+namespace gfo {
+
+int find_bg(const gfo_problem* p) {
+  for (int i = 0; i < p->n_eps; ++i)
+    if (p->h_eps_table[i] == p->eps_bg) return i;
+  return -1;
+}
+
+int validate_problem(const gfo_problem* p) {
+  if (!p) return GFO_EINVAL;
+  if (p->ny < 1 || p->nx < 1 || p->n_mon < 1) return GFO_EINVAL;
+  if (p->dtype != GFO_C64 && p->dtype != GFO_C128) return GFO_EINVAL;
+  if (!(p->wavelength > 0.0) || !(p->pitch > 0.0)) return GFO_EINVAL;
+  if (p->n_eps < 2 || p->n_eps > GFO_MAX_EPS || !p->h_eps_table || !p->h_mon_xy) return GFO_EINVAL;
+  if (p->fom_monitor < 0 || p->fom_monitor >= p->n_mon) return GFO_EINVAL;
+  const int64_t N = (int64_t)p->ny * p->nx;
+  if (N * p->n_eps >= (int64_t)1 << 31 || N + p->n_mon >= (int64_t)1 << 31) return GFO_EINVAL;
+  for (int i = 0; i < p->n_eps; ++i)
+    if (!isfinite(p->h_eps_table[i])) return GFO_EINVAL;
+  for (int i = 0; i < 2 * p->n_mon; ++i)
+    if (!isfinite(p->h_mon_xy[i])) return GFO_EINVAL;
+  if (find_bg(p) < 0) return GFO_EINVAL;
+  return GFO_OK;
+}
+
+Geo make_geo(const gfo_problem* p, int64_t ld) {
+  Geo g = {};
+  g.ny = p->ny;
+  g.nx = p->nx;
+  g.nmon = p->n_mon;
+  g.N = p->ny * p->nx;
+  g.R = g.N + p->n_mon;
+  g.ld = ld;
+  g.k0 = 2.0 * 3.14159265358979323846 / p->wavelength;
+  g.k0sq = g.k0 * g.k0;
+  g.h = p->pitch;
+  for (int i = 0; i < p->n_eps; ++i) g.eps[i] = p->h_eps_table[i];
+  g.n_eps = p->n_eps;
+  g.bg_idx = find_bg(p);
+  g.m0 = p->fom_monitor;
+  g.dtype = p->dtype;
+  return g;
+}
+
+Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
+  const size_t N = (size_t)p->ny * p->nx, R = N + p->n_mon, K = GFO_MAX_RANK_K;
+  const size_t k = kmax > 0 ? (size_t)kmax : 0;
+  Layout L = {};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.table = take(N * 16);
+  L.mon_xy = take((size_t)p->n_mon * 16);
+  L.scores = take(N * p->n_eps * 8);
+  L.partial = take(kScoreMaxBlocks * 8);
+  L.picks = take(K * sizeof(gfo_pick));
+  L.snap = take(sizeof(Snap));
+  L.cu = take(R * 16);
+  L.v = take((size_t)ld * 16);
+  L.rk_S = take(K * 16 + 256);
+  L.rk_M = take(K * K * 16);
+  L.rk_A = take(R * 2 * K * 4);
+  L.rk_B = take(2 * 2 * K * (size_t)ld * 4);
+  L.rk_Abf = take(R * 2 * K * 2);
+  L.rk_Bbf = take(2 * 2 * K * (size_t)ld * 2);
+  L.rf_V = take((N + 64) * 4);
+  L.rf_U = take(R * k * 16);
+  L.rf_A = take(k * k * 16);
+  L.rf_piv = take(k * 4 + 64);
+  L.rf_Z = take(R * k * 16);
+  L.rf_x = take(k * 16 + 64);
+  L.total = o;
+  return L;
+}
+
+static int64_t min_ld(const gfo_problem* p) {
+  const int64_t N = (int64_t)p->ny * p->nx;
+  return (N + 63) / 64 * 64;
+}
+
+static int validate_state(const gfo_problem* p, const gfo_state* st, Layout* L) {
+  if (!st || !st->G || !st->E || !st->diag64 || !st->eps_idx || !st->n_flips || !st->status ||
+      !st->work)
+    return GFO_EINVAL;
+  if (st->flip_cap < 0 || (st->flip_cap > 0 && !st->flips) || st->kmax < 0) return GFO_EINVAL;
+  if (st->ldG < min_ld(p) || st->ldG % 64 != 0) return GFO_EINVAL;
+  if (((uintptr_t)st->work & 255) != 0 || ((uintptr_t)st->G & 15) != 0) return GFO_EINVAL;
+  *L = make_layout(p, st->ldG, st->kmax);
+  if (st->work_bytes < L->total) return GFO_ENOSPC;
+  return GFO_OK;
+}
+
+}  // namespace gfo
+
+using namespace gfo;
+
+extern "C" {
+
+const char* gfo_version(void) { return "libgfo 0.1 gfx950"; }
+
+const char* gfo_strerror(int code) {
+  switch (code) {
+    case GFO_OK: return "ok";
+    case GFO_EINVAL: return "invalid argument (sizes, null pointers or alignment)";
+    case GFO_EHIP: return "a HIP runtime call or kernel launch failed";
+    case GFO_ENOSPC: return "workspace too small";
+    default: return "unknown error";
+  }
+}
+
+int gfo_workspace_size(const gfo_problem* prob, int32_t kmax, size_t* h_bytes) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  if (!h_bytes || kmax < 0) return GFO_EINVAL;
+  *h_bytes = make_layout(prob, min_ld(prob), kmax).total;
+  return GFO_OK;
+}
+
+int gfo_scores_offset(const gfo_problem* prob, int32_t kmax, size_t* h_offset) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  if (!h_offset || kmax < 0) return GFO_EINVAL;
+  *h_offset = make_layout(prob, min_ld(prob), kmax).scores;
+  return GFO_OK;
+}
+
+int64_t gfo_min_ld(const gfo_problem* prob) {
+  if (validate_problem(prob)) return -1;
+  return min_ld(prob);
+}
+
+int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  Layout L;
+  if ((rc = validate_state(prob, st, &L))) return rc;
+  const Geo g = make_geo(prob, st->ldG);
+  char* w = (char*)st->work;
+  // monitor coordinates travel with the call; wait for the copy so that the
+  // caller's host array need not outlive it
+  if (hipMemcpyAsync(w + L.mon_xy, prob->h_mon_xy, (size_t)prob->n_mon * 2 * sizeof(double),
+                     hipMemcpyHostToDevice, stream) != hipSuccess)
+    return GFO_EHIP;
+  if (launch_init(g, st, L, stream) != hipSuccess) return GFO_EHIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return GFO_EHIP;
+  return GFO_OK;
+}
+
+int score_candidates(const gfo_problem* prob, const gfo_state* st, uint32_t cand_mask, double tau,
+                     int32_t topk, int32_t min_spacing, gfo_pick* d_out, hipStream_t stream) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  Layout L;
+  if ((rc = validate_state(prob, st, &L))) return rc;
+  if (!d_out || topk < 1 || topk > GFO_MAX_RANK_K || min_spacing < 0 || !(tau >= 0.0) ||
+      !(tau < 1.0))
+    return GFO_EINVAL;
+  if ((cand_mask & ((1u << prob->n_eps) - 1u)) == 0) return GFO_EINVAL;
+  const Geo g = make_geo(prob, st->ldG);
+  if (launch_score(g, st, L, cand_mask & ((1u << prob->n_eps) - 1u), tau, topk, min_spacing, d_out,
+                   stream) != hipSuccess)
+    return GFO_EHIP;
+  return GFO_OK;
+}
+
+int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick, hipStream_t stream) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  Layout L;
+  if ((rc = validate_state(prob, st, &L))) return rc;
+  if (!d_pick) return GFO_EINVAL;
+  const Geo g = make_geo(prob, st->ldG);
+  if (launch_apply(g, st, L, d_pick, stream) != hipSuccess) return GFO_EHIP;
+  return GFO_OK;
+}
+
+int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_picks, int32_t k,
+                       int32_t gemm_precision, hipStream_t stream) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  Layout L;
+  if ((rc = validate_state(prob, st, &L))) return rc;
+  if (!d_picks || k < 1 || k > GFO_MAX_RANK_K || prob->dtype != GFO_C64 ||
+      (gemm_precision != GFO_FP32 && gemm_precision != GFO_BF16))
+    return GFO_EINVAL;
+  const Geo g = make_geo(prob, st->ldG);
+  if (launch_rank_k(g, st, L, d_picks, k, gemm_precision, stream) != hipSuccess) return GFO_EHIP;
+  return GFO_OK;
+}
+
+int refresh_G(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  Layout L;
+  if ((rc = validate_state(prob, st, &L))) return rc;
+  const Geo g = make_geo(prob, st->ldG);
+  return launch_refresh(g, st, L, stream);
+}
+
+// Autotuner hooks: variants of the streaming rank-1 kernel.
+int gfo_k1_variant_count(int32_t dtype) { return k1_variant_count(dtype); }
+const char* gfo_k1_variant_name(int32_t dtype, int32_t idx) { return k1_variant_name(dtype, idx); }
+int gfo_k1_set_variant(int32_t dtype, int32_t idx) { return k1_set_variant(dtype, idx); }
+int gfo_k1_get_variant(int32_t dtype) { return k1_get_variant(dtype); }
+
+int gfo_time_next_k1(hipEvent_t before, hipEvent_t after) {
+  if ((before == nullptr) != (after == nullptr)) return GFO_EINVAL;
+  k1_time_next(before, after);
+  return GFO_OK;
+}
+
+}  // extern "C"

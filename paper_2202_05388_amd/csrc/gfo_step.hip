@@ -1,0 +1,413 @@
+// One greedy step: candidate scores + selection, move snapshot, pivot gather
+// and the streaming rank-1 Dyson update of G.
+//
+// Scores follow paper eqs. form4-form9 for a one-pixel region evaluated at the
+// FOM monitor (eq. para1); the update is eq. form10 with the one-pixel solve of
+// eq. form14, i.e. G += c G[:, j] G[j, :] with c = alpha / (1 - alpha G_jj).
+#include "gfo_internal.hpp"
+
+#include <atomic>
+#include <math.h>
+
+namespace gfo {
+
+// ------------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// block-wide max; all threads get the result. `sh` holds blockDim/64 doubles.
+__device__ double block_max(double v, double* sh) {
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = -INFINITY;
+  for (int i = 0; i < nw; ++i) r = fmax(r, sh[i]);
+  return r;
+}
+__device__ int block_min(int v, int* sh) {
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_min(v);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  int r = 0x7fffffff;
+  for (int i = 0; i < nw; ++i) r = min(r, sh[i]);
+  return r;
+}
+
+// ------------------------------------------------------------------ K3: scores
+// One thread per pixel (grid-stride).  Writes every (pixel, material) score,
+// -inf for non-candidates, and one block maximum per workgroup.
+template <typename T>
+__global__ __launch_bounds__(kScoreThreads) void k_score(
+    Geo g, const T* __restrict__ G, const T* __restrict__ E, const double2* __restrict__ diag64,
+    const uint8_t* __restrict__ eps_idx, uint32_t mask, double* __restrict__ scores,
+    double* __restrict__ partial, int32_t* __restrict__ status) {
+  __shared__ double sh[kScoreThreads / 64];
+  const double2 Em0 = St<T>::to_d(E[g.N + g.m0]);
+  const T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
+  double best = -INFINITY;
+  bool bad = false;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < g.N; p += gridDim.x * blockDim.x) {
+    const int cur = eps_idx[p];
+    const double2 d = diag64[p];
+    const double2 gE = cmul(St<T>::to_d(grow[p]), St<T>::to_d(E[p]));
+    for (int e = 0; e < g.n_eps; ++e) {
+      double F = -INFINITY;
+      if (((mask >> e) & 1u) && e != cur) {
+        const double a = g.k0sq * (g.eps[e] - g.eps[cur]);
+        const double2 c = rdiv(a, make_double2(1.0 - a * d.x, -a * d.y));   // FP64 denominator
+        const double2 En = cadd(Em0, cmul(c, gE));
+        F = cabs2(En);
+        if (!isfinite(F)) {
+          bad = true;
+          F = -INFINITY;
+        }
+        best = fmax(best, F);
+      }
+      scores[(int64_t)p * g.n_eps + e] = F;
+    }
+  }
+  best = block_max(best, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = best;
+  if (bad) atomicOr(status, GFO_STATUS_NONFINITE);
+}
+
+// ------------------------------------------------------------------ K3b: selection
+// Single workgroup.  Greedy rule with the relative tie band tau and the
+// lowest-(pixel, material) winner, repeated topk times with the spacing
+// exclusion.  Modifies `scores` (marks excluded candidates -inf).
+template <typename T>
+__global__ __launch_bounds__(kSelectThreads) void k_select(
+    Geo g, const T* __restrict__ E, double* __restrict__ scores, const double* __restrict__ partial,
+    int nblk, double tau, int topk, int spacing, gfo_pick* __restrict__ out) {
+  __shared__ double shd[kSelectThreads / 64];
+  __shared__ int shi[kSelectThreads / 64];
+  const double fom = cabs2(St<T>::to_d(E[g.N + g.m0]));
+  const int total = g.N * g.n_eps;
+  const int win = spacing > 1 ? spacing - 1 : 0;
+  int t = 0;
+  for (; t < topk; ++t) {
+    double m = -INFINITY;
+    if (t == 0) {
+      for (int i = threadIdx.x; i < nblk; i += blockDim.x) m = fmax(m, partial[i]);
+    } else {
+      for (int i = threadIdx.x; i < total; i += blockDim.x) m = fmax(m, scores[i]);
+    }
+    m = block_max(m, shd);
+    if (!(m > fom * (1.0 + tau))) break;
+    const double thr = m - tau * m;
+    int first = 0x7fffffff;
+    for (int i = threadIdx.x; i < total; i += blockDim.x) {
+      if (scores[i] >= thr) {
+        first = i;
+        break;
+      }
+    }
+    first = block_min(first, shi);
+    const int j = first / g.n_eps;
+    if (threadIdx.x == 0) {
+      gfo_pick pk;
+      pk.pixel = j;
+      pk.eps_idx = first - j * g.n_eps;
+      pk.fom_new = scores[first];
+      pk.dfom = pk.fom_new - fom;
+      out[t] = pk;
+    }
+    if (t + 1 < topk) {
+      __syncthreads();
+      const int iy = j / g.nx, ix = j - (j / g.nx) * g.nx;
+      const int w = 2 * win + 1;
+      for (int k = threadIdx.x; k < w * w * g.n_eps; k += blockDim.x) {
+        const int e = k % g.n_eps, cell = k / g.n_eps;
+        const int yy = iy - win + cell / w, xx = ix - win + cell % w;
+        if (yy >= 0 && yy < g.ny && xx >= 0 && xx < g.nx)
+          scores[(int64_t)(yy * g.nx + xx) * g.n_eps + e] = -INFINITY;
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    for (; t < topk; ++t) {
+      gfo_pick pk;
+      pk.pixel = -1;
+      pk.eps_idx = -1;
+      pk.fom_new = fom;
+      pk.dfom = 0.0;
+      out[t] = pk;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ K2a: snapshot
+// Single thread.  Validates the pick, computes c in FP64 from diag64 and
+// records the scalars the later kernels need before anything is overwritten.
+template <typename T>
+__global__ void k_snap(Geo g, const gfo_pick* __restrict__ pick, const T* __restrict__ E,
+                       const double2* __restrict__ diag64, uint8_t* __restrict__ eps_idx,
+                       int32_t* __restrict__ flips, int flip_cap, int32_t* __restrict__ n_flips,
+                       int32_t* __restrict__ status, Snap* __restrict__ snap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Snap s = {};
+  s.j = -1;
+  const int j = pick->pixel, e = pick->eps_idx;
+  if (j >= 0 && j < g.N && e >= 0 && e < g.n_eps && e != (int)eps_idx[j]) {
+    const double a = g.k0sq * (g.eps[e] - g.eps[eps_idx[j]]);
+    const double2 d = diag64[j];
+    const double2 den = make_double2(1.0 - a * d.x, -a * d.y);
+    if (cabs2(den) < 1e-24) {
+      atomicOr(status, GFO_STATUS_SINGULAR);
+    } else {
+      s.j = j;
+      s.e_new = e;
+      s.alpha = a;
+      s.c = rdiv(a, den);
+      s.Ej = St<T>::to_d(E[j]);
+      s.dj = d;
+      eps_idx[j] = (uint8_t)e;
+      const int n = *n_flips;
+      if (n < flip_cap) {
+        flips[2 * n] = j;
+        flips[2 * n + 1] = e;
+      } else {
+        atomicOr(status, GFO_STATUS_HISTORY_FULL);
+      }
+      *n_flips = n + 1;
+    }
+  }
+  *snap = s;
+}
+
+// ------------------------------------------------------------------ K2b: pivot gather
+// Thread i: u_i = G[i, j] (column, all R rows) and v_i = G[j, i] (row, N
+// columns) are copied to scratch (cu = c u) before K1 overwrites them, and the
+// O(R) / O(N) parts of the update are applied here:
+//   E_i += c u_i E_j,   diag64_i += c u_i v_i  (FP64),   diag64_j = d_j / (1 - alpha d_j).
+template <typename T>
+__global__ void k_gather(Geo g, const Snap* __restrict__ snap, const T* __restrict__ G,
+                         T* __restrict__ E, double2* __restrict__ diag64, T* __restrict__ cu,
+                         T* __restrict__ v) {
+  const int j = snap->j;
+  if (j < 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double2 c = snap->c;
+  double2 cu_d = make_double2(0.0, 0.0);
+  if (i < g.R) {
+    const double2 u = (i == j) ? snap->dj : St<T>::to_d(G[i * g.ld + j]);
+    cu_d = cmul(c, u);
+    cu[i] = St<T>::from_d(cu_d);
+    E[i] = St<T>::from_d(cadd(St<T>::to_d(E[i]), cmul(cu_d, snap->Ej)));
+  }
+  if (i < g.ld) {
+    if (i < g.N) {
+      const T vi = G[(int64_t)j * g.ld + i];
+      v[i] = vi;
+      if (i == j) {
+        const double2 d = snap->dj;
+        diag64[j] = cmul(d, rdiv(1.0, make_double2(1.0 - snap->alpha * d.x, -snap->alpha * d.y)));
+      } else {
+        diag64[i] = cadd(diag64[i], cmul(cu_d, St<T>::to_d(vi)));
+      }
+    } else {
+      v[i] = St<T>::from_d(make_double2(0.0, 0.0));
+    }
+  }
+}
+
+// ------------------------------------------------------------------ K1: rank-1 update
+// G[r, q] += cu[r] * v[q] over all R rows and ld columns (v is zero beyond N).
+// Workgroup tile: RB rows x (256 threads x 16 bytes).  Each thread keeps its
+// 16-byte slice of v in registers and streams RB rows of G through it, U rows
+// in flight at a time; cu[r] is uniform across the workgroup.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename T> struct Vec16;
+template <> struct Vec16<float2> {
+  using type = f32x4;
+  static constexpr int n = 2;
+  __device__ __forceinline__ static f32x4 fma(float2 c, f32x4 v, f32x4 g) {
+    g.x = fmaf(c.x, v.x, g.x); g.x = fmaf(-c.y, v.y, g.x);
+    g.y = fmaf(c.x, v.y, g.y); g.y = fmaf(c.y, v.x, g.y);
+    g.z = fmaf(c.x, v.z, g.z); g.z = fmaf(-c.y, v.w, g.z);
+    g.w = fmaf(c.x, v.w, g.w); g.w = fmaf(c.y, v.z, g.w);
+    return g;
+  }
+};
+template <> struct Vec16<double2> {
+  using type = f64x2;
+  static constexpr int n = 1;
+  __device__ __forceinline__ static f64x2 fma(double2 c, f64x2 v, f64x2 g) {
+    g.x = fma_d(c.x, v.x, g.x); g.x = fma_d(-c.y, v.y, g.x);
+    g.y = fma_d(c.x, v.y, g.y); g.y = fma_d(c.y, v.x, g.y);
+    return g;
+  }
+  __device__ __forceinline__ static double fma_d(double a, double b, double c) { return ::fma(a, b, c); }
+};
+
+constexpr int kK1Threads = 256;
+
+template <typename T, int RB, int U, bool NT>
+__global__ __launch_bounds__(kK1Threads) void k_rank1(int R, int64_t ld, int ncoltiles,
+                                                      const Snap* __restrict__ snap,
+                                                      const T* __restrict__ cu,
+                                                      const T* __restrict__ v, T* __restrict__ G) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
+  if (snap->j < 0) return;
+  const int ct = blockIdx.x % ncoltiles;
+  const int rt = blockIdx.x / ncoltiles;
+  const int64_t q = (int64_t)ct * (kK1Threads * VN) + threadIdx.x * VN;
+  if (q >= ld) return;
+  const V vv = *reinterpret_cast<const V*>(v + q);
+  const int r0 = rt * RB;
+#pragma unroll 1
+  for (int rr = 0; rr < RB; rr += U) {
+    V gv[U];
+    T cv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + rr + u;
+      if (r < R) {
+        cv[u] = cu[r];
+        V* p = reinterpret_cast<V*>(G + (int64_t)r * ld + q);
+        gv[u] = NT ? __builtin_nontemporal_load(p) : *p;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + rr + u;
+      if (r < R) {
+        V* p = reinterpret_cast<V*>(G + (int64_t)r * ld + q);
+        const V o = Vec16<T>::fma(cv[u], vv, gv[u]);
+        if (NT) __builtin_nontemporal_store(o, p); else *p = o;
+      }
+    }
+  }
+}
+
+struct K1Variant {
+  const char* name;
+  int rb;
+  void (*launch)(int R, int64_t ld, const Snap*, const void*, const void*, void*, hipStream_t);
+};
+
+template <typename T, int RB, int U, bool NT>
+static void launch_k1(int R, int64_t ld, const Snap* snap, const void* cu, const void* v, void* G,
+                      hipStream_t s) {
+  constexpr int VN = Vec16<T>::n;
+  const int ncol = (int)((ld + kK1Threads * VN - 1) / (kK1Threads * VN));
+  const int nrow = (R + RB - 1) / RB;
+  hipLaunchKernelGGL((k_rank1<T, RB, U, NT>), dim3((unsigned)(ncol * nrow)), dim3(kK1Threads), 0, s,
+                     R, ld, ncol, snap, (const T*)cu, (const T*)v, (T*)G);
+}
+
+#define K1V(T, RB, U, NT, NAME) {NAME, RB, launch_k1<T, RB, U, NT>}
+static const K1Variant kK1c64[] = {
+    K1V(float2, 16, 8, false, "16x8"),     K1V(float2, 32, 8, false, "32x8"),
+    K1V(float2, 16, 8, true, "16x8_nt"),   K1V(float2, 32, 8, true, "32x8_nt"),
+    K1V(float2, 64, 16, false, "64x16"),   K1V(float2, 8, 8, false, "8x8"),
+    K1V(float2, 32, 16, true, "32x16_nt"), K1V(float2, 64, 8, true, "64x8_nt"),
+};
+static const K1Variant kK1c128[] = {
+    K1V(double2, 16, 8, false, "16x8"),     K1V(double2, 32, 8, false, "32x8"),
+    K1V(double2, 16, 8, true, "16x8_nt"),   K1V(double2, 32, 8, true, "32x8_nt"),
+    K1V(double2, 64, 16, false, "64x16"),   K1V(double2, 8, 8, false, "8x8"),
+    K1V(double2, 32, 16, true, "32x16_nt"), K1V(double2, 64, 8, true, "64x8_nt"),
+};
+#undef K1V
+static std::atomic<int> g_k1_sel[2] = {{0}, {0}};
+static std::atomic<hipEvent_t> g_k1_before{nullptr}, g_k1_after{nullptr};
+
+void k1_time_next(hipEvent_t before, hipEvent_t after) {
+  g_k1_after.store(after);
+  g_k1_before.store(before);
+}
+
+static const K1Variant* k1_table(int dtype, int* n) {
+  if (dtype == GFO_C64) {
+    *n = (int)(sizeof(kK1c64) / sizeof(kK1c64[0]));
+    return kK1c64;
+  }
+  *n = (int)(sizeof(kK1c128) / sizeof(kK1c128[0]));
+  return kK1c128;
+}
+int k1_variant_count(int dtype) {
+  int n;
+  k1_table(dtype, &n);
+  return n;
+}
+const char* k1_variant_name(int dtype, int idx) {
+  int n;
+  const K1Variant* t = k1_table(dtype, &n);
+  return (idx >= 0 && idx < n) ? t[idx].name : nullptr;
+}
+int k1_set_variant(int dtype, int idx) {
+  int n;
+  k1_table(dtype, &n);
+  if (idx < 0 || idx >= n || (dtype != GFO_C64 && dtype != GFO_C128)) return GFO_EINVAL;
+  g_k1_sel[dtype].store(idx);
+  return GFO_OK;
+}
+int k1_get_variant(int dtype) { return g_k1_sel[dtype == GFO_C64 ? 0 : 1].load(); }
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+static hipError_t score_typed(const Geo& g, const gfo_state* st, const Layout& L, uint32_t mask,
+                              double tau, int topk, int spacing, gfo_pick* out, hipStream_t s) {
+  char* w = (char*)st->work;
+  int nblk = (g.N + kScoreThreads - 1) / kScoreThreads;
+  if (nblk > kScoreMaxBlocks) nblk = kScoreMaxBlocks;
+  hipLaunchKernelGGL(k_score<T>, dim3(nblk), dim3(kScoreThreads), 0, s, g, (const T*)st->G,
+                     (const T*)st->E, (const double2*)st->diag64, (const uint8_t*)st->eps_idx, mask,
+                     (double*)(w + L.scores), (double*)(w + L.partial), st->status);
+  hipLaunchKernelGGL(k_select<T>, dim3(1), dim3(kSelectThreads), 0, s, g, (const T*)st->E,
+                     (double*)(w + L.scores), (const double*)(w + L.partial), nblk, tau, topk,
+                     spacing, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_score(const Geo& g, const gfo_state* st, const Layout& L, uint32_t mask,
+                        double tau, int topk, int spacing, gfo_pick* out, hipStream_t s) {
+  if (g.dtype == GFO_C64) return score_typed<float2>(g, st, L, mask, tau, topk, spacing, out, s);
+  return score_typed<double2>(g, st, L, mask, tau, topk, spacing, out, s);
+}
+
+template <typename T>
+static hipError_t apply_typed(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* pick,
+                              hipStream_t s) {
+  char* w = (char*)st->work;
+  Snap* snap = (Snap*)(w + L.snap);
+  T* cu = (T*)(w + L.cu);
+  T* v = (T*)(w + L.v);
+  hipLaunchKernelGGL(k_snap<T>, dim3(1), dim3(64), 0, s, g, pick, (const T*)st->E,
+                     (const double2*)st->diag64, st->eps_idx, st->flips, st->flip_cap, st->n_flips,
+                     st->status, snap);
+  const int64_t n = g.R > g.ld ? (int64_t)g.R : g.ld;
+  hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g,
+                     (const Snap*)snap, (const T*)st->G, (T*)st->E, (double2*)st->diag64, cu, v);
+  int nv;
+  const K1Variant* tab = k1_table(g.dtype, &nv);
+  hipEvent_t before = g_k1_before.exchange(nullptr);
+  hipEvent_t after = g_k1_after.exchange(nullptr);
+  if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
+  tab[k1_get_variant(g.dtype)].launch(g.R, g.ld, snap, cu, v, st->G, s);
+  if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* pick,
+                        hipStream_t s) {
+  if (g.dtype == GFO_C64) return apply_typed<float2>(g, st, L, pick, s);
+  return apply_typed<double2>(g, st, L, pick, s);
+}
+
+}  // namespace gfo

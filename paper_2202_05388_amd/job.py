@@ -1,0 +1,164 @@
+"""One optimisation job: device buffers (torch allocations) + calls into libgfo.
+
+PyTorch provides device memory and the stream; every computation is a libgfo
+call.  A problem is any object with the attributes ny, nx, n_mon, wavelength,
+pitch, eps_table, cand_mask, dtype, tau, fom_monitor, monitor_xy() (the shared
+workload definitions satisfy this).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DTYPES = {"c64": (L.GFO_C64, torch.complex64, 8), "c128": (L.GFO_C128, torch.complex128, 16)}
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Job:
+    """Device state of one greedy optimisation."""
+
+    def __init__(self, problem, device="cuda", kmax: int = 0, flip_cap: int = None,
+                 dtype: str = None):
+        if not torch.cuda.is_available():
+            raise L.GfoError("libgfo needs a GPU; torch.cuda is not available")
+        L.lib()
+        self.problem = problem
+        self.dtype_name = dtype or problem.dtype
+        code, tdtype, esize = _DTYPES[self.dtype_name]
+        self.device = torch.device(device)
+        self.N = problem.ny * problem.nx
+        self.R = self.N + problem.n_mon
+        self._mon = np.ascontiguousarray(problem.monitor_xy(), dtype=np.float64).reshape(-1)
+        self._eps = np.ascontiguousarray(problem.eps_table, dtype=np.float64)
+        self.prob = L.Problem(
+            ny=problem.ny, nx=problem.nx, n_mon=problem.n_mon, dtype=code,
+            wavelength=float(problem.wavelength), pitch=float(problem.pitch), eps_bg=1.0,
+            h_mon_xy=self._mon.ctypes.data_as(C.POINTER(C.c_double)),
+            fom_monitor=int(problem.fom_monitor), n_eps=len(self._eps),
+            h_eps_table=self._eps.ctypes.data_as(C.POINTER(C.c_double)))
+        self.ld = L.min_ld(self.prob)
+        self.kmax = int(kmax)
+        self.flip_cap = int(flip_cap if flip_cap is not None else max(4 * self.N, 16))
+        work_bytes = L.workspace_size(self.prob, self.kmax)
+        dev = self.device
+        self.G = torch.empty((self.R, self.ld), dtype=tdtype, device=dev)
+        self.E = torch.empty((self.R,), dtype=tdtype, device=dev)
+        self.diag64 = torch.empty((self.N,), dtype=torch.complex128, device=dev)
+        self.eps_idx = torch.empty((self.N,), dtype=torch.uint8, device=dev)
+        self.flips = torch.zeros((2 * self.flip_cap,), dtype=torch.int32, device=dev)
+        self.counters = torch.zeros((4,), dtype=torch.int32, device=dev)   # n_flips, status
+        self.work = torch.empty((work_bytes,), dtype=torch.uint8, device=dev)
+        self.picks = torch.zeros((L.GFO_MAX_RANK_K * L.PICK_BYTES,), dtype=torch.uint8, device=dev)
+        self.state = L.State(
+            G=self.G.data_ptr(), ldG=self.ld, E=self.E.data_ptr(), diag64=self.diag64.data_ptr(),
+            eps_idx=self.eps_idx.data_ptr(), flips=self.flips.data_ptr(), flip_cap=self.flip_cap,
+            n_flips=self.counters.data_ptr(), kmax=self.kmax, work=self.work.data_ptr(),
+            work_bytes=work_bytes, status=self.counters.data_ptr() + 4)
+        self.steps_issued = 0
+
+    # ------------------------------------------------------------------ C-ABI calls
+    def init(self, stream=None):
+        L.init_G0(self.prob, self.state, _stream_handle(stream))
+
+    def score(self, topk=1, min_spacing=0, tau=None, cand_mask=None, out=None, stream=None):
+        tau = self.problem.tau if tau is None else tau
+        mask = self.problem.cand_mask if cand_mask is None else cand_mask
+        ptr = self.picks.data_ptr() if out is None else out
+        L.score_candidates(self.prob, self.state, mask, tau, topk, min_spacing, ptr,
+                           _stream_handle(stream))
+
+    def apply(self, pick_ptr=None, stream=None):
+        ptr = self.picks.data_ptr() if pick_ptr is None else pick_ptr
+        L.apply_flip(self.prob, self.state, ptr, _stream_handle(stream))
+
+    def apply_rank_k(self, k, precision=L.GFO_FP32, pick_ptr=None, stream=None):
+        ptr = self.picks.data_ptr() if pick_ptr is None else pick_ptr
+        L.apply_flips_rank_k(self.prob, self.state, ptr, k, precision, _stream_handle(stream))
+
+    def refresh(self, stream=None):
+        L.refresh_G(self.prob, self.state, _stream_handle(stream))
+
+    def step(self, stream=None):
+        """One greedy step: score + select + rank-1 apply, no host synchronisation."""
+        self.score(stream=stream)
+        self.apply(stream=stream)
+        self.steps_issued += 1
+
+    # ------------------------------------------------------------------ host views
+    def read_picks(self, k=1):
+        raw = self.picks[: k * L.PICK_BYTES].cpu().numpy().tobytes()
+        arr = (L.Pick * k).from_buffer_copy(raw)
+        return [(p.pixel, p.eps_idx, p.fom_new, p.dfom) for p in arr]
+
+    def n_flips(self) -> int:
+        return int(self.counters[0].item())
+
+    def status(self) -> int:
+        return int(self.counters[1].item())
+
+    def history(self):
+        n = min(self.n_flips(), self.flip_cap)
+        return self.flips[: 2 * n].view(-1, 2).cpu().numpy()
+
+    def fom(self) -> float:
+        e = self.E[self.N + self.problem.fom_monitor].cpu().to(torch.complex128).item()
+        return float(e.real**2 + e.imag**2)
+
+    def scores(self):
+        off = L.scores_offset(self.prob, self.kmax)
+        n = self.N * len(self._eps)
+        raw = self.work[off: off + 8 * n]
+        return raw.view(torch.float64).cpu().numpy().reshape(self.N, len(self._eps))
+
+    def host_state(self):
+        """(G[:, :N], E, diag64, eps_idx) copied to host numpy, complex128."""
+        torch.cuda.synchronize(self.device)
+        G = self.G[:, : self.N].cpu().to(torch.complex128).numpy()
+        return (G, self.E.cpu().to(torch.complex128).numpy(), self.diag64.cpu().numpy(),
+                self.eps_idx.cpu().numpy())
+
+    def upload_state(self, G, E, diag, eps_idx):
+        """Overwrite the device state with host arrays (tests build arbitrary states this way)."""
+        _, tdtype, _ = _DTYPES[self.dtype_name]
+        Gt = torch.zeros((self.R, self.ld), dtype=torch.complex128)
+        Gt[:, : self.N] = torch.from_numpy(np.asarray(G, np.complex128))
+        self.G.copy_(Gt.to(tdtype))
+        self.E.copy_(torch.from_numpy(np.asarray(E, np.complex128)).to(tdtype))
+        self.diag64.copy_(torch.from_numpy(np.asarray(diag, np.complex128)))
+        self.eps_idx.copy_(torch.from_numpy(np.asarray(eps_idx, np.uint8)))
+        torch.cuda.synchronize(self.device)
+
+    def set_pick(self, pixel, eps_idx, slot=0):
+        rec = L.Pick(pixel=pixel, eps_idx=eps_idx, fom_new=0.0, dfom=0.0)
+        raw = torch.frombuffer(bytearray(bytes(rec)), dtype=torch.uint8)
+        self.picks[slot * L.PICK_BYTES:(slot + 1) * L.PICK_BYTES].copy_(raw)
+
+    def run_greedy(self, max_steps, poll_every=32, refresh_every=0, stream=None):
+        """Greedy loop.  Steps are issued without host synchronisation; after
+        each chunk of `poll_every` steps the accepted-move counter is read and
+        the loop stops once a step found no improving move (that step and any
+        later ones in its chunk are no-ops on the device).  With refresh_every
+        > 0, refresh_G runs after every refresh_every accepted moves.
+        Returns the number of accepted moves."""
+        start = self.n_flips()
+        done = 0
+        while done < max_steps:
+            chunk = min(poll_every, max_steps - done)
+            if refresh_every:
+                chunk = min(chunk, refresh_every - done % refresh_every)
+            for _ in range(chunk):
+                self.step(stream)
+            done += chunk
+            if self.n_flips() - start < done:
+                break
+            if refresh_every and done % refresh_every == 0:
+                self.refresh(stream)
+        return self.n_flips() - start

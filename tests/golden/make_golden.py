@@ -69,7 +69,7 @@ def main():
         steps = int(sys.argv[2]) if len(sys.argv) > 2 else p.steps
         rng = np.random.default_rng(0)
         sample = np.sort(rng.choice(p.n, 64, replace=False))
-        write(p, "T2", steps, os.path.join(HERE, f"square128_fp64_{steps}.json"), 100, sample)
+        write(p, "T2", steps, os.path.join(HERE, "square128_fp64.json"), 100, sample)
     else:
         raise SystemExit(f"unknown golden {which}")
 

@@ -1,0 +1,106 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point that
+include/gfo.h declares, and rejects invalid arguments on the host."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2202_05388_amd import _lib as L
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "gfo.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\(\s*(?:const\s+)?(?:gfo_problem|int32_t|int|void)\b", src)))
+
+
+def _problem(p, dtype=L.GFO_C128):
+    mon = np.ascontiguousarray(p.monitor_xy().reshape(-1))
+    eps = np.ascontiguousarray(p.eps_table, dtype=np.float64)
+    pr = L.Problem(ny=p.ny, nx=p.nx, n_mon=p.n_mon, dtype=dtype, wavelength=p.wavelength,
+                   pitch=p.pitch, eps_bg=1.0, h_mon_xy=mon.ctypes.data_as(C.POINTER(C.c_double)),
+                   fom_monitor=p.fom_monitor, n_eps=len(eps),
+                   h_eps_table=eps.ctypes.data_as(C.POINTER(C.c_double)))
+    return pr, (mon, eps)
+
+
+def test_library_exports_every_declared_entry_point():
+    lib = L.lib()
+    declared = _declared_functions()
+    for name in ("init_G0", "score_candidates", "apply_flip", "apply_flips_rank_k", "refresh_G",
+                 "gfo_workspace_size", "gfo_strerror", "gfo_version"):
+        assert name in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) <= set(L.EXPORTS)
+    assert "gfx950" in L.version()
+
+
+def test_struct_layouts_match_header():
+    # x86-64 SysV layout of the structs in include/gfo.h
+    assert C.sizeof(L.Problem) == 64
+    assert L.Problem.h_mon_xy.offset == 40 and L.Problem.h_eps_table.offset == 56
+    assert C.sizeof(L.State) == 96
+    assert L.State.work.offset == 72 and L.State.status.offset == 88
+    assert C.sizeof(L.Pick) == 24
+
+
+def test_workspace_size_and_leading_dimension():
+    pr, keep = _problem(W.SQUARE_128)
+    assert L.min_ld(pr) == 16384
+    small = L.workspace_size(pr, 0)
+    big = L.workspace_size(pr, 256)
+    R = 16384 + 64
+    assert big - small >= 2 * R * 256 * 16       # U and Z refresh panels
+    pr2, keep2 = _problem(W.tiny(5, 7, n_mon=3))
+    assert L.min_ld(pr2) == 64
+    assert L.scores_offset(pr2, 0) % 256 == 0
+
+
+@pytest.mark.parametrize("field,value", [("ny", 0), ("n_mon", 0), ("dtype", 7), ("wavelength", 0.0),
+                                         ("fom_monitor", 99), ("n_eps", 1), ("n_eps", 9)])
+def test_invalid_problem_rejected_on_host(field, value):
+    pr, keep = _problem(W.tiny(4, 4))
+    setattr(pr, field, value)
+    out = C.c_size_t(0)
+    assert L.lib().gfo_workspace_size(C.byref(pr), 0, C.byref(out)) == L.GFO_EINVAL
+    st = L.State()
+    assert L.lib().init_G0(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
+
+
+def test_background_must_be_in_table():
+    p = W.tiny(4, 4).replace(eps_table=(2.0, 12.25))
+    pr, keep = _problem(p)
+    assert L.lib().gfo_min_ld(C.byref(pr)) == -1
+
+
+def test_null_state_and_bad_ld_rejected_without_gpu_work():
+    pr, keep = _problem(W.tiny(4, 4))
+    st = L.State()     # all null
+    lib = L.lib()
+    assert lib.init_G0(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
+    assert lib.score_candidates(C.byref(pr), C.byref(st), 3, 1e-9, 1, 0, None, None) == L.GFO_EINVAL
+    assert lib.apply_flip(C.byref(pr), C.byref(st), None, None) == L.GFO_EINVAL
+    assert lib.apply_flips_rank_k(C.byref(pr), C.byref(st), None, 4, 0, None) == L.GFO_EINVAL
+    assert lib.refresh_G(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
+    # non-null but fake pointers with a bad leading dimension: rejected before any launch
+    fake = 1 << 20
+    st = L.State(G=fake, ldG=17, E=fake, diag64=fake, eps_idx=fake, flips=fake, flip_cap=4,
+                 n_flips=fake, kmax=0, work=fake, work_bytes=1 << 30, status=fake)
+    assert lib.init_G0(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
+    st.ldG = 64
+    st.work_bytes = 16
+    assert lib.init_G0(C.byref(pr), C.byref(st), None) == L.GFO_ENOSPC
+
+
+def test_k1_variants_listed():
+    for dt in (L.GFO_C64, L.GFO_C128):
+        names = L.k1_variants(dt)
+        assert len(names) >= 4 and len(set(names)) == len(names)
+    assert L.lib().gfo_k1_set_variant(L.GFO_C64, 999) == L.GFO_EINVAL
+    assert L.lib().gfo_strerror(L.GFO_ENOSPC) == b"workspace too small"
