@@ -51,7 +51,7 @@ Geo make_geo(const gfo_problem* p, int64_t ld) {
 
 Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   const size_t N = (size_t)p->ny * p->nx, R = N + p->n_mon, K = GFO_MAX_RANK_K;
-  const size_t k = kmax > 0 ? (size_t)kmax : 0;
+  const size_t k = kmax > 0 ? ((size_t)kmax + 3) / 4 * 4 : 0;   // padded to the MFMA k-step
   Layout L = {};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -75,8 +75,8 @@ Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   L.rk_Bbf = take(2 * 2 * K * (size_t)ld * 2);
   L.rf_V = take((N + 64) * 4);
   L.rf_U = take(R * k * 16);
-  L.rf_A = take(k * k * 16);
-  L.rf_piv = take(k * 4 + 64);
+  L.rf_A = take(2 * k * k * 16);
+  L.rf_piv = take(k * 16 + 64);
   L.rf_Z = take(R * k * 16);
   L.rf_x = take(k * 16 + 64);
   L.total = o;

@@ -78,12 +78,13 @@ struct Layout {
   size_t rk_Abf;    // R x 2K bf16
   size_t rk_Bbf;    // 2 x 2K x ld bf16
   // refresh
-  size_t rf_V;      // N int32 flipped list, + count
-  size_t rf_U;      // R x kmax double2: G0[:, V]
-  size_t rf_A;      // kmax x kmax double2: (I - B_V G0[V,V]) -> inverse * B_V
-  size_t rf_piv;    // kmax int32
-  size_t rf_Z;      // R x kmax double2: G0[:, V] M
-  size_t rf_x;      // kmax double2: M Einc[V]
+  // (kp = kmax rounded up to a multiple of 4)
+  size_t rf_V;      // N + 1 int32: flipped list, then its length
+  size_t rf_U;      // R x kp double2: G0[:, V]
+  size_t rf_A;      // kp x 2kp double2: Gauss-Jordan on [diag(1/alpha) - G0[V,V] | I]
+  size_t rf_piv;    // kp double2: pivot column of the current Gauss-Jordan step
+  size_t rf_Z;      // R x kp double2: G0[:, V] M
+  size_t rf_x;      // kp double2: M Einc[V]
   size_t total;
 };
 

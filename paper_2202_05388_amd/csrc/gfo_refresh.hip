@@ -1,7 +1,368 @@
-// FP64 refresh of G from G0 and the flipped set (placeholder until the FP64
-// matrix-core path lands).
+// refresh_G: FP64 recomputation of G, E and diag64 from G0 and the flipped set.
+//
+// With V = {p : eps_idx[p] != background}, alpha_p = k0^2 (eps_p - eps_bg) and
+// U = G0[:, V] (R x k), the discretised Dyson equation (paper eq. form2)
+// restricted to V gives
+//     M = (I - B_V G0[V,V])^-1 B_V = (diag(1/alpha) - G0[V,V])^-1,
+//     G = G0 + U M U_D^T,   E = Einc + U M Einc[V],
+// where U_D^T = G0[V, :] by reciprocity of the free-space kernel.
+// Steps: flipped list -> U gather (FP64 table / direct Hankel) -> Gauss-Jordan
+// inverse with partial pivoting -> Z = U M (FP64 MFMA) -> E -> G = G0 + Z U_D^T
+// (FP64 MFMA, G0 added in the epilogue, one rounding to the storage type).
 #include "gfo_internal.hpp"
 
 namespace gfo {
-int launch_refresh(const Geo&, gfo_state*, const Layout&, hipStream_t) { return GFO_EINVAL; }
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double2 g0_kernel(double r, const Geo& g) {
+  const double x = g.k0 * r, s = 0.25 * g.h * g.h;
+  return make_double2(-s * y0(x), s * j0(x));
+}
+
+// G0[row, q] for a design column q; rows >= N are monitors (direct evaluation).
+__device__ __forceinline__ double2 g0_entry(const Geo& g, const double2* __restrict__ table,
+                                            const double* __restrict__ mon_xy, int row, int q) {
+  const int iyq = q / g.nx, ixq = q - (q / g.nx) * g.nx;
+  if (row < g.N) {
+    const int iyr = row / g.nx, ixr = row - (row / g.nx) * g.nx;
+    return table[abs(iyr - iyq) * g.nx + abs(ixr - ixq)];
+  }
+  const int m = row - g.N;
+  const double xq = (ixq - 0.5 * (g.nx - 1)) * g.h, yq = (iyq - 0.5 * (g.ny - 1)) * g.h;
+  const double dx = mon_xy[2 * m] - xq, dy = mon_xy[2 * m + 1] - yq;
+  return g0_kernel(sqrt(dx * dx + dy * dy), g);
+}
+
+__device__ __forceinline__ double2 incident(const Geo& g, const double* __restrict__ mon_xy, int row) {
+  double y;
+  if (row < g.N) {
+    y = ((row / g.nx) - 0.5 * (g.ny - 1)) * g.h;
+  } else {
+    y = mon_xy[2 * (row - g.N) + 1];
+  }
+  double s, c;
+  sincos(g.k0 * y, &s, &c);
+  return make_double2(c, s);
+}
+
+// ------------------------------------------------------------------ flipped list
+// Single workgroup of 1024 threads: ordered compaction of {p : eps_idx[p] != bg}.
+// V[N] receives the count.
+__global__ __launch_bounds__(1024) void k_rf_list(Geo g, const uint8_t* __restrict__ eps_idx,
+                                                  int32_t* __restrict__ V) {
+  __shared__ int wsum[16];
+  __shared__ int base;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int p0 = 0; p0 < g.N; p0 += 1024) {
+    const int p = p0 + threadIdx.x;
+    const int f = (p < g.N && eps_idx[p] != g.bg_idx) ? 1 : 0;
+    // inclusive scan within the wave
+    int x = f;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    int before = base;
+    for (int i = 0; i < w; ++i) before += wsum[i];
+    if (f) V[before + x - 1] = p;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int t = 0;
+      for (int i = 0; i < 16; ++i) t += wsum[i];
+      base += t;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) V[g.N] = base;
+}
+
+__global__ void k_rf_overflow(int32_t* status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr(status, GFO_STATUS_REFRESH_OVERFLOW);
+}
+
+// U[r, i] = G0[r, V_i] for i < k, 0 for k <= i < kp.  Row-major, ld = kp.
+__global__ void k_rf_gather_U(Geo g, const double2* __restrict__ table,
+                              const double* __restrict__ mon_xy, const int32_t* __restrict__ V,
+                              int k, int kp, double2* __restrict__ U) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)g.R * kp) return;
+  const int r = (int)(t / kp), i = (int)(t - (int64_t)r * kp);
+  U[t] = (i < k) ? g0_entry(g, table, mon_xy, r, V[i]) : make_double2(0.0, 0.0);
+}
+
+// Augmented [D - G0[V,V] | I] of size kp x 2kp, D = diag(1 / alpha); identity padding.
+__global__ void k_rf_build_aug(Geo g, const uint8_t* __restrict__ eps_idx,
+                               const int32_t* __restrict__ V, const double2* __restrict__ U, int k,
+                               int kp, double2* __restrict__ Aug) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)kp * 2 * kp) return;
+  const int a = (int)(t / (2 * kp)), b = (int)(t - (int64_t)a * 2 * kp);
+  double2 v = make_double2(0.0, 0.0);
+  if (b < kp) {
+    if (a < k && b < k) {
+      const double2 gab = U[(int64_t)V[a] * kp + b];   // G0[V_a, V_b]
+      v = make_double2(-gab.x, -gab.y);
+      if (a == b) {
+        const double alpha = g.k0sq * (g.eps[eps_idx[V[a]]] - g.eps[g.bg_idx]);
+        v.x += 1.0 / alpha;
+      }
+    } else if (a == b) {
+      v.x = 1.0;
+    }
+  } else if (b - kp == a) {
+    v.x = 1.0;
+  }
+  Aug[t] = v;
+}
+
+// Gauss-Jordan column c: pivot search (largest modulus, lowest row on ties),
+// row swap, scaling of the pivot row; saves column c of every row in f.
+__global__ __launch_bounds__(1024) void k_gj_pivot(double2* __restrict__ Aug, int kp, int c,
+                                                   double2* __restrict__ f, int32_t* status) {
+  __shared__ double smax[16];
+  __shared__ int sidx[16];
+  __shared__ int piv;
+  const int w2 = 2 * kp;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int r = c + threadIdx.x; r < kp; r += blockDim.x) {
+    const double2 v = Aug[(int64_t)r * w2 + c];
+    const double m = v.x * v.x + v.y * v.y;
+    if (m > best) {
+      best = m;
+      bi = r;
+    }
+  }
+  // block arg-max (ties -> lowest row)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    double ob = __shfl_xor(best, o, 64);
+    int oi = __shfl_xor(bi, o, 64);
+    if (ob > best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    smax[w] = best;
+    sidx[w] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = -1.0;
+    int i = 0x7fffffff;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q)
+      if (smax[q] > b || (smax[q] == b && sidx[q] < i)) {
+        b = smax[q];
+        i = sidx[q];
+      }
+    if (!(b > 0.0)) {
+      atomicOr(status, GFO_STATUS_SINGULAR);
+      i = c;
+    }
+    piv = i;
+  }
+  __syncthreads();
+  const int p = piv;
+  if (p != c) {
+    for (int j = threadIdx.x; j < w2; j += blockDim.x) {
+      const double2 t = Aug[(int64_t)c * w2 + j];
+      Aug[(int64_t)c * w2 + j] = Aug[(int64_t)p * w2 + j];
+      Aug[(int64_t)p * w2 + j] = t;
+    }
+  }
+  __syncthreads();
+  const double2 d = Aug[(int64_t)c * w2 + c];
+  const double n = d.x * d.x + d.y * d.y;
+  const double2 inv = n > 0.0 ? make_double2(d.x / n, -d.y / n) : make_double2(1.0, 0.0);
+  __syncthreads();
+  for (int j = threadIdx.x; j < w2; j += blockDim.x) {
+    const int64_t o = (int64_t)c * w2 + j;
+    Aug[o] = cmul(Aug[o], inv);
+  }
+  for (int r = threadIdx.x; r < kp; r += blockDim.x) f[r] = Aug[(int64_t)r * w2 + c];
+}
+
+// Gauss-Jordan column c: eliminate column c from every other row.
+__global__ void k_gj_elim(double2* __restrict__ Aug, int kp, int c, const double2* __restrict__ f) {
+  const int w2 = 2 * kp;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)kp * w2) return;
+  const int r = (int)(t / w2), j = (int)(t - (int64_t)r * w2);
+  if (r == c) return;
+  const double2 fr = f[r];
+  const double2 pc = Aug[(int64_t)c * w2 + j];
+  const double2 v = Aug[t];
+  Aug[t] = make_double2(v.x - (fr.x * pc.x - fr.y * pc.y), v.y - (fr.x * pc.y + fr.y * pc.x));
+}
+
+// ------------------------------------------------------------------ FP64 MFMA complex GEMM
+// C(m, n) = sum_k A(m, k) B(k, n), complex FP64, A row-major (lda).
+// B(k, n) = Bp[k * ldb + n] (BT = false) or Bp[n * ldb + k] (BT = true).
+// Workgroup 256 threads = 4 waves, tile 64 x 64; each wave 32 x 32 = 2 x 2
+// v_mfma_f64_16x16x4 tiles, with separate real and imaginary accumulators:
+//   re += Ar Br - Ai Bi,  im += Ar Bi + Ai Br.
+// Operand layout of the 16x16x4 FP64 instruction (one value per lane):
+//   A(i, k): i = lane % 16, k = lane / 16;  B(k, j): j = lane % 16, k = lane / 16;
+//   D(i, j): j = lane % 16, i = 4 * (lane / 16) + element.
+struct EpiStoreZ {
+  double2* Z;
+  int64_t ldz;
+  __device__ void operator()(int m, int n, double2 v) const { Z[(int64_t)m * ldz + n] = v; }
+};
+
+template <typename T>
+struct EpiG0 {
+  Geo g;
+  const double2* table;
+  const double* mon_xy;
+  T* G;
+  double2* diag64;
+  __device__ void operator()(int m, int n, double2 v) const {
+    const double2 g0 = g0_entry(g, table, mon_xy, m, n);
+    const double2 val = make_double2(g0.x + v.x, g0.y + v.y);
+    G[(int64_t)m * g.ld + n] = St<T>::from_d(val);
+    if (m == n) diag64[m] = val;
+  }
+};
+
+template <bool BT, typename Epi>
+__global__ __launch_bounds__(256) void k_zgemm_f64(int M, int N, int K, const double2* __restrict__ A,
+                                                   int64_t lda, const double2* __restrict__ B,
+                                                   int64_t ldb, Epi epi) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
+  const int n0 = blockIdx.x * 64 + (w & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 re[2][2], im[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      re[t][u] = (f64x4){0.0, 0.0, 0.0, 0.0};
+      im[t][u] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    }
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int kk = k0 + lk;
+    double2 a[2], b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int row = m0 + 16 * t + li;
+      a[t] = (row < M && kk < K) ? A[(int64_t)row * lda + kk] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int col = n0 + 16 * u + li;
+      if (col < N && kk < K)
+        b[u] = BT ? B[(int64_t)col * ldb + kk] : B[(int64_t)kk * ldb + col];
+      else
+        b[u] = make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        re[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t].x, b[u].x, re[t][u], 0, 0, 0);
+        re[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[t].y, b[u].y, re[t][u], 0, 0, 0);
+        im[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t].x, b[u].y, im[t][u], 0, 0, 0);
+        im[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t].y, b[u].x, im[t][u], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = m0 + 16 * t + 4 * lk + e;
+        const int col = n0 + 16 * u + li;
+        if (row < M && col < N) epi(row, col, make_double2(re[t][u][e], im[t][u][e]));
+      }
+}
+
+// x = M Einc[V] (k-vector), then E[r] = Einc[r] + sum_i U[r, i] x_i.
+__global__ void k_rf_xE(Geo g, const double* __restrict__ mon_xy, const int32_t* __restrict__ V,
+                        const double2* __restrict__ Aug, int k, int kp, double2* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kp) return;
+  double2 s = make_double2(0.0, 0.0);
+  if (i < k)
+    for (int j = 0; j < k; ++j)
+      s = cadd(s, cmul(Aug[(int64_t)i * 2 * kp + kp + j], incident(g, mon_xy, V[j])));
+  x[i] = s;
+}
+
+template <typename T>
+__global__ void k_rf_field(Geo g, const double* __restrict__ mon_xy, const double2* __restrict__ U,
+                           const double2* __restrict__ x, int k, int kp, T* __restrict__ E) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= g.R) return;
+  double2 s = incident(g, mon_xy, r);
+  for (int i = 0; i < k; ++i) s = cadd(s, cmul(U[(int64_t)r * kp + i], x[i]));
+  E[r] = St<T>::from_d(s);
+}
+
+template <typename T>
+static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {
+  char* w = (char*)st->work;
+  const double2* table = (const double2*)(w + L.table);
+  const double* mon = (const double*)(w + L.mon_xy);
+  int32_t* V = (int32_t*)(w + L.rf_V);
+  double2* U = (double2*)(w + L.rf_U);
+  double2* Aug = (double2*)(w + L.rf_A);
+  double2* f = (double2*)(w + L.rf_piv);
+  double2* Z = (double2*)(w + L.rf_Z);
+  double2* x = (double2*)(w + L.rf_x);
+  hipLaunchKernelGGL(k_rf_list, dim3(1), dim3(1024), 0, s, g, (const uint8_t*)st->eps_idx, V);
+  int32_t k = 0;
+  if (hipMemcpyAsync(&k, V + g.N, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GFO_EHIP;
+  if (k > st->kmax) {
+    hipLaunchKernelGGL(k_rf_overflow, dim3(1), dim3(64), 0, s, st->status);
+    return hipGetLastError() == hipSuccess ? GFO_OK : GFO_EHIP;
+  }
+  const int kp = (k + 3) / 4 * 4;
+  if (kp > 0) {
+    const int64_t nu = (int64_t)g.R * kp;
+    hipLaunchKernelGGL(k_rf_gather_U, dim3((unsigned)((nu + 255) / 256)), dim3(256), 0, s, g, table,
+                       mon, (const int32_t*)V, k, kp, U);
+    const int64_t na = (int64_t)kp * 2 * kp;
+    hipLaunchKernelGGL(k_rf_build_aug, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, g,
+                       (const uint8_t*)st->eps_idx, (const int32_t*)V, (const double2*)U, k, kp, Aug);
+    for (int c = 0; c < kp; ++c) {
+      hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, Aug, kp, c, f, st->status);
+      hipLaunchKernelGGL(k_gj_elim, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, Aug, kp, c,
+                         (const double2*)f);
+    }
+    // Z = U M, M = right half of Aug (row-major, ld 2kp)
+    EpiStoreZ ez{Z, kp};
+    hipLaunchKernelGGL((k_zgemm_f64<false, EpiStoreZ>), dim3((kp + 63) / 64, (g.R + 63) / 64),
+                       dim3(256), 0, s, g.R, kp, kp, (const double2*)U, (int64_t)kp,
+                       (const double2*)(Aug + kp), (int64_t)2 * kp, ez);
+    hipLaunchKernelGGL(k_rf_xE, dim3((kp + 255) / 256), dim3(256), 0, s, g, mon, (const int32_t*)V,
+                       (const double2*)Aug, k, kp, x);
+  }
+  hipLaunchKernelGGL(k_rf_field<T>, dim3((g.R + 255) / 256), dim3(256), 0, s, g, mon,
+                     (const double2*)U, (const double2*)x, k, kp, (T*)st->E);
+  // G = G0 + Z U_D^T over the N design columns (padding columns stay zero)
+  EpiG0<T> eg{g, table, mon, (T*)st->G, (double2*)st->diag64};
+  hipLaunchKernelGGL((k_zgemm_f64<true, EpiG0<T>>), dim3((g.N + 63) / 64, (g.R + 63) / 64),
+                     dim3(256), 0, s, g.R, g.N, kp, (const double2*)Z, (int64_t)kp,
+                     (const double2*)U, (int64_t)kp, eg);
+  return hipGetLastError() == hipSuccess ? GFO_OK : GFO_EHIP;
+}
+
+int launch_refresh(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {
+  if (g.dtype == GFO_C64) return refresh_typed<float2>(g, st, L, s);
+  return refresh_typed<double2>(g, st, L, s);
+}
+
 }  // namespace gfo

@@ -70,6 +70,12 @@ def main():
         rng = np.random.default_rng(0)
         sample = np.sort(rng.choice(p.n, 64, replace=False))
         write(p, "T2", steps, os.path.join(HERE, "square128_fp64.json"), 100, sample)
+    elif which == "strip":
+        p = W.STRIP_48x2048.replace(tau=1e-9)
+        steps = int(sys.argv[2]) if len(sys.argv) > 2 else p.steps
+        rng = np.random.default_rng(0)
+        sample = np.sort(rng.choice(p.n, 64, replace=False))
+        write(p, "T2", steps, os.path.join(HERE, "strip48x2048_fp64.json"), 50, sample)
     else:
         raise SystemExit(f"unknown golden {which}")
 
