@@ -70,14 +70,41 @@ def run_steps(job, target, poll, events=None, refresh_every=0):
     return accepted, calls, restarts, flags
 
 
-def time_workload(problem, steps, warmup, poll, with_events=True):
+def copy_ceiling(nbytes=2 << 30, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes / time) with torch's copy kernel."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def time_workload(problem, steps, warmup, poll, with_events=True, autotune=True):
     import torch
     from paper_2202_05388_amd.hiprt import EventPool
     from paper_2202_05388_amd.job import Job
+    from paper_2202_05388_amd import autotune as at
 
     kmax = max(problem.refresh_every, 0) * 2 if problem.refresh_every else 0
     job = Job(problem, device="cuda:0", kmax=kmax)
     job.init()
+    tuned = None
+    if autotune:
+        tuned = at.tune(job, reps=6, save=False)
+        _log(f"[bench] autotune {problem.dtype}: {tuned['name']} {tuned['us']:.1f} us "
+             f"({tuned['gbs']:.0f} GB/s) in {tuned['seconds']:.1f} s")
+        job.init()
     if warmup:
         run_steps(job, warmup, poll, refresh_every=problem.refresh_every)
     job.init()
@@ -99,7 +126,8 @@ def time_workload(problem, steps, warmup, poll, with_events=True):
     del job
     torch.cuda.empty_cache()
     return dict(accepted=acc, calls=calls, restarts=restarts, seconds=t1 - t0, k1_ms=k1_ms,
-                status=st, fom_last=fom, last_run_pixels=[int(x) for x in hist[:, 0]])
+                status=st, fom_last=fom, last_run_pixels=[int(x) for x in hist[:, 0]],
+                k1_variant=None if tuned is None else tuned["name"])
 
 
 def cpu_baseline(problem, max_steps):
@@ -131,10 +159,13 @@ def main():
     ap.add_argument("--workload", default="square128_c64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also time a plain 2 GiB device copy (HBM ceiling, counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU row sharding "
-                                   "is a design, not a build (see DESIGN.md)", "n_gpus": args.gpus}))
+                                   "is a design only", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import workloads as W
@@ -142,7 +173,12 @@ def main():
     problem = W.WORKLOADS[args.workload]
     _log(f"[bench] {problem.name}: {problem.ny}x{problem.nx}, {problem.n_mon} monitors, "
          f"{problem.dtype}, steps={args.steps} warmup={args.warmup}")
-    res = time_workload(problem, args.steps, args.warmup, args.poll)
+    copy_gbs = None
+    if args.calib_copy:
+        copy_gbs = copy_ceiling()
+        _log(f"[bench] device copy ceiling {copy_gbs:.0f} GB/s")
+    res = time_workload(problem, args.steps, args.warmup, args.poll,
+                        autotune=not args.no_autotune)
     N, R = problem.n, problem.rows
     elem = 8 if problem.dtype == "c64" else 16
     bytes_per_launch = 2 * elem * N * R            # one read + one write of every stored entry
@@ -156,7 +192,7 @@ def main():
     if not args.no_fp64_plain and problem.dtype == "c64" and problem.name.startswith("square128"):
         pp = W.SQUARE_128_FP64
         _log(f"[bench] plain FP64 loop {pp.name}")
-        r2 = time_workload(pp, args.steps, args.warmup, args.poll)
+        r2 = time_workload(pp, args.steps, args.warmup, args.poll, autotune=not args.no_autotune)
         plain = dict(workload=pp.name, value=r2["accepted"] / r2["seconds"], unit="steps/s",
                      ms_per_step=1e3 * r2["seconds"] / r2["accepted"],
                      k1_us=r2["k1_ms"] * 1e3,
@@ -198,7 +234,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_rank1 (streaming rank-1 update)",
-                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": res["k1_ms"] * 1e3},
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": res["k1_ms"] * 1e3,
+                     "variant": res["k1_variant"], "copy_ceiling_gbs": copy_gbs},
         "fp64_plain": plain,
         "cpu_baseline": cpu,
         "accuracy": accuracy,

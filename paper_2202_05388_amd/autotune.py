@@ -1,0 +1,138 @@
+"""Autotuner for the streaming rank-1 kernel of apply_flip.
+
+Times every tile variant the library exposes on the real problem shape with HIP
+events recorded around the kernel alone, picks the fastest, and caches the
+choice as JSON keyed by (architecture, N, R, storage type).  All variants
+compute bit-identical results (tests/test_gpu_step.py checks this), so the
+choice affects speed only.
+
+Cache path: $GFO_AUTOTUNE_CACHE, else ~/.cache/gfo/autotune.json.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+from . import _lib as L
+
+ARCH = "gfx950"
+
+
+def cache_path() -> str:
+    return os.environ.get("GFO_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "gfo", "autotune.json"))
+
+
+def _key(N: int, R: int, dtype: str) -> str:
+    return f"{ARCH}/N{N}/R{R}/{dtype}"
+
+
+def load_cache() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(d: dict) -> None:
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_k1_variants(job, reps: int = 10, warm: int = 2, variants=None) -> list:
+    """Average kernel time (us) of each variant on `job`'s shape.
+
+    Uses two alternating moves on pixel 0 (to material 1 and back), so the job's
+    structure is unchanged after an even number of calls.
+    """
+    import torch
+    from .hiprt import EventPool
+
+    code = L.GFO_C64 if job.dtype_name == "c64" else L.GFO_C128
+    names = L.k1_variants(code)
+    idxs = range(len(names)) if variants is None else variants
+    base = job.picks.data_ptr()
+    job.set_pick(0, 1, slot=0)
+    job.set_pick(0, 0, slot=1)
+    torch.cuda.synchronize()
+    old = L.k1_get_variant(code)
+    out = []
+    try:
+        for vi in idxs:
+            L.k1_set_variant(code, vi)
+            for i in range(warm):
+                job.apply(pick_ptr=base + (i % 2) * L.PICK_BYTES)
+            ev = EventPool(reps)
+            for i in range(reps):
+                a, b = ev.next()
+                L.time_next_k1(a, b)
+                job.apply(pick_ptr=base + ((warm + i) % 2) * L.PICK_BYTES)
+            if (warm + reps) % 2:
+                job.apply(pick_ptr=base + L.PICK_BYTES)
+            ms = ev.elapsed_ms()
+            ev.close()
+            out.append(dict(variant=vi, name=names[vi], us=1e3 * sum(ms) / len(ms),
+                            us_min=1e3 * min(ms)))
+    finally:
+        L.k1_set_variant(code, old)
+    return out
+
+
+def tune(job, reps: int = 10, save: bool = True) -> dict:
+    """Time all variants on this job's shape, select and cache the fastest."""
+    t0 = time.time()
+    res = time_k1_variants(job, reps=reps)
+    elem = 8 if job.dtype_name == "c64" else 16
+    bytes_per = 2 * elem * job.N * job.R
+    for r in res:
+        r["gbs"] = bytes_per / (r["us"] * 1e-6) / 1e9
+    best = min(res, key=lambda r: r["us"])
+    code = L.GFO_C64 if job.dtype_name == "c64" else L.GFO_C128
+    L.k1_set_variant(code, best["variant"])
+    entry = dict(variant=best["variant"], name=best["name"], us=best["us"], gbs=best["gbs"],
+                 seconds=time.time() - t0, all=res)
+    if save:
+        d = load_cache()
+        d[_key(job.N, job.R, job.dtype_name)] = entry
+        save_cache(d)
+    return entry
+
+
+def apply_cached(job) -> bool:
+    """Select the cached variant for this job's shape, if any.  Returns True if found."""
+    e = load_cache().get(_key(job.N, job.R, job.dtype_name))
+    if not e:
+        return False
+    code = L.GFO_C64 if job.dtype_name == "c64" else L.GFO_C128
+    names = L.k1_variants(code)
+    if e["variant"] < len(names) and names[e["variant"]] == e["name"]:
+        L.k1_set_variant(code, e["variant"])
+        return True
+    return False
+
+
+if __name__ == "__main__":
+    import argparse
+    import sys
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import workloads as W
+    from .job import Job
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="square128_c64")
+    ap.add_argument("--reps", type=int, default=10)
+    args = ap.parse_args()
+    p = W.WORKLOADS[args.workload]
+    job = Job(p, device="cuda:0")
+    job.init()
+    e = tune(job, reps=args.reps)
+    for r in sorted(e["all"], key=lambda r: r["us"]):
+        print(f"{r['name']:>16s} {r['us']:9.1f} us {r['gbs']:7.0f} GB/s", flush=True)
+    print(json.dumps({k: v for k, v in e.items() if k != "all"}))

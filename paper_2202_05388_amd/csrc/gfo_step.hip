@@ -255,40 +255,83 @@ template <> struct Vec16<double2> {
 
 constexpr int kK1Threads = 256;
 
-template <typename T, int RB, int U, bool NT>
+// Workgroup tile: RB rows x (256 threads x CPT chunks x 16 bytes).  Thread t
+// owns chunks at column offsets (t + c*256)*VN, c < CPT, so every load
+// instruction of the workgroup covers 4 KB of one row contiguously.  U rows
+// are in flight per batch; PIPE = true issues the loads of the next batch
+// before the stores of the current one.
+template <typename T, int RB, int U, int CPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(kK1Threads) void k_rank1(int R, int64_t ld, int ncoltiles,
                                                       const Snap* __restrict__ snap,
                                                       const T* __restrict__ cu,
                                                       const T* __restrict__ v, T* __restrict__ G) {
   using V = typename Vec16<T>::type;
   constexpr int VN = Vec16<T>::n;
+  static_assert(RB % U == 0, "RB must be a multiple of U");
   if (snap->j < 0) return;
   const int ct = blockIdx.x % ncoltiles;
   const int rt = blockIdx.x / ncoltiles;
-  const int64_t q = (int64_t)ct * (kK1Threads * VN) + threadIdx.x * VN;
-  if (q >= ld) return;
-  const V vv = *reinterpret_cast<const V*>(v + q);
+  const int64_t qb = (int64_t)ct * (kK1Threads * VN * CPT) + threadIdx.x * VN;
+  V vv[CPT];
+  bool ok[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const int64_t q = qb + (int64_t)c * kK1Threads * VN;
+    ok[c] = q < ld;
+    vv[c] = ok[c] ? *reinterpret_cast<const V*>(v + q) : V{};
+  }
   const int r0 = rt * RB;
-#pragma unroll 1
-  for (int rr = 0; rr < RB; rr += U) {
-    V gv[U];
-    T cv[U];
+  auto load_batch = [&](int rr, V (&gv)[U][CPT], T (&cv)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int r = r0 + rr + u;
       if (r < R) {
         cv[u] = cu[r];
-        V* p = reinterpret_cast<V*>(G + (int64_t)r * ld + q);
-        gv[u] = NT ? __builtin_nontemporal_load(p) : *p;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          if (ok[c]) {
+            V* p = reinterpret_cast<V*>(G + (int64_t)r * ld + qb + (int64_t)c * kK1Threads * VN);
+            gv[u][c] = NT ? __builtin_nontemporal_load(p) : *p;
+          }
+        }
       }
     }
+  };
+  auto store_batch = [&](int rr, V (&gv)[U][CPT], T (&cv)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int r = r0 + rr + u;
       if (r < R) {
-        V* p = reinterpret_cast<V*>(G + (int64_t)r * ld + q);
-        const V o = Vec16<T>::fma(cv[u], vv, gv[u]);
-        if (NT) __builtin_nontemporal_store(o, p); else *p = o;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+          if (ok[c]) {
+            V* p = reinterpret_cast<V*>(G + (int64_t)r * ld + qb + (int64_t)c * kK1Threads * VN);
+            const V o = Vec16<T>::fma(cv[u], vv[c], gv[u][c]);
+            if (NT) __builtin_nontemporal_store(o, p); else *p = o;
+          }
+        }
+      }
+    }
+  };
+  if constexpr (!PIPE) {
+#pragma unroll 1
+    for (int rr = 0; rr < RB; rr += U) {
+      V gv[U][CPT];
+      T cv[U];
+      load_batch(rr, gv, cv);
+      store_batch(rr, gv, cv);
+    }
+  } else {
+    V ga[U][CPT], gb[U][CPT];
+    T ca[U], cb[U];
+    load_batch(0, ga, ca);
+#pragma unroll 1
+    for (int rr = 0; rr < RB; rr += 2 * U) {
+      if (rr + U < RB) load_batch(rr + U, gb, cb);
+      store_batch(rr, ga, ca);
+      if (rr + U < RB) {
+        if (rr + 2 * U < RB) load_batch(rr + 2 * U, ga, ca);
+        store_batch(rr + U, gb, cb);
       }
     }
   }
@@ -296,33 +339,38 @@ __global__ __launch_bounds__(kK1Threads) void k_rank1(int R, int64_t ld, int nco
 
 struct K1Variant {
   const char* name;
-  int rb;
   void (*launch)(int R, int64_t ld, const Snap*, const void*, const void*, void*, hipStream_t);
 };
 
-template <typename T, int RB, int U, bool NT>
+template <typename T, int RB, int U, int CPT, bool NT, bool PIPE>
 static void launch_k1(int R, int64_t ld, const Snap* snap, const void* cu, const void* v, void* G,
                       hipStream_t s) {
   constexpr int VN = Vec16<T>::n;
-  const int ncol = (int)((ld + kK1Threads * VN - 1) / (kK1Threads * VN));
+  constexpr int cols = kK1Threads * VN * CPT;
+  const int ncol = (int)((ld + cols - 1) / cols);
   const int nrow = (R + RB - 1) / RB;
-  hipLaunchKernelGGL((k_rank1<T, RB, U, NT>), dim3((unsigned)(ncol * nrow)), dim3(kK1Threads), 0, s,
-                     R, ld, ncol, snap, (const T*)cu, (const T*)v, (T*)G);
+  hipLaunchKernelGGL((k_rank1<T, RB, U, CPT, NT, PIPE>), dim3((unsigned)(ncol * nrow)),
+                     dim3(kK1Threads), 0, s, R, ld, ncol, snap, (const T*)cu, (const T*)v, (T*)G);
 }
 
-#define K1V(T, RB, U, NT, NAME) {NAME, RB, launch_k1<T, RB, U, NT>}
-static const K1Variant kK1c64[] = {
-    K1V(float2, 16, 8, false, "16x8"),     K1V(float2, 32, 8, false, "32x8"),
-    K1V(float2, 16, 8, true, "16x8_nt"),   K1V(float2, 32, 8, true, "32x8_nt"),
-    K1V(float2, 64, 16, false, "64x16"),   K1V(float2, 8, 8, false, "8x8"),
-    K1V(float2, 32, 16, true, "32x16_nt"), K1V(float2, 64, 8, true, "64x8_nt"),
-};
-static const K1Variant kK1c128[] = {
-    K1V(double2, 16, 8, false, "16x8"),     K1V(double2, 32, 8, false, "32x8"),
-    K1V(double2, 16, 8, true, "16x8_nt"),   K1V(double2, 32, 8, true, "32x8_nt"),
-    K1V(double2, 64, 16, false, "64x16"),   K1V(double2, 8, 8, false, "8x8"),
-    K1V(double2, 32, 16, true, "32x16_nt"), K1V(double2, 64, 8, true, "64x8_nt"),
-};
+// name: rows-per-workgroup x rows-in-flight x 16B-chunks-per-thread [_nt] [_pipe]
+#define K1V(T, RB, U, CPT, NT, PIPE, NAME) {NAME, launch_k1<T, RB, U, CPT, NT, PIPE>}
+#define K1_TABLE(T)                                                                         \
+  {                                                                                         \
+    K1V(T, 16, 8, 1, false, false, "16x8x1"), K1V(T, 32, 8, 1, false, false, "32x8x1"),     \
+    K1V(T, 16, 8, 1, true, false, "16x8x1_nt"), K1V(T, 32, 8, 1, true, false, "32x8x1_nt"), \
+    K1V(T, 64, 16, 1, false, false, "64x16x1"), K1V(T, 8, 8, 1, false, false, "8x8x1"),     \
+    K1V(T, 32, 16, 1, true, false, "32x16x1_nt"), K1V(T, 64, 8, 1, true, false, "64x8x1_nt"), \
+    K1V(T, 16, 4, 2, false, false, "16x4x2"), K1V(T, 32, 4, 2, true, false, "32x4x2_nt"),   \
+    K1V(T, 16, 8, 2, false, false, "16x8x2"), K1V(T, 64, 4, 4, false, false, "64x4x4"),     \
+    K1V(T, 4, 4, 4, false, false, "4x4x4"), K1V(T, 2, 2, 8, false, false, "2x2x8"),         \
+    K1V(T, 1, 1, 16, false, false, "1x1x16"), K1V(T, 32, 4, 1, false, true, "32x4x1_pipe"), \
+    K1V(T, 64, 8, 1, false, true, "64x8x1_pipe"), K1V(T, 32, 4, 2, false, true, "32x4x2_pipe"), \
+    K1V(T, 64, 8, 1, true, true, "64x8x1_nt_pipe"), K1V(T, 16, 2, 4, true, true, "16x2x4_nt_pipe"), \
+  }
+static const K1Variant kK1c64[] = K1_TABLE(float2);
+static const K1Variant kK1c128[] = K1_TABLE(double2);
+#undef K1_TABLE
 #undef K1V
 static std::atomic<int> g_k1_sel[2] = {{0}, {0}};
 static std::atomic<hipEvent_t> g_k1_before{nullptr}, g_k1_after{nullptr};

@@ -143,22 +143,27 @@ class Job:
 
     def run_greedy(self, max_steps, poll_every=32, refresh_every=0, stream=None):
         """Greedy loop.  Steps are issued without host synchronisation; after
-        each chunk of `poll_every` steps the accepted-move counter is read and
-        the loop stops once a step found no improving move (that step and any
-        later ones in its chunk are no-ops on the device).  With refresh_every
-        > 0, refresh_G runs after every refresh_every accepted moves.
-        Returns the number of accepted moves."""
+        each chunk of at most `poll_every` steps the accepted-move counter is
+        read and the loop stops once a step found no improving move (that step
+        and any later ones in its chunk are no-ops on the device).  With
+        refresh_every > 0, refresh_G runs whenever the number of moves accepted
+        since init_G0 reaches a multiple of refresh_every.
+        Returns the number of moves accepted by this call."""
         start = self.n_flips()
+        acc = start
         done = 0
         while done < max_steps:
             chunk = min(poll_every, max_steps - done)
             if refresh_every:
-                chunk = min(chunk, refresh_every - done % refresh_every)
+                chunk = min(chunk, refresh_every - acc % refresh_every)
             for _ in range(chunk):
                 self.step(stream)
             done += chunk
-            if self.n_flips() - start < done:
+            now = self.n_flips()
+            stopped = now - acc < chunk
+            acc = now
+            if stopped:
                 break
-            if refresh_every and done % refresh_every == 0:
+            if refresh_every and acc % refresh_every == 0:
                 self.refresh(stream)
-        return self.n_flips() - start
+        return acc - start
