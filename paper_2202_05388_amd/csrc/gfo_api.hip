@@ -67,8 +67,9 @@ Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   L.snap = take(sizeof(Snap));
   L.cu = take(R * 16);
   L.v = take((size_t)ld * 16);
-  L.rk_S = take(K * 16 + 256);
+  L.rk_S = take(4096);
   L.rk_M = take(K * K * 16);
+  L.rk_U64 = take(R * K * 16);
   L.rk_A = take(R * 2 * K * 4);
   L.rk_B = take(2 * 2 * K * (size_t)ld * 4);
   L.rk_Abf = take(R * 2 * K * 2);

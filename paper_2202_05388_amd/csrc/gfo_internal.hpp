@@ -71,8 +71,9 @@ struct Layout {
   size_t cu;        // R x 16 B: c * G[:, j] (storage type)
   size_t v;         // ld x 16 B: G[j, :] (storage type), zero padded to ld
   // rank-k
-  size_t rk_S;      // GFO_MAX_RANK_K int32 pixels + alphas
+  size_t rk_S;      // header of the accepted set (pixels, contrasts, M E[S])
   size_t rk_M;      // K x K double2 (FP64 Woodbury core)
+  size_t rk_U64;    // R x K double2: G[:, S] in FP64
   size_t rk_A;      // R x 2K float  A operand [Re U | Im U] (U = G[:, S])
   size_t rk_B;      // 2 x 2K x ld float: B operands for the re and im outputs
   size_t rk_Abf;    // R x 2K bf16
