@@ -211,7 +211,7 @@ __global__ void k_gj_elim(double2* __restrict__ Aug, int kp, int c, const double
 //   re += Ar Br - Ai Bi,  im += Ar Bi + Ai Br.
 // Operand layout of the 16x16x4 FP64 instruction (one value per lane):
 //   A(i, k): i = lane % 16, k = lane / 16;  B(k, j): j = lane % 16, k = lane / 16;
-//   D(i, j): j = lane % 16, i = 4 * (lane / 16) + element.
+//   D(i, j): j = lane % 16, i = lane / 16 + 4 * element  (checked on gfx950).
 struct EpiStoreZ {
   double2* Z;
   int64_t ldz;
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(256) void k_zgemm_f64(int M, int N, int K, const do
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int row = m0 + 16 * t + 4 * lk + e;
+        const int row = m0 + 16 * t + lk + 4 * e;
         const int col = n0 + 16 * u + li;
         if (row < M && col < N) epi(row, col, make_double2(re[t][u][e], im[t][u][e]));
       }

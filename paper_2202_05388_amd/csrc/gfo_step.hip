@@ -367,6 +367,11 @@ static void launch_k1(int R, int64_t ld, const Snap* snap, const void* cu, const
     K1V(T, 1, 1, 16, false, false, "1x1x16"), K1V(T, 32, 4, 1, false, true, "32x4x1_pipe"), \
     K1V(T, 64, 8, 1, false, true, "64x8x1_pipe"), K1V(T, 32, 4, 2, false, true, "32x4x2_pipe"), \
     K1V(T, 64, 8, 1, true, true, "64x8x1_nt_pipe"), K1V(T, 16, 2, 4, true, true, "16x2x4_nt_pipe"), \
+    K1V(T, 8, 8, 1, true, false, "8x8x1_nt"), K1V(T, 4, 4, 1, true, false, "4x4x1_nt"),       \
+    K1V(T, 8, 4, 2, true, false, "8x4x2_nt"), K1V(T, 4, 4, 2, true, false, "4x4x2_nt"),       \
+    K1V(T, 8, 8, 2, true, false, "8x8x2_nt"), K1V(T, 2, 2, 4, true, false, "2x2x4_nt"),       \
+    K1V(T, 16, 16, 1, true, false, "16x16x1_nt"), K1V(T, 4, 4, 4, true, false, "4x4x4_nt"),   \
+    K1V(T, 32, 8, 1, true, true, "32x8x1_nt_pipe"), K1V(T, 16, 4, 1, true, true, "16x4x1_nt_pipe"), \
   }
 static const K1Variant kK1c64[] = K1_TABLE(float2);
 static const K1Variant kK1c128[] = K1_TABLE(double2);
