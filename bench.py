@@ -25,6 +25,31 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the streaming rank-1 kernel from rocprofv3 counter runs
+# (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by the value the same
+# counter reports for a device copy of exactly 2 GiB (FETCH 1048599.75 KiB ->
+# factor 2.0; WRITE 2097152 KiB -> factor 1.0).  Valid only for the kernel source
+# and variant it was measured on: any change to the source file voids it.
+PMC_TRAFFIC = {
+    "source": "paper_2202_05388_amd/csrc/gfo_step.hip",
+    "sha256": None,
+    "workload": "square128_c64",
+    "variant": "4x4x1_nt",
+    "fetch_kib": None, "fetch_scale": 2097152.0 / 1048599.75,
+    "write_kib": None, "write_scale": 1.0,
+}
+
+
+def pmc_traffic(workload, variant):
+    import hashlib
+    rec = PMC_TRAFFIC
+    if rec["sha256"] is None or rec["workload"] != workload or rec["variant"] != variant:
+        return None
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
+            return None
+    return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+
 
 def _log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -232,7 +257,9 @@ def main():
                    "refresh_every": problem.refresh_every, "candidates": "eps {1, 12.25}",
                    "restarts_in_timed_region": res["restarts"], "step_calls": res["calls"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": pmc_traffic(problem.name, res["k1_variant"]),
+                     "traffic_unit": "bytes/launch",
                      "kernel": "k_rank1 (streaming rank-1 update)",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": res["k1_ms"] * 1e3,
                      "variant": res["k1_variant"], "copy_ceiling_gbs": copy_gbs},

@@ -353,10 +353,13 @@ static void launch_k1(int R, int64_t ld, const Snap* snap, const void* cu, const
                      dim3(kK1Threads), 0, s, R, ld, ncol, snap, (const T*)cu, (const T*)v, (T*)G);
 }
 
-// name: rows-per-workgroup x rows-in-flight x 16B-chunks-per-thread [_nt] [_pipe]
+// name: rows-per-workgroup x rows-in-flight x 16B-chunks-per-thread [_nt] [_pipe].
+// Entry 0 is the default: the fastest on the 128x128 problem on MI355X for both
+// storage types (4 rows per short-lived workgroup, non-temporal loads and stores).
 #define K1V(T, RB, U, CPT, NT, PIPE, NAME) {NAME, launch_k1<T, RB, U, CPT, NT, PIPE>}
 #define K1_TABLE(T)                                                                         \
   {                                                                                         \
+    K1V(T, 4, 4, 1, true, false, "4x4x1_nt"),                                              \
     K1V(T, 16, 8, 1, false, false, "16x8x1"), K1V(T, 32, 8, 1, false, false, "32x8x1"),     \
     K1V(T, 16, 8, 1, true, false, "16x8x1_nt"), K1V(T, 32, 8, 1, true, false, "32x8x1_nt"), \
     K1V(T, 64, 16, 1, false, false, "64x16x1"), K1V(T, 8, 8, 1, false, false, "8x8x1"),     \
@@ -367,7 +370,7 @@ static void launch_k1(int R, int64_t ld, const Snap* snap, const void* cu, const
     K1V(T, 1, 1, 16, false, false, "1x1x16"), K1V(T, 32, 4, 1, false, true, "32x4x1_pipe"), \
     K1V(T, 64, 8, 1, false, true, "64x8x1_pipe"), K1V(T, 32, 4, 2, false, true, "32x4x2_pipe"), \
     K1V(T, 64, 8, 1, true, true, "64x8x1_nt_pipe"), K1V(T, 16, 2, 4, true, true, "16x2x4_nt_pipe"), \
-    K1V(T, 8, 8, 1, true, false, "8x8x1_nt"), K1V(T, 4, 4, 1, true, false, "4x4x1_nt"),       \
+    K1V(T, 8, 8, 1, true, false, "8x8x1_nt"), K1V(T, 2, 2, 1, true, false, "2x2x1_nt"),       \
     K1V(T, 8, 4, 2, true, false, "8x4x2_nt"), K1V(T, 4, 4, 2, true, false, "4x4x2_nt"),       \
     K1V(T, 8, 8, 2, true, false, "8x8x2_nt"), K1V(T, 2, 2, 4, true, false, "2x2x4_nt"),       \
     K1V(T, 16, 16, 1, true, false, "16x16x1_nt"), K1V(T, 4, 4, 4, true, false, "4x4x4_nt"),   \
