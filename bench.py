@@ -155,6 +155,87 @@ def time_workload(problem, steps, warmup, poll, with_events=True, autotune=True)
                 k1_variant=None if tuned is None else tuned["name"])
 
 
+def time_rank_k(problem, steps, warmup, precision):
+    """Rank-k steps: score with top-k + spacing, then one joint Woodbury update.
+
+    `steps` counts rank-k steps that accepted at least one move; the job is
+    restarted when a step accepts none.  Polls the move counter after every
+    step (a rank-k step is ~1 ms).  Returns moves/s, steps/s and the mean time
+    of the matrix-core update kernels."""
+    import torch
+    from paper_2202_05388_amd import _lib as L
+    from paper_2202_05388_amd.hiprt import EventPool
+    from paper_2202_05388_amd.job import Job
+
+    prec = L.GFO_FP32 if precision == "fp32" else L.GFO_BF16
+    job = Job(problem, device="cuda:0", kmax=0)
+
+    def run(n, events):
+        job.init()
+        done = moves = restarts = 0
+        durations_ok = []
+        last = 0
+        while done < n:
+            if events is not None:
+                a, b = events.next()
+                L.time_next_k1(a, b)
+            job.score(topk=problem.rank_k, min_spacing=problem.min_spacing)
+            job.apply_rank_k(problem.rank_k, precision=prec)
+            now = job.n_flips()
+            durations_ok.append(now > last)
+            if now == last:
+                job.init()
+                restarts += 1
+                last = 0
+                continue
+            moves += now - last
+            last = now
+            done += 1
+        return moves, restarts, durations_ok
+
+    run(warmup, None)
+    torch.cuda.synchronize()
+    ev = EventPool(4 * steps + 16)
+    t0 = time.perf_counter()
+    moves, restarts, ok = run(steps, ev)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    d = [x for x, f in zip(ev.elapsed_ms(), ok) if f]
+    ev.close()
+    N, R = problem.n, problem.rows
+    k_ms = sum(d) / len(d)
+    out = dict(precision=precision, rank=problem.rank_k, min_spacing=problem.min_spacing,
+               steps=steps, moves=moves, restarts=restarts, moves_per_s=moves / dt,
+               steps_per_s=steps / dt, update_us=k_ms * 1e3,
+               update_gbs=16 * N * R / (k_ms * 1e-3) / 1e9,
+               update_tflops=8 * N * R * problem.rank_k / (k_ms * 1e-3) / 1e12,
+               fom_last=job.fom(), status=job.status())
+    del job
+    torch.cuda.empty_cache()
+    return out
+
+
+def time_refresh(problem):
+    """One FP64 refresh of the state the greedy trajectory ends in."""
+    import torch
+    from paper_2202_05388_amd.job import Job
+    job = Job(problem, device="cuda:0", kmax=max(2 * problem.steps, 512))
+    job.init()
+    k = job.run_greedy(problem.steps, poll_every=64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    job.refresh()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    N, R = problem.n, problem.rows
+    flips = int((job.eps_idx.cpu().numpy() != 0).sum())
+    out = dict(flipped_pixels=flips, ms=dt * 1e3,
+               gemm_tflops=8.0 * R * N * flips / dt / 1e12, status=job.status())
+    del job
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(problem, max_steps):
     """The FP64 oracle (flipped-set tier) on the same workload, host cores."""
     import numpy as np
@@ -185,6 +266,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-rank-k", action="store_true")
+    ap.add_argument("--no-refresh-timing", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=64,
+                    help="jobs in the served stream (0 = skip the serving measurement)")
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="job arrivals per second")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also time a plain 2 GiB device copy (HBM ceiling, counter calibration)")
     args = ap.parse_args()
@@ -239,6 +325,29 @@ def main():
         else:
             accuracy = dict(pixels_matching=match, compared=n)
 
+    rank_k = None
+    if not args.no_rank_k and problem.name == "square128_c64":
+        rk = W.SQUARE_128_RANK16
+        rank_k = {}
+        for prec in ("fp32", "bf16"):
+            _log(f"[bench] rank-{rk.rank_k} steps ({prec})")
+            rank_k[prec] = time_rank_k(rk, steps=100, warmup=10, precision=prec)
+            _log(f"[bench] rank-{rk.rank_k} {prec}: {rank_k[prec]}")
+
+    refresh = None
+    if not args.no_refresh_timing and problem.refresh_every:
+        _log("[bench] FP64 refresh at the end of the trajectory")
+        refresh = time_refresh(problem.replace(steps=min(problem.steps, 500)))
+        _log(f"[bench] refresh {refresh}")
+
+    serving = None
+    if args.serve_jobs > 0:
+        from paper_2202_05388_amd.serve import serve_benchmark
+        _log(f"[bench] serving {args.serve_jobs} jobs at {args.serve_rate}/s (mix, then one at a time)")
+        serving = serve_benchmark(n_jobs=args.serve_jobs, rate=args.serve_rate)
+        _log(f"[bench] serving mix {serving['mix']}")
+        _log(f"[bench] serving one-at-a-time {serving['one_at_a_time']}")
+
     out = {
         "metric": "greedy steps/s at 128^2 px (% HBM peak) vs FP64 plain; served p50/p99 latency",
         "value": value,
@@ -266,6 +375,9 @@ def main():
         "fp64_plain": plain,
         "cpu_baseline": cpu,
         "accuracy": accuracy,
+        "rank_k": rank_k,
+        "refresh": refresh,
+        "serving": serving,
         "device_status": res["status"],
     }
     if plain:

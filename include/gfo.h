@@ -186,8 +186,9 @@ const char* gfo_k1_variant_name(int32_t dtype, int32_t idx);   /* NULL if out of
 int gfo_k1_set_variant(int32_t dtype, int32_t idx);           /* GFO_EINVAL if out of range */
 int gfo_k1_get_variant(int32_t dtype);
 
-/* Timing hook: the next apply_flip (on any stream) records `before` on its
- * stream immediately before its streaming rank-1 kernel and `after`
+/* Timing hook: the next apply_flip or apply_flips_rank_k (on any stream)
+ * records `before` on its stream immediately before its G-update kernel (the
+ * streaming rank-1 kernel, or the matrix-core rank-k kernels) and `after`
  * immediately after it, then forgets both events.  Lets a caller time that
  * kernel alone with hipEventElapsedTime.  Both NULL cancels a pending pair.
  * Host only; one pending pair per process. */

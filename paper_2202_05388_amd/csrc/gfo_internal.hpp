@@ -112,5 +112,6 @@ const char* k1_variant_name(int dtype, int idx);
 int k1_set_variant(int dtype, int idx);
 int k1_get_variant(int dtype);
 void k1_time_next(hipEvent_t before, hipEvent_t after);
+void k1_take_timing(hipEvent_t* before, hipEvent_t* after);   // consumes the pending pair
 
 }  // namespace gfo

@@ -356,6 +356,9 @@ hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo
   const int ncg = (int)(g.ld / 64);
   const int nrg = (g.R + 64 * kRkRowBlocks - 1) / (64 * kRkRowBlocks);
   const dim3 grid((unsigned)(ncg * nrg));
+  hipEvent_t before, after;
+  k1_take_timing(&before, &after);
+  if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
   // the rank padding (16 or 32) is decided on the device; both instantiations are
   // launched and the one that does not match exits at once
   if (bf) {
@@ -369,6 +372,7 @@ hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo
     hipLaunchKernelGGL((k_rk_mfma<32, false>), grid, dim3(256), 0, s, g.R, g.ld, (const RkHdr*)hdr,
                        (const float*)Af, (const float*)Bf, (const __bf16*)Abf, (const __bf16*)Bbf, G);
   }
+  if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
   return hipGetLastError();
 }
 

@@ -107,13 +107,35 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(
     if (!(m > fom * (1.0 + tau))) break;
     const double thr = m - tau * m;
     int first = 0x7fffffff;
-    for (int i = threadIdx.x; i < total; i += blockDim.x) {
-      if (scores[i] >= thr) {
-        first = i;
-        break;
+    if (t == 0 && nblk * kScoreThreads >= g.N) {
+      // score workgroup b covered pixels [b*256, b*256 + 256): only workgroups whose
+      // maximum reaches the tie threshold can hold the winner; visit them in order
+      const int span = kScoreThreads * g.n_eps;
+      for (int b = 0; b < nblk; ++b) {
+        if (!(partial[b] >= thr)) continue;          // uniform across the workgroup
+        const int lo = b * span, hi = min(lo + span, total);
+        int f = 0x7fffffff;
+        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+          if (scores[i] >= thr) {
+            f = i;
+            break;
+          }
+        }
+        f = block_min(f, shi);
+        if (f != 0x7fffffff) {
+          first = f;
+          break;
+        }
       }
+    } else {
+      for (int i = threadIdx.x; i < total; i += blockDim.x) {
+        if (scores[i] >= thr) {
+          first = i;
+          break;
+        }
+      }
+      first = block_min(first, shi);
     }
-    first = block_min(first, shi);
     const int j = first / g.n_eps;
     if (threadIdx.x == 0) {
       gfo_pick pk;
@@ -354,12 +376,15 @@ static void launch_k1(int R, int64_t ld, const Snap* snap, const void* cu, const
 }
 
 // name: rows-per-workgroup x rows-in-flight x 16B-chunks-per-thread [_nt] [_pipe].
-// Entry 0 is the default: the fastest on the 128x128 problem on MI355X for both
-// storage types (4 rows per short-lived workgroup, non-temporal loads and stores).
+// Entry 0 is the default: the fastest on the 128x128 and 48x2048 problems on
+// MI355X for both storage types (2 rows per short-lived workgroup, non-temporal
+// loads and stores).
 #define K1V(T, RB, U, CPT, NT, PIPE, NAME) {NAME, launch_k1<T, RB, U, CPT, NT, PIPE>}
 #define K1_TABLE(T)                                                                         \
   {                                                                                         \
-    K1V(T, 4, 4, 1, true, false, "4x4x1_nt"),                                              \
+    K1V(T, 2, 2, 1, true, false, "2x2x1_nt"), K1V(T, 4, 4, 1, true, false, "4x4x1_nt"),     \
+    K1V(T, 1, 1, 1, true, false, "1x1x1_nt"), K1V(T, 2, 2, 2, true, false, "2x2x2_nt"),     \
+    K1V(T, 1, 1, 2, true, false, "1x1x2_nt"), K1V(T, 2, 1, 1, true, false, "2x1x1_nt"),     \
     K1V(T, 16, 8, 1, false, false, "16x8x1"), K1V(T, 32, 8, 1, false, false, "32x8x1"),     \
     K1V(T, 16, 8, 1, true, false, "16x8x1_nt"), K1V(T, 32, 8, 1, true, false, "32x8x1_nt"), \
     K1V(T, 64, 16, 1, false, false, "64x16x1"), K1V(T, 8, 8, 1, false, false, "8x8x1"),     \
@@ -370,7 +395,7 @@ static void launch_k1(int R, int64_t ld, const Snap* snap, const void* cu, const
     K1V(T, 1, 1, 16, false, false, "1x1x16"), K1V(T, 32, 4, 1, false, true, "32x4x1_pipe"), \
     K1V(T, 64, 8, 1, false, true, "64x8x1_pipe"), K1V(T, 32, 4, 2, false, true, "32x4x2_pipe"), \
     K1V(T, 64, 8, 1, true, true, "64x8x1_nt_pipe"), K1V(T, 16, 2, 4, true, true, "16x2x4_nt_pipe"), \
-    K1V(T, 8, 8, 1, true, false, "8x8x1_nt"), K1V(T, 2, 2, 1, true, false, "2x2x1_nt"),       \
+    K1V(T, 8, 8, 1, true, false, "8x8x1_nt"),                                              \
     K1V(T, 8, 4, 2, true, false, "8x4x2_nt"), K1V(T, 4, 4, 2, true, false, "4x4x2_nt"),       \
     K1V(T, 8, 8, 2, true, false, "8x8x2_nt"), K1V(T, 2, 2, 4, true, false, "2x2x4_nt"),       \
     K1V(T, 16, 16, 1, true, false, "16x16x1_nt"), K1V(T, 4, 4, 4, true, false, "4x4x4_nt"),   \
@@ -386,6 +411,11 @@ static std::atomic<hipEvent_t> g_k1_before{nullptr}, g_k1_after{nullptr};
 void k1_time_next(hipEvent_t before, hipEvent_t after) {
   g_k1_after.store(after);
   g_k1_before.store(before);
+}
+
+void k1_take_timing(hipEvent_t* before, hipEvent_t* after) {
+  *before = g_k1_before.exchange(nullptr);
+  *after = g_k1_after.exchange(nullptr);
 }
 
 static const K1Variant* k1_table(int dtype, int* n) {
@@ -452,8 +482,8 @@ static hipError_t apply_typed(const Geo& g, gfo_state* st, const Layout& L, cons
                      (const Snap*)snap, (const T*)st->G, (T*)st->E, (double2*)st->diag64, cu, v);
   int nv;
   const K1Variant* tab = k1_table(g.dtype, &nv);
-  hipEvent_t before = g_k1_before.exchange(nullptr);
-  hipEvent_t after = g_k1_after.exchange(nullptr);
+  hipEvent_t before, after;
+  k1_take_timing(&before, &after);
   if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
   tab[k1_get_variant(g.dtype)].launch(g.R, g.ld, snap, cu, v, st->G, s);
   if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
