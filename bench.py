@@ -55,7 +55,7 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_steps(job, target, poll, events=None, refresh_every=0):
+def run_steps(job, target, poll, events=None, refresh_every=0, flush_events=None):
     """Issue greedy steps until `target` accepted moves; re-init a job that stopped.
 
     Returns (accepted, calls, restarts, accepted_flags) where accepted_flags[i]
@@ -76,6 +76,9 @@ def run_steps(job, target, poll, events=None, refresh_every=0):
         for _ in range(chunk):
             if events is not None:
                 a, b = events.next()
+                L.time_next_k1(a, b)
+            elif flush_events is not None and job.state.pending_calls == job.delay - 1:
+                a, b = flush_events.next()       # this step's apply_flip ends with a flush
                 L.time_next_k1(a, b)
             job.step()
         calls += chunk
@@ -153,6 +156,43 @@ def time_workload(problem, steps, warmup, poll, with_events=True, autotune=True)
     return dict(accepted=acc, calls=calls, restarts=restarts, seconds=t1 - t0, k1_ms=k1_ms,
                 status=st, fom_last=fom, last_run_pixels=[int(x) for x in hist[:, 0]],
                 k1_variant=None if tuned is None else tuned["name"])
+
+
+def time_deferred(problem, steps, warmup, poll, delay):
+    """Greedy steps with deferred rank-1 updates: E, the FP64 diagonal and the monitor
+    rows every step, the design block by one rank-`delay` matrix-core product per
+    `delay` steps.  Times the flush kernel with HIP events on its stream."""
+    import torch
+    from paper_2202_05388_amd.hiprt import EventPool
+    from paper_2202_05388_amd.job import Job
+
+    kmax = 2 * problem.refresh_every if problem.refresh_every else 0
+    job = Job(problem, device="cuda:0", kmax=kmax, delay=delay)
+    job.init()
+    run_steps(job, warmup, poll, refresh_every=problem.refresh_every)
+    job.init()
+    torch.cuda.synchronize()
+    fev = EventPool(steps // delay + 64)
+    t0 = time.perf_counter()
+    acc, calls, restarts, flags = run_steps(job, steps, poll, None, problem.refresh_every,
+                                            flush_events=fev)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fl = fev.elapsed_ms()
+    fev.close()
+    N = problem.n
+    ld = (N + 63) // 64 * 64
+    elem = 8 if problem.dtype == "c64" else 16
+    fl_ms = sum(fl) / len(fl) if fl else None
+    out = dict(delay=delay, storage=problem.dtype, accepted=acc, restarts=restarts,
+               steps_per_s=acc / dt, ms_per_step=1e3 * dt / acc, flushes_timed=len(fl),
+               flush_us=None if fl_ms is None else fl_ms * 1e3,
+               flush_tflops=None if fl_ms is None else 8.0 * N * ld * delay / (fl_ms * 1e-3) / 1e12,
+               flush_gbs=None if fl_ms is None else 2 * elem * N * ld / (fl_ms * 1e-3) / 1e9,
+               fom_last=job.fom(), status=job.status())
+    del job
+    torch.cuda.empty_cache()
+    return out
 
 
 def time_rank_k(problem, steps, warmup, precision):
@@ -267,6 +307,8 @@ def main():
     ap.add_argument("--no-fp64-plain", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-rank-k", action="store_true")
+    ap.add_argument("--no-deferred", action="store_true")
+    ap.add_argument("--delay", type=int, default=64, help="deferred-mode flush interval")
     ap.add_argument("--no-refresh-timing", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=64,
                     help="jobs in the served stream (0 = skip the serving measurement)")
@@ -325,6 +367,17 @@ def main():
         else:
             accuracy = dict(pixels_matching=match, compared=n)
 
+    deferred = None
+    if not args.no_deferred:
+        deferred = {}
+        forms = [problem]
+        if problem.name == "square128_c64":
+            forms.append(W.SQUARE_128_FP64)
+        for pf in forms:
+            _log(f"[bench] deferred updates, {pf.name}, delay {args.delay}")
+            deferred[pf.name] = time_deferred(pf, args.steps, args.warmup, args.poll, args.delay)
+            _log(f"[bench] deferred {pf.name}: {deferred[pf.name]}")
+
     rank_k = None
     if not args.no_rank_k and problem.name == "square128_c64":
         rk = W.SQUARE_128_RANK16
@@ -375,6 +428,7 @@ def main():
         "fp64_plain": plain,
         "cpu_baseline": cpu,
         "accuracy": accuracy,
+        "deferred": deferred,
         "rank_k": rank_k,
         "refresh": refresh,
         "serving": serving,

@@ -57,6 +57,7 @@ enum {                                         /* bits of the device status word
 };
 #define GFO_MAX_EPS 8                          /* permittivity table entries */
 #define GFO_MAX_RANK_K 32                      /* largest k of apply_flips_rank_k */
+#define GFO_MAX_DELAY 64                       /* largest number of deferred rank-1 moves */
 
 /* Problem description, read during a call, not retained. */
 typedef struct {
@@ -82,6 +83,8 @@ typedef struct {
   int32_t kmax;                 /* largest flipped set refresh_G supports */
   void* work; size_t work_bytes;/* scratch, at least gfo_workspace_size() bytes, 256-B aligned */
   int32_t* status;              /* 1 int32 device status word (GFO_STATUS_* bits) */
+  int32_t delay;                /* 0: eager rank-1 updates; 1..GFO_MAX_DELAY: deferred (see apply_flip) */
+  int32_t pending_calls;        /* host counter kept by the library; set 0 before init_G0 */
 } gfo_state;
 
 /* One selected move.  pixel = -1 is the sentinel "no move improves the FOM". */
@@ -155,6 +158,22 @@ int score_candidates(const gfo_problem* prob, const gfo_state* st, uint32_t cand
  * denominator sets GFO_STATUS_SINGULAR and skips the move. */
 int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick,
                hipStream_t stream);
+
+/* Deferred mode (state.delay = r > 0).  The paper's update (eq. form10) is
+ * exact in any grouping, so apply_flip may postpone the design block: it
+ * records c G[:, j] and G[j, :] of the CURRENT matrix (base rows plus the
+ * pending terms) as pending term number s, and updates E, diag64 and the
+ * monitor rows of G at once.  score_candidates reads only those, so the move
+ * sequence is the one of eager mode.  After r apply_flip calls since the last
+ * flush, the design block is brought up to date by one rank-r product on the
+ * matrix cores (FP32 for GFO_C64, FP64 for GFO_C128); gfo_flush does the same
+ * on demand.  Until then G[0:N, :] holds the base rows only.  refresh_G
+ * discards pending terms (it rebuilds G from G0); apply_flips_rank_k flushes
+ * first. */
+
+/* gfo_flush - bring the design block of G up to date in deferred mode (no-op
+ * when nothing is pending or delay = 0). */
+int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 
 /* apply_flips_rank_k - apply k moves jointly by the Woodbury form of the
  * paper's region update (eqs. form10-form14 with V = the k pixels):

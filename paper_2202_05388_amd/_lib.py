@@ -19,12 +19,13 @@ GFO_STATUS_SINGULAR, GFO_STATUS_NONFINITE = 1, 2
 GFO_STATUS_HISTORY_FULL, GFO_STATUS_REFRESH_OVERFLOW = 4, 8
 GFO_MAX_EPS = 8
 GFO_MAX_RANK_K = 32
+GFO_MAX_DELAY = 64
 
 # every entry point that include/gfo.h declares
 EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "gfo_scores_offset",
            "init_G0", "score_candidates", "apply_flip", "apply_flips_rank_k", "refresh_G",
            "gfo_k1_variant_count", "gfo_k1_variant_name", "gfo_k1_set_variant",
-           "gfo_k1_get_variant", "gfo_time_next_k1")
+           "gfo_k1_get_variant", "gfo_time_next_k1", "gfo_flush")
 
 
 class Problem(C.Structure):
@@ -38,7 +39,8 @@ class State(C.Structure):
     _fields_ = [("G", C.c_void_p), ("ldG", C.c_int64), ("E", C.c_void_p),
                 ("diag64", C.c_void_p), ("eps_idx", C.c_void_p), ("flips", C.c_void_p),
                 ("flip_cap", C.c_int32), ("n_flips", C.c_void_p), ("kmax", C.c_int32),
-                ("work", C.c_void_p), ("work_bytes", C.c_size_t), ("status", C.c_void_p)]
+                ("work", C.c_void_p), ("work_bytes", C.c_size_t), ("status", C.c_void_p),
+                ("delay", C.c_int32), ("pending_calls", C.c_int32)]
 
 
 class Pick(C.Structure):
@@ -75,6 +77,7 @@ def lib():
     L.apply_flip.argtypes = [P, S, V, V]
     L.apply_flips_rank_k.argtypes = [P, S, V, C.c_int32, C.c_int32, V]
     L.refresh_G.argtypes = [P, S, V]
+    L.gfo_flush.argtypes = [P, S, V]
     L.gfo_k1_variant_count.argtypes = [C.c_int32]
     L.gfo_k1_variant_name.argtypes = [C.c_int32, C.c_int32]
     L.gfo_k1_variant_name.restype = C.c_char_p
@@ -133,6 +136,10 @@ def apply_flips_rank_k(prob, st, d_picks, k, gemm_precision, stream) -> None:
 
 def refresh_G(prob, st, stream) -> None:
     check(lib().refresh_G(C.byref(prob), C.byref(st), stream), "refresh_G")
+
+
+def flush(prob, st, stream) -> None:
+    check(lib().gfo_flush(C.byref(prob), C.byref(st), stream), "gfo_flush")
 
 
 def k1_variants(dtype: int):

@@ -74,6 +74,11 @@ Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   L.rk_B = take(2 * 2 * K * (size_t)ld * 4);
   L.rk_Abf = take(R * 2 * K * 2);
   L.rk_Bbf = take(2 * 2 * K * (size_t)ld * 2);
+  L.dl_hdr = take(256);
+  L.dl_CU = take((size_t)GFO_MAX_DELAY * R * 16);
+  L.dl_V = take((size_t)GFO_MAX_DELAY * (size_t)ld * 16);
+  L.dl_A = take(N * 2 * GFO_MAX_DELAY * 4);
+  L.dl_B = take((size_t)ld * 4 * GFO_MAX_DELAY * 4);
   L.rf_V = take((N + 64) * 4);
   L.rf_U = take(R * k * 16);
   L.rf_A = take(2 * k * k * 16);
@@ -94,6 +99,7 @@ static int validate_state(const gfo_problem* p, const gfo_state* st, Layout* L) 
       !st->work)
     return GFO_EINVAL;
   if (st->flip_cap < 0 || (st->flip_cap > 0 && !st->flips) || st->kmax < 0) return GFO_EINVAL;
+  if (st->delay < 0 || st->delay > GFO_MAX_DELAY || st->pending_calls < 0) return GFO_EINVAL;
   if (st->ldG < min_ld(p) || st->ldG % 64 != 0) return GFO_EINVAL;
   if (((uintptr_t)st->work & 255) != 0 || ((uintptr_t)st->G & 15) != 0) return GFO_EINVAL;
   *L = make_layout(p, st->ldG, st->kmax);
@@ -153,6 +159,8 @@ int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
                      hipMemcpyHostToDevice, stream) != hipSuccess)
     return GFO_EHIP;
   if (launch_init(g, st, L, stream) != hipSuccess) return GFO_EHIP;
+  if (launch_dl_reset(g, st, L, stream) != hipSuccess) return GFO_EHIP;
+  st->pending_calls = 0;
   if (hipStreamSynchronize(stream) != hipSuccess) return GFO_EHIP;
   return GFO_OK;
 }
@@ -182,6 +190,22 @@ int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick, h
   if (!d_pick) return GFO_EINVAL;
   const Geo g = make_geo(prob, st->ldG);
   if (launch_apply(g, st, L, d_pick, stream) != hipSuccess) return GFO_EHIP;
+  if (st->delay > 0 && ++st->pending_calls >= st->delay) {
+    if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;
+    st->pending_calls = 0;
+  }
+  return GFO_OK;
+}
+
+int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  Layout L;
+  if ((rc = validate_state(prob, st, &L))) return rc;
+  if (st->delay == 0 || st->pending_calls == 0) return GFO_OK;
+  const Geo g = make_geo(prob, st->ldG);
+  if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;
+  st->pending_calls = 0;
   return GFO_OK;
 }
 
@@ -195,6 +219,10 @@ int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d
       (gemm_precision != GFO_FP32 && gemm_precision != GFO_BF16))
     return GFO_EINVAL;
   const Geo g = make_geo(prob, st->ldG);
+  if (st->delay > 0 && st->pending_calls > 0) {
+    if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;
+    st->pending_calls = 0;
+  }
   if (launch_rank_k(g, st, L, d_picks, k, gemm_precision, stream) != hipSuccess) return GFO_EHIP;
   return GFO_OK;
 }
@@ -205,6 +233,8 @@ int refresh_G(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   Layout L;
   if ((rc = validate_state(prob, st, &L))) return rc;
   const Geo g = make_geo(prob, st->ldG);
+  if (launch_dl_reset(g, st, L, stream) != hipSuccess) return GFO_EHIP;   // pending terms discarded
+  st->pending_calls = 0;
   return launch_refresh(g, st, L, stream);
 }
 

@@ -48,7 +48,8 @@ template <> struct St<double2> {
 struct Snap {
   int32_t j;          // pixel, -1 = no move
   int32_t e_new;
-  int32_t pad0, pad1;
+  int32_t slot;       // deferred mode: index of this move's pending term
+  int32_t pad1;
   double alpha;
   double pad2;
   double2 c;          // alpha / (1 - alpha G_jj)
@@ -78,6 +79,12 @@ struct Layout {
   size_t rk_B;      // 2 x 2K x ld float: B operands for the re and im outputs
   size_t rk_Abf;    // R x 2K bf16
   size_t rk_Bbf;    // 2 x 2K x ld bf16
+  // deferred rank-1 terms (GFO_MAX_DELAY slots)
+  size_t dl_hdr;    // int32 count of pending terms
+  size_t dl_CU;     // GFO_MAX_DELAY x R x 16 B: c * G[:, j] of each pending move (storage type)
+  size_t dl_V;      // GFO_MAX_DELAY x ld x 16 B: G[j, :] of each pending move (storage type)
+  size_t dl_A;      // N x 2*GFO_MAX_DELAY float: FP32 A operand of the flush
+  size_t dl_B;      // ld x 4*GFO_MAX_DELAY float: FP32 B operands of the flush
   // refresh
   // (kp = kmax rounded up to a multiple of 4)
   size_t rf_V;      // N + 1 int32: flipped list, then its length
@@ -105,6 +112,15 @@ hipError_t launch_apply(const Geo& g, gfo_state* st, const Layout& L, const gfo_
 hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* picks,
                          int k, int precision, hipStream_t s);
 int launch_refresh(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
+hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
+template <typename T>
+hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, const Snap* snap,
+                                 hipStream_t s);
+hipError_t launch_mfma_update_f32_64(int rows, int64_t ld, const int32_t* count, const float* A,
+                                     const float* B, float2* G, hipStream_t s);
+hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const double2* CU,
+                                   const double2* V, double2* G, hipStream_t s);
+hipError_t launch_dl_reset(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
 
 // K1 variant selection (autotuner); returns number of variants
 int k1_variant_count(int dtype);

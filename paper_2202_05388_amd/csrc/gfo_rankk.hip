@@ -241,13 +241,17 @@ __global__ void k_rk_cols(Geo g, const RkHdr* __restrict__ hdr, const double2* _
 constexpr int kRkRowBlocks = 8;
 
 template <int KP, bool BF16>
-__global__ __launch_bounds__(256) void k_rk_mfma(int R, int64_t ld, const RkHdr* __restrict__ hdr,
+__global__ __launch_bounds__(256) void k_rk_mfma(int R, int64_t ld,
+                                                 const int32_t* __restrict__ gate_count,
+                                                 const int32_t* __restrict__ gate_kp,
                                                  const float* __restrict__ Af,
                                                  const float* __restrict__ Bf,
                                                  const __bf16* __restrict__ Abf,
                                                  const __bf16* __restrict__ Bbf,
                                                  float2* __restrict__ G) {
-  if (hdr->s == 0 || hdr->kp != KP) return;
+  // gate_count: number of active terms (0 = nothing to do); gate_kp: the rank
+  // padding chosen on the device (the instantiation that does not match exits)
+  if (*gate_count == 0 || (gate_kp != nullptr && *gate_kp != KP)) return;
   constexpr int K2 = 2 * KP;
   constexpr int PADF = BF16 ? 4 : 1;   // LDS row padding (floats): 16-B rows for BF16, odd stride for FP32
   __shared__ __attribute__((aligned(16))) float sA[64 * (K2 + PADF)];
@@ -362,17 +366,29 @@ hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo
   // the rank padding (16 or 32) is decided on the device; both instantiations are
   // launched and the one that does not match exits at once
   if (bf) {
-    hipLaunchKernelGGL((k_rk_mfma<16, true>), grid, dim3(256), 0, s, g.R, g.ld, (const RkHdr*)hdr,
+    hipLaunchKernelGGL((k_rk_mfma<16, true>), grid, dim3(256), 0, s, g.R, g.ld, &hdr->s, &hdr->kp,
                        (const float*)Af, (const float*)Bf, (const __bf16*)Abf, (const __bf16*)Bbf, G);
-    hipLaunchKernelGGL((k_rk_mfma<32, true>), grid, dim3(256), 0, s, g.R, g.ld, (const RkHdr*)hdr,
+    hipLaunchKernelGGL((k_rk_mfma<32, true>), grid, dim3(256), 0, s, g.R, g.ld, &hdr->s, &hdr->kp,
                        (const float*)Af, (const float*)Bf, (const __bf16*)Abf, (const __bf16*)Bbf, G);
   } else {
-    hipLaunchKernelGGL((k_rk_mfma<16, false>), grid, dim3(256), 0, s, g.R, g.ld, (const RkHdr*)hdr,
+    hipLaunchKernelGGL((k_rk_mfma<16, false>), grid, dim3(256), 0, s, g.R, g.ld, &hdr->s, &hdr->kp,
                        (const float*)Af, (const float*)Bf, (const __bf16*)Abf, (const __bf16*)Bbf, G);
-    hipLaunchKernelGGL((k_rk_mfma<32, false>), grid, dim3(256), 0, s, g.R, g.ld, (const RkHdr*)hdr,
+    hipLaunchKernelGGL((k_rk_mfma<32, false>), grid, dim3(256), 0, s, g.R, g.ld, &hdr->s, &hdr->kp,
                        (const float*)Af, (const float*)Bf, (const __bf16*)Abf, (const __bf16*)Bbf, G);
   }
   if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
+  return hipGetLastError();
+}
+
+// Rank-64 FP32 update of rows [0, rows) (deferred-mode flush); A, B in the
+// operand layout above with KP = GFO_MAX_DELAY, `count` active terms.
+hipError_t launch_mfma_update_f32_64(int rows, int64_t ld, const int32_t* count, const float* A,
+                                     const float* B, float2* G, hipStream_t s) {
+  const int ncg = (int)(ld / 64);
+  const int nrg = (rows + 64 * kRkRowBlocks - 1) / (64 * kRkRowBlocks);
+  hipLaunchKernelGGL((k_rk_mfma<GFO_MAX_DELAY, false>), dim3((unsigned)(ncg * nrg)), dim3(256), 0, s,
+                     rows, ld, count, (const int32_t*)nullptr, A, B, (const __bf16*)nullptr,
+                     (const __bf16*)nullptr, G);
   return hipGetLastError();
 }
 

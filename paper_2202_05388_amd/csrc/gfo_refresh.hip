@@ -233,10 +233,21 @@ struct EpiG0 {
   }
 };
 
-template <bool BT, typename Epi>
+struct EpiAddG {
+  int64_t ld;
+  double2* G;
+  __device__ void operator()(int m, int n, double2 v) const {
+    double2* p = G + (int64_t)m * ld + n;
+    *p = cadd(*p, v);
+  }
+};
+
+// A(m, k) = A[m * lda + k], or A[k * lda + m] when AT; K is clamped to *kdev when given.
+template <bool AT, bool BT, typename Epi>
 __global__ __launch_bounds__(256) void k_zgemm_f64(int M, int N, int K, const double2* __restrict__ A,
                                                    int64_t lda, const double2* __restrict__ B,
-                                                   int64_t ldb, Epi epi) {
+                                                   int64_t ldb, const int32_t* __restrict__ kdev,
+                                                   Epi epi) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
   const int n0 = blockIdx.x * 64 + (w & 1) * 32;
@@ -249,13 +260,17 @@ __global__ __launch_bounds__(256) void k_zgemm_f64(int M, int N, int K, const do
       re[t][u] = (f64x4){0.0, 0.0, 0.0, 0.0};
       im[t][u] = (f64x4){0.0, 0.0, 0.0, 0.0};
     }
+  if (kdev != nullptr) K = min(K, *kdev);
   for (int k0 = 0; k0 < K; k0 += 4) {
     const int kk = k0 + lk;
     double2 a[2], b[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int row = m0 + 16 * t + li;
-      a[t] = (row < M && kk < K) ? A[(int64_t)row * lda + kk] : make_double2(0.0, 0.0);
+      if (row < M && kk < K)
+        a[t] = AT ? A[(int64_t)kk * lda + row] : A[(int64_t)row * lda + kk];
+      else
+        a[t] = make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -344,9 +359,9 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, hipStream
     }
     // Z = U M, M = right half of Aug (row-major, ld 2kp)
     EpiStoreZ ez{Z, kp};
-    hipLaunchKernelGGL((k_zgemm_f64<false, EpiStoreZ>), dim3((kp + 63) / 64, (g.R + 63) / 64),
+    hipLaunchKernelGGL((k_zgemm_f64<false, false, EpiStoreZ>), dim3((kp + 63) / 64, (g.R + 63) / 64),
                        dim3(256), 0, s, g.R, kp, kp, (const double2*)U, (int64_t)kp,
-                       (const double2*)(Aug + kp), (int64_t)2 * kp, ez);
+                       (const double2*)(Aug + kp), (int64_t)2 * kp, (const int32_t*)nullptr, ez);
     hipLaunchKernelGGL(k_rf_xE, dim3((kp + 255) / 256), dim3(256), 0, s, g, mon, (const int32_t*)V,
                        (const double2*)Aug, k, kp, x);
   }
@@ -354,10 +369,20 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, hipStream
                      (const double2*)U, (const double2*)x, k, kp, (T*)st->E);
   // G = G0 + Z U_D^T over the N design columns (padding columns stay zero)
   EpiG0<T> eg{g, table, mon, (T*)st->G, (double2*)st->diag64};
-  hipLaunchKernelGGL((k_zgemm_f64<true, EpiG0<T>>), dim3((g.N + 63) / 64, (g.R + 63) / 64),
+  hipLaunchKernelGGL((k_zgemm_f64<false, true, EpiG0<T>>), dim3((g.N + 63) / 64, (g.R + 63) / 64),
                      dim3(256), 0, s, g.R, g.N, kp, (const double2*)Z, (int64_t)kp,
-                     (const double2*)U, (int64_t)kp, eg);
+                     (const double2*)U, (int64_t)kp, (const int32_t*)nullptr, eg);
   return hipGetLastError() == hipSuccess ? GFO_OK : GFO_EHIP;
+}
+
+// Deferred-mode flush for complex128 storage: G[0:N, 0:N] += CU^T V over the
+// `count` pending terms (FP64 matrix cores).
+hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const double2* CU,
+                                   const double2* V, double2* G, hipStream_t s) {
+  EpiAddG ep{g.ld, G};
+  hipLaunchKernelGGL((k_zgemm_f64<true, false, EpiAddG>), dim3((g.N + 63) / 64, (g.N + 63) / 64),
+                     dim3(256), 0, s, g.N, g.N, GFO_MAX_DELAY, CU, (int64_t)g.R, V, g.ld, count, ep);
+  return hipGetLastError();
 }
 
 int launch_refresh(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {

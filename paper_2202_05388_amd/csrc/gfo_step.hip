@@ -177,7 +177,8 @@ template <typename T>
 __global__ void k_snap(Geo g, const gfo_pick* __restrict__ pick, const T* __restrict__ E,
                        const double2* __restrict__ diag64, uint8_t* __restrict__ eps_idx,
                        int32_t* __restrict__ flips, int flip_cap, int32_t* __restrict__ n_flips,
-                       int32_t* __restrict__ status, Snap* __restrict__ snap) {
+                       int32_t* __restrict__ status, Snap* __restrict__ snap,
+                       int32_t* __restrict__ dl_count) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   Snap s = {};
   s.j = -1;
@@ -195,6 +196,10 @@ __global__ void k_snap(Geo g, const gfo_pick* __restrict__ pick, const T* __rest
       s.c = rdiv(a, den);
       s.Ej = St<T>::to_d(E[j]);
       s.dj = d;
+      if (dl_count != nullptr) {             // deferred mode: this move's pending-term index
+        s.slot = *dl_count;
+        *dl_count = s.slot + 1;
+      }
       eps_idx[j] = (uint8_t)e;
       const int n = *n_flips;
       if (n < flip_cap) {
@@ -474,9 +479,11 @@ static hipError_t apply_typed(const Geo& g, gfo_state* st, const Layout& L, cons
   Snap* snap = (Snap*)(w + L.snap);
   T* cu = (T*)(w + L.cu);
   T* v = (T*)(w + L.v);
+  int32_t* dl_count = st->delay > 0 ? (int32_t*)(w + L.dl_hdr) : nullptr;
   hipLaunchKernelGGL(k_snap<T>, dim3(1), dim3(64), 0, s, g, pick, (const T*)st->E,
                      (const double2*)st->diag64, st->eps_idx, st->flips, st->flip_cap, st->n_flips,
-                     st->status, snap);
+                     st->status, snap, dl_count);
+  if (st->delay > 0) return launch_apply_deferred<T>(g, st, L, snap, s);
   const int64_t n = g.R > g.ld ? (int64_t)g.R : g.ld;
   hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g,
                      (const Snap*)snap, (const T*)st->G, (T*)st->E, (double2*)st->diag64, cu, v);

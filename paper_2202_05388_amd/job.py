@@ -26,7 +26,7 @@ class Job:
     """Device state of one greedy optimisation."""
 
     def __init__(self, problem, device="cuda", kmax: int = 0, flip_cap: int = None,
-                 dtype: str = None):
+                 dtype: str = None, delay: int = 0):
         if not torch.cuda.is_available():
             raise L.GfoError("libgfo needs a GPU; torch.cuda is not available")
         L.lib()
@@ -61,7 +61,9 @@ class Job:
             G=self.G.data_ptr(), ldG=self.ld, E=self.E.data_ptr(), diag64=self.diag64.data_ptr(),
             eps_idx=self.eps_idx.data_ptr(), flips=self.flips.data_ptr(), flip_cap=self.flip_cap,
             n_flips=self.counters.data_ptr(), kmax=self.kmax, work=self.work.data_ptr(),
-            work_bytes=work_bytes, status=self.counters.data_ptr() + 4)
+            work_bytes=work_bytes, status=self.counters.data_ptr() + 4, delay=int(delay),
+            pending_calls=0)
+        self.delay = int(delay)
         self.steps_issued = 0
 
     # ------------------------------------------------------------------ C-ABI calls
@@ -85,6 +87,10 @@ class Job:
 
     def refresh(self, stream=None):
         L.refresh_G(self.prob, self.state, _stream_handle(stream))
+
+    def flush(self, stream=None):
+        """Deferred mode: bring the design block of G up to date (no-op otherwise)."""
+        L.flush(self.prob, self.state, _stream_handle(stream))
 
     def step(self, stream=None):
         """One greedy step: score + select + rank-1 apply, no host synchronisation."""
@@ -119,7 +125,8 @@ class Job:
         return raw.view(torch.float64).cpu().numpy().reshape(self.N, len(self._eps))
 
     def host_state(self):
-        """(G[:, :N], E, diag64, eps_idx) copied to host numpy, complex128."""
+        """(G[:, :N], E, diag64, eps_idx) copied to host numpy, complex128 (flushes first)."""
+        self.flush()
         torch.cuda.synchronize(self.device)
         G = self.G[:, : self.N].cpu().to(torch.complex128).numpy()
         return (G, self.E.cpu().to(torch.complex128).numpy(), self.diag64.cpu().numpy(),

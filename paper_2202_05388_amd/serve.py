@@ -233,8 +233,13 @@ def serve_benchmark(n_jobs=64, rate=4.0, seed=0, max_slots=16, chunk=16, time_sc
     mix, smix = Server(max_slots=max_slots, chunk=chunk).run(jobs, mode="mix",
                                                            time_scale=time_scale)
     ser, sser = Server(max_slots=1, chunk=chunk).run(jobs, mode="serial", time_scale=time_scale)
+    # the same jobs all arriving at once: throughput of the device, not of the arrival process
+    bmix, sbmix = Server(max_slots=max_slots, chunk=chunk).run(jobs, mode="mix", time_scale=0.0)
+    bser, sbser = Server(max_slots=1, chunk=chunk).run(jobs, mode="serial", time_scale=0.0)
     dm = {r.job_id: r.digest for r in mix}
     ds = {r.job_id: r.digest for r in ser}
-    same = sum(1 for k in dm if dm[k] == ds.get(k))
+    db = {r.job_id: r.digest for r in bmix}
+    same = sum(1 for k in dm if dm[k] == ds.get(k) == db.get(k))
     return dict(jobs=n_jobs, rate_per_s=rate, seed=seed, max_slots=max_slots,
-                mix=smix, one_at_a_time=sser, results_identical=f"{same}/{len(dm)}")
+                mix=smix, one_at_a_time=sser, burst_mix=sbmix, burst_one_at_a_time=sbser,
+                results_identical=f"{same}/{len(dm)}")

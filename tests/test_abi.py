@@ -14,9 +14,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
+    """Names of every function prototype in include/gfo.h (comments stripped)."""
     src = open(os.path.join(ROOT, "include", "gfo.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\(\s*(?:const\s+)?(?:gfo_problem|int32_t|int|void)\b", src)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][A-Za-z0-9_]*)\s*\(",
+                                 src, flags=re.M)))
 
 
 def _problem(p, dtype=L.GFO_C128):
@@ -33,7 +35,7 @@ def test_library_exports_every_declared_entry_point():
     lib = L.lib()
     declared = _declared_functions()
     for name in ("init_G0", "score_candidates", "apply_flip", "apply_flips_rank_k", "refresh_G",
-                 "gfo_workspace_size", "gfo_strerror", "gfo_version"):
+                 "gfo_workspace_size", "gfo_strerror", "gfo_version", "gfo_flush", "gfo_time_next_k1"):
         assert name in declared
     for name in declared:
         assert hasattr(lib, name), name
@@ -45,8 +47,9 @@ def test_struct_layouts_match_header():
     # x86-64 SysV layout of the structs in include/gfo.h
     assert C.sizeof(L.Problem) == 64
     assert L.Problem.h_mon_xy.offset == 40 and L.Problem.h_eps_table.offset == 56
-    assert C.sizeof(L.State) == 96
+    assert C.sizeof(L.State) == 104
     assert L.State.work.offset == 72 and L.State.status.offset == 88
+    assert L.State.delay.offset == 96 and L.State.pending_calls.offset == 100
     assert C.sizeof(L.Pick) == 24
 
 
@@ -88,12 +91,16 @@ def test_null_state_and_bad_ld_rejected_without_gpu_work():
     assert lib.apply_flip(C.byref(pr), C.byref(st), None, None) == L.GFO_EINVAL
     assert lib.apply_flips_rank_k(C.byref(pr), C.byref(st), None, 4, 0, None) == L.GFO_EINVAL
     assert lib.refresh_G(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
+    assert lib.gfo_flush(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
     # non-null but fake pointers with a bad leading dimension: rejected before any launch
     fake = 1 << 20
     st = L.State(G=fake, ldG=17, E=fake, diag64=fake, eps_idx=fake, flips=fake, flip_cap=4,
                  n_flips=fake, kmax=0, work=fake, work_bytes=1 << 30, status=fake)
     assert lib.init_G0(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
     st.ldG = 64
+    st.delay = 65                               # above GFO_MAX_DELAY
+    assert lib.init_G0(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
+    st.delay = 0
     st.work_bytes = 16
     assert lib.init_G0(C.byref(pr), C.byref(st), None) == L.GFO_ENOSPC
 

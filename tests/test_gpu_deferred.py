@@ -1,0 +1,116 @@
+"""Deferred rank-1 updates (state.delay > 0): pending terms, eager E / diagonal /
+monitor rows, rank-r matrix-core flush.  The move sequence and the state after a
+flush must equal eager mode and the oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import state as ost
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _job(p, **kw):
+    from paper_2202_05388_amd.job import Job
+    print(f"[case] {p.name} {p.ny}x{p.nx} {p.dtype} {kw}", flush=True)
+    return Job(p, device="cuda:0", **kw)
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+@pytest.mark.parametrize("dtype,delay", [("c128", 16), ("c128", 64), ("c64", 16), ("c64", 64),
+                                         ("c64", 7)])
+def test_deferred_equals_eager(dtype, delay):
+    p = W.tiny(24, 28, n_mon=8, dtype=dtype, cand_mask=W.MASK_BOTH)
+    eager = _job(p)
+    eager.init()
+    n1 = eager.run_greedy(150, poll_every=25)
+    lazy = _job(p, delay=delay)
+    lazy.init()
+    n2 = lazy.run_greedy(150, poll_every=25)
+    assert n1 == n2
+    assert np.array_equal(eager.history(), lazy.history())
+    Ge, Ee, de, ie = eager.host_state()
+    Gl, El, dl, il = lazy.host_state()
+    tol = 1e-12 if dtype == "c128" else 3e-6
+    assert _rel(Gl, Ge) <= tol and _rel(El, Ee) <= tol and _rel(dl, de) <= tol
+    assert np.array_equal(ie, il) and lazy.status() == 0
+    Gd, Ed = ost.dense_state(p, ost.eps_of(p, il))
+    assert _rel(Gl, Gd) <= (1e-11 if dtype == "c128" else 2e-5)
+
+
+def test_deferred_square32_fp64_matches_stored_oracle():
+    gold = json.load(open(os.path.join(HERE, "golden", "square32_fp64.json")))
+    p = W.SMALL_32
+    job = _job(p, delay=8)
+    job.init()
+    n = job.run_greedy(p.steps, poll_every=10)
+    hist = job.history()
+    assert n == len(gold["steps"])
+    assert [int(x) for x in hist[:, 0]] == [s["pixel"] for s in gold["steps"]]
+    _, E, _, _ = job.host_state()
+    Emon = np.array([complex(*z) for z in gold["final"]["E_mon"]])
+    assert _rel(E[p.n:], Emon) <= 1e-9
+
+
+def test_deferred_square128_c64_matches_oracle():
+    from test_gpu_refresh import certify_sequence
+    gold = json.load(open(os.path.join(HERE, "golden", "square128_fp64.json")))
+    p = W.SQUARE_128
+    N = p.n
+    job = _job(p, delay=64)
+    job.init()
+    assert job.run_greedy(100, poll_every=32) == 100
+    E = job.E.cpu().numpy().astype(np.complex128)
+    ck = gold["checkpoints"]["100"]
+    Em = np.array([complex(*z) for z in ck["E_mon"]])
+    assert _rel(E[N:], Em) <= 1e-4
+    job.run_greedy(2000, poll_every=32)
+    hist = [(int(a), int(b)) for a, b in job.history()]
+    gp = [(s["pixel"], s["eps_idx"]) for s in gold["steps"]]
+    t = certify_sequence(p, gp, hist)
+    print(f"deferred c64 sequence identical for {t} of {len(gp)}", flush=True)
+    assert t >= 150
+    assert abs(job.fom() - gold["steps"][-1]["fom"]) <= 1e-4 * gold["steps"][-1]["fom"]
+
+
+def test_flush_on_demand_and_partial_pending():
+    p = W.tiny(16, 18, n_mon=6, dtype="c128")
+    job = _job(p, delay=64)
+    job.init()
+    job.run_greedy(23, poll_every=23)                 # 23 pending terms, no automatic flush yet
+    assert job.state.pending_calls == 23
+    G, E, d, idx = job.host_state()                   # flushes
+    assert job.state.pending_calls == 0
+    Gd, Ed = ost.dense_state(p, ost.eps_of(p, idx))
+    assert _rel(G, Gd) <= 1e-11 and _rel(E, Ed) <= 1e-11 and _rel(d, np.diagonal(Gd[: p.n])) <= 1e-11
+
+
+def test_refresh_discards_pending_and_rank_k_flushes_first():
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(16, 18, n_mon=6, dtype="c64")
+    job = _job(p, delay=16, kmax=64)
+    job.init()
+    job.run_greedy(10, poll_every=10)
+    job.refresh()                                     # pending terms dropped, G rebuilt in FP64
+    G, E, d, idx = job.host_state()
+    Gd, Ed = ost.dense_state(p, ost.eps_of(p, idx))
+    assert _rel(G, Gd) <= 3e-7
+    job.run_greedy(5, poll_every=5)                   # five pending terms
+    idx0 = job.eps_idx.cpu().numpy()
+    job.score(topk=4, min_spacing=3)
+    picks = [(a, b) for a, b, _, _ in job.read_picks(4) if a >= 0]
+    job.apply_rank_k(4, precision=L.GFO_FP32)
+    G, E, d, idx = job.host_state()
+    idx1 = idx0.copy()
+    for a, b in picks:
+        idx1[a] = b
+    assert np.array_equal(idx, idx1)
+    Gd, Ed = ost.dense_state(p, ost.eps_of(p, idx))
+    assert _rel(G, Gd) <= 2e-5 and _rel(E, Ed) <= 2e-5
