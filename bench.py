@@ -89,12 +89,16 @@ def run_steps(job, target, poll, events=None, refresh_every=0, flush_events=None
         in_run_acc = n
         in_run_issued += chunk
         if new < chunk:                        # the trajectory ended: restart the job
+            if job.delay:
+                job.flush()                    # apply every accepted move to G before discarding it
             job.init()
             restarts += 1
             in_run_issued = 0
             in_run_acc = 0
         elif refresh_every and in_run_acc % refresh_every == 0:
             job.refresh()
+    if job.delay:
+        job.flush()                            # no pending update is left outside the timed work
     return accepted, calls, restarts, flags
 
 

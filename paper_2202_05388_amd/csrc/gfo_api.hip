@@ -77,8 +77,6 @@ Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   L.dl_hdr = take(256);
   L.dl_CU = take((size_t)GFO_MAX_DELAY * R * 16);
   L.dl_V = take((size_t)GFO_MAX_DELAY * (size_t)ld * 16);
-  L.dl_A = take(N * 2 * GFO_MAX_DELAY * 4);
-  L.dl_B = take((size_t)ld * 4 * GFO_MAX_DELAY * 4);
   L.rf_V = take((N + 64) * 4);
   L.rf_U = take(R * k * 16);
   L.rf_A = take(2 * k * k * 16);

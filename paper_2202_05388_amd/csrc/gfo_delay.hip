@@ -76,35 +76,51 @@ __global__ void k_mon_dl(Geo g, const Snap* __restrict__ snap, const T* __restri
   }
 }
 
-// FP32 operands of the flush, same lane order as the rank-k product:
-// A[r][kappa] (r < N): kappa < 64 Re cu_kappa[r], kappa >= 64 Im cu;
-// B[q][out][kappa]: out 0 = [Re v ; -Im v], out 1 = [Im v ; Re v]; slots >= count are zero.
-__global__ void k_dl_packA(Geo g, const int32_t* __restrict__ count, const float2* __restrict__ CU,
-                           float* __restrict__ A) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= g.N) return;
-  const int n = *count;
-  constexpr int KP = GFO_MAX_DELAY;
-  for (int s = 0; s < KP; ++s) {
-    const float2 v = s < n ? CU[(int64_t)s * g.R + r] : make_float2(0.f, 0.f);
-    A[(int64_t)r * 2 * KP + s] = v.x;
-    A[(int64_t)r * 2 * KP + KP + s] = v.y;
-  }
-}
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__global__ void k_dl_packB(Geo g, const int32_t* __restrict__ count, const float2* __restrict__ V,
-                           float* __restrict__ B) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= g.ld) return;
-  const int n = *count;
-  constexpr int KP = GFO_MAX_DELAY;
-  const int64_t base = q * 4 * KP;
-  for (int s = 0; s < KP; ++s) {
-    const float2 w = s < n ? V[(int64_t)s * g.ld + q] : make_float2(0.f, 0.f);
-    B[base + s] = w.x;
-    B[base + KP + s] = -w.y;
-    B[base + 2 * KP + s] = w.y;
-    B[base + 3 * KP + s] = w.x;
+// FP32 flush for complex64 storage: G[m, n] += sum_{s < count} CU[s][m] V[s][n]
+// for design rows m < N and all ld columns, as complex FP32 on the matrix cores
+// (v_mfma_f32_32x32x2_f32; re += Ar Br - Ai Bi, im += Ar Bi + Ai Br).  The G tile
+// is loaded into the accumulators, so G is read and written once.  Workgroup of
+// 4 waves = 64 x 64 outputs, each wave 32 x 32.  Lane layout of the instruction:
+// A(i, k): i = lane % 32, k = lane / 32; B(k, j): j = lane % 32, k = lane / 32;
+// accumulator element e: row 8*(e/4) + 4*(lane/32) + e%4, column lane % 32.
+__global__ __launch_bounds__(256) void k_flush_c64(int M, int R, int64_t ld,
+                                                   const int32_t* __restrict__ count,
+                                                   const float2* __restrict__ CU,
+                                                   const float2* __restrict__ V,
+                                                   float2* __restrict__ G) {
+  const int K = *count;
+  if (K == 0) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
+  const int n = blockIdx.x * 64 + (w & 1) * 32 + (lane & 31);
+  const int h = lane >> 5;
+  f32x16 accr, acci;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int row = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
+    const float2 gv = row < M ? G[(int64_t)row * ld + n] : make_float2(0.f, 0.f);
+    accr[e] = gv.x;
+    acci[e] = gv.y;
+  }
+  const int am = m0 + (lane & 31);
+  for (int k0 = 0; k0 < K; k0 += 2) {
+    const int kk = k0 + h;
+    float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
+    if (kk < K) {
+      if (am < M) a = CU[(int64_t)kk * R + am];
+      b = V[(int64_t)kk * ld + n];
+    }
+    accr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, accr, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, accr, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, acci, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, acci, 0, 0, 0);
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int row = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
+    if (row < M) G[(int64_t)row * ld + n] = make_float2(accr[e], acci[e]);
   }
 }
 
@@ -143,14 +159,11 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
   k1_take_timing(&before, &after);
   hipError_t e;
   if (g.dtype == GFO_C64) {
-    float* A = (float*)(w + L.dl_A);
-    float* B = (float*)(w + L.dl_B);
-    hipLaunchKernelGGL(k_dl_packA, dim3((g.N + 255) / 256), dim3(256), 0, s, g, count,
-                       (const float2*)(w + L.dl_CU), A);
-    hipLaunchKernelGGL(k_dl_packB, dim3((unsigned)((g.ld + 255) / 256)), dim3(256), 0, s, g, count,
-                       (const float2*)(w + L.dl_V), B);
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
-    e = launch_mfma_update_f32_64(g.N, g.ld, count, A, B, (float2*)st->G, s);
+    hipLaunchKernelGGL(k_flush_c64, dim3((unsigned)(g.ld / 64), (unsigned)((g.N + 63) / 64)),
+                       dim3(256), 0, s, g.N, g.R, g.ld, count, (const float2*)(w + L.dl_CU),
+                       (const float2*)(w + L.dl_V), (float2*)st->G);
+    e = hipGetLastError();
   } else {
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
     e = launch_zgemm_update_f64(g, count, (const double2*)(w + L.dl_CU),

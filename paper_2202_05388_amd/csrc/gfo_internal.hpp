@@ -83,8 +83,6 @@ struct Layout {
   size_t dl_hdr;    // int32 count of pending terms
   size_t dl_CU;     // GFO_MAX_DELAY x R x 16 B: c * G[:, j] of each pending move (storage type)
   size_t dl_V;      // GFO_MAX_DELAY x ld x 16 B: G[j, :] of each pending move (storage type)
-  size_t dl_A;      // N x 2*GFO_MAX_DELAY float: FP32 A operand of the flush
-  size_t dl_B;      // ld x 4*GFO_MAX_DELAY float: FP32 B operands of the flush
   // refresh
   // (kp = kmax rounded up to a multiple of 4)
   size_t rf_V;      // N + 1 int32: flipped list, then its length
@@ -116,8 +114,6 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
 template <typename T>
 hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, const Snap* snap,
                                  hipStream_t s);
-hipError_t launch_mfma_update_f32_64(int rows, int64_t ld, const int32_t* count, const float* A,
-                                     const float* B, float2* G, hipStream_t s);
 hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const double2* CU,
                                    const double2* V, double2* G, hipStream_t s);
 hipError_t launch_dl_reset(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);

@@ -380,16 +380,4 @@ hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo
   return hipGetLastError();
 }
 
-// Rank-64 FP32 update of rows [0, rows) (deferred-mode flush); A, B in the
-// operand layout above with KP = GFO_MAX_DELAY, `count` active terms.
-hipError_t launch_mfma_update_f32_64(int rows, int64_t ld, const int32_t* count, const float* A,
-                                     const float* B, float2* G, hipStream_t s) {
-  const int ncg = (int)(ld / 64);
-  const int nrg = (rows + 64 * kRkRowBlocks - 1) / (64 * kRkRowBlocks);
-  hipLaunchKernelGGL((k_rk_mfma<GFO_MAX_DELAY, false>), dim3((unsigned)(ncg * nrg)), dim3(256), 0, s,
-                     rows, ld, count, (const int32_t*)nullptr, A, B, (const __bf16*)nullptr,
-                     (const __bf16*)nullptr, G);
-  return hipGetLastError();
-}
-
 }  // namespace gfo
