@@ -162,6 +162,47 @@ def time_workload(problem, steps, warmup, poll, with_events=True, autotune=True)
                 k1_variant=None if tuned is None else tuned["name"])
 
 
+def time_deferred_graph(problem, steps, warmup, delay):
+    """Deferred mode with every window of `delay` steps replayed from a HIP graph."""
+    import torch
+    from paper_2202_05388_amd.job import Job
+
+    kmax = 2 * problem.refresh_every if problem.refresh_every else 0
+    job = Job(problem, device="cuda:0", kmax=kmax, delay=delay)
+    job.init()
+    g, s = job.capture_steps(delay)
+    re = problem.refresh_every
+
+    def run(target):
+        job.init()
+        acc = restarts = 0
+        while acc < target:
+            before = job.n_flips()
+            g.replay()
+            now = job.n_flips()
+            acc += now - before
+            if now - before < delay:
+                job.flush()
+                job.init()
+                restarts += 1
+            elif re and now % re == 0:
+                job.refresh()
+        return acc, restarts
+
+    run(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    acc, restarts = run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = dict(delay=delay, storage=problem.dtype, graph_window=delay, accepted=acc,
+               restarts=restarts, steps_per_s=acc / dt, ms_per_step=1e3 * dt / acc,
+               fom_last=job.fom(), status=job.status())
+    del job, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_deferred(problem, steps, warmup, poll, delay):
     """Greedy steps with deferred rank-1 updates: E, the FP64 diagonal and the monitor
     rows every step, the design block by one rank-`delay` matrix-core product per
@@ -173,6 +214,12 @@ def time_deferred(problem, steps, warmup, poll, delay):
     kmax = 2 * problem.refresh_every if problem.refresh_every else 0
     job = Job(problem, device="cuda:0", kmax=kmax, delay=delay)
     job.init()
+    flush_tuned = None
+    if problem.dtype == "c64":
+        from paper_2202_05388_amd import autotune as at
+        flush_tuned = at.tune_flush(job)
+        _log(f"[bench] flush autotune: {flush_tuned}")
+        job.init()
     run_steps(job, warmup, poll, refresh_every=problem.refresh_every)
     job.init()
     torch.cuda.synchronize()
@@ -190,6 +237,7 @@ def time_deferred(problem, steps, warmup, poll, delay):
     fl_ms = sum(fl) / len(fl) if fl else None
     out = dict(delay=delay, storage=problem.dtype, accepted=acc, restarts=restarts,
                steps_per_s=acc / dt, ms_per_step=1e3 * dt / acc, flushes_timed=len(fl),
+               flush_variant=None if flush_tuned is None else flush_tuned["name"],
                flush_us=None if fl_ms is None else fl_ms * 1e3,
                flush_tflops=None if fl_ms is None else 8.0 * N * ld * delay / (fl_ms * 1e-3) / 1e12,
                flush_gbs=None if fl_ms is None else 2 * elem * N * ld / (fl_ms * 1e-3) / 1e9,
@@ -381,6 +429,9 @@ def main():
             _log(f"[bench] deferred updates, {pf.name}, delay {args.delay}")
             deferred[pf.name] = time_deferred(pf, args.steps, args.warmup, args.poll, args.delay)
             _log(f"[bench] deferred {pf.name}: {deferred[pf.name]}")
+            key = pf.name + "_graph"
+            deferred[key] = time_deferred_graph(pf, args.steps, args.warmup, args.delay)
+            _log(f"[bench] deferred {key}: {deferred[key]}")
 
     rank_k = None
     if not args.no_rank_k and problem.name == "square128_c64":

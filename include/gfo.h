@@ -205,6 +205,14 @@ const char* gfo_k1_variant_name(int32_t dtype, int32_t idx);   /* NULL if out of
 int gfo_k1_set_variant(int32_t dtype, int32_t idx);           /* GFO_EINVAL if out of range */
 int gfo_k1_get_variant(int32_t dtype);
 
+/* Autotuner hooks for the complex64 deferred-mode flush: tile variants of the
+ * same rank-r matrix-core product (bit-identical results are not guaranteed
+ * across variants: the FP32 summation order differs).  Host only. */
+int gfo_flush_variant_count(void);
+const char* gfo_flush_variant_name(int32_t idx);              /* NULL if out of range */
+int gfo_flush_set_variant(int32_t idx);                       /* GFO_EINVAL if out of range */
+int gfo_flush_get_variant(void);
+
 /* Timing hook: the next apply_flip or apply_flips_rank_k (on any stream)
  * records `before` on its stream immediately before its G-update kernel (the
  * streaming rank-1 kernel, or the matrix-core rank-k kernels) and `after`

@@ -25,7 +25,8 @@ GFO_MAX_DELAY = 64
 EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "gfo_scores_offset",
            "init_G0", "score_candidates", "apply_flip", "apply_flips_rank_k", "refresh_G",
            "gfo_k1_variant_count", "gfo_k1_variant_name", "gfo_k1_set_variant",
-           "gfo_k1_get_variant", "gfo_time_next_k1", "gfo_flush")
+           "gfo_k1_get_variant", "gfo_time_next_k1", "gfo_flush", "gfo_flush_variant_count",
+           "gfo_flush_variant_name", "gfo_flush_set_variant", "gfo_flush_get_variant")
 
 
 class Problem(C.Structure):
@@ -78,6 +79,9 @@ def lib():
     L.apply_flips_rank_k.argtypes = [P, S, V, C.c_int32, C.c_int32, V]
     L.refresh_G.argtypes = [P, S, V]
     L.gfo_flush.argtypes = [P, S, V]
+    L.gfo_flush_variant_name.argtypes = [C.c_int32]
+    L.gfo_flush_variant_name.restype = C.c_char_p
+    L.gfo_flush_set_variant.argtypes = [C.c_int32]
     L.gfo_k1_variant_count.argtypes = [C.c_int32]
     L.gfo_k1_variant_name.argtypes = [C.c_int32, C.c_int32]
     L.gfo_k1_variant_name.restype = C.c_char_p
@@ -157,3 +161,16 @@ def k1_get_variant(dtype: int) -> int:
 
 def time_next_k1(before: int, after: int) -> None:
     check(lib().gfo_time_next_k1(before, after), "gfo_time_next_k1")
+
+
+def flush_variants():
+    L = lib()
+    return [L.gfo_flush_variant_name(i).decode() for i in range(L.gfo_flush_variant_count())]
+
+
+def flush_set_variant(idx: int) -> None:
+    check(lib().gfo_flush_set_variant(idx), "gfo_flush_set_variant")
+
+
+def flush_get_variant() -> int:
+    return lib().gfo_flush_get_variant()

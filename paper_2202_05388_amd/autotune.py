@@ -104,6 +104,48 @@ def tune(job, reps: int = 10, save: bool = True) -> dict:
     return entry
 
 
+def time_flush_variants(job, reps: int = 2) -> list:
+    """Mean flush-kernel time (us) of each complex64 flush variant on `job`'s shape
+    (deferred job, delay d): each measurement runs d greedy steps, whose last apply
+    ends with the flush; the job restarts when its trajectory ends."""
+    import torch
+    from .hiprt import EventPool
+
+    if not job.delay or job.dtype_name != "c64":
+        raise L.GfoError("flush tuning needs a complex64 job in deferred mode")
+    names = L.flush_variants()
+    old = L.flush_get_variant()
+    out = []
+    try:
+        for vi in range(len(names)):
+            L.flush_set_variant(vi)
+            ev = EventPool(reps + 1)
+            for rep in range(reps + 1):
+                job.flush()
+                start = job.n_flips()
+                for i in range(job.delay):
+                    if i == job.delay - 1 and rep > 0:
+                        a, b = ev.next()
+                        L.time_next_k1(a, b)
+                    job.step()
+                if job.n_flips() - start < job.delay:
+                    job.init()
+            ms = ev.elapsed_ms()
+            ev.close()
+            out.append(dict(variant=vi, name=names[vi], us=1e3 * sum(ms) / max(len(ms), 1)))
+    finally:
+        L.flush_set_variant(old)
+    torch.cuda.synchronize()
+    return out
+
+
+def tune_flush(job, reps: int = 2) -> dict:
+    res = time_flush_variants(job, reps)
+    best = min(res, key=lambda r: r["us"])
+    L.flush_set_variant(best["variant"])
+    return dict(variant=best["variant"], name=best["name"], us=best["us"], all=res)
+
+
 def apply_cached(job) -> bool:
     """Select the cached variant for this job's shape, if any.  Returns True if found."""
     e = load_cache().get(_key(job.N, job.R, job.dtype_name))

@@ -6,6 +6,8 @@
 // pending terms.
 #include "gfo_internal.hpp"
 
+#include <atomic>
+
 namespace gfo {
 
 // Thread i: u_i = G_t[i, j] (base + pending, rows < N; monitor rows are current),
@@ -124,6 +126,93 @@ __global__ __launch_bounds__(256) void k_flush_c64(int M, int R, int64_t ld,
   }
 }
 
+// Same product with a 64 x 64 output tile per wave (2 x 2 instruction tiles) and
+// 128 x 128 per workgroup, so each operand load feeds 8 instructions instead of 4.
+// Workgroups are numbered XCD-aware: consecutive workgroup ids go to different
+// XCDs (round robin), so id b is given to XCD b % 8, and each XCD walks its own
+// band of row blocks; the A rows of a band then stay in that XCD's L2.
+__global__ __launch_bounds__(256) void k_flush_c64_w64(int M, int R, int64_t ld, int nbx, int nby,
+                                                       const int32_t* __restrict__ count,
+                                                       const float2* __restrict__ CU,
+                                                       const float2* __restrict__ V,
+                                                       float2* __restrict__ G) {
+  const int K = *count;
+  if (K == 0) return;
+  // XCD-aware tile order
+  const int nxcd = 8;
+  const int b = blockIdx.x;
+  const int xcd = b % nxcd, local = b / nxcd;
+  const int per = (nbx * nby + nxcd - 1) / nxcd;          // workgroups per XCD
+  const int t = xcd * per + local;                        // position in row-major tile order
+  if (t >= nbx * nby) return;
+  const int by = t / nbx, bx = t - (t / nbx) * nbx;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = by * 128 + (w >> 1) * 64;
+  const int n0 = bx * 128 + (w & 1) * 64;
+  const int h = lane >> 5, l32 = lane & 31;
+  f32x16 accr[2][2], acci[2][2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) {
+      const int n = n0 + 32 * tj + l32;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = m0 + 32 * ti + 8 * (e >> 2) + 4 * h + (e & 3);
+        const float2 gv = (row < M && n < ld) ? G[(int64_t)row * ld + n] : make_float2(0.f, 0.f);
+        accr[ti][tj][e] = gv.x;
+        acci[ti][tj][e] = gv.y;
+      }
+    }
+  for (int k0 = 0; k0 < K; k0 += 2) {
+    const int kk = k0 + h;
+    float2 a[2], bb[2];
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti) {
+      const int am = m0 + 32 * ti + l32;
+      a[ti] = (kk < K && am < M) ? CU[(int64_t)kk * R + am] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) {
+      const int n = n0 + 32 * tj + l32;
+      bb[tj] = (kk < K && n < ld) ? V[(int64_t)kk * ld + n] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        accr[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ti].x, bb[tj].x, accr[ti][tj], 0, 0, 0);
+        accr[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[ti].y, bb[tj].y, accr[ti][tj], 0, 0, 0);
+        acci[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ti].x, bb[tj].y, acci[ti][tj], 0, 0, 0);
+        acci[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ti].y, bb[tj].x, acci[ti][tj], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) {
+      const int n = n0 + 32 * tj + l32;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = m0 + 32 * ti + 8 * (e >> 2) + 4 * h + (e & 3);
+        if (row < M && n < ld) G[(int64_t)row * ld + n] = make_float2(accr[ti][tj][e], acci[ti][tj][e]);
+      }
+    }
+}
+
+// flush variants for complex64 storage (selected by the autotuner)
+static std::atomic<int> g_flush_sel{0};
+int flush_variant_count() { return 2; }
+const char* flush_variant_name(int i) {
+  return i == 0 ? "w32" : (i == 1 ? "w64_xcd" : nullptr);
+}
+int flush_set_variant(int i) {
+  if (i < 0 || i > 1) return GFO_EINVAL;
+  g_flush_sel.store(i);
+  return GFO_OK;
+}
+int flush_get_variant() { return g_flush_sel.load(); }
+
 __global__ void k_dl_reset(int32_t* count) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *count = 0;
 }
@@ -160,9 +249,17 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
   hipError_t e;
   if (g.dtype == GFO_C64) {
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
-    hipLaunchKernelGGL(k_flush_c64, dim3((unsigned)(g.ld / 64), (unsigned)((g.N + 63) / 64)),
-                       dim3(256), 0, s, g.N, g.R, g.ld, count, (const float2*)(w + L.dl_CU),
-                       (const float2*)(w + L.dl_V), (float2*)st->G);
+    if (flush_get_variant() == 0) {
+      hipLaunchKernelGGL(k_flush_c64, dim3((unsigned)(g.ld / 64), (unsigned)((g.N + 63) / 64)),
+                         dim3(256), 0, s, g.N, g.R, g.ld, count, (const float2*)(w + L.dl_CU),
+                         (const float2*)(w + L.dl_V), (float2*)st->G);
+    } else {
+      const int nbx = (int)((g.ld + 127) / 128), nby = (g.N + 127) / 128;
+      const int per = (nbx * nby + 7) / 8;
+      hipLaunchKernelGGL(k_flush_c64_w64, dim3((unsigned)(per * 8)), dim3(256), 0, s, g.N, g.R, g.ld,
+                         nbx, nby, count, (const float2*)(w + L.dl_CU), (const float2*)(w + L.dl_V),
+                         (float2*)st->G);
+    }
     e = hipGetLastError();
   } else {
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;

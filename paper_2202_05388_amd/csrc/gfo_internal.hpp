@@ -125,5 +125,9 @@ int k1_set_variant(int dtype, int idx);
 int k1_get_variant(int dtype);
 void k1_time_next(hipEvent_t before, hipEvent_t after);
 void k1_take_timing(hipEvent_t* before, hipEvent_t* after);   // consumes the pending pair
+int flush_variant_count();
+const char* flush_variant_name(int idx);
+int flush_set_variant(int idx);
+int flush_get_variant();
 
 }  // namespace gfo

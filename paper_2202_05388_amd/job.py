@@ -174,3 +174,44 @@ class Job:
             if refresh_every and acc % refresh_every == 0:
                 self.refresh(stream)
         return acc - start
+
+    # ------------------------------------------------------------------ HIP graphs
+    def capture_steps(self, n: int, stream=None):
+        """Capture n greedy steps (score + select + apply, and in deferred mode the
+        flush that ends a window of `delay` steps) into a HIP graph on `stream`.
+
+        Capture records launches only; nothing runs.  The window must start with
+        no pending deferred terms, and n a multiple of delay in deferred mode, so
+        that every replay ends with its own flush and leaves no pending term."""
+        if self.delay:
+            if n % self.delay or self.state.pending_calls:
+                raise L.GfoError("graph window must be a multiple of delay and start flushed")
+        s = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        g = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize(self.device)
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(n):
+                self.score(stream=s)
+                self.apply(stream=s)
+        return g, s
+
+    def run_greedy_graph(self, max_steps, window=64, refresh_every=0):
+        """Greedy loop that replays a captured window of steps; polls and refreshes
+        between replays.  Returns the number of moves accepted by this call."""
+        if refresh_every and refresh_every % window:
+            raise L.GfoError("refresh_every must be a multiple of the window")
+        g, s = self.capture_steps(window)
+        start = self.n_flips()
+        acc = start
+        done = 0
+        while done < max_steps:
+            g.replay()
+            done += window
+            now = self.n_flips()
+            stopped = now - acc < window
+            acc = now
+            if stopped:
+                break
+            if refresh_every and acc % refresh_every == 0:
+                self.refresh()
+        return acc - start

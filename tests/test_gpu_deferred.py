@@ -114,3 +114,21 @@ def test_refresh_discards_pending_and_rank_k_flushes_first():
     assert np.array_equal(idx, idx1)
     Gd, Ed = ost.dense_state(p, ost.eps_of(p, idx))
     assert _rel(G, Gd) <= 2e-5 and _rel(E, Ed) <= 2e-5
+
+
+@pytest.mark.parametrize("dtype,delay", [("c128", 16), ("c64", 16)])
+def test_graph_replays_equal_stream_launches(dtype, delay):
+    """A captured window of steps, replayed with host polls and device work between
+    replays, gives the same moves and state as launching every step on a stream."""
+    p = W.tiny(20, 22, n_mon=6, dtype=dtype, cand_mask=W.MASK_BOTH)
+    ref = _job(p, delay=delay)
+    ref.init()
+    n_ref = ref.run_greedy(5 * delay, poll_every=delay)
+    job = _job(p, delay=delay)
+    job.init()
+    n = job.run_greedy_graph(5 * delay, window=delay)
+    assert n == n_ref
+    assert np.array_equal(job.history(), ref.history())
+    Gr, Er, dr, ir = ref.host_state()
+    G, E, d, i = job.host_state()
+    assert np.array_equal(G, Gr) and np.array_equal(E, Er) and np.array_equal(d, dr)
