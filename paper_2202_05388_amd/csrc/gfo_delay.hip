@@ -28,10 +28,13 @@ __global__ void k_gather_dl(Geo g, const Snap* __restrict__ snap, const T* __res
       u = snap->dj;
     } else {
       u = St<T>::to_d(G[i * g.ld + j]);
-      if (i < g.N)
+      if (i < g.N) {
+        // independent loads, 8 terms in flight per batch
+#pragma unroll 8
         for (int s = 0; s < slot; ++s)
           u = cadd(u, cmul(St<T>::to_d(CU[(int64_t)s * g.R + i]),
                            St<T>::to_d(V[(int64_t)s * g.ld + j])));
+      }
     }
     cu_d = cmul(c, u);
     CU[(int64_t)slot * g.R + i] = St<T>::from_d(cu_d);
@@ -44,6 +47,7 @@ __global__ void k_gather_dl(Geo g, const Snap* __restrict__ snap, const T* __res
         v = snap->dj;
       } else {
         v = St<T>::to_d(G[(int64_t)j * g.ld + i]);
+#pragma unroll 8
         for (int s = 0; s < slot; ++s)
           v = cadd(v, cmul(St<T>::to_d(CU[(int64_t)s * g.R + j]),
                            St<T>::to_d(V[(int64_t)s * g.ld + i])));
@@ -107,6 +111,7 @@ __global__ __launch_bounds__(256) void k_flush_c64(int M, int R, int64_t ld,
     acci[e] = gv.y;
   }
   const int am = m0 + (lane & 31);
+#pragma unroll 4
   for (int k0 = 0; k0 < K; k0 += 2) {
     const int kk = k0 + h;
     float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
