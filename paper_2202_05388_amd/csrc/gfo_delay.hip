@@ -10,75 +10,83 @@
 
 namespace gfo {
 
-// Thread i: u_i = G_t[i, j] (base + pending, rows < N; monitor rows are current),
-// v_i = G_t[j, i]; stores term `slot`; E_i += c u_i E_j; diag64_i += c u_i v_i.
+// Pending terms are stored element-major: CU[r * D + s], V[q * D + s] with
+// D = GFO_MAX_DELAY, so the terms of one element are contiguous.
+constexpr int D = GFO_MAX_DELAY;
+
+// Threads [0, R): u_r = G_t[r, j] (base + pending for design rows; monitor rows
+// are current); cu_r = c u_r is stored as term `slot` and in `cu`;
+// E_r += cu_r E_j.  Threads [R, R + ld): v_q = G_t[j, q] (q < N, 0 beyond),
+// stored as term `slot` and in `v`.
 template <typename T>
 __global__ void k_gather_dl(Geo g, const Snap* __restrict__ snap, const T* __restrict__ G,
-                            T* __restrict__ E, double2* __restrict__ diag64, T* __restrict__ CU,
-                            T* __restrict__ V) {
+                            T* __restrict__ E, T* __restrict__ CU, T* __restrict__ V,
+                            T* __restrict__ cu_out, T* __restrict__ v_out) {
   const int j = snap->j;
   if (j < 0) return;
   const int slot = snap->slot;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double2 c = snap->c;
-  double2 cu_d = make_double2(0.0, 0.0);
-  if (i < g.R) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < g.R) {
+    const int64_t i = t;
     double2 u;
     if (i == j) {
       u = snap->dj;
     } else {
       u = St<T>::to_d(G[i * g.ld + j]);
       if (i < g.N) {
-        // independent loads, 8 terms in flight per batch
+        const T* __restrict__ cr = CU + i * D;
+        const T* __restrict__ vj = V + (int64_t)j * D;
 #pragma unroll 8
-        for (int s = 0; s < slot; ++s)
-          u = cadd(u, cmul(St<T>::to_d(CU[(int64_t)s * g.R + i]),
-                           St<T>::to_d(V[(int64_t)s * g.ld + j])));
+        for (int s = 0; s < slot; ++s) u = cadd(u, cmul(St<T>::to_d(cr[s]), St<T>::to_d(vj[s])));
       }
     }
-    cu_d = cmul(c, u);
-    CU[(int64_t)slot * g.R + i] = St<T>::from_d(cu_d);
+    const double2 cu_d = cmul(snap->c, u);
+    const T cu = St<T>::from_d(cu_d);
+    CU[i * D + slot] = cu;
+    cu_out[i] = cu;
     E[i] = St<T>::from_d(cadd(St<T>::to_d(E[i]), cmul(cu_d, snap->Ej)));
-  }
-  if (i < g.ld) {
-    if (i < g.N) {
-      double2 v;
-      if (i == j) {
+  } else if (t < g.R + g.ld) {
+    const int64_t q = t - g.R;
+    double2 v = make_double2(0.0, 0.0);
+    if (q < g.N) {
+      if (q == j) {
         v = snap->dj;
       } else {
-        v = St<T>::to_d(G[(int64_t)j * g.ld + i]);
+        v = St<T>::to_d(G[(int64_t)j * g.ld + q]);
+        const T* __restrict__ cj = CU + (int64_t)j * D;
+        const T* __restrict__ vq = V + q * D;
 #pragma unroll 8
-        for (int s = 0; s < slot; ++s)
-          v = cadd(v, cmul(St<T>::to_d(CU[(int64_t)s * g.R + j]),
-                           St<T>::to_d(V[(int64_t)s * g.ld + i])));
+        for (int s = 0; s < slot; ++s) v = cadd(v, cmul(St<T>::to_d(cj[s]), St<T>::to_d(vq[s])));
       }
-      V[(int64_t)slot * g.ld + i] = St<T>::from_d(v);
-      if (i == j) {
-        const double2 d = snap->dj;
-        diag64[j] = cmul(d, rdiv(1.0, make_double2(1.0 - snap->alpha * d.x, -snap->alpha * d.y)));
-      } else {
-        diag64[i] = cadd(diag64[i], cmul(cu_d, v));
-      }
-    } else {
-      V[(int64_t)slot * g.ld + i] = St<T>::from_d(make_double2(0.0, 0.0));
     }
+    const T vv = St<T>::from_d(v);
+    V[q * D + slot] = vv;
+    v_out[q] = vv;
   }
 }
 
-// Monitor rows stay current: G[N+m, q] += cu[N+m] v[q].
+// Monitor rows stay current: G[N+m, q] += cu[N+m] v[q]; the FP64 diagonal gets
+// diag64[q] += cu[q] v[q] (q != j) and diag64[j] = d_j / (1 - alpha d_j).
 template <typename T>
-__global__ void k_mon_dl(Geo g, const Snap* __restrict__ snap, const T* __restrict__ CU,
-                         const T* __restrict__ V, T* __restrict__ G) {
-  if (snap->j < 0) return;
-  const int slot = snap->slot;
+__global__ void k_mon_dl(Geo g, const Snap* __restrict__ snap, const T* __restrict__ cu,
+                         const T* __restrict__ v, T* __restrict__ G, double2* __restrict__ diag64) {
+  const int j = snap->j;
+  if (j < 0) return;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.ld) return;
-  const double2 vq = St<T>::to_d(V[(int64_t)slot * g.ld + q]);
+  const double2 vq = St<T>::to_d(v[q]);
+  if (blockIdx.y == 0 && q < g.N) {
+    if (q == j) {
+      const double2 d = snap->dj;
+      diag64[j] = cmul(d, rdiv(1.0, make_double2(1.0 - snap->alpha * d.x, -snap->alpha * d.y)));
+    } else {
+      diag64[q] = cadd(diag64[q], cmul(St<T>::to_d(cu[q]), vq));
+    }
+  }
   for (int m = blockIdx.y; m < g.nmon; m += gridDim.y) {
     const int64_t r = g.N + m;
-    const double2 cu = St<T>::to_d(CU[(int64_t)slot * g.R + r]);
     T* p = G + r * g.ld + q;
-    *p = St<T>::from_d(cadd(St<T>::to_d(*p), cmul(cu, vq)));
+    *p = St<T>::from_d(cadd(St<T>::to_d(*p), cmul(St<T>::to_d(cu[r]), vq)));
   }
 }
 
@@ -110,19 +118,31 @@ __global__ __launch_bounds__(256) void k_flush_c64(int M, int R, int64_t ld,
     accr[e] = gv.x;
     acci[e] = gv.y;
   }
+  // the sum over terms is order-free: lane half h takes terms h*32 + t, so each
+  // lane reads its terms contiguously, two per 16-byte load
   const int am = m0 + (lane & 31);
-#pragma unroll 4
-  for (int k0 = 0; k0 < K; k0 += 2) {
-    const int kk = k0 + h;
-    float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
-    if (kk < K) {
-      if (am < M) a = CU[(int64_t)kk * R + am];
-      b = V[(int64_t)kk * ld + n];
+  const float4* __restrict__ arow = reinterpret_cast<const float4*>(CU + (int64_t)(am < M ? am : 0) * D + h * 32);
+  const float4* __restrict__ bcol = reinterpret_cast<const float4*>(V + (int64_t)n * D + h * 32);
+  const int T2 = K < 32 ? K : 32;                          // terms per lane half
+#pragma unroll 2
+  for (int t = 0; t < T2; t += 2) {
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (h * 32 + t < K) {
+      if (am < M) a = arow[t >> 1];
+      b = bcol[t >> 1];
+      if (h * 32 + t + 1 >= K) {                           // odd tail: second term absent
+        a.z = a.w = 0.f;
+        b.z = b.w = 0.f;
+      }
     }
     accr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, accr, 0, 0, 0);
     accr = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, accr, 0, 0, 0);
     acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, acci, 0, 0, 0);
     acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, acci, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, accr, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.w, b.w, accr, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.w, acci, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.z, acci, 0, 0, 0);
   }
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -169,18 +189,19 @@ __global__ __launch_bounds__(256) void k_flush_c64_w64(int M, int R, int64_t ld,
         acci[ti][tj][e] = gv.y;
       }
     }
-  for (int k0 = 0; k0 < K; k0 += 2) {
-    const int kk = k0 + h;
+  const int T2 = K < 32 ? K : 32;
+  for (int t = 0; t < T2; ++t) {
+    const int kk = h * 32 + t;                            // lane half h takes terms h*32 + t
     float2 a[2], bb[2];
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti) {
       const int am = m0 + 32 * ti + l32;
-      a[ti] = (kk < K && am < M) ? CU[(int64_t)kk * R + am] : make_float2(0.f, 0.f);
+      a[ti] = (kk < K && am < M) ? CU[(int64_t)am * D + kk] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj) {
       const int n = n0 + 32 * tj + l32;
-      bb[tj] = (kk < K && n < ld) ? V[(int64_t)kk * ld + n] : make_float2(0.f, 0.f);
+      bb[tj] = (kk < K && n < ld) ? V[(int64_t)n * D + kk] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
@@ -233,12 +254,14 @@ hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, c
   char* w = (char*)st->work;
   T* CU = (T*)(w + L.dl_CU);
   T* V = (T*)(w + L.dl_V);
-  const int64_t n = g.R > g.ld ? (int64_t)g.R : g.ld;
+  T* cu = (T*)(w + L.cu);
+  T* v = (T*)(w + L.v);
+  const int64_t n = (int64_t)g.R + g.ld;
   hipLaunchKernelGGL(k_gather_dl<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, snap,
-                     (const T*)st->G, (T*)st->E, (double2*)st->diag64, CU, V);
+                     (const T*)st->G, (T*)st->E, CU, V, cu, v);
   dim3 gm((unsigned)((g.ld + 255) / 256), (unsigned)(g.nmon < 65535 ? g.nmon : 65535));
-  hipLaunchKernelGGL(k_mon_dl<T>, gm, dim3(256), 0, s, g, snap, (const T*)CU, (const T*)V,
-                     (T*)st->G);
+  hipLaunchKernelGGL(k_mon_dl<T>, gm, dim3(256), 0, s, g, snap, (const T*)cu, (const T*)v,
+                     (T*)st->G, (double2*)st->diag64);
   return hipGetLastError();
 }
 template hipError_t launch_apply_deferred<float2>(const Geo&, gfo_state*, const Layout&,

@@ -81,8 +81,8 @@ struct Layout {
   size_t rk_Bbf;    // 2 x 2K x ld bf16
   // deferred rank-1 terms (GFO_MAX_DELAY slots)
   size_t dl_hdr;    // int32 count of pending terms
-  size_t dl_CU;     // GFO_MAX_DELAY x R x 16 B: c * G[:, j] of each pending move (storage type)
-  size_t dl_V;      // GFO_MAX_DELAY x ld x 16 B: G[j, :] of each pending move (storage type)
+  size_t dl_CU;     // R x GFO_MAX_DELAY x 16 B: c * G[:, j] of each pending move, element-major
+  size_t dl_V;      // ld x GFO_MAX_DELAY x 16 B: G[j, :] of each pending move, element-major
   // refresh
   // (kp = kmax rounded up to a multiple of 4)
   size_t rf_V;      // N + 1 int32: flipped list, then its length
