@@ -77,6 +77,8 @@ Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   L.dl_hdr = take(256);
   L.dl_CU = take((size_t)GFO_MAX_DELAY * R * 16);
   L.dl_V = take((size_t)GFO_MAX_DELAY * (size_t)ld * 16);
+  L.dl_CUs = take((size_t)GFO_MAX_DELAY * R * 16);
+  L.dl_Vs = take((size_t)GFO_MAX_DELAY * (size_t)ld * 16);
   L.rf_V = take((N + 64) * 4);
   L.rf_U = take(R * k * 16);
   L.rf_A = take(2 * k * k * 16);

@@ -10,8 +10,11 @@
 
 namespace gfo {
 
-// Pending terms are stored element-major: CU[r * D + s], V[q * D + s] with
-// D = GFO_MAX_DELAY, so the terms of one element are contiguous.
+// Pending terms are stored twice: element-major, CU[r * D + s] and V[q * D + s]
+// (D = GFO_MAX_DELAY; the terms of one element are contiguous, which the
+// per-step gathers read), and slot-major, CUs[s * R + r] and Vs[s * ld + q]
+// (consecutive elements of one term are contiguous, which the flush reads
+// coalesced across lanes).
 constexpr int D = GFO_MAX_DELAY;
 
 // Threads [0, R): u_r = G_t[r, j] (base + pending for design rows; monitor rows
@@ -21,6 +24,7 @@ constexpr int D = GFO_MAX_DELAY;
 template <typename T>
 __global__ void k_gather_dl(Geo g, const Snap* __restrict__ snap, const T* __restrict__ G,
                             T* __restrict__ E, T* __restrict__ CU, T* __restrict__ V,
+                            T* __restrict__ CUs, T* __restrict__ Vs,
                             T* __restrict__ cu_out, T* __restrict__ v_out) {
   const int j = snap->j;
   if (j < 0) return;
@@ -43,6 +47,7 @@ __global__ void k_gather_dl(Geo g, const Snap* __restrict__ snap, const T* __res
     const double2 cu_d = cmul(snap->c, u);
     const T cu = St<T>::from_d(cu_d);
     CU[i * D + slot] = cu;
+    CUs[(int64_t)slot * g.R + i] = cu;
     cu_out[i] = cu;
     E[i] = St<T>::from_d(cadd(St<T>::to_d(E[i]), cmul(cu_d, snap->Ej)));
   } else if (t < g.R + g.ld) {
@@ -61,6 +66,7 @@ __global__ void k_gather_dl(Geo g, const Snap* __restrict__ snap, const T* __res
     }
     const T vv = St<T>::from_d(v);
     V[q * D + slot] = vv;
+    Vs[(int64_t)slot * g.ld + q] = vv;
     v_out[q] = vv;
   }
 }
@@ -118,31 +124,19 @@ __global__ __launch_bounds__(256) void k_flush_c64(int M, int R, int64_t ld,
     accr[e] = gv.x;
     acci[e] = gv.y;
   }
-  // the sum over terms is order-free: lane half h takes terms h*32 + t, so each
-  // lane reads its terms contiguously, two per 16-byte load
   const int am = m0 + (lane & 31);
-  const float4* __restrict__ arow = reinterpret_cast<const float4*>(CU + (int64_t)(am < M ? am : 0) * D + h * 32);
-  const float4* __restrict__ bcol = reinterpret_cast<const float4*>(V + (int64_t)n * D + h * 32);
-  const int T2 = K < 32 ? K : 32;                          // terms per lane half
-#pragma unroll 2
-  for (int t = 0; t < T2; t += 2) {
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (h * 32 + t < K) {
-      if (am < M) a = arow[t >> 1];
-      b = bcol[t >> 1];
-      if (h * 32 + t + 1 >= K) {                           // odd tail: second term absent
-        a.z = a.w = 0.f;
-        b.z = b.w = 0.f;
-      }
+#pragma unroll 4
+  for (int k0 = 0; k0 < K; k0 += 2) {
+    const int kk = k0 + h;
+    float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
+    if (kk < K) {
+      if (am < M) a = CU[(int64_t)kk * R + am];
+      b = V[(int64_t)kk * ld + n];
     }
     accr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, accr, 0, 0, 0);
     accr = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, accr, 0, 0, 0);
     acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, acci, 0, 0, 0);
     acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, acci, 0, 0, 0);
-    accr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.z, accr, 0, 0, 0);
-    accr = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.w, b.w, accr, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.w, acci, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, b.z, acci, 0, 0, 0);
   }
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -189,19 +183,18 @@ __global__ __launch_bounds__(256) void k_flush_c64_w64(int M, int R, int64_t ld,
         acci[ti][tj][e] = gv.y;
       }
     }
-  const int T2 = K < 32 ? K : 32;
-  for (int t = 0; t < T2; ++t) {
-    const int kk = h * 32 + t;                            // lane half h takes terms h*32 + t
+  for (int k0 = 0; k0 < K; k0 += 2) {
+    const int kk = k0 + h;
     float2 a[2], bb[2];
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti) {
       const int am = m0 + 32 * ti + l32;
-      a[ti] = (kk < K && am < M) ? CU[(int64_t)am * D + kk] : make_float2(0.f, 0.f);
+      a[ti] = (kk < K && am < M) ? CU[(int64_t)kk * R + am] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int tj = 0; tj < 2; ++tj) {
       const int n = n0 + 32 * tj + l32;
-      bb[tj] = (kk < K && n < ld) ? V[(int64_t)n * D + kk] : make_float2(0.f, 0.f);
+      bb[tj] = (kk < K && n < ld) ? V[(int64_t)kk * ld + n] : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
@@ -254,11 +247,13 @@ hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, c
   char* w = (char*)st->work;
   T* CU = (T*)(w + L.dl_CU);
   T* V = (T*)(w + L.dl_V);
+  T* CUs = (T*)(w + L.dl_CUs);
+  T* Vs = (T*)(w + L.dl_Vs);
   T* cu = (T*)(w + L.cu);
   T* v = (T*)(w + L.v);
   const int64_t n = (int64_t)g.R + g.ld;
   hipLaunchKernelGGL(k_gather_dl<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, snap,
-                     (const T*)st->G, (T*)st->E, CU, V, cu, v);
+                     (const T*)st->G, (T*)st->E, CU, V, CUs, Vs, cu, v);
   dim3 gm((unsigned)((g.ld + 255) / 256), (unsigned)(g.nmon < 65535 ? g.nmon : 65535));
   hipLaunchKernelGGL(k_mon_dl<T>, gm, dim3(256), 0, s, g, snap, (const T*)cu, (const T*)v,
                      (T*)st->G, (double2*)st->diag64);
@@ -279,20 +274,20 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
     if (flush_get_variant() == 0) {
       hipLaunchKernelGGL(k_flush_c64, dim3((unsigned)(g.ld / 64), (unsigned)((g.N + 63) / 64)),
-                         dim3(256), 0, s, g.N, g.R, g.ld, count, (const float2*)(w + L.dl_CU),
-                         (const float2*)(w + L.dl_V), (float2*)st->G);
+                         dim3(256), 0, s, g.N, g.R, g.ld, count, (const float2*)(w + L.dl_CUs),
+                         (const float2*)(w + L.dl_Vs), (float2*)st->G);
     } else {
       const int nbx = (int)((g.ld + 127) / 128), nby = (g.N + 127) / 128;
       const int per = (nbx * nby + 7) / 8;
       hipLaunchKernelGGL(k_flush_c64_w64, dim3((unsigned)(per * 8)), dim3(256), 0, s, g.N, g.R, g.ld,
-                         nbx, nby, count, (const float2*)(w + L.dl_CU), (const float2*)(w + L.dl_V),
+                         nbx, nby, count, (const float2*)(w + L.dl_CUs), (const float2*)(w + L.dl_Vs),
                          (float2*)st->G);
     }
     e = hipGetLastError();
   } else {
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
-    e = launch_zgemm_update_f64(g, count, (const double2*)(w + L.dl_CU),
-                                (const double2*)(w + L.dl_V), (double2*)st->G, s);
+    e = launch_zgemm_update_f64(g, count, (const double2*)(w + L.dl_CUs),
+                                (const double2*)(w + L.dl_Vs), (double2*)st->G, s);
   }
   if (e != hipSuccess) return e;
   if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;

@@ -83,6 +83,8 @@ struct Layout {
   size_t dl_hdr;    // int32 count of pending terms
   size_t dl_CU;     // R x GFO_MAX_DELAY x 16 B: c * G[:, j] of each pending move, element-major
   size_t dl_V;      // ld x GFO_MAX_DELAY x 16 B: G[j, :] of each pending move, element-major
+  size_t dl_CUs;    // the same terms slot-major: GFO_MAX_DELAY x R x 16 B
+  size_t dl_Vs;     // slot-major: GFO_MAX_DELAY x ld x 16 B
   // refresh
   // (kp = kmax rounded up to a multiple of 4)
   size_t rf_V;      // N + 1 int32: flipped list, then its length
