@@ -25,30 +25,31 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM traffic of the streaming rank-1 kernel from rocprofv3 counter runs
-# (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by the value the same
-# counter reports for a device copy of exactly 2 GiB (FETCH 1048599.75 KiB ->
-# factor 2.0; WRITE 2097152 KiB -> factor 1.0).  Valid only for the kernel source
-# and variant it was measured on: any change to the source file voids it.
-PMC_TRAFFIC = {
-    "source": "paper_2202_05388_amd/csrc/gfo_step.hip",
-    "sha256": None,
-    "workload": "square128_c64",
-    "variant": "4x4x1_nt",
-    "fetch_kib": None, "fetch_scale": 2097152.0 / 1048599.75,
-    "write_kib": None, "write_scale": 1.0,
-}
+MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # dense FP32 / FP64 matrix peaks
+
+# HBM traffic per launch from rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE in KiB
+# per dispatch), each scaled by what the same counter reports for a device copy of
+# exactly 2 GiB (FETCH 1048599.75 KiB -> factor 2.0; WRITE 2097152 KiB -> factor
+# 1.0).  A record is valid only for the kernel source and variant it was measured
+# on: any change to that source file voids it (traffic is then reported as null).
+FETCH_SCALE = 2097152.0 / 1048599.75
+WRITE_SCALE = 1.0
+PMC_TRAFFIC = [
+    # {"kernel": ..., "source": ..., "sha256": ..., "workload": ..., "variant": ...,
+    #  "fetch_kib": ..., "write_kib": ...}
+]
 
 
-def pmc_traffic(workload, variant):
+def pmc_traffic(kernel, workload, variant):
     import hashlib
-    rec = PMC_TRAFFIC
-    if rec["sha256"] is None or rec["workload"] != workload or rec["variant"] != variant:
-        return None
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
-            return None
-    return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+    for rec in PMC_TRAFFIC:
+        if (rec["kernel"], rec["workload"], rec["variant"]) != (kernel, workload, variant):
+            continue
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
+                return None
+        return 1024.0 * (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE)
+    return None
 
 
 def _log(msg):
@@ -231,6 +232,7 @@ def time_deferred(problem, steps, warmup, poll, delay):
     dt = time.perf_counter() - t0
     fl = fev.elapsed_ms()
     fev.close()
+    hist = job.history()
     N = problem.n
     ld = (N + 63) // 64 * 64
     elem = 8 if problem.dtype == "c64" else 16
@@ -241,7 +243,8 @@ def time_deferred(problem, steps, warmup, poll, delay):
                flush_us=None if fl_ms is None else fl_ms * 1e3,
                flush_tflops=None if fl_ms is None else 8.0 * N * ld * delay / (fl_ms * 1e-3) / 1e12,
                flush_gbs=None if fl_ms is None else 2 * elem * N * ld / (fl_ms * 1e-3) / 1e9,
-               fom_last=job.fom(), status=job.status())
+               fom_last=job.fom(), status=job.status(),
+               last_run_pixels=[int(x) for x in hist[:, 0]])
     del job
     torch.cuda.empty_cache()
     return out
@@ -456,30 +459,62 @@ def main():
         _log(f"[bench] serving mix {serving['mix']}")
         _log(f"[bench] serving one-at-a-time {serving['one_at_a_time']}")
 
+    N, R, ld = problem.n, problem.rows, (problem.n + 63) // 64 * 64
+    eager_roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": achieved / HBM_PEAK_GBS,
+                  "traffic": pmc_traffic("k_rank1", problem.name, res["k1_variant"]),
+                  "traffic_unit": "bytes/launch",
+                  "kernel": "k_rank1 (streaming rank-1 update)",
+                  "bytes_per_launch": bytes_per_launch, "avg_launch_us": res["k1_ms"] * 1e3,
+                  "variant": res["k1_variant"], "copy_ceiling_gbs": copy_gbs}
+    eager = dict(value=value, unit="steps/s", ms_per_step=1e3 * res["seconds"] / res["accepted"],
+                 restarts=res["restarts"], roofline=eager_roof)
+    d = (deferred or {}).get(problem.name)
+    if d is not None and d.get("flush_us"):
+        mode = f"deferred rank-1 updates, flush every {d['delay']} moves"
+        head_value = d["steps_per_s"]
+        head_ms = d["ms_per_step"]
+        flops = 8.0 * N * ld * d["delay"]
+        peak = MFMA_PEAK_TFLOPS[problem.dtype]
+        roofline = {"bound": "mfma", "achieved": d["flush_tflops"], "peak": peak,
+                    "unit": "TFLOP/s", "frac": d["flush_tflops"] / peak,
+                    "traffic": pmc_traffic("k_flush_c64", problem.name, d["flush_variant"]),
+                    "traffic_unit": "bytes/launch",
+                    "kernel": "k_flush_c64 (rank-64 flush of the deferred updates, FP32 MFMA)",
+                    "flops_per_launch": flops, "avg_launch_us": d["flush_us"],
+                    "algorithmic_bytes_per_launch": 2 * elem * N * ld,
+                    "variant": d["flush_variant"]}
+        pix = d["last_run_pixels"]
+    else:
+        mode = "eager rank-1 updates"
+        head_value, head_ms, roofline = value, eager["ms_per_step"], eager_roof
+        pix = res["last_run_pixels"]
+    if accuracy is not None and not args.no_cpu_baseline:
+        m = sum(1 for a, b in zip(ref_pixels, pix) if a == b)
+        accuracy["headline_path_pixels_matching"] = f"{m}/{min(len(pix), len(ref_pixels))}"
+    if deferred:
+        for v in deferred.values():
+            v.pop("last_run_pixels", None)
+
     out = {
         "metric": "greedy steps/s at 128^2 px (% HBM peak) vs FP64 plain; served p50/p99 latency",
-        "value": value,
+        "value": head_value,
         "unit": "steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * res["seconds"] / res["accepted"],
+        "ms_per_step": head_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": problem.dtype,
         "data": "synthetic",
         "config": {"workload": problem.name, "grid": f"{problem.ny}x{problem.nx}",
-                   "monitors": problem.n_mon, "storage": problem.dtype,
+                   "monitors": problem.n_mon, "storage": problem.dtype, "mode": mode,
                    "refresh_every": problem.refresh_every, "candidates": "eps {1, 12.25}",
-                   "restarts_in_timed_region": res["restarts"], "step_calls": res["calls"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": pmc_traffic(problem.name, res["k1_variant"]),
-                     "traffic_unit": "bytes/launch",
-                     "kernel": "k_rank1 (streaming rank-1 update)",
-                     "bytes_per_launch": bytes_per_launch, "avg_launch_us": res["k1_ms"] * 1e3,
-                     "variant": res["k1_variant"], "copy_ceiling_gbs": copy_gbs},
+                   "restart_when_trajectory_ends": True},
+        "roofline": roofline,
+        "eager": eager,
         "fp64_plain": plain,
         "cpu_baseline": cpu,
         "accuracy": accuracy,
@@ -490,7 +525,7 @@ def main():
         "device_status": res["status"],
     }
     if plain:
-        out["speedup_vs_fp64_plain"] = value / plain["value"]
+        out["speedup_vs_fp64_plain"] = head_value / plain["value"]
     print(json.dumps(out), flush=True)
 
 
