@@ -32,11 +32,15 @@ MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # dense FP32 / FP64 matrix p
 # exactly 2 GiB (FETCH 1048599.75 KiB -> factor 2.0; WRITE 2097152 KiB -> factor
 # 1.0).  A record is valid only for the kernel source and variant it was measured
 # on: any change to that source file voids it (traffic is then reported as null).
+# Counters: profiles/k_rank1_square128_c64.md and profiles/deferred_step_square128_c64.md.
 FETCH_SCALE = 2097152.0 / 1048599.75
 WRITE_SCALE = 1.0
 PMC_TRAFFIC = [
-    # {"kernel": ..., "source": ..., "sha256": ..., "workload": ..., "variant": ...,
-    #  "fetch_kib": ..., "write_kib": ...}
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "b9f72fda2c118b5250337b3884f89eeb342e4fa9278fd3a0c53f3029af764968", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053777.5, "write_kib": 2105376.25},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "b9f72fda2c118b5250337b3884f89eeb342e4fa9278fd3a0c53f3029af764968", "workload": "square128_c64", "variant": "2x2x1_nt", "fetch_kib": 1053779.0, "write_kib": 2105416.625},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "b9f72fda2c118b5250337b3884f89eeb342e4fa9278fd3a0c53f3029af764968", "workload": "square128_c64", "variant": "1x1x1_nt", "fetch_kib": 1053777.0, "write_kib": 2107658.625},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "b9f72fda2c118b5250337b3884f89eeb342e4fa9278fd3a0c53f3029af764968", "workload": "square128_c64", "variant": "4x4x1_nt", "fetch_kib": 1053783.0, "write_kib": 2105414.125},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_delay.hip", "sha256": "f799cfb0099a16847ad64af4d67b5150dd32518f0acc97964a8e8c5a876ba0c3", "workload": "square128_c64", "variant": "w32", "fetch_kib": 1204753.5, "write_kib": 2097152.0},
 ]
 
 
