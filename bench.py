@@ -459,7 +459,7 @@ def main():
     if args.serve_jobs > 0:
         from paper_2202_05388_amd.serve import serve_benchmark
         _log(f"[bench] serving {args.serve_jobs} jobs at {args.serve_rate}/s (mix, then one at a time)")
-        serving = serve_benchmark(n_jobs=args.serve_jobs, rate=args.serve_rate)
+        serving = serve_benchmark(n_jobs=args.serve_jobs, rate=args.serve_rate, delay=args.delay)
         _log(f"[bench] serving mix {serving['mix']}")
         _log(f"[bench] serving one-at-a-time {serving['one_at_a_time']}")
 

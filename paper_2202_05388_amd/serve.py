@@ -83,11 +83,14 @@ class _Active:
 
 
 class Server:
-    def __init__(self, budget_bytes=288e9, max_slots=16, chunk=16, device="cuda:0"):
+    """delay > 0 serves every job in deferred-update mode (flush every `delay` moves)."""
+
+    def __init__(self, budget_bytes=288e9, max_slots=16, chunk=16, device="cuda:0", delay=0):
         self.budget = float(budget_bytes)
         self.max_slots = int(max_slots)
         self.chunk = int(chunk)
         self.device = device
+        self.delay = int(delay)
 
     # ------------------------------------------------------------------ helpers
     def _issue(self, a: _Active, now_event):
@@ -178,7 +181,8 @@ class Server:
                 stream = torch.cuda.Stream(device=self.device)
                 with torch.cuda.stream(stream):
                     # buffers are zero-filled on the job's own stream, ahead of init_G0
-                    job = Job(p, device=self.device, kmax=km, flip_cap=p.steps + 8)
+                    job = Job(p, device=self.device, kmax=km, flip_cap=p.steps + 8,
+                              delay=self.delay)
                     job.init(stream=stream)
                 a = _Active(rec, job, stream, p.steps, p.refresh_every, self.chunk)
                 a.fp = fp
@@ -224,22 +228,22 @@ def summarize(results, wall):
                 nonzero_status=sum(1 for r in results if r.status))
 
 
-def serve_benchmark(n_jobs=64, rate=4.0, seed=0, max_slots=16, chunk=16, time_scale=1.0):
+def serve_benchmark(n_jobs=64, rate=4.0, seed=0, max_slots=16, chunk=16, time_scale=1.0, delay=64):
     """The served workload: a seeded Poisson stream of jobs (grid side 24..160,
     wavelength 0.8..1.2, 200..1000 step budget, complex64, refresh every 256),
     served concurrently and, for comparison, one at a time in arrival order."""
     import workloads as W
     jobs = W.served_jobs(n_jobs=n_jobs, rate=rate, seed=seed)
-    mix, smix = Server(max_slots=max_slots, chunk=chunk).run(jobs, mode="mix",
-                                                           time_scale=time_scale)
-    ser, sser = Server(max_slots=1, chunk=chunk).run(jobs, mode="serial", time_scale=time_scale)
+    kw = dict(chunk=chunk, delay=delay)
+    mix, smix = Server(max_slots=max_slots, **kw).run(jobs, mode="mix", time_scale=time_scale)
+    ser, sser = Server(max_slots=1, **kw).run(jobs, mode="serial", time_scale=time_scale)
     # the same jobs all arriving at once: throughput of the device, not of the arrival process
-    bmix, sbmix = Server(max_slots=max_slots, chunk=chunk).run(jobs, mode="mix", time_scale=0.0)
-    bser, sbser = Server(max_slots=1, chunk=chunk).run(jobs, mode="serial", time_scale=0.0)
+    bmix, sbmix = Server(max_slots=max_slots, **kw).run(jobs, mode="mix", time_scale=0.0)
+    bser, sbser = Server(max_slots=1, **kw).run(jobs, mode="serial", time_scale=0.0)
     dm = {r.job_id: r.digest for r in mix}
     ds = {r.job_id: r.digest for r in ser}
     db = {r.job_id: r.digest for r in bmix}
     same = sum(1 for k in dm if dm[k] == ds.get(k) == db.get(k))
-    return dict(jobs=n_jobs, rate_per_s=rate, seed=seed, max_slots=max_slots,
+    return dict(jobs=n_jobs, rate_per_s=rate, seed=seed, max_slots=max_slots, delay=delay,
                 mix=smix, one_at_a_time=sser, burst_mix=sbmix, burst_one_at_a_time=sbser,
                 results_identical=f"{same}/{len(dm)}")

@@ -15,13 +15,14 @@ def _jobs():
     return [W.Job(j.job_id, j.arrival, j.problem.replace(refresh_every=16)) for j in js]
 
 
-def test_mixed_results_equal_alone():
+@pytest.mark.parametrize("delay", [0, 16])
+def test_mixed_results_equal_alone(delay):
     from paper_2202_05388_amd.serve import Server
     jobs = _jobs()
-    print(f"[case] serving {len(jobs)} jobs: " +
+    print(f"[case] serving {len(jobs)} jobs, delay {delay}: " +
           ", ".join(f"{j.problem.ny}x{j.problem.nx}/{j.problem.steps}" for j in jobs), flush=True)
-    mix, smix = Server(max_slots=4, chunk=8).run(jobs, mode="mix")
-    alone, salone = Server(max_slots=1, chunk=8).run(jobs, mode="serial")
+    mix, smix = Server(max_slots=4, chunk=8, delay=delay).run(jobs, mode="mix")
+    alone, salone = Server(max_slots=1, chunk=8, delay=delay).run(jobs, mode="serial")
     dm = {r.job_id: r for r in mix}
     da = {r.job_id: r for r in alone}
     assert set(dm) == set(da) == {j.job_id for j in jobs}

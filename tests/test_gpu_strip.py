@@ -23,14 +23,15 @@ def _c(z):
     return np.array([complex(*v) for v in z])
 
 
-def test_strip48x2048_c64_matches_oracle():
+@pytest.mark.parametrize("delay", [0, 64])
+def test_strip48x2048_c64_matches_oracle(delay):
     import torch
     from paper_2202_05388_amd.job import Job
     gold = json.load(open(os.path.join(HERE, "golden", "strip48x2048_fp64.json")))
     p = W.STRIP_48x2048
     N = p.n
-    print(f"[case] {p.name}: G {p.storage_bytes() / 1e9:.1f} GB", flush=True)
-    job = Job(p, device="cuda:0", kmax=512)
+    print(f"[case] {p.name}: G {p.storage_bytes() / 1e9:.1f} GB, delay {delay}", flush=True)
+    job = Job(p, device="cuda:0", kmax=512, delay=delay)
     job.init()
     fields = {}
     done = 0
