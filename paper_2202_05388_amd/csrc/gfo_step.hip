@@ -288,7 +288,15 @@ constexpr int kK1Threads = 256;
 // are in flight per batch; PIPE = true issues the loads of the next batch
 // before the stores of the current one.
 template <typename T, int RB, int U, int CPT, bool NT, bool PIPE>
+__device__ __forceinline__ void k_rank1_tile(int R, int64_t ld, int ct, int64_t rt,
+                                             const T* __restrict__ cu, const T* __restrict__ v,
+                                             T* __restrict__ G);
+
+// Tiles are visited grid-stride (tile = blockIdx.x, blockIdx.x + gridDim.x, ...), so
+// the launch can stay below the 2^32 work-item limit of one dispatch on any shape.
+template <typename T, int RB, int U, int CPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(kK1Threads) void k_rank1(int R, int64_t ld, int ncoltiles,
+                                                      int64_t ntiles,
                                                       const Snap* __restrict__ snap,
                                                       const T* __restrict__ cu,
                                                       const T* __restrict__ v, T* __restrict__ G) {
@@ -296,8 +304,17 @@ __global__ __launch_bounds__(kK1Threads) void k_rank1(int R, int64_t ld, int nco
   constexpr int VN = Vec16<T>::n;
   static_assert(RB % U == 0, "RB must be a multiple of U");
   if (snap->j < 0) return;
-  const int ct = blockIdx.x % ncoltiles;
-  const int rt = blockIdx.x / ncoltiles;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    k_rank1_tile<T, RB, U, CPT, NT, PIPE>(R, ld, (int)(tile % ncoltiles), tile / ncoltiles, cu, v, G);
+  }
+}
+
+template <typename T, int RB, int U, int CPT, bool NT, bool PIPE>
+__device__ __forceinline__ void k_rank1_tile(int R, int64_t ld, int ct, int64_t rt,
+                                             const T* __restrict__ cu, const T* __restrict__ v,
+                                             T* __restrict__ G) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
   const int64_t qb = (int64_t)ct * (kK1Threads * VN * CPT) + threadIdx.x * VN;
   V vv[CPT];
   bool ok[CPT];
@@ -307,7 +324,7 @@ __global__ __launch_bounds__(kK1Threads) void k_rank1(int R, int64_t ld, int nco
     ok[c] = q < ld;
     vv[c] = ok[c] ? *reinterpret_cast<const V*>(v + q) : V{};
   }
-  const int r0 = rt * RB;
+  const int r0 = (int)(rt * RB);
   auto load_batch = [&](int rr, V (&gv)[U][CPT], T (&cv)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -369,22 +386,27 @@ struct K1Variant {
   void (*launch)(int R, int64_t ld, const Snap*, const void*, const void*, void*, hipStream_t);
 };
 
-template <typename T, int RB, int U, int CPT, bool NT, bool PIPE>
+// at most MAXB workgroups per launch (4M x 256 work-items stays far below 2^32)
+template <typename T, int RB, int U, int CPT, bool NT, bool PIPE, int64_t MAXB = (int64_t)1 << 22>
 static void launch_k1(int R, int64_t ld, const Snap* snap, const void* cu, const void* v, void* G,
                       hipStream_t s) {
   constexpr int VN = Vec16<T>::n;
   constexpr int cols = kK1Threads * VN * CPT;
   const int ncol = (int)((ld + cols - 1) / cols);
-  const int nrow = (R + RB - 1) / RB;
-  hipLaunchKernelGGL((k_rank1<T, RB, U, CPT, NT, PIPE>), dim3((unsigned)(ncol * nrow)),
-                     dim3(kK1Threads), 0, s, R, ld, ncol, snap, (const T*)cu, (const T*)v, (T*)G);
+  const int64_t nrow = (R + RB - 1) / RB;
+  const int64_t ntiles = (int64_t)ncol * nrow;
+  const int64_t nblk = ntiles < MAXB ? ntiles : MAXB;
+  hipLaunchKernelGGL((k_rank1<T, RB, U, CPT, NT, PIPE>), dim3((unsigned)nblk), dim3(kK1Threads), 0,
+                     s, R, ld, ncol, ntiles, snap, (const T*)cu, (const T*)v, (T*)G);
 }
 
-// name: rows-per-workgroup x rows-in-flight x 16B-chunks-per-thread [_nt] [_pipe].
+// name: rows-per-workgroup x rows-in-flight x 16B-chunks-per-thread [_nt] [_pipe]
+// [_gB: at most B workgroups, each walking many tiles].
 // Entry 0 is the default: the fastest on the 128x128 and 48x2048 problems on
 // MI355X for both storage types (2 rows per short-lived workgroup, non-temporal
 // loads and stores).
 #define K1V(T, RB, U, CPT, NT, PIPE, NAME) {NAME, launch_k1<T, RB, U, CPT, NT, PIPE>}
+#define K1G(T, RB, U, CPT, NT, PIPE, MAXB, NAME) {NAME, launch_k1<T, RB, U, CPT, NT, PIPE, MAXB>}
 #define K1_TABLE(T)                                                                         \
   {                                                                                         \
     K1V(T, 2, 2, 1, true, false, "2x2x1_nt"), K1V(T, 4, 4, 1, true, false, "4x4x1_nt"),     \
@@ -405,10 +427,12 @@ static void launch_k1(int R, int64_t ld, const Snap* snap, const void* cu, const
     K1V(T, 8, 8, 2, true, false, "8x8x2_nt"), K1V(T, 2, 2, 4, true, false, "2x2x4_nt"),       \
     K1V(T, 16, 16, 1, true, false, "16x16x1_nt"), K1V(T, 4, 4, 4, true, false, "4x4x4_nt"),   \
     K1V(T, 32, 8, 1, true, true, "32x8x1_nt_pipe"), K1V(T, 16, 4, 1, true, true, "16x4x1_nt_pipe"), \
+    K1G(T, 2, 1, 1, true, false, 64, "2x1x1_nt_g64"),                                      \
   }
 static const K1Variant kK1c64[] = K1_TABLE(float2);
 static const K1Variant kK1c128[] = K1_TABLE(double2);
 #undef K1_TABLE
+#undef K1G
 #undef K1V
 static std::atomic<int> g_k1_sel[2] = {{0}, {0}};
 static std::atomic<hipEvent_t> g_k1_before{nullptr}, g_k1_after{nullptr};

@@ -39,6 +39,11 @@ class EventPool:
         self.used = 0
 
     def next(self):
+        if self.used == len(self.pairs):          # grow on demand
+            a, b = C.c_void_p(), C.c_void_p()
+            if hip().hipEventCreate(C.byref(a)) or hip().hipEventCreate(C.byref(b)):
+                raise RuntimeError("hipEventCreate failed")
+            self.pairs.append((a.value, b.value))
         p = self.pairs[self.used]
         self.used += 1
         return p
