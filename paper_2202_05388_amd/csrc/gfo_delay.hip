@@ -17,24 +17,59 @@ namespace gfo {
 // coalesced across lanes).
 constexpr int D = GFO_MAX_DELAY;
 
-// Threads [0, R): u_r = G_t[r, j] (base + pending for design rows; monitor rows
-// are current); cu_r = c u_r is stored as term `slot` and in `cu`;
-// E_r += cu_r E_j.  Threads [R, R + ld): v_q = G_t[j, q] (q < N, 0 beyond),
-// stored as term `slot` and in `v`.
+// The move's scalars, computed by every thread from values no thread of this
+// launch writes (pick, eps_idx[j], diag64[j], E[j], the term count).
 template <typename T>
-__global__ void k_gather_dl(Geo g, const Snap* __restrict__ snap, const T* __restrict__ G,
-                            T* __restrict__ E, T* __restrict__ CU, T* __restrict__ V,
-                            T* __restrict__ CUs, T* __restrict__ Vs,
-                            T* __restrict__ cu_out, T* __restrict__ v_out) {
-  const int j = snap->j;
+__device__ __forceinline__ Snap deferred_snapshot(const Geo& g, const gfo_pick* __restrict__ pick,
+                                                  const T* __restrict__ E,
+                                                  const double2* __restrict__ diag64,
+                                                  const uint8_t* __restrict__ eps_idx,
+                                                  const int32_t* __restrict__ count) {
+  Snap s = {};
+  s.j = -1;
+  const int j = pick->pixel, e = pick->eps_idx;
+  if (j >= 0 && j < g.N && e >= 0 && e < g.n_eps && e != (int)eps_idx[j]) {
+    const double a = g.k0sq * (g.eps[e] - g.eps[eps_idx[j]]);
+    const double2 d = diag64[j];
+    const double2 den = make_double2(1.0 - a * d.x, -a * d.y);
+    if (cabs2(den) < 1e-24) {
+      s.pad1 = 1;                           // singular: refused, flagged by the next kernel
+    } else {
+      s.j = j;
+      s.e_new = e;
+      s.alpha = a;
+      s.c = rdiv(a, den);
+      s.Ej = St<T>::to_d(E[j]);
+      s.dj = d;
+      s.slot = *count;
+    }
+  }
+  return s;
+}
+
+// Threads [0, R): u_r = G_t[r, j] (base + pending for design rows; monitor rows
+// are current); cu_r = c u_r is stored as term `slot` (both layouts) and in `cu`.
+// Threads [R, R + ld): v_q = G_t[j, q] (q < N, 0 beyond), stored likewise and in
+// `v`.  Workgroup 0 publishes the snapshot for the next kernel.  This kernel
+// writes nothing that it reads.
+template <typename T>
+__global__ void k_gather_dl(Geo g, const gfo_pick* __restrict__ pick, const T* __restrict__ G,
+                            const T* __restrict__ E, const double2* __restrict__ diag64,
+                            const uint8_t* __restrict__ eps_idx, const int32_t* __restrict__ count,
+                            Snap* __restrict__ snap_out, T* __restrict__ CU, T* __restrict__ V,
+                            T* __restrict__ CUs, T* __restrict__ Vs, T* __restrict__ cu_out,
+                            T* __restrict__ v_out) {
+  const Snap sn = deferred_snapshot<T>(g, pick, E, diag64, eps_idx, count);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *snap_out = sn;
+  const int j = sn.j;
   if (j < 0) return;
-  const int slot = snap->slot;
+  const int slot = sn.slot;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < g.R) {
     const int64_t i = t;
     double2 u;
     if (i == j) {
-      u = snap->dj;
+      u = sn.dj;
     } else {
       u = St<T>::to_d(G[i * g.ld + j]);
       if (i < g.N) {
@@ -44,18 +79,16 @@ __global__ void k_gather_dl(Geo g, const Snap* __restrict__ snap, const T* __res
         for (int s = 0; s < slot; ++s) u = cadd(u, cmul(St<T>::to_d(cr[s]), St<T>::to_d(vj[s])));
       }
     }
-    const double2 cu_d = cmul(snap->c, u);
-    const T cu = St<T>::from_d(cu_d);
+    const T cu = St<T>::from_d(cmul(sn.c, u));
     CU[i * D + slot] = cu;
     CUs[(int64_t)slot * g.R + i] = cu;
     cu_out[i] = cu;
-    E[i] = St<T>::from_d(cadd(St<T>::to_d(E[i]), cmul(cu_d, snap->Ej)));
   } else if (t < g.R + g.ld) {
     const int64_t q = t - g.R;
     double2 v = make_double2(0.0, 0.0);
     if (q < g.N) {
       if (q == j) {
-        v = snap->dj;
+        v = sn.dj;
       } else {
         v = St<T>::to_d(G[(int64_t)j * g.ld + q]);
         const T* __restrict__ cj = CU + (int64_t)j * D;
@@ -71,24 +104,47 @@ __global__ void k_gather_dl(Geo g, const Snap* __restrict__ snap, const T* __res
   }
 }
 
-// Monitor rows stay current: G[N+m, q] += cu[N+m] v[q]; the FP64 diagonal gets
-// diag64[q] += cu[q] v[q] (q != j) and diag64[j] = d_j / (1 - alpha d_j).
+// Applies the move's O(R) and O(N) parts: E_r += cu_r E_j for every row, the
+// monitor rows G[N+m, q] += cu[N+m] v[q], diag64[q] += cu[q] v[q] (q != j),
+// diag64[j] = d_j / (1 - alpha d_j); then records the move (eps_idx, history,
+// move counter, term count).  Grid x covers max(R, ld); y walks the monitors.
 template <typename T>
 __global__ void k_mon_dl(Geo g, const Snap* __restrict__ snap, const T* __restrict__ cu,
-                         const T* __restrict__ v, T* __restrict__ G, double2* __restrict__ diag64) {
+                         const T* __restrict__ v, T* __restrict__ G, T* __restrict__ E,
+                         double2* __restrict__ diag64, uint8_t* __restrict__ eps_idx,
+                         int32_t* __restrict__ flips, int flip_cap, int32_t* __restrict__ n_flips,
+                         int32_t* __restrict__ status, int32_t* __restrict__ count) {
   const int j = snap->j;
-  if (j < 0) return;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= g.ld) return;
-  const double2 vq = St<T>::to_d(v[q]);
-  if (blockIdx.y == 0 && q < g.N) {
-    if (q == j) {
-      const double2 d = snap->dj;
-      diag64[j] = cmul(d, rdiv(1.0, make_double2(1.0 - snap->alpha * d.x, -snap->alpha * d.y)));
-    } else {
-      diag64[q] = cadd(diag64[q], cmul(St<T>::to_d(cu[q]), vq));
+  if (j < 0) {
+    if (q == 0 && blockIdx.y == 0 && snap->pad1) atomicOr(status, GFO_STATUS_SINGULAR);
+    return;
+  }
+  if (blockIdx.y == 0) {
+    if (q < g.R) E[q] = St<T>::from_d(cadd(St<T>::to_d(E[q]), cmul(St<T>::to_d(cu[q]), snap->Ej)));
+    if (q < g.N) {
+      if (q == j) {
+        const double2 d = snap->dj;
+        diag64[j] = cmul(d, rdiv(1.0, make_double2(1.0 - snap->alpha * d.x, -snap->alpha * d.y)));
+      } else {
+        diag64[q] = cadd(diag64[q], cmul(St<T>::to_d(cu[q]), St<T>::to_d(v[q])));
+      }
+    }
+    if (q == 0) {
+      eps_idx[j] = (uint8_t)snap->e_new;
+      const int n = *n_flips;
+      if (n < flip_cap) {
+        flips[2 * n] = j;
+        flips[2 * n + 1] = snap->e_new;
+      } else {
+        atomicOr(status, GFO_STATUS_HISTORY_FULL);
+      }
+      *n_flips = n + 1;
+      *count = snap->slot + 1;
     }
   }
+  if (q >= g.ld) return;
+  const double2 vq = St<T>::to_d(v[q]);
   for (int m = blockIdx.y; m < g.nmon; m += gridDim.y) {
     const int64_t r = g.N + m;
     T* p = G + r * g.ld + q;
@@ -242,27 +298,29 @@ hipError_t launch_dl_reset(const Geo&, gfo_state* st, const Layout& L, hipStream
 }
 
 template <typename T>
-hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, const Snap* snap,
+hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* pick,
                                  hipStream_t s) {
   char* w = (char*)st->work;
-  T* CU = (T*)(w + L.dl_CU);
-  T* V = (T*)(w + L.dl_V);
-  T* CUs = (T*)(w + L.dl_CUs);
-  T* Vs = (T*)(w + L.dl_Vs);
+  Snap* snap = (Snap*)(w + L.snap);
+  int32_t* count = (int32_t*)(w + L.dl_hdr);
   T* cu = (T*)(w + L.cu);
   T* v = (T*)(w + L.v);
   const int64_t n = (int64_t)g.R + g.ld;
-  hipLaunchKernelGGL(k_gather_dl<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, snap,
-                     (const T*)st->G, (T*)st->E, CU, V, CUs, Vs, cu, v);
-  dim3 gm((unsigned)((g.ld + 255) / 256), (unsigned)(g.nmon < 65535 ? g.nmon : 65535));
-  hipLaunchKernelGGL(k_mon_dl<T>, gm, dim3(256), 0, s, g, snap, (const T*)cu, (const T*)v,
-                     (T*)st->G, (double2*)st->diag64);
+  hipLaunchKernelGGL(k_gather_dl<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, pick,
+                     (const T*)st->G, (const T*)st->E, (const double2*)st->diag64,
+                     (const uint8_t*)st->eps_idx, (const int32_t*)count, snap, (T*)(w + L.dl_CU),
+                     (T*)(w + L.dl_V), (T*)(w + L.dl_CUs), (T*)(w + L.dl_Vs), cu, v);
+  const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
+  dim3 gm((unsigned)((nx + 255) / 256), (unsigned)(g.nmon < 65535 ? g.nmon : 65535));
+  hipLaunchKernelGGL(k_mon_dl<T>, gm, dim3(256), 0, s, g, (const Snap*)snap, (const T*)cu,
+                     (const T*)v, (T*)st->G, (T*)st->E, (double2*)st->diag64, st->eps_idx, st->flips,
+                     st->flip_cap, st->n_flips, st->status, count);
   return hipGetLastError();
 }
 template hipError_t launch_apply_deferred<float2>(const Geo&, gfo_state*, const Layout&,
-                                                  const Snap*, hipStream_t);
+                                                  const gfo_pick*, hipStream_t);
 template hipError_t launch_apply_deferred<double2>(const Geo&, gfo_state*, const Layout&,
-                                                   const Snap*, hipStream_t);
+                                                   const gfo_pick*, hipStream_t);
 
 hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {
   char* w = (char*)st->work;

@@ -49,7 +49,7 @@ struct Snap {
   int32_t j;          // pixel, -1 = no move
   int32_t e_new;
   int32_t slot;       // deferred mode: index of this move's pending term
-  int32_t pad1;
+  int32_t pad1;       // deferred mode: 1 = singular denominator, move refused
   double alpha;
   double pad2;
   double2 c;          // alpha / (1 - alpha G_jj)
@@ -67,6 +67,7 @@ struct Layout {
   size_t mon_xy;    // 2*nmon double
   size_t scores;    // N*n_eps double
   size_t partial;   // kScoreMaxBlocks double
+  size_t ticket;    // int32 ticket of the fused score + greedy pick (zero between launches)
   size_t picks;     // GFO_MAX_RANK_K gfo_pick (internal rank-k scratch)
   size_t snap;      // Snap
   size_t cu;        // R x 16 B: c * G[:, j] (storage type)
@@ -114,7 +115,7 @@ hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo
 int launch_refresh(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
 hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
 template <typename T>
-hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, const Snap* snap,
+hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* pick,
                                  hipStream_t s);
 hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const double2* CU,
                                    const double2* V, double2* G, hipStream_t s);
