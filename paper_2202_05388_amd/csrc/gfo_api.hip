@@ -63,7 +63,6 @@ Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   L.mon_xy = take((size_t)p->n_mon * 16);
   L.scores = take(N * p->n_eps * 8);
   L.partial = take(kScoreMaxBlocks * 8);
-  L.ticket = take(256);
   L.picks = take(K * sizeof(gfo_pick));
   L.snap = take(sizeof(Snap));
   L.cu = take(R * 16);

@@ -85,7 +85,7 @@ template <typename T>
 __global__ void k_init_vectors(Geo g, T* __restrict__ E, double2* __restrict__ diag64,
                                uint8_t* __restrict__ eps_idx, const double* __restrict__ mon_xy,
                                const double2* __restrict__ table, int32_t* n_flips,
-                               int32_t* status, int32_t* ticket) {
+                               int32_t* status) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < g.R) {
     double y;
@@ -106,7 +106,6 @@ __global__ void k_init_vectors(Geo g, T* __restrict__ E, double2* __restrict__ d
   if (i == 0) {
     *n_flips = 0;
     *status = 0;
-    *ticket = 0;
   }
 }
 
@@ -127,7 +126,7 @@ static hipError_t init_typed(const Geo& g, gfo_state* st, const Layout& L, hipSt
   }
   hipLaunchKernelGGL(k_init_vectors<T>, dim3((g.R + 255) / 256), dim3(256), 0, s, g, (T*)st->E,
                      (double2*)st->diag64, st->eps_idx, (const double*)mon, (const double2*)table,
-                     st->n_flips, st->status, (int32_t*)(w + L.ticket));
+                     st->n_flips, st->status);
   return hipGetLastError();
 }
 

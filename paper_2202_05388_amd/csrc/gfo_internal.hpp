@@ -67,7 +67,6 @@ struct Layout {
   size_t mon_xy;    // 2*nmon double
   size_t scores;    // N*n_eps double
   size_t partial;   // kScoreMaxBlocks double
-  size_t ticket;    // int32 ticket of the fused score + greedy pick (zero between launches)
   size_t picks;     // GFO_MAX_RANK_K gfo_pick (internal rank-k scratch)
   size_t snap;      // Snap
   size_t cu;        // R x 16 B: c * G[:, j] (storage type)

@@ -44,83 +44,14 @@ __device__ int block_min(int v, int* sh) {
   return r;
 }
 
-// ------------------------------------------------------------------ greedy pick
-// One workgroup: F* = max of the per-workgroup maxima, then the lowest (pixel,
-// material) whose score is within the relative tie band tau of F*; accepted iff
-// F* > FOM (1 + tau), else the sentinel.  When every score workgroup covered one
-// contiguous range of 256 pixels, only the workgroups whose maximum reaches the
-// band are scanned, in order.
-template <typename T>
-__device__ void greedy_pick_block(const Geo& g, const T* __restrict__ E,
-                                  const double* __restrict__ scores,
-                                  const double* __restrict__ partial, int nblk, double tau,
-                                  gfo_pick* __restrict__ out, double* shd, int* shi) {
-  const double fom = cabs2(St<T>::to_d(E[g.N + g.m0]));
-  const int total = g.N * g.n_eps;
-  double m = -INFINITY;
-  for (int i = threadIdx.x; i < nblk; i += blockDim.x) m = fmax(m, partial[i]);
-  m = block_max(m, shd);
-  int first = 0x7fffffff;
-  if (m > fom * (1.0 + tau)) {
-    const double thr = m - tau * m;
-    if (nblk * kScoreThreads >= g.N) {
-      const int span = kScoreThreads * g.n_eps;
-      for (int b = 0; b < nblk; ++b) {
-        if (!(partial[b] >= thr)) continue;             // uniform across the workgroup
-        const int lo = b * span, hi = min(lo + span, total);
-        int f = 0x7fffffff;
-        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-          if (scores[i] >= thr) {
-            f = i;
-            break;
-          }
-        }
-        f = block_min(f, shi);
-        if (f != 0x7fffffff) {
-          first = f;
-          break;
-        }
-      }
-    } else {
-      for (int i = threadIdx.x; i < total; i += blockDim.x) {
-        if (scores[i] >= thr) {
-          first = i;
-          break;
-        }
-      }
-      first = block_min(first, shi);
-    }
-  }
-  if (threadIdx.x == 0) {
-    gfo_pick pk;
-    if (first != 0x7fffffff) {
-      pk.pixel = first / g.n_eps;
-      pk.eps_idx = first - pk.pixel * g.n_eps;
-      pk.fom_new = scores[first];
-      pk.dfom = pk.fom_new - fom;
-    } else {
-      pk.pixel = -1;
-      pk.eps_idx = -1;
-      pk.fom_new = fom;
-      pk.dfom = 0.0;
-    }
-    out[0] = pk;
-  }
-}
-
 // ------------------------------------------------------------------ K3: scores
 // One thread per pixel (grid-stride).  Writes every (pixel, material) score,
 // -inf for non-candidates, and one block maximum per workgroup.
-// With `out` non-null (greedy pick, topk = 1) the last workgroup to finish also
-// makes the pick: every workgroup publishes its scores and maximum (agent-scope
-// fence), takes a ticket, and the workgroup holding the last ticket reads them
-// back after another fence and resets the ticket for the next launch.
 template <typename T>
 __global__ __launch_bounds__(kScoreThreads) void k_score(
     Geo g, const T* __restrict__ G, const T* __restrict__ E, const double2* __restrict__ diag64,
     const uint8_t* __restrict__ eps_idx, uint32_t mask, double* __restrict__ scores,
-    double* __restrict__ partial, int32_t* __restrict__ status, int32_t* __restrict__ ticket,
-    double tau, gfo_pick* __restrict__ out) {
+    double* __restrict__ partial, int32_t* __restrict__ status) {
   __shared__ double sh[kScoreThreads / 64];
   const double2 Em0 = St<T>::to_d(E[g.N + g.m0]);
   const T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
@@ -149,17 +80,6 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(
   best = block_max(best, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = best;
   if (bad) atomicOr(status, GFO_STATUS_NONFINITE);
-  if (out == nullptr) return;
-  __shared__ int is_last;
-  __shared__ int shi[kScoreThreads / 64];
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = (atomicAdd(ticket, 1) == (int)gridDim.x - 1);
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  greedy_pick_block<T>(g, E, scores, partial, (int)gridDim.x, tau, out, sh, shi);
-  if (threadIdx.x == 0) *ticket = 0;
 }
 
 // ------------------------------------------------------------------ K3b: selection
@@ -561,12 +481,9 @@ static hipError_t score_typed(const Geo& g, const gfo_state* st, const Layout& L
   char* w = (char*)st->work;
   int nblk = (g.N + kScoreThreads - 1) / kScoreThreads;
   if (nblk > kScoreMaxBlocks) nblk = kScoreMaxBlocks;
-  int32_t* ticket = (int32_t*)(w + L.ticket);
   hipLaunchKernelGGL(k_score<T>, dim3(nblk), dim3(kScoreThreads), 0, s, g, (const T*)st->G,
                      (const T*)st->E, (const double2*)st->diag64, (const uint8_t*)st->eps_idx, mask,
-                     (double*)(w + L.scores), (double*)(w + L.partial), st->status, ticket, tau,
-                     topk == 1 ? out : (gfo_pick*)nullptr);
-  if (topk == 1) return hipGetLastError();
+                     (double*)(w + L.scores), (double*)(w + L.partial), st->status);
   // the greedy pick scans only the score workgroups that reach the tie band: 256
   // threads suffice; the spaced top-k rescans every score after each pick
   const int sel_threads = topk == 1 ? 256 : kSelectThreads;
