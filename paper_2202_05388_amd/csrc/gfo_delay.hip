@@ -153,6 +153,10 @@ __global__ void k_mon_dl(Geo g, const Snap* __restrict__ snap, const T* __restri
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// Fourth word of a raw buffer resource on gfx9-family chips (32-bit data format;
+// reads past the range return zero).
+constexpr int kBufferDword3 = 0x00020000;
 
 // FP32 flush for complex64 storage: G[m, n] += sum_{s < count} CU[s][m] V[s][n]
 // for design rows m < N and all ld columns, as complex FP32 on the matrix cores
@@ -275,14 +279,251 @@ __global__ __launch_bounds__(256) void k_flush_c64_w64(int M, int R, int64_t ld,
     }
 }
 
+// Variants with TM row tiles of 32 per wave (a 32*TM x 32 output tile; the TM
+// tiles share each B value) and 64*TM x 64 per workgroup.  The accumulators of
+// different row tiles are independent, so consecutive matrix instructions do not
+// wait on each other's results.  THREE_MULT uses three real products per complex
+// product (Gauss): with P = sum Ar Br, Q = sum Ai Bi, S = sum (Ar + Ai)(Br + Bi),
+// re = Gr + P - Q and im = Gi + S - P - Q; the accumulators start at X = Gr,
+// Y = 0, Z = Gr + Gi, so that re = X - Y and im = Z - X - Y.  This removes a
+// quarter of the matrix work; its rounding differs from the four-product form
+// by a few units of FP32 in the last place relative to |G| + |CU||V|.
+template <int TM, bool THREE_MULT>
+__global__ __launch_bounds__(256) void k_flush_c64_tm(int M, int R, int64_t ld,
+                                                      const int32_t* __restrict__ count,
+                                                      const float2* __restrict__ CU,
+                                                      const float2* __restrict__ V,
+                                                      float2* __restrict__ G) {
+  const int K = *count;
+  if (K == 0) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * (64 * TM) + (w >> 1) * (32 * TM);
+  const int n = blockIdx.x * 64 + (w & 1) * 32 + (lane & 31);
+  const int h = lane >> 5;
+  f32x16 X[TM], Y[TM], Z[TM];
+#pragma unroll
+  for (int t = 0; t < TM; ++t) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r = m0 + 32 * t + 8 * (e >> 2) + 4 * h + (e & 3);
+      const float2 gv = r < M ? G[(int64_t)r * ld + n] : make_float2(0.f, 0.f);
+      X[t][e] = gv.x;
+      if (THREE_MULT) {
+        Y[t][e] = 0.f;
+        Z[t][e] = gv.x + gv.y;
+      } else {
+        Y[t][e] = gv.y;
+      }
+    }
+  }
+#pragma unroll 2
+  for (int k0 = 0; k0 < K; k0 += 2) {
+    const int kk = k0 + h;
+    float2 a[TM], b = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < TM; ++t) a[t] = make_float2(0.f, 0.f);
+    if (kk < K) {
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const int am = m0 + 32 * t + (lane & 31);
+        if (am < M) a[t] = CU[(int64_t)kk * R + am];
+      }
+      b = V[(int64_t)kk * ld + n];
+    }
+    if (THREE_MULT) {
+      const float bs = b.x + b.y;
+#pragma unroll
+      for (int t = 0; t < TM; ++t) X[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].x, b.x, X[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < TM; ++t) Y[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].y, b.y, Y[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < TM; ++t)
+        Z[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].x + a[t].y, bs, Z[t], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int t = 0; t < TM; ++t) X[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].x, b.x, X[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < TM; ++t) Y[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].x, b.y, Y[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < TM; ++t) X[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[t].y, b.y, X[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < TM; ++t) Y[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].y, b.x, Y[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TM; ++t) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r = m0 + 32 * t + 8 * (e >> 2) + 4 * h + (e & 3);
+      if (r >= M) continue;
+      const float2 out = THREE_MULT ? make_float2(X[t][e] - Y[t][e], Z[t][e] - X[t][e] - Y[t][e])
+                                    : make_float2(X[t][e], Y[t][e]);
+      G[(int64_t)r * ld + n] = out;
+    }
+  }
+}
+
+// Prefetching variant, 32 x 32 per wave and 64 x 64 per workgroup: every CU and
+// V operand of the wave (all GFO_MAX_DELAY slots, 32 instruction steps; slots
+// past the pending count contribute zero) is loaded into registers first, then
+// the wave's G tile is requested, and the products accumulate from zero while
+// the G loads are in flight; G is added in the epilogue.  Vector loads complete
+// in issue order, so the operands are ready without waiting for G.  A partial
+// flush costs as much as a full one.  Byte offsets are 32-bit: the launcher uses
+// this form only when GFO_MAX_DELAY * max(R, ld) * 8 < 2^31.  THREE_MULT as in
+// k_flush_c64_tm.
+template <bool THREE_MULT>
+__global__ __launch_bounds__(256) void k_flush_c64_pf(int M, int R, int64_t ld,
+                                                      const int32_t* __restrict__ count,
+                                                      const float2* __restrict__ CU,
+                                                      const float2* __restrict__ V,
+                                                      float2* __restrict__ G) {
+  const int K = *count;
+  if (K == 0) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
+  const int n = blockIdx.x * 64 + (w & 1) * 32 + (lane & 31);
+  const int h = lane >> 5;
+  const int am = m0 + (lane & 31);
+  constexpr int P = GFO_MAX_DELAY / 2;           // instruction steps (two terms each)
+  // Operands come through buffer loads whose range ends at the pending count, so
+  // the slots past it (and rows past the end, given an offset beyond the range)
+  // read as zero without a branch or a select: the first product then waits only
+  // for the operand loads, not for the G loads issued after them.
+  const __amdgpu_buffer_rsrc_t ra =
+      __builtin_amdgcn_make_buffer_rsrc((void*)CU, (short)0, K * R * 8, kBufferDword3);
+  const __amdgpu_buffer_rsrc_t rb =
+      __builtin_amdgcn_make_buffer_rsrc((void*)V, (short)0, (int)(K * ld * 8), kBufferDword3);
+  const unsigned a_off = am < M ? (unsigned)(h * R + am) * 8u : 0xFFFFFFF0u;
+  const unsigned b_off = (unsigned)(h * ld + n) * 8u;
+  float2 a[P], b[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const unsigned da = am < M ? (unsigned)(2 * i) * (unsigned)R * 8u : 0u;
+    const auto va = __builtin_amdgcn_raw_buffer_load_b64(ra, a_off + da, 0, 0);
+    const auto vb = __builtin_amdgcn_raw_buffer_load_b64(rb, b_off + (unsigned)(2 * i * ld) * 8u, 0, 0);
+    const f32x2 fa = __builtin_bit_cast(f32x2, va), fb = __builtin_bit_cast(f32x2, vb);
+    a[i] = make_float2(fa[0], fa[1]);
+    b[i] = make_float2(fb[0], fb[1]);
+  }
+  // keep the issue order (operands, then G, then products): the scheduler would
+  // otherwise sink the loads next to their first use
+  __builtin_amdgcn_sched_barrier(0);
+  float2 gv[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
+    gv[e] = G[(int64_t)(r < M ? r : M - 1) * ld + n];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  f32x16 X, Y, Z;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) X[e] = Y[e] = Z[e] = 0.f;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    if (THREE_MULT) {
+      X = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[i].x, X, 0, 0, 0);
+      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[i].y, Y, 0, 0, 0);
+      Z = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x + a[i].y, b[i].x + b[i].y, Z, 0, 0, 0);
+    } else {
+      X = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[i].x, X, 0, 0, 0);
+      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[i].y, Y, 0, 0, 0);
+      X = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[i].y, b[i].y, X, 0, 0, 0);
+      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[i].x, Y, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
+    if (r >= M) continue;
+    const float2 out = THREE_MULT ? make_float2(gv[e].x + (X[e] - Y[e]), gv[e].y + (Z[e] - X[e] - Y[e]))
+                                  : make_float2(gv[e].x + X[e], gv[e].y + Y[e]);
+    G[(int64_t)r * ld + n] = out;
+  }
+}
+
+// Software-pipelined form of k_flush_c64_pf: registers hold the operands of 16
+// instruction steps (half the slots); the G tile is requested after the first
+// 16, and each register is reloaded with the operands 16 steps ahead as soon as
+// its step is consumed.  Same ranged buffer loads (empty slots read as zero), and
+// the same 32-bit offset limit.
+template <bool THREE_MULT>
+__global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld,
+                                                        const int32_t* __restrict__ count,
+                                                        const float2* __restrict__ CU,
+                                                        const float2* __restrict__ V,
+                                                        float2* __restrict__ G) {
+  const int K = *count;
+  if (K == 0) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
+  const int n = blockIdx.x * 64 + (w & 1) * 32 + (lane & 31);
+  const int h = lane >> 5;
+  const int am = m0 + (lane & 31);
+  constexpr int P = GFO_MAX_DELAY / 2, H = P / 2;
+  const __amdgpu_buffer_rsrc_t ra =
+      __builtin_amdgcn_make_buffer_rsrc((void*)CU, (short)0, K * R * 8, kBufferDword3);
+  const __amdgpu_buffer_rsrc_t rb =
+      __builtin_amdgcn_make_buffer_rsrc((void*)V, (short)0, (int)(K * ld * 8), kBufferDword3);
+  const unsigned a_off = am < M ? (unsigned)(h * R + am) * 8u : 0xFFFFFFF0u;
+  const unsigned a_step = am < M ? 2u * (unsigned)R * 8u : 0u;
+  const unsigned b_off = (unsigned)(h * ld + n) * 8u, b_step = 2u * (unsigned)ld * 8u;
+  f32x2 a[H], b[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    a[i] = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(ra, a_off + i * a_step, 0, 0));
+    b[i] = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rb, b_off + i * b_step, 0, 0));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  float2 gv[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
+    gv[e] = G[(int64_t)(r < M ? r : M - 1) * ld + n];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  f32x16 X, Y, Z;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) X[e] = Y[e] = Z[e] = 0.f;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const f32x2 ai = a[i % H], bi = b[i % H];
+    if (i < H) {
+      a[i] = __builtin_bit_cast(f32x2,
+                                __builtin_amdgcn_raw_buffer_load_b64(ra, a_off + (i + H) * a_step, 0, 0));
+      b[i] = __builtin_bit_cast(f32x2,
+                                __builtin_amdgcn_raw_buffer_load_b64(rb, b_off + (i + H) * b_step, 0, 0));
+    }
+    if (THREE_MULT) {
+      X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
+      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[1], bi[1], Y, 0, 0, 0);
+      Z = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0] + ai[1], bi[0] + bi[1], Z, 0, 0, 0);
+    } else {
+      X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
+      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[1], Y, 0, 0, 0);
+      X = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[1], bi[1], X, 0, 0, 0);
+      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[1], bi[0], Y, 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
+    if (r >= M) continue;
+    const float2 out = THREE_MULT ? make_float2(gv[e].x + (X[e] - Y[e]), gv[e].y + (Z[e] - X[e] - Y[e]))
+                                  : make_float2(gv[e].x + X[e], gv[e].y + Y[e]);
+    G[(int64_t)r * ld + n] = out;
+  }
+}
+
 // flush variants for complex64 storage (selected by the autotuner)
 static std::atomic<int> g_flush_sel{0};
-int flush_variant_count() { return 2; }
-const char* flush_variant_name(int i) {
-  return i == 0 ? "w32" : (i == 1 ? "w64_xcd" : nullptr);
-}
+static const char* const kFlushNames[] = {"w32", "w64_xcd", "w32x2", "w32_3m", "w32x2_3m", "w32_pf", "w32_pf_3m", "w32_pipe", "w32_pipe_3m"};
+constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
+int flush_variant_count() { return kFlushCount; }
+const char* flush_variant_name(int i) { return i >= 0 && i < kFlushCount ? kFlushNames[i] : nullptr; }
 int flush_set_variant(int i) {
-  if (i < 0 || i > 1) return GFO_EINVAL;
+  if (i < 0 || i >= kFlushCount) return GFO_EINVAL;
   g_flush_sel.store(i);
   return GFO_OK;
 }
@@ -330,7 +571,36 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
   hipError_t e;
   if (g.dtype == GFO_C64) {
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
-    if (flush_get_variant() == 0) {
+    const int fv = flush_get_variant();
+    const float2* cu = (const float2*)(w + L.dl_CUs);
+    const float2* vv = (const float2*)(w + L.dl_Vs);
+    const dim3 g1((unsigned)(g.ld / 64), (unsigned)((g.N + 63) / 64));
+    const dim3 g2((unsigned)(g.ld / 64), (unsigned)((g.N + 127) / 128));
+    if (fv == 2) {
+      hipLaunchKernelGGL((k_flush_c64_tm<2, false>), g2, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
+                         (float2*)st->G);
+    } else if (fv == 3) {
+      hipLaunchKernelGGL((k_flush_c64_tm<1, true>), g1, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
+                         (float2*)st->G);
+    } else if (fv == 4) {
+      hipLaunchKernelGGL((k_flush_c64_tm<2, true>), g2, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
+                         (float2*)st->G);
+    } else if (fv >= 5 && fv <= 8 &&
+               (int64_t)GFO_MAX_DELAY * (g.ld > g.R ? g.ld : g.R) * 8 >= ((int64_t)1 << 31)) {
+      return hipErrorInvalidValue;
+    } else if (fv == 5) {
+      hipLaunchKernelGGL((k_flush_c64_pf<false>), g1, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
+                         (float2*)st->G);
+    } else if (fv == 6) {
+      hipLaunchKernelGGL((k_flush_c64_pf<true>), g1, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
+                         (float2*)st->G);
+    } else if (fv == 7) {
+      hipLaunchKernelGGL((k_flush_c64_pipe<false>), g1, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
+                         (float2*)st->G);
+    } else if (fv == 8) {
+      hipLaunchKernelGGL((k_flush_c64_pipe<true>), g1, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
+                         (float2*)st->G);
+    } else if (fv == 0) {
       hipLaunchKernelGGL(k_flush_c64, dim3((unsigned)(g.ld / 64), (unsigned)((g.N + 63) / 64)),
                          dim3(256), 0, s, g.N, g.R, g.ld, count, (const float2*)(w + L.dl_CUs),
                          (const float2*)(w + L.dl_Vs), (float2*)st->G);

@@ -484,9 +484,9 @@ static hipError_t score_typed(const Geo& g, const gfo_state* st, const Layout& L
   hipLaunchKernelGGL(k_score<T>, dim3(nblk), dim3(kScoreThreads), 0, s, g, (const T*)st->G,
                      (const T*)st->E, (const double2*)st->diag64, (const uint8_t*)st->eps_idx, mask,
                      (double*)(w + L.scores), (double*)(w + L.partial), st->status);
-  // the greedy pick scans only the score workgroups that reach the tie band: 256
-  // threads suffice; the spaced top-k rescans every score after each pick
-  const int sel_threads = topk == 1 ? 256 : kSelectThreads;
+  // the greedy pick scans only the score workgroups that reach the tie band: one
+  // wave suffices; the spaced top-k rescans every score after each pick
+  const int sel_threads = topk == 1 ? 64 : kSelectThreads;   // one wave: no cross-wave barriers
   hipLaunchKernelGGL(k_select<T>, dim3(1), dim3(sel_threads), 0, s, g, (const T*)st->E,
                      (double*)(w + L.scores), (const double*)(w + L.partial), nblk, tau, topk,
                      spacing, out);

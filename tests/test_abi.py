@@ -110,4 +110,6 @@ def test_k1_variants_listed():
         names = L.k1_variants(dt)
         assert len(names) >= 4 and len(set(names)) == len(names)
     assert L.lib().gfo_k1_set_variant(L.GFO_C64, 999) == L.GFO_EINVAL
+    assert L.flush_variants() == ["w32", "w64_xcd", "w32x2", "w32_3m", "w32x2_3m", "w32_pf",
+                                  "w32_pf_3m", "w32_pipe", "w32_pipe_3m"]
     assert L.lib().gfo_strerror(L.GFO_ENOSPC) == b"workspace too small"

@@ -132,3 +132,32 @@ def test_graph_replays_equal_stream_launches(dtype, delay):
     Gr, Er, dr, ir = ref.host_state()
     G, E, d, i = job.host_state()
     assert np.array_equal(G, Gr) and np.array_equal(E, Er) and np.array_equal(d, dr)
+
+
+def test_flush_variants_agree():
+    """Every complex64 flush variant gives the eager move sequence and state; the
+    four-product variants round identically to each other, bit for bit."""
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(40, 44, n_mon=8, dtype="c64", cand_mask=W.MASK_BOTH)
+    eager = _job(p)
+    eager.init()
+    n_ref = eager.run_greedy(150, poll_every=25)
+    Ge, Ee, de, ie = eager.host_state()
+    names = L.flush_variants()
+    old = L.flush_get_variant()
+    states = {}
+    try:
+        for vi, name in enumerate(names):
+            L.flush_set_variant(vi)
+            print(f"[flush variant] {name}", flush=True)
+            job = _job(p, delay=64)
+            job.init()
+            assert job.run_greedy(150, poll_every=25) == n_ref
+            assert np.array_equal(job.history(), eager.history())
+            G, E, d, i = job.host_state()
+            assert _rel(G, Ge) <= 3e-6 and _rel(E, Ee) <= 3e-6 and np.array_equal(i, ie)
+            states[name] = G
+    finally:
+        L.flush_set_variant(old)
+    assert np.array_equal(states["w32"], states["w32x2"])
+    assert np.array_equal(states["w32_3m"], states["w32x2_3m"])
