@@ -60,8 +60,13 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_steps(job, target, poll, events=None, refresh_every=0, flush_events=None):
+# extra columns of G beyond the minimum leading dimension (--ld-pad)
+LD_PAD = 0
+
+
+def run_steps(job, target, poll, events=None, refresh_every=0, flush_events=None, fused=False):
     """Issue greedy steps until `target` accepted moves; re-init a job that stopped.
+    fused: each chunk of steps is one gfo_greedy_steps call.
 
     Returns (accepted, calls, restarts, accepted_flags) where accepted_flags[i]
     tells whether step call i made a move.
@@ -78,14 +83,22 @@ def run_steps(job, target, poll, events=None, refresh_every=0, flush_events=None
         chunk = min(poll, target - accepted)
         if refresh_every:
             chunk = min(chunk, refresh_every - in_run_acc % refresh_every)
-        for _ in range(chunk):
-            if events is not None:
-                a, b = events.next()
+        if fused:
+            # every call counts toward the flush interval, so a chunk that reaches it
+            # is certain to launch a flush: time the first one
+            if flush_events is not None and job.state.pending_calls + chunk >= job.delay:
+                a, b = flush_events.next()
                 L.time_next_k1(a, b)
-            elif flush_events is not None and job.state.pending_calls == job.delay - 1:
-                a, b = flush_events.next()       # this step's apply_flip ends with a flush
-                L.time_next_k1(a, b)
-            job.step()
+            job.greedy_steps(chunk)
+        else:
+            for _ in range(chunk):
+                if events is not None:
+                    a, b = events.next()
+                    L.time_next_k1(a, b)
+                elif flush_events is not None and job.state.pending_calls == job.delay - 1:
+                    a, b = flush_events.next()       # this step's apply_flip ends with a flush
+                    L.time_next_k1(a, b)
+                job.step()
         calls += chunk
         n = job.n_flips()                     # host sync
         new = n - in_run_acc
@@ -134,7 +147,7 @@ def time_workload(problem, steps, warmup, poll, with_events=True, autotune=True)
     from paper_2202_05388_amd import autotune as at
 
     kmax = max(problem.refresh_every, 0) * 2 if problem.refresh_every else 0
-    job = Job(problem, device="cuda:0", kmax=kmax)
+    job = Job(problem, device="cuda:0", kmax=kmax, ld_pad=LD_PAD)
     job.init()
     tuned = None
     if autotune:
@@ -167,15 +180,16 @@ def time_workload(problem, steps, warmup, poll, with_events=True, autotune=True)
                 k1_variant=None if tuned is None else tuned["name"])
 
 
-def time_deferred_graph(problem, steps, warmup, delay):
-    """Deferred mode with every window of `delay` steps replayed from a HIP graph."""
+def time_deferred_graph(problem, steps, warmup, delay, fused=True):
+    """Deferred mode with every window of `delay` steps replayed from a HIP graph
+    (captured from gfo_greedy_steps when fused)."""
     import torch
     from paper_2202_05388_amd.job import Job
 
     kmax = 2 * problem.refresh_every if problem.refresh_every else 0
-    job = Job(problem, device="cuda:0", kmax=kmax, delay=delay)
+    job = Job(problem, device="cuda:0", kmax=kmax, delay=delay, ld_pad=LD_PAD)
     job.init()
-    g, s = job.capture_steps(delay)
+    g, s = job.capture_steps(delay, fused=fused)
     re = problem.refresh_every
 
     def run(target):
@@ -200,7 +214,7 @@ def time_deferred_graph(problem, steps, warmup, delay):
     acc, restarts = run(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    out = dict(delay=delay, storage=problem.dtype, graph_window=delay, accepted=acc,
+    out = dict(delay=delay, fused=fused, storage=problem.dtype, graph_window=delay, accepted=acc,
                restarts=restarts, steps_per_s=acc / dt, ms_per_step=1e3 * dt / acc,
                fom_last=job.fom(), status=job.status())
     del job, g
@@ -208,30 +222,36 @@ def time_deferred_graph(problem, steps, warmup, delay):
     return out
 
 
-def time_deferred(problem, steps, warmup, poll, delay):
+def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True):
     """Greedy steps with deferred rank-1 updates: E, the FP64 diagonal and the monitor
     rows every step, the design block by one rank-`delay` matrix-core product per
-    `delay` steps.  Times the flush kernel with HIP events on its stream."""
+    `delay` steps.  fused: gfo_greedy_steps (two kernels per move), else
+    score_candidates + apply_flip per move.  Times the flush kernel with HIP
+    events on its stream."""
     import torch
     from paper_2202_05388_amd.hiprt import EventPool
     from paper_2202_05388_amd.job import Job
 
     kmax = 2 * problem.refresh_every if problem.refresh_every else 0
-    job = Job(problem, device="cuda:0", kmax=kmax, delay=delay)
+    job = Job(problem, device="cuda:0", kmax=kmax, delay=delay, ld_pad=LD_PAD)
     job.init()
     flush_tuned = None
     if problem.dtype == "c64":
+        from paper_2202_05388_amd import _lib as L
         from paper_2202_05388_amd import autotune as at
-        flush_tuned = at.tune_flush(job)
-        _log(f"[bench] flush autotune: {flush_tuned}")
-        job.init()
-    run_steps(job, warmup, poll, refresh_every=problem.refresh_every)
+        if tune:
+            flush_tuned = at.tune_flush(job)
+            _log(f"[bench] flush autotune: {flush_tuned}")
+            job.init()
+        else:
+            flush_tuned = dict(name=L.flush_variants()[L.flush_get_variant()])
+    run_steps(job, warmup, poll, refresh_every=problem.refresh_every, fused=fused)
     job.init()
     torch.cuda.synchronize()
     fev = EventPool(steps // delay + 64)
     t0 = time.perf_counter()
     acc, calls, restarts, flags = run_steps(job, steps, poll, None, problem.refresh_every,
-                                            flush_events=fev)
+                                            flush_events=fev, fused=fused)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     fl = fev.elapsed_ms()
@@ -241,7 +261,7 @@ def time_deferred(problem, steps, warmup, poll, delay):
     ld = (N + 63) // 64 * 64
     elem = 8 if problem.dtype == "c64" else 16
     fl_ms = sum(fl) / len(fl) if fl else None
-    out = dict(delay=delay, storage=problem.dtype, accepted=acc, restarts=restarts,
+    out = dict(delay=delay, fused=fused, storage=problem.dtype, accepted=acc, restarts=restarts,
                steps_per_s=acc / dt, ms_per_step=1e3 * dt / acc, flushes_timed=len(fl),
                flush_variant=None if flush_tuned is None else flush_tuned["name"],
                flush_us=None if fl_ms is None else fl_ms * 1e3,
@@ -372,6 +392,8 @@ def main():
     ap.add_argument("--serve-jobs", type=int, default=64,
                     help="jobs in the served stream (0 = skip the serving measurement)")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="job arrivals per second")
+    ap.add_argument("--ld-pad", type=int, default=0,
+                    help="extra columns of G (a multiple of 64) beyond the minimum leading dimension")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also time a plain 2 GiB device copy (HBM ceiling, counter calibration)")
     args = ap.parse_args()
@@ -382,6 +404,8 @@ def main():
 
     import workloads as W
 
+    global LD_PAD
+    LD_PAD = args.ld_pad
     problem = W.WORKLOADS[args.workload]
     _log(f"[bench] {problem.name}: {problem.ny}x{problem.nx}, {problem.n_mon} monitors, "
          f"{problem.dtype}, steps={args.steps} warmup={args.warmup}")
@@ -436,6 +460,10 @@ def main():
             _log(f"[bench] deferred updates, {pf.name}, delay {args.delay}")
             deferred[pf.name] = time_deferred(pf, args.steps, args.warmup, args.poll, args.delay)
             _log(f"[bench] deferred {pf.name}: {deferred[pf.name]}")
+            key = pf.name + "_per_call"
+            deferred[key] = time_deferred(pf, args.steps, args.warmup, args.poll, args.delay,
+                                          fused=False, tune=False)
+            _log(f"[bench] deferred {key}: {deferred[key]}")
             key = pf.name + "_graph"
             deferred[key] = time_deferred_graph(pf, args.steps, args.warmup, args.delay)
             _log(f"[bench] deferred {key}: {deferred[key]}")
@@ -475,7 +503,8 @@ def main():
                  restarts=res["restarts"], roofline=eager_roof)
     d = (deferred or {}).get(problem.name)
     if d is not None and d.get("flush_us"):
-        mode = f"deferred rank-1 updates, flush every {d['delay']} moves"
+        mode = (f"deferred rank-1 updates, flush every {d['delay']} moves, "
+                f"{'fused greedy loop (gfo_greedy_steps)' if d['fused'] else 'per-call'}")
         head_value = d["steps_per_s"]
         head_ms = d["ms_per_step"]
         flops = 8.0 * N * ld * d["delay"]
@@ -484,7 +513,7 @@ def main():
                     "unit": "TFLOP/s", "frac": d["flush_tflops"] / peak,
                     "traffic": pmc_traffic("k_flush_c64", problem.name, d["flush_variant"]),
                     "traffic_unit": "bytes/launch",
-                    "kernel": "k_flush_c64 (rank-64 flush of the deferred updates, FP32 MFMA)",
+                    "kernel": f"flush of the deferred updates, FP32 MFMA, variant {d['flush_variant']}",
                     "flops_per_launch": flops, "avg_launch_us": d["flush_us"],
                     "algorithmic_bytes_per_launch": 2 * elem * N * ld,
                     "variant": d["flush_variant"]}

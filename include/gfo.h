@@ -100,9 +100,10 @@ const char* gfo_version(void);
 /* Human-readable text of a return code. */
 const char* gfo_strerror(int code);
 
-/* Bytes of workspace that a job of this problem needs when refresh_G must
- * support up to kmax flipped pixels (kmax = 0: no refresh).  Host only. */
-int gfo_workspace_size(const gfo_problem* prob, int32_t kmax, size_t* h_bytes);
+/* Bytes of workspace that a job of this problem needs with leading dimension
+ * ldG (0: gfo_min_ld; else at least that and a multiple of 64) when refresh_G
+ * must support up to kmax flipped pixels (kmax = 0: no refresh).  Host only. */
+int gfo_workspace_size(const gfo_problem* prob, int64_t ldG, int32_t kmax, size_t* h_bytes);
 
 /* Smallest valid leading dimension of G for this problem (N rounded up to 64). */
 int64_t gfo_min_ld(const gfo_problem* prob);
@@ -112,7 +113,7 @@ int64_t gfo_min_ld(const gfo_problem* prob);
  * order, -inf where (pixel, eps_idx) is not a candidate (and, after a call
  * with topk > 1, where the spacing rule excluded it).  Host only; for
  * inspection and tests. */
-int gfo_scores_offset(const gfo_problem* prob, int32_t kmax, size_t* h_offset);
+int gfo_scores_offset(const gfo_problem* prob, int64_t ldG, int32_t kmax, size_t* h_offset);
 
 /* init_G0 - Green's matrix and field of the vacuum reference structure
  * (paper Sec. II: an analytic G0 is the starting point; Sec. IV starts from
@@ -174,6 +175,21 @@ int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick,
 /* gfo_flush - bring the design block of G up to date in deferred mode (no-op
  * when nothing is pending or delay = 0). */
 int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
+
+/* gfo_greedy_steps - n_steps greedy moves (paper Sec. II: score every
+ * one-pixel flip, take the best if it improves the FOM by more than the relative
+ * band tau, apply it as the rank-1 update), with the results of n_steps calls
+ * of score_candidates (topk = 1, min_spacing = 0) each followed by apply_flip
+ * on its pick: the same moves, bit for bit the same state.  In deferred mode
+ * (delay > 0) a move takes two kernels instead of four: the previous move's
+ * elementwise updates are fused into the scoring, and the pick into the pivot
+ * gather (every workgroup repeats the pick; it reads only the scores).  Once
+ * the stop rule refuses a move, the remaining steps are no-ops.
+ * d_picks: device array of n_steps records (the pick of each step, sentinel
+ * when refused), or NULL.  n_steps >= 0; cand_mask and tau as for
+ * score_candidates.  Asynchronous on `stream`. */
+int gfo_greedy_steps(const gfo_problem* prob, gfo_state* st, int32_t n_steps,
+                     uint32_t cand_mask, double tau, gfo_pick* d_picks, hipStream_t stream);
 
 /* apply_flips_rank_k - apply k moves jointly by the Woodbury form of the
  * paper's region update (eqs. form10-form14 with V = the k pixels):

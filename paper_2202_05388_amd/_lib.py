@@ -26,7 +26,8 @@ EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "g
            "init_G0", "score_candidates", "apply_flip", "apply_flips_rank_k", "refresh_G",
            "gfo_k1_variant_count", "gfo_k1_variant_name", "gfo_k1_set_variant",
            "gfo_k1_get_variant", "gfo_time_next_k1", "gfo_flush", "gfo_flush_variant_count",
-           "gfo_flush_variant_name", "gfo_flush_set_variant", "gfo_flush_get_variant")
+           "gfo_flush_variant_name", "gfo_flush_set_variant", "gfo_flush_get_variant",
+           "gfo_greedy_steps")
 
 
 class Problem(C.Structure):
@@ -69,16 +70,17 @@ def lib():
     L.gfo_version.restype = C.c_char_p
     L.gfo_strerror.restype = C.c_char_p
     L.gfo_strerror.argtypes = [C.c_int]
-    L.gfo_workspace_size.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
+    L.gfo_workspace_size.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
     L.gfo_min_ld.argtypes = [P]
     L.gfo_min_ld.restype = C.c_int64
-    L.gfo_scores_offset.argtypes = [P, C.c_int32, C.POINTER(C.c_size_t)]
+    L.gfo_scores_offset.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
     L.init_G0.argtypes = [P, S, V]
     L.score_candidates.argtypes = [P, S, C.c_uint32, C.c_double, C.c_int32, C.c_int32, V, V]
     L.apply_flip.argtypes = [P, S, V, V]
     L.apply_flips_rank_k.argtypes = [P, S, V, C.c_int32, C.c_int32, V]
     L.refresh_G.argtypes = [P, S, V]
     L.gfo_flush.argtypes = [P, S, V]
+    L.gfo_greedy_steps.argtypes = [P, S, C.c_int32, C.c_uint32, C.c_double, V, V]
     L.gfo_flush_variant_name.argtypes = [C.c_int32]
     L.gfo_flush_variant_name.restype = C.c_char_p
     L.gfo_flush_set_variant.argtypes = [C.c_int32]
@@ -101,15 +103,15 @@ def version() -> str:
     return lib().gfo_version().decode()
 
 
-def workspace_size(prob: Problem, kmax: int) -> int:
+def workspace_size(prob: Problem, kmax: int, ld: int = 0) -> int:
     out = C.c_size_t(0)
-    check(lib().gfo_workspace_size(C.byref(prob), kmax, C.byref(out)), "gfo_workspace_size")
+    check(lib().gfo_workspace_size(C.byref(prob), ld, kmax, C.byref(out)), "gfo_workspace_size")
     return out.value
 
 
-def scores_offset(prob: Problem, kmax: int) -> int:
+def scores_offset(prob: Problem, kmax: int, ld: int = 0) -> int:
     out = C.c_size_t(0)
-    check(lib().gfo_scores_offset(C.byref(prob), kmax, C.byref(out)), "gfo_scores_offset")
+    check(lib().gfo_scores_offset(C.byref(prob), ld, kmax, C.byref(out)), "gfo_scores_offset")
     return out.value
 
 
@@ -144,6 +146,11 @@ def refresh_G(prob, st, stream) -> None:
 
 def flush(prob, st, stream) -> None:
     check(lib().gfo_flush(C.byref(prob), C.byref(st), stream), "gfo_flush")
+
+
+def greedy_steps(prob, st, n_steps, cand_mask, tau, d_picks, stream) -> None:
+    check(lib().gfo_greedy_steps(C.byref(prob), C.byref(st), n_steps, cand_mask, tau, d_picks,
+                                 stream), "gfo_greedy_steps")
 
 
 def k1_variants(dtype: int):

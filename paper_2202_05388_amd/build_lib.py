@@ -17,6 +17,10 @@ HIPCC_FLAGS = [
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
+    # multiply-adds are fused per source expression only, so one expression gives
+    # the same rounding in every kernel it is inlined into (the fused greedy loop
+    # and the per-call kernels share their update expressions bit for bit)
+    "-ffp-contract=on",
 ]
 
 

@@ -63,10 +63,12 @@ Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   L.mon_xy = take((size_t)p->n_mon * 16);
   L.scores = take(N * p->n_eps * 8);
   L.partial = take(kScoreMaxBlocks * 8);
+  L.pfirst = take(kScoreMaxBlocks * 4);
   L.picks = take(K * sizeof(gfo_pick));
   L.snap = take(sizeof(Snap));
   L.cu = take(R * 16);
   L.v = take((size_t)ld * 16);
+  L.emon = take((size_t)p->n_mon * 16);
   L.rk_S = take(4096);
   L.rk_M = take(K * K * 16);
   L.rk_U64 = take(R * K * 16);
@@ -75,8 +77,6 @@ Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   L.rk_Abf = take(R * 2 * K * 2);
   L.rk_Bbf = take(2 * 2 * K * (size_t)ld * 2);
   L.dl_hdr = take(256);
-  L.dl_CU = take((size_t)GFO_MAX_DELAY * R * 16);
-  L.dl_V = take((size_t)GFO_MAX_DELAY * (size_t)ld * 16);
   L.dl_CUs = take((size_t)GFO_MAX_DELAY * R * 16);
   L.dl_Vs = take((size_t)GFO_MAX_DELAY * (size_t)ld * 16);
   L.rf_V = take((N + 64) * 4);
@@ -125,19 +125,27 @@ const char* gfo_strerror(int code) {
   }
 }
 
-int gfo_workspace_size(const gfo_problem* prob, int32_t kmax, size_t* h_bytes) {
+// ldG argument of the size queries: 0 = the minimum, else checked like state.ldG
+static int64_t query_ld(const gfo_problem* p, int64_t ldG) {
+  if (ldG == 0) return min_ld(p);
+  return ldG >= min_ld(p) && ldG % 64 == 0 ? ldG : -1;
+}
+
+int gfo_workspace_size(const gfo_problem* prob, int64_t ldG, int32_t kmax, size_t* h_bytes) {
   int rc = validate_problem(prob);
   if (rc) return rc;
-  if (!h_bytes || kmax < 0) return GFO_EINVAL;
-  *h_bytes = make_layout(prob, min_ld(prob), kmax).total;
+  const int64_t ld = query_ld(prob, ldG);
+  if (!h_bytes || kmax < 0 || ld < 0) return GFO_EINVAL;
+  *h_bytes = make_layout(prob, ld, kmax).total;
   return GFO_OK;
 }
 
-int gfo_scores_offset(const gfo_problem* prob, int32_t kmax, size_t* h_offset) {
+int gfo_scores_offset(const gfo_problem* prob, int64_t ldG, int32_t kmax, size_t* h_offset) {
   int rc = validate_problem(prob);
   if (rc) return rc;
-  if (!h_offset || kmax < 0) return GFO_EINVAL;
-  *h_offset = make_layout(prob, min_ld(prob), kmax).scores;
+  const int64_t ld = query_ld(prob, ldG);
+  if (!h_offset || kmax < 0 || ld < 0) return GFO_EINVAL;
+  *h_offset = make_layout(prob, ld, kmax).scores;
   return GFO_OK;
 }
 
@@ -206,6 +214,54 @@ int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   const Geo g = make_geo(prob, st->ldG);
   if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;
   st->pending_calls = 0;
+  return GFO_OK;
+}
+
+int gfo_greedy_steps(const gfo_problem* prob, gfo_state* st, int32_t n_steps, uint32_t cand_mask,
+                     double tau, gfo_pick* d_picks, hipStream_t stream) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  Layout L;
+  if ((rc = validate_state(prob, st, &L))) return rc;
+  if (n_steps < 0 || !(tau >= 0.0) || !(tau < 1.0)) return GFO_EINVAL;
+  const uint32_t mask = cand_mask & ((1u << prob->n_eps) - 1u);
+  if (mask == 0) return GFO_EINVAL;
+  if (n_steps == 0) return GFO_OK;
+  const Geo g = make_geo(prob, st->ldG);
+  gfo_pick* internal = (gfo_pick*)((char*)st->work + L.picks);
+  const bool fused = st->delay > 0 && (g.N + kScoreThreads - 1) / kScoreThreads <= kScoreMaxBlocks;
+  if (!fused) {
+    for (int t = 0; t < n_steps; ++t) {
+      gfo_pick* pk = d_picks ? d_picks + t : internal;
+      if (launch_score(g, st, L, mask, tau, 1, 0, pk, stream) != hipSuccess) return GFO_EHIP;
+      if (launch_apply(g, st, L, pk, stream) != hipSuccess) return GFO_EHIP;
+      if (st->delay > 0 && ++st->pending_calls >= st->delay) {
+        if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;
+        st->pending_calls = 0;
+      }
+    }
+    return GFO_OK;
+  }
+  for (int t = 0; t < n_steps; ++t) {
+    // a full term buffer is flushed after the previous move's elementwise part
+    // (which sets the term count) and before this move's gather
+    const bool flush = st->pending_calls >= st->delay;
+    gfo_pick* pk = d_picks ? d_picks + t : internal;
+    const hipError_t e =
+        g.dtype == GFO_C64
+            ? launch_fused_move<float2>(g, st, L, t > 0, mask, tau, pk, flush, stream)
+            : launch_fused_move<double2>(g, st, L, t > 0, mask, tau, pk, flush, stream);
+    if (e != hipSuccess) return GFO_EHIP;
+    if (flush) st->pending_calls = 0;
+    ++st->pending_calls;
+  }
+  const hipError_t e = g.dtype == GFO_C64 ? launch_fused_finish<float2>(g, st, L, stream)
+                                          : launch_fused_finish<double2>(g, st, L, stream);
+  if (e != hipSuccess) return GFO_EHIP;
+  if (st->pending_calls >= st->delay) {
+    if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;
+    st->pending_calls = 0;
+  }
   return GFO_OK;
 }
 

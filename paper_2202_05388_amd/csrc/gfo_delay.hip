@@ -10,28 +10,29 @@
 
 namespace gfo {
 
-// Pending terms are stored twice: element-major, CU[r * D + s] and V[q * D + s]
-// (D = GFO_MAX_DELAY; the terms of one element are contiguous, which the
-// per-step gathers read), and slot-major, CUs[s * R + r] and Vs[s * ld + q]
-// (consecutive elements of one term are contiguous, which the flush reads
-// coalesced across lanes).
-constexpr int D = GFO_MAX_DELAY;
+// Pending terms are stored slot-major, CUs[s * R + r] and Vs[s * ld + q]: the
+// consecutive elements of one term are contiguous, which both the per-move
+// gathers (one element per lane, all terms of it) and the flush read coalesced.
 
-// The move's scalars, computed by every thread from values no thread of this
-// launch writes (pick, eps_idx[j], diag64[j], E[j], the term count).
+// x + a b in FP64, rounded to the storage type: the E, monitor-row and (via
+// emon) monitor-field updates of every path go through this one expression.
 template <typename T>
-__device__ __forceinline__ Snap deferred_snapshot(const Geo& g, const gfo_pick* __restrict__ pick,
-                                                  const T* __restrict__ E,
-                                                  const double2* __restrict__ diag64,
-                                                  const uint8_t* __restrict__ eps_idx,
-                                                  const int32_t* __restrict__ count) {
+__device__ __forceinline__ T axpy_st(T x, T a, double2 b) {
+  return St<T>::from_d(cadd(St<T>::to_d(x), cmul(St<T>::to_d(a), b)));
+}
+
+// The move's scalars, from the pick and the values at its pixel that no thread
+// of this launch writes (eps_idx[j], diag64[j], E[j], the term count); cur, dj
+// and Ej are read at jc, the pick's pixel clamped into range.
+template <typename T>
+__device__ __forceinline__ Snap deferred_snapshot(const Geo& g, const gfo_pick pk, int cur,
+                                                  double2 dj, T Ej, int cnt) {
   Snap s = {};
   s.j = -1;
-  const int j = pick->pixel, e = pick->eps_idx;
-  if (j >= 0 && j < g.N && e >= 0 && e < g.n_eps && e != (int)eps_idx[j]) {
-    const double a = g.k0sq * (g.eps[e] - g.eps[eps_idx[j]]);
-    const double2 d = diag64[j];
-    const double2 den = make_double2(1.0 - a * d.x, -a * d.y);
+  const int j = pk.pixel, e = pk.eps_idx;
+  if (j >= 0 && j < g.N && e >= 0 && e < g.n_eps && e != cur) {
+    const double a = g.k0sq * (g.eps[e] - g.eps[cur]);
+    const double2 den = make_double2(1.0 - a * dj.x, -a * dj.y);
     if (cabs2(den) < 1e-24) {
       s.pad1 = 1;                           // singular: refused, flagged by the next kernel
     } else {
@@ -39,117 +40,310 @@ __device__ __forceinline__ Snap deferred_snapshot(const Geo& g, const gfo_pick* 
       s.e_new = e;
       s.alpha = a;
       s.c = rdiv(a, den);
-      s.Ej = St<T>::to_d(E[j]);
-      s.dj = d;
-      s.slot = *count;
+      s.Ej = St<T>::to_d(Ej);
+      s.dj = dj;
+      s.slot = cnt;
     }
   }
   return s;
 }
 
 // Threads [0, R): u_r = G_t[r, j] (base + pending for design rows; monitor rows
-// are current); cu_r = c u_r is stored as term `slot` (both layouts) and in `cu`.
+// are current); cu_r = c u_r is stored as term `slot` and in `cu`; the monitor
+// rows also give E at the monitors after the move, emon[m] = E[N+m] + cu[N+m] E_j.
 // Threads [R, R + ld): v_q = G_t[j, q] (q < N, 0 beyond), stored likewise and in
-// `v`.  Workgroup 0 publishes the snapshot for the next kernel.  This kernel
-// writes nothing that it reads.
+// `v`.  Workgroup 0 publishes the snapshot for the next kernel.  Nothing written
+// here is read by this launch.
+//
+// Two phases, so that the loads that do not depend on the pick can be in flight
+// while it is taken: gather_prefetch reads the term count and this thread's
+// operands of the first kGatherBatch pending terms (CU[s][i] for a column thread,
+// V[s][q] for a row thread); gather_finish issues every load that depends on the
+// pick at once (the pixel's scalars, the base entry, the other operand of each
+// term), then sums the terms in slot order from zero and adds the base entry.
+constexpr int kGatherBatch = 16;
+
 template <typename T>
-__global__ void k_gather_dl(Geo g, const gfo_pick* __restrict__ pick, const T* __restrict__ G,
-                            const T* __restrict__ E, const double2* __restrict__ diag64,
-                            const uint8_t* __restrict__ eps_idx, const int32_t* __restrict__ count,
-                            Snap* __restrict__ snap_out, T* __restrict__ CU, T* __restrict__ V,
-                            T* __restrict__ CUs, T* __restrict__ Vs, T* __restrict__ cu_out,
-                            T* __restrict__ v_out) {
-  const Snap sn = deferred_snapshot<T>(g, pick, E, diag64, eps_idx, count);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *snap_out = sn;
-  const int j = sn.j;
-  if (j < 0) return;
-  const int slot = sn.slot;
+struct GatherPre {
+  int cnt;                    // pending terms = this move's slot
+  T a[kGatherBatch];          // this thread's operands of terms 0 .. kGatherBatch-1
+};
+
+template <typename T>
+__device__ __forceinline__ void gather_prefetch(const Geo& g, const int32_t* __restrict__ count,
+                                                const T* __restrict__ CUs,
+                                                const T* __restrict__ Vs, GatherPre<T>& pre) {
+  pre.cnt = __builtin_amdgcn_readfirstlane(*count);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < g.R) {
-    const int64_t i = t;
-    double2 u;
-    if (i == j) {
-      u = sn.dj;
-    } else {
-      u = St<T>::to_d(G[i * g.ld + j]);
-      if (i < g.N) {
-        const T* __restrict__ cr = CU + i * D;
-        const T* __restrict__ vj = V + (int64_t)j * D;
-#pragma unroll 8
-        for (int s = 0; s < slot; ++s) u = cadd(u, cmul(St<T>::to_d(cr[s]), St<T>::to_d(vj[s])));
+  const bool col = t < g.R;
+  const int64_t i = col ? t : 0, q = col ? 0 : (t - g.R < g.ld ? t - g.R : g.ld - 1);
+#pragma unroll
+  for (int k = 0; k < kGatherBatch; ++k)
+    if (k < pre.cnt) pre.a[k] = col ? CUs[(int64_t)k * g.R + i] : Vs[(int64_t)k * g.ld + q];
+}
+
+template <typename T>
+__device__ __forceinline__ void gather_finish(const Geo& g, const gfo_pick pk,
+                                              const GatherPre<T>& pre, const T* __restrict__ G,
+                                              const T* __restrict__ E,
+                                              const double2* __restrict__ diag64,
+                                              const uint8_t* __restrict__ eps_idx,
+                                              Snap* __restrict__ snap_out, T* __restrict__ CUs,
+                                              T* __restrict__ Vs, T* __restrict__ cu_out,
+                                              T* __restrict__ v_out, T* __restrict__ emon) {
+  const int cnt = pre.cnt;
+  const int jc = pk.pixel >= 0 && pk.pixel < g.N ? pk.pixel : 0;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool col = t < g.R;
+  const int64_t i = col ? t : 0, q = col ? 0 : (t - g.R < g.ld ? t - g.R : g.ld - 1);
+  // every load that depends on the pick, issued together
+  const int cur = eps_idx[jc];
+  const double2 dj = diag64[jc];
+  const T Ej = E[jc];
+  const T base = col ? G[i * g.ld + jc] : G[(int64_t)jc * g.ld + q];
+  T b[kGatherBatch];
+#pragma unroll
+  for (int k = 0; k < kGatherBatch; ++k)
+    if (k < cnt) b[k] = col ? Vs[(int64_t)k * g.ld + jc] : CUs[(int64_t)k * g.R + jc];
+  const Snap sn = deferred_snapshot<T>(g, pk, cur, dj, Ej, cnt);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *snap_out = sn;
+  const int j = __builtin_amdgcn_readfirstlane(sn.j);
+  if (j < 0 || t >= g.R + g.ld) return;
+  const int slot = cnt;
+  // the terms of a design entry (column i < N, or row entry q < N, not the pivot)
+  const bool terms = col ? (i < g.N && i != j) : (q < g.N && q != j);
+  double2 acc = make_double2(0.0, 0.0);
+  if (terms) {
+#pragma unroll
+    for (int k = 0; k < kGatherBatch; ++k)
+      if (k < slot) acc = cadd(acc, cmul(St<T>::to_d(col ? pre.a[k] : b[k]),
+                                         St<T>::to_d(col ? b[k] : pre.a[k])));
+    for (int s0 = kGatherBatch; s0 < slot; s0 += kGatherBatch) {
+      T x[kGatherBatch], y[kGatherBatch];
+#pragma unroll
+      for (int k = 0; k < kGatherBatch; ++k) {
+        if (s0 + k < slot) {
+          x[k] = CUs[(int64_t)(s0 + k) * g.R + (col ? i : j)];
+          y[k] = Vs[(int64_t)(s0 + k) * g.ld + (col ? j : q)];
+        }
       }
+#pragma unroll
+      for (int k = 0; k < kGatherBatch; ++k)
+        if (s0 + k < slot) acc = cadd(acc, cmul(St<T>::to_d(x[k]), St<T>::to_d(y[k])));
     }
+  }
+  if (col) {
+    double2 u;
+    if (i == j) u = sn.dj;
+    else if (i < g.N) u = cadd(St<T>::to_d(base), acc);
+    else u = St<T>::to_d(base);                   // monitor rows: current, no pending terms
     const T cu = St<T>::from_d(cmul(sn.c, u));
-    CU[i * D + slot] = cu;
     CUs[(int64_t)slot * g.R + i] = cu;
     cu_out[i] = cu;
-  } else if (t < g.R + g.ld) {
-    const int64_t q = t - g.R;
+    if (i >= g.N) emon[i - g.N] = axpy_st<T>(E[i], cu, sn.Ej);
+  } else {
+    const int64_t qq = t - g.R;
     double2 v = make_double2(0.0, 0.0);
-    if (q < g.N) {
-      if (q == j) {
-        v = sn.dj;
-      } else {
-        v = St<T>::to_d(G[(int64_t)j * g.ld + q]);
-        const T* __restrict__ cj = CU + (int64_t)j * D;
-        const T* __restrict__ vq = V + q * D;
-#pragma unroll 8
-        for (int s = 0; s < slot; ++s) v = cadd(v, cmul(St<T>::to_d(cj[s]), St<T>::to_d(vq[s])));
-      }
-    }
+    if (qq < g.N) v = qq == j ? sn.dj : cadd(St<T>::to_d(base), acc);
     const T vv = St<T>::from_d(v);
-    V[q * D + slot] = vv;
-    Vs[(int64_t)slot * g.ld + q] = vv;
-    v_out[q] = vv;
+    Vs[(int64_t)slot * g.ld + qq] = vv;
+    v_out[qq] = vv;
   }
 }
 
-// Applies the move's O(R) and O(N) parts: E_r += cu_r E_j for every row, the
-// monitor rows G[N+m, q] += cu[N+m] v[q], diag64[q] += cu[q] v[q] (q != j),
-// diag64[j] = d_j / (1 - alpha d_j); then records the move (eps_idx, history,
-// move counter, term count).  Grid x covers max(R, ld); y walks the monitors.
 template <typename T>
-__global__ void k_mon_dl(Geo g, const Snap* __restrict__ snap, const T* __restrict__ cu,
-                         const T* __restrict__ v, T* __restrict__ G, T* __restrict__ E,
-                         double2* __restrict__ diag64, uint8_t* __restrict__ eps_idx,
-                         int32_t* __restrict__ flips, int flip_cap, int32_t* __restrict__ n_flips,
-                         int32_t* __restrict__ status, int32_t* __restrict__ count) {
-  const int j = snap->j;
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < 0) {
-    if (q == 0 && blockIdx.y == 0 && snap->pad1) atomicOr(status, GFO_STATUS_SINGULAR);
-    return;
-  }
-  if (blockIdx.y == 0) {
-    if (q < g.R) E[q] = St<T>::from_d(cadd(St<T>::to_d(E[q]), cmul(St<T>::to_d(cu[q]), snap->Ej)));
+__global__ __launch_bounds__(256) void k_gather_dl(
+    Geo g, const gfo_pick* __restrict__ pick, const T* __restrict__ G, const T* __restrict__ E,
+    const double2* __restrict__ diag64, const uint8_t* __restrict__ eps_idx,
+    const int32_t* __restrict__ count, Snap* __restrict__ snap_out, T* __restrict__ CUs,
+    T* __restrict__ Vs, T* __restrict__ cu_out, T* __restrict__ v_out, T* __restrict__ emon) {
+  GatherPre<T> pre;
+  gather_prefetch<T>(g, count, CUs, Vs, pre);
+  gather_finish<T>(g, *pick, pre, G, E, diag64, eps_idx, snap_out, CUs, Vs, cu_out, v_out, emon);
+}
+
+// Fused pick + gather: every workgroup takes the greedy pick from the score
+// summaries (identical in all of them: the same reads, exact max and min
+// reductions) while its pick-independent gather loads are in flight; workgroup
+// 0 records the pick in `pick_out`.
+template <typename T>
+__global__ __launch_bounds__(256) void k_select_gather(
+    Geo g, const double* __restrict__ scores, const double* __restrict__ partial,
+    const int* __restrict__ pfirst, int nblk, double tau, gfo_pick* __restrict__ pick_out,
+    const T* __restrict__ G, const T* __restrict__ E, const double2* __restrict__ diag64,
+    const uint8_t* __restrict__ eps_idx, const int32_t* __restrict__ count,
+    Snap* __restrict__ snap_out, T* __restrict__ CUs, T* __restrict__ Vs, T* __restrict__ cu_out,
+    T* __restrict__ v_out, T* __restrict__ emon) {
+  __shared__ double shd[4];
+  __shared__ int shi[4];
+  GatherPre<T> pre;
+  gather_prefetch<T>(g, count, CUs, Vs, pre);
+  const double fom = cabs2(St<T>::to_d(E[g.N + g.m0]));
+  const gfo_pick pk = greedy_pick_block(g, fom, scores, partial, pfirst, nblk, tau, shd, shi);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *pick_out = pk;
+  gather_finish<T>(g, pk, pre, G, E, diag64, eps_idx, snap_out, CUs, Vs, cu_out, v_out, emon);
+}
+
+// The move's elementwise part for one index q (design pixel or monitor row):
+// E_q += cu_q E_j (the monitor fields are taken from emon, computed by the
+// gather with the same expression), diag64 (q != j: += cu_q v_q; q = j:
+// d_j / (1 - alpha d_j)) and eps_idx[j]; the monitor rows G[N+m, q] +=
+// cu[N+m] v_q.  Shared by the per-call path and the fused greedy loop.
+template <typename T>
+__device__ __forceinline__ void elementwise_move(const Geo& g, const Snap& sn, int64_t q,
+                                                 const T* __restrict__ cu,
+                                                 const T* __restrict__ v,
+                                                 const T* __restrict__ emon, T* __restrict__ G,
+                                                 T* __restrict__ E, double2* __restrict__ diag64,
+                                                 uint8_t* __restrict__ eps_idx, int m_begin,
+                                                 int m_step) {
+  const int j = sn.j;
+  if (m_begin == 0) {
     if (q < g.N) {
+      E[q] = axpy_st<T>(E[q], cu[q], sn.Ej);
       if (q == j) {
-        const double2 d = snap->dj;
-        diag64[j] = cmul(d, rdiv(1.0, make_double2(1.0 - snap->alpha * d.x, -snap->alpha * d.y)));
+        const double2 d = sn.dj;
+        diag64[j] = cmul(d, rdiv(1.0, make_double2(1.0 - sn.alpha * d.x, -sn.alpha * d.y)));
+        eps_idx[j] = (uint8_t)sn.e_new;
       } else {
         diag64[q] = cadd(diag64[q], cmul(St<T>::to_d(cu[q]), St<T>::to_d(v[q])));
       }
-    }
-    if (q == 0) {
-      eps_idx[j] = (uint8_t)snap->e_new;
-      const int n = *n_flips;
-      if (n < flip_cap) {
-        flips[2 * n] = j;
-        flips[2 * n + 1] = snap->e_new;
-      } else {
-        atomicOr(status, GFO_STATUS_HISTORY_FULL);
-      }
-      *n_flips = n + 1;
-      *count = snap->slot + 1;
+    } else if (q < g.R) {
+      E[q] = emon[q - g.N];
     }
   }
   if (q >= g.ld) return;
   const double2 vq = St<T>::to_d(v[q]);
-  for (int m = blockIdx.y; m < g.nmon; m += gridDim.y) {
-    const int64_t r = g.N + m;
-    T* p = G + r * g.ld + q;
-    *p = St<T>::from_d(cadd(St<T>::to_d(*p), cmul(St<T>::to_d(cu[r]), vq)));
+  for (int m = m_begin; m < g.nmon; m += m_step) {
+    T* p = G + (int64_t)(g.N + m) * g.ld + q;
+    *p = axpy_st<T>(*p, cu[g.N + m], vq);
   }
+}
+
+// Bookkeeping of an applied move (history, move counter, pending-term count).
+__device__ __forceinline__ void record_move(const Snap& sn, int32_t* __restrict__ flips,
+                                            int flip_cap, int32_t* __restrict__ n_flips,
+                                            int32_t* __restrict__ status,
+                                            int32_t* __restrict__ count) {
+  const int n = *n_flips;
+  if (n < flip_cap) {
+    flips[2 * n] = sn.j;
+    flips[2 * n + 1] = sn.e_new;
+  } else {
+    atomicOr(status, GFO_STATUS_HISTORY_FULL);
+  }
+  *n_flips = n + 1;
+  *count = sn.slot + 1;
+}
+
+// Applies the move's elementwise part.  Grid x covers max(R, ld); y walks the
+// monitor rows.
+template <typename T>
+__global__ void k_mon_dl(Geo g, const Snap* __restrict__ snap, const T* __restrict__ cu,
+                         const T* __restrict__ v, const T* __restrict__ emon, T* __restrict__ G,
+                         T* __restrict__ E, double2* __restrict__ diag64,
+                         uint8_t* __restrict__ eps_idx, int32_t* __restrict__ flips, int flip_cap,
+                         int32_t* __restrict__ n_flips, int32_t* __restrict__ status,
+                         int32_t* __restrict__ count) {
+  const Snap sn = *snap;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sn.j < 0) {
+    if (q == 0 && blockIdx.y == 0 && sn.pad1) atomicOr(status, GFO_STATUS_SINGULAR);
+    return;
+  }
+  if (q == 0 && blockIdx.y == 0) record_move(sn, flips, flip_cap, n_flips, status, count);
+  elementwise_move<T>(g, sn, q, cu, v, emon, G, E, diag64, eps_idx, blockIdx.y, gridDim.y);
+}
+
+// Monitor rows other than m0 handled by one workgroup row of k_mon_score.
+constexpr int kMonRowsPerBlock = 16;
+
+// Fused greedy loop, first kernel of a move.  Grid x covers max(R, ld) indices q;
+// grid y = 1 + ceil((nmon - 1) / kMonRowsPerBlock).
+//   y = 0: the previous move's elementwise part for index q (if apply_prev) and
+//     then the scores of pixel q (workgroup b covers pixels [256 b, 256 b + 256)
+//     and writes partial[b] for b < nblk).  Thread q updates exactly the values
+//     it then scores with (E_q, diag64[q], eps_idx[q], G[N+m0, q]) and scores
+//     from registers; E at the FOM monitor comes from emon.
+//   y > 0: the update of a group of the other monitor rows, column q.
+// The expressions are those of k_mon_dl and k_score, so the state and the scores
+// are bit for bit those of the per-call path.
+template <typename T>
+__global__ __launch_bounds__(kScoreThreads) void k_mon_score(
+    Geo g, int apply_prev, const Snap* __restrict__ snap, const T* __restrict__ cu,
+    const T* __restrict__ v, const T* __restrict__ emon, T* __restrict__ G, T* __restrict__ E,
+    double2* __restrict__ diag64, uint8_t* __restrict__ eps_idx, int32_t* __restrict__ flips,
+    int flip_cap, int32_t* __restrict__ n_flips, int32_t* __restrict__ status,
+    int32_t* __restrict__ count, uint32_t mask, double tau, double* __restrict__ scores,
+    double* __restrict__ partial, int* __restrict__ pfirst, int nblk) {
+  __shared__ double sh[kScoreThreads / 64];
+  __shared__ int shi[kScoreThreads / 64];
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  Snap sn;
+  sn.j = -1;
+  if (apply_prev) sn = *snap;
+  const bool moved = sn.j >= 0;
+  if (blockIdx.y > 0) {
+    // rows m != m0, group blockIdx.y - 1: all loads, then all stores
+    if (!moved || q >= g.ld) return;
+    const int r0 = ((int)blockIdx.y - 1) * kMonRowsPerBlock;
+    T x[kMonRowsPerBlock], c[kMonRowsPerBlock];
+#pragma unroll
+    for (int k = 0; k < kMonRowsPerBlock; ++k) {
+      const int r = r0 + k, m = r < g.m0 ? r : r + 1;
+      if (m < g.nmon) {
+        x[k] = G[(int64_t)(g.N + m) * g.ld + q];
+        c[k] = cu[g.N + m];
+      }
+    }
+    const double2 vd = St<T>::to_d(v[q]);
+#pragma unroll
+    for (int k = 0; k < kMonRowsPerBlock; ++k) {
+      const int r = r0 + k, m = r < g.m0 ? r : r + 1;
+      if (m < g.nmon) G[(int64_t)(g.N + m) * g.ld + q] = axpy_st<T>(x[k], c[k], vd);
+    }
+    return;
+  }
+  if (!moved && apply_prev && q == 0 && sn.pad1) atomicOr(status, GFO_STATUS_SINGULAR);
+  if (moved && q == 0) record_move(sn, flips, flip_cap, n_flips, status, count);
+  const double2 Em0 = St<T>::to_d(moved ? emon[g.m0] : E[g.N + g.m0]);
+  // every load of this thread is issued before any store, unconditionally
+  // (indices clamped to valid elements; values past the ends are not used)
+  const int64_t qc = q < g.N ? q : g.N - 1, ql = q < g.ld ? q : g.ld - 1;
+  T Eq = E[qc];
+  double2 dq = diag64[qc];
+  int cur = eps_idx[qc];
+  const T cuq = cu[qc], vq = v[ql];
+  T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
+  T grow_q = grow[ql];
+  if (moved) {
+    grow_q = axpy_st<T>(grow_q, cu[g.N + g.m0], St<T>::to_d(vq));
+    if (q < g.ld) grow[q] = grow_q;
+  }
+  double best = -INFINITY;
+  bool bad = false;
+  double F[GFO_MAX_EPS];
+  if (q < g.N) {
+    if (moved) {
+      Eq = axpy_st<T>(Eq, cuq, sn.Ej);
+      E[q] = Eq;
+      if (q == sn.j) {
+        const double2 dd = sn.dj;
+        dq = cmul(dd, rdiv(1.0, make_double2(1.0 - sn.alpha * dd.x, -sn.alpha * dd.y)));
+        cur = sn.e_new;
+        eps_idx[q] = (uint8_t)cur;
+      } else {
+        dq = cadd(dq, cmul(St<T>::to_d(cuq), St<T>::to_d(vq)));
+      }
+      diag64[q] = dq;
+    }
+    const double2 gE = cmul(St<T>::to_d(grow_q), St<T>::to_d(Eq));
+    best = score_pixel(g, (int)q, cur, dq, gE, Em0, mask, scores, &bad, F);
+  } else if (moved && q < g.R) {
+    E[q] = emon[q - g.N];
+  }
+  score_block_end(g, best, (int)(q < g.N ? q : g.N), true, F, tau, partial, pfirst, nblk, sh, shi);
+  if (bad) atomicOr(status, GFO_STATUS_NONFINITE);
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -203,80 +397,6 @@ __global__ __launch_bounds__(256) void k_flush_c64(int M, int R, int64_t ld,
     const int row = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
     if (row < M) G[(int64_t)row * ld + n] = make_float2(accr[e], acci[e]);
   }
-}
-
-// Same product with a 64 x 64 output tile per wave (2 x 2 instruction tiles) and
-// 128 x 128 per workgroup, so each operand load feeds 8 instructions instead of 4.
-// Workgroups are numbered XCD-aware: consecutive workgroup ids go to different
-// XCDs (round robin), so id b is given to XCD b % 8, and each XCD walks its own
-// band of row blocks; the A rows of a band then stay in that XCD's L2.
-__global__ __launch_bounds__(256) void k_flush_c64_w64(int M, int R, int64_t ld, int nbx, int nby,
-                                                       const int32_t* __restrict__ count,
-                                                       const float2* __restrict__ CU,
-                                                       const float2* __restrict__ V,
-                                                       float2* __restrict__ G) {
-  const int K = *count;
-  if (K == 0) return;
-  // XCD-aware tile order
-  const int nxcd = 8;
-  const int b = blockIdx.x;
-  const int xcd = b % nxcd, local = b / nxcd;
-  const int per = (nbx * nby + nxcd - 1) / nxcd;          // workgroups per XCD
-  const int t = xcd * per + local;                        // position in row-major tile order
-  if (t >= nbx * nby) return;
-  const int by = t / nbx, bx = t - (t / nbx) * nbx;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = by * 128 + (w >> 1) * 64;
-  const int n0 = bx * 128 + (w & 1) * 64;
-  const int h = lane >> 5, l32 = lane & 31;
-  f32x16 accr[2][2], acci[2][2];
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj) {
-      const int n = n0 + 32 * tj + l32;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = m0 + 32 * ti + 8 * (e >> 2) + 4 * h + (e & 3);
-        const float2 gv = (row < M && n < ld) ? G[(int64_t)row * ld + n] : make_float2(0.f, 0.f);
-        accr[ti][tj][e] = gv.x;
-        acci[ti][tj][e] = gv.y;
-      }
-    }
-  for (int k0 = 0; k0 < K; k0 += 2) {
-    const int kk = k0 + h;
-    float2 a[2], bb[2];
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti) {
-      const int am = m0 + 32 * ti + l32;
-      a[ti] = (kk < K && am < M) ? CU[(int64_t)kk * R + am] : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj) {
-      const int n = n0 + 32 * tj + l32;
-      bb[tj] = (kk < K && n < ld) ? V[(int64_t)kk * ld + n] : make_float2(0.f, 0.f);
-    }
-#pragma unroll
-    for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-      for (int tj = 0; tj < 2; ++tj) {
-        accr[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ti].x, bb[tj].x, accr[ti][tj], 0, 0, 0);
-        accr[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[ti].y, bb[tj].y, accr[ti][tj], 0, 0, 0);
-        acci[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ti].x, bb[tj].y, acci[ti][tj], 0, 0, 0);
-        acci[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[ti].y, bb[tj].x, acci[ti][tj], 0, 0, 0);
-      }
-  }
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj) {
-      const int n = n0 + 32 * tj + l32;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = m0 + 32 * ti + 8 * (e >> 2) + 4 * h + (e & 3);
-        if (row < M && n < ld) G[(int64_t)row * ld + n] = make_float2(accr[ti][tj][e], acci[ti][tj][e]);
-      }
-    }
 }
 
 // Variants with TM row tiles of 32 per wave (a 32*TM x 32 output tile; the TM
@@ -363,91 +483,19 @@ __global__ __launch_bounds__(256) void k_flush_c64_tm(int M, int R, int64_t ld,
   }
 }
 
-// Prefetching variant, 32 x 32 per wave and 64 x 64 per workgroup: every CU and
-// V operand of the wave (all GFO_MAX_DELAY slots, 32 instruction steps; slots
-// past the pending count contribute zero) is loaded into registers first, then
-// the wave's G tile is requested, and the products accumulate from zero while
-// the G loads are in flight; G is added in the epilogue.  Vector loads complete
-// in issue order, so the operands are ready without waiting for G.  A partial
-// flush costs as much as a full one.  Byte offsets are 32-bit: the launcher uses
-// this form only when GFO_MAX_DELAY * max(R, ld) * 8 < 2^31.  THREE_MULT as in
-// k_flush_c64_tm.
-template <bool THREE_MULT>
-__global__ __launch_bounds__(256) void k_flush_c64_pf(int M, int R, int64_t ld,
-                                                      const int32_t* __restrict__ count,
-                                                      const float2* __restrict__ CU,
-                                                      const float2* __restrict__ V,
-                                                      float2* __restrict__ G) {
-  const int K = *count;
-  if (K == 0) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
-  const int n = blockIdx.x * 64 + (w & 1) * 32 + (lane & 31);
-  const int h = lane >> 5;
-  const int am = m0 + (lane & 31);
-  constexpr int P = GFO_MAX_DELAY / 2;           // instruction steps (two terms each)
-  // Operands come through buffer loads whose range ends at the pending count, so
-  // the slots past it (and rows past the end, given an offset beyond the range)
-  // read as zero without a branch or a select: the first product then waits only
-  // for the operand loads, not for the G loads issued after them.
-  const __amdgpu_buffer_rsrc_t ra =
-      __builtin_amdgcn_make_buffer_rsrc((void*)CU, (short)0, K * R * 8, kBufferDword3);
-  const __amdgpu_buffer_rsrc_t rb =
-      __builtin_amdgcn_make_buffer_rsrc((void*)V, (short)0, (int)(K * ld * 8), kBufferDword3);
-  const unsigned a_off = am < M ? (unsigned)(h * R + am) * 8u : 0xFFFFFFF0u;
-  const unsigned b_off = (unsigned)(h * ld + n) * 8u;
-  float2 a[P], b[P];
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const unsigned da = am < M ? (unsigned)(2 * i) * (unsigned)R * 8u : 0u;
-    const auto va = __builtin_amdgcn_raw_buffer_load_b64(ra, a_off + da, 0, 0);
-    const auto vb = __builtin_amdgcn_raw_buffer_load_b64(rb, b_off + (unsigned)(2 * i * ld) * 8u, 0, 0);
-    const f32x2 fa = __builtin_bit_cast(f32x2, va), fb = __builtin_bit_cast(f32x2, vb);
-    a[i] = make_float2(fa[0], fa[1]);
-    b[i] = make_float2(fb[0], fb[1]);
-  }
-  // keep the issue order (operands, then G, then products): the scheduler would
-  // otherwise sink the loads next to their first use
-  __builtin_amdgcn_sched_barrier(0);
-  float2 gv[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    gv[e] = G[(int64_t)(r < M ? r : M - 1) * ld + n];
-  }
-  __builtin_amdgcn_sched_barrier(0);
-  f32x16 X, Y, Z;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) X[e] = Y[e] = Z[e] = 0.f;
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    if (THREE_MULT) {
-      X = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[i].x, X, 0, 0, 0);
-      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[i].y, Y, 0, 0, 0);
-      Z = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x + a[i].y, b[i].x + b[i].y, Z, 0, 0, 0);
-    } else {
-      X = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[i].x, X, 0, 0, 0);
-      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].x, b[i].y, Y, 0, 0, 0);
-      X = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[i].y, b[i].y, X, 0, 0, 0);
-      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i].y, b[i].x, Y, 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    if (r >= M) continue;
-    const float2 out = THREE_MULT ? make_float2(gv[e].x + (X[e] - Y[e]), gv[e].y + (Z[e] - X[e] - Y[e]))
-                                  : make_float2(gv[e].x + X[e], gv[e].y + Y[e]);
-    G[(int64_t)r * ld + n] = out;
-  }
-}
-
-// Software-pipelined form of k_flush_c64_pf: registers hold the operands of 16
-// instruction steps (half the slots); the G tile is requested after the first
-// 16, and each register is reloaded with the operands 16 steps ahead as soon as
-// its step is consumed.  Same ranged buffer loads (empty slots read as zero), and
-// the same 32-bit offset limit.
-template <bool THREE_MULT>
+// Software-pipelined flush, 32 x 32 outputs per wave and 64 x 64 per workgroup.
+// The CU and V operands come through buffer loads whose range ends at the
+// pending count, so slots past it (and rows past the end, given an offset
+// beyond the range) read as zero without a branch or a select.  Registers hold
+// the operands of H instruction steps (a ring); the wave's G tile is requested
+// after the first H, and each ring entry is reloaded with the operands H steps
+// ahead as soon as its step is consumed.  The products accumulate from zero and
+// G is added in the epilogue: vector loads complete in issue order, so no
+// product waits for the G loads.  Every launch runs all GFO_MAX_DELAY / 2 steps
+// (a partial flush costs a full one).  Byte offsets are 32-bit: the launcher
+// uses this form only when GFO_MAX_DELAY * max(R, ld) * 8 < 2^31.  THREE_MULT
+// as in k_flush_c64_tm.
+template <bool THREE_MULT, int H>
 __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld,
                                                         const int32_t* __restrict__ count,
                                                         const float2* __restrict__ CU,
@@ -460,7 +508,8 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
   const int n = blockIdx.x * 64 + (w & 1) * 32 + (lane & 31);
   const int h = lane >> 5;
   const int am = m0 + (lane & 31);
-  constexpr int P = GFO_MAX_DELAY / 2, H = P / 2;
+  constexpr int P = GFO_MAX_DELAY / 2;
+  static_assert(P % H == 0, "ring depth divides the step count");
   const __amdgpu_buffer_rsrc_t ra =
       __builtin_amdgcn_make_buffer_rsrc((void*)CU, (short)0, K * R * 8, kBufferDword3);
   const __amdgpu_buffer_rsrc_t rb =
@@ -488,11 +537,11 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     const f32x2 ai = a[i % H], bi = b[i % H];
-    if (i < H) {
-      a[i] = __builtin_bit_cast(f32x2,
-                                __builtin_amdgcn_raw_buffer_load_b64(ra, a_off + (i + H) * a_step, 0, 0));
-      b[i] = __builtin_bit_cast(f32x2,
-                                __builtin_amdgcn_raw_buffer_load_b64(rb, b_off + (i + H) * b_step, 0, 0));
+    if (i + H < P) {
+      a[i % H] = __builtin_bit_cast(
+          f32x2, __builtin_amdgcn_raw_buffer_load_b64(ra, a_off + (i + H) * a_step, 0, 0));
+      b[i % H] = __builtin_bit_cast(
+          f32x2, __builtin_amdgcn_raw_buffer_load_b64(rb, b_off + (i + H) * b_step, 0, 0));
     }
     if (THREE_MULT) {
       X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
@@ -516,10 +565,13 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
   }
 }
 
-// flush variants for complex64 storage (selected by the autotuner)
-static std::atomic<int> g_flush_sel{0};
-static const char* const kFlushNames[] = {"w32", "w64_xcd", "w32x2", "w32_3m", "w32x2_3m", "w32_pf", "w32_pf_3m", "w32_pipe", "w32_pipe_3m"};
+// flush variants for complex64 storage (selected by the autotuner; all give the
+// eager results to FP32 rounding, tests/test_gpu_deferred.py)
+static const char* const kFlushNames[] = {"w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8",
+                                          "w32_pipe8_3m"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
+constexpr int kFlushDefault = 4;
+static std::atomic<int> g_flush_sel{kFlushDefault};
 int flush_variant_count() { return kFlushCount; }
 const char* flush_variant_name(int i) { return i >= 0 && i < kFlushCount ? kFlushNames[i] : nullptr; }
 int flush_set_variant(int i) {
@@ -546,18 +598,68 @@ hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, c
   int32_t* count = (int32_t*)(w + L.dl_hdr);
   T* cu = (T*)(w + L.cu);
   T* v = (T*)(w + L.v);
+  T* emon = (T*)(w + L.emon);
   const int64_t n = (int64_t)g.R + g.ld;
   hipLaunchKernelGGL(k_gather_dl<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, pick,
                      (const T*)st->G, (const T*)st->E, (const double2*)st->diag64,
-                     (const uint8_t*)st->eps_idx, (const int32_t*)count, snap, (T*)(w + L.dl_CU),
-                     (T*)(w + L.dl_V), (T*)(w + L.dl_CUs), (T*)(w + L.dl_Vs), cu, v);
+                     (const uint8_t*)st->eps_idx, (const int32_t*)count, snap, (T*)(w + L.dl_CUs),
+                     (T*)(w + L.dl_Vs), cu, v, emon);
+  return launch_fused_finish<T>(g, st, L, s);
+}
+
+template <typename T>
+hipError_t launch_fused_finish(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {
+  char* w = (char*)st->work;
   const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
   dim3 gm((unsigned)((nx + 255) / 256), (unsigned)(g.nmon < 65535 ? g.nmon : 65535));
-  hipLaunchKernelGGL(k_mon_dl<T>, gm, dim3(256), 0, s, g, (const Snap*)snap, (const T*)cu,
-                     (const T*)v, (T*)st->G, (T*)st->E, (double2*)st->diag64, st->eps_idx, st->flips,
-                     st->flip_cap, st->n_flips, st->status, count);
+  hipLaunchKernelGGL(k_mon_dl<T>, gm, dim3(256), 0, s, g, (const Snap*)(w + L.snap),
+                     (const T*)(w + L.cu), (const T*)(w + L.v), (const T*)(w + L.emon), (T*)st->G,
+                     (T*)st->E, (double2*)st->diag64, st->eps_idx, st->flips, st->flip_cap,
+                     st->n_flips, st->status, (int32_t*)(w + L.dl_hdr));
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_fused_move(const Geo& g, gfo_state* st, const Layout& L, int apply_prev,
+                             uint32_t mask, double tau, gfo_pick* pick_out, bool flush_between,
+                             hipStream_t s) {
+  char* w = (char*)st->work;
+  Snap* snap = (Snap*)(w + L.snap);
+  int32_t* count = (int32_t*)(w + L.dl_hdr);
+  T* cu = (T*)(w + L.cu);
+  T* v = (T*)(w + L.v);
+  T* emon = (T*)(w + L.emon);
+  double* scores = (double*)(w + L.scores);
+  double* partial = (double*)(w + L.partial);
+  int* pfirst = (int*)(w + L.pfirst);
+  const int nblk = (g.N + kScoreThreads - 1) / kScoreThreads;
+  const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
+  const unsigned gy = 1 + (unsigned)((g.nmon - 1 + kMonRowsPerBlock - 1) / kMonRowsPerBlock);
+  hipLaunchKernelGGL(k_mon_score<T>, dim3((unsigned)((nx + kScoreThreads - 1) / kScoreThreads), gy),
+                     dim3(kScoreThreads), 0, s, g, apply_prev, (const Snap*)snap, (const T*)cu,
+                     (const T*)v, (const T*)emon, (T*)st->G, (T*)st->E, (double2*)st->diag64,
+                     st->eps_idx, st->flips, st->flip_cap, st->n_flips, st->status, count, mask,
+                     tau, scores, partial, pfirst, nblk);
+  if (flush_between) {
+    const hipError_t e = launch_flush(g, st, L, s);
+    if (e != hipSuccess) return e;
+  }
+  const int64_t n = (int64_t)g.R + g.ld;
+  hipLaunchKernelGGL(k_select_gather<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g,
+                     (const double*)scores, (const double*)partial, (const int*)pfirst, nblk, tau,
+                     pick_out,
+                     (const T*)st->G, (const T*)st->E, (const double2*)st->diag64,
+                     (const uint8_t*)st->eps_idx, (const int32_t*)count, snap, (T*)(w + L.dl_CUs),
+                     (T*)(w + L.dl_Vs), cu, v, emon);
+  return hipGetLastError();
+}
+template hipError_t launch_fused_move<float2>(const Geo&, gfo_state*, const Layout&, int, uint32_t,
+                                              double, gfo_pick*, bool, hipStream_t);
+template hipError_t launch_fused_move<double2>(const Geo&, gfo_state*, const Layout&, int, uint32_t,
+                                               double, gfo_pick*, bool, hipStream_t);
+template hipError_t launch_fused_finish<float2>(const Geo&, gfo_state*, const Layout&, hipStream_t);
+template hipError_t launch_fused_finish<double2>(const Geo&, gfo_state*, const Layout&, hipStream_t);
+
 template hipError_t launch_apply_deferred<float2>(const Geo&, gfo_state*, const Layout&,
                                                   const gfo_pick*, hipStream_t);
 template hipError_t launch_apply_deferred<double2>(const Geo&, gfo_state*, const Layout&,
@@ -571,45 +673,33 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
   hipError_t e;
   if (g.dtype == GFO_C64) {
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
-    const int fv = flush_get_variant();
+    int fv = flush_get_variant();
+    // the pipelined forms address the term buffers with 32-bit byte offsets
+    const bool off32 = (int64_t)GFO_MAX_DELAY * (g.ld > g.R ? g.ld : g.R) * 8 < ((int64_t)1 << 31);
+    if (fv >= 2 && !off32) fv = 1;
     const float2* cu = (const float2*)(w + L.dl_CUs);
     const float2* vv = (const float2*)(w + L.dl_Vs);
-    const dim3 g1((unsigned)(g.ld / 64), (unsigned)((g.N + 63) / 64));
-    const dim3 g2((unsigned)(g.ld / 64), (unsigned)((g.N + 127) / 128));
-    if (fv == 2) {
-      hipLaunchKernelGGL((k_flush_c64_tm<2, false>), g2, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
-                         (float2*)st->G);
-    } else if (fv == 3) {
-      hipLaunchKernelGGL((k_flush_c64_tm<1, true>), g1, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
-                         (float2*)st->G);
-    } else if (fv == 4) {
-      hipLaunchKernelGGL((k_flush_c64_tm<2, true>), g2, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
-                         (float2*)st->G);
-    } else if (fv >= 5 && fv <= 8 &&
-               (int64_t)GFO_MAX_DELAY * (g.ld > g.R ? g.ld : g.R) * 8 >= ((int64_t)1 << 31)) {
-      return hipErrorInvalidValue;
-    } else if (fv == 5) {
-      hipLaunchKernelGGL((k_flush_c64_pf<false>), g1, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
-                         (float2*)st->G);
-    } else if (fv == 6) {
-      hipLaunchKernelGGL((k_flush_c64_pf<true>), g1, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
-                         (float2*)st->G);
-    } else if (fv == 7) {
-      hipLaunchKernelGGL((k_flush_c64_pipe<false>), g1, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
-                         (float2*)st->G);
-    } else if (fv == 8) {
-      hipLaunchKernelGGL((k_flush_c64_pipe<true>), g1, dim3(256), 0, s, g.N, g.R, g.ld, count, cu, vv,
-                         (float2*)st->G);
-    } else if (fv == 0) {
-      hipLaunchKernelGGL(k_flush_c64, dim3((unsigned)(g.ld / 64), (unsigned)((g.N + 63) / 64)),
-                         dim3(256), 0, s, g.N, g.R, g.ld, count, (const float2*)(w + L.dl_CUs),
-                         (const float2*)(w + L.dl_Vs), (float2*)st->G);
-    } else {
-      const int nbx = (int)((g.ld + 127) / 128), nby = (g.N + 127) / 128;
-      const int per = (nbx * nby + 7) / 8;
-      hipLaunchKernelGGL(k_flush_c64_w64, dim3((unsigned)(per * 8)), dim3(256), 0, s, g.N, g.R, g.ld,
-                         nbx, nby, count, (const float2*)(w + L.dl_CUs), (const float2*)(w + L.dl_Vs),
-                         (float2*)st->G);
+    float2* G = (float2*)st->G;
+    const dim3 grid((unsigned)(g.ld / 64), (unsigned)((g.N + 63) / 64)), blk(256);
+    switch (fv) {
+      case 0:
+        hipLaunchKernelGGL(k_flush_c64, grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G);
+        break;
+      case 1:
+        hipLaunchKernelGGL((k_flush_c64_tm<1, true>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G);
+        break;
+      case 2:
+        hipLaunchKernelGGL((k_flush_c64_pipe<true, 16>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv,
+                           G);
+        break;
+      case 3:
+        hipLaunchKernelGGL((k_flush_c64_pipe<false, 8>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv,
+                           G);
+        break;
+      default:
+        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv,
+                           G);
+        break;
     }
     e = hipGetLastError();
   } else {

@@ -44,6 +44,39 @@ template <> struct St<double2> {
   __device__ __forceinline__ static double2 from_d(double2 v) { return v; }
 };
 
+// ------------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// block-wide max; all threads get the result. `sh` holds blockDim/64 doubles.
+__device__ inline double block_max(double v, double* sh) {
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_max(v);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = -INFINITY;
+  for (int i = 0; i < nw; ++i) r = fmax(r, sh[i]);
+  return r;
+}
+__device__ inline int block_min(int v, int* sh) {
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_min(v);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  int r = 0x7fffffff;
+  for (int i = 0; i < nw; ++i) r = min(r, sh[i]);
+  return r;
+}
+
 // Snapshot of the accepted move, written before G is modified.
 struct Snap {
   int32_t j;          // pixel, -1 = no move
@@ -66,11 +99,13 @@ struct Layout {
   size_t table;     // ny*nx double2: G0 over non-negative pixel offsets
   size_t mon_xy;    // 2*nmon double
   size_t scores;    // N*n_eps double
-  size_t partial;   // kScoreMaxBlocks double
+  size_t partial;   // kScoreMaxBlocks double: best score of each score workgroup
+  size_t pfirst;    // kScoreMaxBlocks int32: lowest index within the tie band of that best
   size_t picks;     // GFO_MAX_RANK_K gfo_pick (internal rank-k scratch)
   size_t snap;      // Snap
   size_t cu;        // R x 16 B: c * G[:, j] (storage type)
   size_t v;         // ld x 16 B: G[j, :] (storage type), zero padded to ld
+  size_t emon;      // nmon x 16 B: E at the monitors after the last gathered move
   // rank-k
   size_t rk_S;      // header of the accepted set (pixels, contrasts, M E[S])
   size_t rk_M;      // K x K double2 (FP64 Woodbury core)
@@ -81,10 +116,8 @@ struct Layout {
   size_t rk_Bbf;    // 2 x 2K x ld bf16
   // deferred rank-1 terms (GFO_MAX_DELAY slots)
   size_t dl_hdr;    // int32 count of pending terms
-  size_t dl_CU;     // R x GFO_MAX_DELAY x 16 B: c * G[:, j] of each pending move, element-major
-  size_t dl_V;      // ld x GFO_MAX_DELAY x 16 B: G[j, :] of each pending move, element-major
-  size_t dl_CUs;    // the same terms slot-major: GFO_MAX_DELAY x R x 16 B
-  size_t dl_Vs;     // slot-major: GFO_MAX_DELAY x ld x 16 B
+  size_t dl_CUs;    // GFO_MAX_DELAY x R x 16 B: c * G[:, j] of each pending move, slot-major
+  size_t dl_Vs;     // GFO_MAX_DELAY x ld x 16 B: G[j, :] of each pending move, slot-major
   // refresh
   // (kp = kmax rounded up to a multiple of 4)
   size_t rf_V;      // N + 1 int32: flipped list, then its length
@@ -95,6 +128,124 @@ struct Layout {
   size_t rf_x;      // kp double2: M Einc[V]
   size_t total;
 };
+
+// Scores of pixel p for every material (eqs. form4-form9 at the FOM monitor):
+// F = |E_m0 + c G[m0, p] E_p|^2 with c = alpha / (1 - alpha G_pp) in FP64; -inf
+// for non-candidates and the current material.  Writes them to `scores` and to
+// F[0 .. n_eps) (a register array: the loop is unrolled over GFO_MAX_EPS), returns
+// the largest and sets *bad on a non-finite one.
+__device__ inline double score_pixel(const Geo& g, int p, int cur, double2 d, double2 gE,
+                                     double2 Em0, uint32_t mask, double* __restrict__ scores,
+                                     bool* bad, double (&F)[GFO_MAX_EPS]) {
+  double best = -INFINITY;
+#pragma unroll
+  for (int e = 0; e < GFO_MAX_EPS; ++e) {
+    if (e < g.n_eps) {
+      double Fe = -INFINITY;
+      if (((mask >> e) & 1u) && e != cur) {
+        const double a = g.k0sq * (g.eps[e] - g.eps[cur]);
+        const double2 c = rdiv(a, make_double2(1.0 - a * d.x, -a * d.y));   // FP64 denominator
+        const double2 En = cadd(Em0, cmul(c, gE));
+        Fe = cabs2(En);
+        if (!isfinite(Fe)) {
+          *bad = true;
+          Fe = -INFINITY;
+        }
+        best = fmax(best, Fe);
+      }
+      F[e] = Fe;
+      scores[(int64_t)p * g.n_eps + e] = Fe;
+    }
+  }
+  return best;
+}
+
+// Relative tie band of the greedy rule: scores within tau of the best, m.
+__device__ __forceinline__ double tie_threshold(double m, double tau) { return m - tau * m; }
+
+// Lowest (pixel, material) index of pixel p whose score reaches thr, else INT_MAX.
+__device__ inline int first_at_least(const Geo& g, int p, const double (&F)[GFO_MAX_EPS],
+                                     double thr) {
+  int f = 0x7fffffff;
+#pragma unroll
+  for (int e = GFO_MAX_EPS - 1; e >= 0; --e)
+    if (e < g.n_eps && F[e] >= thr) f = p * g.n_eps + e;
+  return f;
+}
+
+// End of a score workgroup that scored one pixel per thread: partial[b] = its
+// best score, pfirst[b] = the lowest index whose score is within the tie band of
+// that best (INT_MAX if no candidate, or when has_F is false: pixels of a
+// thread not all in F).  All threads of the workgroup must call it.
+__device__ inline void score_block_end(const Geo& g, double best, int p, bool has_F,
+                                       const double (&F)[GFO_MAX_EPS], double tau,
+                                       double* __restrict__ partial, int* __restrict__ pfirst,
+                                       int nblk, double* shd, int* shi) {
+  const double bb = block_max(best, shd);
+  int f = 0x7fffffff;
+  if (has_F && p < g.N && bb > -INFINITY) f = first_at_least(g, p, F, tie_threshold(bb, tau));
+  f = block_min(f, shi);
+  if (threadIdx.x == 0 && (int)blockIdx.x < nblk) {
+    partial[blockIdx.x] = bb;
+    pfirst[blockIdx.x] = f;
+  }
+}
+
+// The greedy pick over scores written one pixel per thread by workgroups of
+// kScoreThreads (workgroup b covered pixels [b * kScoreThreads, ...) and left
+// partial[b] and pfirst[b], score_block_end): accept the best score F* only if
+// F* > fom (1 + tau); the winner is the lowest (pixel, material) index whose
+// score is within the relative band tau of F*.  It lies in the lowest workgroup
+// whose maximum reaches the band (that maximum itself qualifies); if that
+// workgroup holds F*, pfirst is the winner, otherwise (a near-tie across
+// workgroups) its scores are scanned.  Every thread of the calling workgroup
+// gets the pick.
+__device__ inline gfo_pick greedy_pick_block(const Geo& g, double fom,
+                                             const double* __restrict__ scores,
+                                             const double* __restrict__ partial,
+                                             const int* __restrict__ pfirst, int nblk, double tau,
+                                             double* shd, int* shi) {
+  gfo_pick pk;
+  pk.pixel = -1;
+  pk.eps_idx = -1;
+  pk.fom_new = fom;
+  pk.dfom = 0.0;
+  double m = -INFINITY;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) m = fmax(m, partial[i]);
+  m = block_max(m, shd);
+  if (!(m > fom * (1.0 + tau))) return pk;
+  const double thr = tie_threshold(m, tau);
+  int bq = 0x7fffffff;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+    if (partial[i] >= thr) {
+      bq = i;
+      break;
+    }
+  }
+  bq = block_min(bq, shi);
+  int first = 0x7fffffff;
+  const int pf = pfirst[bq];
+  if (partial[bq] == m && pf != 0x7fffffff) {
+    first = pf;
+  } else {
+    const int total = g.N * g.n_eps, span = kScoreThreads * g.n_eps;
+    const int lo = bq * span, hi = min(lo + span, total);
+    int f = 0x7fffffff;
+    for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      if (scores[i] >= thr) {
+        f = i;
+        break;
+      }
+    }
+    first = block_min(f, shi);
+  }
+  if (first == 0x7fffffff) return pk;
+  pk.pixel = first / g.n_eps;
+  pk.eps_idx = first - pk.pixel * g.n_eps;
+  pk.fom_new = scores[first];
+  pk.dfom = pk.fom_new - fom;
+  return pk;
+}
 
 Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax);
 Geo make_geo(const gfo_problem* p, int64_t ld);
@@ -119,6 +270,12 @@ hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, c
 hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const double2* CU,
                                    const double2* V, double2* G, hipStream_t s);
 hipError_t launch_dl_reset(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
+template <typename T>
+hipError_t launch_fused_move(const Geo& g, gfo_state* st, const Layout& L, int apply_prev,
+                             uint32_t mask, double tau, gfo_pick* pick_out, bool flush_between,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_fused_finish(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
 
 // K1 variant selection (autotuner); returns number of variants
 int k1_variant_count(int dtype);

@@ -11,74 +11,31 @@
 
 namespace gfo {
 
-// ------------------------------------------------------------------ reductions
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
-}
-// block-wide max; all threads get the result. `sh` holds blockDim/64 doubles.
-__device__ double block_max(double v, double* sh) {
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  v = wave_max(v);
-  __syncthreads();
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  double r = -INFINITY;
-  for (int i = 0; i < nw; ++i) r = fmax(r, sh[i]);
-  return r;
-}
-__device__ int block_min(int v, int* sh) {
-  int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  v = wave_min(v);
-  __syncthreads();
-  if (lane == 0) sh[w] = v;
-  __syncthreads();
-  int r = 0x7fffffff;
-  for (int i = 0; i < nw; ++i) r = min(r, sh[i]);
-  return r;
-}
-
 // ------------------------------------------------------------------ K3: scores
 // One thread per pixel (grid-stride).  Writes every (pixel, material) score,
-// -inf for non-candidates, and one block maximum per workgroup.
+// -inf for non-candidates, and per workgroup its best score and, when every
+// thread scored one pixel, the lowest index within the tie band of that best.
 template <typename T>
 __global__ __launch_bounds__(kScoreThreads) void k_score(
     Geo g, const T* __restrict__ G, const T* __restrict__ E, const double2* __restrict__ diag64,
-    const uint8_t* __restrict__ eps_idx, uint32_t mask, double* __restrict__ scores,
-    double* __restrict__ partial, int32_t* __restrict__ status) {
+    const uint8_t* __restrict__ eps_idx, uint32_t mask, double tau, double* __restrict__ scores,
+    double* __restrict__ partial, int* __restrict__ pfirst, int32_t* __restrict__ status) {
   __shared__ double sh[kScoreThreads / 64];
+  __shared__ int shi[kScoreThreads / 64];
   const double2 Em0 = St<T>::to_d(E[g.N + g.m0]);
   const T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
   double best = -INFINITY;
   bool bad = false;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < g.N; p += gridDim.x * blockDim.x) {
+  double F[GFO_MAX_EPS];
+  const int p0 = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int p = p0; p < g.N; p += gridDim.x * blockDim.x) {
     const int cur = eps_idx[p];
     const double2 d = diag64[p];
     const double2 gE = cmul(St<T>::to_d(grow[p]), St<T>::to_d(E[p]));
-    for (int e = 0; e < g.n_eps; ++e) {
-      double F = -INFINITY;
-      if (((mask >> e) & 1u) && e != cur) {
-        const double a = g.k0sq * (g.eps[e] - g.eps[cur]);
-        const double2 c = rdiv(a, make_double2(1.0 - a * d.x, -a * d.y));   // FP64 denominator
-        const double2 En = cadd(Em0, cmul(c, gE));
-        F = cabs2(En);
-        if (!isfinite(F)) {
-          bad = true;
-          F = -INFINITY;
-        }
-        best = fmax(best, F);
-      }
-      scores[(int64_t)p * g.n_eps + e] = F;
-    }
+    best = fmax(best, score_pixel(g, p, cur, d, gE, Em0, mask, scores, &bad, F));
   }
-  best = block_max(best, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = best;
+  const bool one_pixel_each = (int64_t)gridDim.x * blockDim.x >= g.N;
+  score_block_end(g, best, p0, one_pixel_each, F, tau, partial, pfirst, gridDim.x, sh, shi);
   if (bad) atomicOr(status, GFO_STATUS_NONFINITE);
 }
 
@@ -89,10 +46,17 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(
 template <typename T>
 __global__ __launch_bounds__(kSelectThreads) void k_select(
     Geo g, const T* __restrict__ E, double* __restrict__ scores, const double* __restrict__ partial,
-    int nblk, double tau, int topk, int spacing, gfo_pick* __restrict__ out) {
+    const int* __restrict__ pfirst, int nblk, double tau, int topk, int spacing,
+    gfo_pick* __restrict__ out) {
   __shared__ double shd[kSelectThreads / 64];
   __shared__ int shi[kSelectThreads / 64];
   const double fom = cabs2(St<T>::to_d(E[g.N + g.m0]));
+  if (topk == 1 && nblk * kScoreThreads >= g.N) {
+    // the greedy pick of the fused loop (one pixel per score thread)
+    const gfo_pick pk = greedy_pick_block(g, fom, scores, partial, pfirst, nblk, tau, shd, shi);
+    if (threadIdx.x == 0) out[0] = pk;
+    return;
+  }
   const int total = g.N * g.n_eps;
   const int win = spacing > 1 ? spacing - 1 : 0;
   int t = 0;
@@ -483,13 +447,14 @@ static hipError_t score_typed(const Geo& g, const gfo_state* st, const Layout& L
   if (nblk > kScoreMaxBlocks) nblk = kScoreMaxBlocks;
   hipLaunchKernelGGL(k_score<T>, dim3(nblk), dim3(kScoreThreads), 0, s, g, (const T*)st->G,
                      (const T*)st->E, (const double2*)st->diag64, (const uint8_t*)st->eps_idx, mask,
-                     (double*)(w + L.scores), (double*)(w + L.partial), st->status);
-  // the greedy pick scans only the score workgroups that reach the tie band: one
-  // wave suffices; the spaced top-k rescans every score after each pick
-  const int sel_threads = topk == 1 ? 64 : kSelectThreads;   // one wave: no cross-wave barriers
+                     tau, (double*)(w + L.scores), (double*)(w + L.partial), (int*)(w + L.pfirst),
+                     st->status);
+  // the greedy pick reads the workgroup summaries (one wave); the spaced top-k
+  // rescans every score after each pick
+  const int sel_threads = topk == 1 ? 64 : kSelectThreads;
   hipLaunchKernelGGL(k_select<T>, dim3(1), dim3(sel_threads), 0, s, g, (const T*)st->E,
-                     (double*)(w + L.scores), (const double*)(w + L.partial), nblk, tau, topk,
-                     spacing, out);
+                     (double*)(w + L.scores), (const double*)(w + L.partial),
+                     (const int*)(w + L.pfirst), nblk, tau, topk, spacing, out);
   return hipGetLastError();
 }
 

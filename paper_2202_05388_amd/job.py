@@ -26,7 +26,7 @@ class Job:
     """Device state of one greedy optimisation."""
 
     def __init__(self, problem, device="cuda", kmax: int = 0, flip_cap: int = None,
-                 dtype: str = None, delay: int = 0):
+                 dtype: str = None, delay: int = 0, ld_pad: int = 0):
         if not torch.cuda.is_available():
             raise L.GfoError("libgfo needs a GPU; torch.cuda is not available")
         L.lib()
@@ -44,10 +44,12 @@ class Job:
             h_mon_xy=self._mon.ctypes.data_as(C.POINTER(C.c_double)),
             fom_monitor=int(problem.fom_monitor), n_eps=len(self._eps),
             h_eps_table=self._eps.ctypes.data_as(C.POINTER(C.c_double)))
-        self.ld = L.min_ld(self.prob)
+        if ld_pad < 0 or ld_pad % 64:
+            raise L.GfoError("ld_pad must be a non-negative multiple of 64")
+        self.ld = L.min_ld(self.prob) + int(ld_pad)   # padding breaks power-of-two row strides
         self.kmax = int(kmax)
         self.flip_cap = int(flip_cap if flip_cap is not None else max(4 * self.N, 16))
-        work_bytes = L.workspace_size(self.prob, self.kmax)
+        work_bytes = L.workspace_size(self.prob, self.kmax, self.ld)
         dev = self.device
         self.G = torch.empty((self.R, self.ld), dtype=tdtype, device=dev)
         self.E = torch.empty((self.R,), dtype=tdtype, device=dev)
@@ -98,6 +100,14 @@ class Job:
         self.apply(stream=stream)
         self.steps_issued += 1
 
+    def greedy_steps(self, n, tau=None, cand_mask=None, out=None, stream=None):
+        """n greedy steps through gfo_greedy_steps (fused kernels in deferred
+        mode); `out`: device pointer to n pick records, or None."""
+        tau = self.problem.tau if tau is None else tau
+        mask = self.problem.cand_mask if cand_mask is None else cand_mask
+        L.greedy_steps(self.prob, self.state, n, mask, tau, out, _stream_handle(stream))
+        self.steps_issued += n
+
     # ------------------------------------------------------------------ host views
     def read_picks(self, k=1):
         raw = self.picks[: k * L.PICK_BYTES].cpu().numpy().tobytes()
@@ -119,7 +129,7 @@ class Job:
         return float(e.real**2 + e.imag**2)
 
     def scores(self):
-        off = L.scores_offset(self.prob, self.kmax)
+        off = L.scores_offset(self.prob, self.kmax, self.ld)
         n = self.N * len(self._eps)
         raw = self.work[off: off + 8 * n]
         return raw.view(torch.float64).cpu().numpy().reshape(self.N, len(self._eps))
@@ -148,13 +158,14 @@ class Job:
         raw = torch.frombuffer(bytearray(bytes(rec)), dtype=torch.uint8)
         self.picks[slot * L.PICK_BYTES:(slot + 1) * L.PICK_BYTES].copy_(raw)
 
-    def run_greedy(self, max_steps, poll_every=32, refresh_every=0, stream=None):
+    def run_greedy(self, max_steps, poll_every=32, refresh_every=0, stream=None, fused=False):
         """Greedy loop.  Steps are issued without host synchronisation; after
         each chunk of at most `poll_every` steps the accepted-move counter is
         read and the loop stops once a step found no improving move (that step
         and any later ones in its chunk are no-ops on the device).  With
         refresh_every > 0, refresh_G runs whenever the number of moves accepted
-        since init_G0 reaches a multiple of refresh_every.
+        since init_G0 reaches a multiple of refresh_every.  fused: each chunk
+        is one gfo_greedy_steps call (same moves and state).
         Returns the number of moves accepted by this call."""
         start = self.n_flips()
         acc = start
@@ -163,8 +174,11 @@ class Job:
             chunk = min(poll_every, max_steps - done)
             if refresh_every:
                 chunk = min(chunk, refresh_every - acc % refresh_every)
-            for _ in range(chunk):
-                self.step(stream)
+            if fused:
+                self.greedy_steps(chunk, stream=stream)
+            else:
+                for _ in range(chunk):
+                    self.step(stream)
             done += chunk
             now = self.n_flips()
             stopped = now - acc < chunk
@@ -176,9 +190,10 @@ class Job:
         return acc - start
 
     # ------------------------------------------------------------------ HIP graphs
-    def capture_steps(self, n: int, stream=None):
+    def capture_steps(self, n: int, stream=None, fused=False):
         """Capture n greedy steps (score + select + apply, and in deferred mode the
-        flush that ends a window of `delay` steps) into a HIP graph on `stream`.
+        flush that ends a window of `delay` steps) into a HIP graph on `stream`;
+        fused: as one gfo_greedy_steps call.
 
         Capture records launches only; nothing runs.  The window must start with
         no pending deferred terms, and n a multiple of delay in deferred mode, so
@@ -190,17 +205,20 @@ class Job:
         g = torch.cuda.CUDAGraph()
         torch.cuda.synchronize(self.device)
         with torch.cuda.graph(g, stream=s):
-            for _ in range(n):
-                self.score(stream=s)
-                self.apply(stream=s)
+            if fused:
+                self.greedy_steps(n, stream=s)
+            else:
+                for _ in range(n):
+                    self.score(stream=s)
+                    self.apply(stream=s)
         return g, s
 
-    def run_greedy_graph(self, max_steps, window=64, refresh_every=0):
+    def run_greedy_graph(self, max_steps, window=64, refresh_every=0, fused=False):
         """Greedy loop that replays a captured window of steps; polls and refreshes
         between replays.  Returns the number of moves accepted by this call."""
         if refresh_every and refresh_every % window:
             raise L.GfoError("refresh_every must be a multiple of the window")
-        g, s = self.capture_steps(window)
+        g, s = self.capture_steps(window, fused=fused)
         start = self.n_flips()
         acc = start
         done = 0

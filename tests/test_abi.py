@@ -63,6 +63,11 @@ def test_workspace_size_and_leading_dimension():
     pr2, keep2 = _problem(W.tiny(5, 7, n_mon=3))
     assert L.min_ld(pr2) == 64
     assert L.scores_offset(pr2, 0) % 256 == 0
+    # a padded leading dimension grows the workspace; invalid ones are refused
+    assert L.workspace_size(pr, 0, 16384 + 64) > small
+    out = C.c_size_t(0)
+    for bad in (16384 - 64, 16384 + 32):
+        assert L.lib().gfo_workspace_size(C.byref(pr), bad, 0, C.byref(out)) == L.GFO_EINVAL
 
 
 @pytest.mark.parametrize("field,value", [("ny", 0), ("n_mon", 0), ("dtype", 7), ("wavelength", 0.0),
@@ -71,7 +76,7 @@ def test_invalid_problem_rejected_on_host(field, value):
     pr, keep = _problem(W.tiny(4, 4))
     setattr(pr, field, value)
     out = C.c_size_t(0)
-    assert L.lib().gfo_workspace_size(C.byref(pr), 0, C.byref(out)) == L.GFO_EINVAL
+    assert L.lib().gfo_workspace_size(C.byref(pr), 0, 0, C.byref(out)) == L.GFO_EINVAL
     st = L.State()
     assert L.lib().init_G0(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
 
@@ -110,6 +115,6 @@ def test_k1_variants_listed():
         names = L.k1_variants(dt)
         assert len(names) >= 4 and len(set(names)) == len(names)
     assert L.lib().gfo_k1_set_variant(L.GFO_C64, 999) == L.GFO_EINVAL
-    assert L.flush_variants() == ["w32", "w64_xcd", "w32x2", "w32_3m", "w32x2_3m", "w32_pf",
-                                  "w32_pf_3m", "w32_pipe", "w32_pipe_3m"]
+    assert L.flush_variants() == ["w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8", "w32_pipe8_3m"]
+    assert L.flush_get_variant() == 4
     assert L.lib().gfo_strerror(L.GFO_ENOSPC) == b"workspace too small"
