@@ -495,17 +495,30 @@ __global__ __launch_bounds__(256) void k_flush_c64_tm(int M, int R, int64_t ld,
 // (a partial flush costs a full one).  Byte offsets are 32-bit: the launcher
 // uses this form only when GFO_MAX_DELAY * max(R, ld) * 8 < 2^31.  THREE_MULT
 // as in k_flush_c64_tm.
-template <bool THREE_MULT, int H>
+//
+// XCD: a one-dimensional grid numbered for the chip's eight XCDs (consecutive
+// workgroup ids go to different XCDs, id b to XCD b % 8).  XCD x takes the row
+// blocks [x * bpx, (x + 1) * bpx) and walks them column block by column block:
+// its band of CU rows stays in its own L2 and each V column block is reused
+// across the band.  nby = row blocks, bpx = ceil(nby / 8), grid = 8 * bpx * nbx.
+template <bool THREE_MULT, int H, bool XCD>
 __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld,
                                                         const int32_t* __restrict__ count,
                                                         const float2* __restrict__ CU,
                                                         const float2* __restrict__ V,
-                                                        float2* __restrict__ G) {
+                                                        float2* __restrict__ G, int nby) {
   const int K = *count;
   if (K == 0) return;
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (XCD) {
+    const int bpx = (nby + 7) / 8, xcd = (int)(blockIdx.x & 7), local = (int)(blockIdx.x >> 3);
+    bx = local / bpx;
+    by = xcd * bpx + local % bpx;
+    if (by >= nby) return;
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
-  const int n = blockIdx.x * 64 + (w & 1) * 32 + (lane & 31);
+  const int m0 = by * 64 + (w >> 1) * 32;
+  const int n = bx * 64 + (w & 1) * 32 + (lane & 31);
   const int h = lane >> 5;
   const int am = m0 + (lane & 31);
   constexpr int P = GFO_MAX_DELAY / 2;
@@ -568,7 +581,7 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
 // flush variants for complex64 storage (selected by the autotuner; all give the
 // eager results to FP32 rounding, tests/test_gpu_deferred.py)
 static const char* const kFlushNames[] = {"w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8",
-                                          "w32_pipe8_3m"};
+                                          "w32_pipe8_3m", "w32_pipe8_3m_xcd"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
 constexpr int kFlushDefault = 4;
 static std::atomic<int> g_flush_sel{kFlushDefault};
@@ -689,17 +702,23 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         hipLaunchKernelGGL((k_flush_c64_tm<1, true>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G);
         break;
       case 2:
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 16>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv,
-                           G);
+        hipLaunchKernelGGL((k_flush_c64_pipe<true, 16, false>), grid, blk, 0, s, g.N, g.R, g.ld, count,
+                           cu, vv, G, (int)grid.y);
         break;
       case 3:
-        hipLaunchKernelGGL((k_flush_c64_pipe<false, 8>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv,
-                           G);
+        hipLaunchKernelGGL((k_flush_c64_pipe<false, 8, false>), grid, blk, 0, s, g.N, g.R, g.ld, count,
+                           cu, vv, G, (int)grid.y);
         break;
-      default:
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv,
-                           G);
+      case 4:
+        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false>), grid, blk, 0, s, g.N, g.R, g.ld, count,
+                           cu, vv, G, (int)grid.y);
         break;
+      default: {
+        const unsigned nby = grid.y, bpx = (nby + 7) / 8;
+        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true>), dim3(8 * bpx * grid.x), blk, 0, s, g.N,
+                           g.R, g.ld, count, cu, vv, G, (int)nby);
+        break;
+      }
     }
     e = hipGetLastError();
   } else {

@@ -107,7 +107,9 @@ class Server:
             return
         with torch.cuda.stream(a.stream):
             for _ in range(n):
-                a.job.step(stream=a.stream)
+                # one step per call (fused kernels in deferred mode), so that every
+                # step has its own completion event
+                a.job.greedy_steps(1, stream=a.stream)
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(a.stream)
                 a.events.append(ev)
