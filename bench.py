@@ -36,11 +36,11 @@ MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # dense FP32 / FP64 matrix p
 FETCH_SCALE = 2097152.0 / 1048599.75
 WRITE_SCALE = 1.0
 PMC_TRAFFIC = [
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "b9f72fda2c118b5250337b3884f89eeb342e4fa9278fd3a0c53f3029af764968", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053777.5, "write_kib": 2105376.25},
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "b9f72fda2c118b5250337b3884f89eeb342e4fa9278fd3a0c53f3029af764968", "workload": "square128_c64", "variant": "2x2x1_nt", "fetch_kib": 1053779.0, "write_kib": 2105416.625},
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "b9f72fda2c118b5250337b3884f89eeb342e4fa9278fd3a0c53f3029af764968", "workload": "square128_c64", "variant": "1x1x1_nt", "fetch_kib": 1053777.0, "write_kib": 2107658.625},
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "b9f72fda2c118b5250337b3884f89eeb342e4fa9278fd3a0c53f3029af764968", "workload": "square128_c64", "variant": "4x4x1_nt", "fetch_kib": 1053783.0, "write_kib": 2105414.125},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_delay.hip", "sha256": "f799cfb0099a16847ad64af4d67b5150dd32518f0acc97964a8e8c5a876ba0c3", "workload": "square128_c64", "variant": "w32", "fetch_kib": 1204753.5, "write_kib": 2097152.0},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "ea2219c6041b5498cc12b6cc7ee36cd72d7c07326ce66a698b65f6d41970041c", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053783.0, "write_kib": 2105373.5},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "ea2219c6041b5498cc12b6cc7ee36cd72d7c07326ce66a698b65f6d41970041c", "workload": "square128_c64", "variant": "2x2x1_nt", "fetch_kib": 1053785.0, "write_kib": 2105477.9},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "ea2219c6041b5498cc12b6cc7ee36cd72d7c07326ce66a698b65f6d41970041c", "workload": "square128_c64", "variant": "1x1x1_nt", "fetch_kib": 1053779.0, "write_kib": 2106484.6},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "ea2219c6041b5498cc12b6cc7ee36cd72d7c07326ce66a698b65f6d41970041c", "workload": "square128_c64", "variant": "4x4x1_nt", "fetch_kib": 1053783.5, "write_kib": 2105409.5},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_delay.hip", "sha256": "b19ec2636ba06c71c05492f104c3c889b65a3186d94aec3033a91e407d3252ef", "workload": "square128_c64", "variant": "w32_pipe8_3m", "fetch_kib": 1174401.3, "write_kib": 2097152.0},
 ]
 
 
