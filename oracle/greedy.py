@@ -22,6 +22,15 @@ improve the FOM individually, whose pixel is not yet chosen and whose
 Chebyshev distance to every chosen pixel is at least `min_spacing`, until k
 pixels are chosen or none is eligible.  The chosen set is then applied jointly
 (eq. form14 with V = the set).
+
+Epsilon-greedy policy (Sec. V): with probability 1 - eps the agent takes the
+greedy move; otherwise it explores, choosing at random among the top four
+FOM-increasing moves; it runs until no FOM-increasing move is left.  Readings
+adopted: the top four are the first four picks of the rank-k rule with no
+spacing (distinct pixels; for a two-material table these are the four best
+moves), the greedy move among them; random numbers are inputs, one pair
+(u_explore, u_choice) per step: the step explores iff u_explore < eps and then
+takes entry floor(u_choice * n) of the n (<= 4) improving moves.
 """
 from __future__ import annotations
 
@@ -209,6 +218,45 @@ def rank_k_trajectory(problem, steps=None, tier="T2", tau=None) -> Trajectory:
         fom = state.fom_of_state(problem, E)
         traj.steps.append([Step(t, pk.pixel, pk.eps_idx, pk.fom_new, fom, pk.n_tied)
                            for pk in picks])
+    traj.eps_idx = eps_idx
+    traj.E = E
+    return traj
+
+
+def select_eps_greedy(F: np.ndarray, fom_now: float, tau: float, eps: float, u_explore: float,
+                      u_choice: float, nx: int, n_top: int = 4):
+    """Epsilon-greedy choice; None when no candidate improves the FOM."""
+    top = select_rank_k(F, fom_now, tau, n_top, 0, nx)
+    if not top:
+        return None
+    i = 0
+    if u_explore < eps:
+        i = min(int(u_choice * len(top)), len(top) - 1)
+    return top[i]
+
+
+def eps_greedy(problem, eps, draws, steps=None, tier="T2", eps_idx0=None, tau=None,
+               n_top=4) -> Trajectory:
+    """Epsilon-greedy trajectory; step t uses draws[t] = (u_explore, u_choice)."""
+    steps = problem.steps if steps is None else steps
+    tau = problem.tau if tau is None else tau
+    ev = _Evaluator(problem, tier)
+    eps_idx = (np.zeros(problem.n, np.uint8) if eps_idx0 is None
+               else np.asarray(eps_idx0, np.uint8).copy())
+    E, diag, row = ev(eps_idx)
+    fom = state.fom_of_state(problem, E)
+    traj = Trajectory(problem.name, fom0=fom)
+    for t in range(min(steps, len(draws))):
+        F = scores_closed_form(problem, E, diag, row, eps_idx)
+        pick = select_eps_greedy(F, fom, tau, eps, float(draws[t][0]), float(draws[t][1]),
+                                 problem.nx, n_top)
+        if pick is None:
+            traj.stopped = True
+            break
+        eps_idx[pick.pixel] = pick.eps_idx
+        E, diag, row = ev(eps_idx)
+        fom = state.fom_of_state(problem, E)
+        traj.steps.append(Step(t, pick.pixel, pick.eps_idx, pick.fom_new, fom, pick.n_tied))
     traj.eps_idx = eps_idx
     traj.E = E
     return traj

@@ -119,3 +119,49 @@ def test_stored_square32_trajectory_reproduced_by_flipped_set_tier():
     assert [s.pixel for s in tr.steps] == [s["pixel"] for s in gold["steps"]]
     for a, b in zip(tr.steps, gold["steps"]):
         assert abs(a.fom - b["fom"]) <= 1e-11 * b["fom"]
+
+
+# ---------------------------------------------------------------- epsilon-greedy (Sec. V)
+def test_eps_greedy_with_eps_zero_is_the_greedy_trajectory():
+    p = W.tiny(6, 7, n_mon=4, cand_mask=W.MASK_BOTH, steps=60)
+    g = greedy.greedy(p, tier="T2")
+    e = greedy.eps_greedy(p, 0.0, W.eps_greedy_draws(60, seed=3), tier="T2")
+    assert [(s.pixel, s.eps_idx) for s in e.steps] == [(s.pixel, s.eps_idx) for s in g.steps]
+    assert e.stopped == g.stopped and np.allclose([s.fom for s in e.steps], [s.fom for s in g.steps])
+
+
+def test_eps_greedy_explore_choice_is_the_drawn_rank_by_brute_force():
+    """With eps = 1 every step explores: the move taken must be the
+    floor(u * n)-th best of the n <= 4 FOM-increasing moves, ranking every
+    candidate structure by a full re-solve (tier T0) and sorting."""
+    p = W.tiny(4, 5, n_mon=4, cand_mask=W.MASK_BOTH, steps=12)
+    idx0 = W.random_eps_idx(p, 0.3, seed=11)              # breaks the mirror ties
+    draws = W.eps_greedy_draws(12, seed=5)
+    tr = greedy.eps_greedy(p, 1.0, draws, tier="T1", eps_idx0=idx0)
+    assert len(tr.steps) >= 4
+    G0 = greens.build_G0(p)
+    cur = idx0.copy()
+    for t, s in enumerate(tr.steps):
+        F = state.brute_force_scores(p, cur, G0)
+        _, E = state.dense_state(p, state.eps_of(p, cur), G0)
+        fom = state.fom_of_state(p, E)
+        # best move of each pixel (two materials: one candidate per pixel), improving only
+        best = F.max(axis=1)
+        order = [int(q) for q in np.argsort(-best, kind="stable") if best[q] > fom * (1 + p.tau)]
+        top = order[:4]
+        vals = best[top]
+        assert np.all(np.diff(vals) < 0) and np.all(-np.diff(vals) > 1e-9 * vals[0])  # no ties here
+        want = top[min(int(draws[t][1] * len(top)), len(top) - 1)]
+        assert s.pixel == want and s.eps_idx == int(np.argmax(F[want]))
+        cur[s.pixel] = s.eps_idx
+
+
+def test_eps_greedy_fom_rises_and_ends_without_an_improving_move():
+    p = W.tiny(6, 6, n_mon=4, cand_mask=W.MASK_BOTH, steps=400)
+    tr = greedy.eps_greedy(p, 0.5, W.eps_greedy_draws(400, seed=2), tier="T2")
+    assert tr.stopped
+    foms = [tr.fom0] + [s.fom for s in tr.steps]
+    assert all(b > a for a, b in zip(foms, foms[1:]))
+    G0 = greens.build_G0(p)
+    F = state.brute_force_scores(p, tr.eps_idx, G0)
+    assert not F.max() > foms[-1] * (1 + p.tau)

@@ -113,3 +113,36 @@ def test_pin_catches_highest_index_tie_break(monkeypatch):
         return greedy.Pick(flat // F.shape[1], flat % F.shape[1], float(F.ravel()[flat]))
     monkeypatch.setattr(greedy, "select_greedy", bad)
     assert not _mirror_tie_pin_holds()
+
+
+def _eps_greedy_pin_holds():
+    """Explore steps take the drawn rank of the brute-force ordering (eps = 1)."""
+    p = W.tiny(4, 5, n_mon=4, cand_mask=W.MASK_BOTH, steps=6)
+    idx0 = W.random_eps_idx(p, 0.3, seed=11)
+    draws = W.eps_greedy_draws(6, seed=5)
+    tr = greedy.eps_greedy(p, 1.0, draws, tier="T1", eps_idx0=idx0)
+    G0 = greens.build_G0(p)
+    cur = idx0.copy()
+    for t, s in enumerate(tr.steps):
+        F = state.brute_force_scores(p, cur, G0)
+        _, E = state.dense_state(p, state.eps_of(p, cur), G0)
+        fom = state.fom_of_state(p, E)
+        best = F.max(axis=1)
+        top = [int(q) for q in np.argsort(-best, kind="stable") if best[q] > fom * (1 + p.tau)][:4]
+        if s.pixel != top[min(int(draws[t][1] * len(top)), len(top) - 1)]:
+            return False
+        cur[s.pixel] = s.eps_idx
+    return len(tr.steps) > 0
+
+
+def test_pin_catches_eps_greedy_rank_slip(monkeypatch):
+    assert _eps_greedy_pin_holds()
+
+    def bad(F, fom_now, tau, eps, u_explore, u_choice, nx, n_top=4):
+        top = greedy.select_rank_k(F, fom_now, tau, n_top, 0, nx)
+        if not top:
+            return None
+        i = min(int(u_choice * (len(top) - 1)), len(top) - 1) if u_explore < eps else 0  # never the last
+        return top[i]
+    monkeypatch.setattr(greedy, "select_eps_greedy", bad)
+    assert not _eps_greedy_pin_holds()

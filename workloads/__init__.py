@@ -100,8 +100,16 @@ STRIP_48x2048 = Problem("strip48x2048_c64", 48, 2048, 256, pitch=1.0 / 16,
 SQUARE_128_RANK16 = SQUARE_128.replace(name="square128_rank16", steps=300, rank_k=16,
                                        min_spacing=3, refresh_every=16)
 
+# 21x21 focusing lens for the exploration study: the 2-D analogue of the paper's
+# small epsilon-greedy demonstration (21x21 pixels at lambda/20, silicon eps 12,
+# focus at NA 0.7: half-aperture 0.525 lambda, focal distance 0.525/tan(asin 0.7)
+# = 0.536 lambda past the exit face).
+SQUARE_21 = Problem("square21_fp64", 21, 21, 8, pitch=0.05, mon_distance=0.536,
+                    eps_table=(EPS_VACUUM, 12.0), cand_mask=MASK_BOTH, dtype="c128",
+                    steps=2000)
+
 WORKLOADS = {p.name: p for p in (SMALL_32, SQUARE_128, SQUARE_128_FP64, STRIP_48x2048,
-                                 SQUARE_128_RANK16)}
+                                 SQUARE_128_RANK16, SQUARE_21)}
 
 
 def tiny(ny: int, nx: int, n_mon: int = 4, **kw) -> Problem:
@@ -125,6 +133,12 @@ def mirror_symmetric_eps_idx(problem: Problem, fill: float, seed: int) -> np.nda
     m = (rng.random((problem.ny, half)) < fill).astype(np.uint8)
     full = np.concatenate([m, m[:, : problem.nx - half][:, ::-1]], axis=1)
     return np.ascontiguousarray(full.reshape(-1))
+
+
+def eps_greedy_draws(n_steps: int, seed: int) -> np.ndarray:
+    """(n_steps, 2) float64 uniforms in [0, 1): for step t, the draw that decides
+    whether the step explores, and the draw that chooses among the top moves."""
+    return np.random.default_rng(seed).random((n_steps, 2))
 
 
 @dataclass
