@@ -274,6 +274,89 @@ def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True):
     return out
 
 
+def eps_greedy_study(runs=20, eps_list=(0.0, 0.1, 0.2, 0.3), with_oracle=True):
+    """Epsilon-greedy on the 21x21 lens (the 2-D analogue of the paper's Sec. V
+    study): `runs` seeded trajectories per eps, each to termination.  Reports the
+    terminal FOM statistics and the GPU step rate; one trajectory is also run by
+    the oracle on the host and compared move for move."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2202_05388_amd.job import Job
+
+    p = W.SQUARE_21
+    job = Job(p, device="cuda:0")
+    out = {}
+    steps_total, t_total = 0, 0.0
+    for eps in eps_list:
+        foms, lens = [], []
+        for seed in range(runs):
+            draws = W.eps_greedy_draws(2000, seed)
+            job.init()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n = job.run_eps_greedy(eps, draws, poll_every=64)
+            torch.cuda.synchronize()
+            t_total += time.perf_counter() - t0
+            steps_total += n
+            foms.append(job.fom())
+            lens.append(n)
+        out[f"eps_{eps}"] = dict(fom_mean=float(np.mean(foms)), fom_std=float(np.std(foms)),
+                                 fom_max=float(np.max(foms)), moves_mean=float(np.mean(lens)))
+    greedy_fom = out["eps_0.0"]["fom_mean"]
+    for k, v in out.items():
+        v["vs_greedy"] = v["fom_mean"] / greedy_fom
+    cpu = None
+    if with_oracle:
+        # CPU baseline: one trajectory on the oracle (host cores), compared with the GPU's
+        from oracle import greedy as og
+        draws = W.eps_greedy_draws(2000, 0)
+        t0 = time.perf_counter()
+        ref = og.eps_greedy(p, 0.1, draws, tier="T2")
+        t_cpu = time.perf_counter() - t0
+        job.init()
+        job.run_eps_greedy(0.1, draws, poll_every=64)
+        same = [tuple(map(int, h)) for h in job.history()] == [(s.pixel, s.eps_idx)
+                                                                for s in ref.steps]
+        cpu = dict(kind="oracle", eps=0.1, seed=0, moves=len(ref.steps), seconds=t_cpu,
+                   moves_per_s=len(ref.steps) / t_cpu, gpu_matches=bool(same))
+    del job
+    torch.cuda.empty_cache()
+    return dict(workload=p.name, runs_per_eps=runs, by_eps=out,
+                gpu_moves_per_s=steps_total / t_total, cpu_baseline=cpu)
+
+
+def time_eps_greedy(problem, steps, eps, delay):
+    """Epsilon-greedy steps (top-4 scores, drawn choice, rank-1 apply; deferred
+    updates when delay > 0) until `steps` moves, restarting finished trajectories."""
+    import torch
+    import workloads as W
+    from paper_2202_05388_amd.job import Job
+
+    job = Job(problem, device="cuda:0", delay=delay, ld_pad=LD_PAD)
+    job.init()
+    job.run_eps_greedy(eps, W.eps_greedy_draws(64, 99), poll_every=64)   # warm-up
+    job.init()
+    torch.cuda.synchronize()
+    moves, restarts, seed = 0, 0, 0
+    t0 = time.perf_counter()
+    while moves < steps:
+        n = job.run_eps_greedy(eps, W.eps_greedy_draws(min(2000, steps - moves), seed),
+                               poll_every=32)
+        moves += n
+        seed += 1
+        if job.delay:
+            job.flush()
+        job.init()
+        restarts += 1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del job
+    torch.cuda.empty_cache()
+    return dict(eps=eps, delay=delay, moves=moves, restarts=restarts, moves_per_s=moves / dt,
+                ms_per_move=1e3 * dt / moves)
+
+
 def time_rank_k(problem, steps, warmup, precision):
     """Rank-k steps: score with top-k + spacing, then one joint Woodbury update.
 
@@ -389,6 +472,7 @@ def main():
     ap.add_argument("--no-deferred", action="store_true")
     ap.add_argument("--delay", type=int, default=64, help="deferred-mode flush interval")
     ap.add_argument("--no-refresh-timing", action="store_true")
+    ap.add_argument("--no-eps-greedy", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=64,
                     help="jobs in the served stream (0 = skip the serving measurement)")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="job arrivals per second")
@@ -477,6 +561,14 @@ def main():
             rank_k[prec] = time_rank_k(rk, steps=100, warmup=10, precision=prec)
             _log(f"[bench] rank-{rk.rank_k} {prec}: {rank_k[prec]}")
 
+    eps_greedy = None
+    if not args.no_eps_greedy and problem.name == "square128_c64":
+        _log("[bench] epsilon-greedy study (21x21 lens) and rate at 128^2")
+        eps_greedy = dict(study=eps_greedy_study(with_oracle=not args.no_cpu_baseline),
+                          square128_c64=time_eps_greedy(problem, min(args.steps, 1000), 0.1,
+                                                        args.delay))
+        _log(f"[bench] epsilon-greedy {eps_greedy}")
+
     refresh = None
     if not args.no_refresh_timing and problem.refresh_every:
         _log("[bench] FP64 refresh at the end of the trajectory")
@@ -553,6 +645,7 @@ def main():
         "accuracy": accuracy,
         "deferred": deferred,
         "rank_k": rank_k,
+        "eps_greedy": eps_greedy,
         "refresh": refresh,
         "serving": serving,
         "device_status": res["status"],

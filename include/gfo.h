@@ -191,6 +191,18 @@ int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 int gfo_greedy_steps(const gfo_problem* prob, gfo_state* st, int32_t n_steps,
                      uint32_t cand_mask, double tau, gfo_pick* d_picks, hipStream_t stream);
 
+/* gfo_choose_eps_greedy - the epsilon-greedy policy of paper Sec. V: act
+ * greedily with probability 1 - eps, otherwise choose at random among the top
+ * improving moves.  d_top: the k records of score_candidates(topk = k,
+ * min_spacing = 0) (device; improving moves first, the greedy one at index 0,
+ * then sentinels).  The random numbers are inputs: the step explores iff
+ * u_explore < eps, and then takes record floor(u_choice * n) of the n
+ * improving ones.  Writes one record to d_out (device; the sentinel when no
+ * move improves the FOM), for apply_flip.  1 <= k <= GFO_MAX_RANK_K,
+ * 0 <= eps <= 1, 0 <= u < 1.  Asynchronous on `stream`. */
+int gfo_choose_eps_greedy(const gfo_pick* d_top, int32_t k, double eps, double u_explore,
+                          double u_choice, gfo_pick* d_out, hipStream_t stream);
+
 /* apply_flips_rank_k - apply k moves jointly by the Woodbury form of the
  * paper's region update (eqs. form10-form14 with V = the k pixels):
  *   M = (I - B_S G[S,S])^-1 B_S  (k x k, FP64, B_S = diag(alpha)),

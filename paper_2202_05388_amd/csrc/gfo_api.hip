@@ -265,6 +265,16 @@ int gfo_greedy_steps(const gfo_problem* prob, gfo_state* st, int32_t n_steps, ui
   return GFO_OK;
 }
 
+int gfo_choose_eps_greedy(const gfo_pick* d_top, int32_t k, double eps, double u_explore,
+                          double u_choice, gfo_pick* d_out, hipStream_t stream) {
+  if (!d_top || !d_out || k < 1 || k > GFO_MAX_RANK_K || !(eps >= 0.0 && eps <= 1.0) ||
+      !(u_explore >= 0.0 && u_explore < 1.0) || !(u_choice >= 0.0 && u_choice < 1.0))
+    return GFO_EINVAL;
+  if (launch_choose_eps_greedy(d_top, k, eps, u_explore, u_choice, d_out, stream) != hipSuccess)
+    return GFO_EHIP;
+  return GFO_OK;
+}
+
 int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_picks, int32_t k,
                        int32_t gemm_precision, hipStream_t stream) {
   int rc = validate_problem(prob);

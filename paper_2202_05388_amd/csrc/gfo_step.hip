@@ -134,6 +134,29 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(
   }
 }
 
+// ------------------------------------------------------------------ policy
+// Epsilon-greedy choice (Sec. V) among the records of a top-k selection: the
+// improving moves come first (the greedy one at index 0), sentinels after.
+__global__ void k_choose_eps_greedy(const gfo_pick* __restrict__ top, int k, double eps,
+                                    double u_explore, double u_choice, gfo_pick* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int n = 0;
+  while (n < k && top[n].pixel >= 0) ++n;
+  int i = 0;
+  if (n > 0 && u_explore < eps) {
+    i = (int)(u_choice * (double)n);
+    if (i > n - 1) i = n - 1;
+  }
+  *out = top[i];
+}
+
+hipError_t launch_choose_eps_greedy(const gfo_pick* top, int k, double eps, double u_explore,
+                                    double u_choice, gfo_pick* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_choose_eps_greedy, dim3(1), dim3(64), 0, s, top, k, eps, u_explore, u_choice,
+                     out);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ K2a: snapshot
 // Single thread.  Validates the pick, computes c in FP64 from diag64 and
 // records the scalars the later kernels need before anything is overwritten.

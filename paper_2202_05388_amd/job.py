@@ -108,6 +108,34 @@ class Job:
         L.greedy_steps(self.prob, self.state, n, mask, tau, out, _stream_handle(stream))
         self.steps_issued += n
 
+    def eps_greedy_step(self, eps, u_explore, u_choice, n_top=4, stream=None):
+        """One epsilon-greedy step (paper Sec. V): top-n_top scores, the policy's
+        choice (records 0..n_top-1 and 8 of the pick buffer), rank-1 apply."""
+        base = self.picks.data_ptr()
+        chosen = base + 8 * L.PICK_BYTES
+        self.score(topk=n_top, min_spacing=0, out=base, stream=stream)
+        L.choose_eps_greedy(base, n_top, float(eps), float(u_explore), float(u_choice), chosen,
+                            _stream_handle(stream))
+        self.apply(pick_ptr=chosen, stream=stream)
+        self.steps_issued += 1
+
+    def run_eps_greedy(self, eps, draws, max_steps=None, poll_every=32, stream=None):
+        """Epsilon-greedy trajectory; step t uses draws[t] = (u_explore, u_choice).
+        Polls the move counter every poll_every steps and stops once a step made no
+        move (every earlier step moved: the policy only takes improving moves).
+        Returns the number of moves made by this call."""
+        start = self.n_flips()
+        n = len(draws) if max_steps is None else min(max_steps, len(draws))
+        t = 0
+        while t < n:
+            chunk = min(poll_every, n - t)
+            for i in range(chunk):
+                self.eps_greedy_step(eps, draws[t + i][0], draws[t + i][1], stream=stream)
+            t += chunk
+            if self.n_flips() - start < t:
+                break
+        return self.n_flips() - start
+
     # ------------------------------------------------------------------ host views
     def read_picks(self, k=1):
         raw = self.picks[: k * L.PICK_BYTES].cpu().numpy().tobytes()

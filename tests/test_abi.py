@@ -119,3 +119,12 @@ def test_k1_variants_listed():
                                   "w32_pipe8_3m_xcd"]
     assert L.flush_get_variant() == 4
     assert L.lib().gfo_strerror(L.GFO_ENOSPC) == b"workspace too small"
+
+
+def test_choose_eps_greedy_rejects_bad_arguments_on_host():
+    lib = L.lib()
+    fake = C.c_void_p(256)          # never dereferenced: every case fails validation first
+    for k, eps, u1, u2 in ((0, 0.1, 0.5, 0.5), (33, 0.1, 0.5, 0.5), (4, -0.1, 0.5, 0.5),
+                           (4, 1.5, 0.5, 0.5), (4, 0.1, 1.0, 0.5), (4, 0.1, 0.5, -0.2)):
+        assert lib.gfo_choose_eps_greedy(fake, k, eps, u1, u2, fake, None) == L.GFO_EINVAL
+    assert lib.gfo_choose_eps_greedy(None, 4, 0.1, 0.5, 0.5, fake, None) == L.GFO_EINVAL

@@ -1,0 +1,63 @@
+"""Epsilon-greedy policy on the GPU (paper Sec. V): top-4 scores, the drawn
+choice, rank-1 apply.  The move sequence must be the oracle's, draw for draw."""
+import numpy as np
+import pytest
+
+from oracle import greedy as og
+from oracle import state as ost
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _job(p, **kw):
+    from paper_2202_05388_amd.job import Job
+    print(f"[case] {p.name} {p.ny}x{p.nx} {p.dtype} {kw}", flush=True)
+    return Job(p, device="cuda:0", **kw)
+
+
+@pytest.mark.parametrize("eps,seed", [(0.1, 7), (0.3, 8), (1.0, 9)])
+def test_eps_greedy_square21_matches_oracle(eps, seed):
+    p = W.SQUARE_21
+    draws = W.eps_greedy_draws(400, seed)
+    ref = og.eps_greedy(p, eps, draws, tier="T2")
+    assert ref.stopped
+    job = _job(p)
+    job.init()
+    n = job.run_eps_greedy(eps, draws, poll_every=16)
+    hist = [(int(a), int(b)) for a, b in job.history()]
+    assert hist == [(s.pixel, s.eps_idx) for s in ref.steps] and n == len(ref.steps)
+    assert abs(job.fom() - ref.steps[-1].fom) <= 1e-9 * ref.steps[-1].fom
+    E = job.E.cpu().numpy()
+    assert np.linalg.norm(E - ref.E) <= 1e-9 * np.linalg.norm(ref.E)
+    assert job.status() == 0
+
+
+def test_eps_zero_is_the_greedy_path():
+    p = W.SQUARE_21
+    a = _job(p)
+    a.init()
+    a.run_greedy(400, poll_every=16)
+    b = _job(p)
+    b.init()
+    b.run_eps_greedy(0.0, W.eps_greedy_draws(400, 1), poll_every=16)
+    assert np.array_equal(a.history(), b.history())
+
+
+@pytest.mark.parametrize("dtype,delay", [("c128", 16), ("c64", 8)])
+def test_eps_greedy_deferred_equals_eager(dtype, delay):
+    p = W.SQUARE_21.replace(dtype=dtype, tau=1e-9 if dtype == "c128" else 1e-6)
+    draws = W.eps_greedy_draws(400, 4)
+    a = _job(p)
+    a.init()
+    a.run_eps_greedy(0.2, draws, poll_every=16)
+    b = _job(p, delay=delay)
+    b.init()
+    b.run_eps_greedy(0.2, draws, poll_every=16)
+    assert np.array_equal(a.history(), b.history())
+    Ga, Ea, _, _ = a.host_state()
+    Gb, Eb, _, _ = b.host_state()
+    tol = 1e-12 if dtype == "c128" else 3e-6
+    assert np.linalg.norm(Gb - Ga) <= tol * np.linalg.norm(Ga)
+    Gd, Ed = ost.dense_state(p, ost.eps_of(p, b.eps_idx.cpu().numpy()))
+    assert np.linalg.norm(Eb - Ed) <= (1e-11 if dtype == "c128" else 2e-5) * np.linalg.norm(Ed)
