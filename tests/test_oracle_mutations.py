@@ -146,3 +146,41 @@ def test_pin_catches_eps_greedy_rank_slip(monkeypatch):
         return top[i]
     monkeypatch.setattr(greedy, "select_eps_greedy", bad)
     assert not _eps_greedy_pin_holds()
+
+
+def _region_score_pin_holds():
+    from oracle import regions
+    p = W.tiny(4, 6, n_mon=4, cand_mask=W.MASK_BOTH)
+    idx = W.random_eps_idx(p, 0.4, seed=3)
+    E, row, G_VV = regions._RegionEvaluator(p, 2, "T1")(idx)
+    F = regions.region_scores(p, 2, E, G_VV, row, idx)
+    F0 = regions.brute_force_region_scores(p, 2, idx)
+    fin = np.isfinite(F0)
+    return np.allclose(F[fin], F0[fin], rtol=1e-10, atol=0)
+
+
+def test_pin_catches_region_solve_with_B_on_the_wrong_side(monkeypatch):
+    from oracle import regions
+    assert _region_score_pin_holds()
+    orig_solve = np.linalg.solve
+
+    def scores_bad(problem, b, E, G_VV, g_mon_row, eps_idx):
+        K = regions.n_regions(problem, b)
+        k0 = greens.k0_of(problem)
+        table = np.asarray(problem.eps_table)
+        cur = np.asarray(eps_idx, np.int64)
+        Em0 = E[problem.n + problem.fom_monitor]
+        out = np.full((K, table.size), -np.inf)
+        for k in range(K):
+            V = regions.region_pixels(problem, b, k)
+            for e in range(table.size):
+                if not (problem.cand_mask >> e) & 1 or np.all(cur[V] == e):
+                    continue
+                bv = k0**2 * (table[e] - table[cur[V]])
+                A = np.eye(V.size) - bv[:, None] * G_VV[k]          # B G instead of G B
+                x = orig_solve(A, E[V])
+                En = Em0 + g_mon_row[V] @ (bv * x)
+                out[k, e] = abs(En) ** 2
+        return out
+    monkeypatch.setattr(regions, "region_scores", scores_bad)
+    assert not _region_score_pin_holds()

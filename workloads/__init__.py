@@ -48,6 +48,7 @@ class Problem:
     rank_k: int = 1
     min_spacing: int = 0
     tau: float = 1e-9            # relative tie band of the greedy selection
+    region: int = 1              # side of the square regions a move flips (1 = one pixel)
 
     @property
     def n(self) -> int:
@@ -108,8 +109,14 @@ SQUARE_21 = Problem("square21_fp64", 21, 21, 8, pitch=0.05, mon_distance=0.536,
                     eps_table=(EPS_VACUUM, 12.0), cand_mask=MASK_BOTH, dtype="c128",
                     steps=2000)
 
+# 2x2-pixel region moves (pillars) on a 128x128 grid at lambda/40, so that a
+# region has the lambda/20 footprint of one pixel of the other workloads.
+SQUARE_128_REGIONS = Problem("square128_regions_c64", 128, 128, 64, pitch=0.025,
+                             mon_distance=1.0, cand_mask=MASK_BOTH, dtype="c64", steps=2000,
+                             refresh_every=256, tau=1e-6, region=2)
+
 WORKLOADS = {p.name: p for p in (SMALL_32, SQUARE_128, SQUARE_128_FP64, STRIP_48x2048,
-                                 SQUARE_128_RANK16, SQUARE_21)}
+                                 SQUARE_128_RANK16, SQUARE_21, SQUARE_128_REGIONS)}
 
 
 def tiny(ny: int, nx: int, n_mon: int = 4, **kw) -> Problem:
