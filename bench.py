@@ -357,6 +357,52 @@ def time_eps_greedy(problem, steps, eps, delay):
                 ms_per_move=1e3 * dt / moves)
 
 
+def time_regions(problem, steps, delay, apply):
+    """Greedy 2x2-region moves (score_regions, pixel moves, then four rank-1
+    updates in deferred mode or one joint rank-k step) until `steps` region moves,
+    restarting finished trajectories; every pending term is flushed before a
+    restart and at the end."""
+    import torch
+    from paper_2202_05388_amd.job import Job
+
+    job = Job(problem, device="cuda:0", delay=delay, ld_pad=LD_PAD)
+    job.init()
+    job.run_region_greedy(16, poll_every=16, apply=apply)            # warm-up
+    job.flush()
+    job.init()
+    torch.cuda.synchronize()
+    moves, restarts = 0, 0
+    t0 = time.perf_counter()
+    while moves < steps:
+        want = steps - moves
+        n, made = job.run_region_greedy(want, poll_every=32, apply=apply)
+        moves += n
+        if n < want:                               # the trajectory ended: restart
+            job.flush()
+            job.init()
+            restarts += 1
+    job.flush()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = dict(workload=problem.name, region="2x2", delay=delay, apply=apply, moves=moves,
+               restarts=restarts, moves_per_s=moves / dt, ms_per_move=1e3 * dt / moves,
+               status=job.status())
+    del job
+    torch.cuda.empty_cache()
+    return out
+
+
+def regions_cpu_baseline(problem, steps=20):
+    """The oracle's region greedy (flipped-set tier) for a bounded number of moves."""
+    from oracle import regions as orr
+    t0 = time.perf_counter()
+    tr = orr.region_greedy(problem, 2, steps=steps, tier="T2")
+    dt = time.perf_counter() - t0
+    return dict(kind="oracle", value=len(tr.steps) / dt, unit="region moves/s",
+                sample=f"first {len(tr.steps)} region moves of {problem.name} (T2), {dt:.1f} s",
+                cores=os.cpu_count())
+
+
 def time_rank_k(problem, steps, warmup, precision):
     """Rank-k steps: score with top-k + spacing, then one joint Woodbury update.
 
@@ -473,6 +519,7 @@ def main():
     ap.add_argument("--delay", type=int, default=64, help="deferred-mode flush interval")
     ap.add_argument("--no-refresh-timing", action="store_true")
     ap.add_argument("--no-eps-greedy", action="store_true")
+    ap.add_argument("--no-regions", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=64,
                     help="jobs in the served stream (0 = skip the serving measurement)")
     ap.add_argument("--serve-rate", type=float, default=4.0, help="job arrivals per second")
@@ -569,6 +616,16 @@ def main():
                                                         args.delay))
         _log(f"[bench] epsilon-greedy {eps_greedy}")
 
+    regions = None
+    if not args.no_regions and problem.name == "square128_c64":
+        rp = W.SQUARE_128_REGIONS
+        _log(f"[bench] region moves ({rp.name})")
+        regions = dict(deferred=time_regions(rp, 500, args.delay, "sequential"),
+                       rank_k=time_regions(rp, 100, 0, "rank_k"))
+        if not args.no_cpu_baseline:
+            regions["cpu_baseline"] = regions_cpu_baseline(rp)
+        _log(f"[bench] regions {regions}")
+
     refresh = None
     if not args.no_refresh_timing and problem.refresh_every:
         _log("[bench] FP64 refresh at the end of the trajectory")
@@ -646,6 +703,7 @@ def main():
         "deferred": deferred,
         "rank_k": rank_k,
         "eps_greedy": eps_greedy,
+        "regions": regions,
         "refresh": refresh,
         "serving": serving,
         "device_status": res["status"],

@@ -191,6 +191,31 @@ int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 int gfo_greedy_steps(const gfo_problem* prob, gfo_state* st, int32_t n_steps,
                      uint32_t cand_mask, double tau, gfo_pick* d_picks, hipStream_t stream);
 
+/* score_regions - greedy pick among multi-pixel region moves (paper Sec. II
+ * with a flipped region V of N_V = 4 pixels; Sec. IV flips 2x2-pixel pillars).
+ * Square regions of side `region` (= 2) tile the design grid (ny, nx even);
+ * region k = by * (nx / 2) + bx, pixels row-major inside it.  A move sets every
+ * pixel of the region to one material.  Score of (k, e): B = diag(b_i) with
+ * b_i = k0^2 (eps_e - eps_cur_i), x = (I - G_VV B)^-1 E_V (eqs. form6-form9),
+ * FOM' = |E_m0 + G[m0, V] B x|^2 (eq. form4 at the monitor, eq. para1), solved in
+ * FP64 with the FP64 diagonal; in deferred mode the in-block entries include the
+ * pending terms.  Candidates: materials in cand_mask that change at least one
+ * pixel.  The greedy rule and the tie band tau are those of score_candidates,
+ * with (region, material) in place of (pixel, material).  Writes one record to
+ * d_out (device): pixel = region index, or the sentinel.  Uses the workspace's
+ * score array (then holding n_regions x n_eps region scores).  EINVAL for
+ * another region side, an odd grid or more than 262144 regions. */
+int score_regions(const gfo_problem* prob, const gfo_state* st, int32_t region,
+                  uint32_t cand_mask, double tau, gfo_pick* d_out, hipStream_t stream);
+
+/* gfo_region_pixels - the pixel moves of a region move (the d_out of
+ * score_regions): region*region records in d_pixels (device), record i = pixel i
+ * of the region with the region's material, or the sentinel where the pixel
+ * already has it.  Applying them with apply_flip one after the other (any order)
+ * or jointly with apply_flips_rank_k is the region update of eqs. form10-form14. */
+int gfo_region_pixels(const gfo_problem* prob, const gfo_state* st, int32_t region,
+                      const gfo_pick* d_region, gfo_pick* d_pixels, hipStream_t stream);
+
 /* gfo_choose_eps_greedy - the epsilon-greedy policy of paper Sec. V: act
  * greedily with probability 1 - eps, otherwise choose at random among the top
  * improving moves.  d_top: the k records of score_candidates(topk = k,

@@ -27,7 +27,7 @@ EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "g
            "gfo_k1_variant_count", "gfo_k1_variant_name", "gfo_k1_set_variant",
            "gfo_k1_get_variant", "gfo_time_next_k1", "gfo_flush", "gfo_flush_variant_count",
            "gfo_flush_variant_name", "gfo_flush_set_variant", "gfo_flush_get_variant",
-           "gfo_greedy_steps", "gfo_choose_eps_greedy")
+           "gfo_greedy_steps", "gfo_choose_eps_greedy", "score_regions", "gfo_region_pixels")
 
 
 class Problem(C.Structure):
@@ -82,6 +82,8 @@ def lib():
     L.gfo_flush.argtypes = [P, S, V]
     L.gfo_greedy_steps.argtypes = [P, S, C.c_int32, C.c_uint32, C.c_double, V, V]
     L.gfo_choose_eps_greedy.argtypes = [V, C.c_int32, C.c_double, C.c_double, C.c_double, V, V]
+    L.score_regions.argtypes = [P, S, C.c_int32, C.c_uint32, C.c_double, V, V]
+    L.gfo_region_pixels.argtypes = [P, S, C.c_int32, V, V, V]
     L.gfo_flush_variant_name.argtypes = [C.c_int32]
     L.gfo_flush_variant_name.restype = C.c_char_p
     L.gfo_flush_set_variant.argtypes = [C.c_int32]
@@ -147,6 +149,16 @@ def refresh_G(prob, st, stream) -> None:
 
 def flush(prob, st, stream) -> None:
     check(lib().gfo_flush(C.byref(prob), C.byref(st), stream), "gfo_flush")
+
+
+def score_regions(prob, st, region, cand_mask, tau, d_out, stream) -> None:
+    check(lib().score_regions(C.byref(prob), C.byref(st), region, cand_mask, tau, d_out, stream),
+          "score_regions")
+
+
+def region_pixels(prob, st, region, d_region, d_pixels, stream) -> None:
+    check(lib().gfo_region_pixels(C.byref(prob), C.byref(st), region, d_region, d_pixels, stream),
+          "gfo_region_pixels")
 
 
 def choose_eps_greedy(d_top, k, eps, u_explore, u_choice, d_out, stream) -> None:

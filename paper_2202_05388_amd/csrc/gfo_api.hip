@@ -265,6 +265,41 @@ int gfo_greedy_steps(const gfo_problem* prob, gfo_state* st, int32_t n_steps, ui
   return GFO_OK;
 }
 
+static int validate_regions(const gfo_problem* prob, int32_t region) {
+  if (region != region_side() || prob->ny % region || prob->nx % region) return GFO_EINVAL;
+  const int64_t n = (int64_t)(prob->ny / region) * (prob->nx / region);
+  if ((n + kScoreThreads - 1) / kScoreThreads > kScoreMaxBlocks) return GFO_EINVAL;
+  return GFO_OK;
+}
+
+int score_regions(const gfo_problem* prob, const gfo_state* st, int32_t region,
+                  uint32_t cand_mask, double tau, gfo_pick* d_out, hipStream_t stream) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  Layout L;
+  if ((rc = validate_state(prob, st, &L))) return rc;
+  if ((rc = validate_regions(prob, region))) return rc;
+  if (!d_out || !(tau >= 0.0) || !(tau < 1.0)) return GFO_EINVAL;
+  const uint32_t mask = cand_mask & ((1u << prob->n_eps) - 1u);
+  if (mask == 0) return GFO_EINVAL;
+  const Geo g = make_geo(prob, st->ldG);
+  if (launch_score_regions(g, st, L, mask, tau, d_out, stream) != hipSuccess) return GFO_EHIP;
+  return GFO_OK;
+}
+
+int gfo_region_pixels(const gfo_problem* prob, const gfo_state* st, int32_t region,
+                      const gfo_pick* d_region, gfo_pick* d_pixels, hipStream_t stream) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  Layout L;
+  if ((rc = validate_state(prob, st, &L))) return rc;
+  if ((rc = validate_regions(prob, region))) return rc;
+  if (!d_region || !d_pixels) return GFO_EINVAL;
+  const Geo g = make_geo(prob, st->ldG);
+  if (launch_region_pixels(g, st, d_region, d_pixels, stream) != hipSuccess) return GFO_EHIP;
+  return GFO_OK;
+}
+
 int gfo_choose_eps_greedy(const gfo_pick* d_top, int32_t k, double eps, double u_explore,
                           double u_choice, gfo_pick* d_out, hipStream_t stream) {
   if (!d_top || !d_out || k < 1 || k > GFO_MAX_RANK_K || !(eps >= 0.0 && eps <= 1.0) ||

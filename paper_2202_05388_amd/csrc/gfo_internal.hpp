@@ -270,6 +270,11 @@ hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, c
 hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const double2* CU,
                                    const double2* V, double2* G, hipStream_t s);
 hipError_t launch_dl_reset(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
+int region_side();
+hipError_t launch_score_regions(const Geo& g, const gfo_state* st, const Layout& L, uint32_t mask,
+                                double tau, gfo_pick* out, hipStream_t s);
+hipError_t launch_region_pixels(const Geo& g, const gfo_state* st, const gfo_pick* region,
+                                gfo_pick* out, hipStream_t s);
 hipError_t launch_choose_eps_greedy(const gfo_pick* top, int k, double eps, double u_explore,
                                     double u_choice, gfo_pick* out, hipStream_t s);
 template <typename T>

@@ -136,6 +136,58 @@ class Job:
                 break
         return self.n_flips() - start
 
+    def region_step(self, apply="sequential", log_ptr=None, stream=None):
+        """One greedy region move (2x2 pixels, paper Sec. II with N_V = 4):
+        score_regions, its pixel moves (records 16..19 of the pick buffer), then
+        the rank-1 updates one after the other ("sequential") or the joint rank-k
+        step ("rank_k", complex64 storage).  The region pick goes to log_ptr
+        (device) or record 12."""
+        base = self.picks.data_ptr()
+        rpick = base + 12 * L.PICK_BYTES if log_ptr is None else log_ptr
+        pix = base + 16 * L.PICK_BYTES
+        h = _stream_handle(stream)
+        region = self.problem.region if self.problem.region > 1 else 2
+        L.score_regions(self.prob, self.state, region, self.problem.cand_mask, self.problem.tau,
+                        rpick, h)
+        L.region_pixels(self.prob, self.state, region, rpick, pix, h)
+        n = region * region
+        if apply == "rank_k":
+            if self.delay and self.state.pending_calls:
+                self.flush(stream)
+            L.apply_flips_rank_k(self.prob, self.state, pix, n, L.GFO_FP32, h)
+        else:
+            for i in range(n):
+                self.apply(pick_ptr=pix + i * L.PICK_BYTES, stream=stream)
+        self.steps_issued += 1
+
+    def run_region_greedy(self, max_steps, poll_every=32, apply="sequential", refresh_every=0,
+                          stream=None):
+        """Greedy loop over region moves; each step's region pick is logged on the
+        device and read at every poll; the loop stops at the first step that found
+        no improving region move (later steps of its chunk are no-ops).  With
+        refresh_every > 0, refresh_G runs after every refresh_every region moves.
+        Returns (region moves made, their region picks as (region, material))."""
+        log = torch.zeros(poll_every * L.PICK_BYTES, dtype=torch.uint8, device=self.device)
+        moves = []
+        done = 0
+        while done < max_steps:
+            chunk = min(poll_every, max_steps - done)
+            if refresh_every:
+                chunk = min(chunk, refresh_every - len(moves) % refresh_every)
+            for i in range(chunk):
+                self.region_step(apply=apply, log_ptr=log.data_ptr() + i * L.PICK_BYTES,
+                                 stream=stream)
+            done += chunk
+            raw = log[: chunk * L.PICK_BYTES].cpu().numpy().tobytes()
+            recs = (L.Pick * chunk).from_buffer_copy(raw)
+            made = [(r.pixel, r.eps_idx) for r in recs if r.pixel >= 0]
+            moves.extend(made)
+            if len(made) < chunk:
+                break
+            if refresh_every and len(moves) % refresh_every == 0:
+                self.refresh(stream)
+        return len(moves), moves
+
     # ------------------------------------------------------------------ host views
     def read_picks(self, k=1):
         raw = self.picks[: k * L.PICK_BYTES].cpu().numpy().tobytes()

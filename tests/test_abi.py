@@ -128,3 +128,24 @@ def test_choose_eps_greedy_rejects_bad_arguments_on_host():
                            (4, 1.5, 0.5, 0.5), (4, 0.1, 1.0, 0.5), (4, 0.1, 0.5, -0.2)):
         assert lib.gfo_choose_eps_greedy(fake, k, eps, u1, u2, fake, None) == L.GFO_EINVAL
     assert lib.gfo_choose_eps_greedy(None, 4, 0.1, 0.5, 0.5, fake, None) == L.GFO_EINVAL
+
+
+def test_region_calls_reject_bad_region_on_host():
+    """Another region side, or an odd grid, is refused before anything is launched."""
+    lib = L.lib()
+    pr, keep = _problem(W.tiny(8, 8, n_mon=4))
+    ld = L.min_ld(pr)
+    work = L.workspace_size(pr, 0)
+    fake = 1 << 20                       # aligned, never dereferenced
+    st = L.State(G=fake, ldG=ld, E=fake, diag64=fake, eps_idx=fake, flips=fake, flip_cap=16,
+                 n_flips=fake, kmax=0, work=fake, work_bytes=work, status=fake, delay=0,
+                 pending_calls=0)
+    out = C.c_void_p(fake)
+    for region in (0, 1, 3, 4):
+        assert lib.score_regions(C.byref(pr), C.byref(st), region, 3, 1e-9, out, None) == L.GFO_EINVAL
+        assert lib.gfo_region_pixels(C.byref(pr), C.byref(st), region, out, out, None) == L.GFO_EINVAL
+    pr2, keep2 = _problem(W.tiny(7, 8, n_mon=4))
+    st2 = L.State(G=fake, ldG=L.min_ld(pr2), E=fake, diag64=fake, eps_idx=fake, flips=fake,
+                  flip_cap=16, n_flips=fake, kmax=0, work=fake, work_bytes=L.workspace_size(pr2, 0),
+                  status=fake, delay=0, pending_calls=0)
+    assert lib.score_regions(C.byref(pr2), C.byref(st2), 2, 3, 1e-9, out, None) == L.GFO_EINVAL
