@@ -348,6 +348,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_mon_score(
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 // Fourth word of a raw buffer resource on gfx9-family chips (32-bit data format;
 // reads past the range return zero).
 constexpr int kBufferDword3 = 0x00020000;
@@ -578,10 +579,170 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
   }
 }
 
+// Warp-specialised persistent flush: one workgroup of 8 waves per CU walks the
+// 64 x 64 output tiles (tile id = blockIdx.x + i * gridDim.x; bx = id % nbx,
+// by = id / nbx).  Waves 0-3 only stream CU/V operands and issue matrix
+// instructions (32 x 32 outputs each, three real products per complex one, an
+// operand ring of H instruction steps that runs on into the next tile); waves
+// 4-7 move G: they bring the next tile's G into one of two LDS buffers while the
+// current tile computes, and store the finished tile from LDS.  The matrix waves
+// thus never wait on G traffic (vector memory operations of a wave complete in
+// issue order).  Per tile, every wave passes the same two barriers:
+//   X: the matrix waves hold the tile's products, G_in[t % 2] is loaded, the
+//      movers have read the previous finished tile out of G_out;
+//   Y: G_out holds tile t (G + products), G_in[(t + 1) % 2] holds tile t + 1.
+// Same operand loads and 32-bit offset limit as k_flush_c64_pipe.
+constexpr int kWsPitch = 66;                     // float2 per LDS row (16-B aligned rows)
+constexpr int kWsTile = 64 * kWsPitch;
+
+template <int H>
+__global__ __launch_bounds__(512) void k_flush_c64_ws(int M, int R, int64_t ld,
+                                                      const int32_t* __restrict__ count,
+                                                      const float2* __restrict__ CU,
+                                                      const float2* __restrict__ V,
+                                                      float2* __restrict__ G, int nbx, int nby) {
+  __shared__ __align__(16) float2 lds[3 * kWsTile];     // G_in[0], G_in[1], G_out
+  const int K = *count;
+  if (K == 0) return;
+  const int ntiles = nbx * nby;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int P = GFO_MAX_DELAY / 2;
+  static_assert(P % H == 0 && H < P, "ring depth");
+  if (w >= 4) {
+    // ---------------------------------------------------------------- movers
+    const int mt = threadIdx.x - 256;             // 0..255: 8 x 16 B of a 32 KB tile each
+    auto tile_rc = [&](int id, int j, int& r, int& c) {
+      const int idx = (j * 256 + mt) * 2;         // float2 index within the 64 x 64 tile
+      r = idx >> 6;
+      c = idx & 63;
+      (void)id;
+    };
+    f32x4 buf[8];
+    auto load_tile = [&](int id) {
+      const int bx = id % nbx, by = id / nbx;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        int r, c;
+        tile_rc(id, j, r, c);
+        const int row = by * 64 + r;
+        buf[j] = row < M ? *(const f32x4*)(G + (int64_t)row * ld + bx * 64 + c) : f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+    };
+    auto put_in = [&](int slot) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        int r, c;
+        tile_rc(0, j, r, c);
+        *(f32x4*)(lds + slot * kWsTile + r * kWsPitch + c) = buf[j];
+      }
+    };
+    auto store_out = [&](int id) {
+      const int bx = id % nbx, by = id / nbx;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        int r, c;
+        tile_rc(id, j, r, c);
+        const f32x4 v = *(const f32x4*)(lds + 2 * kWsTile + r * kWsPitch + c);
+        const int row = by * 64 + r;
+        if (row < M) *(f32x4*)(G + (int64_t)row * ld + bx * 64 + c) = v;
+      }
+    };
+    int id = blockIdx.x;
+    if (id < ntiles) {
+      load_tile(id);
+      put_in(0);
+    }
+    __syncthreads();                              // prologue: G_in[0] holds the first tile
+    int it = 0;
+    for (; id < ntiles; id += gridDim.x, ++it) {
+      if (it > 0) store_out(id - (int)gridDim.x);            // the previous finished tile
+      const int nid = id + (int)gridDim.x;
+      if (nid < ntiles) load_tile(nid);
+      __syncthreads();                            // X
+      if (nid < ntiles) put_in((it + 1) & 1);
+      __syncthreads();                            // Y
+    }
+    if (it > 0) store_out(id - (int)gridDim.x);
+    return;
+  }
+  // ---------------------------------------------------------------- matrix waves
+  const int h = lane >> 5;
+  const __amdgpu_buffer_rsrc_t ra =
+      __builtin_amdgcn_make_buffer_rsrc((void*)CU, (short)0, K * R * 8, kBufferDword3);
+  const __amdgpu_buffer_rsrc_t rb =
+      __builtin_amdgcn_make_buffer_rsrc((void*)V, (short)0, (int)(K * ld * 8), kBufferDword3);
+  const unsigned a_step = 2u * (unsigned)R * 8u, b_step = 2u * (unsigned)ld * 8u;
+  // operand offsets of a tile (an id past the end gives offsets past the range: zeros)
+  auto offsets = [&](int id, unsigned& ao, unsigned& bo) {
+    if (id >= ntiles) {
+      ao = bo = 0xFFFFFFF0u;
+      return;
+    }
+    const int bx = id % nbx, by = id / nbx;
+    const int am = by * 64 + (w >> 1) * 32 + (lane & 31);
+    const int n = bx * 64 + (w & 1) * 32 + (lane & 31);
+    ao = am < M ? (unsigned)(h * R + am) * 8u : 0xFFFFFFF0u;
+    bo = (unsigned)(h * ld + n) * 8u;
+  };
+  auto ld_a = [&](unsigned base, int step) {
+    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(
+                                         ra, base == 0xFFFFFFF0u ? base : base + step * a_step, 0, 0));
+  };
+  auto ld_b = [&](unsigned base, int step) {
+    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(
+                                         rb, base == 0xFFFFFFF0u ? base : base + step * b_step, 0, 0));
+  };
+  int id = blockIdx.x;
+  unsigned a_off, b_off;
+  offsets(id, a_off, b_off);
+  f32x2 ra_[H], rb_[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    ra_[i] = ld_a(a_off, i);
+    rb_[i] = ld_b(b_off, i);
+  }
+  __syncthreads();                                // prologue
+  const int lr0 = (w >> 1) * 32 + 4 * h, lc = (w & 1) * 32 + (lane & 31);
+  for (int it = 0; id < ntiles; id += gridDim.x, ++it) {
+    unsigned na, nb;
+    offsets(id + (int)gridDim.x, na, nb);
+    f32x16 X, Y, Z;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) X[e] = Y[e] = Z[e] = 0.f;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const f32x2 ai = ra_[i % H], bi = rb_[i % H];
+      if (i + H < P) {
+        ra_[i % H] = ld_a(a_off, i + H);
+        rb_[i % H] = ld_b(b_off, i + H);
+      } else {
+        ra_[i % H] = ld_a(na, i + H - P);
+        rb_[i % H] = ld_b(nb, i + H - P);
+      }
+      X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
+      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[1], bi[1], Y, 0, 0, 0);
+      Z = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0] + ai[1], bi[0] + bi[1], Z, 0, 0, 0);
+    }
+    __syncthreads();                              // X
+    const float2* gin = lds + (it & 1) * kWsTile;
+    float2* gout = lds + 2 * kWsTile;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r = lr0 + 8 * (e >> 2) + (e & 3);
+      const float2 gv = gin[r * kWsPitch + lc];
+      gout[r * kWsPitch + lc] = make_float2(gv.x + (X[e] - Y[e]), gv.y + (Z[e] - X[e] - Y[e]));
+    }
+    __syncthreads();                              // Y
+    a_off = na;
+    b_off = nb;
+  }
+}
+
 // flush variants for complex64 storage (selected by the autotuner; all give the
 // eager results to FP32 rounding, tests/test_gpu_deferred.py)
 static const char* const kFlushNames[] = {"w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8",
-                                          "w32_pipe8_3m", "w32_pipe8_3m_xcd"};
+                                          "w32_pipe8_3m", "w32_pipe8_3m_xcd", "ws8_3m",
+                                          "ws16_3m"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
 constexpr int kFlushDefault = 4;
 static std::atomic<int> g_flush_sel{kFlushDefault};
@@ -713,6 +874,29 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false>), grid, blk, 0, s, g.N, g.R, g.ld, count,
                            cu, vv, G, (int)grid.y);
         break;
+      case 6:
+      case 7: {
+        // one persistent workgroup per CU (its LDS allows no second one)
+        static std::atomic<int> n_cu_cache{0};
+        int n_cu = n_cu_cache.load();
+        if (n_cu == 0) {
+          int dev = 0;
+          if (hipGetDevice(&dev) != hipSuccess ||
+              hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+              n_cu <= 0)
+            return hipErrorUnknown;
+          n_cu_cache.store(n_cu);
+        }
+        const int nbx = (int)grid.x, nby = (int)grid.y;
+        const int nwg = n_cu < nbx * nby ? n_cu : nbx * nby;
+        if (fv == 6)
+          hipLaunchKernelGGL((k_flush_c64_ws<8>), dim3(nwg), dim3(512), 0, s, g.N, g.R, g.ld, count, cu,
+                             vv, G, nbx, nby);
+        else
+          hipLaunchKernelGGL((k_flush_c64_ws<16>), dim3(nwg), dim3(512), 0, s, g.N, g.R, g.ld, count,
+                             cu, vv, G, nbx, nby);
+        break;
+      }
       default: {
         const unsigned nby = grid.y, bpx = (nby + 7) / 8;
         hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true>), dim3(8 * bpx * grid.x), blk, 0, s, g.N,
