@@ -36,11 +36,8 @@ MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # dense FP32 / FP64 matrix p
 FETCH_SCALE = 2097152.0 / 1048599.75
 WRITE_SCALE = 1.0
 PMC_TRAFFIC = [
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "ea2219c6041b5498cc12b6cc7ee36cd72d7c07326ce66a698b65f6d41970041c", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053783.0, "write_kib": 2105373.5},
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "ea2219c6041b5498cc12b6cc7ee36cd72d7c07326ce66a698b65f6d41970041c", "workload": "square128_c64", "variant": "2x2x1_nt", "fetch_kib": 1053785.0, "write_kib": 2105477.9},
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "ea2219c6041b5498cc12b6cc7ee36cd72d7c07326ce66a698b65f6d41970041c", "workload": "square128_c64", "variant": "1x1x1_nt", "fetch_kib": 1053779.0, "write_kib": 2106484.6},
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "ea2219c6041b5498cc12b6cc7ee36cd72d7c07326ce66a698b65f6d41970041c", "workload": "square128_c64", "variant": "4x4x1_nt", "fetch_kib": 1053783.5, "write_kib": 2105409.5},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_delay.hip", "sha256": "b19ec2636ba06c71c05492f104c3c889b65a3186d94aec3033a91e407d3252ef", "workload": "square128_c64", "variant": "w32_pipe8_3m", "fetch_kib": 1174401.3, "write_kib": 2097152.0},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "ba19d3f156614bff5508ef76e53c53f54211d9cb4b179361daaeb5fdb8606911", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053783.0, "write_kib": 2105382.75},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_delay.hip", "sha256": "7f784adc6f3fafc38c4b68304829f996ddbc808d8cee2c1b08ea049cbd7f87f2", "workload": "square128_c64", "variant": "sym_pipe8_3m", "fetch_kib": 1014106.5, "write_kib": 2098155.4},
 ]
 
 
@@ -266,7 +263,9 @@ def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True):
                flush_variant=None if flush_tuned is None else flush_tuned["name"],
                flush_us=None if fl_ms is None else fl_ms * 1e3,
                flush_tflops=None if fl_ms is None else 8.0 * N * ld * delay / (fl_ms * 1e-3) / 1e12,
-               flush_gbs=None if fl_ms is None else 2 * elem * N * ld / (fl_ms * 1e-3) / 1e9,
+               flush_gbs=None if fl_ms is None else
+               (12 if str(flush_tuned and flush_tuned.get("name")).startswith("sym") and elem == 8
+                else 2 * elem) * N * ld / (fl_ms * 1e-3) / 1e9,
                fom_last=job.fom(), status=job.status(),
                last_run_pixels=[int(x) for x in hist[:, 0]])
     del job
@@ -656,16 +655,30 @@ def main():
                 f"{'fused greedy loop (gfo_greedy_steps)' if d['fused'] else 'per-call'}")
         head_value = d["steps_per_s"]
         head_ms = d["ms_per_step"]
-        flops = 8.0 * N * ld * d["delay"]
+        flops = 8.0 * N * ld * d["delay"]            # complex rank-r update, 8 real flops per MAC
         peak = MFMA_PEAK_TFLOPS[problem.dtype]
-        roofline = {"bound": "mfma", "achieved": d["flush_tflops"], "peak": peak,
-                    "unit": "TFLOP/s", "frac": d["flush_tflops"] / peak,
-                    "traffic": pmc_traffic("k_flush_c64", problem.name, d["flush_variant"]),
-                    "traffic_unit": "bytes/launch",
-                    "kernel": f"flush of the deferred updates, FP32 MFMA, variant {d['flush_variant']}",
-                    "flops_per_launch": flops, "avg_launch_us": d["flush_us"],
-                    "algorithmic_bytes_per_launch": 2 * elem * N * ld,
-                    "variant": d["flush_variant"]}
+        sym = str(d["flush_variant"]).startswith("sym")
+        # issued matrix work: three real products per complex one (_3m variants),
+        # on the upper triangle only (sym: the design block is symmetric)
+        issued = flops * (0.75 if "3m" in str(d["flush_variant"]) else 1.0) * (0.5 if sym else 1.0)
+        # minimal HBM traffic: the design block read and written once; with the
+        # symmetric update half of it read, all of it written
+        alg_bytes = (12 if sym else 16) * N * ld if problem.dtype == "c64" else 32 * N * ld
+        t_mfma, t_hbm = issued / (peak * 1e12), alg_bytes / (HBM_PEAK_GBS * 1e9)
+        secs = d["flush_us"] * 1e-6
+        common = {"kernel": f"flush of the deferred updates, FP32 MFMA, variant {d['flush_variant']}",
+                  "traffic": pmc_traffic("k_flush_c64", problem.name, d["flush_variant"]),
+                  "traffic_unit": "bytes/launch", "avg_launch_us": d["flush_us"],
+                  "flops_per_launch": flops, "issued_flops_per_launch": issued,
+                  "algorithmic_bytes_per_launch": alg_bytes, "variant": d["flush_variant"],
+                  "complex_update_tflops": flops / secs / 1e12}
+        if t_hbm >= t_mfma:
+            achieved = alg_bytes / secs / 1e9
+            roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, **common}
+        else:
+            roofline = {"bound": "mfma", "achieved": d["flush_tflops"], "peak": peak,
+                        "unit": "TFLOP/s", "frac": d["flush_tflops"] / peak, **common}
         pix = d["last_run_pixels"]
     else:
         mode = "eager rank-1 updates"

@@ -502,7 +502,15 @@ __global__ __launch_bounds__(256) void k_flush_c64_tm(int M, int R, int64_t ld,
 // blocks [x * bpx, (x + 1) * bpx) and walks them column block by column block:
 // its band of CU rows stays in its own L2 and each V column block is reused
 // across the band.  nby = row blocks, bpx = ceil(nby / 8), grid = 8 * bpx * nbx.
-template <bool THREE_MULT, int H, bool XCD>
+//
+// SYM: the design block is symmetric (reciprocity: G_D = G_D^T, and each pending
+// term restricted to it, c_s v_s v_s^T, is symmetric too), so only the tiles on
+// and above the diagonal are computed: a one-dimensional grid of nby (nby + 1) / 2
+// workgroups, tile t in row-major order over that triangle (nby = design blocks).
+// An off-diagonal tile is written twice, in place and mirrored (the mirrored
+// copy replaces the lower tile, whose old values are not read).  Only design
+// columns are covered, and the mirrored rows are design rows.
+template <bool THREE_MULT, int H, bool XCD, bool SYM = false>
 __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld,
                                                         const int32_t* __restrict__ count,
                                                         const float2* __restrict__ CU,
@@ -516,6 +524,18 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
     bx = local / bpx;
     by = xcd * bpx + local % bpx;
     if (by >= nby) return;
+  }
+  if (SYM) {
+    // row r of the triangle starts at tile r * nby - r (r - 1) / 2
+    const int t = blockIdx.x, nb = nby;
+    auto start = [nb](int r) { return r * nb - r * (r - 1) / 2; };
+    const double b2 = 2.0 * nb + 1.0;
+    int r = (int)((b2 - sqrt(b2 * b2 - 8.0 * t)) * 0.5);
+    r = r < 0 ? 0 : (r > nb - 1 ? nb - 1 : r);
+    while (r > 0 && start(r) > t) --r;
+    while (r < nb - 1 && start(r + 1) <= t) ++r;
+    by = r;
+    bx = r + (t - start(r));
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = by * 64 + (w >> 1) * 32;
@@ -569,13 +589,31 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
     }
     __builtin_amdgcn_sched_barrier(0);
   }
+  float2 out[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
+    out[e] = THREE_MULT ? make_float2(gv[e].x + (X[e] - Y[e]), gv[e].y + (Z[e] - X[e] - Y[e]))
+                        : make_float2(gv[e].x + X[e], gv[e].y + Y[e]);
     const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    if (r >= M) continue;
-    const float2 out = THREE_MULT ? make_float2(gv[e].x + (X[e] - Y[e]), gv[e].y + (Z[e] - X[e] - Y[e]))
-                                  : make_float2(gv[e].x + X[e], gv[e].y + Y[e]);
-    G[(int64_t)r * ld + n] = out;
+    if (r < M) G[(int64_t)r * ld + n] = out[e];
+  }
+  if (SYM && bx != by && n < M) {
+    // mirrored copy: this lane's column n is row n of the lower tile; its values
+    // e = 4k .. 4k+3 are the four consecutive columns m0 + 8k + 4h + (0..3)
+    float2* __restrict__ trow = G + (int64_t)n * ld;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c0 = m0 + 8 * k + 4 * h;
+      if (c0 + 3 < M) {
+        *(f32x4*)(trow + c0) = f32x4{out[4 * k].x, out[4 * k].y, out[4 * k + 1].x, out[4 * k + 1].y};
+        *(f32x4*)(trow + c0 + 2) =
+            f32x4{out[4 * k + 2].x, out[4 * k + 2].y, out[4 * k + 3].x, out[4 * k + 3].y};
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (c0 + i < M) trow[c0 + i] = out[4 * k + i];
+      }
+    }
   }
 }
 
@@ -742,9 +780,9 @@ __global__ __launch_bounds__(512) void k_flush_c64_ws(int M, int R, int64_t ld,
 // eager results to FP32 rounding, tests/test_gpu_deferred.py)
 static const char* const kFlushNames[] = {"w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8",
                                           "w32_pipe8_3m", "w32_pipe8_3m_xcd", "ws8_3m",
-                                          "ws16_3m"};
+                                          "ws16_3m", "sym_pipe8_3m"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
-constexpr int kFlushDefault = 4;
+constexpr int kFlushDefault = 8;
 static std::atomic<int> g_flush_sel{kFlushDefault};
 int flush_variant_count() { return kFlushCount; }
 const char* flush_variant_name(int i) { return i >= 0 && i < kFlushCount ? kFlushNames[i] : nullptr; }
@@ -895,6 +933,13 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         else
           hipLaunchKernelGGL((k_flush_c64_ws<16>), dim3(nwg), dim3(512), 0, s, g.N, g.R, g.ld, count,
                              cu, vv, G, nbx, nby);
+        break;
+      }
+      case 8: {
+        // design-block triangle only (symmetric flush)
+        const int nb = (g.N + 63) / 64;
+        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true>), dim3((unsigned)(nb * (nb + 1) / 2)),
+                           blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G, nb);
         break;
       }
       default: {
