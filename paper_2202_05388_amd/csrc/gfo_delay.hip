@@ -510,7 +510,10 @@ __global__ __launch_bounds__(256) void k_flush_c64_tm(int M, int R, int64_t ld,
 // An off-diagonal tile is written twice, in place and mirrored (the mirrored
 // copy replaces the lower tile, whose old values are not read).  Only design
 // columns are covered, and the mirrored rows are design rows.
-template <bool THREE_MULT, int H, bool XCD, bool SYM = false>
+//
+// NT: G is read and written with non-temporal (streaming) loads and stores;
+// the operand terms, which every workgroup re-reads, keep the normal policy.
+template <bool THREE_MULT, int H, bool XCD, bool SYM = false, bool NT = false>
 __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld,
                                                         const int32_t* __restrict__ count,
                                                         const float2* __restrict__ CU,
@@ -562,7 +565,8 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    gv[e] = G[(int64_t)(r < M ? r : M - 1) * ld + n];
+    const float2* src = G + (int64_t)(r < M ? r : M - 1) * ld + n;
+    gv[e] = NT ? __builtin_bit_cast(float2, __builtin_nontemporal_load((const f32x2*)src)) : *src;
   }
   __builtin_amdgcn_sched_barrier(0);
   f32x16 X, Y, Z;
@@ -595,23 +599,49 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
     out[e] = THREE_MULT ? make_float2(gv[e].x + (X[e] - Y[e]), gv[e].y + (Z[e] - X[e] - Y[e]))
                         : make_float2(gv[e].x + X[e], gv[e].y + Y[e]);
     const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    if (r < M) G[(int64_t)r * ld + n] = out[e];
+    if (r < M) {
+      float2* dst = G + (int64_t)r * ld + n;
+      if (NT)
+        __builtin_nontemporal_store(f32x2{out[e].x, out[e].y}, (f32x2*)dst);
+      else
+        *dst = out[e];
+    }
   }
-  if (SYM && bx != by && n < M) {
-    // mirrored copy: this lane's column n is row n of the lower tile; its values
-    // e = 4k .. 4k+3 are the four consecutive columns m0 + 8k + 4h + (0..3)
-    float2* __restrict__ trow = G + (int64_t)n * ld;
+  if (SYM && bx != by) {
+    // Mirrored copy, transposed through LDS (33-float2 rows against bank
+    // conflicts): lane (h, c) holds column n0 + c of the wave's tile, which is
+    // row n0 + c of the lower tile.  After the transpose, store i of lane l
+    // writes 16 bytes of lower row n0 + 4 i + l / 16 at columns
+    // m0 + 2 (l % 16) and m0 + 2 (l % 16) + 1, so each store covers four whole
+    // 256-byte row segments (the untransposed stores cover 16-byte pieces of
+    // 32 rows, which costs a third more time per byte).
+    __shared__ float2 tsh[SYM ? 4 : 1][32][33];
+    float2 (*T)[33] = tsh[SYM ? w : 0];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int c0 = m0 + 8 * k + 4 * h;
-      if (c0 + 3 < M) {
-        *(f32x4*)(trow + c0) = f32x4{out[4 * k].x, out[4 * k].y, out[4 * k + 1].x, out[4 * k + 1].y};
-        *(f32x4*)(trow + c0 + 2) =
-            f32x4{out[4 * k + 2].x, out[4 * k + 2].y, out[4 * k + 3].x, out[4 * k + 3].y};
-      } else {
+    for (int e = 0; e < 16; ++e) T[8 * (e >> 2) + 4 * h + (e & 3)][lane & 31] = out[e];
+    // only this wave reads its tile: its LDS operations complete in order
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int n0 = n - (lane & 31), rr = 2 * (lane & 15), c = m0 + rr;
+    float2 v0[8], v1[8];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (c0 + i < M) trow[c0 + i] = out[4 * k + i];
+    for (int i = 0; i < 8; ++i) {
+      v0[i] = T[rr][4 * i + (lane >> 4)];
+      v1[i] = T[rr + 1][4 * i + (lane >> 4)];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int nr = n0 + 4 * i + (lane >> 4);
+      float2* __restrict__ p = G + (int64_t)nr * ld + c;
+      if (nr < M && c + 1 < M) {
+        const f32x4 q = f32x4{v0[i].x, v0[i].y, v1[i].x, v1[i].y};
+        if (NT)
+          __builtin_nontemporal_store(q, (f32x4*)p);
+        else
+          *(f32x4*)p = q;
+      } else if (nr < M && c < M) {
+        *p = v0[i];
       }
     }
   }
@@ -780,9 +810,10 @@ __global__ __launch_bounds__(512) void k_flush_c64_ws(int M, int R, int64_t ld,
 // eager results to FP32 rounding, tests/test_gpu_deferred.py)
 static const char* const kFlushNames[] = {"w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8",
                                           "w32_pipe8_3m", "w32_pipe8_3m_xcd", "ws8_3m",
-                                          "ws16_3m", "sym_pipe8_3m"};
+                                          "ws16_3m", "sym_pipe8_3m", "sym_pipe8_3m_nt",
+                                          "sym_pipe4_3m_nt"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
-constexpr int kFlushDefault = 8;
+constexpr int kFlushDefault = 9;
 static std::atomic<int> g_flush_sel{kFlushDefault};
 int flush_variant_count() { return kFlushCount; }
 const char* flush_variant_name(int i) { return i >= 0 && i < kFlushCount ? kFlushNames[i] : nullptr; }
@@ -935,11 +966,21 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
                              cu, vv, G, nbx, nby);
         break;
       }
-      case 8: {
+      case 8:
+      case 9:
+      case 10: {
         // design-block triangle only (symmetric flush)
         const int nb = (g.N + 63) / 64;
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true>), dim3((unsigned)(nb * (nb + 1) / 2)),
-                           blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G, nb);
+        const dim3 tri((unsigned)(nb * (nb + 1) / 2));
+        if (fv == 8)
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true>), tri, blk, 0, s, g.N, g.R, g.ld,
+                             count, cu, vv, G, nb);
+        else if (fv == 9)
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true>), tri, blk, 0, s, g.N, g.R,
+                             g.ld, count, cu, vv, G, nb);
+        else
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 4, false, true, true>), tri, blk, 0, s, g.N, g.R,
+                             g.ld, count, cu, vv, G, nb);
         break;
       }
       default: {
