@@ -85,6 +85,9 @@ typedef struct {
   int32_t* status;              /* 1 int32 device status word (GFO_STATUS_* bits) */
   int32_t delay;                /* 0: eager rank-1 updates; 1..GFO_MAX_DELAY: deferred (see apply_flip) */
   int32_t pending_calls;        /* host counter kept by the library; set 0 before init_G0 */
+  int32_t lower_stale;          /* host flag kept by the library: 1 while the strict lower
+                                   triangle of the design block is out of date (see
+                                   gfo_sync_lower); 0 or 1, set 0 before init_G0 */
 } gfo_state;
 
 /* One selected move.  pixel = -1 is the sentinel "no move improves the FOM". */
@@ -170,11 +173,27 @@ int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick,
  * matrix cores (FP32 for GFO_C64, FP64 for GFO_C128); gfo_flush does the same
  * on demand.  Until then G[0:N, :] holds the base rows only.  refresh_G
  * discards pending terms (it rebuilds G from G0); apply_flips_rank_k flushes
- * first. */
+ * first.
+ * The design block G_D is symmetric at every step (reciprocity of the medium,
+ * and each pending term restricted to it is c v v^T), so in deferred mode the
+ * library reads its entries from the upper triangle (row <= column) only, and
+ * a complex64 flush may bring only that triangle up to date (variant
+ * "up_pipe8_3m_nt", the default); it then sets state.lower_stale.  While
+ * lower_stale is set, every call reads design entries from the upper
+ * triangle, in eager mode too.  gfo_sync_lower copies the upper triangle into
+ * the lower one for callers that read G directly. */
 
 /* gfo_flush - bring the design block of G up to date in deferred mode (no-op
- * when nothing is pending or delay = 0). */
+ * when nothing is pending or delay = 0).  Its lower triangle may be left out
+ * of date (state.lower_stale); gfo_sync_lower completes it. */
 int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
+
+/* gfo_sync_lower - copy the upper triangle of the design block into its strict
+ * lower triangle (G[q, p] = G[p, q] for p < q < N) when state.lower_stale is
+ * set, then clear it; a no-op otherwise.  Pending deferred terms are not
+ * applied (call gfo_flush first for a current matrix).  GFO_C64 only sets the
+ * flag.  Asynchronous on `stream`. */
+int gfo_sync_lower(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 
 /* gfo_greedy_steps - n_steps greedy moves (paper Sec. II: score every
  * one-pixel flip, take the best if it improves the FOM by more than the relative

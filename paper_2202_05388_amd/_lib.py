@@ -27,7 +27,8 @@ EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "g
            "gfo_k1_variant_count", "gfo_k1_variant_name", "gfo_k1_set_variant",
            "gfo_k1_get_variant", "gfo_time_next_k1", "gfo_flush", "gfo_flush_variant_count",
            "gfo_flush_variant_name", "gfo_flush_set_variant", "gfo_flush_get_variant",
-           "gfo_greedy_steps", "gfo_choose_eps_greedy", "score_regions", "gfo_region_pixels")
+           "gfo_greedy_steps", "gfo_choose_eps_greedy", "score_regions", "gfo_region_pixels",
+           "gfo_sync_lower")
 
 
 class Problem(C.Structure):
@@ -42,7 +43,7 @@ class State(C.Structure):
                 ("diag64", C.c_void_p), ("eps_idx", C.c_void_p), ("flips", C.c_void_p),
                 ("flip_cap", C.c_int32), ("n_flips", C.c_void_p), ("kmax", C.c_int32),
                 ("work", C.c_void_p), ("work_bytes", C.c_size_t), ("status", C.c_void_p),
-                ("delay", C.c_int32), ("pending_calls", C.c_int32)]
+                ("delay", C.c_int32), ("pending_calls", C.c_int32), ("lower_stale", C.c_int32)]
 
 
 class Pick(C.Structure):
@@ -80,6 +81,7 @@ def lib():
     L.apply_flips_rank_k.argtypes = [P, S, V, C.c_int32, C.c_int32, V]
     L.refresh_G.argtypes = [P, S, V]
     L.gfo_flush.argtypes = [P, S, V]
+    L.gfo_sync_lower.argtypes = [P, S, V]
     L.gfo_greedy_steps.argtypes = [P, S, C.c_int32, C.c_uint32, C.c_double, V, V]
     L.gfo_choose_eps_greedy.argtypes = [V, C.c_int32, C.c_double, C.c_double, C.c_double, V, V]
     L.score_regions.argtypes = [P, S, C.c_int32, C.c_uint32, C.c_double, V, V]
@@ -149,6 +151,10 @@ def refresh_G(prob, st, stream) -> None:
 
 def flush(prob, st, stream) -> None:
     check(lib().gfo_flush(C.byref(prob), C.byref(st), stream), "gfo_flush")
+
+
+def sync_lower(prob, st, stream) -> None:
+    check(lib().gfo_sync_lower(C.byref(prob), C.byref(st), stream), "gfo_sync_lower")
 
 
 def score_regions(prob, st, region, cand_mask, tau, d_out, stream) -> None:

@@ -49,6 +49,12 @@ Geo make_geo(const gfo_problem* p, int64_t ld) {
   return g;
 }
 
+Geo make_geo(const gfo_problem* p, const gfo_state* st) {
+  Geo g = make_geo(p, st->ldG);
+  g.upper = st->delay > 0 || st->lower_stale ? 1 : 0;
+  return g;
+}
+
 Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   const size_t N = (size_t)p->ny * p->nx, R = N + p->n_mon, K = GFO_MAX_RANK_K;
   const size_t k = kmax > 0 ? ((size_t)kmax + 3) / 4 * 4 : 0;   // padded to the MFMA k-step
@@ -100,6 +106,7 @@ static int validate_state(const gfo_problem* p, const gfo_state* st, Layout* L) 
     return GFO_EINVAL;
   if (st->flip_cap < 0 || (st->flip_cap > 0 && !st->flips) || st->kmax < 0) return GFO_EINVAL;
   if (st->delay < 0 || st->delay > GFO_MAX_DELAY || st->pending_calls < 0) return GFO_EINVAL;
+  if (st->lower_stale != 0 && st->lower_stale != 1) return GFO_EINVAL;
   if (st->ldG < min_ld(p) || st->ldG % 64 != 0) return GFO_EINVAL;
   if (((uintptr_t)st->work & 255) != 0 || ((uintptr_t)st->G & 15) != 0) return GFO_EINVAL;
   *L = make_layout(p, st->ldG, st->kmax);
@@ -159,7 +166,7 @@ int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   if (rc) return rc;
   Layout L;
   if ((rc = validate_state(prob, st, &L))) return rc;
-  const Geo g = make_geo(prob, st->ldG);
+  const Geo g = make_geo(prob, st);
   char* w = (char*)st->work;
   // monitor coordinates travel with the call; wait for the copy so that the
   // caller's host array need not outlive it
@@ -169,6 +176,7 @@ int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   if (launch_init(g, st, L, stream) != hipSuccess) return GFO_EHIP;
   if (launch_dl_reset(g, st, L, stream) != hipSuccess) return GFO_EHIP;
   st->pending_calls = 0;
+  st->lower_stale = 0;
   if (hipStreamSynchronize(stream) != hipSuccess) return GFO_EHIP;
   return GFO_OK;
 }
@@ -183,7 +191,7 @@ int score_candidates(const gfo_problem* prob, const gfo_state* st, uint32_t cand
       !(tau < 1.0))
     return GFO_EINVAL;
   if ((cand_mask & ((1u << prob->n_eps) - 1u)) == 0) return GFO_EINVAL;
-  const Geo g = make_geo(prob, st->ldG);
+  const Geo g = make_geo(prob, st);
   if (launch_score(g, st, L, cand_mask & ((1u << prob->n_eps) - 1u), tau, topk, min_spacing, d_out,
                    stream) != hipSuccess)
     return GFO_EHIP;
@@ -196,7 +204,7 @@ int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick, h
   Layout L;
   if ((rc = validate_state(prob, st, &L))) return rc;
   if (!d_pick) return GFO_EINVAL;
-  const Geo g = make_geo(prob, st->ldG);
+  const Geo g = make_geo(prob, st);
   if (launch_apply(g, st, L, d_pick, stream) != hipSuccess) return GFO_EHIP;
   if (st->delay > 0 && ++st->pending_calls >= st->delay) {
     if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;
@@ -211,9 +219,21 @@ int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   Layout L;
   if ((rc = validate_state(prob, st, &L))) return rc;
   if (st->delay == 0 || st->pending_calls == 0) return GFO_OK;
-  const Geo g = make_geo(prob, st->ldG);
+  const Geo g = make_geo(prob, st);
   if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;
   st->pending_calls = 0;
+  return GFO_OK;
+}
+
+int gfo_sync_lower(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  Layout L;
+  if ((rc = validate_state(prob, st, &L))) return rc;
+  if (!st->lower_stale) return GFO_OK;
+  const Geo g = make_geo(prob, st);
+  if (launch_sync_lower(g, st, stream) != hipSuccess) return GFO_EHIP;
+  st->lower_stale = 0;
   return GFO_OK;
 }
 
@@ -227,7 +247,7 @@ int gfo_greedy_steps(const gfo_problem* prob, gfo_state* st, int32_t n_steps, ui
   const uint32_t mask = cand_mask & ((1u << prob->n_eps) - 1u);
   if (mask == 0) return GFO_EINVAL;
   if (n_steps == 0) return GFO_OK;
-  const Geo g = make_geo(prob, st->ldG);
+  const Geo g = make_geo(prob, st);
   gfo_pick* internal = (gfo_pick*)((char*)st->work + L.picks);
   const bool fused = st->delay > 0 && (g.N + kScoreThreads - 1) / kScoreThreads <= kScoreMaxBlocks;
   if (!fused) {
@@ -282,7 +302,7 @@ int score_regions(const gfo_problem* prob, const gfo_state* st, int32_t region,
   if (!d_out || !(tau >= 0.0) || !(tau < 1.0)) return GFO_EINVAL;
   const uint32_t mask = cand_mask & ((1u << prob->n_eps) - 1u);
   if (mask == 0) return GFO_EINVAL;
-  const Geo g = make_geo(prob, st->ldG);
+  const Geo g = make_geo(prob, st);
   if (launch_score_regions(g, st, L, mask, tau, d_out, stream) != hipSuccess) return GFO_EHIP;
   return GFO_OK;
 }
@@ -295,7 +315,7 @@ int gfo_region_pixels(const gfo_problem* prob, const gfo_state* st, int32_t regi
   if ((rc = validate_state(prob, st, &L))) return rc;
   if ((rc = validate_regions(prob, region))) return rc;
   if (!d_region || !d_pixels) return GFO_EINVAL;
-  const Geo g = make_geo(prob, st->ldG);
+  const Geo g = make_geo(prob, st);
   if (launch_region_pixels(g, st, d_region, d_pixels, stream) != hipSuccess) return GFO_EHIP;
   return GFO_OK;
 }
@@ -319,7 +339,7 @@ int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d
   if (!d_picks || k < 1 || k > GFO_MAX_RANK_K || prob->dtype != GFO_C64 ||
       (gemm_precision != GFO_FP32 && gemm_precision != GFO_BF16))
     return GFO_EINVAL;
-  const Geo g = make_geo(prob, st->ldG);
+  const Geo g = make_geo(prob, st);
   if (st->delay > 0 && st->pending_calls > 0) {
     if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;
     st->pending_calls = 0;
@@ -333,10 +353,12 @@ int refresh_G(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   if (rc) return rc;
   Layout L;
   if ((rc = validate_state(prob, st, &L))) return rc;
-  const Geo g = make_geo(prob, st->ldG);
+  const Geo g = make_geo(prob, st);
   if (launch_dl_reset(g, st, L, stream) != hipSuccess) return GFO_EHIP;   // pending terms discarded
   st->pending_calls = 0;
-  return launch_refresh(g, st, L, stream);
+  rc = launch_refresh(g, st, L, stream);
+  if (rc == GFO_OK) st->lower_stale = 0;                 // every entry rebuilt
+  return rc;
 }
 
 // Autotuner hooks: variants of the streaming rank-1 kernel.

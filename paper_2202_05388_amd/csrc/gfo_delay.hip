@@ -100,7 +100,7 @@ __device__ __forceinline__ void gather_finish(const Geo& g, const gfo_pick pk,
   const int cur = eps_idx[jc];
   const double2 dj = diag64[jc];
   const T Ej = E[jc];
-  const T base = col ? G[i * g.ld + jc] : G[(int64_t)jc * g.ld + q];
+  const T base = col ? G[g_at(g, i, jc)] : G[g_at(g, jc, q)];
   T b[kGatherBatch];
 #pragma unroll
   for (int k = 0; k < kGatherBatch; ++k)
@@ -484,6 +484,19 @@ __global__ __launch_bounds__(256) void k_flush_c64_tm(int M, int R, int64_t ld,
   }
 }
 
+// Tile t (row-major) of the triangle of nb x nb tiles on and above the
+// diagonal: row r starts at tile r nb - r (r - 1) / 2.
+__device__ __forceinline__ void tri_tile(int t, int nb, int& r, int& c) {
+  auto start = [nb](int i) { return i * nb - i * (i - 1) / 2; };
+  const double b2 = 2.0 * nb + 1.0;
+  int i = (int)((b2 - sqrt(b2 * b2 - 8.0 * t)) * 0.5);
+  i = i < 0 ? 0 : (i > nb - 1 ? nb - 1 : i);
+  while (i > 0 && start(i) > t) --i;
+  while (i < nb - 1 && start(i + 1) <= t) ++i;
+  r = i;
+  c = i + (t - start(i));
+}
+
 // Software-pipelined flush, 32 x 32 outputs per wave and 64 x 64 per workgroup.
 // The CU and V operands come through buffer loads whose range ends at the
 // pending count, so slots past it (and rows past the end, given an offset
@@ -513,7 +526,13 @@ __global__ __launch_bounds__(256) void k_flush_c64_tm(int M, int R, int64_t ld,
 //
 // NT: G is read and written with non-temporal (streaming) loads and stores;
 // the operand terms, which every workgroup re-reads, keep the normal policy.
-template <bool THREE_MULT, int H, bool XCD, bool SYM = false, bool NT = false>
+//
+// MIRROR = false (with SYM): the upper triangle alone is brought up to date;
+// the lower tiles are left as they are (the caller records that the lower
+// triangle is out of date, and readers take design entries from the upper
+// one).  Diagonal tiles are computed whole, their lower halves from the old
+// values.
+template <bool THREE_MULT, int H, bool XCD, bool SYM = false, bool NT = false, bool MIRROR = true>
 __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld,
                                                         const int32_t* __restrict__ count,
                                                         const float2* __restrict__ CU,
@@ -528,18 +547,7 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
     by = xcd * bpx + local % bpx;
     if (by >= nby) return;
   }
-  if (SYM) {
-    // row r of the triangle starts at tile r * nby - r (r - 1) / 2
-    const int t = blockIdx.x, nb = nby;
-    auto start = [nb](int r) { return r * nb - r * (r - 1) / 2; };
-    const double b2 = 2.0 * nb + 1.0;
-    int r = (int)((b2 - sqrt(b2 * b2 - 8.0 * t)) * 0.5);
-    r = r < 0 ? 0 : (r > nb - 1 ? nb - 1 : r);
-    while (r > 0 && start(r) > t) --r;
-    while (r < nb - 1 && start(r + 1) <= t) ++r;
-    by = r;
-    bx = r + (t - start(r));
-  }
+  if (SYM) tri_tile((int)blockIdx.x, nby, by, bx);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = by * 64 + (w >> 1) * 32;
   const int n = bx * 64 + (w & 1) * 32 + (lane & 31);
@@ -607,7 +615,7 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
         *dst = out[e];
     }
   }
-  if (SYM && bx != by) {
+  if (SYM && MIRROR && bx != by) {
     // Mirrored copy, transposed through LDS (33-float2 rows against bank
     // conflicts): lane (h, c) holds column n0 + c of the wave's tile, which is
     // row n0 + c of the lower tile.  After the transpose, store i of lane l
@@ -811,9 +819,9 @@ __global__ __launch_bounds__(512) void k_flush_c64_ws(int M, int R, int64_t ld,
 static const char* const kFlushNames[] = {"w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8",
                                           "w32_pipe8_3m", "w32_pipe8_3m_xcd", "ws8_3m",
                                           "ws16_3m", "sym_pipe8_3m", "sym_pipe8_3m_nt",
-                                          "sym_pipe4_3m_nt"};
+                                          "sym_pipe4_3m_nt", "up_pipe8_3m_nt"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
-constexpr int kFlushDefault = 9;
+constexpr int kFlushDefault = 11;
 static std::atomic<int> g_flush_sel{kFlushDefault};
 int flush_variant_count() { return kFlushCount; }
 const char* flush_variant_name(int i) { return i >= 0 && i < kFlushCount ? kFlushNames[i] : nullptr; }
@@ -983,6 +991,15 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
                              g.ld, count, cu, vv, G, nb);
         break;
       }
+      case 11: {
+        // upper triangle only; the lower one is out of date from here on
+        const int nb = (g.N + 63) / 64;
+        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false>),
+                           dim3((unsigned)(nb * (nb + 1) / 2)), blk, 0, s, g.N, g.R, g.ld, count, cu, vv,
+                           G, nb);
+        st->lower_stale = 1;
+        break;
+      }
       default: {
         const unsigned nby = grid.y, bpx = (nby + 7) / 8;
         hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true>), dim3(8 * bpx * grid.x), blk, 0, s, g.N,
@@ -999,6 +1016,39 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
   if (e != hipSuccess) return e;
   if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
   hipLaunchKernelGGL(k_dl_reset, dim3(1), dim3(64), 0, s, (int32_t*)(w + L.dl_hdr));
+  return hipGetLastError();
+}
+
+// Upper triangle of the design block copied into its strict lower triangle:
+// workgroup t takes 32 x 32 tile (by, bx) on or above the diagonal (tri_tile
+// order), reads it row by row into LDS and writes its transpose into tile
+// (bx, by) row by row (on diagonal tiles only below the diagonal).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sync_lower(int N, int64_t ld, T* __restrict__ G, int nb) {
+  __shared__ T tile[32][33];
+  int by, bx;
+  tri_tile((int)blockIdx.x, nb, by, bx);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = by * 32 + ty + 8 * k, c = bx * 32 + tx;
+    if (r < N && c < N) tile[ty + 8 * k][tx] = G[(int64_t)r * ld + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int lr = ty + 8 * k, row = bx * 32 + lr, col = by * 32 + tx;
+    if (row < N && col < N && (bx != by || lr > tx)) G[(int64_t)row * ld + col] = tile[tx][lr];
+  }
+}
+
+hipError_t launch_sync_lower(const Geo& g, gfo_state* st, hipStream_t s) {
+  const int nb = (g.N + 31) / 32;
+  const dim3 grid((unsigned)((int64_t)nb * (nb + 1) / 2));
+  if (g.dtype == GFO_C64)
+    hipLaunchKernelGGL(k_sync_lower<float2>, grid, dim3(256), 0, s, g.N, g.ld, (float2*)st->G, nb);
+  else
+    hipLaunchKernelGGL(k_sync_lower<double2>, grid, dim3(256), 0, s, g.N, g.ld, (double2*)st->G, nb);
   return hipGetLastError();
 }
 

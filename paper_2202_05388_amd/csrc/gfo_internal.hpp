@@ -18,7 +18,17 @@ struct Geo {
   double eps[GFO_MAX_EPS];
   int n_eps, bg_idx, m0;
   int dtype;
+  // 1: entries of the design block are read from its upper triangle (row <=
+  // column).  The block is symmetric (reciprocity of the medium), and in
+  // deferred mode a flush may bring only the upper triangle up to date.
+  int upper;
 };
+
+// Offset of entry (p, q) of G; design-block entries (p, q < N) come from the
+// upper triangle when g.upper.
+__device__ __forceinline__ int64_t g_at(const Geo& g, int64_t p, int64_t q) {
+  return g.upper && p > q && p < g.N ? q * g.ld + p : p * g.ld + q;
+}
 
 // ------------------------------------------------------------------ complex FP64
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -249,6 +259,8 @@ __device__ inline gfo_pick greedy_pick_block(const Geo& g, double fom,
 
 Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax);
 Geo make_geo(const gfo_problem* p, int64_t ld);
+// make_geo for a job: upper = deferred mode or an out-of-date lower triangle
+Geo make_geo(const gfo_problem* p, const gfo_state* st);
 int validate_problem(const gfo_problem* p);
 int find_bg(const gfo_problem* p);
 
@@ -264,6 +276,7 @@ hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo
                          int k, int precision, hipStream_t s);
 int launch_refresh(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
 hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
+hipError_t launch_sync_lower(const Geo& g, gfo_state* st, hipStream_t s);
 template <typename T>
 hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* pick,
                                  hipStream_t s);

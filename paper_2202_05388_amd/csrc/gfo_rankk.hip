@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void k_rk_prepare(Geo g, const gfo_pick* __res
     const int a = idx / (2 * s), b = idx - (idx / (2 * s)) * 2 * s;
     double2 v;
     if (b < s) {
-      const double2 gab = (a == b) ? diag64[S[a]] : St<T>::to_d(G[(int64_t)S[a] * g.ld + S[b]]);
+      const double2 gab = (a == b) ? diag64[S[a]] : St<T>::to_d(G[g_at(g, S[a], S[b])]);
       v = make_double2((a == b ? 1.0 : 0.0) - al[a] * gab.x, -al[a] * gab.y);
     } else {
       v = make_double2(b - s == a ? al[a] : 0.0, 0.0);
@@ -169,7 +169,7 @@ __global__ void k_rk_rows(Geo g, const RkHdr* __restrict__ hdr, const T* __restr
     double2 u = make_double2(0.0, 0.0);
     if (a < s) {
       const int c = hdr->S[a];
-      u = (r == c) ? diag64[r] : St<T>::to_d(G[(int64_t)r * g.ld + c]);
+      u = (r == c) ? diag64[r] : St<T>::to_d(G[g_at(g, r, c)]);
       acc = cadd(acc, cmul(u, hdr->y[a]));
     }
     U64[(int64_t)r * KR + a] = u;
@@ -203,7 +203,7 @@ __global__ void k_rk_cols(Geo g, const RkHdr* __restrict__ hdr, const double2* _
     gs[b] = make_double2(0.0, 0.0);
     if (b < s && q < g.N) {
       const int c = hdr->S[b];
-      gs[b] = (q == c) ? diag64[c] : St<T>::to_d(G[(int64_t)c * g.ld + q]);
+      gs[b] = (q == c) ? diag64[c] : St<T>::to_d(G[g_at(g, c, q)]);
     }
   }
   double2 dsum = make_double2(0.0, 0.0);

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_regions(
       gm[i] = St<T>::to_d(grow[V[i]]);
 #pragma unroll
       for (int j = 0; j < kRegionPix; ++j)
-        Gvv[i][j] = i == j ? diag64[V[i]] : St<T>::to_d(G[(int64_t)V[i] * g.ld + V[j]]);
+        Gvv[i][j] = i == j ? diag64[V[i]] : St<T>::to_d(G[g_at(g, V[i], V[j])]);
     }
     const int K = count ? *count : 0;
     for (int s = 0; s < K; ++s) {

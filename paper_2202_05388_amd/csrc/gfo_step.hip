@@ -216,14 +216,14 @@ __global__ void k_gather(Geo g, const Snap* __restrict__ snap, const T* __restri
   const double2 c = snap->c;
   double2 cu_d = make_double2(0.0, 0.0);
   if (i < g.R) {
-    const double2 u = (i == j) ? snap->dj : St<T>::to_d(G[i * g.ld + j]);
+    const double2 u = (i == j) ? snap->dj : St<T>::to_d(G[g_at(g, i, j)]);
     cu_d = cmul(c, u);
     cu[i] = St<T>::from_d(cu_d);
     E[i] = St<T>::from_d(cadd(St<T>::to_d(E[i]), cmul(cu_d, snap->Ej)));
   }
   if (i < g.ld) {
     if (i < g.N) {
-      const T vi = G[(int64_t)j * g.ld + i];
+      const T vi = G[g_at(g, j, i)];
       v[i] = vi;
       if (i == j) {
         const double2 d = snap->dj;

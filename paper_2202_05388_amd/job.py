@@ -64,7 +64,7 @@ class Job:
             eps_idx=self.eps_idx.data_ptr(), flips=self.flips.data_ptr(), flip_cap=self.flip_cap,
             n_flips=self.counters.data_ptr(), kmax=self.kmax, work=self.work.data_ptr(),
             work_bytes=work_bytes, status=self.counters.data_ptr() + 4, delay=int(delay),
-            pending_calls=0)
+            pending_calls=0, lower_stale=0)
         self.delay = int(delay)
         self.steps_issued = 0
 
@@ -91,8 +91,14 @@ class Job:
         L.refresh_G(self.prob, self.state, _stream_handle(stream))
 
     def flush(self, stream=None):
-        """Deferred mode: bring the design block of G up to date (no-op otherwise)."""
+        """Deferred mode: bring the design block of G up to date (no-op otherwise);
+        its lower triangle may stay out of date (see sync_lower)."""
         L.flush(self.prob, self.state, _stream_handle(stream))
+
+    def sync_lower(self, stream=None):
+        """Copy the upper triangle of the design block into the lower one if a
+        flush left the lower one out of date."""
+        L.sync_lower(self.prob, self.state, _stream_handle(stream))
 
     def step(self, stream=None):
         """One greedy step: score + select + rank-1 apply, no host synchronisation."""
@@ -215,8 +221,10 @@ class Job:
         return raw.view(torch.float64).cpu().numpy().reshape(self.N, len(self._eps))
 
     def host_state(self):
-        """(G[:, :N], E, diag64, eps_idx) copied to host numpy, complex128 (flushes first)."""
+        """(G[:, :N], E, diag64, eps_idx) copied to host numpy, complex128 (flushes
+        and completes the lower triangle first)."""
         self.flush()
+        self.sync_lower()
         torch.cuda.synchronize(self.device)
         G = self.G[:, : self.N].cpu().to(torch.complex128).numpy()
         return (G, self.E.cpu().to(torch.complex128).numpy(), self.diag64.cpu().numpy(),
@@ -232,6 +240,7 @@ class Job:
         self.diag64.copy_(torch.from_numpy(np.asarray(diag, np.complex128)))
         self.eps_idx.copy_(torch.from_numpy(np.asarray(eps_idx, np.uint8)))
         torch.cuda.synchronize(self.device)
+        self.state.lower_stale = 0                    # the whole matrix was written
 
     def set_pick(self, pixel, eps_idx, slot=0):
         rec = L.Pick(pixel=pixel, eps_idx=eps_idx, fom_new=0.0, dfom=0.0)

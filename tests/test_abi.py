@@ -47,9 +47,10 @@ def test_struct_layouts_match_header():
     # x86-64 SysV layout of the structs in include/gfo.h
     assert C.sizeof(L.Problem) == 64
     assert L.Problem.h_mon_xy.offset == 40 and L.Problem.h_eps_table.offset == 56
-    assert C.sizeof(L.State) == 104
+    assert C.sizeof(L.State) == 112
     assert L.State.work.offset == 72 and L.State.status.offset == 88
     assert L.State.delay.offset == 96 and L.State.pending_calls.offset == 100
+    assert L.State.lower_stale.offset == 104
     assert C.sizeof(L.Pick) == 24
 
 
@@ -117,8 +118,8 @@ def test_k1_variants_listed():
     assert L.lib().gfo_k1_set_variant(L.GFO_C64, 999) == L.GFO_EINVAL
     assert L.flush_variants() == ["w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8", "w32_pipe8_3m",
                                   "w32_pipe8_3m_xcd", "ws8_3m", "ws16_3m", "sym_pipe8_3m",
-                                  "sym_pipe8_3m_nt", "sym_pipe4_3m_nt"]
-    assert L.flush_get_variant() == 9
+                                  "sym_pipe8_3m_nt", "sym_pipe4_3m_nt", "up_pipe8_3m_nt"]
+    assert L.flush_get_variant() == 11
     assert L.lib().gfo_strerror(L.GFO_ENOSPC) == b"workspace too small"
 
 
@@ -150,3 +151,18 @@ def test_region_calls_reject_bad_region_on_host():
                   flip_cap=16, n_flips=fake, kmax=0, work=fake, work_bytes=L.workspace_size(pr2, 0),
                   status=fake, delay=0, pending_calls=0)
     assert lib.score_regions(C.byref(pr2), C.byref(st2), 2, 3, 1e-9, out, None) == L.GFO_EINVAL
+
+
+def test_sync_lower_validates_and_is_a_no_op_when_current():
+    """gfo_sync_lower refuses a flag other than 0 or 1 and launches nothing when
+    the lower triangle is current (the pointers here are never dereferenced)."""
+    lib = L.lib()
+    pr, keep = _problem(W.tiny(8, 8, n_mon=4))
+    fake = 1 << 20
+    st = L.State(G=fake, ldG=L.min_ld(pr), E=fake, diag64=fake, eps_idx=fake, flips=fake,
+                 flip_cap=16, n_flips=fake, kmax=0, work=fake, work_bytes=L.workspace_size(pr, 0),
+                 status=fake, delay=16, pending_calls=0, lower_stale=0)
+    assert lib.gfo_sync_lower(C.byref(pr), C.byref(st), None) == L.GFO_OK
+    st.lower_stale = 2
+    assert lib.gfo_sync_lower(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
+    assert lib.gfo_flush(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL

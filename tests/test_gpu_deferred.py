@@ -204,3 +204,63 @@ def test_greedy_steps_picks_record_and_stop():
     Gd, Ed = ost.dense_state(p, ost.eps_of(p, job.eps_idx.cpu().numpy()))
     G, E, _, _ = job.host_state()
     assert _rel(G, Gd) <= 1e-11 and _rel(E, Ed) <= 1e-11
+
+
+def test_upper_only_flush_then_sync_lower():
+    """The default complex64 flush brings only the upper triangle of the design
+    block up to date and marks the lower one out of date.  The moves are those
+    of eager mode, the upper triangle and the monitor rows match eager G, and
+    gfo_sync_lower then makes the whole block match (lower = upper exactly)."""
+    import torch
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(40, 44, n_mon=8, dtype="c64", cand_mask=W.MASK_BOTH)
+    eager = _job(p)
+    eager.init()
+    n_ref = eager.run_greedy(150, poll_every=25)
+    Ge, Ee, de, ie = eager.host_state()
+    assert L.flush_variants()[L.flush_get_variant()] == "up_pipe8_3m_nt"
+    job = _job(p, delay=64)
+    job.init()
+    assert job.state.lower_stale == 0
+    assert job.run_greedy(150, poll_every=25) == n_ref
+    assert np.array_equal(job.history(), eager.history())
+    job.flush()
+    assert job.state.lower_stale == 1
+    torch.cuda.synchronize()
+    N = p.n
+    G = job.G[:, :N].cpu().to(torch.complex128).numpy()
+    iu, il = np.triu_indices(N), np.tril_indices(N, -1)
+    D, De = G[:N], Ge[:N]
+    assert _rel(D[iu], De[iu]) <= 3e-6
+    assert _rel(D[il], De[il]) > 1e-3              # the lower triangle was left behind
+    assert _rel(G[N:], Ge[N:]) <= 3e-6             # monitor rows are current
+    job.sync_lower()
+    assert job.state.lower_stale == 0
+    G2, E2, d2, i2 = job.host_state()
+    D2 = G2[:N]
+    assert np.array_equal(D2[iu], D[iu]) and np.array_equal(D2[il], D2.T[il])
+    assert _rel(G2, Ge) <= 3e-6 and _rel(E2, Ee) <= 3e-6 and np.array_equal(i2, ie)
+    job.sync_lower()                                # current: a no-op
+    assert np.array_equal(job.host_state()[0], G2)
+
+
+def test_eager_moves_after_an_upper_only_flush():
+    """A job switched to eager updates while its lower triangle is out of date
+    reads design entries from the upper triangle: same moves and state as a job
+    that was eager throughout."""
+    p = W.tiny(40, 44, n_mon=8, dtype="c64", cand_mask=W.MASK_BOTH)
+    ref = _job(p)
+    ref.init()
+    assert ref.run_greedy(80, poll_every=16) == 80
+    job = _job(p, delay=16)
+    job.init()
+    assert job.run_greedy(48, poll_every=16) == 48
+    assert job.state.pending_calls == 0 and job.state.lower_stale == 1
+    job.delay = 0
+    job.state.delay = 0
+    assert job.run_greedy(32, poll_every=16) == 32
+    assert job.state.lower_stale == 1
+    assert np.array_equal(job.history(), ref.history())
+    G, E, d, i = job.host_state()
+    Gr, Er, dr, ir = ref.host_state()
+    assert _rel(G, Gr) <= 3e-6 and _rel(E, Er) <= 3e-6 and np.array_equal(i, ir)

@@ -82,12 +82,16 @@ def test_region_greedy_deferred_equals_eager(dtype, delay):
     assert np.linalg.norm(Eb - Ed) <= (1e-11 if dtype == "c128" else 2e-5) * np.linalg.norm(Ed)
 
 
-def test_region_rank_k_application_equals_sequential():
+@pytest.mark.parametrize("delay", [0, 16])
+def test_region_rank_k_application_equals_sequential(delay):
+    """Joint rank-k application of the region moves equals the pixel moves one by
+    one; with delay > 0 the rank-k step follows flushes that leave the lower
+    triangle of the design block out of date, so it reads the upper one."""
     p = _lens(24, dtype="c64")
     a = _job(p)
     a.init()
     na, ma = a.run_region_greedy(300, poll_every=16, apply="sequential")
-    b = _job(p)
+    b = _job(p, delay=delay)
     b.init()
     nb, mb = b.run_region_greedy(300, poll_every=16, apply="rank_k")
     assert ma == mb and na >= 10
