@@ -166,12 +166,13 @@ int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick,
 /* Deferred mode (state.delay = r > 0).  The paper's update (eq. form10) is
  * exact in any grouping, so apply_flip may postpone the design block: it
  * records c G[:, j] and G[j, :] of the CURRENT matrix (base rows plus the
- * pending terms) as pending term number s, and updates E, diag64 and the
- * monitor rows of G at once.  score_candidates reads only those, so the move
- * sequence is the one of eager mode.  After r apply_flip calls since the last
- * flush, the design block is brought up to date by one rank-r product on the
- * matrix cores (FP32 for GFO_C64, FP64 for GFO_C128); gfo_flush does the same
- * on demand.  Until then G[0:N, :] holds the base rows only.  refresh_G
+ * pending terms) as pending term number s, and updates E, diag64 and the FOM
+ * monitor's row of G at once.  score_candidates reads only those, so the move
+ * sequence is the one of eager mode.  After r apply_flip calls since the
+ * last flush, the design block and the other monitor rows are brought up to
+ * date by one rank-r product on the matrix cores (FP32 for GFO_C64, FP64 for
+ * GFO_C128); gfo_flush does the same on demand.  Until then those rows hold
+ * their base values only.  refresh_G
  * discards pending terms (it rebuilds G from G0); apply_flips_rank_k flushes
  * first.
  * The design block G_D is symmetric at every step (reciprocity of the medium,
@@ -191,8 +192,8 @@ int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 /* gfo_sync_lower - copy the upper triangle of the design block into its strict
  * lower triangle (G[q, p] = G[p, q] for p < q < N) when state.lower_stale is
  * set, then clear it; a no-op otherwise.  Pending deferred terms are not
- * applied (call gfo_flush first for a current matrix).  GFO_C64 only sets the
- * flag.  Asynchronous on `stream`. */
+ * applied (call gfo_flush first for a current matrix).  Only complex64
+ * flushes set the flag.  Asynchronous on `stream`. */
 int gfo_sync_lower(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 
 /* gfo_greedy_steps - n_steps greedy moves (paper Sec. II: score every

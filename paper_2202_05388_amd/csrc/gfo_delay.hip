@@ -110,8 +110,10 @@ __device__ __forceinline__ void gather_finish(const Geo& g, const gfo_pick pk,
   const int j = __builtin_amdgcn_readfirstlane(sn.j);
   if (j < 0 || t >= g.R + g.ld) return;
   const int slot = cnt;
-  // the terms of a design entry (column i < N, or row entry q < N, not the pivot)
-  const bool terms = col ? (i < g.N && i != j) : (q < g.N && q != j);
+  // the terms of an entry: design entries other than the pivot, and the
+  // monitor rows except the FOM monitor's, which is kept current move by move
+  const int64_t mrow = (int64_t)g.N + g.m0;
+  const bool terms = col ? (i != j && i != mrow) : (q < g.N && q != j);
   double2 acc = make_double2(0.0, 0.0);
   if (terms) {
 #pragma unroll
@@ -135,10 +137,11 @@ __device__ __forceinline__ void gather_finish(const Geo& g, const gfo_pick pk,
   if (col) {
     double2 u;
     if (i == j) u = sn.dj;
-    else if (i < g.N) u = cadd(St<T>::to_d(base), acc);
-    else u = St<T>::to_d(base);                   // monitor rows: current, no pending terms
+    else if (i != mrow) u = cadd(St<T>::to_d(base), acc);
+    else u = St<T>::to_d(base);                   // FOM monitor row: current
     const T cu = St<T>::from_d(cmul(sn.c, u));
-    CUs[(int64_t)slot * g.R + i] = cu;
+    // the FOM monitor row takes no term at the flush (it already has this one)
+    CUs[(int64_t)slot * g.R + i] = i == mrow ? St<T>::from_d(make_double2(0.0, 0.0)) : cu;
     cu_out[i] = cu;
     if (i >= g.N) emon[i - g.N] = axpy_st<T>(E[i], cu, sn.Ej);
   } else {
@@ -187,18 +190,19 @@ __global__ __launch_bounds__(256) void k_select_gather(
 // The move's elementwise part for one index q (design pixel or monitor row):
 // E_q += cu_q E_j (the monitor fields are taken from emon, computed by the
 // gather with the same expression), diag64 (q != j: += cu_q v_q; q = j:
-// d_j / (1 - alpha d_j)) and eps_idx[j]; the monitor rows G[N+m, q] +=
-// cu[N+m] v_q.  Shared by the per-call path and the fused greedy loop.
+// d_j / (1 - alpha d_j)) and eps_idx[j]; the FOM monitor row G[N+m0, q] +=
+// cu[N+m0] v_q (the scores read it; the other monitor rows take their pending
+// terms at the flush, like the design block).  Shared by the per-call path and
+// the fused greedy loop.
 template <typename T>
 __device__ __forceinline__ void elementwise_move(const Geo& g, const Snap& sn, int64_t q,
                                                  const T* __restrict__ cu,
                                                  const T* __restrict__ v,
                                                  const T* __restrict__ emon, T* __restrict__ G,
                                                  T* __restrict__ E, double2* __restrict__ diag64,
-                                                 uint8_t* __restrict__ eps_idx, int m_begin,
-                                                 int m_step) {
+                                                 uint8_t* __restrict__ eps_idx) {
   const int j = sn.j;
-  if (m_begin == 0) {
+  {
     if (q < g.N) {
       E[q] = axpy_st<T>(E[q], cu[q], sn.Ej);
       if (q == j) {
@@ -213,11 +217,8 @@ __device__ __forceinline__ void elementwise_move(const Geo& g, const Snap& sn, i
     }
   }
   if (q >= g.ld) return;
-  const double2 vq = St<T>::to_d(v[q]);
-  for (int m = m_begin; m < g.nmon; m += m_step) {
-    T* p = G + (int64_t)(g.N + m) * g.ld + q;
-    *p = axpy_st<T>(*p, cu[g.N + m], vq);
-  }
+  T* p = G + (int64_t)(g.N + g.m0) * g.ld + q;
+  *p = axpy_st<T>(*p, cu[g.N + g.m0], St<T>::to_d(v[q]));
 }
 
 // Bookkeeping of an applied move (history, move counter, pending-term count).
@@ -236,8 +237,7 @@ __device__ __forceinline__ void record_move(const Snap& sn, int32_t* __restrict_
   *count = sn.slot + 1;
 }
 
-// Applies the move's elementwise part.  Grid x covers max(R, ld); y walks the
-// monitor rows.
+// Applies the move's elementwise part.  Grid x covers max(R, ld).
 template <typename T>
 __global__ void k_mon_dl(Geo g, const Snap* __restrict__ snap, const T* __restrict__ cu,
                          const T* __restrict__ v, const T* __restrict__ emon, T* __restrict__ G,
@@ -248,24 +248,19 @@ __global__ void k_mon_dl(Geo g, const Snap* __restrict__ snap, const T* __restri
   const Snap sn = *snap;
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (sn.j < 0) {
-    if (q == 0 && blockIdx.y == 0 && sn.pad1) atomicOr(status, GFO_STATUS_SINGULAR);
+    if (q == 0 && sn.pad1) atomicOr(status, GFO_STATUS_SINGULAR);
     return;
   }
-  if (q == 0 && blockIdx.y == 0) record_move(sn, flips, flip_cap, n_flips, status, count);
-  elementwise_move<T>(g, sn, q, cu, v, emon, G, E, diag64, eps_idx, blockIdx.y, gridDim.y);
+  if (q == 0) record_move(sn, flips, flip_cap, n_flips, status, count);
+  elementwise_move<T>(g, sn, q, cu, v, emon, G, E, diag64, eps_idx);
 }
 
-// Monitor rows other than m0 handled by one workgroup row of k_mon_score.
-constexpr int kMonRowsPerBlock = 16;
-
-// Fused greedy loop, first kernel of a move.  Grid x covers max(R, ld) indices q;
-// grid y = 1 + ceil((nmon - 1) / kMonRowsPerBlock).
-//   y = 0: the previous move's elementwise part for index q (if apply_prev) and
-//     then the scores of pixel q (workgroup b covers pixels [256 b, 256 b + 256)
-//     and writes partial[b] for b < nblk).  Thread q updates exactly the values
-//     it then scores with (E_q, diag64[q], eps_idx[q], G[N+m0, q]) and scores
-//     from registers; E at the FOM monitor comes from emon.
-//   y > 0: the update of a group of the other monitor rows, column q.
+// Fused greedy loop, first kernel of a move.  Grid x covers max(R, ld) indices
+// q: the previous move's elementwise part for index q (if apply_prev) and then
+// the scores of pixel q (workgroup b covers pixels [256 b, 256 b + 256) and
+// writes partial[b] for b < nblk).  Thread q updates exactly the values it then
+// scores with (E_q, diag64[q], eps_idx[q], G[N+m0, q]) and scores from
+// registers; E at the FOM monitor comes from emon.
 // The expressions are those of k_mon_dl and k_score, so the state and the scores
 // are bit for bit those of the per-call path.
 template <typename T>
@@ -283,27 +278,6 @@ __global__ __launch_bounds__(kScoreThreads) void k_mon_score(
   sn.j = -1;
   if (apply_prev) sn = *snap;
   const bool moved = sn.j >= 0;
-  if (blockIdx.y > 0) {
-    // rows m != m0, group blockIdx.y - 1: all loads, then all stores
-    if (!moved || q >= g.ld) return;
-    const int r0 = ((int)blockIdx.y - 1) * kMonRowsPerBlock;
-    T x[kMonRowsPerBlock], c[kMonRowsPerBlock];
-#pragma unroll
-    for (int k = 0; k < kMonRowsPerBlock; ++k) {
-      const int r = r0 + k, m = r < g.m0 ? r : r + 1;
-      if (m < g.nmon) {
-        x[k] = G[(int64_t)(g.N + m) * g.ld + q];
-        c[k] = cu[g.N + m];
-      }
-    }
-    const double2 vd = St<T>::to_d(v[q]);
-#pragma unroll
-    for (int k = 0; k < kMonRowsPerBlock; ++k) {
-      const int r = r0 + k, m = r < g.m0 ? r : r + 1;
-      if (m < g.nmon) G[(int64_t)(g.N + m) * g.ld + q] = axpy_st<T>(x[k], c[k], vd);
-    }
-    return;
-  }
   if (!moved && apply_prev && q == 0 && sn.pad1) atomicOr(status, GFO_STATUS_SINGULAR);
   if (moved && q == 0) record_move(sn, flips, flip_cap, n_flips, status, count);
   const double2 Em0 = St<T>::to_d(moved ? emon[g.m0] : E[g.N + g.m0]);
@@ -414,11 +388,11 @@ __global__ __launch_bounds__(256) void k_flush_c64_tm(int M, int R, int64_t ld,
                                                       const int32_t* __restrict__ count,
                                                       const float2* __restrict__ CU,
                                                       const float2* __restrict__ V,
-                                                      float2* __restrict__ G) {
+                                                      float2* __restrict__ G, int row0) {
   const int K = *count;
   if (K == 0) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * (64 * TM) + (w >> 1) * (32 * TM);
+  const int m0 = row0 + blockIdx.y * (64 * TM) + (w >> 1) * (32 * TM);
   const int n = blockIdx.x * 64 + (w & 1) * 32 + (lane & 31);
   const int h = lane >> 5;
   f32x16 X[TM], Y[TM], Z[TM];
@@ -862,8 +836,7 @@ template <typename T>
 hipError_t launch_fused_finish(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {
   char* w = (char*)st->work;
   const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
-  dim3 gm((unsigned)((nx + 255) / 256), (unsigned)(g.nmon < 65535 ? g.nmon : 65535));
-  hipLaunchKernelGGL(k_mon_dl<T>, gm, dim3(256), 0, s, g, (const Snap*)(w + L.snap),
+  hipLaunchKernelGGL(k_mon_dl<T>, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, g, (const Snap*)(w + L.snap),
                      (const T*)(w + L.cu), (const T*)(w + L.v), (const T*)(w + L.emon), (T*)st->G,
                      (T*)st->E, (double2*)st->diag64, st->eps_idx, st->flips, st->flip_cap,
                      st->n_flips, st->status, (int32_t*)(w + L.dl_hdr));
@@ -885,8 +858,7 @@ hipError_t launch_fused_move(const Geo& g, gfo_state* st, const Layout& L, int a
   int* pfirst = (int*)(w + L.pfirst);
   const int nblk = (g.N + kScoreThreads - 1) / kScoreThreads;
   const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
-  const unsigned gy = 1 + (unsigned)((g.nmon - 1 + kMonRowsPerBlock - 1) / kMonRowsPerBlock);
-  hipLaunchKernelGGL(k_mon_score<T>, dim3((unsigned)((nx + kScoreThreads - 1) / kScoreThreads), gy),
+  hipLaunchKernelGGL(k_mon_score<T>, dim3((unsigned)((nx + kScoreThreads - 1) / kScoreThreads)),
                      dim3(kScoreThreads), 0, s, g, apply_prev, (const Snap*)snap, (const T*)cu,
                      (const T*)v, (const T*)emon, (T*)st->G, (T*)st->E, (double2*)st->diag64,
                      st->eps_idx, st->flips, st->flip_cap, st->n_flips, st->status, count, mask,
@@ -937,7 +909,8 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         hipLaunchKernelGGL(k_flush_c64, grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G);
         break;
       case 1:
-        hipLaunchKernelGGL((k_flush_c64_tm<1, true>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G);
+        hipLaunchKernelGGL((k_flush_c64_tm<1, true>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G,
+                           0);
         break;
       case 2:
         hipLaunchKernelGGL((k_flush_c64_pipe<true, 16, false>), grid, blk, 0, s, g.N, g.R, g.ld, count,
@@ -1007,6 +980,12 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         break;
       }
     }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the monitor rows (the FOM monitor's terms are stored as zeros)
+    hipLaunchKernelGGL((k_flush_c64_tm<1, true>),
+                       dim3((unsigned)((g.N + 63) / 64), (unsigned)((g.nmon + 63) / 64)), blk, 0, s,
+                       g.R, g.R, g.ld, count, cu, vv, G, g.N);
     e = hipGetLastError();
   } else {
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;

@@ -379,10 +379,12 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, hipStream
 // `count` pending terms (FP64 matrix cores).
 hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const double2* CU,
                                    const double2* V, double2* G, hipStream_t s) {
-  // slot-major terms: A(m, k) = CU[k * R + m], B(k, n) = V[k * ld + n]
+  // slot-major terms: A(m, k) = CU[k * R + m], B(k, n) = V[k * ld + n]; all R
+  // rows (the design block and the monitor rows; the FOM monitor's terms are
+  // zeros)
   EpiAddG ep{g.ld, G};
-  hipLaunchKernelGGL((k_zgemm_f64<true, false, EpiAddG>), dim3((g.N + 63) / 64, (g.N + 63) / 64),
-                     dim3(256), 0, s, g.N, g.N, GFO_MAX_DELAY, CU, (int64_t)g.R, V, g.ld, count, ep);
+  hipLaunchKernelGGL((k_zgemm_f64<true, false, EpiAddG>), dim3((g.N + 63) / 64, (g.R + 63) / 64),
+                     dim3(256), 0, s, g.R, g.N, GFO_MAX_DELAY, CU, (int64_t)g.R, V, g.ld, count, ep);
   return hipGetLastError();
 }
 
