@@ -1,12 +1,11 @@
 // Deferred rank-1 updates.  Eq. form10 applied move by move gives
 //   G_t = G_base + sum_{s < t} cu_s v_s^T,   cu_s = c_s G_s[:, j_s],  v_s = G_s[j_s, :],
-// so the design block can be brought up to date later, in one rank-r product,
-// while everything the scores read (E, diag64, the monitor rows) is updated at
+// so the design block (and the monitor rows other than the FOM monitor's) can be
+// brought up to date later, in one rank-r product (gfo_flush.hip), while
+// everything the scores read (E, diag64, the FOM monitor row) is updated at
 // once.  Column j and row j of the current matrix are the base entries plus the
 // pending terms.
 #include "gfo_internal.hpp"
-
-#include <atomic>
 
 namespace gfo {
 
@@ -48,9 +47,10 @@ __device__ __forceinline__ Snap deferred_snapshot(const Geo& g, const gfo_pick p
   return s;
 }
 
-// Threads [0, R): u_r = G_t[r, j] (base + pending for design rows; monitor rows
-// are current); cu_r = c u_r is stored as term `slot` and in `cu`; the monitor
-// rows also give E at the monitors after the move, emon[m] = E[N+m] + cu[N+m] E_j.
+// Threads [0, R): u_r = G_t[r, j] (base + pending, except the FOM monitor row,
+// which is current); cu_r = c u_r is stored as term `slot` and in `cu`; the
+// monitor rows also give E at the monitors after the move,
+// emon[m] = E[N+m] + cu[N+m] E_j.
 // Threads [R, R + ld): v_q = G_t[j, q] (q < N, 0 beyond), stored likewise and in
 // `v`.  Workgroup 0 publishes the snapshot for the next kernel.  Nothing written
 // here is read by this launch.
@@ -320,492 +320,6 @@ __global__ __launch_bounds__(kScoreThreads) void k_mon_score(
   if (bad) atomicOr(status, GFO_STATUS_NONFINITE);
 }
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-// Fourth word of a raw buffer resource on gfx9-family chips (32-bit data format;
-// reads past the range return zero).
-constexpr int kBufferDword3 = 0x00020000;
-
-// FP32 flush for complex64 storage: G[m, n] += sum_{s < count} CU[s][m] V[s][n]
-// for design rows m < N and all ld columns, as complex FP32 on the matrix cores
-// (v_mfma_f32_32x32x2_f32; re += Ar Br - Ai Bi, im += Ar Bi + Ai Br).  The G tile
-// is loaded into the accumulators, so G is read and written once.  Workgroup of
-// 4 waves = 64 x 64 outputs, each wave 32 x 32.  Lane layout of the instruction:
-// A(i, k): i = lane % 32, k = lane / 32; B(k, j): j = lane % 32, k = lane / 32;
-// accumulator element e: row 8*(e/4) + 4*(lane/32) + e%4, column lane % 32.
-__global__ __launch_bounds__(256) void k_flush_c64(int M, int R, int64_t ld,
-                                                   const int32_t* __restrict__ count,
-                                                   const float2* __restrict__ CU,
-                                                   const float2* __restrict__ V,
-                                                   float2* __restrict__ G) {
-  const int K = *count;
-  if (K == 0) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
-  const int n = blockIdx.x * 64 + (w & 1) * 32 + (lane & 31);
-  const int h = lane >> 5;
-  f32x16 accr, acci;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int row = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    const float2 gv = row < M ? G[(int64_t)row * ld + n] : make_float2(0.f, 0.f);
-    accr[e] = gv.x;
-    acci[e] = gv.y;
-  }
-  const int am = m0 + (lane & 31);
-#pragma unroll 4
-  for (int k0 = 0; k0 < K; k0 += 2) {
-    const int kk = k0 + h;
-    float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
-    if (kk < K) {
-      if (am < M) a = CU[(int64_t)kk * R + am];
-      b = V[(int64_t)kk * ld + n];
-    }
-    accr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, accr, 0, 0, 0);
-    accr = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, accr, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, acci, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, acci, 0, 0, 0);
-  }
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int row = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    if (row < M) G[(int64_t)row * ld + n] = make_float2(accr[e], acci[e]);
-  }
-}
-
-// Variants with TM row tiles of 32 per wave (a 32*TM x 32 output tile; the TM
-// tiles share each B value) and 64*TM x 64 per workgroup.  The accumulators of
-// different row tiles are independent, so consecutive matrix instructions do not
-// wait on each other's results.  THREE_MULT uses three real products per complex
-// product (Gauss): with P = sum Ar Br, Q = sum Ai Bi, S = sum (Ar + Ai)(Br + Bi),
-// re = Gr + P - Q and im = Gi + S - P - Q; the accumulators start at X = Gr,
-// Y = 0, Z = Gr + Gi, so that re = X - Y and im = Z - X - Y.  This removes a
-// quarter of the matrix work; its rounding differs from the four-product form
-// by a few units of FP32 in the last place relative to |G| + |CU||V|.
-template <int TM, bool THREE_MULT>
-__global__ __launch_bounds__(256) void k_flush_c64_tm(int M, int R, int64_t ld,
-                                                      const int32_t* __restrict__ count,
-                                                      const float2* __restrict__ CU,
-                                                      const float2* __restrict__ V,
-                                                      float2* __restrict__ G, int row0) {
-  const int K = *count;
-  if (K == 0) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = row0 + blockIdx.y * (64 * TM) + (w >> 1) * (32 * TM);
-  const int n = blockIdx.x * 64 + (w & 1) * 32 + (lane & 31);
-  const int h = lane >> 5;
-  f32x16 X[TM], Y[TM], Z[TM];
-#pragma unroll
-  for (int t = 0; t < TM; ++t) {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int r = m0 + 32 * t + 8 * (e >> 2) + 4 * h + (e & 3);
-      const float2 gv = r < M ? G[(int64_t)r * ld + n] : make_float2(0.f, 0.f);
-      X[t][e] = gv.x;
-      if (THREE_MULT) {
-        Y[t][e] = 0.f;
-        Z[t][e] = gv.x + gv.y;
-      } else {
-        Y[t][e] = gv.y;
-      }
-    }
-  }
-#pragma unroll 2
-  for (int k0 = 0; k0 < K; k0 += 2) {
-    const int kk = k0 + h;
-    float2 a[TM], b = make_float2(0.f, 0.f);
-#pragma unroll
-    for (int t = 0; t < TM; ++t) a[t] = make_float2(0.f, 0.f);
-    if (kk < K) {
-#pragma unroll
-      for (int t = 0; t < TM; ++t) {
-        const int am = m0 + 32 * t + (lane & 31);
-        if (am < M) a[t] = CU[(int64_t)kk * R + am];
-      }
-      b = V[(int64_t)kk * ld + n];
-    }
-    if (THREE_MULT) {
-      const float bs = b.x + b.y;
-#pragma unroll
-      for (int t = 0; t < TM; ++t) X[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].x, b.x, X[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < TM; ++t) Y[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].y, b.y, Y[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < TM; ++t)
-        Z[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].x + a[t].y, bs, Z[t], 0, 0, 0);
-    } else {
-#pragma unroll
-      for (int t = 0; t < TM; ++t) X[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].x, b.x, X[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < TM; ++t) Y[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].x, b.y, Y[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < TM; ++t) X[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(-a[t].y, b.y, X[t], 0, 0, 0);
-#pragma unroll
-      for (int t = 0; t < TM; ++t) Y[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[t].y, b.x, Y[t], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < TM; ++t) {
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int r = m0 + 32 * t + 8 * (e >> 2) + 4 * h + (e & 3);
-      if (r >= M) continue;
-      const float2 out = THREE_MULT ? make_float2(X[t][e] - Y[t][e], Z[t][e] - X[t][e] - Y[t][e])
-                                    : make_float2(X[t][e], Y[t][e]);
-      G[(int64_t)r * ld + n] = out;
-    }
-  }
-}
-
-// Tile t (row-major) of the triangle of nb x nb tiles on and above the
-// diagonal: row r starts at tile r nb - r (r - 1) / 2.
-__device__ __forceinline__ void tri_tile(int t, int nb, int& r, int& c) {
-  auto start = [nb](int i) { return i * nb - i * (i - 1) / 2; };
-  const double b2 = 2.0 * nb + 1.0;
-  int i = (int)((b2 - sqrt(b2 * b2 - 8.0 * t)) * 0.5);
-  i = i < 0 ? 0 : (i > nb - 1 ? nb - 1 : i);
-  while (i > 0 && start(i) > t) --i;
-  while (i < nb - 1 && start(i + 1) <= t) ++i;
-  r = i;
-  c = i + (t - start(i));
-}
-
-// Software-pipelined flush, 32 x 32 outputs per wave and 64 x 64 per workgroup.
-// The CU and V operands come through buffer loads whose range ends at the
-// pending count, so slots past it (and rows past the end, given an offset
-// beyond the range) read as zero without a branch or a select.  Registers hold
-// the operands of H instruction steps (a ring); the wave's G tile is requested
-// after the first H, and each ring entry is reloaded with the operands H steps
-// ahead as soon as its step is consumed.  The products accumulate from zero and
-// G is added in the epilogue: vector loads complete in issue order, so no
-// product waits for the G loads.  Every launch runs all GFO_MAX_DELAY / 2 steps
-// (a partial flush costs a full one).  Byte offsets are 32-bit: the launcher
-// uses this form only when GFO_MAX_DELAY * max(R, ld) * 8 < 2^31.  THREE_MULT
-// as in k_flush_c64_tm.
-//
-// XCD: a one-dimensional grid numbered for the chip's eight XCDs (consecutive
-// workgroup ids go to different XCDs, id b to XCD b % 8).  XCD x takes the row
-// blocks [x * bpx, (x + 1) * bpx) and walks them column block by column block:
-// its band of CU rows stays in its own L2 and each V column block is reused
-// across the band.  nby = row blocks, bpx = ceil(nby / 8), grid = 8 * bpx * nbx.
-//
-// SYM: the design block is symmetric (reciprocity: G_D = G_D^T, and each pending
-// term restricted to it, c_s v_s v_s^T, is symmetric too), so only the tiles on
-// and above the diagonal are computed: a one-dimensional grid of nby (nby + 1) / 2
-// workgroups, tile t in row-major order over that triangle (nby = design blocks).
-// An off-diagonal tile is written twice, in place and mirrored (the mirrored
-// copy replaces the lower tile, whose old values are not read).  Only design
-// columns are covered, and the mirrored rows are design rows.
-//
-// NT: G is read and written with non-temporal (streaming) loads and stores;
-// the operand terms, which every workgroup re-reads, keep the normal policy.
-//
-// MIRROR = false (with SYM): the upper triangle alone is brought up to date;
-// the lower tiles are left as they are (the caller records that the lower
-// triangle is out of date, and readers take design entries from the upper
-// one).  Diagonal tiles are computed whole, their lower halves from the old
-// values.
-template <bool THREE_MULT, int H, bool XCD, bool SYM = false, bool NT = false, bool MIRROR = true>
-__global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld,
-                                                        const int32_t* __restrict__ count,
-                                                        const float2* __restrict__ CU,
-                                                        const float2* __restrict__ V,
-                                                        float2* __restrict__ G, int nby) {
-  const int K = *count;
-  if (K == 0) return;
-  int bx = blockIdx.x, by = blockIdx.y;
-  if (XCD) {
-    const int bpx = (nby + 7) / 8, xcd = (int)(blockIdx.x & 7), local = (int)(blockIdx.x >> 3);
-    bx = local / bpx;
-    by = xcd * bpx + local % bpx;
-    if (by >= nby) return;
-  }
-  if (SYM) tri_tile((int)blockIdx.x, nby, by, bx);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = by * 64 + (w >> 1) * 32;
-  const int n = bx * 64 + (w & 1) * 32 + (lane & 31);
-  const int h = lane >> 5;
-  const int am = m0 + (lane & 31);
-  constexpr int P = GFO_MAX_DELAY / 2;
-  static_assert(P % H == 0, "ring depth divides the step count");
-  const __amdgpu_buffer_rsrc_t ra =
-      __builtin_amdgcn_make_buffer_rsrc((void*)CU, (short)0, K * R * 8, kBufferDword3);
-  const __amdgpu_buffer_rsrc_t rb =
-      __builtin_amdgcn_make_buffer_rsrc((void*)V, (short)0, (int)(K * ld * 8), kBufferDword3);
-  const unsigned a_off = am < M ? (unsigned)(h * R + am) * 8u : 0xFFFFFFF0u;
-  const unsigned a_step = am < M ? 2u * (unsigned)R * 8u : 0u;
-  const unsigned b_off = (unsigned)(h * ld + n) * 8u, b_step = 2u * (unsigned)ld * 8u;
-  f32x2 a[H], b[H];
-#pragma unroll
-  for (int i = 0; i < H; ++i) {
-    a[i] = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(ra, a_off + i * a_step, 0, 0));
-    b[i] = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rb, b_off + i * b_step, 0, 0));
-  }
-  __builtin_amdgcn_sched_barrier(0);
-  float2 gv[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    const float2* src = G + (int64_t)(r < M ? r : M - 1) * ld + n;
-    gv[e] = NT ? __builtin_bit_cast(float2, __builtin_nontemporal_load((const f32x2*)src)) : *src;
-  }
-  __builtin_amdgcn_sched_barrier(0);
-  f32x16 X, Y, Z;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) X[e] = Y[e] = Z[e] = 0.f;
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const f32x2 ai = a[i % H], bi = b[i % H];
-    if (i + H < P) {
-      a[i % H] = __builtin_bit_cast(
-          f32x2, __builtin_amdgcn_raw_buffer_load_b64(ra, a_off + (i + H) * a_step, 0, 0));
-      b[i % H] = __builtin_bit_cast(
-          f32x2, __builtin_amdgcn_raw_buffer_load_b64(rb, b_off + (i + H) * b_step, 0, 0));
-    }
-    if (THREE_MULT) {
-      X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
-      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[1], bi[1], Y, 0, 0, 0);
-      Z = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0] + ai[1], bi[0] + bi[1], Z, 0, 0, 0);
-    } else {
-      X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
-      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[1], Y, 0, 0, 0);
-      X = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[1], bi[1], X, 0, 0, 0);
-      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[1], bi[0], Y, 0, 0, 0);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  float2 out[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    out[e] = THREE_MULT ? make_float2(gv[e].x + (X[e] - Y[e]), gv[e].y + (Z[e] - X[e] - Y[e]))
-                        : make_float2(gv[e].x + X[e], gv[e].y + Y[e]);
-    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    if (r < M) {
-      float2* dst = G + (int64_t)r * ld + n;
-      if (NT)
-        __builtin_nontemporal_store(f32x2{out[e].x, out[e].y}, (f32x2*)dst);
-      else
-        *dst = out[e];
-    }
-  }
-  if (SYM && MIRROR && bx != by) {
-    // Mirrored copy, transposed through LDS (33-float2 rows against bank
-    // conflicts): lane (h, c) holds column n0 + c of the wave's tile, which is
-    // row n0 + c of the lower tile.  After the transpose, store i of lane l
-    // writes 16 bytes of lower row n0 + 4 i + l / 16 at columns
-    // m0 + 2 (l % 16) and m0 + 2 (l % 16) + 1, so each store covers four whole
-    // 256-byte row segments (the untransposed stores cover 16-byte pieces of
-    // 32 rows, which costs a third more time per byte).
-    __shared__ float2 tsh[SYM ? 4 : 1][32][33];
-    float2 (*T)[33] = tsh[SYM ? w : 0];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) T[8 * (e >> 2) + 4 * h + (e & 3)][lane & 31] = out[e];
-    // only this wave reads its tile: its LDS operations complete in order
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int n0 = n - (lane & 31), rr = 2 * (lane & 15), c = m0 + rr;
-    float2 v0[8], v1[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      v0[i] = T[rr][4 * i + (lane >> 4)];
-      v1[i] = T[rr + 1][4 * i + (lane >> 4)];
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int nr = n0 + 4 * i + (lane >> 4);
-      float2* __restrict__ p = G + (int64_t)nr * ld + c;
-      if (nr < M && c + 1 < M) {
-        const f32x4 q = f32x4{v0[i].x, v0[i].y, v1[i].x, v1[i].y};
-        if (NT)
-          __builtin_nontemporal_store(q, (f32x4*)p);
-        else
-          *(f32x4*)p = q;
-      } else if (nr < M && c < M) {
-        *p = v0[i];
-      }
-    }
-  }
-}
-
-// Warp-specialised persistent flush: one workgroup of 8 waves per CU walks the
-// 64 x 64 output tiles (tile id = blockIdx.x + i * gridDim.x; bx = id % nbx,
-// by = id / nbx).  Waves 0-3 only stream CU/V operands and issue matrix
-// instructions (32 x 32 outputs each, three real products per complex one, an
-// operand ring of H instruction steps that runs on into the next tile); waves
-// 4-7 move G: they bring the next tile's G into one of two LDS buffers while the
-// current tile computes, and store the finished tile from LDS.  The matrix waves
-// thus never wait on G traffic (vector memory operations of a wave complete in
-// issue order).  Per tile, every wave passes the same two barriers:
-//   X: the matrix waves hold the tile's products, G_in[t % 2] is loaded, the
-//      movers have read the previous finished tile out of G_out;
-//   Y: G_out holds tile t (G + products), G_in[(t + 1) % 2] holds tile t + 1.
-// Same operand loads and 32-bit offset limit as k_flush_c64_pipe.
-constexpr int kWsPitch = 66;                     // float2 per LDS row (16-B aligned rows)
-constexpr int kWsTile = 64 * kWsPitch;
-
-template <int H>
-__global__ __launch_bounds__(512) void k_flush_c64_ws(int M, int R, int64_t ld,
-                                                      const int32_t* __restrict__ count,
-                                                      const float2* __restrict__ CU,
-                                                      const float2* __restrict__ V,
-                                                      float2* __restrict__ G, int nbx, int nby) {
-  __shared__ __align__(16) float2 lds[3 * kWsTile];     // G_in[0], G_in[1], G_out
-  const int K = *count;
-  if (K == 0) return;
-  const int ntiles = nbx * nby;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  constexpr int P = GFO_MAX_DELAY / 2;
-  static_assert(P % H == 0 && H < P, "ring depth");
-  if (w >= 4) {
-    // ---------------------------------------------------------------- movers
-    const int mt = threadIdx.x - 256;             // 0..255: 8 x 16 B of a 32 KB tile each
-    auto tile_rc = [&](int id, int j, int& r, int& c) {
-      const int idx = (j * 256 + mt) * 2;         // float2 index within the 64 x 64 tile
-      r = idx >> 6;
-      c = idx & 63;
-      (void)id;
-    };
-    f32x4 buf[8];
-    auto load_tile = [&](int id) {
-      const int bx = id % nbx, by = id / nbx;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        int r, c;
-        tile_rc(id, j, r, c);
-        const int row = by * 64 + r;
-        buf[j] = row < M ? *(const f32x4*)(G + (int64_t)row * ld + bx * 64 + c) : f32x4{0.f, 0.f, 0.f, 0.f};
-      }
-    };
-    auto put_in = [&](int slot) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        int r, c;
-        tile_rc(0, j, r, c);
-        *(f32x4*)(lds + slot * kWsTile + r * kWsPitch + c) = buf[j];
-      }
-    };
-    auto store_out = [&](int id) {
-      const int bx = id % nbx, by = id / nbx;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        int r, c;
-        tile_rc(id, j, r, c);
-        const f32x4 v = *(const f32x4*)(lds + 2 * kWsTile + r * kWsPitch + c);
-        const int row = by * 64 + r;
-        if (row < M) *(f32x4*)(G + (int64_t)row * ld + bx * 64 + c) = v;
-      }
-    };
-    int id = blockIdx.x;
-    if (id < ntiles) {
-      load_tile(id);
-      put_in(0);
-    }
-    __syncthreads();                              // prologue: G_in[0] holds the first tile
-    int it = 0;
-    for (; id < ntiles; id += gridDim.x, ++it) {
-      if (it > 0) store_out(id - (int)gridDim.x);            // the previous finished tile
-      const int nid = id + (int)gridDim.x;
-      if (nid < ntiles) load_tile(nid);
-      __syncthreads();                            // X
-      if (nid < ntiles) put_in((it + 1) & 1);
-      __syncthreads();                            // Y
-    }
-    if (it > 0) store_out(id - (int)gridDim.x);
-    return;
-  }
-  // ---------------------------------------------------------------- matrix waves
-  const int h = lane >> 5;
-  const __amdgpu_buffer_rsrc_t ra =
-      __builtin_amdgcn_make_buffer_rsrc((void*)CU, (short)0, K * R * 8, kBufferDword3);
-  const __amdgpu_buffer_rsrc_t rb =
-      __builtin_amdgcn_make_buffer_rsrc((void*)V, (short)0, (int)(K * ld * 8), kBufferDword3);
-  const unsigned a_step = 2u * (unsigned)R * 8u, b_step = 2u * (unsigned)ld * 8u;
-  // operand offsets of a tile (an id past the end gives offsets past the range: zeros)
-  auto offsets = [&](int id, unsigned& ao, unsigned& bo) {
-    if (id >= ntiles) {
-      ao = bo = 0xFFFFFFF0u;
-      return;
-    }
-    const int bx = id % nbx, by = id / nbx;
-    const int am = by * 64 + (w >> 1) * 32 + (lane & 31);
-    const int n = bx * 64 + (w & 1) * 32 + (lane & 31);
-    ao = am < M ? (unsigned)(h * R + am) * 8u : 0xFFFFFFF0u;
-    bo = (unsigned)(h * ld + n) * 8u;
-  };
-  auto ld_a = [&](unsigned base, int step) {
-    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(
-                                         ra, base == 0xFFFFFFF0u ? base : base + step * a_step, 0, 0));
-  };
-  auto ld_b = [&](unsigned base, int step) {
-    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(
-                                         rb, base == 0xFFFFFFF0u ? base : base + step * b_step, 0, 0));
-  };
-  int id = blockIdx.x;
-  unsigned a_off, b_off;
-  offsets(id, a_off, b_off);
-  f32x2 ra_[H], rb_[H];
-#pragma unroll
-  for (int i = 0; i < H; ++i) {
-    ra_[i] = ld_a(a_off, i);
-    rb_[i] = ld_b(b_off, i);
-  }
-  __syncthreads();                                // prologue
-  const int lr0 = (w >> 1) * 32 + 4 * h, lc = (w & 1) * 32 + (lane & 31);
-  for (int it = 0; id < ntiles; id += gridDim.x, ++it) {
-    unsigned na, nb;
-    offsets(id + (int)gridDim.x, na, nb);
-    f32x16 X, Y, Z;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) X[e] = Y[e] = Z[e] = 0.f;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const f32x2 ai = ra_[i % H], bi = rb_[i % H];
-      if (i + H < P) {
-        ra_[i % H] = ld_a(a_off, i + H);
-        rb_[i % H] = ld_b(b_off, i + H);
-      } else {
-        ra_[i % H] = ld_a(na, i + H - P);
-        rb_[i % H] = ld_b(nb, i + H - P);
-      }
-      X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
-      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[1], bi[1], Y, 0, 0, 0);
-      Z = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0] + ai[1], bi[0] + bi[1], Z, 0, 0, 0);
-    }
-    __syncthreads();                              // X
-    const float2* gin = lds + (it & 1) * kWsTile;
-    float2* gout = lds + 2 * kWsTile;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int r = lr0 + 8 * (e >> 2) + (e & 3);
-      const float2 gv = gin[r * kWsPitch + lc];
-      gout[r * kWsPitch + lc] = make_float2(gv.x + (X[e] - Y[e]), gv.y + (Z[e] - X[e] - Y[e]));
-    }
-    __syncthreads();                              // Y
-    a_off = na;
-    b_off = nb;
-  }
-}
-
-// flush variants for complex64 storage (selected by the autotuner; all give the
-// eager results to FP32 rounding, tests/test_gpu_deferred.py)
-static const char* const kFlushNames[] = {"w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8",
-                                          "w32_pipe8_3m", "w32_pipe8_3m_xcd", "ws8_3m",
-                                          "ws16_3m", "sym_pipe8_3m", "sym_pipe8_3m_nt",
-                                          "sym_pipe4_3m_nt", "up_pipe8_3m_nt"};
-constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
-constexpr int kFlushDefault = 11;
-static std::atomic<int> g_flush_sel{kFlushDefault};
-int flush_variant_count() { return kFlushCount; }
-const char* flush_variant_name(int i) { return i >= 0 && i < kFlushCount ? kFlushNames[i] : nullptr; }
-int flush_set_variant(int i) {
-  if (i < 0 || i >= kFlushCount) return GFO_EINVAL;
-  g_flush_sel.store(i);
-  return GFO_OK;
-}
-int flush_get_variant() { return g_flush_sel.load(); }
-
 __global__ void k_dl_reset(int32_t* count) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *count = 0;
 }
@@ -887,148 +401,5 @@ template hipError_t launch_apply_deferred<float2>(const Geo&, gfo_state*, const 
                                                   const gfo_pick*, hipStream_t);
 template hipError_t launch_apply_deferred<double2>(const Geo&, gfo_state*, const Layout&,
                                                    const gfo_pick*, hipStream_t);
-
-hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {
-  char* w = (char*)st->work;
-  const int32_t* count = (const int32_t*)(w + L.dl_hdr);
-  hipEvent_t before, after;
-  k1_take_timing(&before, &after);
-  hipError_t e;
-  if (g.dtype == GFO_C64) {
-    if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
-    int fv = flush_get_variant();
-    // the pipelined forms address the term buffers with 32-bit byte offsets
-    const bool off32 = (int64_t)GFO_MAX_DELAY * (g.ld > g.R ? g.ld : g.R) * 8 < ((int64_t)1 << 31);
-    if (fv >= 2 && !off32) fv = 1;
-    const float2* cu = (const float2*)(w + L.dl_CUs);
-    const float2* vv = (const float2*)(w + L.dl_Vs);
-    float2* G = (float2*)st->G;
-    const dim3 grid((unsigned)(g.ld / 64), (unsigned)((g.N + 63) / 64)), blk(256);
-    switch (fv) {
-      case 0:
-        hipLaunchKernelGGL(k_flush_c64, grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G);
-        break;
-      case 1:
-        hipLaunchKernelGGL((k_flush_c64_tm<1, true>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G,
-                           0);
-        break;
-      case 2:
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 16, false>), grid, blk, 0, s, g.N, g.R, g.ld, count,
-                           cu, vv, G, (int)grid.y);
-        break;
-      case 3:
-        hipLaunchKernelGGL((k_flush_c64_pipe<false, 8, false>), grid, blk, 0, s, g.N, g.R, g.ld, count,
-                           cu, vv, G, (int)grid.y);
-        break;
-      case 4:
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false>), grid, blk, 0, s, g.N, g.R, g.ld, count,
-                           cu, vv, G, (int)grid.y);
-        break;
-      case 6:
-      case 7: {
-        // one persistent workgroup per CU (its LDS allows no second one)
-        static std::atomic<int> n_cu_cache{0};
-        int n_cu = n_cu_cache.load();
-        if (n_cu == 0) {
-          int dev = 0;
-          if (hipGetDevice(&dev) != hipSuccess ||
-              hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-              n_cu <= 0)
-            return hipErrorUnknown;
-          n_cu_cache.store(n_cu);
-        }
-        const int nbx = (int)grid.x, nby = (int)grid.y;
-        const int nwg = n_cu < nbx * nby ? n_cu : nbx * nby;
-        if (fv == 6)
-          hipLaunchKernelGGL((k_flush_c64_ws<8>), dim3(nwg), dim3(512), 0, s, g.N, g.R, g.ld, count, cu,
-                             vv, G, nbx, nby);
-        else
-          hipLaunchKernelGGL((k_flush_c64_ws<16>), dim3(nwg), dim3(512), 0, s, g.N, g.R, g.ld, count,
-                             cu, vv, G, nbx, nby);
-        break;
-      }
-      case 8:
-      case 9:
-      case 10: {
-        // design-block triangle only (symmetric flush)
-        const int nb = (g.N + 63) / 64;
-        const dim3 tri((unsigned)(nb * (nb + 1) / 2));
-        if (fv == 8)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true>), tri, blk, 0, s, g.N, g.R, g.ld,
-                             count, cu, vv, G, nb);
-        else if (fv == 9)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true>), tri, blk, 0, s, g.N, g.R,
-                             g.ld, count, cu, vv, G, nb);
-        else
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 4, false, true, true>), tri, blk, 0, s, g.N, g.R,
-                             g.ld, count, cu, vv, G, nb);
-        break;
-      }
-      case 11: {
-        // upper triangle only; the lower one is out of date from here on
-        const int nb = (g.N + 63) / 64;
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false>),
-                           dim3((unsigned)(nb * (nb + 1) / 2)), blk, 0, s, g.N, g.R, g.ld, count, cu, vv,
-                           G, nb);
-        st->lower_stale = 1;
-        break;
-      }
-      default: {
-        const unsigned nby = grid.y, bpx = (nby + 7) / 8;
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true>), dim3(8 * bpx * grid.x), blk, 0, s, g.N,
-                           g.R, g.ld, count, cu, vv, G, (int)nby);
-        break;
-      }
-    }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // the monitor rows (the FOM monitor's terms are stored as zeros)
-    hipLaunchKernelGGL((k_flush_c64_tm<1, true>),
-                       dim3((unsigned)((g.N + 63) / 64), (unsigned)((g.nmon + 63) / 64)), blk, 0, s,
-                       g.R, g.R, g.ld, count, cu, vv, G, g.N);
-    e = hipGetLastError();
-  } else {
-    if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
-    e = launch_zgemm_update_f64(g, count, (const double2*)(w + L.dl_CUs),
-                                (const double2*)(w + L.dl_Vs), (double2*)st->G, s);
-  }
-  if (e != hipSuccess) return e;
-  if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
-  hipLaunchKernelGGL(k_dl_reset, dim3(1), dim3(64), 0, s, (int32_t*)(w + L.dl_hdr));
-  return hipGetLastError();
-}
-
-// Upper triangle of the design block copied into its strict lower triangle:
-// workgroup t takes 32 x 32 tile (by, bx) on or above the diagonal (tri_tile
-// order), reads it row by row into LDS and writes its transpose into tile
-// (bx, by) row by row (on diagonal tiles only below the diagonal).
-template <typename T>
-__global__ __launch_bounds__(256) void k_sync_lower(int N, int64_t ld, T* __restrict__ G, int nb) {
-  __shared__ T tile[32][33];
-  int by, bx;
-  tri_tile((int)blockIdx.x, nb, by, bx);
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int r = by * 32 + ty + 8 * k, c = bx * 32 + tx;
-    if (r < N && c < N) tile[ty + 8 * k][tx] = G[(int64_t)r * ld + c];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int lr = ty + 8 * k, row = bx * 32 + lr, col = by * 32 + tx;
-    if (row < N && col < N && (bx != by || lr > tx)) G[(int64_t)row * ld + col] = tile[tx][lr];
-  }
-}
-
-hipError_t launch_sync_lower(const Geo& g, gfo_state* st, hipStream_t s) {
-  const int nb = (g.N + 31) / 32;
-  const dim3 grid((unsigned)((int64_t)nb * (nb + 1) / 2));
-  if (g.dtype == GFO_C64)
-    hipLaunchKernelGGL(k_sync_lower<float2>, grid, dim3(256), 0, s, g.N, g.ld, (float2*)st->G, nb);
-  else
-    hipLaunchKernelGGL(k_sync_lower<double2>, grid, dim3(256), 0, s, g.N, g.ld, (double2*)st->G, nb);
-  return hipGetLastError();
-}
 
 }  // namespace gfo

@@ -304,6 +304,9 @@ int k1_set_variant(int dtype, int idx);
 int k1_get_variant(int dtype);
 void k1_time_next(hipEvent_t before, hipEvent_t after);
 void k1_take_timing(hipEvent_t* before, hipEvent_t* after);   // consumes the pending pair
+// the streaming rank-1 update of G with the selected tile variant (timed if requested)
+hipError_t launch_rank1(const Geo& g, const Snap* snap, const void* cu, const void* v, void* G,
+                        hipStream_t s);
 int flush_variant_count();
 const char* flush_variant_name(int idx);
 int flush_set_variant(int idx);
