@@ -47,39 +47,92 @@ __device__ __forceinline__ Snap deferred_snapshot(const Geo& g, const gfo_pick p
   return s;
 }
 
-// Threads [0, R): u_r = G_t[r, j] (base + pending, except the FOM monitor row,
-// which is current); cu_r = c u_r is stored as term `slot` and in `cu`; the
-// monitor rows also give E at the monitors after the move,
-// emon[m] = E[N+m] + cu[N+m] E_j.
-// Threads [R, R + ld): v_q = G_t[j, q] (q < N, 0 beyond), stored likewise and in
-// `v`.  Workgroup 0 publishes the snapshot for the next kernel.  Nothing written
-// here is read by this launch.
+// Column j and row j of the current matrix G_t = G_base + sum_s cu_s v_s^T:
+//   row entries    v_q = G[j, q] + sum_s CU_s[j] V_s[q]  for q < N (0 beyond);
+//   design column  u_i = v_i: the design block is symmetric (reciprocity), and
+//                  so is each pending term restricted to it;
+//   monitor rows   u_{N+m} = G[N+m, j] + sum_s CU_s[N+m] V_s[j], except the FOM
+//                  monitor's row, which is current.
+// cu = c u and v are stored as term `slot` (the FOM monitor's entry as zero: its
+// row already has the term) and in cu_out / v_out; the monitor rows also give E
+// at the monitors after the move, emon[m] = E[N+m] + cu[N+m] E_j.  Workgroup 0
+// publishes the snapshot for the next kernel.  Nothing written here is read by
+// this launch.
 //
-// Two phases, so that the loads that do not depend on the pick can be in flight
-// while it is taken: gather_prefetch reads the term count and this thread's
-// operands of the first kGatherBatch pending terms (CU[s][i] for a column thread,
-// V[s][q] for a row thread); gather_finish issues every load that depends on the
-// pick at once (the pixel's scalars, the base entry, the other operand of each
-// term), then sums the terms in slot order from zero and adds the base entry.
-constexpr int kGatherBatch = 16;
+// Elements e of [0, mpad + ld), mpad = nmon rounded up to kGatherElems: monitor
+// row N + e for e < nmon (none for nmon <= e < mpad), else row entry
+// q = e - mpad, so that a workgroup holds one kind only.  A workgroup of
+// kGatherParts waves takes kGatherElems consecutive elements, one per lane;
+// wave w sums the terms
+// [w kGatherBatch, (w + 1) kGatherBatch) from zero in slot order, the partial
+// sums meet in LDS, and wave 0 adds them pairwise to the base entry and stores.
+// Two phases, so that the loads that do not depend on the pick are in flight
+// while it is taken: gather_prefetch reads the term count and the lane's own
+// operand of each of its wave's terms (CU_s[N+m] or V_s[q], through buffer
+// loads whose range ends at the term count, so that slots past it read as zero
+// without a branch); gather_finish
+// issues the loads that depend on the pick at once (the pixel's scalars, the
+// base entries, and the terms' entries at j, staged once per workgroup in LDS).
+constexpr int kGatherParts = 4;
+constexpr int kGatherBatch = GFO_MAX_DELAY / kGatherParts;
+constexpr int kGatherElems = 64;
+static_assert(kGatherParts * 64 == 256, "one wave per part");
 
 template <typename T>
 struct GatherPre {
   int cnt;                    // pending terms = this move's slot
-  T a[kGatherBatch];          // this thread's operands of terms 0 .. kGatherBatch-1
+  T a[kGatherBatch];          // the lane's operands of its wave's terms
 };
+
+__host__ __device__ inline int gather_mpad(const Geo& g) {
+  return (g.nmon + kGatherElems - 1) / kGatherElems * kGatherElems;
+}
+
+// The element of this lane: e, whether it is a monitor row (uniform over the
+// workgroup), and whether it exists.
+struct GatherElem {
+  int64_t e;
+  bool mon, live;
+  int64_t i, q;               // monitor row N + e, or row entry q (clamped)
+};
+
+__device__ __forceinline__ GatherElem gather_elem(const Geo& g) {
+  GatherElem el;
+  const int mpad = gather_mpad(g);
+  el.e = (int64_t)blockIdx.x * kGatherElems + (threadIdx.x & 63);
+  el.mon = (int64_t)blockIdx.x * kGatherElems < mpad;
+  el.live = el.mon ? el.e < g.nmon : el.e - mpad < g.ld;
+  el.i = el.mon ? g.N + (el.live ? el.e : 0) : 0;
+  el.q = el.mon ? 0 : (el.live ? el.e - mpad : 0);
+  return el;
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <>
+__device__ __forceinline__ float2 buf_load<float2>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double2 buf_load<double2>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
 
 template <typename T>
 __device__ __forceinline__ void gather_prefetch(const Geo& g, const int32_t* __restrict__ count,
                                                 const T* __restrict__ CUs,
                                                 const T* __restrict__ Vs, GatherPre<T>& pre) {
   pre.cnt = __builtin_amdgcn_readfirstlane(*count);
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool col = t < g.R;
-  const int64_t i = col ? t : 0, q = col ? 0 : (t - g.R < g.ld ? t - g.R : g.ld - 1);
+  const GatherElem el = gather_elem(g);
+  // one resource per workgroup: its range ends at the term count
+  const int64_t stride = el.mon ? g.R : g.ld;
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(el.mon ? CUs : Vs), (short)0, (int)(pre.cnt * stride * (int64_t)sizeof(T)), 0x00020000);
+  const unsigned off = (unsigned)((el.mon ? el.i : el.q) * (int64_t)sizeof(T));
+  const int s0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kGatherBatch;
 #pragma unroll
   for (int k = 0; k < kGatherBatch; ++k)
-    if (k < pre.cnt) pre.a[k] = col ? CUs[(int64_t)k * g.R + i] : Vs[(int64_t)k * g.ld + q];
+    pre.a[k] = buf_load<T>(r, off + (unsigned)((s0 + k) * stride * (int64_t)sizeof(T)));
 }
 
 template <typename T>
@@ -91,66 +144,59 @@ __device__ __forceinline__ void gather_finish(const Geo& g, const gfo_pick pk,
                                               Snap* __restrict__ snap_out, T* __restrict__ CUs,
                                               T* __restrict__ Vs, T* __restrict__ cu_out,
                                               T* __restrict__ v_out, T* __restrict__ emon) {
+  __shared__ T yj[2][GFO_MAX_DELAY];              // V_s[j] (monitor rows), CU_s[j] (row entries)
+  __shared__ double2 part[kGatherParts - 1][kGatherElems];
   const int cnt = pre.cnt;
-  const int jc = pk.pixel >= 0 && pk.pixel < g.N ? pk.pixel : 0;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool col = t < g.R;
-  const int64_t i = col ? t : 0, q = col ? 0 : (t - g.R < g.ld ? t - g.R : g.ld - 1);
+  const int jc = __builtin_amdgcn_readfirstlane(pk.pixel >= 0 && pk.pixel < g.N ? pk.pixel : 0);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const GatherElem el = gather_elem(g);
+  const int64_t e = el.e, i = el.i, q = el.q;
+  const bool mon = el.mon, live = el.live;
   // every load that depends on the pick, issued together
   const int cur = eps_idx[jc];
   const double2 dj = diag64[jc];
   const T Ej = E[jc];
-  const T base = col ? G[g_at(g, i, jc)] : G[g_at(g, jc, q)];
-  T b[kGatherBatch];
-#pragma unroll
-  for (int k = 0; k < kGatherBatch; ++k)
-    if (k < cnt) b[k] = col ? Vs[(int64_t)k * g.ld + jc] : CUs[(int64_t)k * g.R + jc];
+  T base = St<T>::from_d(make_double2(0.0, 0.0));
+  if (w == 0) base = mon ? G[i * g.ld + jc] : G[g_at(g, jc, q)];
+  if (threadIdx.x < cnt) yj[0][threadIdx.x] = Vs[(int64_t)threadIdx.x * g.ld + jc];
+  if (threadIdx.x >= 64 && threadIdx.x - 64 < cnt)
+    yj[1][threadIdx.x - 64] = CUs[(int64_t)(threadIdx.x - 64) * g.R + jc];
   const Snap sn = deferred_snapshot<T>(g, pk, cur, dj, Ej, cnt);
   if (blockIdx.x == 0 && threadIdx.x == 0) *snap_out = sn;
   const int j = __builtin_amdgcn_readfirstlane(sn.j);
-  if (j < 0 || t >= g.R + g.ld) return;
-  const int slot = cnt;
-  // the terms of an entry: design entries other than the pivot, and the
-  // monitor rows except the FOM monitor's, which is kept current move by move
-  const int64_t mrow = (int64_t)g.N + g.m0;
-  const bool terms = col ? (i != j && i != mrow) : (q < g.N && q != j);
+  __syncthreads();
+  // the terms of an entry: design row entries other than the pivot, and the
+  // monitor rows except the FOM monitor's
+  const bool terms = mon ? (e != g.m0) : (q < g.N && q != j);
+  const int s0 = w * kGatherBatch;
   double2 acc = make_double2(0.0, 0.0);
-  if (terms) {
+  if (j >= 0 && terms) {
 #pragma unroll
     for (int k = 0; k < kGatherBatch; ++k)
-      if (k < slot) acc = cadd(acc, cmul(St<T>::to_d(col ? pre.a[k] : b[k]),
-                                         St<T>::to_d(col ? b[k] : pre.a[k])));
-    for (int s0 = kGatherBatch; s0 < slot; s0 += kGatherBatch) {
-      T x[kGatherBatch], y[kGatherBatch];
-#pragma unroll
-      for (int k = 0; k < kGatherBatch; ++k) {
-        if (s0 + k < slot) {
-          x[k] = CUs[(int64_t)(s0 + k) * g.R + (col ? i : j)];
-          y[k] = Vs[(int64_t)(s0 + k) * g.ld + (col ? j : q)];
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kGatherBatch; ++k)
-        if (s0 + k < slot) acc = cadd(acc, cmul(St<T>::to_d(x[k]), St<T>::to_d(y[k])));
-    }
+      if (s0 + k < cnt) acc = cadd(acc, cmul(St<T>::to_d(pre.a[k]), St<T>::to_d(yj[mon ? 0 : 1][s0 + k])));
   }
-  if (col) {
-    double2 u;
-    if (i == j) u = sn.dj;
-    else if (i != mrow) u = cadd(St<T>::to_d(base), acc);
-    else u = St<T>::to_d(base);                   // FOM monitor row: current
+  if (w > 0) part[w - 1][lane] = acc;
+  __syncthreads();
+  if (j < 0 || w != 0 || !live) return;
+  acc = cadd(cadd(acc, part[0][lane]), cadd(part[1][lane], part[2][lane]));
+  const int slot = cnt;
+  if (mon) {
+    const double2 u = e != g.m0 ? cadd(St<T>::to_d(base), acc) : St<T>::to_d(base);
     const T cu = St<T>::from_d(cmul(sn.c, u));
-    // the FOM monitor row takes no term at the flush (it already has this one)
-    CUs[(int64_t)slot * g.R + i] = i == mrow ? St<T>::from_d(make_double2(0.0, 0.0)) : cu;
+    CUs[(int64_t)slot * g.R + i] = e != g.m0 ? cu : St<T>::from_d(make_double2(0.0, 0.0));
     cu_out[i] = cu;
-    if (i >= g.N) emon[i - g.N] = axpy_st<T>(E[i], cu, sn.Ej);
+    emon[e] = axpy_st<T>(E[i], cu, sn.Ej);
   } else {
-    const int64_t qq = t - g.R;
     double2 v = make_double2(0.0, 0.0);
-    if (qq < g.N) v = qq == j ? sn.dj : cadd(St<T>::to_d(base), acc);
+    if (q < g.N) v = q == j ? sn.dj : cadd(St<T>::to_d(base), acc);
     const T vv = St<T>::from_d(v);
-    Vs[(int64_t)slot * g.ld + qq] = vv;
-    v_out[qq] = vv;
+    Vs[(int64_t)slot * g.ld + q] = vv;
+    v_out[q] = vv;
+    if (q < g.N) {
+      const T cu = St<T>::from_d(cmul(sn.c, v));
+      CUs[(int64_t)slot * g.R + q] = cu;
+      cu_out[q] = cu;
+    }
   }
 }
 
@@ -165,7 +211,7 @@ __global__ __launch_bounds__(256) void k_gather_dl(
   gather_finish<T>(g, *pick, pre, G, E, diag64, eps_idx, snap_out, CUs, Vs, cu_out, v_out, emon);
 }
 
-// Fused pick + gather: every workgroup takes the greedy pick from the score
+// Fused pick + gather: every wave takes the greedy pick from the score
 // summaries (identical in all of them: the same reads, exact max and min
 // reductions) while its pick-independent gather loads are in flight; workgroup
 // 0 records the pick in `pick_out`.
@@ -177,14 +223,25 @@ __global__ __launch_bounds__(256) void k_select_gather(
     const uint8_t* __restrict__ eps_idx, const int32_t* __restrict__ count,
     Snap* __restrict__ snap_out, T* __restrict__ CUs, T* __restrict__ Vs, T* __restrict__ cu_out,
     T* __restrict__ v_out, T* __restrict__ emon) {
-  __shared__ double shd[4];
-  __shared__ int shi[4];
+  // the summaries first: waiting for them then does not wait for the term
+  // operands (vector loads complete in issue order)
+  PickPre pp;
+  pick_wave_load(partial, nblk, pp);
+  const double fom = cabs2(St<T>::to_d(E[g.N + g.m0]));
+  __builtin_amdgcn_sched_barrier(0);
   GatherPre<T> pre;
   gather_prefetch<T>(g, count, CUs, Vs, pre);
-  const double fom = cabs2(St<T>::to_d(E[g.N + g.m0]));
-  const gfo_pick pk = greedy_pick_block(g, fom, scores, partial, pfirst, nblk, tau, shd, shi);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *pick_out = pk;
+  __builtin_amdgcn_sched_barrier(0);
+  gfo_pick pk = pick_wave_take(g, fom, pp, scores, partial, pfirst, tau, false);
   gather_finish<T>(g, pk, pre, G, E, diag64, eps_idx, snap_out, CUs, Vs, cu_out, v_out, emon);
+  // the record of the pick, off the gather's critical path
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (pk.pixel >= 0) {
+      pk.fom_new = scores[pk.pixel * g.n_eps + pk.eps_idx];
+      pk.dfom = pk.fom_new - fom;
+    }
+    *pick_out = pk;
+  }
 }
 
 // The move's elementwise part for one index q (design pixel or monitor row):
@@ -338,8 +395,9 @@ hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, c
   T* cu = (T*)(w + L.cu);
   T* v = (T*)(w + L.v);
   T* emon = (T*)(w + L.emon);
-  const int64_t n = (int64_t)g.R + g.ld;
-  hipLaunchKernelGGL(k_gather_dl<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g, pick,
+  const int64_t n = (int64_t)gather_mpad(g) + g.ld;
+  hipLaunchKernelGGL(k_gather_dl<T>, dim3((unsigned)((n + kGatherElems - 1) / kGatherElems)), dim3(256),
+                     0, s, g, pick,
                      (const T*)st->G, (const T*)st->E, (const double2*)st->diag64,
                      (const uint8_t*)st->eps_idx, (const int32_t*)count, snap, (T*)(w + L.dl_CUs),
                      (T*)(w + L.dl_Vs), cu, v, emon);
@@ -381,8 +439,9 @@ hipError_t launch_fused_move(const Geo& g, gfo_state* st, const Layout& L, int a
     const hipError_t e = launch_flush(g, st, L, s);
     if (e != hipSuccess) return e;
   }
-  const int64_t n = (int64_t)g.R + g.ld;
-  hipLaunchKernelGGL(k_select_gather<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g,
+  const int64_t n = (int64_t)gather_mpad(g) + g.ld;
+  hipLaunchKernelGGL(k_select_gather<T>, dim3((unsigned)((n + kGatherElems - 1) / kGatherElems)),
+                     dim3(256), 0, s, g,
                      (const double*)scores, (const double*)partial, (const int*)pfirst, nblk, tau,
                      pick_out,
                      (const T*)st->G, (const T*)st->E, (const double2*)st->diag64,

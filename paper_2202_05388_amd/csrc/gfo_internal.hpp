@@ -55,16 +55,13 @@ template <> struct St<double2> {
 };
 
 // ------------------------------------------------------------------ reductions
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
-}
+// Wave-wide max and min over all 64 lanes (every lane active), with the ROCm
+// device library's wave reductions (cross-lane data-parallel moves instead of
+// LDS permutes).  Exact operations, so the result does not depend on the order.
+extern "C" __device__ __attribute__((const)) double __ockl_wfred_max_f64(double);
+extern "C" __device__ __attribute__((const)) int __ockl_wfred_min_i32(int);
+__device__ __forceinline__ double wave_max(double v) { return __ockl_wfred_max_f64(v); }
+__device__ __forceinline__ int wave_min(int v) { return __ockl_wfred_min_i32(v); }
 // block-wide max; all threads get the result. `sh` holds blockDim/64 doubles.
 __device__ inline double block_max(double v, double* sh) {
   int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -254,6 +251,80 @@ __device__ inline gfo_pick greedy_pick_block(const Geo& g, double fom,
   pk.eps_idx = first - pk.pixel * g.n_eps;
   pk.fom_new = scores[first];
   pk.dfom = pk.fom_new - fom;
+  return pk;
+}
+
+// The same pick taken by each wave on its own (no LDS, no barrier), in two
+// steps so that a caller can put other loads in flight between them:
+// pick_wave_load reads the workgroup summaries (lane l holds partial[l + 64 k]),
+// pick_wave_take reduces them with cross-lane operations and reads the winner
+// with uniform (scalar) loads.  Same decisions as greedy_pick_block (exact max
+// and min).
+constexpr int kPickPerLane = kScoreMaxBlocks / 64;
+
+struct PickPre {
+  double pv[kPickPerLane];
+};
+
+__device__ __forceinline__ void pick_wave_load(const double* __restrict__ partial, int nblk,
+                                               PickPre& pp) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < kPickPerLane; ++k) {
+    const int i = lane + 64 * k;
+    pp.pv[k] = -INFINITY;
+    if (i < nblk) pp.pv[k] = partial[i];
+  }
+}
+
+// with_score = false leaves fom_new and dfom of an accepted pick unset (the
+// caller reads scores[pixel * n_eps + eps_idx] where it needs them).
+__device__ __forceinline__ gfo_pick pick_wave_take(const Geo& g, double fom, const PickPre& pp,
+                                                   const double* __restrict__ scores,
+                                                   const double* __restrict__ partial,
+                                                   const int* __restrict__ pfirst, double tau,
+                                                   bool with_score = true) {
+  gfo_pick pk;
+  pk.pixel = -1;
+  pk.eps_idx = -1;
+  pk.fom_new = fom;
+  pk.dfom = 0.0;
+  const int lane = threadIdx.x & 63;
+  double m = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < kPickPerLane; ++k) m = fmax(m, pp.pv[k]);
+  m = wave_max(m);
+  if (!(m > fom * (1.0 + tau))) return pk;
+  const double thr = tie_threshold(m, tau);
+  int bq = 0x7fffffff;
+#pragma unroll
+  for (int k = kPickPerLane - 1; k >= 0; --k)
+    if (pp.pv[k] >= thr) bq = lane + 64 * k;
+  bq = __builtin_amdgcn_readfirstlane(wave_min(bq));
+  int first = 0x7fffffff;
+  const int pf = pfirst[bq];
+  if (partial[bq] == m && pf != 0x7fffffff) {
+    first = pf;
+  } else {
+    const int total = g.N * g.n_eps, span = kScoreThreads * g.n_eps;
+    const int lo = bq * span, hi = min(lo + span, total);
+    int f = 0x7fffffff;
+    for (int i = lo + lane; i < hi; i += 64) {
+      if (scores[i] >= thr) {
+        f = i;
+        break;
+      }
+    }
+    first = wave_min(f);
+  }
+  first = __builtin_amdgcn_readfirstlane(first);
+  if (first == 0x7fffffff) return pk;
+  pk.pixel = first / g.n_eps;
+  pk.eps_idx = first - pk.pixel * g.n_eps;
+  if (with_score) {
+    pk.fom_new = scores[first];
+    pk.dfom = pk.fom_new - fom;
+  }
   return pk;
 }
 
