@@ -128,7 +128,9 @@ int gfo_scores_offset(const gfo_problem* prob, int64_t ldG, int32_t kmax, size_t
  * status = 0, and the FP64 offset table in the workspace that refresh_G
  * reuses.  Pixel centres: x = (ix - (nx-1)/2) h, y = (iy - (ny-1)/2) h.
  * All Hankel values are evaluated in FP64 and rounded once to the storage
- * type. */
+ * type.  In deferred mode (state.delay > 0) the design block is written on
+ * and above its diagonal only and state.lower_stale is set (gfo_sync_lower
+ * completes it); otherwise the whole matrix is written and the flag cleared. */
 int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 
 /* score_candidates - score every candidate move and select (paper Sec. II A:
@@ -192,8 +194,9 @@ int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 /* gfo_sync_lower - copy the upper triangle of the design block into its strict
  * lower triangle (G[q, p] = G[p, q] for p < q < N) when state.lower_stale is
  * set, then clear it; a no-op otherwise.  Pending deferred terms are not
- * applied (call gfo_flush first for a current matrix).  Only complex64
- * flushes set the flag.  Asynchronous on `stream`. */
+ * applied (call gfo_flush first for a current matrix).  init_G0 in deferred
+ * mode (it fills the upper triangle only) and the complex64 upper-only flush
+ * set the flag.  Asynchronous on `stream`. */
 int gfo_sync_lower(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 
 /* gfo_greedy_steps - n_steps greedy moves (paper Sec. II: score every

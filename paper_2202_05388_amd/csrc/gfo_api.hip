@@ -176,7 +176,7 @@ int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   if (launch_init(g, st, L, stream) != hipSuccess) return GFO_EHIP;
   if (launch_dl_reset(g, st, L, stream) != hipSuccess) return GFO_EHIP;
   st->pending_calls = 0;
-  st->lower_stale = 0;
+  st->lower_stale = st->delay > 0 ? 1 : 0;   // deferred mode fills the upper triangle only
   if (hipStreamSynchronize(stream) != hipSuccess) return GFO_EHIP;
   return GFO_OK;
 }

@@ -226,13 +226,13 @@ __global__ __launch_bounds__(256) void k_select_gather(
   // the summaries first: waiting for them then does not wait for the term
   // operands (vector loads complete in issue order)
   PickPre pp;
-  pick_wave_load(partial, nblk, pp);
+  pick_wave_load(partial, pfirst, nblk, pp);
   const double fom = cabs2(St<T>::to_d(E[g.N + g.m0]));
   __builtin_amdgcn_sched_barrier(0);
   GatherPre<T> pre;
   gather_prefetch<T>(g, count, CUs, Vs, pre);
   __builtin_amdgcn_sched_barrier(0);
-  gfo_pick pk = pick_wave_take(g, fom, pp, scores, partial, pfirst, tau, false);
+  gfo_pick pk = pick_wave_take(g, fom, pp, scores, tau, false);
   gather_finish<T>(g, pk, pre, G, E, diag64, eps_idx, snap_out, CUs, Vs, cu_out, v_out, emon);
   // the record of the pick, off the gather's critical path
   if (blockIdx.x == 0 && threadIdx.x == 0) {

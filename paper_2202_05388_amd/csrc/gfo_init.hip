@@ -12,6 +12,9 @@
 
 namespace gfo {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ double2 kernel_h2g(double r, const Geo& g) {
   double x = g.k0 * r;
   double s = 0.25 * g.h * g.h;
@@ -42,21 +45,42 @@ __global__ void k_init_table(Geo g, double2* __restrict__ table) {
 }
 
 // Design block: G[p, q] = table[|iy_p - iy_q|, |ix_p - ix_q|]; columns >= N zeroed.
+// A thread writes VN = 16 / sizeof(T) consecutive columns of a row with one
+// 16-byte non-temporal store; the workgroups of grid row y take the rows
+// y, y + gridDim.y, ...  With `upper`, stores that lie wholly below the
+// diagonal are skipped (deferred mode reads the design block from its upper
+// triangle; the caller marks the lower one out of date).
 template <typename T>
-__global__ void k_fill_design(Geo g, T* __restrict__ G, const double2* __restrict__ table) {
-  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= g.ld) return;
-  int iyq = (int)(q / g.nx), ixq = (int)(q - (int64_t)iyq * g.nx);
-  for (int p = blockIdx.y; p < g.N; p += gridDim.y) {
-    T out;
-    if (q < g.N) {
-      int iyp = p / g.nx, ixp = p - (p / g.nx) * g.nx;
-      int dy = abs(iyp - iyq), dx = abs(ixp - ixq);
-      out = St<T>::from_d(table[dy * g.nx + dx]);
-    } else {
-      out = St<T>::from_d(make_double2(0.0, 0.0));
+__global__ void k_fill_design(Geo g, T* __restrict__ G, const double2* __restrict__ table,
+                              int upper) {
+  constexpr int VN = 16 / (int)sizeof(T);
+  const int64_t q0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VN;
+  if (q0 >= g.ld) return;
+  int iyq[VN], ixq[VN];
+#pragma unroll
+  for (int v = 0; v < VN; ++v) {
+    iyq[v] = (int)((q0 + v) / g.nx);
+    ixq[v] = (int)(q0 + v - (int64_t)iyq[v] * g.nx);
+  }
+  // with `upper`, rows past the workgroup's last column hold nothing to write
+  const int64_t wg_end = ((int64_t)blockIdx.x + 1) * blockDim.x * VN;
+  const int p_end = upper && wg_end < g.N ? (int)wg_end : g.N;
+  for (int p = blockIdx.y; p < p_end; p += gridDim.y) {
+    if (upper && q0 + VN - 1 < p) continue;
+    const int iyp = p / g.nx, ixp = p - (p / g.nx) * g.nx;
+    double2 d[VN];
+#pragma unroll
+    for (int v = 0; v < VN; ++v) {
+      d[v] = make_double2(0.0, 0.0);
+      if (q0 + v < g.N) d[v] = table[abs(iyp - iyq[v]) * g.nx + abs(ixp - ixq[v])];
     }
-    G[(int64_t)p * g.ld + q] = out;
+    T* dst = G + (int64_t)p * g.ld + q0;
+    if constexpr (VN == 2) {
+      const float2 a = St<T>::from_d(d[0]), b = St<T>::from_d(d[1]);
+      __builtin_nontemporal_store(f32x4{a.x, a.y, b.x, b.y}, (f32x4*)dst);
+    } else {
+      __builtin_nontemporal_store(f64x2{d[0].x, d[0].y}, (f64x2*)dst);
+    }
   }
 }
 
@@ -118,8 +142,11 @@ static hipError_t init_typed(const Geo& g, gfo_state* st, const Layout& L, hipSt
   int nt = g.ny * g.nx;
   hipLaunchKernelGGL(k_init_table, dim3((nt + 255) / 256), dim3(256), 0, s, g, table);
   dim3 blk(256);
-  dim3 grd((unsigned)((g.ld + 255) / 256), (unsigned)(g.N < 65535 ? g.N : 65535));
-  hipLaunchKernelGGL(k_fill_design<T>, grd, blk, 0, s, g, G, (const double2*)table);
+  constexpr int VN = 16 / (int)sizeof(T);
+  // a few rows per workgroup: workgroup dispatch, not the stores, bounds one row each
+  dim3 grd((unsigned)((g.ld + 256 * VN - 1) / (256 * VN)), (unsigned)(g.N < 2048 ? g.N : 2048));
+  hipLaunchKernelGGL(k_fill_design<T>, grd, blk, 0, s, g, G, (const double2*)table,
+                     st->delay > 0 ? 1 : 0);
   if (g.nmon > 0) {
     dim3 grm((unsigned)((g.ld + 255) / 256), (unsigned)(g.nmon < 65535 ? g.nmon : 65535));
     hipLaunchKernelGGL(k_fill_monitors<T>, grm, blk, 0, s, g, G, (const double*)mon);

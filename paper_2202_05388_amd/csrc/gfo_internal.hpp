@@ -256,33 +256,39 @@ __device__ inline gfo_pick greedy_pick_block(const Geo& g, double fom,
 
 // The same pick taken by each wave on its own (no LDS, no barrier), in two
 // steps so that a caller can put other loads in flight between them:
-// pick_wave_load reads the workgroup summaries (lane l holds partial[l + 64 k]),
-// pick_wave_take reduces them with cross-lane operations and reads the winner
-// with uniform (scalar) loads.  Same decisions as greedy_pick_block (exact max
-// and min).
+// pick_wave_load reads the workgroup summaries (lane l holds partial[l + 64 k]
+// and pfirst[l + 64 k]), pick_wave_take reduces them with cross-lane
+// operations and takes the winning workgroup's entries from the lane that
+// holds them, so the pick costs one round trip to memory (plus a scan of one
+// workgroup's scores in a near-tie across workgroups).  Same decisions as
+// greedy_pick_block (exact max and min).
 constexpr int kPickPerLane = kScoreMaxBlocks / 64;
 
 struct PickPre {
   double pv[kPickPerLane];
+  int pf[kPickPerLane];
 };
 
-__device__ __forceinline__ void pick_wave_load(const double* __restrict__ partial, int nblk,
+__device__ __forceinline__ void pick_wave_load(const double* __restrict__ partial,
+                                               const int* __restrict__ pfirst, int nblk,
                                                PickPre& pp) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int k = 0; k < kPickPerLane; ++k) {
     const int i = lane + 64 * k;
     pp.pv[k] = -INFINITY;
-    if (i < nblk) pp.pv[k] = partial[i];
+    pp.pf[k] = 0x7fffffff;
+    if (i < nblk) {
+      pp.pv[k] = partial[i];
+      pp.pf[k] = pfirst[i];
+    }
   }
 }
 
 // with_score = false leaves fom_new and dfom of an accepted pick unset (the
 // caller reads scores[pixel * n_eps + eps_idx] where it needs them).
 __device__ __forceinline__ gfo_pick pick_wave_take(const Geo& g, double fom, const PickPre& pp,
-                                                   const double* __restrict__ scores,
-                                                   const double* __restrict__ partial,
-                                                   const int* __restrict__ pfirst, double tau,
+                                                   const double* __restrict__ scores, double tau,
                                                    bool with_score = true) {
   gfo_pick pk;
   pk.pixel = -1;
@@ -301,9 +307,24 @@ __device__ __forceinline__ gfo_pick pick_wave_take(const Geo& g, double fom, con
   for (int k = kPickPerLane - 1; k >= 0; --k)
     if (pp.pv[k] >= thr) bq = lane + 64 * k;
   bq = __builtin_amdgcn_readfirstlane(wave_min(bq));
+  // workgroup bq's summary, from lane bq % 64, register bq / 64
+  const int kb = bq >> 6, lb = bq & 63;
+  double pvb = -INFINITY;
+  int pfb = 0x7fffffff;
+#pragma unroll
+  for (int k = 0; k < kPickPerLane; ++k) {
+    if (k == kb) {
+      pvb = pp.pv[k];
+      pfb = pp.pf[k];
+    }
+  }
+  const int pf = __builtin_amdgcn_readlane(pfb, lb);
+  const double pb = __builtin_bit_cast(
+      double, ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(__builtin_bit_cast(uint64_t, pvb) >> 32), lb)
+               << 32) |
+                  (uint32_t)__builtin_amdgcn_readlane((int)__builtin_bit_cast(uint64_t, pvb), lb));
   int first = 0x7fffffff;
-  const int pf = pfirst[bq];
-  if (partial[bq] == m && pf != 0x7fffffff) {
+  if (pb == m && pf != 0x7fffffff) {
     first = pf;
   } else {
     const int total = g.N * g.n_eps, span = kScoreThreads * g.n_eps;
