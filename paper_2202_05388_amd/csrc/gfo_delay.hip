@@ -331,24 +331,26 @@ __global__ __launch_bounds__(kScoreThreads) void k_mon_score(
   __shared__ double sh[kScoreThreads / 64];
   __shared__ int shi[kScoreThreads / 64];
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // every load of this thread first and unconditionally (indices clamped to
+  // valid elements; values past the ends are not used), together with the
+  // move's snapshot, so that the kernel waits for memory once before its stores
+  const int64_t qc = q < g.N ? q : g.N - 1, ql = q < g.ld ? q : g.ld - 1;
+  const int64_t qm = q < g.N ? 0 : (q - g.N < g.nmon ? q - g.N : g.nmon - 1);
+  T Eq = E[qc];
+  double2 dq = diag64[qc];
+  int cur = eps_idx[qc];
+  const T cuq = cu[qc], vq = v[ql], emq = emon[qm];
+  T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
+  T grow_q = grow[ql];
+  const T em0 = emon[g.m0], e0 = E[g.N + g.m0], cum0 = cu[g.N + g.m0];
+  __builtin_amdgcn_sched_barrier(0);
   Snap sn;
   sn.j = -1;
   if (apply_prev) sn = *snap;
   const bool moved = sn.j >= 0;
-  if (!moved && apply_prev && q == 0 && sn.pad1) atomicOr(status, GFO_STATUS_SINGULAR);
-  if (moved && q == 0) record_move(sn, flips, flip_cap, n_flips, status, count);
-  const double2 Em0 = St<T>::to_d(moved ? emon[g.m0] : E[g.N + g.m0]);
-  // every load of this thread is issued before any store, unconditionally
-  // (indices clamped to valid elements; values past the ends are not used)
-  const int64_t qc = q < g.N ? q : g.N - 1, ql = q < g.ld ? q : g.ld - 1;
-  T Eq = E[qc];
-  double2 dq = diag64[qc];
-  int cur = eps_idx[qc];
-  const T cuq = cu[qc], vq = v[ql];
-  T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
-  T grow_q = grow[ql];
+  const double2 Em0 = St<T>::to_d(moved ? em0 : e0);
   if (moved) {
-    grow_q = axpy_st<T>(grow_q, cu[g.N + g.m0], St<T>::to_d(vq));
+    grow_q = axpy_st<T>(grow_q, cum0, St<T>::to_d(vq));
     if (q < g.ld) grow[q] = grow_q;
   }
   double best = -INFINITY;
@@ -371,10 +373,13 @@ __global__ __launch_bounds__(kScoreThreads) void k_mon_score(
     const double2 gE = cmul(St<T>::to_d(grow_q), St<T>::to_d(Eq));
     best = score_pixel(g, (int)q, cur, dq, gE, Em0, mask, scores, &bad, F);
   } else if (moved && q < g.R) {
-    E[q] = emon[q - g.N];
+    E[q] = emq;
   }
   score_block_end(g, best, (int)(q < g.N ? q : g.N), true, F, tau, partial, pfirst, nblk, sh, shi);
   if (bad) atomicOr(status, GFO_STATUS_NONFINITE);
+  // the move's bookkeeping (nothing in this launch reads it)
+  if (!moved && apply_prev && q == 0 && sn.pad1) atomicOr(status, GFO_STATUS_SINGULAR);
+  if (moved && q == 0) record_move(sn, flips, flip_cap, n_flips, status, count);
 }
 
 __global__ void k_dl_reset(int32_t* count) {
