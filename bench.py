@@ -36,8 +36,8 @@ MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # dense FP32 / FP64 matrix p
 FETCH_SCALE = 2097152.0 / 1048599.75
 WRITE_SCALE = 1.0
 PMC_TRAFFIC = [
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_step.hip", "sha256": "ba19d3f156614bff5508ef76e53c53f54211d9cb4b179361daaeb5fdb8606911", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053783.0, "write_kib": 2105382.75},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_delay.hip", "sha256": "7f784adc6f3fafc38c4b68304829f996ddbc808d8cee2c1b08ea049cbd7f87f2", "workload": "square128_c64", "variant": "sym_pipe8_3m", "fetch_kib": 1014106.5, "write_kib": 2098155.4},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_rank1.hip", "sha256": "f9233914f923ea25d51ae1a538469ee73746eb0c9b044ddd9099fdd17677fbea", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053783.0, "write_kib": 2105344.25},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "4e130b18acf46cf774bd8e4c8b76888ad66200e8590a2a13812d9316d09643e3", "workload": "square128_c64", "variant": "up_pipe8_3m_nt", "fetch_kib": 816745.06, "write_kib": 1052672.0},
 ]
 
 

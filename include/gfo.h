@@ -289,10 +289,11 @@ const char* gfo_flush_variant_name(int32_t idx);              /* NULL if out of 
 int gfo_flush_set_variant(int32_t idx);                       /* GFO_EINVAL if out of range */
 int gfo_flush_get_variant(void);
 
-/* Timing hook: the next apply_flip or apply_flips_rank_k (on any stream)
- * records `before` on its stream immediately before its G-update kernel (the
- * streaming rank-1 kernel, or the matrix-core rank-k kernels) and `after`
- * immediately after it, then forgets both events.  Lets a caller time that
+/* Timing hook: the next G update (on any stream) records `before` on its
+ * stream immediately before its G-update kernel (the streaming rank-1 kernel
+ * of apply_flip, the matrix-core rank-k kernels of apply_flips_rank_k, or the
+ * design-block kernel of a deferred-mode flush) and `after` immediately after
+ * it, then forgets both events.  Lets a caller time that
  * kernel alone with hipEventElapsedTime.  Both NULL cancels a pending pair.
  * Host only; one pending pair per process. */
 int gfo_time_next_k1(hipEvent_t before, hipEvent_t after);

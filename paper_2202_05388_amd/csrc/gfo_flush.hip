@@ -589,6 +589,8 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // the timed interval is the design-block kernel alone
+    if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
     // the monitor rows (the FOM monitor's terms are stored as zeros)
     hipLaunchKernelGGL((k_flush_c64_tm<1, true>),
                        dim3((unsigned)((g.N + 63) / 64), (unsigned)((g.nmon + 63) / 64)), blk, 0, s,
@@ -598,9 +600,9 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
     e = launch_zgemm_update_f64(g, count, (const double2*)(w + L.dl_CUs),
                                 (const double2*)(w + L.dl_Vs), (double2*)st->G, s);
+    if (e == hipSuccess && after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
   }
   if (e != hipSuccess) return e;
-  if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
   return launch_dl_reset(g, st, L, s);
 }
 
