@@ -180,8 +180,9 @@ int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick,
  * The design block G_D is symmetric at every step (reciprocity of the medium,
  * and each pending term restricted to it is c v v^T), so in deferred mode the
  * library reads its entries from the upper triangle (row <= column) only, and
- * a complex64 flush may bring only that triangle up to date (variant
- * "up_pipe8_3m_nt", the default); it then sets state.lower_stale.  While
+ * the flushes (complex128, and the complex64 default "up_pipe8_3m_nt"),
+ * init_G0 and refresh_G bring only that triangle up to date; they then set
+ * state.lower_stale.  While
  * lower_stale is set, every call reads design entries from the upper
  * triangle, in eager mode too.  gfo_sync_lower copies the upper triangle into
  * the lower one for callers that read G directly. */
@@ -194,9 +195,10 @@ int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 /* gfo_sync_lower - copy the upper triangle of the design block into its strict
  * lower triangle (G[q, p] = G[p, q] for p < q < N) when state.lower_stale is
  * set, then clear it; a no-op otherwise.  Pending deferred terms are not
- * applied (call gfo_flush first for a current matrix).  init_G0 in deferred
- * mode (it fills the upper triangle only) and the complex64 upper-only flush
- * set the flag.  Asynchronous on `stream`. */
+ * applied (call gfo_flush first for a current matrix).  In deferred mode
+ * init_G0 and refresh_G (they write the upper triangle only), the complex128
+ * flush and the complex64 upper-only flush set the flag.  Asynchronous on
+ * `stream`. */
 int gfo_sync_lower(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 
 /* gfo_greedy_steps - n_steps greedy moves (paper Sec. II: score every
@@ -269,7 +271,8 @@ int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d
  * then rounds G and E once to the storage type.  Removes the rounding drift
  * of repeated rank-1 updates.  Requires init_G0 on this workspace and
  * |V| <= kmax (else GFO_STATUS_REFRESH_OVERFLOW and nothing is changed).
- * Synchronises `stream` once to read |V|. */
+ * In deferred mode the design block is written on and above its diagonal only
+ * (state.lower_stale set).  Synchronises `stream` once to read |V|. */
 int refresh_G(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 
 /* Autotuner hooks for the streaming rank-1 kernel of apply_flip: the kernel

@@ -357,7 +357,8 @@ int refresh_G(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   if (launch_dl_reset(g, st, L, stream) != hipSuccess) return GFO_EHIP;   // pending terms discarded
   st->pending_calls = 0;
   rc = launch_refresh(g, st, L, stream);
-  if (rc == GFO_OK) st->lower_stale = 0;                 // every entry rebuilt
+  // every entry rebuilt, or in deferred mode the upper triangle of the design block
+  if (rc == GFO_OK) st->lower_stale = st->delay > 0 ? 1 : 0;
   return rc;
 }
 

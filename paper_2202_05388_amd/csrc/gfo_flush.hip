@@ -601,6 +601,7 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
     e = launch_zgemm_update_f64(g, count, (const double2*)(w + L.dl_CUs),
                                 (const double2*)(w + L.dl_Vs), (double2*)st->G, s);
     if (e == hipSuccess && after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
+    st->lower_stale = 1;
   }
   if (e != hipSuccess) return e;
   return launch_dl_reset(g, st, L, s);

@@ -243,11 +243,14 @@ struct EpiAddG {
 };
 
 // A(m, k) = A[m * lda + k], or A[k * lda + m] when AT; K is clamped to *kdev when given.
+// skip_below > 0: tiles wholly below the diagonal within rows < skip_below are
+// not computed (deferred mode keeps the design block's upper triangle only).
 template <bool AT, bool BT, typename Epi>
 __global__ __launch_bounds__(256) void k_zgemm_f64(int M, int N, int K, const double2* __restrict__ A,
                                                    int64_t lda, const double2* __restrict__ B,
                                                    int64_t ldb, const int32_t* __restrict__ kdev,
-                                                   Epi epi) {
+                                                   Epi epi, int skip_below) {
+  if (skip_below > 0 && blockIdx.y > blockIdx.x && ((int64_t)blockIdx.y + 1) * 64 <= skip_below) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
   const int n0 = blockIdx.x * 64 + (w & 1) * 32;
@@ -361,22 +364,26 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, hipStream
     EpiStoreZ ez{Z, kp};
     hipLaunchKernelGGL((k_zgemm_f64<false, false, EpiStoreZ>), dim3((kp + 63) / 64, (g.R + 63) / 64),
                        dim3(256), 0, s, g.R, kp, kp, (const double2*)U, (int64_t)kp,
-                       (const double2*)(Aug + kp), (int64_t)2 * kp, (const int32_t*)nullptr, ez);
+                       (const double2*)(Aug + kp), (int64_t)2 * kp, (const int32_t*)nullptr, ez, 0);
     hipLaunchKernelGGL(k_rf_xE, dim3((kp + 255) / 256), dim3(256), 0, s, g, mon, (const int32_t*)V,
                        (const double2*)Aug, k, kp, x);
   }
   hipLaunchKernelGGL(k_rf_field<T>, dim3((g.R + 255) / 256), dim3(256), 0, s, g, mon,
                      (const double2*)U, (const double2*)x, k, kp, (T*)st->E);
-  // G = G0 + Z U_D^T over the N design columns (padding columns stay zero)
+  // G = G0 + Z U_D^T over the N design columns (padding columns stay zero); in
+  // deferred mode the design block on and above its diagonal only
   EpiG0<T> eg{g, table, mon, (T*)st->G, (double2*)st->diag64};
   hipLaunchKernelGGL((k_zgemm_f64<false, true, EpiG0<T>>), dim3((g.N + 63) / 64, (g.R + 63) / 64),
                      dim3(256), 0, s, g.R, g.N, kp, (const double2*)Z, (int64_t)kp,
-                     (const double2*)U, (int64_t)kp, (const int32_t*)nullptr, eg);
+                     (const double2*)U, (int64_t)kp, (const int32_t*)nullptr, eg,
+                     st->delay > 0 ? g.N : 0);
   return hipGetLastError() == hipSuccess ? GFO_OK : GFO_EHIP;
 }
 
-// Deferred-mode flush for complex128 storage: G[0:N, 0:N] += CU V^T over the
-// `count` pending terms (FP64 matrix cores).
+// Deferred-mode flush for complex128 storage: G[r, 0:N] += CU V^T over the
+// `count` pending terms (FP64 matrix cores), for the monitor rows and the design
+// block's tiles on and above its diagonal (the caller marks the lower triangle
+// out of date).
 hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const double2* CU,
                                    const double2* V, double2* G, hipStream_t s) {
   // slot-major terms: A(m, k) = CU[k * R + m], B(k, n) = V[k * ld + n]; all R
@@ -384,7 +391,7 @@ hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const dou
   // zeros)
   EpiAddG ep{g.ld, G};
   hipLaunchKernelGGL((k_zgemm_f64<true, false, EpiAddG>), dim3((g.N + 63) / 64, (g.R + 63) / 64),
-                     dim3(256), 0, s, g.R, g.N, GFO_MAX_DELAY, CU, (int64_t)g.R, V, g.ld, count, ep);
+                     dim3(256), 0, s, g.R, g.N, GFO_MAX_DELAY, CU, (int64_t)g.R, V, g.ld, count, ep, g.N);
   return hipGetLastError();
 }
 
