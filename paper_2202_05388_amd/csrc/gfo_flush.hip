@@ -168,8 +168,10 @@ __device__ __forceinline__ void tri_tile(int t, int nb, int& r, int& c) {
 // after the first H, and each ring entry is reloaded with the operands H steps
 // ahead as soon as its step is consumed.  The products accumulate from zero and
 // G is added in the epilogue: vector loads complete in issue order, so no
-// product waits for the G loads.  Every launch runs all GFO_MAX_DELAY / 2 steps
-// (a partial flush costs a full one).  Byte offsets are 32-bit: the launcher
+// product waits for the G loads.  A launch runs P steps of two terms (terms
+// past the count read as zeros): GFO_MAX_DELAY / 2, or for the upper-only
+// default the fewest of 8, 16 and 32 that cover the caller's bound on the
+// count.  Byte offsets are 32-bit: the launcher
 // uses this form only when GFO_MAX_DELAY * max(R, ld) * 8 < 2^31.  THREE_MULT
 // as in k_flush_c64_tm.
 //
@@ -195,7 +197,8 @@ __device__ __forceinline__ void tri_tile(int t, int nb, int& r, int& c) {
 // triangle is out of date, and readers take design entries from the upper
 // one).  Diagonal tiles are computed whole, their lower halves from the old
 // values.
-template <bool THREE_MULT, int H, bool XCD, bool SYM = false, bool NT = false, bool MIRROR = true>
+template <bool THREE_MULT, int H, bool XCD, bool SYM = false, bool NT = false, bool MIRROR = true,
+          int P = GFO_MAX_DELAY / 2>
 __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld,
                                                         const int32_t* __restrict__ count,
                                                         const float2* __restrict__ CU,
@@ -216,7 +219,6 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
   const int n = bx * 64 + (w & 1) * 32 + (lane & 31);
   const int h = lane >> 5;
   const int am = m0 + (lane & 31);
-  constexpr int P = GFO_MAX_DELAY / 2;
   static_assert(P % H == 0, "ring depth divides the step count");
   const __amdgpu_buffer_rsrc_t ra =
       __builtin_amdgcn_make_buffer_rsrc((void*)CU, (short)0, K * R * 8, kBufferDword3);
@@ -572,11 +574,21 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         break;
       }
       case 11: {
-        // upper triangle only; the lower one is out of date from here on
+        // upper triangle only; the lower one is out of date from here on.  The
+        // calls since the last flush bound the term count (a refused move
+        // records none), so a partial flush runs fewer steps.
         const int nb = (g.N + 63) / 64;
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false>),
-                           dim3((unsigned)(nb * (nb + 1) / 2)), blk, 0, s, g.N, g.R, g.ld, count, cu, vv,
-                           G, nb);
+        const dim3 tri((unsigned)(nb * (nb + 1) / 2));
+        const int bound = st->pending_calls;
+        if (bound <= 16)
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false, 8>), tri, blk, 0, s,
+                             g.N, g.R, g.ld, count, cu, vv, G, nb);
+        else if (bound <= 32)
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false, 16>), tri, blk, 0, s,
+                             g.N, g.R, g.ld, count, cu, vv, G, nb);
+        else
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false, 32>), tri, blk, 0, s,
+                             g.N, g.R, g.ld, count, cu, vv, G, nb);
         st->lower_stale = 1;
         break;
       }
