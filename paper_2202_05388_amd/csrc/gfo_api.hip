@@ -75,6 +75,11 @@ Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   L.cu = take(R * 16);
   L.v = take((size_t)ld * 16);
   L.emon = take((size_t)p->n_mon * 16);
+  L.snap2 = take(sizeof(Snap));
+  L.emon2 = take((size_t)p->n_mon * 16);
+  L.scores2 = take(N * p->n_eps * 8);
+  L.partial2 = take(kScoreMaxBlocks * 8);
+  L.pfirst2 = take(kScoreMaxBlocks * 4);
   L.rk_S = take(4096);
   L.rk_M = take(K * K * 16);
   L.rk_U64 = take(R * K * 16);
@@ -249,6 +254,39 @@ int gfo_greedy_steps(const gfo_problem* prob, gfo_state* st, int32_t n_steps, ui
   if (n_steps == 0) return GFO_OK;
   const Geo g = make_geo(prob, st);
   gfo_pick* internal = (gfo_pick*)((char*)st->work + L.picks);
+  if (st->delay > 0 && one_kernel_loop(g)) {
+    // one kernel per move (pick, gather, elementwise part, next scores)
+    const bool c64 = g.dtype == GFO_C64;
+    if ((c64 ? launch_move_scores<float2>(g, st, L, mask, tau, stream)
+             : launch_move_scores<double2>(g, st, L, mask, tau, stream)) != hipSuccess)
+      return GFO_EHIP;
+    for (int t = 0; t < n_steps; ++t) {
+      int flushed = 0;
+      if (st->pending_calls >= st->delay) {
+        // the previous move's pivot values and the term count reach memory
+        // before the flush
+        if (t > 0 && (c64 ? launch_move_finish<float2>(g, st, L, t - 1, stream)
+                          : launch_move_finish<double2>(g, st, L, t - 1, stream)) != hipSuccess)
+          return GFO_EHIP;
+        if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;
+        st->pending_calls = 0;
+        flushed = 1;
+      }
+      gfo_pick* pk = d_picks ? d_picks + t : internal;
+      if ((c64 ? launch_move<float2>(g, st, L, t, flushed, mask, tau, pk, stream)
+               : launch_move<double2>(g, st, L, t, flushed, mask, tau, pk, stream)) != hipSuccess)
+        return GFO_EHIP;
+      ++st->pending_calls;
+    }
+    if ((c64 ? launch_move_finish<float2>(g, st, L, n_steps - 1, stream)
+             : launch_move_finish<double2>(g, st, L, n_steps - 1, stream)) != hipSuccess)
+      return GFO_EHIP;
+    if (st->pending_calls >= st->delay) {
+      if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;
+      st->pending_calls = 0;
+    }
+    return GFO_OK;
+  }
   const bool fused = st->delay > 0 && (g.N + kScoreThreads - 1) / kScoreThreads <= kScoreMaxBlocks;
   if (!fused) {
     for (int t = 0; t < n_steps; ++t) {

@@ -119,10 +119,9 @@ __device__ __forceinline__ double2 buf_load<double2>(__amdgpu_buffer_rsrc_t r, u
 }
 
 template <typename T>
-__device__ __forceinline__ void gather_prefetch(const Geo& g, const int32_t* __restrict__ count,
-                                                const T* __restrict__ CUs,
-                                                const T* __restrict__ Vs, GatherPre<T>& pre) {
-  pre.cnt = __builtin_amdgcn_readfirstlane(*count);
+__device__ __forceinline__ void gather_prefetch_n(const Geo& g, int cnt, const T* __restrict__ CUs,
+                                                  const T* __restrict__ Vs, GatherPre<T>& pre) {
+  pre.cnt = cnt;
   const GatherElem el = gather_elem(g);
   // one resource per workgroup: its range ends at the term count
   const int64_t stride = el.mon ? g.R : g.ld;
@@ -133,6 +132,13 @@ __device__ __forceinline__ void gather_prefetch(const Geo& g, const int32_t* __r
 #pragma unroll
   for (int k = 0; k < kGatherBatch; ++k)
     pre.a[k] = buf_load<T>(r, off + (unsigned)((s0 + k) * stride * (int64_t)sizeof(T)));
+}
+
+template <typename T>
+__device__ __forceinline__ void gather_prefetch(const Geo& g, const int32_t* __restrict__ count,
+                                                const T* __restrict__ CUs,
+                                                const T* __restrict__ Vs, GatherPre<T>& pre) {
+  gather_prefetch_n<T>(g, __builtin_amdgcn_readfirstlane(*count), CUs, Vs, pre);
 }
 
 template <typename T>
@@ -391,6 +397,224 @@ hipError_t launch_dl_reset(const Geo&, gfo_state* st, const Layout& L, hipStream
   return hipGetLastError();
 }
 
+// One kernel per move (fused greedy loop, deferred mode, when the pixels fit
+// kScoreMaxBlocks summaries of kGatherElems).  Kernel t takes the pick of move t
+// from the summaries the previous kernel left, gathers row j and the monitor
+// rows of column j as k_select_gather does, then each row-entry lane applies
+// the move's elementwise part to its own pixel (E, FP64 diagonal, material,
+// FOM monitor row) and scores that pixel for move t + 1; wave 0 of each
+// workgroup leaves one summary per kGatherElems pixels.  Nothing is written
+// during a kernel that another workgroup of it reads: the pivot's values
+// (E[j], diag64[j], eps_idx[j], G[N+m0, j]) after the move travel in the
+// move's snapshot and reach memory in the next kernel, or in k_move_finish
+// (after the last move of a call and before a flush: the flush rewrites the
+// FOM monitor row, so it must see the pivot's entry); the fields at the
+// monitors go through emon buffers, and E[N+m] is written one kernel late; the
+// term count is carried by the snapshots (the first kernel of a call, and the
+// flush, read it from memory, which k_move_finish brings up to date);
+// snapshots, scores and summaries alternate between two sets of buffers.  The expressions are those of the per-call path (k_gather_dl,
+// k_mon_dl, k_score), so the state and the picks are bit for bit the same.
+template <typename T>
+__global__ __launch_bounds__(256) void k_move(
+    Geo g, int has_prev, int flushed, const Snap* __restrict__ snap_prev,
+    Snap* __restrict__ snap_out, const double* __restrict__ scores_prev,
+    const double* __restrict__ partial_prev, const int* __restrict__ pfirst_prev, int nblk_prev,
+    int bpix_prev, double* __restrict__ scores_next, double* __restrict__ partial_next,
+    int* __restrict__ pfirst_next, const T* __restrict__ emon_prev, T* __restrict__ emon_next,
+    uint32_t mask, double tau, gfo_pick* __restrict__ pick_out, T* __restrict__ G,
+    T* __restrict__ E, double2* __restrict__ diag64, uint8_t* __restrict__ eps_idx,
+    const int32_t* __restrict__ count, int32_t* __restrict__ flips, int flip_cap,
+    int32_t* __restrict__ n_flips, int32_t* __restrict__ status, T* __restrict__ CUs,
+    T* __restrict__ Vs) {
+  __shared__ T yj[2][GFO_MAX_DELAY];              // V_s[j] (monitor rows), CU_s[j] (row entries)
+  __shared__ double2 part[kGatherParts - 1][kGatherElems];
+  const T zero = St<T>::from_d(make_double2(0.0, 0.0));
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const GatherElem el = gather_elem(g);
+  const int64_t e = el.e, i = el.i, q = el.q;
+  const bool mon = el.mon, live = el.live;
+  T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
+  // loads that need nothing else: the summaries first, then this lane's own
+  // values (its pixel, or its monitor's field)
+  PickPre pp;
+  pick_wave_load(partial_prev, pfirst_prev, nblk_prev, pp);
+  const int64_t qc = q < g.N ? q : g.N - 1;
+  const T Eown = E[mon ? i : qc];
+  const double2 dq = diag64[qc];
+  const int curq = eps_idx[qc];
+  const T gq = grow[qc];
+  const T emon_e = has_prev && mon ? emon_prev[live ? e : 0] : Eown;
+  const T em0_prev = has_prev ? emon_prev[g.m0] : E[g.N + g.m0];
+  __builtin_amdgcn_sched_barrier(0);
+  Snap sp;
+  sp.j = -1;
+  sp.cnt_after = 0;
+  if (has_prev) sp = *snap_prev;
+  // after a flush the previous move's values are in memory (k_move_finish ran
+  // before it, so that the flush saw them)
+  const bool carry = has_prev && !flushed;
+  const int cnt = flushed ? 0 : (has_prev ? sp.cnt_after : *count);
+  GatherPre<T> pre;
+  gather_prefetch_n<T>(g, cnt, CUs, Vs, pre);
+  __builtin_amdgcn_sched_barrier(0);
+  const double fom = cabs2(St<T>::to_d(em0_prev));
+  const gfo_pick pk = pick_wave_take(g, fom, pp, scores_prev, tau, false, bpix_prev);
+  const int jc = __builtin_amdgcn_readfirstlane(pk.pixel >= 0 && pk.pixel < g.N ? pk.pixel : 0);
+  // the pivot's values before this move (the previous pivot's from its snapshot)
+  const bool ovr = carry && sp.j >= 0 && sp.j == jc;
+  int cur = eps_idx[jc];
+  double2 dj = diag64[jc];
+  T Ej = E[jc], gm0j = grow[jc];
+  if (ovr) {
+    cur = sp.e_new;
+    dj = sp.dj_new;
+    Ej = St<T>::from_d(sp.Ej_new);
+    gm0j = St<T>::from_d(sp.gm0_new);
+  }
+  T base = zero;
+  if (w == 0) base = mon ? (e == g.m0 ? gm0j : G[i * g.ld + jc]) : G[g_at(g, jc, q)];
+  if (threadIdx.x < cnt) yj[0][threadIdx.x] = Vs[(int64_t)threadIdx.x * g.ld + jc];
+  if (threadIdx.x >= 64 && threadIdx.x - 64 < cnt)
+    yj[1][threadIdx.x - 64] = CUs[(int64_t)(threadIdx.x - 64) * g.R + jc];
+  const Snap sn = deferred_snapshot<T>(g, pk, cur, dj, Ej, cnt);
+  const int j = __builtin_amdgcn_readfirstlane(sn.j);
+  const bool moved = j >= 0;
+  // the FOM monitor's term entry and field after the move, alike everywhere
+  const T cu_m0 = moved ? St<T>::from_d(cmul(sn.c, St<T>::to_d(gm0j))) : zero;
+  const T em0_new = moved ? axpy_st<T>(em0_prev, cu_m0, sn.Ej) : em0_prev;
+  __syncthreads();
+  const bool terms = moved && (mon ? e != g.m0 : (q < g.N && q != j));
+  const int s0 = w * kGatherBatch;
+  double2 acc = make_double2(0.0, 0.0);
+  if (terms) {
+#pragma unroll
+    for (int k = 0; k < kGatherBatch; ++k)
+      if (s0 + k < cnt) acc = cadd(acc, cmul(St<T>::to_d(pre.a[k]), St<T>::to_d(yj[mon ? 0 : 1][s0 + k])));
+  }
+  if (w > 0) part[w - 1][lane] = acc;
+  __syncthreads();
+  if (w != 0) return;
+  acc = cadd(cadd(acc, part[0][lane]), cadd(part[1][lane], part[2][lane]));
+  const int slot = cnt;
+  double best = -INFINITY;
+  double F[GFO_MAX_EPS];
+  bool bad = false;
+  if (mon) {
+    if (live) {
+      if (has_prev) E[i] = emon_e;                // the previous move's field (no reader here)
+      T em = emon_e;
+      if (moved) {
+        const double2 u = e != g.m0 ? cadd(St<T>::to_d(base), acc) : St<T>::to_d(base);
+        const T cu = St<T>::from_d(cmul(sn.c, u));
+        CUs[(int64_t)slot * g.R + i] = e != g.m0 ? cu : zero;
+        em = axpy_st<T>(em, cu, sn.Ej);
+      }
+      emon_next[e] = em;
+    }
+  } else if (live) {
+    T vv = zero, cuq = zero;
+    if (moved) {
+      double2 v = make_double2(0.0, 0.0);
+      if (q < g.N) v = q == j ? sn.dj : cadd(St<T>::to_d(base), acc);
+      vv = St<T>::from_d(v);
+      Vs[(int64_t)slot * g.ld + q] = vv;
+      if (q < g.N) {
+        cuq = St<T>::from_d(cmul(sn.c, v));
+        CUs[(int64_t)slot * g.R + q] = cuq;
+      }
+    }
+    if (q < g.N) {
+      // pixel q before this move (the previous pivot's values from its snapshot)
+      const bool prevp = carry && sp.j >= 0 && q == sp.j;
+      T Ec = prevp ? St<T>::from_d(sp.Ej_new) : Eown;
+      double2 dc = prevp ? sp.dj_new : dq;
+      int cc = prevp ? sp.e_new : curq;
+      T gc = prevp ? St<T>::from_d(sp.gm0_new) : gq;
+      if (moved) {
+        Ec = axpy_st<T>(Ec, cuq, sn.Ej);
+        if (q == j) {
+          dc = cmul(sn.dj, rdiv(1.0, make_double2(1.0 - sn.alpha * sn.dj.x, -sn.alpha * sn.dj.y)));
+          cc = sn.e_new;
+        } else {
+          dc = cadd(dc, cmul(St<T>::to_d(cuq), St<T>::to_d(vv)));
+        }
+        gc = axpy_st<T>(gc, cu_m0, St<T>::to_d(vv));
+      }
+      if ((moved || prevp) && !(moved && q == j)) {
+        E[q] = Ec;
+        diag64[q] = dc;
+        eps_idx[q] = (uint8_t)cc;
+        grow[q] = gc;
+      }
+      const double2 gE = cmul(St<T>::to_d(gc), St<T>::to_d(Ec));
+      best = score_pixel(g, (int)q, cc, dc, gE, St<T>::to_d(em0_new), mask, scores_next, &bad, F);
+    }
+  }
+  if (!mon) {
+    // this workgroup's pixels: its best score and the lowest index within the
+    // tie band of that best
+    const double bb = wave_max(best);
+    int f = 0x7fffffff;
+    if (live && q < g.N && bb > -INFINITY) f = first_at_least(g, (int)q, F, tie_threshold(bb, tau));
+    f = wave_min(f);
+    const int64_t pb = (int64_t)blockIdx.x - gather_mpad(g) / kGatherElems;
+    if (lane == 0 && pb * kGatherElems < g.N) {
+      partial_next[pb] = bb;
+      pfirst_next[pb] = f;
+    }
+  }
+  if (bad) atomicOr(status, GFO_STATUS_NONFINITE);
+  if (blockIdx.x == 0 && lane == 0) {
+    *snap_out = sn;
+    snap_out->cnt_after = moved ? cnt + 1 : cnt;
+    if (moved) {
+      const T cuj = St<T>::from_d(cmul(sn.c, sn.dj));
+      snap_out->Ej_new = St<T>::to_d(axpy_st<T>(Ej, cuj, sn.Ej));
+      snap_out->dj_new =
+          cmul(sn.dj, rdiv(1.0, make_double2(1.0 - sn.alpha * sn.dj.x, -sn.alpha * sn.dj.y)));
+      snap_out->gm0_new = St<T>::to_d(axpy_st<T>(gm0j, cu_m0, St<T>::to_d(St<T>::from_d(sn.dj))));
+      // the history (the term count stays in the snapshots)
+      const int n = *n_flips;
+      if (n < flip_cap) {
+        flips[2 * n] = sn.j;
+        flips[2 * n + 1] = sn.e_new;
+      } else {
+        atomicOr(status, GFO_STATUS_HISTORY_FULL);
+      }
+      *n_flips = n + 1;
+    } else if (sn.pad1) {
+      atomicOr(status, GFO_STATUS_SINGULAR);
+    }
+    gfo_pick rec = pk;
+    if (rec.pixel >= 0) {
+      rec.fom_new = scores_prev[rec.pixel * g.n_eps + rec.eps_idx];
+      rec.dfom = rec.fom_new - fom;
+    }
+    *pick_out = rec;
+  }
+}
+
+// After move t of a one-kernel loop (its last, or before a flush): the move's
+// pivot values, the fields at the monitors and the term count reach memory.
+template <typename T>
+__global__ void k_move_finish(Geo g, const Snap* __restrict__ snap_last,
+                              const T* __restrict__ emon_last, T* __restrict__ G,
+                              T* __restrict__ E, double2* __restrict__ diag64,
+                              uint8_t* __restrict__ eps_idx, int32_t* __restrict__ count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < g.nmon) E[g.N + t] = emon_last[t];
+  if (t == 0) {
+    const Snap sn = *snap_last;
+    *count = sn.cnt_after;
+    if (sn.j >= 0) {
+      E[sn.j] = St<T>::from_d(sn.Ej_new);
+      diag64[sn.j] = sn.dj_new;
+      eps_idx[sn.j] = (uint8_t)sn.e_new;
+      G[(int64_t)(g.N + g.m0) * g.ld + sn.j] = St<T>::from_d(sn.gm0_new);
+    }
+  }
+}
+
 template <typename T>
 hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* pick,
                                  hipStream_t s) {
@@ -454,6 +678,80 @@ hipError_t launch_fused_move(const Geo& g, gfo_state* st, const Layout& L, int a
                      (T*)(w + L.dl_Vs), cu, v, emon);
   return hipGetLastError();
 }
+
+// The one-kernel loop serves shapes whose pixels fit kScoreMaxBlocks summaries
+// of kGatherElems pixels.
+bool one_kernel_loop(const Geo& g) {
+  return (g.N + kGatherElems - 1) / kGatherElems <= kScoreMaxBlocks;
+}
+
+// One-kernel loop (k_move): move t of a call reads the buffer set t % 2 and
+// writes the other; `flushed`: a flush ran since the previous move.
+template <typename T>
+hipError_t launch_move(const Geo& g, gfo_state* st, const Layout& L, int t, int flushed,
+                       uint32_t mask, double tau, gfo_pick* pick_out, hipStream_t s) {
+  char* w = (char*)st->work;
+  Snap* snaps[2] = {(Snap*)(w + L.snap), (Snap*)(w + L.snap2)};
+  T* emons[2] = {(T*)(w + L.emon), (T*)(w + L.emon2)};
+  double* scores[2] = {(double*)(w + L.scores), (double*)(w + L.scores2)};
+  double* partial[2] = {(double*)(w + L.partial), (double*)(w + L.partial2)};
+  int* pfirst[2] = {(int*)(w + L.pfirst), (int*)(w + L.pfirst2)};
+  const int a = t & 1, b = a ^ 1;
+  // move 0 picks from the scoring kernel's summaries (kScoreThreads pixels each)
+  const int bpix = t == 0 ? kScoreThreads : kGatherElems;
+  const int nblk = (g.N + bpix - 1) / bpix;
+  const int64_t n = (int64_t)gather_mpad(g) + g.ld;
+  hipLaunchKernelGGL(k_move<T>, dim3((unsigned)((n + kGatherElems - 1) / kGatherElems)), dim3(256), 0,
+                     s, g, t > 0 ? 1 : 0, flushed, (const Snap*)snaps[b], snaps[a],
+                     (const double*)scores[a], (const double*)partial[a], (const int*)pfirst[a], nblk,
+                     bpix, scores[b], partial[b], pfirst[b], (const T*)emons[b], emons[a], mask, tau,
+                     pick_out, (T*)st->G, (T*)st->E, (double2*)st->diag64, st->eps_idx,
+                     (const int32_t*)(w + L.dl_hdr), st->flips, st->flip_cap, st->n_flips,
+                     st->status, (T*)(w + L.dl_CUs), (T*)(w + L.dl_Vs));
+  return hipGetLastError();
+}
+
+// After move t of a one-kernel loop: its last, or one before a flush.
+template <typename T>
+hipError_t launch_move_finish(const Geo& g, gfo_state* st, const Layout& L, int t, hipStream_t s) {
+  char* w = (char*)st->work;
+  const int a = t & 1;
+  const Snap* snap = (const Snap*)(w + (a ? L.snap2 : L.snap));
+  const T* emon = (const T*)(w + (a ? L.emon2 : L.emon));
+  hipLaunchKernelGGL(k_move_finish<T>, dim3((unsigned)((g.nmon + 255) / 256)), dim3(256), 0, s, g,
+                     snap, emon, (T*)st->G, (T*)st->E, (double2*)st->diag64, st->eps_idx,
+                     (int32_t*)(w + L.dl_hdr));
+  return hipGetLastError();
+}
+
+// Scores of the current state into the first buffer set (the start of a
+// one-kernel loop).
+template <typename T>
+hipError_t launch_move_scores(const Geo& g, gfo_state* st, const Layout& L, uint32_t mask,
+                              double tau, hipStream_t s) {
+  char* w = (char*)st->work;
+  const int nblk = (g.N + kScoreThreads - 1) / kScoreThreads;
+  const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
+  hipLaunchKernelGGL(k_mon_score<T>, dim3((unsigned)((nx + kScoreThreads - 1) / kScoreThreads)),
+                     dim3(kScoreThreads), 0, s, g, 0, (const Snap*)(w + L.snap),
+                     (const T*)(w + L.cu), (const T*)(w + L.v), (const T*)(w + L.emon), (T*)st->G,
+                     (T*)st->E, (double2*)st->diag64, st->eps_idx, st->flips, st->flip_cap,
+                     st->n_flips, st->status, (int32_t*)(w + L.dl_hdr), mask, tau,
+                     (double*)(w + L.scores), (double*)(w + L.partial), (int*)(w + L.pfirst), nblk);
+  return hipGetLastError();
+}
+
+template hipError_t launch_move<float2>(const Geo&, gfo_state*, const Layout&, int, int, uint32_t,
+                                        double, gfo_pick*, hipStream_t);
+template hipError_t launch_move<double2>(const Geo&, gfo_state*, const Layout&, int, int, uint32_t,
+                                         double, gfo_pick*, hipStream_t);
+template hipError_t launch_move_finish<float2>(const Geo&, gfo_state*, const Layout&, int, hipStream_t);
+template hipError_t launch_move_finish<double2>(const Geo&, gfo_state*, const Layout&, int, hipStream_t);
+template hipError_t launch_move_scores<float2>(const Geo&, gfo_state*, const Layout&, uint32_t, double,
+                                               hipStream_t);
+template hipError_t launch_move_scores<double2>(const Geo&, gfo_state*, const Layout&, uint32_t,
+                                                double, hipStream_t);
+
 template hipError_t launch_fused_move<float2>(const Geo&, gfo_state*, const Layout&, int, uint32_t,
                                               double, gfo_pick*, bool, hipStream_t);
 template hipError_t launch_fused_move<double2>(const Geo&, gfo_state*, const Layout&, int, uint32_t,

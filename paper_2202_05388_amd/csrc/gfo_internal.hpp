@@ -95,6 +95,11 @@ struct Snap {
   double2 c;          // alpha / (1 - alpha G_jj)
   double2 Ej;         // E[j] before the move
   double2 dj;         // G_jj before the move (FP64)
+  // one-kernel greedy loop: the pivot's values after the move (E[j] and
+  // G[N+m0, j] in the storage type's values, the FP64 diagonal), written to
+  // memory by the next kernel, and the term count after the move
+  double2 Ej_new, dj_new, gm0_new;
+  int32_t cnt_after, pad3, pad4, pad5;
 };
 
 constexpr int kScoreThreads = 256;
@@ -113,6 +118,9 @@ struct Layout {
   size_t cu;        // R x 16 B: c * G[:, j] (storage type)
   size_t v;         // ld x 16 B: G[j, :] (storage type), zero padded to ld
   size_t emon;      // nmon x 16 B: E at the monitors after the last gathered move
+  // second buffers of the one-kernel greedy loop (kernel t reads one set and
+  // writes the other)
+  size_t snap2, emon2, scores2, partial2, pfirst2;
   // rank-k
   size_t rk_S;      // header of the accepted set (pixels, contrasts, M E[S])
   size_t rk_M;      // K x K double2 (FP64 Woodbury core)
@@ -289,7 +297,8 @@ __device__ __forceinline__ void pick_wave_load(const double* __restrict__ partia
 // caller reads scores[pixel * n_eps + eps_idx] where it needs them).
 __device__ __forceinline__ gfo_pick pick_wave_take(const Geo& g, double fom, const PickPre& pp,
                                                    const double* __restrict__ scores, double tau,
-                                                   bool with_score = true) {
+                                                   bool with_score = true,
+                                                   int bpix = kScoreThreads) {
   gfo_pick pk;
   pk.pixel = -1;
   pk.eps_idx = -1;
@@ -327,7 +336,7 @@ __device__ __forceinline__ gfo_pick pick_wave_take(const Geo& g, double fom, con
   if (pb == m && pf != 0x7fffffff) {
     first = pf;
   } else {
-    const int total = g.N * g.n_eps, span = kScoreThreads * g.n_eps;
+    const int total = g.N * g.n_eps, span = bpix * g.n_eps;
     const int lo = bq * span, hi = min(lo + span, total);
     int f = 0x7fffffff;
     for (int i = lo + lane; i < hi; i += 64) {
@@ -382,6 +391,16 @@ hipError_t launch_region_pixels(const Geo& g, const gfo_state* st, const gfo_pic
                                 gfo_pick* out, hipStream_t s);
 hipError_t launch_choose_eps_greedy(const gfo_pick* top, int k, double eps, double u_explore,
                                     double u_choice, gfo_pick* out, hipStream_t s);
+// one-kernel greedy loop (deferred mode)
+bool one_kernel_loop(const Geo& g);
+template <typename T>
+hipError_t launch_move_scores(const Geo& g, gfo_state* st, const Layout& L, uint32_t mask,
+                              double tau, hipStream_t s);
+template <typename T>
+hipError_t launch_move(const Geo& g, gfo_state* st, const Layout& L, int t, int flushed,
+                       uint32_t mask, double tau, gfo_pick* pick_out, hipStream_t s);
+template <typename T>
+hipError_t launch_move_finish(const Geo& g, gfo_state* st, const Layout& L, int t, hipStream_t s);
 template <typename T>
 hipError_t launch_fused_move(const Geo& g, gfo_state* st, const Layout& L, int apply_prev,
                              uint32_t mask, double tau, gfo_pick* pick_out, bool flush_between,
