@@ -37,7 +37,7 @@ FETCH_SCALE = 2097152.0 / 1048599.75
 WRITE_SCALE = 1.0
 PMC_TRAFFIC = [
     {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_rank1.hip", "sha256": "f9233914f923ea25d51ae1a538469ee73746eb0c9b044ddd9099fdd17677fbea", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053783.0, "write_kib": 2105344.25},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "4e130b18acf46cf774bd8e4c8b76888ad66200e8590a2a13812d9316d09643e3", "workload": "square128_c64", "variant": "up_pipe8_3m_nt", "fetch_kib": 816745.06, "write_kib": 1052672.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "c9d5fcd7e1ebafa45f06af4336c3436b3d50ccdf58f622c4c7babd32c2dd67b2", "workload": "square128_c64", "variant": "up_pipe8_3m_nt", "fetch_kib": 817776.66, "write_kib": 1052672.0},
 ]
 
 
@@ -239,7 +239,7 @@ def time_deferred_graph(problem, steps, warmup, delay, fused=True):
 def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True):
     """Greedy steps with deferred rank-1 updates: E, the FP64 diagonal and the monitor
     rows every step, the design block by one rank-`delay` matrix-core product per
-    `delay` steps.  fused: gfo_greedy_steps (two kernels per move), else
+    `delay` steps.  fused: gfo_greedy_steps (one kernel per move), else
     score_candidates + apply_flip per move.  Times the flush kernel with HIP
     events on its stream."""
     import torch

@@ -206,10 +206,11 @@ int gfo_sync_lower(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
  * band tau, apply it as the rank-1 update), with the results of n_steps calls
  * of score_candidates (topk = 1, min_spacing = 0) each followed by apply_flip
  * on its pick: the same moves, bit for bit the same state.  In deferred mode
- * (delay > 0) a move takes two kernels instead of four: the previous move's
- * elementwise updates are fused into the scoring, and the pick into the pivot
- * gather (every workgroup repeats the pick; it reads only the scores).  Once
- * the stop rule refuses a move, the remaining steps are no-ops.
+ * (delay > 0) a move takes one kernel instead of four: every workgroup repeats
+ * the pick from the previous kernel's score summaries, gathers its share of
+ * the pivot row and column, applies the move to its own pixels and scores them
+ * for the next move (two kernels per move on grids of more than 65,536 pixels).
+ * Once the stop rule refuses a move, the remaining steps are no-ops.
  * d_picks: device array of n_steps records (the pick of each step, sentinel
  * when refused), or NULL.  n_steps >= 0; cand_mask and tau as for
  * score_candidates.  Asynchronous on `stream`. */
