@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void k_select_gather(
     T* __restrict__ v_out, T* __restrict__ emon) {
   // the summaries first: waiting for them then does not wait for the term
   // operands (vector loads complete in issue order)
-  PickPre pp;
+  PickPre<> pp;
   pick_wave_load(partial, pfirst, nblk, pp);
   const double fom = cabs2(St<T>::to_d(E[g.N + g.m0]));
   __builtin_amdgcn_sched_barrier(0);
@@ -414,7 +414,7 @@ hipError_t launch_dl_reset(const Geo&, gfo_state* st, const Layout& L, hipStream
 // flush, read it from memory, which k_move_finish brings up to date);
 // snapshots, scores and summaries alternate between two sets of buffers.  The expressions are those of the per-call path (k_gather_dl,
 // k_mon_dl, k_score), so the state and the picks are bit for bit the same.
-template <typename T>
+template <typename T, int PPL>
 __global__ __launch_bounds__(256) void k_move(
     Geo g, int has_prev, int flushed, const Snap* __restrict__ snap_prev,
     Snap* __restrict__ snap_out, const double* __restrict__ scores_prev,
@@ -434,10 +434,14 @@ __global__ __launch_bounds__(256) void k_move(
   const int64_t e = el.e, i = el.i, q = el.q;
   const bool mon = el.mon, live = el.live;
   T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
-  // loads that need nothing else: the summaries first, then this lane's own
-  // values (its pixel, or its monitor's field)
-  PickPre pp;
+  // loads that need nothing else: the summaries first, then the lane's operand
+  // of every slot of its wave's terms (those past the term count, not known
+  // yet, are not used), then this lane's own values (its pixel, or its
+  // monitor's field)
+  PickPre<PPL> pp;
   pick_wave_load(partial_prev, pfirst_prev, nblk_prev, pp);
+  GatherPre<T> pre;
+  gather_prefetch_n<T>(g, GFO_MAX_DELAY, CUs, Vs, pre);
   const int64_t qc = q < g.N ? q : g.N - 1;
   const T Eown = E[mon ? i : qc];
   const double2 dq = diag64[qc];
@@ -454,9 +458,6 @@ __global__ __launch_bounds__(256) void k_move(
   // before it, so that the flush saw them)
   const bool carry = has_prev && !flushed;
   const int cnt = flushed ? 0 : (has_prev ? sp.cnt_after : *count);
-  GatherPre<T> pre;
-  gather_prefetch_n<T>(g, cnt, CUs, Vs, pre);
-  __builtin_amdgcn_sched_barrier(0);
   const double fom = cabs2(St<T>::to_d(em0_prev));
   const gfo_pick pk = pick_wave_take(g, fom, pp, scores_prev, tau, false, bpix_prev);
   const int jc = __builtin_amdgcn_readfirstlane(pk.pixel >= 0 && pk.pixel < g.N ? pk.pixel : 0);
@@ -701,7 +702,10 @@ hipError_t launch_move(const Geo& g, gfo_state* st, const Layout& L, int t, int 
   const int bpix = t == 0 ? kScoreThreads : kGatherElems;
   const int nblk = (g.N + bpix - 1) / bpix;
   const int64_t n = (int64_t)gather_mpad(g) + g.ld;
-  hipLaunchKernelGGL(k_move<T>, dim3((unsigned)((n + kGatherElems - 1) / kGatherElems)), dim3(256), 0,
+  // summaries per lane: 4 while the grid has at most 256 of 64 pixels
+  const bool small = (g.N + kGatherElems - 1) / kGatherElems <= 4 * 64;
+  hipLaunchKernelGGL((small ? k_move<T, 4> : k_move<T, kPickPerLane>),
+                     dim3((unsigned)((n + kGatherElems - 1) / kGatherElems)), dim3(256), 0,
                      s, g, t > 0 ? 1 : 0, flushed, (const Snap*)snaps[b], snaps[a],
                      (const double*)scores[a], (const double*)partial[a], (const int*)pfirst[a], nblk,
                      bpix, scores[b], partial[b], pfirst[b], (const T*)emons[b], emons[a], mask, tau,

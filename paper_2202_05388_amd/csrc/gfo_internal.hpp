@@ -269,20 +269,24 @@ __device__ inline gfo_pick greedy_pick_block(const Geo& g, double fom,
 // operations and takes the winning workgroup's entries from the lane that
 // holds them, so the pick costs one round trip to memory (plus a scan of one
 // workgroup's scores in a near-tie across workgroups).  Same decisions as
-// greedy_pick_block (exact max and min).
+// greedy_pick_block (exact max and min).  PPL summaries per lane: up to 64 PPL
+// workgroup summaries (the caller picks the smallest that covers its grid, as
+// the reductions walk every register).
 constexpr int kPickPerLane = kScoreMaxBlocks / 64;
 
+template <int PPL = kPickPerLane>
 struct PickPre {
-  double pv[kPickPerLane];
-  int pf[kPickPerLane];
+  double pv[PPL];
+  int pf[PPL];
 };
 
+template <int PPL>
 __device__ __forceinline__ void pick_wave_load(const double* __restrict__ partial,
                                                const int* __restrict__ pfirst, int nblk,
-                                               PickPre& pp) {
+                                               PickPre<PPL>& pp) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int k = 0; k < kPickPerLane; ++k) {
+  for (int k = 0; k < PPL; ++k) {
     const int i = lane + 64 * k;
     pp.pv[k] = -INFINITY;
     pp.pf[k] = 0x7fffffff;
@@ -295,7 +299,8 @@ __device__ __forceinline__ void pick_wave_load(const double* __restrict__ partia
 
 // with_score = false leaves fom_new and dfom of an accepted pick unset (the
 // caller reads scores[pixel * n_eps + eps_idx] where it needs them).
-__device__ __forceinline__ gfo_pick pick_wave_take(const Geo& g, double fom, const PickPre& pp,
+template <int PPL>
+__device__ __forceinline__ gfo_pick pick_wave_take(const Geo& g, double fom, const PickPre<PPL>& pp,
                                                    const double* __restrict__ scores, double tau,
                                                    bool with_score = true,
                                                    int bpix = kScoreThreads) {
@@ -307,13 +312,13 @@ __device__ __forceinline__ gfo_pick pick_wave_take(const Geo& g, double fom, con
   const int lane = threadIdx.x & 63;
   double m = -INFINITY;
 #pragma unroll
-  for (int k = 0; k < kPickPerLane; ++k) m = fmax(m, pp.pv[k]);
+  for (int k = 0; k < PPL; ++k) m = fmax(m, pp.pv[k]);
   m = wave_max(m);
   if (!(m > fom * (1.0 + tau))) return pk;
   const double thr = tie_threshold(m, tau);
   int bq = 0x7fffffff;
 #pragma unroll
-  for (int k = kPickPerLane - 1; k >= 0; --k)
+  for (int k = PPL - 1; k >= 0; --k)
     if (pp.pv[k] >= thr) bq = lane + 64 * k;
   bq = __builtin_amdgcn_readfirstlane(wave_min(bq));
   // workgroup bq's summary, from lane bq % 64, register bq / 64
@@ -321,7 +326,7 @@ __device__ __forceinline__ gfo_pick pick_wave_take(const Geo& g, double fom, con
   double pvb = -INFINITY;
   int pfb = 0x7fffffff;
 #pragma unroll
-  for (int k = 0; k < kPickPerLane; ++k) {
+  for (int k = 0; k < PPL; ++k) {
     if (k == kb) {
       pvb = pp.pv[k];
       pfb = pp.pf[k];
