@@ -293,6 +293,14 @@ const char* gfo_flush_variant_name(int32_t idx);              /* NULL if out of 
 int gfo_flush_set_variant(int32_t idx);                       /* GFO_EINVAL if out of range */
 int gfo_flush_get_variant(void);
 
+/* Test and benchmark hook for gfo_greedy_steps in deferred mode: form 0
+ * (default) runs one kernel per move on grids of up to 65,536 pixels and two
+ * kernels per move above; form 1 runs two kernels per move on every grid.  Both
+ * forms make the same moves and leave bit for bit the same state.
+ * Process-wide; host only. */
+int gfo_loop_set_form(int32_t form);                          /* GFO_EINVAL unless 0 or 1 */
+int gfo_loop_get_form(void);
+
 /* Timing hook: the next G update (on any stream) records `before` on its
  * stream immediately before its G-update kernel (the streaming rank-1 kernel
  * of apply_flip, the matrix-core rank-k kernels of apply_flips_rank_k, or the

@@ -27,6 +27,7 @@ EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "g
            "gfo_k1_variant_count", "gfo_k1_variant_name", "gfo_k1_set_variant",
            "gfo_k1_get_variant", "gfo_time_next_k1", "gfo_flush", "gfo_flush_variant_count",
            "gfo_flush_variant_name", "gfo_flush_set_variant", "gfo_flush_get_variant",
+           "gfo_loop_set_form", "gfo_loop_get_form",
            "gfo_greedy_steps", "gfo_choose_eps_greedy", "score_regions", "gfo_region_pixels",
            "gfo_sync_lower")
 
@@ -89,6 +90,7 @@ def lib():
     L.gfo_flush_variant_name.argtypes = [C.c_int32]
     L.gfo_flush_variant_name.restype = C.c_char_p
     L.gfo_flush_set_variant.argtypes = [C.c_int32]
+    L.gfo_loop_set_form.argtypes = [C.c_int32]
     L.gfo_k1_variant_count.argtypes = [C.c_int32]
     L.gfo_k1_variant_name.argtypes = [C.c_int32, C.c_int32]
     L.gfo_k1_variant_name.restype = C.c_char_p
@@ -205,3 +207,13 @@ def flush_set_variant(idx: int) -> None:
 
 def flush_get_variant() -> int:
     return lib().gfo_flush_get_variant()
+
+
+def loop_set_form(form: int) -> None:
+    """Deferred-mode greedy loop: 0 automatic (one kernel per move where the grid
+    allows), 1 two kernels per move."""
+    check(lib().gfo_loop_set_form(form), "gfo_loop_set_form")
+
+
+def loop_get_form() -> int:
+    return lib().gfo_loop_get_form()

@@ -5,7 +5,13 @@
 #include <math.h>
 #include <string.h>
 
+#include <atomic>
+
 namespace gfo {
+
+// Form of the deferred-mode greedy loop (gfo_loop_set_form): 0 automatic, 1
+// two kernels per move.
+static std::atomic<int> g_loop_form{0};
 
 int find_bg(const gfo_problem* p) {
   for (int i = 0; i < p->n_eps; ++i)
@@ -254,7 +260,7 @@ int gfo_greedy_steps(const gfo_problem* prob, gfo_state* st, int32_t n_steps, ui
   if (n_steps == 0) return GFO_OK;
   const Geo g = make_geo(prob, st);
   gfo_pick* internal = (gfo_pick*)((char*)st->work + L.picks);
-  if (st->delay > 0 && one_kernel_loop(g)) {
+  if (st->delay > 0 && g_loop_form.load() == 0 && one_kernel_loop(g)) {
     // one kernel per move (pick, gather, elementwise part, next scores)
     const bool c64 = g.dtype == GFO_C64;
     if ((c64 ? launch_move_scores<float2>(g, st, L, mask, tau, stream)
@@ -410,6 +416,13 @@ int gfo_flush_variant_count(void) { return flush_variant_count(); }
 const char* gfo_flush_variant_name(int32_t idx) { return flush_variant_name(idx); }
 int gfo_flush_set_variant(int32_t idx) { return flush_set_variant(idx); }
 int gfo_flush_get_variant(void) { return flush_get_variant(); }
+
+int gfo_loop_set_form(int32_t form) {
+  if (form != 0 && form != 1) return GFO_EINVAL;
+  g_loop_form.store(form);
+  return GFO_OK;
+}
+int gfo_loop_get_form(void) { return g_loop_form.load(); }
 
 int gfo_time_next_k1(hipEvent_t before, hipEvent_t after) {
   if ((before == nullptr) != (after == nullptr)) return GFO_EINVAL;

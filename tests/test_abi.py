@@ -166,3 +166,20 @@ def test_sync_lower_validates_and_is_a_no_op_when_current():
     st.lower_stale = 2
     assert lib.gfo_sync_lower(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
     assert lib.gfo_flush(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
+
+
+def test_loop_form_hook_validates_and_round_trips():
+    """gfo_loop_set_form accepts 0 (automatic) and 1 (two kernels per move) only;
+    host-side state, no device work."""
+    lib = L.lib()
+    old = L.loop_get_form()
+    assert old == 0
+    try:
+        assert lib.gfo_loop_set_form(2) == L.GFO_EINVAL
+        assert lib.gfo_loop_set_form(-1) == L.GFO_EINVAL
+        assert L.loop_get_form() == old
+        L.loop_set_form(1)
+        assert L.loop_get_form() == 1
+    finally:
+        L.loop_set_form(old)
+    assert L.loop_get_form() == 0

@@ -162,19 +162,28 @@ def test_flush_variants_agree():
     assert len(states) == len(names)
 
 
-@pytest.mark.parametrize("dtype,delay,poll", [("c128", 16, 25), ("c64", 64, 32), ("c64", 7, 10),
-                                               ("c64", 0, 20)])
-def test_greedy_steps_equal_per_call_path(dtype, delay, poll):
+@pytest.mark.parametrize("dtype,delay,poll,form", [("c128", 16, 25, 0), ("c64", 64, 32, 0),
+                                                    ("c64", 7, 10, 0), ("c64", 0, 20, 0),
+                                                    ("c128", 16, 25, 1), ("c64", 64, 32, 1),
+                                                    ("c64", 7, 10, 1)])
+def test_greedy_steps_equal_per_call_path(dtype, delay, poll, form):
     """gfo_greedy_steps (fused kernels in deferred mode) makes the same moves and
     leaves bit for bit the same state as score_candidates + apply_flip per move,
-    including the flushes, the stop and the refresh boundary."""
+    including the flushes, the stop and the refresh boundary.  form 0: one kernel
+    per move on this grid; form 1: the two-kernel loop of larger grids."""
+    from paper_2202_05388_amd import _lib as L
     p = W.tiny(40, 44, n_mon=8, dtype=dtype, cand_mask=W.MASK_BOTH)   # stops after ~130 moves
     ref = _job(p, delay=delay, kmax=256)
     ref.init()
     n_ref = ref.run_greedy(400, poll_every=poll, refresh_every=50)
     job = _job(p, delay=delay, kmax=256)
     job.init()
-    n = job.run_greedy(400, poll_every=poll, refresh_every=50, fused=True)
+    old = L.loop_get_form()
+    L.loop_set_form(form)
+    try:
+        n = job.run_greedy(400, poll_every=poll, refresh_every=50, fused=True)
+    finally:
+        L.loop_set_form(old)
     assert n == n_ref and n > 100
     assert np.array_equal(job.history(), ref.history())
     assert job.state.pending_calls == ref.state.pending_calls
