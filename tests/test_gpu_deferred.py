@@ -59,19 +59,27 @@ def test_deferred_square32_fp64_matches_stored_oracle():
     assert _rel(E[p.n:], Emon) <= 1e-9
 
 
-def test_deferred_square128_c64_matches_oracle():
+@pytest.mark.parametrize("fused", [False, True])
+def test_deferred_square128_c64_matches_oracle(fused):
+    """128 x 128 pixels, complex64, deferred rank-1 updates flushed every 64 moves,
+    chunks of 32 moves, refresh every 256 (the benchmark's configuration); fused:
+    gfo_greedy_steps (one kernel per move), else score_candidates + apply_flip.
+    The fields at the monitors and at sampled pixels after 100 moves, the move
+    sequence (up to certified ties) and the final FOM match the FP64 oracle."""
     from test_gpu_refresh import certify_sequence
     gold = json.load(open(os.path.join(HERE, "golden", "square128_fp64.json")))
     p = W.SQUARE_128
     N = p.n
-    job = _job(p, delay=64)
+    job = _job(p, delay=64, kmax=512)
     job.init()
-    assert job.run_greedy(100, poll_every=32) == 100
-    E = job.E.cpu().numpy().astype(np.complex128)
+    assert job.run_greedy(100, poll_every=32, refresh_every=256, fused=fused) == 100
+    E = job.E.cpu().numpy().astype(np.complex128)      # E is current in deferred mode
     ck = gold["checkpoints"]["100"]
     Em = np.array([complex(*z) for z in ck["E_mon"]])
     assert _rel(E[N:], Em) <= 1e-4
-    job.run_greedy(2000, poll_every=32)
+    Ep = np.array([complex(*z) for z in ck["E_pix"]])
+    assert _rel(E[gold["sample_pixels"]], Ep) <= 1e-4
+    job.run_greedy(2000, poll_every=32, refresh_every=256, fused=fused)
     hist = [(int(a), int(b)) for a, b in job.history()]
     gp = [(s["pixel"], s["eps_idx"]) for s in gold["steps"]]
     t = certify_sequence(p, gp, hist)

@@ -23,20 +23,23 @@ def _c(z):
     return np.array([complex(*v) for v in z])
 
 
-@pytest.mark.parametrize("delay", [0, 64])
-def test_strip48x2048_c64_matches_oracle(delay):
+@pytest.mark.parametrize("delay,fused", [(0, False), (64, False), (64, True)])
+def test_strip48x2048_c64_matches_oracle(delay, fused):
+    """fused: gfo_greedy_steps, as the benchmark drives the strip (two kernels per
+    move on a grid of this size), else score_candidates + apply_flip per move."""
     import torch
     from paper_2202_05388_amd.job import Job
     gold = json.load(open(os.path.join(HERE, "golden", "strip48x2048_fp64.json")))
     p = W.STRIP_48x2048
     N = p.n
-    print(f"[case] {p.name}: G {p.storage_bytes() / 1e9:.1f} GB, delay {delay}", flush=True)
+    print(f"[case] {p.name}: G {p.storage_bytes() / 1e9:.1f} GB, delay {delay}, fused {fused}",
+          flush=True)
     job = Job(p, device="cuda:0", kmax=512, delay=delay)
     job.init()
     fields = {}
     done = 0
     for ck in sorted(int(k) for k in gold["checkpoints"]):
-        done += job.run_greedy(ck - done, poll_every=50, refresh_every=256)
+        done += job.run_greedy(ck - done, poll_every=50, refresh_every=256, fused=fused)
         if done < ck:
             break
         E = job.E.cpu().to(torch.complex128).numpy()
