@@ -170,17 +170,18 @@ def test_flush_variants_agree():
     assert len(states) == len(names)
 
 
-@pytest.mark.parametrize("dtype,delay,poll,form", [("c128", 16, 25, 0), ("c64", 64, 32, 0),
-                                                    ("c64", 7, 10, 0), ("c64", 0, 20, 0),
-                                                    ("c128", 16, 25, 1), ("c64", 64, 32, 1),
-                                                    ("c64", 7, 10, 1)])
-def test_greedy_steps_equal_per_call_path(dtype, delay, poll, form):
+@pytest.mark.parametrize("dtype,delay,poll,form,n_mon", [
+    ("c128", 16, 25, 0, 8), ("c64", 64, 32, 0, 8), ("c64", 7, 10, 0, 8), ("c64", 0, 20, 0, 8),
+    ("c128", 16, 25, 1, 8), ("c64", 64, 32, 1, 8), ("c64", 7, 10, 1, 8),
+    ("c64", 16, 10, 0, 150), ("c128", 16, 10, 1, 150)])
+def test_greedy_steps_equal_per_call_path(dtype, delay, poll, form, n_mon):
     """gfo_greedy_steps (fused kernels in deferred mode) makes the same moves and
     leaves bit for bit the same state as score_candidates + apply_flip per move,
     including the flushes, the stop and the refresh boundary.  form 0: one kernel
-    per move on this grid; form 1: the two-kernel loop of larger grids."""
+    per move on this grid; form 1: the two-kernel loop of larger grids.  150
+    monitors: three monitor workgroups, the FOM monitor (75) in the second."""
     from paper_2202_05388_amd import _lib as L
-    p = W.tiny(40, 44, n_mon=8, dtype=dtype, cand_mask=W.MASK_BOTH)   # stops after ~130 moves
+    p = W.tiny(40, 44, n_mon=n_mon, dtype=dtype, cand_mask=W.MASK_BOTH)   # ~130 moves
     ref = _job(p, delay=delay, kmax=256)
     ref.init()
     n_ref = ref.run_greedy(400, poll_every=poll, refresh_every=50)
@@ -199,6 +200,33 @@ def test_greedy_steps_equal_per_call_path(dtype, delay, poll, form):
     G, E, d, i = job.host_state()
     assert np.array_equal(G, Gr) and np.array_equal(E, Er) and np.array_equal(d, dr)
     assert np.array_equal(i, ir) and job.status() == ref.status() == 0
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_greedy_steps_history_full(form):
+    """Past the history capacity the fused loop flags GFO_STATUS_HISTORY_FULL,
+    keeps counting moves, and still makes the per-call path's moves and state."""
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(40, 44, n_mon=8, dtype="c64", cand_mask=W.MASK_BOTH)   # ~130 moves
+    ref = _job(p, delay=16, flip_cap=10)
+    ref.init()
+    for _ in range(30):
+        ref.step()
+    job = _job(p, delay=16, flip_cap=10)
+    job.init()
+    old = L.loop_get_form()
+    L.loop_set_form(form)
+    try:
+        job.greedy_steps(30)
+    finally:
+        L.loop_set_form(old)
+    assert job.n_flips() == ref.n_flips() == 30
+    assert job.status() == ref.status() == L.GFO_STATUS_HISTORY_FULL
+    assert np.array_equal(job.history(), ref.history()) and len(job.history()) == 10
+    Gr, Er, dr, ir = ref.host_state()
+    G, E, d, i = job.host_state()
+    assert np.array_equal(G, Gr) and np.array_equal(E, Er) and np.array_equal(d, dr)
+    assert np.array_equal(i, ir)
 
 
 def test_greedy_steps_picks_record_and_stop():
