@@ -180,7 +180,7 @@ int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick,
  * The design block G_D is symmetric at every step (reciprocity of the medium,
  * and each pending term restricted to it is c v v^T), so in deferred mode the
  * library reads its entries from the upper triangle (row <= column) only, and
- * the flushes (complex128, and the complex64 default "up_pipe8_3m_nt"),
+ * the flushes (complex128, and the complex64 default "up_pair4_3m_nt"),
  * init_G0 and refresh_G bring only that triangle up to date; they then set
  * state.lower_stale.  While
  * lower_stale is set, every call reads design entries from the upper

@@ -320,6 +320,111 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
   }
 }
 
+// Pair-interleaved copy of the pending terms (complex64): slots 2p and 2p + 1 of
+// index i side by side, CU2[p R + i] = (CU_2p[i], CU_2p+1[i]) and likewise V2
+// with ld, zero past the count, so that one 16-byte load brings a lane the
+// operands of two matrix steps.  Grid: x over max(R, ld) / 256, y over the pairs.
+__global__ __launch_bounds__(256) void k_flush_pack(int R, int64_t ld,
+                                                    const int32_t* __restrict__ count,
+                                                    const float2* __restrict__ CU,
+                                                    const float2* __restrict__ V,
+                                                    f32x4* __restrict__ CU2, f32x4* __restrict__ V2) {
+  const int K = *count;
+  const int p = (int)blockIdx.y;
+  if (2 * p >= K) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool second = 2 * p + 1 < K;
+  if (i < R) {
+    const float2 a = CU[(int64_t)(2 * p) * R + i];
+    const float2 b = second ? CU[(int64_t)(2 * p + 1) * R + i] : make_float2(0.f, 0.f);
+    CU2[(int64_t)p * R + i] = f32x4{a.x, a.y, b.x, b.y};
+  }
+  if (i < ld) {
+    const float2 a = V[(int64_t)(2 * p) * ld + i];
+    const float2 b = second ? V[(int64_t)(2 * p + 1) * ld + i] : make_float2(0.f, 0.f);
+    V2[(int64_t)p * ld + i] = f32x4{a.x, a.y, b.x, b.y};
+  }
+}
+
+// The upper-only three-product flush (k_flush_c64_pipe with SYM, NT, no
+// MIRROR) on the pair-interleaved terms: in pair step m, lane (row or column,
+// h) loads pair 2m + h, i.e. slots 4m + 2h and 4m + 2h + 1, and feeds them to
+// two matrix steps (the instruction sums its two k lanes, here slots 4m + 2h'
+// for h' = 0, 1 in the first step and 4m + 2h' + 1 in the second).  Half the
+// operand load instructions for the same bytes.  HP pair steps of operands in
+// registers; PP pair steps per launch (the count rounded up to 4 terms, as in
+// the P-step form).  The default complex64 flush: ring depths of 2 and 8 pair
+// steps measured no faster (8 drops to two waves per SIMD), nor did moving the
+// G tile in 16-byte pieces (adjacent lanes exchanging halves).
+template <int HP, int PP>
+__global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld,
+                                                        const int32_t* __restrict__ count,
+                                                        const f32x4* __restrict__ CU2,
+                                                        const f32x4* __restrict__ V2,
+                                                        float2* __restrict__ G, int nby) {
+  const int K = *count;
+  if (K == 0) return;
+  int by, bx;
+  tri_tile((int)blockIdx.x, nby, by, bx);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m0 = by * 64 + (w >> 1) * 32;
+  const int n = bx * 64 + (w & 1) * 32 + (lane & 31);
+  const int h = lane >> 5;
+  const int am = m0 + (lane & 31);
+  static_assert(PP % HP == 0, "ring depth divides the pair-step count");
+  const int np = (K + 1) / 2;
+  const __amdgpu_buffer_rsrc_t ra =
+      __builtin_amdgcn_make_buffer_rsrc((void*)CU2, (short)0, np * R * 16, kBufferDword3);
+  const __amdgpu_buffer_rsrc_t rb =
+      __builtin_amdgcn_make_buffer_rsrc((void*)V2, (short)0, (int)(np * ld * 16), kBufferDword3);
+  const unsigned a_off = am < M ? (unsigned)(h * R + am) * 16u : 0xFFFFFFF0u;
+  const unsigned a_step = am < M ? 2u * (unsigned)R * 16u : 0u;
+  const unsigned b_off = (unsigned)(h * ld + n) * 16u, b_step = 2u * (unsigned)ld * 16u;
+  f32x4 a[HP], b[HP];
+#pragma unroll
+  for (int i = 0; i < HP; ++i) {
+    a[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, a_off + i * a_step, 0, 0));
+    b[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb, b_off + i * b_step, 0, 0));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  float2 gv[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
+    const float2* src = G + (int64_t)(r < M ? r : M - 1) * ld + n;
+    gv[e] = __builtin_bit_cast(float2, __builtin_nontemporal_load((const f32x2*)src));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  f32x16 X, Y, Z;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) X[e] = Y[e] = Z[e] = 0.f;
+#pragma unroll
+  for (int i = 0; i < PP; ++i) {
+    const f32x4 ai = a[i % HP], bi = b[i % HP];
+    if (i + HP < PP) {
+      a[i % HP] = __builtin_bit_cast(
+          f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, a_off + (i + HP) * a_step, 0, 0));
+      b[i % HP] = __builtin_bit_cast(
+          f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb, b_off + (i + HP) * b_step, 0, 0));
+    }
+    X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
+    Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[1], bi[1], Y, 0, 0, 0);
+    Z = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0] + ai[1], bi[0] + bi[1], Z, 0, 0, 0);
+    X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[2], bi[2], X, 0, 0, 0);
+    Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[3], bi[3], Y, 0, 0, 0);
+    Z = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[2] + ai[3], bi[2] + bi[3], Z, 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
+    if (r < M) {
+      const float2 out = make_float2(gv[e].x + (X[e] - Y[e]), gv[e].y + (Z[e] - X[e] - Y[e]));
+      __builtin_nontemporal_store(f32x2{out.x, out.y}, (f32x2*)(G + (int64_t)r * ld + n));
+    }
+  }
+}
+
 // Warp-specialised persistent flush: one workgroup of 8 waves per CU walks the
 // 64 x 64 output tiles (tile id = blockIdx.x + i * gridDim.x; bx = id % nbx,
 // by = id / nbx).  Waves 0-3 only stream CU/V operands and issue matrix
@@ -484,9 +589,9 @@ __global__ __launch_bounds__(512) void k_flush_c64_ws(int M, int R, int64_t ld,
 static const char* const kFlushNames[] = {"w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8",
                                           "w32_pipe8_3m", "w32_pipe8_3m_xcd", "ws8_3m",
                                           "ws16_3m", "sym_pipe8_3m", "sym_pipe8_3m_nt",
-                                          "sym_pipe4_3m_nt", "up_pipe8_3m_nt"};
+                                          "sym_pipe4_3m_nt", "up_pipe8_3m_nt", "up_pair4_3m_nt"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
-constexpr int kFlushDefault = 11;
+constexpr int kFlushDefault = 12;
 static std::atomic<int> g_flush_sel{kFlushDefault};
 int flush_variant_count() { return kFlushCount; }
 const char* flush_variant_name(int i) { return i >= 0 && i < kFlushCount ? kFlushNames[i] : nullptr; }
@@ -589,6 +694,29 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         else
           hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false, 32>), tri, blk, 0, s,
                              g.N, g.R, g.ld, count, cu, vv, G, nb);
+        st->lower_stale = 1;
+        break;
+      }
+      case 12: {
+        // upper triangle only, pair-interleaved terms in the unused halves of
+        // the term buffers (complex64 slots take 8 of their 16 bytes)
+        const int nb = (g.N + 63) / 64;
+        f32x4* cu2 = (f32x4*)(w + L.dl_CUs + (size_t)GFO_MAX_DELAY * g.R * 8);
+        f32x4* vv2 = (f32x4*)(w + L.dl_Vs + (size_t)GFO_MAX_DELAY * g.ld * 8);
+        const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
+        hipLaunchKernelGGL(k_flush_pack, dim3((unsigned)((nx + 255) / 256), GFO_MAX_DELAY / 2), blk, 0, s,
+                           g.R, g.ld, count, cu, vv, cu2, vv2);
+        const dim3 tri((unsigned)(nb * (nb + 1) / 2));
+        const int bound = st->pending_calls;
+        if (bound <= 16)
+          hipLaunchKernelGGL((k_flush_c64_pair<4, 4>), tri, blk, 0, s, g.N, g.R, g.ld, count,
+                             (const f32x4*)cu2, (const f32x4*)vv2, G, nb);
+        else if (bound <= 32)
+          hipLaunchKernelGGL((k_flush_c64_pair<4, 8>), tri, blk, 0, s, g.N, g.R, g.ld, count,
+                             (const f32x4*)cu2, (const f32x4*)vv2, G, nb);
+        else
+          hipLaunchKernelGGL((k_flush_c64_pair<4, 16>), tri, blk, 0, s, g.N, g.R, g.ld, count,
+                             (const f32x4*)cu2, (const f32x4*)vv2, G, nb);
         st->lower_stale = 1;
         break;
       }

@@ -118,8 +118,9 @@ def test_k1_variants_listed():
     assert L.lib().gfo_k1_set_variant(L.GFO_C64, 999) == L.GFO_EINVAL
     assert L.flush_variants() == ["w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8", "w32_pipe8_3m",
                                   "w32_pipe8_3m_xcd", "ws8_3m", "ws16_3m", "sym_pipe8_3m",
-                                  "sym_pipe8_3m_nt", "sym_pipe4_3m_nt", "up_pipe8_3m_nt"]
-    assert L.flush_get_variant() == 11
+                                  "sym_pipe8_3m_nt", "sym_pipe4_3m_nt", "up_pipe8_3m_nt",
+                                  "up_pair4_3m_nt"]
+    assert L.flush_get_variant() == 12
     assert L.lib().gfo_strerror(L.GFO_ENOSPC) == b"workspace too small"
 
 

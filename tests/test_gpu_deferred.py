@@ -263,7 +263,7 @@ def test_upper_only_flush_then_sync_lower():
     eager.init()
     n_ref = eager.run_greedy(150, poll_every=25)
     Ge, Ee, de, ie = eager.host_state()
-    assert L.flush_variants()[L.flush_get_variant()] == "up_pipe8_3m_nt"
+    assert L.flush_variants()[L.flush_get_variant()] == "up_pair4_3m_nt"
     job = _job(p, delay=64)
     job.init()
     assert job.state.lower_stale == 1               # init_G0 filled the upper triangle only
