@@ -57,7 +57,7 @@ enum {                                         /* bits of the device status word
 };
 #define GFO_MAX_EPS 8                          /* permittivity table entries */
 #define GFO_MAX_RANK_K 32                      /* largest k of apply_flips_rank_k */
-#define GFO_MAX_DELAY 64                       /* largest number of deferred rank-1 moves */
+#define GFO_MAX_DELAY 128                      /* largest number of deferred rank-1 moves */
 
 /* Problem description, read during a call, not retained. */
 typedef struct {

@@ -19,7 +19,7 @@ GFO_STATUS_SINGULAR, GFO_STATUS_NONFINITE = 1, 2
 GFO_STATUS_HISTORY_FULL, GFO_STATUS_REFRESH_OVERFLOW = 4, 8
 GFO_MAX_EPS = 8
 GFO_MAX_RANK_K = 32
-GFO_MAX_DELAY = 64
+GFO_MAX_DELAY = 128
 
 # every entry point that include/gfo.h declares
 EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "gfo_scores_offset",

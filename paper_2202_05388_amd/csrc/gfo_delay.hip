@@ -64,7 +64,7 @@ __device__ __forceinline__ Snap deferred_snapshot(const Geo& g, const gfo_pick p
 // q = e - mpad, so that a workgroup holds one kind only.  A workgroup of
 // kGatherParts waves takes kGatherElems consecutive elements, one per lane;
 // wave w sums the terms
-// [w kGatherBatch, (w + 1) kGatherBatch) from zero in slot order, the partial
+// [w B, (w + 1) B) from zero in slot order, the partial
 // sums meet in LDS, and wave 0 adds them pairwise to the base entry and stores.
 // Two phases, so that the loads that do not depend on the pick are in flight
 // while it is taken: gather_prefetch reads the term count and the lane's own
@@ -73,15 +73,20 @@ __device__ __forceinline__ Snap deferred_snapshot(const Geo& g, const gfo_pick p
 // without a branch); gather_finish
 // issues the loads that depend on the pick at once (the pixel's scalars, the
 // base entries, and the terms' entries at j, staged once per workgroup in LDS).
+// B terms per wave: 16 while the state's delay is at most 64, else 32 (the
+// slots of a term buffer of 4 B); every path of a state uses the same B, so
+// their sums agree bit for bit.
 constexpr int kGatherParts = 4;
-constexpr int kGatherBatch = GFO_MAX_DELAY / kGatherParts;
 constexpr int kGatherElems = 64;
 static_assert(kGatherParts * 64 == 256, "one wave per part");
+static_assert(GFO_MAX_DELAY <= kGatherParts * 32, "two term batches cover every delay");
 
-template <typename T>
+__host__ __device__ constexpr int gather_batch(int delay) { return delay <= 64 ? 16 : 32; }
+
+template <typename T, int B>
 struct GatherPre {
   int cnt;                    // pending terms = this move's slot
-  T a[kGatherBatch];          // the lane's operands of its wave's terms
+  T a[B];                     // the lane's operands of its wave's terms
 };
 
 __host__ __device__ inline int gather_mpad(const Geo& g) {
@@ -118,9 +123,9 @@ __device__ __forceinline__ double2 buf_load<double2>(__amdgpu_buffer_rsrc_t r, u
   return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
-template <typename T>
+template <typename T, int B>
 __device__ __forceinline__ void gather_prefetch_n(const Geo& g, int cnt, const T* __restrict__ CUs,
-                                                  const T* __restrict__ Vs, GatherPre<T>& pre) {
+                                                  const T* __restrict__ Vs, GatherPre<T, B>& pre) {
   pre.cnt = cnt;
   const GatherElem el = gather_elem(g);
   // one resource per workgroup: its range ends at the term count
@@ -128,22 +133,22 @@ __device__ __forceinline__ void gather_prefetch_n(const Geo& g, int cnt, const T
   const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
       (void*)(el.mon ? CUs : Vs), (short)0, (int)(pre.cnt * stride * (int64_t)sizeof(T)), 0x00020000);
   const unsigned off = (unsigned)((el.mon ? el.i : el.q) * (int64_t)sizeof(T));
-  const int s0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * kGatherBatch;
+  const int s0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * B;
 #pragma unroll
-  for (int k = 0; k < kGatherBatch; ++k)
+  for (int k = 0; k < B; ++k)
     pre.a[k] = buf_load<T>(r, off + (unsigned)((s0 + k) * stride * (int64_t)sizeof(T)));
 }
 
-template <typename T>
+template <typename T, int B>
 __device__ __forceinline__ void gather_prefetch(const Geo& g, const int32_t* __restrict__ count,
                                                 const T* __restrict__ CUs,
-                                                const T* __restrict__ Vs, GatherPre<T>& pre) {
-  gather_prefetch_n<T>(g, __builtin_amdgcn_readfirstlane(*count), CUs, Vs, pre);
+                                                const T* __restrict__ Vs, GatherPre<T, B>& pre) {
+  gather_prefetch_n<T, B>(g, __builtin_amdgcn_readfirstlane(*count), CUs, Vs, pre);
 }
 
-template <typename T>
+template <typename T, int B>
 __device__ __forceinline__ void gather_finish(const Geo& g, const gfo_pick pk,
-                                              const GatherPre<T>& pre, const T* __restrict__ G,
+                                              const GatherPre<T, B>& pre, const T* __restrict__ G,
                                               const T* __restrict__ E,
                                               const double2* __restrict__ diag64,
                                               const uint8_t* __restrict__ eps_idx,
@@ -174,11 +179,11 @@ __device__ __forceinline__ void gather_finish(const Geo& g, const gfo_pick pk,
   // the terms of an entry: design row entries other than the pivot, and the
   // monitor rows except the FOM monitor's
   const bool terms = mon ? (e != g.m0) : (q < g.N && q != j);
-  const int s0 = w * kGatherBatch;
+  const int s0 = w * B;
   double2 acc = make_double2(0.0, 0.0);
   if (j >= 0 && terms) {
 #pragma unroll
-    for (int k = 0; k < kGatherBatch; ++k)
+    for (int k = 0; k < B; ++k)
       if (s0 + k < cnt) acc = cadd(acc, cmul(St<T>::to_d(pre.a[k]), St<T>::to_d(yj[mon ? 0 : 1][s0 + k])));
   }
   if (w > 0) part[w - 1][lane] = acc;
@@ -206,22 +211,22 @@ __device__ __forceinline__ void gather_finish(const Geo& g, const gfo_pick pk,
   }
 }
 
-template <typename T>
+template <typename T, int B>
 __global__ __launch_bounds__(256) void k_gather_dl(
     Geo g, const gfo_pick* __restrict__ pick, const T* __restrict__ G, const T* __restrict__ E,
     const double2* __restrict__ diag64, const uint8_t* __restrict__ eps_idx,
     const int32_t* __restrict__ count, Snap* __restrict__ snap_out, T* __restrict__ CUs,
     T* __restrict__ Vs, T* __restrict__ cu_out, T* __restrict__ v_out, T* __restrict__ emon) {
-  GatherPre<T> pre;
-  gather_prefetch<T>(g, count, CUs, Vs, pre);
-  gather_finish<T>(g, *pick, pre, G, E, diag64, eps_idx, snap_out, CUs, Vs, cu_out, v_out, emon);
+  GatherPre<T, B> pre;
+  gather_prefetch<T, B>(g, count, CUs, Vs, pre);
+  gather_finish<T, B>(g, *pick, pre, G, E, diag64, eps_idx, snap_out, CUs, Vs, cu_out, v_out, emon);
 }
 
 // Fused pick + gather: every wave takes the greedy pick from the score
 // summaries (identical in all of them: the same reads, exact max and min
 // reductions) while its pick-independent gather loads are in flight; workgroup
 // 0 records the pick in `pick_out`.
-template <typename T>
+template <typename T, int B>
 __global__ __launch_bounds__(256) void k_select_gather(
     Geo g, const double* __restrict__ scores, const double* __restrict__ partial,
     const int* __restrict__ pfirst, int nblk, double tau, gfo_pick* __restrict__ pick_out,
@@ -235,11 +240,11 @@ __global__ __launch_bounds__(256) void k_select_gather(
   pick_wave_load(partial, pfirst, nblk, pp);
   const double fom = cabs2(St<T>::to_d(E[g.N + g.m0]));
   __builtin_amdgcn_sched_barrier(0);
-  GatherPre<T> pre;
-  gather_prefetch<T>(g, count, CUs, Vs, pre);
+  GatherPre<T, B> pre;
+  gather_prefetch<T, B>(g, count, CUs, Vs, pre);
   __builtin_amdgcn_sched_barrier(0);
   gfo_pick pk = pick_wave_take(g, fom, pp, scores, tau, false);
-  gather_finish<T>(g, pk, pre, G, E, diag64, eps_idx, snap_out, CUs, Vs, cu_out, v_out, emon);
+  gather_finish<T, B>(g, pk, pre, G, E, diag64, eps_idx, snap_out, CUs, Vs, cu_out, v_out, emon);
   // the record of the pick, off the gather's critical path
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (pk.pixel >= 0) {
@@ -414,7 +419,7 @@ hipError_t launch_dl_reset(const Geo&, gfo_state* st, const Layout& L, hipStream
 // flush, read it from memory, which k_move_finish brings up to date);
 // snapshots, scores and summaries alternate between two sets of buffers.  The expressions are those of the per-call path (k_gather_dl,
 // k_mon_dl, k_score), so the state and the picks are bit for bit the same.
-template <typename T, int PPL>
+template <typename T, int PPL, int B>
 __global__ __launch_bounds__(256) void k_move(
     Geo g, int has_prev, int flushed, const Snap* __restrict__ snap_prev,
     Snap* __restrict__ snap_out, const double* __restrict__ scores_prev,
@@ -440,8 +445,8 @@ __global__ __launch_bounds__(256) void k_move(
   // monitor's field)
   PickPre<PPL> pp;
   pick_wave_load(partial_prev, pfirst_prev, nblk_prev, pp);
-  GatherPre<T> pre;
-  gather_prefetch_n<T>(g, GFO_MAX_DELAY, CUs, Vs, pre);
+  GatherPre<T, B> pre;
+  gather_prefetch_n<T, B>(g, kGatherParts * B, CUs, Vs, pre);
   const int64_t qc = q < g.N ? q : g.N - 1;
   const T Eown = E[mon ? i : qc];
   const double2 dq = diag64[qc];
@@ -485,11 +490,11 @@ __global__ __launch_bounds__(256) void k_move(
   const T em0_new = moved ? axpy_st<T>(em0_prev, cu_m0, sn.Ej) : em0_prev;
   __syncthreads();
   const bool terms = moved && (mon ? e != g.m0 : (q < g.N && q != j));
-  const int s0 = w * kGatherBatch;
+  const int s0 = w * B;
   double2 acc = make_double2(0.0, 0.0);
   if (terms) {
 #pragma unroll
-    for (int k = 0; k < kGatherBatch; ++k)
+    for (int k = 0; k < B; ++k)
       if (s0 + k < cnt) acc = cadd(acc, cmul(St<T>::to_d(pre.a[k]), St<T>::to_d(yj[mon ? 0 : 1][s0 + k])));
   }
   if (w > 0) part[w - 1][lane] = acc;
@@ -626,8 +631,8 @@ hipError_t launch_apply_deferred(const Geo& g, gfo_state* st, const Layout& L, c
   T* v = (T*)(w + L.v);
   T* emon = (T*)(w + L.emon);
   const int64_t n = (int64_t)gather_mpad(g) + g.ld;
-  hipLaunchKernelGGL(k_gather_dl<T>, dim3((unsigned)((n + kGatherElems - 1) / kGatherElems)), dim3(256),
-                     0, s, g, pick,
+  hipLaunchKernelGGL((gather_batch(st->delay) == 16 ? k_gather_dl<T, 16> : k_gather_dl<T, 32>),
+                     dim3((unsigned)((n + kGatherElems - 1) / kGatherElems)), dim3(256), 0, s, g, pick,
                      (const T*)st->G, (const T*)st->E, (const double2*)st->diag64,
                      (const uint8_t*)st->eps_idx, (const int32_t*)count, snap, (T*)(w + L.dl_CUs),
                      (T*)(w + L.dl_Vs), cu, v, emon);
@@ -670,7 +675,8 @@ hipError_t launch_fused_move(const Geo& g, gfo_state* st, const Layout& L, int a
     if (e != hipSuccess) return e;
   }
   const int64_t n = (int64_t)gather_mpad(g) + g.ld;
-  hipLaunchKernelGGL(k_select_gather<T>, dim3((unsigned)((n + kGatherElems - 1) / kGatherElems)),
+  hipLaunchKernelGGL((gather_batch(st->delay) == 16 ? k_select_gather<T, 16> : k_select_gather<T, 32>),
+                     dim3((unsigned)((n + kGatherElems - 1) / kGatherElems)),
                      dim3(256), 0, s, g,
                      (const double*)scores, (const double*)partial, (const int*)pfirst, nblk, tau,
                      pick_out,
@@ -704,7 +710,9 @@ hipError_t launch_move(const Geo& g, gfo_state* st, const Layout& L, int t, int 
   const int64_t n = (int64_t)gather_mpad(g) + g.ld;
   // summaries per lane: 4 while the grid has at most 256 of 64 pixels
   const bool small = (g.N + kGatherElems - 1) / kGatherElems <= 4 * 64;
-  hipLaunchKernelGGL((small ? k_move<T, 4> : k_move<T, kPickPerLane>),
+  const bool b16 = gather_batch(st->delay) == 16;
+  hipLaunchKernelGGL((small ? (b16 ? k_move<T, 4, 16> : k_move<T, 4, 32>)
+                            : (b16 ? k_move<T, kPickPerLane, 16> : k_move<T, kPickPerLane, 32>)),
                      dim3((unsigned)((n + kGatherElems - 1) / kGatherElems)), dim3(256), 0,
                      s, g, t > 0 ? 1 : 0, flushed, (const Snap*)snaps[b], snaps[a],
                      (const double*)scores[a], (const double*)partial[a], (const int*)pfirst[a], nblk,

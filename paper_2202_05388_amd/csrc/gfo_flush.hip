@@ -170,7 +170,7 @@ __device__ __forceinline__ void tri_tile(int t, int nb, int& r, int& c) {
 // G is added in the epilogue: vector loads complete in issue order, so no
 // product waits for the G loads.  A launch runs P steps of two terms (terms
 // past the count read as zeros): GFO_MAX_DELAY / 2, or for the upper-only
-// default the fewest of 8, 16 and 32 that cover the caller's bound on the
+// default the fewest of 8, 16, 32 and 64 that cover the caller's bound on the
 // count.  Byte offsets are 32-bit: the launcher
 // uses this form only when GFO_MAX_DELAY * max(R, ld) * 8 < 2^31.  THREE_MULT
 // as in k_flush_c64_tm.
@@ -691,8 +691,11 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         else if (bound <= 32)
           hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false, 16>), tri, blk, 0, s,
                              g.N, g.R, g.ld, count, cu, vv, G, nb);
-        else
+        else if (bound <= 64)
           hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false, 32>), tri, blk, 0, s,
+                             g.N, g.R, g.ld, count, cu, vv, G, nb);
+        else
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false, 64>), tri, blk, 0, s,
                              g.N, g.R, g.ld, count, cu, vv, G, nb);
         st->lower_stale = 1;
         break;
@@ -714,8 +717,11 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         else if (bound <= 32)
           hipLaunchKernelGGL((k_flush_c64_pair<4, 8>), tri, blk, 0, s, g.N, g.R, g.ld, count,
                              (const f32x4*)cu2, (const f32x4*)vv2, G, nb);
-        else
+        else if (bound <= 64)
           hipLaunchKernelGGL((k_flush_c64_pair<4, 16>), tri, blk, 0, s, g.N, g.R, g.ld, count,
+                             (const f32x4*)cu2, (const f32x4*)vv2, G, nb);
+        else
+          hipLaunchKernelGGL((k_flush_c64_pair<4, 32>), tri, blk, 0, s, g.N, g.R, g.ld, count,
                              (const f32x4*)cu2, (const f32x4*)vv2, G, nb);
         st->lower_stale = 1;
         break;

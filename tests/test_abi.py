@@ -104,7 +104,7 @@ def test_null_state_and_bad_ld_rejected_without_gpu_work():
                  n_flips=fake, kmax=0, work=fake, work_bytes=1 << 30, status=fake)
     assert lib.init_G0(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
     st.ldG = 64
-    st.delay = 65                               # above GFO_MAX_DELAY
+    st.delay = 129                              # above GFO_MAX_DELAY
     assert lib.init_G0(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
     st.delay = 0
     st.work_bytes = 16

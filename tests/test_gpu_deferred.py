@@ -25,7 +25,7 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("dtype,delay", [("c128", 16), ("c128", 64), ("c64", 16), ("c64", 64),
-                                         ("c64", 7)])
+                                         ("c64", 7), ("c64", 128), ("c128", 100)])
 def test_deferred_equals_eager(dtype, delay):
     p = W.tiny(24, 28, n_mon=8, dtype=dtype, cand_mask=W.MASK_BOTH)
     eager = _job(p)
@@ -143,7 +143,8 @@ def test_graph_replays_equal_stream_launches(dtype, delay, fused):
     assert np.array_equal(G, Gr) and np.array_equal(E, Er) and np.array_equal(d, dr)
 
 
-def test_flush_variants_agree():
+@pytest.mark.parametrize("delay", [64, 128])
+def test_flush_variants_agree(delay):
     """Every complex64 flush variant gives the eager move sequence and state."""
     from paper_2202_05388_amd import _lib as L
     p = W.tiny(40, 44, n_mon=8, dtype="c64", cand_mask=W.MASK_BOTH)
@@ -158,7 +159,7 @@ def test_flush_variants_agree():
         for vi, name in enumerate(names):
             L.flush_set_variant(vi)
             print(f"[flush variant] {name}", flush=True)
-            job = _job(p, delay=64)
+            job = _job(p, delay=delay)
             job.init()
             assert job.run_greedy(150, poll_every=25) == n_ref
             assert np.array_equal(job.history(), eager.history())
@@ -173,7 +174,8 @@ def test_flush_variants_agree():
 @pytest.mark.parametrize("dtype,delay,poll,form,n_mon", [
     ("c128", 16, 25, 0, 8), ("c64", 64, 32, 0, 8), ("c64", 7, 10, 0, 8), ("c64", 0, 20, 0, 8),
     ("c128", 16, 25, 1, 8), ("c64", 64, 32, 1, 8), ("c64", 7, 10, 1, 8),
-    ("c64", 16, 10, 0, 150), ("c128", 16, 10, 1, 150)])
+    ("c64", 16, 10, 0, 150), ("c128", 16, 10, 1, 150),
+    ("c64", 128, 40, 0, 8), ("c64", 100, 30, 1, 8), ("c128", 128, 50, 0, 150)])
 def test_greedy_steps_equal_per_call_path(dtype, delay, poll, form, n_mon):
     """gfo_greedy_steps (fused kernels in deferred mode) makes the same moves and
     leaves bit for bit the same state as score_candidates + apply_flip per move,
