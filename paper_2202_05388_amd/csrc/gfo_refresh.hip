@@ -245,8 +245,12 @@ struct EpiAddG {
 // A(m, k) = A[m * lda + k], or A[k * lda + m] when AT; K is clamped to *kdev when given.
 // skip_below > 0: tiles wholly below the diagonal within rows < skip_below are
 // not computed (deferred mode keeps the design block's upper triangle only).
+// Four waves per SIMD requested: the accumulators then live in ordinary vector
+// registers and every instantiation fits 4-5 waves without spilling (left to
+// itself the compiler put them in accumulation registers at 2-3 waves, and the
+// matrix instructions waited on their operand loads).
 template <bool AT, bool BT, typename Epi>
-__global__ __launch_bounds__(256) void k_zgemm_f64(int M, int N, int K, const double2* __restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_zgemm_f64(int M, int N, int K, const double2* __restrict__ A,
                                                    int64_t lda, const double2* __restrict__ B,
                                                    int64_t ldb, const int32_t* __restrict__ kdev,
                                                    Epi epi, int skip_below) {
