@@ -160,14 +160,14 @@ def copy_ceiling(nbytes=2 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def time_workload(problem, steps, warmup, poll, with_events=True, autotune=True):
+def time_workload(problem, steps, warmup, poll, with_events=True, autotune=True, upper=False):
     import torch
     from paper_2202_05388_amd.hiprt import EventPool
     from paper_2202_05388_amd.job import Job
     from paper_2202_05388_amd import autotune as at
 
     kmax = max(problem.refresh_every, 0) * 2 if problem.refresh_every else 0
-    job = Job(problem, device="cuda:0", kmax=kmax, ld_pad=LD_PAD)
+    job = Job(problem, device="cuda:0", kmax=kmax, ld_pad=LD_PAD, upper=upper)
     job.init()
     tuned = None
     if autotune:
@@ -535,6 +535,8 @@ def main():
     ap.add_argument("--workload", default="square128_c64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-plain", action="store_true")
+    ap.add_argument("--no-eager-upper", action="store_true",
+                    help="skip the eager leg that keeps the upper triangle of the design block alone")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-rank-k", action="store_true")
     ap.add_argument("--no-deferred", action="store_true")
@@ -580,6 +582,22 @@ def main():
     value = res["accepted"] / res["seconds"]
     _log(f"[bench] {res['accepted']} moves, {res['restarts']} restarts, {res['seconds']:.3f} s, "
          f"K1 {res['k1_ms'] * 1e3:.1f} us = {achieved:.0f} GB/s")
+
+    # eager updates of the upper triangle alone (the design block is symmetric):
+    # minimal traffic = the triangle with its diagonal and the monitor rows, read
+    # and written once
+    eager_upper = None
+    if not args.no_eager_upper:
+        _log("[bench] eager, upper triangle of the design block alone")
+        ru = time_workload(problem, args.steps, args.warmup, args.poll, autotune=False, upper=True)
+        up_bytes = 2 * elem * (N * (N + 1) // 2 + problem.n_mon * N)
+        up_gbs = up_bytes / (ru["k1_ms"] / 1e3) / 1e9
+        eager_upper = dict(value=ru["accepted"] / ru["seconds"], unit="steps/s",
+                           ms_per_step=1e3 * ru["seconds"] / ru["accepted"], restarts=ru["restarts"],
+                           k1_us=ru["k1_ms"] * 1e3, algorithmic_bytes_per_launch=up_bytes,
+                           achieved_gbs=up_gbs, frac=up_gbs / HBM_PEAK_GBS,
+                           variant=res["k1_variant"], status=ru["status"])
+        _log(f"[bench] eager upper {eager_upper}")
 
     plain = None
     if not args.no_fp64_plain and problem.dtype == "c64" and problem.name.startswith("square128"):
@@ -737,6 +755,7 @@ def main():
                    "restart_when_trajectory_ends": True},
         "roofline": roofline,
         "eager": eager,
+        "eager_upper": eager_upper,
         "fp64_plain": plain,
         "cpu_baseline": cpu,
         "accuracy": accuracy,

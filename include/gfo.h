@@ -87,7 +87,10 @@ typedef struct {
   int32_t pending_calls;        /* host counter kept by the library; set 0 before init_G0 */
   int32_t lower_stale;          /* host flag kept by the library: 1 while the strict lower
                                    triangle of the design block is out of date (see
-                                   gfo_sync_lower); 0 or 1, set 0 before init_G0 */
+                                   gfo_sync_lower); 0 or 1.  Before init_G0 (and refresh_G)
+                                   set 0, or 1 to keep the upper triangle alone in eager
+                                   mode too: the rank-1 update then skips the tiles below
+                                   the diagonal, about half its HBM traffic */
 } gfo_state;
 
 /* One selected move.  pixel = -1 is the sentinel "no move improves the FOM". */
@@ -182,7 +185,9 @@ int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick,
  * library reads its entries from the upper triangle (row <= column) only, and
  * the flushes (complex128, and the complex64 default "up_pair4_3m_nt"),
  * init_G0 and refresh_G bring only that triangle up to date; they then set
- * state.lower_stale.  While
+ * state.lower_stale.  In eager mode the same holds when state.lower_stale is 1
+ * on entry to init_G0 or refresh_G: the rank-1 update of apply_flip then skips
+ * the tiles of design rows wholly below the diagonal.  While
  * lower_stale is set, every call reads design entries from the upper
  * triangle, in eager mode too.  gfo_sync_lower copies the upper triangle into
  * the lower one for callers that read G directly. */

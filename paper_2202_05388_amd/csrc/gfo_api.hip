@@ -187,7 +187,9 @@ int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   if (launch_init(g, st, L, stream) != hipSuccess) return GFO_EHIP;
   if (launch_dl_reset(g, st, L, stream) != hipSuccess) return GFO_EHIP;
   st->pending_calls = 0;
-  st->lower_stale = st->delay > 0 ? 1 : 0;   // deferred mode fills the upper triangle only
+  // deferred mode, or a caller that asked for it (lower_stale = 1 on entry),
+  // keeps the upper triangle of the design block alone
+  st->lower_stale = g.upper;
   if (hipStreamSynchronize(stream) != hipSuccess) return GFO_EHIP;
   return GFO_OK;
 }
@@ -401,8 +403,9 @@ int refresh_G(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   if (launch_dl_reset(g, st, L, stream) != hipSuccess) return GFO_EHIP;   // pending terms discarded
   st->pending_calls = 0;
   rc = launch_refresh(g, st, L, stream);
-  // every entry rebuilt, or in deferred mode the upper triangle of the design block
-  if (rc == GFO_OK) st->lower_stale = st->delay > 0 ? 1 : 0;
+  // every entry rebuilt, or (deferred mode, or lower_stale = 1 on entry) the
+  // upper triangle of the design block
+  if (rc == GFO_OK) st->lower_stale = g.upper;
   return rc;
 }
 

@@ -146,7 +146,7 @@ static hipError_t init_typed(const Geo& g, gfo_state* st, const Layout& L, hipSt
   // a few rows per workgroup: workgroup dispatch, not the stores, bounds one row each
   dim3 grd((unsigned)((g.ld + 256 * VN - 1) / (256 * VN)), (unsigned)(g.N < 2048 ? g.N : 2048));
   hipLaunchKernelGGL(k_fill_design<T>, grd, blk, 0, s, g, G, (const double2*)table,
-                     st->delay > 0 ? 1 : 0);
+                     g.upper);
   if (g.nmon > 0) {
     dim3 grm((unsigned)((g.ld + 255) / 256), (unsigned)(g.nmon < 65535 ? g.nmon : 65535));
     hipLaunchKernelGGL(k_fill_monitors<T>, grm, blk, 0, s, g, G, (const double*)mon);

@@ -52,16 +52,23 @@ __device__ __forceinline__ void k_rank1_tile(int R, int64_t ld, int ct, int64_t 
 
 // Tiles are visited grid-stride (tile = blockIdx.x, blockIdx.x + gridDim.x, ...), so
 // the launch can stay below the 2^32 work-item limit of one dispatch on any shape.
+// upper: only the upper triangle of the design block is kept current (the
+// block is symmetric; readers take (min, max)), so tiles of design rows that
+// lie wholly below its diagonal are skipped; monitor rows are always updated.
 template <typename T, int RB, int U, int CPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(kK1Threads) void k_rank1(int R, int64_t ld, int ncoltiles,
-                                                      int64_t ntiles,
+                                                      int64_t ntiles, int N, int upper,
                                                       const Snap* __restrict__ snap,
                                                       const T* __restrict__ cu,
                                                       const T* __restrict__ v, T* __restrict__ G) {
   static_assert(RB % U == 0, "RB must be a multiple of U");
+  constexpr int64_t cols = (int64_t)kK1Threads * Vec16<T>::n * CPT;
   if (snap->j < 0) return;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    k_rank1_tile<T, RB, U, CPT, NT, PIPE>(R, ld, (int)(tile % ncoltiles), tile / ncoltiles, cu, v, G);
+    const int ct = (int)(tile % ncoltiles);
+    const int64_t rt = tile / ncoltiles;
+    if (upper && rt * RB + RB <= N && rt * RB > ct * cols + cols - 1) continue;
+    k_rank1_tile<T, RB, U, CPT, NT, PIPE>(R, ld, ct, rt, cu, v, G);
   }
 }
 
@@ -139,13 +146,14 @@ __device__ __forceinline__ void k_rank1_tile(int R, int64_t ld, int ct, int64_t 
 
 struct K1Variant {
   const char* name;
-  void (*launch)(int R, int64_t ld, const Snap*, const void*, const void*, void*, hipStream_t);
+  void (*launch)(int R, int64_t ld, int N, int upper, const Snap*, const void*, const void*, void*,
+                 hipStream_t);
 };
 
 // at most MAXB workgroups per launch (4M x 256 work-items stays far below 2^32)
 template <typename T, int RB, int U, int CPT, bool NT, bool PIPE, int64_t MAXB = (int64_t)1 << 22>
-static void launch_k1(int R, int64_t ld, const Snap* snap, const void* cu, const void* v, void* G,
-                      hipStream_t s) {
+static void launch_k1(int R, int64_t ld, int N, int upper, const Snap* snap, const void* cu,
+                      const void* v, void* G, hipStream_t s) {
   constexpr int VN = Vec16<T>::n;
   constexpr int cols = kK1Threads * VN * CPT;
   const int ncol = (int)((ld + cols - 1) / cols);
@@ -153,7 +161,7 @@ static void launch_k1(int R, int64_t ld, const Snap* snap, const void* cu, const
   const int64_t ntiles = (int64_t)ncol * nrow;
   const int64_t nblk = ntiles < MAXB ? ntiles : MAXB;
   hipLaunchKernelGGL((k_rank1<T, RB, U, CPT, NT, PIPE>), dim3((unsigned)nblk), dim3(kK1Threads), 0,
-                     s, R, ld, ncol, ntiles, snap, (const T*)cu, (const T*)v, (T*)G);
+                     s, R, ld, ncol, ntiles, N, upper, snap, (const T*)cu, (const T*)v, (T*)G);
 }
 
 // name: rows-per-workgroup x rows-in-flight x 16B-chunks-per-thread [_nt] [_pipe]
@@ -237,7 +245,7 @@ hipError_t launch_rank1(const Geo& g, const Snap* snap, const void* cu, const vo
   hipEvent_t before, after;
   k1_take_timing(&before, &after);
   if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
-  tab[k1_get_variant(g.dtype)].launch(g.R, g.ld, snap, cu, v, G, s);
+  tab[k1_get_variant(g.dtype)].launch(g.R, g.ld, g.N, g.upper, snap, cu, v, G, s);
   if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
   return hipGetLastError();
 }

@@ -375,12 +375,13 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, hipStream
   hipLaunchKernelGGL(k_rf_field<T>, dim3((g.R + 255) / 256), dim3(256), 0, s, g, mon,
                      (const double2*)U, (const double2*)x, k, kp, (T*)st->E);
   // G = G0 + Z U_D^T over the N design columns (padding columns stay zero); in
-  // deferred mode the design block on and above its diagonal only
+  // deferred mode, or when the caller keeps the upper triangle alone, the
+  // design block on and above its diagonal only
   EpiG0<T> eg{g, table, mon, (T*)st->G, (double2*)st->diag64};
   hipLaunchKernelGGL((k_zgemm_f64<false, true, EpiG0<T>>), dim3((g.N + 63) / 64, (g.R + 63) / 64),
                      dim3(256), 0, s, g.R, g.N, kp, (const double2*)Z, (int64_t)kp,
                      (const double2*)U, (int64_t)kp, (const int32_t*)nullptr, eg,
-                     st->delay > 0 ? g.N : 0);
+                     g.upper ? g.N : 0);
   return hipGetLastError() == hipSuccess ? GFO_OK : GFO_EHIP;
 }
 

@@ -26,7 +26,7 @@ class Job:
     """Device state of one greedy optimisation."""
 
     def __init__(self, problem, device="cuda", kmax: int = 0, flip_cap: int = None,
-                 dtype: str = None, delay: int = 0, ld_pad: int = 0):
+                 dtype: str = None, delay: int = 0, ld_pad: int = 0, upper: bool = False):
         if not torch.cuda.is_available():
             raise L.GfoError("libgfo needs a GPU; torch.cuda is not available")
         L.lib()
@@ -66,10 +66,15 @@ class Job:
             work_bytes=work_bytes, status=self.counters.data_ptr() + 4, delay=int(delay),
             pending_calls=0, lower_stale=0)
         self.delay = int(delay)
+        # keep only the upper triangle of the (symmetric) design block current,
+        # in eager mode too: init_G0 and refresh_G are called with lower_stale = 1
+        self.upper = bool(upper)
         self.steps_issued = 0
 
     # ------------------------------------------------------------------ C-ABI calls
     def init(self, stream=None):
+        if self.upper:
+            self.state.lower_stale = 1
         L.init_G0(self.prob, self.state, _stream_handle(stream))
 
     def score(self, topk=1, min_spacing=0, tau=None, cand_mask=None, out=None, stream=None):
@@ -88,6 +93,8 @@ class Job:
         L.apply_flips_rank_k(self.prob, self.state, ptr, k, precision, _stream_handle(stream))
 
     def refresh(self, stream=None):
+        if self.upper:
+            self.state.lower_stale = 1
         L.refresh_G(self.prob, self.state, _stream_handle(stream))
 
     def flush(self, stream=None):

@@ -195,3 +195,29 @@ def test_run_is_deterministic():
         res.append(job.host_state())
     for a, b in zip(res[0], res[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype,refresh_every", [("c64", 0), ("c128", 0), ("c64", 50)])
+def test_eager_upper_triangle_equals_full(dtype, refresh_every):
+    """Eager rank-1 updates that keep only the upper triangle of the design block
+    (lower_stale = 1 before init_G0 and refresh_G; the update skips the tiles
+    below the diagonal) make the same moves as full eager updates and, with the
+    lower triangle copied back, leave the same state."""
+    from paper_2202_05388_amd.job import Job
+    p = W.tiny(40, 44, n_mon=8, dtype=dtype, cand_mask=W.MASK_BOTH)
+    print(f"[case] eager upper {dtype} refresh {refresh_every}", flush=True)
+    full = Job(p, device="cuda:0", kmax=256)
+    full.init()
+    n_full = full.run_greedy(150, poll_every=25, refresh_every=refresh_every)
+    up = Job(p, device="cuda:0", kmax=256, upper=True)
+    up.init()
+    assert up.state.lower_stale == 1
+    n_up = up.run_greedy(150, poll_every=25, refresh_every=refresh_every)
+    assert n_up == n_full > 100
+    assert up.state.lower_stale == 1
+    assert np.array_equal(up.history(), full.history())
+    Gf, Ef, df, i_f = full.host_state()
+    Gu, Eu, du, iu = up.host_state()
+    tol = 1e-12 if dtype == "c128" else 3e-6
+    assert _rel(Gu, Gf) <= tol and _rel(Eu, Ef) <= tol and _rel(du, df) <= tol
+    assert np.array_equal(iu, i_f) and up.status() == 0
