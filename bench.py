@@ -36,7 +36,7 @@ MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # dense FP32 / FP64 matrix p
 FETCH_SCALE = 2097152.0 / 1048599.75
 WRITE_SCALE = 1.0
 PMC_TRAFFIC = [
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_rank1.hip", "sha256": "f9233914f923ea25d51ae1a538469ee73746eb0c9b044ddd9099fdd17677fbea", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053783.0, "write_kib": 2105344.25},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_rank1.hip", "sha256": "ce1af5cc48984ca588038afcb039097a02bee46cd883c6fd06b0ef5a615e2c8d", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053784.0, "write_kib": 2105344.0},
     # the flush of up_pair4_3m_nt is two kernels (k_flush_pack, then k_flush_c64_pair): their sum
     {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "6a879238764e35976a27e4e53ef78140dd1da7f0a2a77539535d7890788d8722", "workload": "square128_c64", "variant": "up_pair4_3m_nt", "fetch_kib": 818694.5 + 8221.0, "write_kib": 1052672.0 + 16416.0},
 ]
