@@ -356,6 +356,10 @@ __global__ __launch_bounds__(256) void k_flush_pack(int R, int64_t ld,
 // the P-step form).  The default complex64 flush: ring depths of 2 and 8 pair
 // steps measured no faster (8 drops to two waves per SIMD), nor did moving the
 // G tile in 16-byte pieces (adjacent lanes exchanging halves).
+//
+// The workgroups past the nby (nby + 1) / 2 triangle tiles take the monitor
+// rows [M, R) in 64 x 64 tiles over all ld columns (the FOM monitor's terms
+// are zeros, and G is added in the epilogue, so its row is rewritten unchanged).
 template <int HP, int PP>
 __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld,
                                                         const int32_t* __restrict__ count,
@@ -364,10 +368,20 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
                                                         float2* __restrict__ G, int nby) {
   const int K = *count;
   if (K == 0) return;
-  int by, bx;
-  tri_tile((int)blockIdx.x, nby, by, bx);
+  const int ntri = nby * (nby + 1) / 2;
+  int by, bx, lim, rbase;
+  if ((int)blockIdx.x < ntri) {
+    tri_tile((int)blockIdx.x, nby, by, bx);
+    lim = M;
+    rbase = by * 64;
+  } else {
+    const int t = (int)blockIdx.x - ntri, nbx = (int)(ld / 64);
+    bx = t % nbx;
+    lim = R;
+    rbase = M + (t / nbx) * 64;
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = by * 64 + (w >> 1) * 32;
+  const int m0 = rbase + (w >> 1) * 32;
   const int n = bx * 64 + (w & 1) * 32 + (lane & 31);
   const int h = lane >> 5;
   const int am = m0 + (lane & 31);
@@ -377,8 +391,8 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
       __builtin_amdgcn_make_buffer_rsrc((void*)CU2, (short)0, np * R * 16, kBufferDword3);
   const __amdgpu_buffer_rsrc_t rb =
       __builtin_amdgcn_make_buffer_rsrc((void*)V2, (short)0, (int)(np * ld * 16), kBufferDword3);
-  const unsigned a_off = am < M ? (unsigned)(h * R + am) * 16u : 0xFFFFFFF0u;
-  const unsigned a_step = am < M ? 2u * (unsigned)R * 16u : 0u;
+  const unsigned a_off = am < lim ? (unsigned)(h * R + am) * 16u : 0xFFFFFFF0u;
+  const unsigned a_step = am < lim ? 2u * (unsigned)R * 16u : 0u;
   const unsigned b_off = (unsigned)(h * ld + n) * 16u, b_step = 2u * (unsigned)ld * 16u;
   f32x4 a[HP], b[HP];
 #pragma unroll
@@ -391,7 +405,7 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    const float2* src = G + (int64_t)(r < M ? r : M - 1) * ld + n;
+    const float2* src = G + (int64_t)(r < lim ? r : lim - 1) * ld + n;
     gv[e] = __builtin_bit_cast(float2, __builtin_nontemporal_load((const f32x2*)src));
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -418,7 +432,7 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    if (r < M) {
+    if (r < lim) {
       const float2 out = make_float2(gv[e].x + (X[e] - Y[e]), gv[e].y + (Z[e] - X[e] - Y[e]));
       __builtin_nontemporal_store(f32x2{out.x, out.y}, (f32x2*)(G + (int64_t)r * ld + n));
     }
@@ -611,6 +625,7 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
   if (g.dtype == GFO_C64) {
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
     int fv = flush_get_variant();
+    bool monitors_done = false;
     // the pipelined forms address the term buffers with 32-bit byte offsets
     const bool off32 = (int64_t)GFO_MAX_DELAY * (g.ld > g.R ? g.ld : g.R) * 8 < ((int64_t)1 << 31);
     if (fv >= 2 && !off32) fv = 1;
@@ -709,7 +724,9 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
         hipLaunchKernelGGL(k_flush_pack, dim3((unsigned)((nx + 255) / 256), GFO_MAX_DELAY / 2), blk, 0, s,
                            g.R, g.ld, count, cu, vv, cu2, vv2);
-        const dim3 tri((unsigned)(nb * (nb + 1) / 2));
+        // the triangle's tiles, then the monitor rows' (no separate monitor kernel)
+        const dim3 tri((unsigned)(nb * (nb + 1) / 2 + (g.nmon + 63) / 64 * (g.ld / 64)));
+        monitors_done = true;
         const int bound = st->pending_calls;
         if (bound <= 16)
           hipLaunchKernelGGL((k_flush_c64_pair<4, 4>), tri, blk, 0, s, g.N, g.R, g.ld, count,
@@ -738,10 +755,12 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
     // the timed interval is the design-block kernel alone
     if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
     // the monitor rows (the FOM monitor's terms are stored as zeros)
-    hipLaunchKernelGGL((k_flush_c64_tm<1, true>),
-                       dim3((unsigned)((g.N + 63) / 64), (unsigned)((g.nmon + 63) / 64)), blk, 0, s,
-                       g.R, g.R, g.ld, count, cu, vv, G, g.N);
-    e = hipGetLastError();
+    if (!monitors_done) {
+      hipLaunchKernelGGL((k_flush_c64_tm<1, true>),
+                         dim3((unsigned)((g.N + 63) / 64), (unsigned)((g.nmon + 63) / 64)), blk, 0, s,
+                         g.R, g.R, g.ld, count, cu, vv, G, g.N);
+      e = hipGetLastError();
+    }
   } else {
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
     e = launch_zgemm_update_f64(g, count, (const double2*)(w + L.dl_CUs),
