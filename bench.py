@@ -37,8 +37,9 @@ FETCH_SCALE = 2097152.0 / 1048599.75
 WRITE_SCALE = 1.0
 PMC_TRAFFIC = [
     {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_rank1.hip", "sha256": "ce1af5cc48984ca588038afcb039097a02bee46cd883c6fd06b0ef5a615e2c8d", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053784.0, "write_kib": 2105344.0},
-    # the flush of up_pair4_3m_nt is two kernels (k_flush_pack, then k_flush_c64_pair): their sum
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "6a879238764e35976a27e4e53ef78140dd1da7f0a2a77539535d7890788d8722", "workload": "square128_c64", "variant": "up_pair4_3m_nt", "fetch_kib": 818694.5 + 8221.0, "write_kib": 1052672.0 + 16416.0},
+    # the flush of up_pair4_3m_nt is two kernels (k_flush_pack, then k_flush_c64_pair, which also
+    # updates the monitor rows): their sum
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "515a365d7ed52b926e1719505684a52a05bce9063db027bd574a93ede389ffd0", "workload": "square128_c64", "variant": "up_pair4_3m_nt", "fetch_kib": 826184.56 + 8221.0, "write_kib": 1060864.0 + 16416.0},
 ]
 
 
@@ -130,14 +131,21 @@ def flush_triangle(variant):
     return "sym" if v.startswith("sym") else ("up" if v.startswith("up") else None)
 
 
-def flush_alg_bytes(variant, dtype, N, ld):
+def flush_covers_monitors(variant):
+    """The pair-interleaved flush updates the monitor rows in the same kernel."""
+    return str(variant).startswith("up_pair")
+
+
+def flush_alg_bytes(variant, dtype, N, ld, n_mon=0):
     """Minimal HBM bytes of one flush of the N x ld design block: read and
     written once (complex128: 32 N ld); complex64 symmetric variants read half
     of it and write all of it (12 N ld) or, keeping only the upper triangle,
-    read and write half of it (8 N ld)."""
+    read and write half of it (8 N ld).  Plus the monitor rows (16 n_mon ld)
+    for a variant that updates them in the same kernel."""
     if dtype != "c64":
         return 32 * N * ld
-    return {"sym": 12, "up": 8, None: 16}[flush_triangle(variant)] * N * ld
+    mon = 16 * n_mon * ld if flush_covers_monitors(variant) else 0
+    return {"sym": 12, "up": 8, None: 16}[flush_triangle(variant)] * N * ld + mon
 
 
 def copy_ceiling(nbytes=2 << 30, reps=10):
@@ -287,7 +295,8 @@ def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True):
                flush_us=None if fl_ms is None else fl_ms * 1e3,
                flush_tflops=None if fl_ms is None else 8.0 * N * ld * delay / (fl_ms * 1e-3) / 1e12,
                flush_gbs=None if fl_ms is None else
-               flush_alg_bytes(flush_tuned and flush_tuned.get("name"), problem.dtype, N, ld)
+               flush_alg_bytes(flush_tuned and flush_tuned.get("name"), problem.dtype, N, ld,
+                               problem.n_mon)
                / (fl_ms * 1e-3) / 1e9,
                fom_last=job.fom(), status=job.status(),
                last_run_pixels=[int(x) for x in hist[:, 0]])
@@ -706,7 +715,9 @@ def main():
         # issued matrix work: three real products per complex one (_3m variants),
         # on the tiles on and above the diagonal only (the design block is symmetric)
         issued = flops * (0.75 if "3m" in str(d["flush_variant"]) else 1.0) * (0.5 if tri else 1.0)
-        alg_bytes = flush_alg_bytes(d["flush_variant"], problem.dtype, N, ld)
+        if flush_covers_monitors(d["flush_variant"]):
+            issued += 8.0 * problem.n_mon * ld * d["delay"] * 0.75     # the monitor rows' tiles
+        alg_bytes = flush_alg_bytes(d["flush_variant"], problem.dtype, N, ld, problem.n_mon)
         t_mfma, t_hbm = issued / (peak * 1e12), alg_bytes / (HBM_PEAK_GBS * 1e9)
         secs = d["flush_us"] * 1e-6
         common = {"kernel": f"flush of the deferred updates, FP32 MFMA, variant {d['flush_variant']}",
