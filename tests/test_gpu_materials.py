@@ -1,0 +1,78 @@
+"""More than two materials (a permittivity table of up to GFO_MAX_EPS entries):
+every (pixel, material) pair in the candidate mask is scored by eqs. form4-form9,
+the greedy pick follows the tie rule over (pixel, material), and trajectories
+equal the oracle's move for move."""
+import numpy as np
+import pytest
+
+from oracle import greedy as og
+from oracle import state as ost
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TABLES = {3: (1.0, 12.25, 2.25), 8: (1.0, 12.25, 2.25, 4.0, 6.25, 9.0, 3.0, 1.5)}
+
+
+def _job(p, **kw):
+    from paper_2202_05388_amd.job import Job
+    print(f"[case] {p.name} {p.ny}x{p.nx} n_eps={len(p.eps_table)} mask={p.cand_mask:#x} "
+          f"{p.dtype} {kw}", flush=True)
+    return Job(p, device="cuda:0", **kw)
+
+
+def _problem(ny, nx, n_eps, dtype, drop=None):
+    mask = (1 << n_eps) - 1
+    if drop is not None:
+        mask &= ~(1 << drop)
+    return W.tiny(ny, nx, n_mon=6, dtype=dtype, cand_mask=mask, eps_table=TABLES[n_eps])
+
+
+@pytest.mark.parametrize("n_eps,drop,dtype,seed", [
+    (3, None, "c128", 0), (8, None, "c128", 1), (8, 2, "c64", 2), (3, 1, "c64", 3)])
+def test_multi_material_scores_and_pick(n_eps, drop, dtype, seed):
+    p = _problem(9, 11, n_eps, dtype, drop)
+    N = p.n
+    idx = W.random_material_idx(p, seed)
+    G, E = ost.dense_state(p, ost.eps_of(p, idx))
+    job = _job(p)
+    job.upload_state(G, E, np.diagonal(G[:N]), idx)
+    job.score(topk=1, tau=1e-9)
+    F_gpu = job.scores()
+    F_ref = og.scores_closed_form(p, E, np.diagonal(G[:N]), G[N + p.fom_monitor], idx)
+    assert F_gpu.shape == F_ref.shape == (N, n_eps)
+    fin = np.isfinite(F_ref)
+    assert np.array_equal(fin, np.isfinite(F_gpu))
+    if drop is not None:
+        assert not fin[:, drop].any()
+    tol = 1e-12 if dtype == "c128" else 1e-6
+    assert np.allclose(F_gpu[fin], F_ref[fin], rtol=tol, atol=0)
+    pick = job.read_picks(1)[0]
+    ref = og.select_greedy(F_ref, ost.fom_of_state(p, E), 1e-9)
+    assert (pick[0], pick[1]) == (ref.pixel, ref.eps_idx)
+
+
+@pytest.mark.parametrize("n_eps", [3, 8])
+def test_multi_material_trajectory_matches_oracle(n_eps):
+    p = _problem(10, 12, n_eps, "c128")
+    traj = og.greedy(p, steps=300, tier="T2")
+    ref_moves = [(s.pixel, s.eps_idx) for s in traj.steps]
+    eager = _job(p)
+    eager.init()
+    n = eager.run_greedy(300, poll_every=16)
+    assert n == len(ref_moves) and traj.stopped and n > 5
+    assert [tuple(int(v) for v in m) for m in eager.history()] == ref_moves
+    per_call = _job(p, delay=16)
+    per_call.init()
+    fused = _job(p, delay=16)
+    fused.init()
+    assert per_call.run_greedy(300, poll_every=16) == n
+    assert fused.run_greedy(300, poll_every=16, fused=True) == n
+    assert np.array_equal(fused.history(), eager.history())
+    Gp, Ep, dp, ip = per_call.host_state()
+    Gf, Ef, df, i_f = fused.host_state()
+    assert np.array_equal(Gf, Gp) and np.array_equal(Ef, Ep) and np.array_equal(df, dp)
+    assert np.array_equal(i_f, ip) and np.array_equal(ip, traj.eps_idx)
+    Gd, Ed = ost.dense_state(p, ost.eps_of(p, ip))
+    assert np.linalg.norm(Ep - Ed) / np.linalg.norm(Ed) <= 1e-9
+    assert eager.status() == per_call.status() == fused.status() == 0

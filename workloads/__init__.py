@@ -133,6 +133,12 @@ def random_eps_idx(problem: Problem, fill: float, seed: int) -> np.ndarray:
     return (rng.random(problem.n) < fill).astype(np.uint8)
 
 
+def random_material_idx(problem: Problem, seed: int) -> np.ndarray:
+    """uint8 material index per pixel, uniform over the permittivity table."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, len(problem.eps_table), problem.n).astype(np.uint8)
+
+
 def mirror_symmetric_eps_idx(problem: Problem, fill: float, seed: int) -> np.ndarray:
     """Random material mask that is symmetric under ix -> nx-1-ix."""
     rng = np.random.default_rng(seed)
