@@ -99,3 +99,51 @@ def test_region_rank_k_application_equals_sequential(delay):
     Gb, Eb, _, _ = b.host_state()
     assert np.linalg.norm(Gb - Ga) <= 5e-6 * np.linalg.norm(Ga)
     assert np.linalg.norm(Eb - Ea) <= 5e-6 * np.linalg.norm(Ea)
+
+
+def _lens3(n, dtype="c128"):
+    """The lens with a three-entry permittivity table, every material a candidate."""
+    return _lens(n, dtype).replace(eps_table=(1.0, 12.25, 2.25), cand_mask=0b111)
+
+
+def test_region_scores_three_materials():
+    """Regions of mixed materials: a candidate is any material that changes at
+    least one of the region's pixels."""
+    p = _lens3(12)
+    idx = W.random_material_idx(p, seed=5)
+    job = _job(p)
+    job.init()
+    G, E = ost.dense_state(p, ost.eps_of(p, idx))
+    job.upload_state(G, E, np.diagonal(G[: p.n]).copy(), idx)
+    job.region_step(apply="sequential")
+    F_gpu = _gpu_region_scores(job).copy()
+    ev = orr._RegionEvaluator(p, 2, "T1")
+    Eo, row, G_VV = ev(idx)
+    F = orr.region_scores(p, 2, Eo, G_VV, row, idx)
+    assert F.shape == F_gpu.shape and F.shape[1] == 3
+    fin = np.isfinite(F)
+    assert np.array_equal(np.isfinite(F_gpu), fin)
+    assert np.allclose(F_gpu[fin], F[fin], rtol=1e-10, atol=0)
+
+
+def test_region_greedy_three_materials_matches_oracle():
+    p = _lens3(16)
+    ref = orr.region_greedy(p, 2, steps=200, tier="T2")
+    assert ref.stopped and len(ref.steps) >= 10
+    job = _job(p)
+    job.init()
+    n, moves = job.run_region_greedy(200, poll_every=8)
+    assert moves == [(s.pixel, s.eps_idx) for s in ref.steps]
+    E = job.E.cpu().numpy()
+    assert np.linalg.norm(E - ref.E) <= 1e-9 * np.linalg.norm(ref.E) and job.status() == 0
+
+
+def test_region_moves_on_an_odd_grid_are_refused():
+    """2x2 regions need an even grid: EINVAL before any launch, state untouched."""
+    from paper_2202_05388_amd import _lib as L
+    p = _lens(12).replace(nx=13)
+    job = _job(p)
+    job.init()
+    with pytest.raises(L.GfoError):
+        job.region_step(apply="sequential")
+    assert job.n_flips() == 0 and job.status() == 0
