@@ -61,3 +61,22 @@ def test_eps_greedy_deferred_equals_eager(dtype, delay):
     assert np.linalg.norm(Gb - Ga) <= tol * np.linalg.norm(Ga)
     Gd, Ed = ost.dense_state(p, ost.eps_of(p, b.eps_idx.cpu().numpy()))
     assert np.linalg.norm(Eb - Ed) <= (1e-11 if dtype == "c128" else 2e-5) * np.linalg.norm(Ed)
+
+
+@pytest.mark.parametrize("eps,seed", [(0.3, 11), (1.0, 12)])
+def test_eps_greedy_three_materials_matches_oracle(eps, seed):
+    """With three materials a pixel has two candidate moves, so the exploration set
+    (the best move at each of the four best distinct pixels) differs from the four
+    best moves."""
+    p = W.SQUARE_21.replace(eps_table=(1.0, 12.25, 2.25), cand_mask=0b111)
+    draws = W.eps_greedy_draws(600, seed)
+    ref = og.eps_greedy(p, eps, draws, tier="T2", steps=600)
+    assert ref.stopped and len({s.eps_idx for s in ref.steps}) == 3
+    job = _job(p)
+    job.init()
+    n = job.run_eps_greedy(eps, draws, poll_every=16)
+    hist = [(int(a), int(b)) for a, b in job.history()]
+    assert hist == [(s.pixel, s.eps_idx) for s in ref.steps] and n == len(ref.steps)
+    E = job.E.cpu().numpy()
+    assert np.linalg.norm(E - ref.E) <= 1e-9 * np.linalg.norm(ref.E)
+    assert job.status() == 0
