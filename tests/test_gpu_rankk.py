@@ -112,3 +112,23 @@ def test_rank_k_trajectory_matches_oracle_policy():
         job.apply_rank_k(16, precision=L.GFO_FP32)
         fom = job.fom()
         assert abs(fom - group[0].fom) <= 1e-4 * group[0].fom
+
+
+def test_rank_k_three_materials_follows_oracle_policy():
+    """Spaced top-k over (pixel, material) with a three-entry table: at most one
+    move per pixel, the chosen sets and the FOM follow the oracle's policy."""
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(32, 32, n_mon=8, dtype="c64", cand_mask=0b111, eps_table=(1.0, 12.25, 2.25),
+               rank_k=16, min_spacing=3, steps=3, tau=1e-6)
+    ref = og.rank_k_trajectory(p, steps=3, tier="T2")
+    assert len({s.eps_idx for g in ref.steps for s in g}) >= 2
+    job = _job(p)
+    job.init()
+    for t, group in enumerate(ref.steps):
+        job.score(topk=16, min_spacing=3, tau=1e-6)
+        got = [(a, b) for a, b, _, _ in job.read_picks(16) if a >= 0]
+        assert got == [(s.pixel, s.eps_idx) for s in group], t
+        assert len({a for a, _ in got}) == len(got)
+        job.apply_rank_k(16, precision=L.GFO_FP32)
+        assert abs(job.fom() - group[0].fom) <= 1e-4 * group[0].fom
+    assert job.status() == 0
