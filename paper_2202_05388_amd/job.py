@@ -241,11 +241,12 @@ class Job:
         """Overwrite the device state with host arrays (tests build arbitrary states this way)."""
         _, tdtype, _ = _DTYPES[self.dtype_name]
         Gt = torch.zeros((self.R, self.ld), dtype=torch.complex128)
-        Gt[:, : self.N] = torch.from_numpy(np.asarray(G, np.complex128))
+        # np.array copies: read-only views (np.diagonal) are not valid tensor storage
+        Gt[:, : self.N] = torch.from_numpy(np.array(G, np.complex128))
         self.G.copy_(Gt.to(tdtype))
-        self.E.copy_(torch.from_numpy(np.asarray(E, np.complex128)).to(tdtype))
-        self.diag64.copy_(torch.from_numpy(np.asarray(diag, np.complex128)))
-        self.eps_idx.copy_(torch.from_numpy(np.asarray(eps_idx, np.uint8)))
+        self.E.copy_(torch.from_numpy(np.array(E, np.complex128)).to(tdtype))
+        self.diag64.copy_(torch.from_numpy(np.array(diag, np.complex128)))
+        self.eps_idx.copy_(torch.from_numpy(np.array(eps_idx, np.uint8)))
         torch.cuda.synchronize(self.device)
         self.state.lower_stale = 0                    # the whole matrix was written
 
