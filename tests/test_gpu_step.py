@@ -221,3 +221,30 @@ def test_eager_upper_triangle_equals_full(dtype, refresh_every):
     tol = 1e-12 if dtype == "c128" else 3e-6
     assert _rel(Gu, Gf) <= tol and _rel(Eu, Ef) <= tol and _rel(du, df) <= tol
     assert np.array_equal(iu, i_f) and up.status() == 0
+
+
+@pytest.mark.parametrize("delay", [0, 16])
+def test_invalid_arguments_are_refused_before_any_launch(delay):
+    """An empty candidate mask (also one with only bits past the table), a tie band
+    outside [0, 1), topk outside 1..GFO_MAX_RANK_K, a negative spacing or step
+    count: EINVAL, and the state is left as it was."""
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(8, 9, n_mon=5, dtype="c64", cand_mask=W.MASK_BOTH)
+    job = _job(p, delay=delay)
+    job.init()
+    E0 = job.E.cpu().clone()
+    bad_scores = [dict(cand_mask=0), dict(cand_mask=0b100), dict(tau=-1e-9), dict(tau=1.0),
+                  dict(tau=float("nan")), dict(topk=0), dict(topk=L.GFO_MAX_RANK_K + 1),
+                  dict(min_spacing=-1)]
+    for kw in bad_scores:
+        with pytest.raises(L.GfoError):
+            job.score(**kw)
+    for kw in (dict(cand_mask=0), dict(tau=float("inf"))):
+        with pytest.raises(L.GfoError):
+            job.greedy_steps(4, **kw)
+    with pytest.raises(L.GfoError):
+        job.greedy_steps(-1)
+    job.greedy_steps(0)
+    assert job.n_flips() == 0 and job.status() == 0
+    assert job.state.pending_calls == 0
+    assert bool((job.E.cpu() == E0).all())
