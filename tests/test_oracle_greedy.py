@@ -165,3 +165,96 @@ def test_eps_greedy_fom_rises_and_ends_without_an_improving_move():
     G0 = greens.build_G0(p)
     F = state.brute_force_scores(p, tr.eps_idx, G0)
     assert not F.max() > foms[-1] * (1 + p.tau)
+
+
+# ---------------------------------------------------------------- rank-k selection vs brute force
+def spaced_top_k_brute_force(F, fom, tau, k, spacing, nx):
+    """Independent statement of the rank-k rule (eq. form14 moves with a
+    minimum-spacing set): list every candidate, sort by (-FOM', pixel,
+    material), walk the list and accept a candidate iff it improves the FOM by
+    more than the band, its pixel is not yet chosen and its Chebyshev distance
+    to EVERY accepted pixel is at least `spacing` (checked pair by pair), until
+    k are accepted.  Equal to the band rule only where tied scores are exactly
+    equal, which the callers arrange."""
+    N, ne = F.shape
+    cands = sorted((-F[p, e], p, e) for p in range(N) for e in range(ne) if np.isfinite(F[p, e]))
+    chosen = []
+    for negf, p, e in cands:
+        if len(chosen) == k or not -negf > fom * (1.0 + tau):
+            break
+        ok = True
+        for q, _ in chosen:
+            cheb = max(abs(p // nx - q // nx), abs(p % nx - q % nx))
+            if q == p or cheb < spacing:
+                ok = False
+                break
+        if ok:
+            chosen.append((p, e))
+    return chosen
+
+
+def rank_k_case(kind, seed=0):
+    """(problem, F, fom) of a state on a 14x14 grid whose scores are computed by
+    the closed form on the exact (tier T1) state.  'random': a random mask;
+    'mirror': a mirror-symmetric mask with the score array symmetrised so that
+    mirror pairs tie exactly; 'three': a three-material table (so one pixel has
+    two candidates)."""
+    if kind == "three":
+        p = W.tiny(14, 14, n_mon=4, cand_mask=0b111, eps_table=(1.0, 12.25, 4.0))
+        idx = W.random_material_idx(p, seed)
+    else:
+        p = W.tiny(14, 14, n_mon=4, cand_mask=W.MASK_BOTH)
+        idx = (W.mirror_symmetric_eps_idx(p, 0.25, seed) if kind == "mirror"
+               else W.random_eps_idx(p, 0.25, seed))
+    N = p.n
+    G, E = state.dense_state(p, state.eps_of(p, idx))
+    F = greedy.scores_closed_form(p, E, np.diagonal(G[:N]), G[N + p.fom_monitor], idx)
+    if kind == "mirror":
+        Fm = F.reshape(p.ny, p.nx, -1)[:, ::-1, :].reshape(N, -1)
+        F = np.maximum(F, Fm)
+    fom = state.fom_of_state(p, E)
+    return p, F, fom
+
+
+def _distinct_scores_separated(F, tau):
+    v = np.unique(F[np.isfinite(F)])
+    return v.size < 2 or np.min(np.diff(v) / v[1:]) > 4 * tau
+
+
+@pytest.mark.parametrize("kind", ["random", "mirror", "three"])
+@pytest.mark.parametrize("spacing", [0, 2, 3])
+def test_rank_k_selection_equals_brute_force_spaced_top_k(kind, spacing):
+    p, F, fom = rank_k_case(kind, seed=4)
+    # band tau on scores whose distinct values lie further apart than the band (then
+    # the band holds exact ties only), and tau = 0 on the same scores
+    tau = 1e-9
+    assert _distinct_scores_separated(F, tau)
+    for t in (0.0, tau):
+        for k in (1, 5, 16, 40):
+            got = [(pk.pixel, pk.eps_idx) for pk in greedy.select_rank_k(F, fom, t, k, spacing, p.nx)]
+            want = spaced_top_k_brute_force(F, fom, t, k, spacing, p.nx)
+            assert got == want, (kind, spacing, t, k)
+    # the case exercises the rule: with k = 40 the spacing rule, not k, ends the set
+    # (spacing >= 2), and the accepted set is strictly smaller than without it
+    full = spaced_top_k_brute_force(F, fom, tau, 40, spacing, p.nx)
+    if spacing >= 2:
+        assert len(full) < 40
+        assert len(spaced_top_k_brute_force(F, fom, tau, 40, 0, p.nx)) > len(full)
+
+
+def test_rank_k_band_takes_the_lowest_index_among_near_ties():
+    """Near-ties within the band (not exact ties): the lowest (pixel, material)
+    of the band is accepted first, then the rule repeats over what is left."""
+    nx = 10
+    F = np.full((30, 2), -np.inf)
+    F[25, 1] = 2.0 + 1e-9          # the largest score
+    F[3, 1] = 2.0                  # within tau = 1e-9 * 2 of it: tied, lower index wins
+    F[28, 1] = 1.5                 # (2, 8): far from pixels 3 (0, 3) and 25 (2, 5)
+    F[4, 1] = 1.9                  # Chebyshev distance 1 from pixel 3: excluded at spacing 2
+    picks = greedy.select_rank_k(F, 1.0, 1e-9, 4, 2, nx)
+    assert [(pk.pixel, pk.eps_idx) for pk in picks] == [(3, 1), (25, 1), (28, 1)]
+    # spacing 1 keeps pixel 4 (distance 1 >= 1), ordered by score after the band
+    picks = greedy.select_rank_k(F, 1.0, 1e-9, 4, 1, nx)
+    assert [pk.pixel for pk in picks] == [3, 25, 4, 28]
+    # nothing above fom (1 + tau) is accepted
+    assert greedy.select_rank_k(F, 2.0 + 1e-9, 1e-9, 4, 0, nx) == []

@@ -184,3 +184,67 @@ def test_pin_catches_region_solve_with_B_on_the_wrong_side(monkeypatch):
         return out
     monkeypatch.setattr(regions, "region_scores", scores_bad)
     assert not _region_score_pin_holds()
+
+
+# ---------------------------------------------------------------- rank-k selection (spaced top-k)
+def _rank_k_pin_holds():
+    """select_rank_k equals the brute-force spaced top-k on every case of the pin."""
+    from test_oracle_greedy import rank_k_case, spaced_top_k_brute_force
+    for kind in ("random", "mirror", "three"):
+        p, F, fom = rank_k_case(kind, seed=4)
+        for spacing in (0, 2, 3):
+            for t in (0.0, 1e-9):
+                for k in (5, 16, 40):
+                    got = [(pk.pixel, pk.eps_idx)
+                           for pk in greedy.select_rank_k(F, fom, t, k, spacing, p.nx)]
+                    if got != spaced_top_k_brute_force(F, fom, t, k, spacing, p.nx):
+                        return False
+    return True
+
+
+def _rank_k_with(mask_fn):
+    """A select_rank_k whose exclusion after each pick is mask_fn(dy, dx, spacing, pixel, q)."""
+    def bad(F, fom_now, tau, k, min_spacing, nx):
+        F = F.copy()
+        picks = []
+        N = F.shape[0]
+        q = np.arange(N)
+        while len(picks) < k:
+            pk = greedy.select_greedy(F, fom_now, tau)
+            if pk is None:
+                break
+            picks.append(pk)
+            dy = np.abs(q // nx - pk.pixel // nx)
+            dx = np.abs(q % nx - pk.pixel % nx)
+            F[mask_fn(dy, dx, min_spacing, pk.pixel, q), :] = -np.inf
+        return picks
+    return bad
+
+
+@pytest.mark.parametrize("name,mask_fn", [
+    # one more than the spacing asks for (over-strict)
+    ("spacing_plus_1", lambda dy, dx, s, p, q: np.maximum(dy, dx) < max(s, 1) + 1),
+    # one less (a neighbour at distance spacing - 1 accepted)
+    ("spacing_minus_1", lambda dy, dx, s, p, q: np.maximum(dy, dx) < max(s - 1, 1)),
+    # an eligible candidate skipped: the next pixel in row-major order is dropped too
+    ("skips_next_pixel", lambda dy, dx, s, p, q: (np.maximum(dy, dx) < max(s, 1)) | (q == p + 1)),
+    # Manhattan distance in place of Chebyshev
+    ("manhattan", lambda dy, dx, s, p, q: dy + dx < max(s, 1)),
+    # only the chosen pixel's row is checked (the column offset ignored)
+    ("row_only", lambda dy, dx, s, p, q: (dy == 0) & (dx < max(s, 1))),
+])
+def test_pin_catches_rank_k_exclusion_slip(monkeypatch, name, mask_fn):
+    assert _rank_k_pin_holds()
+    monkeypatch.setattr(greedy, "select_rank_k", _rank_k_with(mask_fn))
+    assert not _rank_k_pin_holds(), name
+
+
+def test_pin_catches_rank_k_that_ignores_the_improvement_rule(monkeypatch):
+    """A set filled up to k with candidates that do not improve the FOM."""
+    assert _rank_k_pin_holds()
+    orig = greedy.select_rank_k
+
+    def bad(F, fom_now, tau, k, min_spacing, nx):
+        return orig(F, -1.0, tau, k, min_spacing, nx)     # every finite score "improves"
+    monkeypatch.setattr(greedy, "select_rank_k", bad)
+    assert not _rank_k_pin_holds()
