@@ -121,7 +121,19 @@ class Trajectory:
 
 
 class _Evaluator:
-    """Exact state of the current structure by tier T1 or T2."""
+    """Exact state of the current structure by tier T1, T2 or T2u.
+
+    T2u walks a sequence of one-pixel moves: E and the FOM monitor's row come
+    from the flipped set (tier T2, O(k N) once the k x k system is solved), and
+    diag(G) is carried from the previous structure by the paper's update
+    (eq. form10 with a one-pixel region, restricted to the diagonal):
+        diag'[q] = diag[q] + c G[q, j] G[j, q],  c = alpha / (1 - alpha G[j, j]),
+    with column j of the previous structure's G taken exactly from the flipped
+    set and G[j, q] = G[q, j] (reciprocity).  Any other change of structure
+    (the first call, or more than one pixel changed) is a full T2 evaluation.
+    It avoids the O(k^2 N) diagonal of T2 at every step of a long replay; the
+    tests pin it against T2 along random move sequences.
+    """
 
     def __init__(self, problem, tier):
         self.problem = problem
@@ -132,6 +144,7 @@ class _Evaluator:
             self.G0 = greens.build_G0(problem)
         else:
             self.fs = state.FlippedSet(problem)
+        self.prev = None
 
     def __call__(self, eps_idx):
         eps = state.eps_of(self.problem, eps_idx)
@@ -139,8 +152,29 @@ class _Evaluator:
             G, E = state.dense_state(self.problem, eps, self.G0)
             N = self.problem.n
             return E, np.diagonal(G[:N]).copy(), G[self.m0_row]
+        if self.tier == "T2u":
+            return self._walk(np.asarray(eps_idx).copy(), eps)
         E, diag, rows = self.fs.state(eps, rows=[self.m0_row])
         return E, diag, rows[self.m0_row]
+
+    def _walk(self, eps_idx, eps):
+        N = self.problem.n
+        changed = None if self.prev is None else np.flatnonzero(eps_idx != self.prev[0])
+        if changed is not None and changed.size == 0:
+            return self.prev[2:]
+        if changed is None or changed.size > 1:
+            E, diag, rows = self.fs.state(eps, rows=[self.m0_row])
+        else:
+            j = int(changed[0])
+            eps_prev, diag_prev = self.prev[1], self.prev[3]
+            col = self.fs.column_of(eps_prev, j)[:N]
+            alpha = greens.k0_of(self.problem) ** 2 * (eps[j] - eps_prev[j])
+            c = alpha / (1.0 - alpha * col[j])
+            diag = diag_prev + c * col * col
+            E, _, rows = self.fs.state(eps, rows=[self.m0_row], with_diag=False)
+        row = rows[self.m0_row]
+        self.prev = (eps_idx, eps, E, diag, row)
+        return E, diag, row
 
 
 def greedy(problem, steps=None, tier="T1", eps_idx0=None, tau=None, callback=None) -> Trajectory:
@@ -170,11 +204,14 @@ def greedy(problem, steps=None, tier="T1", eps_idx0=None, tau=None, callback=Non
     return traj
 
 
-def replay(problem, moves, tier="T2", eps_idx0=None, check_every=1, callback=None):
+def replay(problem, moves, tier="T2", eps_idx0=None, check_every=1, callback=None, final=False):
     """Follow a given move sequence [(pixel, eps_idx), ...] and certify each choice.
 
     At each checked step returns the oracle's best candidate FOM F*, the oracle
-    FOM of the move actually taken, and the oracle's own greedy pick.
+    FOM of the move actually taken, and the oracle's own greedy pick.  final:
+    one more record (step = len(moves), F_taken None) with F*, the FOM and the
+    field E of the structure the sequence ends in, so a caller can check that
+    no move is left that improves the FOM.  tier "T2u" suits long sequences (check_every = 1).
     """
     ev = _Evaluator(problem, tier)
     eps_idx = (np.zeros(problem.n, np.uint8) if eps_idx0 is None
@@ -194,6 +231,15 @@ def replay(problem, moves, tier="T2", eps_idx0=None, check_every=1, callback=Non
             E, diag, row = ev(eps_idx)
             if callback is not None:
                 callback(t, eps_idx, E)
+    if final:
+        if not moves:
+            E, diag, row = ev(eps_idx)
+        F = scores_closed_form(problem, E, diag, row, eps_idx)
+        best = select_greedy(F, state.fom_of_state(problem, E), problem.tau)
+        out.append(dict(step=len(moves), Fstar=float(np.max(F)), F_taken=None,
+                        oracle_pixel=None if best is None else best.pixel,
+                        oracle_eps=None if best is None else best.eps_idx,
+                        fom_before=state.fom_of_state(problem, E), E=E))
     return out
 
 

@@ -104,33 +104,79 @@ class FlippedSet:
         return c
 
     def solve(self, eps):
-        """Return (V, U = G0[:, V], Q = (I - B_V G0[V,V])^-1 B_V)."""
+        """Return (V, U = G0[:, V], Q = (I - B_V G0[V,V])^-1 B_V), V in the order
+        of U's columns (any order of the flipped set gives the same state).  The
+        last structure's solve is kept, so consecutive calls on one structure
+        solve once; U is a view that the next solve of another structure changes."""
+        key = np.asarray(eps, dtype=np.float64).tobytes()
+        if getattr(self, "_last_key", None) == key:
+            return self._last
+        self._last = self._solve(eps)
+        self._last_key = key
+        return self._last
+
+    def _columns(self, Vset):
+        """U = G0[:, V] for the flipped set, as a view of a persistent R x cap
+        buffer whose columns are kept in slot order: a pixel that leaves the set
+        frees its slot (the last slot's column moves into it), a new pixel takes
+        the next slot.  A one-pixel change of V then moves one column instead of
+        restacking k of them.  Returns (V in slot order, U)."""
+        if not hasattr(self, "_slots"):
+            self._slots, self._pos = [], {}
+            self._U = np.zeros((self.R, 16), np.complex128)
+        for q in [q for q in self._slots if q not in Vset]:
+            i, last = self._pos.pop(q), self._slots.pop()
+            if last != q:
+                self._slots[i] = last
+                self._pos[last] = i
+                self._U[:, i] = self._U[:, len(self._slots)]
+        for q in sorted(Vset - set(self._pos)):
+            if len(self._slots) == self._U.shape[1]:
+                grown = np.zeros((self.R, 2 * self._U.shape[1]), np.complex128)
+                grown[:, : len(self._slots)] = self._U[:, : len(self._slots)]
+                self._U = grown
+            self._pos[q] = len(self._slots)
+            self._U[:, len(self._slots)] = self.column(q)
+            self._slots.append(q)
+        return np.array(self._slots, dtype=np.int64), self._U[:, : len(self._slots)]
+
+    def _solve(self, eps):
         alpha = greens.alpha_of(self.problem, eps)
-        V = np.flatnonzero(alpha != 0.0)
+        V, U = self._columns({int(q) for q in np.flatnonzero(alpha != 0.0)})   # U: R x k
         k = V.size
         if k == 0:
             return V, np.zeros((self.R, 0), np.complex128), np.zeros((0, 0), np.complex128)
-        U = np.stack([self.column(int(p)) for p in V], axis=1)          # R x k
         aV = alpha[V]
         A = np.eye(k, dtype=np.complex128) - aV[:, None] * U[V, :]     # I - B_V G0[V,V]
         Q = np.linalg.solve(A, np.diag(aV).astype(np.complex128))
         return V, U, Q
 
-    def state(self, eps, rows=()):
+    def column_of(self, eps, j: int) -> np.ndarray:
+        """Column j (a design pixel) of G of the structure `eps`, all R rows:
+        G[:, j] = G0[:, j] + U Q G0[V, j], with G0[V, j] = U[j, :] (symmetry)."""
+        V, U, Q = self.solve(eps)
+        col = self.column(j).copy()
+        if V.size:
+            col = col + U @ (Q @ U[j, :])
+        return col
+
+    def state(self, eps, rows=(), with_diag=True):
         """E (R), diag(G) over design pixels (N), and the requested full rows of G.
 
         G0 is symmetric on the design block (reciprocity of the free-space
-        kernel), so G0[V, q] for design q equals U[q, :].
+        kernel), so G0[V, q] for design q equals U[q, :].  with_diag=False
+        skips the O(k^2 N) diagonal (returned as None).
         """
         V, U, Q = self.solve(eps)
         N = self.N
         E = self.Einc.copy()
-        diag = np.full(N, self.G0_diag, dtype=np.complex128)
+        diag = np.full(N, self.G0_diag, dtype=np.complex128) if with_diag else None
         out_rows = {}
         if V.size:
             E = E + U @ (Q @ self.Einc[V])
-            U_D = U[:N]
-            diag = diag + np.einsum("qa,qa->q", U_D @ Q, U_D)
+            if with_diag:
+                U_D = U[:N]
+                diag = diag + np.einsum("qa,qa->q", U_D @ Q, U_D)
         for r in rows:
             base = greens.G0_block(self.problem, [r], np.arange(N))[0]
             if V.size:

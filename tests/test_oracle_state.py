@@ -153,3 +153,47 @@ def test_brute_force_scores_equal_closed_form():
     assert np.array_equal(fin, np.isfinite(F1))
     assert fin.sum() == N          # two materials, both allowed: one candidate per pixel
     assert np.allclose(F1[fin], F0[fin], rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("table", [(1.0, 12.25), (1.0, 12.25, 4.0)])
+def test_walking_tier_equals_flipped_set_tier_along_moves(table):
+    """Tier T2u (diagonal carried by the paper's one-pixel update, E and the FOM
+    row from the flipped set) equals tier T2 at every structure of a random move
+    sequence that also un-flips and re-flips pixels."""
+    from oracle import greedy as og
+    p = W.tiny(7, 9, n_mon=4, eps_table=table, cand_mask=(1 << len(table)) - 1)
+    rng = np.random.default_rng(5)
+    walk = og._Evaluator(p, "T2u")
+    full = og._Evaluator(p, "T2")
+    idx = np.zeros(p.n, np.uint8)
+    for t in range(30):
+        if t:
+            j = int(rng.integers(0, p.n)) if t % 4 else int(np.flatnonzero(idx)[0])
+            idx[j] = (idx[j] + 1 + int(rng.integers(0, len(table) - 1))) % len(table)
+        Ew, dw, rw = walk(idx)
+        Ef, df, rf = full(idx)
+        assert np.max(np.abs(Ew - Ef)) <= 1e-12 * np.max(np.abs(Ef))
+        assert np.max(np.abs(dw - df)) <= 1e-12 * np.max(np.abs(df))
+        assert np.max(np.abs(rw - rf)) <= 1e-12 * np.max(np.abs(rf))
+    # two pixels changed at once: a full evaluation
+    idx[:2] = 1 - np.minimum(idx[:2], 1)
+    Ew, dw, _ = walk(idx)
+    Ef, df, _ = full(idx)
+    assert np.allclose(dw, df, rtol=1e-12, atol=0) and np.allclose(Ew, Ef, rtol=1e-12, atol=0)
+
+
+def test_replay_final_record_reports_the_end_state():
+    """replay(final=True) of a whole greedy trajectory ends at a state where no
+    move improves the FOM, the same FOM as the trajectory's last step."""
+    from oracle import greedy as og
+    p = W.tiny(5, 6, n_mon=4, steps=200)
+    tr = og.greedy(p, tier="T2")
+    assert tr.stopped
+    rep = og.replay(p, [(s.pixel, s.eps_idx) for s in tr.steps], tier="T2u", final=True)
+    assert len(rep) == len(tr.steps) + 1
+    for r, s in zip(rep, tr.steps):
+        assert (r["oracle_pixel"], r["oracle_eps"]) == (s.pixel, s.eps_idx)
+    last = rep[-1]
+    assert last["F_taken"] is None and last["oracle_pixel"] is None
+    assert abs(last["fom_before"] - tr.steps[-1].fom) <= 1e-12 * tr.steps[-1].fom
+    assert not last["Fstar"] > last["fom_before"] * (1 + p.tau)
