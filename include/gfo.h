@@ -31,7 +31,8 @@
  *     after the stream is synchronised.  Exceptions are stated per function.
  *   - Return value: GFO_OK (0) or a negative error detected on the host:
  *     GFO_EINVAL (bad sizes or null pointers), GFO_EHIP (a HIP call failed),
- *     GFO_ENOSPC (workspace too small).  Conditions met on the device are OR-ed
+ *     GFO_ENOSPC (workspace too small), GFO_ERANGE (refresh_G: more flipped
+ *     pixels than kmax).  Conditions met on the device are OR-ed
  *     into *state->status (GFO_STATUS_*), to be read by the caller when it
  *     synchronises.  The library never aborts the process.
  */
@@ -48,7 +49,7 @@ extern "C" {
 
 enum { GFO_C64 = 0, GFO_C128 = 1 };            /* storage type of G and E */
 enum { GFO_FP32 = 0, GFO_BF16 = 1 };           /* MFMA input type of the rank-k update */
-enum { GFO_OK = 0, GFO_EINVAL = -1, GFO_EHIP = -2, GFO_ENOSPC = -3 };
+enum { GFO_OK = 0, GFO_EINVAL = -1, GFO_EHIP = -2, GFO_ENOSPC = -3, GFO_ERANGE = -4 };
 enum {                                         /* bits of the device status word */
   GFO_STATUS_SINGULAR = 1,      /* |1 - alpha G_jj| < 1e-12: move refused */
   GFO_STATUS_NONFINITE = 2,     /* a candidate score was NaN or infinite */
@@ -133,7 +134,10 @@ int gfo_scores_offset(const gfo_problem* prob, int64_t ldG, int32_t kmax, size_t
  * All Hankel values are evaluated in FP64 and rounded once to the storage
  * type.  In deferred mode (state.delay > 0) the design block is written on
  * and above its diagonal only and state.lower_stale is set (gfo_sync_lower
- * completes it); otherwise the whole matrix is written and the flag cleared. */
+ * completes it); otherwise the whole matrix is written and the flag cleared.
+ * Exception to asynchrony: copies h_mon_xy to the workspace and synchronises
+ * `stream` before returning, so the caller's host array need not outlive the
+ * call. */
 int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 
 /* score_candidates - score every candidate move and select (paper Sec. II A:
@@ -275,10 +279,15 @@ int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d
  *   G = G0 + G0[:, V] (I - B_V G0[V, V])^-1 B_V G0[V, :],
  *   E = Einc + G0[:, V] (I - B_V G0[V, V])^-1 B_V Einc[V],
  * then rounds G and E once to the storage type.  Removes the rounding drift
- * of repeated rank-1 updates.  Requires init_G0 on this workspace and
- * |V| <= kmax (else GFO_STATUS_REFRESH_OVERFLOW and nothing is changed).
- * In deferred mode the design block is written on and above its diagonal only
- * (state.lower_stale set).  Synchronises `stream` once to read |V|. */
+ * of repeated rank-1 updates, and discards pending deferred terms (the
+ * rebuilt G includes every accepted move).  Requires init_G0 on this workspace
+ * and |V| <= kmax.  |V| is counted first: with |V| > kmax the call returns
+ * GFO_ERANGE and sets GFO_STATUS_REFRESH_OVERFLOW, and nothing else changes
+ * (G, E, diag64, the pending deferred terms and state.pending_calls are left
+ * as they were).  In deferred mode the design block is written on and above
+ * its diagonal only (state.lower_stale set).  Exception to asynchrony:
+ * synchronises `stream` once, to read |V|, before any of the rebuild is
+ * enqueued. */
 int refresh_G(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 
 /* Autotuner hooks for the streaming rank-1 kernel of apply_flip: the kernel

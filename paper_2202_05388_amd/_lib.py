@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libgfo.so")
 
 GFO_C64, GFO_C128 = 0, 1
 GFO_FP32, GFO_BF16 = 0, 1
-GFO_OK, GFO_EINVAL, GFO_EHIP, GFO_ENOSPC = 0, -1, -2, -3
+GFO_OK, GFO_EINVAL, GFO_EHIP, GFO_ENOSPC, GFO_ERANGE = 0, -1, -2, -3, -4
 GFO_STATUS_SINGULAR, GFO_STATUS_NONFINITE = 1, 2
 GFO_STATUS_HISTORY_FULL, GFO_STATUS_REFRESH_OVERFLOW = 4, 8
 GFO_MAX_EPS = 8
@@ -57,7 +57,12 @@ _lib = None
 
 
 class GfoError(RuntimeError):
-    pass
+    """A libgfo call returned an error; `code` is its GFO_E* value (None when
+    the error was found in the binding itself)."""
+
+    def __init__(self, msg, code=None):
+        super().__init__(msg)
+        self.code = code
 
 
 def lib():
@@ -103,7 +108,7 @@ def lib():
 
 def check(rc: int, what: str) -> None:
     if rc != GFO_OK:
-        raise GfoError(f"{what} failed: {rc} ({lib().gfo_strerror(rc).decode()})")
+        raise GfoError(f"{what} failed: {rc} ({lib().gfo_strerror(rc).decode()})", code=rc)
 
 
 def version() -> str:

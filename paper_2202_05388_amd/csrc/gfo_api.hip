@@ -139,6 +139,7 @@ const char* gfo_strerror(int code) {
     case GFO_EINVAL: return "invalid argument (sizes, null pointers or alignment)";
     case GFO_EHIP: return "a HIP runtime call or kernel launch failed";
     case GFO_ENOSPC: return "workspace too small";
+    case GFO_ERANGE: return "more flipped pixels than the refresh workspace holds (kmax)";
     default: return "unknown error";
   }
 }
@@ -400,9 +401,17 @@ int refresh_G(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   Layout L;
   if ((rc = validate_state(prob, st, &L))) return rc;
   const Geo g = make_geo(prob, st);
+  // the flipped set is counted first: a set larger than kmax is refused before
+  // anything of the state changes (pending deferred terms included)
+  int32_t k = 0;
+  if ((rc = launch_refresh_count(g, st, L, stream, &k))) return rc;
+  if (k > st->kmax) {
+    if (launch_refresh_overflow(st, stream) != hipSuccess) return GFO_EHIP;
+    return GFO_ERANGE;
+  }
   if (launch_dl_reset(g, st, L, stream) != hipSuccess) return GFO_EHIP;   // pending terms discarded
   st->pending_calls = 0;
-  rc = launch_refresh(g, st, L, stream);
+  rc = launch_refresh(g, st, L, k, stream);
   // every entry rebuilt, or (deferred mode, or lower_stale = 1 on entry) the
   // upper triangle of the design block
   if (rc == GFO_OK) st->lower_stale = g.upper;

@@ -380,7 +380,11 @@ hipError_t launch_apply(const Geo& g, gfo_state* st, const Layout& L, const gfo_
                         hipStream_t s);
 hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* picks,
                          int k, int precision, hipStream_t s);
-int launch_refresh(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
+// refresh_G in two parts: the flipped list and its length k (synchronises the
+// stream), then the rebuild for that list (k <= kmax)
+int launch_refresh_count(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s, int32_t* k);
+hipError_t launch_refresh_overflow(gfo_state* st, hipStream_t s);
+int launch_refresh(const Geo& g, gfo_state* st, const Layout& L, int32_t k, hipStream_t s);
 hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
 hipError_t launch_sync_lower(const Geo& g, gfo_state* st, hipStream_t s);
 template <typename T>

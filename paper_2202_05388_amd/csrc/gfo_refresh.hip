@@ -331,8 +331,26 @@ __global__ void k_rf_field(Geo g, const double* __restrict__ mon_xy, const doubl
   E[r] = St<T>::from_d(s);
 }
 
+// Flipped list V (in the workspace) and its length k, read back to the host
+// (one stream synchronisation).  Changes nothing else.
+int launch_refresh_count(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s,
+                         int32_t* k) {
+  int32_t* V = (int32_t*)((char*)st->work + L.rf_V);
+  hipLaunchKernelGGL(k_rf_list, dim3(1), dim3(1024), 0, s, g, (const uint8_t*)st->eps_idx, V);
+  *k = 0;
+  if (hipMemcpyAsync(k, V + g.N, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return GFO_EHIP;
+  return GFO_OK;
+}
+
+hipError_t launch_refresh_overflow(gfo_state* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_rf_overflow, dim3(1), dim3(64), 0, s, st->status);
+  return hipGetLastError();
+}
+
 template <typename T>
-static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {
+static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, int32_t k, hipStream_t s) {
   char* w = (char*)st->work;
   const double2* table = (const double2*)(w + L.table);
   const double* mon = (const double*)(w + L.mon_xy);
@@ -342,15 +360,6 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, hipStream
   double2* f = (double2*)(w + L.rf_piv);
   double2* Z = (double2*)(w + L.rf_Z);
   double2* x = (double2*)(w + L.rf_x);
-  hipLaunchKernelGGL(k_rf_list, dim3(1), dim3(1024), 0, s, g, (const uint8_t*)st->eps_idx, V);
-  int32_t k = 0;
-  if (hipMemcpyAsync(&k, V + g.N, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return GFO_EHIP;
-  if (k > st->kmax) {
-    hipLaunchKernelGGL(k_rf_overflow, dim3(1), dim3(64), 0, s, st->status);
-    return hipGetLastError() == hipSuccess ? GFO_OK : GFO_EHIP;
-  }
   const int kp = (k + 3) / 4 * 4;
   if (kp > 0) {
     const int64_t nu = (int64_t)g.R * kp;
@@ -400,9 +409,9 @@ hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const dou
   return hipGetLastError();
 }
 
-int launch_refresh(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {
-  if (g.dtype == GFO_C64) return refresh_typed<float2>(g, st, L, s);
-  return refresh_typed<double2>(g, st, L, s);
+int launch_refresh(const Geo& g, gfo_state* st, const Layout& L, int32_t k, hipStream_t s) {
+  if (g.dtype == GFO_C64) return refresh_typed<float2>(g, st, L, k, s);
+  return refresh_typed<double2>(g, st, L, k, s);
 }
 
 }  // namespace gfo
