@@ -15,7 +15,8 @@ def test_flush_minimal_bytes_per_variant():
     assert bench.flush_alg_bytes("w32_pipe8_3m", "c64", N, ld) == 16 * N * ld
     assert bench.flush_alg_bytes("sym_pipe8_3m_nt", "c64", N, ld) == 12 * N * ld
     assert bench.flush_alg_bytes("up_pipe8_3m_nt", "c64", N, ld, n_mon) == 8 * N * ld
-    assert bench.flush_alg_bytes(None, "c128", N, ld) == 32 * N * ld
+    # complex128: the FP64 flush of the upper triangle and the monitor rows
+    assert bench.flush_alg_bytes(None, "c128", N, ld, n_mon) == 16 * N * ld + 32 * n_mon * ld
     # the pair flush also updates the monitor rows (read and written once)
     assert bench.flush_covers_monitors("up_pair4_3m_nt")
     assert not bench.flush_covers_monitors("up_pipe8_3m_nt")
@@ -35,3 +36,32 @@ def test_long_trajectory_workloads_flush_every_128():
     import workloads as W
     assert bench.LONG_TRAJECTORY_DELAY == {"strip48x2048_c64": 128}
     assert "strip48x2048_c64" in W.WORKLOADS
+
+
+def test_flush_flops_count_the_folded_terms_only():
+    N, ld, n_mon = 16384, 16384, 64
+    nb = N // 64
+    tiles = nb * (nb + 1) // 2 + ld // 64          # the triangle, then one band of monitor tiles
+    f64 = bench.flush_mfma_flops("up_pair4_3m_nt", "c64", N, ld, n_mon, 64)
+    assert f64 == 6.0 * 4096 * tiles * 64            # three real products of 2 flops each
+    assert bench.flush_mfma_flops("up_pair4_3m_nt", "c64", N, ld, n_mon, 20) == f64 * 20 / 64
+    # four real products in the plain form, every tile of the block
+    assert bench.flush_mfma_flops("w32", "c64", N, ld, n_mon, 1) == 8.0 * 4096 * nb * (ld // 64)
+
+
+def test_flush_roofline_bound_follows_the_terms():
+    N, ld, n_mon = 16384, 16384, 64
+    v = "up_pair4_3m_nt"
+    # 64 terms per flush at 0.575 ms: matrix-core bound, below the FP32 peak
+    r = bench.flush_roofline(v, "c64", N, ld, n_mon, [64, 64], [0.575, 0.575])
+    assert r["bound"] == "mfma" and 0.5 < r["frac"] < 0.6 and r["launches"] == 2
+    # a lone 20-term flush moves the same bytes for a third of the products: HBM bound
+    r = bench.flush_roofline(v, "c64", N, ld, n_mon, [20], [0.40])
+    assert r["bound"] == "hbm" and r["achieved"] == r["algorithmic_bytes_per_launch"] / 0.40e-3 / 1e9
+    assert bench.flush_roofline(v, "c64", N, ld, n_mon, [], []) is None
+
+
+def test_host_info_fields():
+    h = bench.host_info()
+    assert set(h) == {"cpu_model", "logical_cpus", "ram_gb", "blas", "blas_threads"}
+    assert h["logical_cpus"] >= 1

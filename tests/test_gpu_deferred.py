@@ -20,8 +20,8 @@ def _job(p, **kw):
     return Job(p, device="cuda:0", **kw)
 
 
-def _rel(a, b):
-    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+# element-wise relative error with an absolute floor of 1e-3 x the largest entry
+from parity import c64_drift_tol, rel_elem as _rel  # noqa: E402
 
 
 @pytest.mark.parametrize("dtype,delay", [("c128", 16), ("c128", 64), ("c64", 16), ("c64", 64),
@@ -38,11 +38,11 @@ def test_deferred_equals_eager(dtype, delay):
     assert np.array_equal(eager.history(), lazy.history())
     Ge, Ee, de, ie = eager.host_state()
     Gl, El, dl, il = lazy.host_state()
-    tol = 1e-12 if dtype == "c128" else 3e-6
+    tol = 1e-12 if dtype == "c128" else c64_drift_tol(n1)
     assert _rel(Gl, Ge) <= tol and _rel(El, Ee) <= tol and _rel(dl, de) <= tol
     assert np.array_equal(ie, il) and lazy.status() == 0
     Gd, Ed = ost.dense_state(p, ost.eps_of(p, il))
-    assert _rel(Gl, Gd) <= (1e-11 if dtype == "c128" else 2e-5)
+    assert _rel(Gl, Gd) <= (1e-11 if dtype == "c128" else c64_drift_tol(n1))
 
 
 def test_deferred_square32_fp64_matches_stored_oracle():
@@ -66,7 +66,7 @@ def test_deferred_square128_c64_matches_oracle(fused):
     gfo_greedy_steps (one kernel per move), else score_candidates + apply_flip.
     The fields at the monitors and at sampled pixels after 100 moves, the move
     sequence (up to certified ties) and the final FOM match the FP64 oracle."""
-    from test_gpu_refresh import certify_sequence
+    from parity import certify_sequence
     gold = json.load(open(os.path.join(HERE, "golden", "square128_fp64.json")))
     p = W.SQUARE_128
     N = p.n
@@ -164,7 +164,8 @@ def test_flush_variants_agree(delay):
             assert job.run_greedy(150, poll_every=25) == n_ref
             assert np.array_equal(job.history(), eager.history())
             G, E, d, i = job.host_state()
-            assert _rel(G, Ge) <= 3e-6 and _rel(E, Ee) <= 3e-6 and np.array_equal(i, ie)
+            tol = c64_drift_tol(n_ref)
+            assert _rel(G, Ge) <= tol and _rel(E, Ee) <= tol and np.array_equal(i, ie)
             states[name] = G
     finally:
         L.flush_set_variant(old)
@@ -278,15 +279,16 @@ def test_upper_only_flush_then_sync_lower():
     G = job.G[:, :N].cpu().to(torch.complex128).numpy()
     iu, il = np.triu_indices(N), np.tril_indices(N, -1)
     D, De = G[:N], Ge[:N]
-    assert _rel(D[iu], De[iu]) <= 3e-6
-    assert not _rel(D[il], De[il]) <= 1e-3         # the lower triangle was left behind
-    assert _rel(G[N:], Ge[N:]) <= 3e-6             # monitor rows are current
+    tol = c64_drift_tol(n_ref)
+    assert _rel(D[iu], De[iu]) <= tol
+    assert not _rel(D[il], De[il]) <= 1e-1         # the lower triangle was left behind
+    assert _rel(G[N:], Ge[N:]) <= tol              # monitor rows are current
     job.sync_lower()
     assert job.state.lower_stale == 0
     G2, E2, d2, i2 = job.host_state()
     D2 = G2[:N]
     assert np.array_equal(D2[iu], D[iu]) and np.array_equal(D2[il], D2.T[il])
-    assert _rel(G2, Ge) <= 3e-6 and _rel(E2, Ee) <= 3e-6 and np.array_equal(i2, ie)
+    assert _rel(G2, Ge) <= tol and _rel(E2, Ee) <= tol and np.array_equal(i2, ie)
     job.sync_lower()                                # current: a no-op
     assert np.array_equal(job.host_state()[0], G2)
 
@@ -310,4 +312,5 @@ def test_eager_moves_after_an_upper_only_flush():
     assert np.array_equal(job.history(), ref.history())
     G, E, d, i = job.host_state()
     Gr, Er, dr, ir = ref.host_state()
-    assert _rel(G, Gr) <= 3e-6 and _rel(E, Er) <= 3e-6 and np.array_equal(i, ir)
+    tol = c64_drift_tol(80)
+    assert _rel(G, Gr) <= tol and _rel(E, Er) <= tol and np.array_equal(i, ir)

@@ -6,6 +6,7 @@ import pytest
 from oracle import greedy as og
 from oracle import state as ost
 import workloads as W
+from parity import c64_drift_tol, rel_elem
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +30,7 @@ def test_eps_greedy_square21_matches_oracle(eps, seed):
     assert hist == [(s.pixel, s.eps_idx) for s in ref.steps] and n == len(ref.steps)
     assert abs(job.fom() - ref.steps[-1].fom) <= 1e-9 * ref.steps[-1].fom
     E = job.E.cpu().numpy()
-    assert np.linalg.norm(E - ref.E) <= 1e-9 * np.linalg.norm(ref.E)
+    assert rel_elem(E, ref.E) <= 1e-9
     assert job.status() == 0
 
 
@@ -57,10 +58,10 @@ def test_eps_greedy_deferred_equals_eager(dtype, delay):
     assert np.array_equal(a.history(), b.history())
     Ga, Ea, _, _ = a.host_state()
     Gb, Eb, _, _ = b.host_state()
-    tol = 1e-12 if dtype == "c128" else 3e-6
-    assert np.linalg.norm(Gb - Ga) <= tol * np.linalg.norm(Ga)
+    tol = 1e-12 if dtype == "c128" else c64_drift_tol(b.n_flips())
+    assert rel_elem(Gb, Ga) <= tol
     Gd, Ed = ost.dense_state(p, ost.eps_of(p, b.eps_idx.cpu().numpy()))
-    assert np.linalg.norm(Eb - Ed) <= (1e-11 if dtype == "c128" else 2e-5) * np.linalg.norm(Ed)
+    assert rel_elem(Eb, Ed) <= (1e-11 if dtype == "c128" else 2e-5)
 
 
 @pytest.mark.parametrize("eps,seed", [(0.3, 11), (1.0, 12)])
@@ -78,5 +79,5 @@ def test_eps_greedy_three_materials_matches_oracle(eps, seed):
     hist = [(int(a), int(b)) for a, b in job.history()]
     assert hist == [(s.pixel, s.eps_idx) for s in ref.steps] and n == len(ref.steps)
     E = job.E.cpu().numpy()
-    assert np.linalg.norm(E - ref.E) <= 1e-9 * np.linalg.norm(ref.E)
+    assert rel_elem(E, ref.E) <= 1e-9
     assert job.status() == 0

@@ -2,9 +2,12 @@
 topk > 1) against the oracle's rank-k rule, and apply_flips_rank_k (FP64 Woodbury
 core + matrix-core rank-k update) against the dense re-solve of the new structure.
 
-Tolerances: FP32 matrix-core inputs round U and W once to FP32, so G matches the
-re-solve to 5e-6 relative; BF16 inputs (8-bit mantissa) give about 4e-3
-relative error in the update term, checked at 1e-2 of the update and reported.
+Tolerances (element by element, tests/parity.py): E and the FP64 diagonal come
+from the FP64 Woodbury core, 5e-6; FP32 matrix-core inputs round U and W once to
+FP32, so G is held to the complex64 drift bound of k updates; BF16 inputs (8-bit
+mantissa) are held to 1e-2 of the largest update entry and reported.  Along the
+128x128 rank-16 trajectory the fields and the FOM agree with the exact state of
+the GPU's structure to 1e-4.
 """
 import numpy as np
 import pytest
@@ -21,8 +24,8 @@ def _job(p, **kw):
     return Job(p, device="cuda:0", **kw)
 
 
-def _rel(a, b):
-    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+# element-wise relative error with an absolute floor of 1e-3 x the largest entry
+from parity import c64_drift_tol, certify_rank_k_set, rel_elem as _rel  # noqa: E402
 
 
 @pytest.mark.parametrize("k,spacing,seed", [(16, 3, 0), (5, 0, 1), (32, 2, 2)])
@@ -71,9 +74,13 @@ def test_rank_k_update_equals_resolve(precision, s):
     assert _rel(d1, np.diagonal(Gd[:N])) <= 5e-6
     assert _rel(E1, Ed) <= 5e-6
     if precision == "fp32":
-        assert err_G / np.linalg.norm(Gd) <= 5e-6
+        assert _rel(G1, Gd) <= c64_drift_tol(s)
     else:
-        assert err_G / upd <= 1e-2
+        # each entry against the largest update entry: both BF16 factors of a
+        # product are rounded (unit roundoff 2^-8), so a product is off by up to
+        # 2 * 2^-8 = 7.8e-3 of |U_ri W_iq|, which cancellation can leave far above
+        # the entry's own update
+        assert _rel(G1 - G, Gd - G, floor=1.0) <= 1e-2
 
 
 def test_rank_k_skips_sentinels_duplicates_and_noops():
@@ -131,4 +138,51 @@ def test_rank_k_three_materials_follows_oracle_policy():
         assert len({a for a, _ in got}) == len(got)
         job.apply_rank_k(16, precision=L.GFO_FP32)
         assert abs(job.fom() - group[0].fom) <= 1e-4 * group[0].fom
+    assert job.status() == 0
+
+
+@pytest.mark.timeout(300)
+def test_rank16_square128_follows_oracle_policy():
+    """The 128x128 rank-16 workload (spacing 3, FP32 matrix-core inputs), 8 steps:
+    each step's set equals the oracle's rank-k rule up to certified ties, judged
+    on the exact (FP64 flipped-set) scores of the structure the GPU chose it at;
+    after each step the FOM and the fields at the monitors and at sampled pixels
+    agree element by element with the exact state of the GPU's structure to 1e-4,
+    and while the sets agree the FOM follows the oracle's own rank-k trajectory."""
+    from paper_2202_05388_amd import _lib as L
+    p = W.SQUARE_128_RANK16
+    N, steps = p.n, 8
+    m0 = N + p.fom_monitor
+    ref = og.rank_k_trajectory(p, steps=steps, tier="T2")
+    assert len(ref.steps) == steps
+    fs = ost.FlippedSet(p)
+    sample = np.random.default_rng(0).choice(N, 256, replace=False)
+    job = _job(p)
+    job.init()
+    idx = np.zeros(N, np.uint8)
+    same = 0
+    E, diag, rows = fs.state(ost.eps_of(p, idx), rows=[m0])
+    for t in range(steps):
+        job.score(topk=p.rank_k, min_spacing=p.min_spacing, tau=p.tau)
+        got = [(a, b) for a, b, _, _ in job.read_picks(p.rank_k) if a >= 0]
+        F = og.scores_closed_form(p, E, diag, rows[m0], idx)
+        common = certify_rank_k_set(F, ost.fom_of_state(p, E), got, p.rank_k, p.min_spacing,
+                                    p.nx, tol=1e-4)
+        if same == t and got == [(s.pixel, s.eps_idx) for s in ref.steps[t]]:
+            same += 1
+        print(f"  step {t}: {len(got)} picks, {common} equal to the oracle rule's prefix",
+              flush=True)
+        job.apply_rank_k(p.rank_k, precision=L.GFO_FP32)
+        for j, e in got:
+            idx[j] = e
+        E, diag, rows = fs.state(ost.eps_of(p, idx), rows=[m0])
+        fom = ost.fom_of_state(p, E)
+        assert abs(job.fom() - fom) <= 1e-4 * fom
+        if same == t + 1:
+            assert abs(job.fom() - ref.steps[t][0].fom) <= 1e-4 * ref.steps[t][0].fom
+        Eg = job.E.cpu().numpy().astype(np.complex128)
+        assert _rel(Eg[N:], E[N:]) <= 1e-4
+        assert _rel(Eg[sample], E[sample]) <= 1e-4
+        assert np.array_equal(job.eps_idx.cpu().numpy(), idx)
+    print(f"rank-16 at 128x128: sets equal to the oracle's for {same} of {steps} steps", flush=True)
     assert job.status() == 0

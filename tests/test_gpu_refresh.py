@@ -20,8 +20,8 @@ def _job(p, **kw):
     return Job(p, device="cuda:0", **kw)
 
 
-def _rel(a, b):
-    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+# element-wise relative error with an absolute floor of 1e-3 x the largest entry
+from parity import c64_drift_tol, certify_sequence, rel_elem as _rel  # noqa: E402
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
@@ -48,6 +48,9 @@ def test_refresh_equals_dense_resolve(dtype, fill, seed):
 
 
 def test_refresh_overflow_sets_status_and_changes_nothing():
+    """More flipped pixels than kmax: GFO_ERANGE, the status bit, and the state
+    exactly as it was."""
+    from paper_2202_05388_amd import _lib as L
     p = W.tiny(6, 6, n_mon=4)
     idx = W.random_eps_idx(p, 0.5, 3)
     job = _job(p, kmax=4)
@@ -55,10 +58,35 @@ def test_refresh_overflow_sets_status_and_changes_nothing():
     G0, E0, d0, _ = job.host_state()
     import torch
     job.eps_idx.copy_(torch.from_numpy(idx))
-    job.refresh()
+    with pytest.raises(L.GfoError) as err:
+        job.refresh()
+    assert err.value.code == L.GFO_ERANGE
     G1, E1, d1, _ = job.host_state()
-    assert job.status() & 8
-    assert np.array_equal(G0, G1) and np.array_equal(E0, E1)
+    assert job.status() & L.GFO_STATUS_REFRESH_OVERFLOW
+    assert np.array_equal(G0, G1) and np.array_equal(E0, E1) and np.array_equal(d0, d1)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_refresh_overflow_in_deferred_mode_keeps_pending_terms(dtype):
+    """Deferred mode with pending terms and a flipped set larger than kmax: the
+    refused refresh keeps the pending terms and the pending count, so the state
+    after the next flush is still the dense re-solve of the structure."""
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(10, 12, n_mon=4, dtype=dtype)
+    job = _job(p, kmax=3, delay=16)
+    job.init()
+    n = job.run_greedy(9, poll_every=9)
+    assert n == 9 and job.state.pending_calls == 9
+    with pytest.raises(L.GfoError) as err:
+        job.refresh()
+    assert err.value.code == L.GFO_ERANGE
+    assert job.state.pending_calls == 9
+    assert job.status() & L.GFO_STATUS_REFRESH_OVERFLOW
+    G, E, d, idx = job.host_state()                 # flushes the nine pending terms
+    Gd, Ed = ost.dense_state(p, ost.eps_of(p, idx))
+    tol = 1e-11 if dtype == "c128" else c64_drift_tol(9)
+    assert _rel(G, Gd) <= tol and _rel(E, Ed) <= tol
+    assert _rel(d, np.diagonal(Gd[:p.n])) <= (1e-11 if dtype == "c128" else 2e-6)
 
 
 def test_refresh_is_idempotent_and_removes_drift_c64():
@@ -109,38 +137,6 @@ def test_square128_fp64_trajectory_matches_oracle():
     assert abs(job.fom() - gold["steps"][-1]["fom"]) <= 1e-9 * gold["steps"][-1]["fom"]
 
 
-def certify_sequence(p, oracle_moves, gpu_moves, tol=1e-4):
-    """Parity of a reduced-precision move sequence against the FP64 greedy sequence.
-
-    The sequences must agree up to a step t; from t on, the oracle replays the
-    GPU's own moves and every move must be a certified tie: its exact FP64 score is
-    within tol of the best exact score at that state.  If the GPU stops first, the
-    oracle's best remaining move must improve the FOM by less than tol.
-    Returns the index of the first divergence (len of the sequences if none).
-    """
-    t = 0
-    while t < min(len(oracle_moves), len(gpu_moves)) and oracle_moves[t] == gpu_moves[t]:
-        t += 1
-    if t == len(oracle_moves) == len(gpu_moves):
-        return t
-    N = p.n
-    fs = ost.FlippedSet(p)
-    idx = np.zeros(N, np.uint8)
-    for j, e in gpu_moves[:t]:
-        idx[j] = e
-    for u in range(t, len(gpu_moves) + 1):
-        E, diag, rows = fs.state(ost.eps_of(p, idx), rows=[N + p.fom_monitor])
-        F = og.scores_closed_form(p, E, diag, rows[N + p.fom_monitor], idx)
-        Fstar = float(np.max(F))
-        if u == len(gpu_moves):
-            assert Fstar <= ost.fom_of_state(p, E) * (1 + tol), "stopped before the oracle"
-            break
-        j, e = gpu_moves[u]
-        assert F[j, e] >= (1 - tol) * Fstar, f"step {u}: move {j} is not a certified tie"
-        idx[j] = e
-    return t
-
-
 @pytest.mark.parametrize("refresh_every", [0, 64])
 def test_square128_c64_trajectory_matches_oracle(refresh_every):
     """complex64 storage, FP64 denominators, optional FP64 refresh: same pixel
@@ -160,11 +156,19 @@ def test_square128_c64_trajectory_matches_oracle(refresh_every):
     n = 100 + job.run_greedy(2000, poll_every=32, refresh_every=refresh_every)
     hist = [(int(a), int(b)) for a, b in job.history()]
     gp = [(s["pixel"], s["eps_idx"]) for s in gold["steps"]]
-    t = certify_sequence(p, gp, hist)
+    _, E, _, _ = job.host_state()
+    seen = {}
+    t = certify_sequence(p, gp, hist, checkpoints=[len(hist)],
+                         on_state=lambda step, Ex: seen.setdefault(step, Ex))
     print(f"c64 sequence: {n} moves, identical for the first {t}, oracle {len(gp)}", flush=True)
     assert t >= 150
-    _, E, _, _ = job.host_state()
     if t == len(gp) == len(hist):
         assert _rel(E[N:], _c(gold["final"]["E_mon"])) <= 1e-4
+        assert _rel(E[gold["sample_pixels"]], _c(gold["final"]["E_pix"])) <= 1e-4
+    else:
+        # the final fields against the oracle's state of the GPU's own structure
+        Ex = seen[len(hist)]
+        assert _rel(E[N:], Ex[N:]) <= 1e-4
+        assert _rel(E[gold["sample_pixels"]], Ex[gold["sample_pixels"]]) <= 1e-4
     assert abs(job.fom() - gold["steps"][-1]["fom"]) <= 1e-4 * gold["steps"][-1]["fom"]
     assert job.status() == 0

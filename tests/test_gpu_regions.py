@@ -7,6 +7,7 @@ import pytest
 from oracle import regions as orr
 from oracle import state as ost
 import workloads as W
+from parity import c64_drift_tol, rel_elem
 
 pytestmark = pytest.mark.gpu
 
@@ -61,7 +62,7 @@ def test_region_greedy_matches_oracle_trajectory():
     assert moves == [(s.pixel, s.eps_idx) for s in ref.steps]
     assert abs(job.fom() - ref.steps[-1].fom) <= 1e-9 * ref.steps[-1].fom
     E = job.E.cpu().numpy()
-    assert np.linalg.norm(E - ref.E) <= 1e-9 * np.linalg.norm(ref.E) and job.status() == 0
+    assert rel_elem(E, ref.E) <= 1e-9 and job.status() == 0
 
 
 @pytest.mark.parametrize("dtype,delay", [("c128", 16), ("c64", 64)])
@@ -76,10 +77,10 @@ def test_region_greedy_deferred_equals_eager(dtype, delay):
     assert ma == mb and na >= 10
     Ga, Ea, _, _ = a.host_state()
     Gb, Eb, _, _ = b.host_state()
-    tol = 1e-12 if dtype == "c128" else 3e-6
-    assert np.linalg.norm(Gb - Ga) <= tol * np.linalg.norm(Ga)
+    tol = 1e-12 if dtype == "c128" else c64_drift_tol(b.n_flips())
+    assert rel_elem(Gb, Ga) <= tol
     Gd, Ed = ost.dense_state(p, ost.eps_of(p, b.eps_idx.cpu().numpy()))
-    assert np.linalg.norm(Eb - Ed) <= (1e-11 if dtype == "c128" else 2e-5) * np.linalg.norm(Ed)
+    assert rel_elem(Eb, Ed) <= (1e-11 if dtype == "c128" else 2e-5)
 
 
 @pytest.mark.parametrize("delay", [0, 16])
@@ -97,8 +98,9 @@ def test_region_rank_k_application_equals_sequential(delay):
     assert ma == mb and na >= 10
     Ga, Ea, _, _ = a.host_state()
     Gb, Eb, _, _ = b.host_state()
-    assert np.linalg.norm(Gb - Ga) <= 5e-6 * np.linalg.norm(Ga)
-    assert np.linalg.norm(Eb - Ea) <= 5e-6 * np.linalg.norm(Ea)
+    tol = c64_drift_tol(b.n_flips())
+    assert rel_elem(Gb, Ga) <= tol
+    assert rel_elem(Eb, Ea) <= tol
 
 
 def _lens3(n, dtype="c128"):
@@ -135,7 +137,7 @@ def test_region_greedy_three_materials_matches_oracle():
     n, moves = job.run_region_greedy(200, poll_every=8)
     assert moves == [(s.pixel, s.eps_idx) for s in ref.steps]
     E = job.E.cpu().numpy()
-    assert np.linalg.norm(E - ref.E) <= 1e-9 * np.linalg.norm(ref.E) and job.status() == 0
+    assert rel_elem(E, ref.E) <= 1e-9 and job.status() == 0
 
 
 def test_region_moves_on_an_odd_grid_are_refused():
