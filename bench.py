@@ -72,6 +72,11 @@ def run_steps(job, target, poll, events=None, refresh_every=0, flush_events=None
     """Issue greedy steps until `target` accepted moves; re-init a job that stopped.
     fused: each chunk of steps is one gfo_greedy_steps call.
 
+    flush_events: an EventPool; every flush in the window is timed with a pair
+    of its events (the flush a chunk ends with, the flush before a restart and
+    the one at the end), and the number of terms it folds (accepted moves since
+    the previous flush, refresh or init) is recorded in flush_events.terms.
+
     Returns (accepted, calls, restarts, accepted_flags) where accepted_flags[i]
     tells whether step call i made a move.
     """
@@ -81,16 +86,30 @@ def run_steps(job, target, poll, events=None, refresh_every=0, flush_events=None
     calls = 0
     restarts = 0
     flags = []
-    in_run_issued = 0
     in_run_acc = job.n_flips()
+    since_flush = 0                         # accepted moves not yet folded into G
+    if flush_events is not None and not hasattr(flush_events, "terms"):
+        flush_events.terms = []
+
+    def timed_flush():
+        nonlocal since_flush
+        if job.delay and job.state.pending_calls > 0:
+            if flush_events is not None:
+                a, b = flush_events.next()
+                L.time_next_k1(a, b)
+                flush_events.terms.append(since_flush)
+            job.flush()
+        since_flush = 0
+
     while accepted < target:
         chunk = min(poll, target - accepted)
         if refresh_every:
             chunk = min(chunk, refresh_every - in_run_acc % refresh_every)
+        # every call counts toward the flush interval: a chunk that reaches it
+        # launches exactly one flush (chunk <= delay)
+        flushes = bool(job.delay) and job.state.pending_calls + chunk >= job.delay
         if fused:
-            # every call counts toward the flush interval, so a chunk that reaches it
-            # is certain to launch a flush: time the first one
-            if flush_events is not None and job.state.pending_calls + chunk >= job.delay:
+            if flush_events is not None and flushes:
                 a, b = flush_events.next()
                 L.time_next_k1(a, b)
             job.greedy_steps(chunk)
@@ -109,18 +128,21 @@ def run_steps(job, target, poll, events=None, refresh_every=0, flush_events=None
         flags.extend([True] * new + [False] * (chunk - new))
         accepted += new
         in_run_acc = n
-        in_run_issued += chunk
+        since_flush += new
+        if flushes:
+            folded = min(job.delay, since_flush)
+            if flush_events is not None:
+                flush_events.terms.append(folded)
+            since_flush -= folded
         if new < chunk:                        # the trajectory ended: restart the job
-            if job.delay:
-                job.flush()                    # apply every accepted move to G before discarding it
+            timed_flush()                      # apply every accepted move to G before discarding it
             job.init()
             restarts += 1
-            in_run_issued = 0
             in_run_acc = 0
         elif refresh_every and in_run_acc % refresh_every == 0:
-            job.refresh()
-    if job.delay:
-        job.flush()                            # no pending update is left outside the timed work
+            job.refresh()                      # rebuilds G from every accepted move
+            since_flush = 0
+    timed_flush()                              # no pending update is left outside the timed work
     return accepted, calls, restarts, flags
 
 
@@ -137,15 +159,59 @@ def flush_covers_monitors(variant):
 
 
 def flush_alg_bytes(variant, dtype, N, ld, n_mon=0):
-    """Minimal HBM bytes of one flush of the N x ld design block: read and
-    written once (complex128: 32 N ld); complex64 symmetric variants read half
-    of it and write all of it (12 N ld) or, keeping only the upper triangle,
-    read and write half of it (8 N ld).  Plus the monitor rows (16 n_mon ld)
-    for a variant that updates them in the same kernel."""
+    """Minimal HBM bytes of one flush of the N x ld design block.  complex64:
+    symmetric variants read half of it and write all of it (12 N ld) or, keeping
+    only the upper triangle, read and write half of it (8 N ld); plus the
+    monitor rows (16 n_mon ld) for a variant that updates them in the same
+    kernel.  complex128 (FP64 flush of the upper triangle and the monitor rows):
+    16 N ld + 32 n_mon ld."""
     if dtype != "c64":
-        return 32 * N * ld
+        return 16 * N * ld + 32 * n_mon * ld
     mon = 16 * n_mon * ld if flush_covers_monitors(variant) else 0
     return {"sym": 12, "up": 8, None: 16}[flush_triangle(variant)] * N * ld + mon
+
+
+def flush_mfma_flops(variant, dtype, N, ld, n_mon, terms):
+    """Matrix-core flops of one flush that folds `terms` pending terms: real
+    flops of the complex products over the 64 x 64 tiles the kernel computes
+    (for the triangle variants and the complex128 flush, the tiles on and above
+    the diagonal of the design block, plus the monitor rows where the kernel
+    covers them), 2 flops per real product and three real products per complex
+    one in the _3m variants (four otherwise).  Only the terms actually folded
+    count, not the zero padding up to the kernel's term bucket."""
+    nb = (N + 63) // 64
+    if dtype != "c64":
+        tiles = nb * (nb + 1) // 2 + (n_mon + 63) // 64 * (ld // 64)
+        per = 8
+    else:
+        tri = flush_triangle(variant)
+        tiles = nb * (nb + 1) // 2 if tri else nb * (ld // 64)
+        if flush_covers_monitors(variant):
+            tiles += (n_mon + 63) // 64 * (ld // 64)
+        per = 6 if "3m" in str(variant) else 8
+    return float(per) * 64 * 64 * tiles * terms
+
+
+def flush_roofline(variant, dtype, N, ld, n_mon, terms, ms):
+    """Roofline of the flushes of a timed window: every flush's matrix-core
+    flops (from the terms it folds) and minimal HBM bytes, summed, against the
+    summed kernel time; the bound is the larger of the two ideal times."""
+    if not ms:
+        return None
+    flops = sum(flush_mfma_flops(variant, dtype, N, ld, n_mon, r) for r in terms)
+    nbytes = flush_alg_bytes(variant, dtype, N, ld, n_mon) * len(ms)
+    secs = sum(ms) * 1e-3
+    peak = MFMA_PEAK_TFLOPS[dtype]
+    t_mfma, t_hbm = flops / (peak * 1e12), nbytes / (HBM_PEAK_GBS * 1e9)
+    common = dict(avg_launch_us=1e6 * secs / len(ms), launches=len(ms),
+                  mean_terms=sum(terms) / len(terms), mfma_flops_per_launch=flops / len(ms),
+                  algorithmic_bytes_per_launch=nbytes / len(ms), variant=variant)
+    if t_hbm >= t_mfma:
+        a = nbytes / secs / 1e9
+        return dict(bound="hbm", achieved=a, peak=HBM_PEAK_GBS, unit="GB/s", frac=a / HBM_PEAK_GBS,
+                    **common)
+    a = flops / secs / 1e12
+    return dict(bound="mfma", achieved=a, peak=peak, unit="TFLOP/s", frac=a / peak, **common)
 
 
 def copy_ceiling(nbytes=2 << 30, reps=10):
@@ -283,22 +349,19 @@ def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     fl = fev.elapsed_ms()
+    terms = list(getattr(fev, "terms", []))
     fev.close()
+    assert len(terms) == len(fl), (len(terms), len(fl))
     hist = job.history()
     N = problem.n
     ld = (N + 63) // 64 * 64
-    elem = 8 if problem.dtype == "c64" else 16
-    fl_ms = sum(fl) / len(fl) if fl else None
+    variant = None if flush_tuned is None else flush_tuned["name"]
+    roof = flush_roofline(variant, problem.dtype, N, ld, problem.n_mon, terms, fl)
     out = dict(delay=delay, fused=fused, storage=problem.dtype, accepted=acc, restarts=restarts,
                steps_per_s=acc / dt, ms_per_step=1e3 * dt / acc, flushes_timed=len(fl),
-               flush_variant=None if flush_tuned is None else flush_tuned["name"],
-               flush_us=None if fl_ms is None else fl_ms * 1e3,
-               flush_tflops=None if fl_ms is None else 8.0 * N * ld * delay / (fl_ms * 1e-3) / 1e12,
-               flush_gbs=None if fl_ms is None else
-               flush_alg_bytes(flush_tuned and flush_tuned.get("name"), problem.dtype, N, ld,
-                               problem.n_mon)
-               / (fl_ms * 1e-3) / 1e9,
-               fom_last=job.fom(), status=job.status(),
+               flush_terms=terms, flush_variant=variant,
+               flush_us=None if not fl else 1e3 * sum(fl) / len(fl),
+               flush_roofline=roof, fom_last=job.fom(), status=job.status(),
                last_run_pixels=[int(x) for x in hist[:, 0]])
     del job
     torch.cuda.empty_cache()
@@ -435,24 +498,32 @@ def regions_cpu_baseline(problem, steps=20):
 
 
 def time_rank_k(problem, steps, warmup, precision):
-    """Rank-k steps: score with top-k + spacing, then one joint Woodbury update.
+    """Rank-k steps as the batched workload specifies them: score with top-k and
+    the spacing rule, one joint Woodbury update, and the FP64 refresh after every
+    `problem.refresh_every` rank-k steps (kmax covers every pixel those steps can
+    flip).  `steps` counts rank-k steps that accepted at least one move; a job
+    whose step accepts none is restarted.  Polls the move counter after every
+    step (a rank-k step is ~1 ms).
 
-    `steps` counts rank-k steps that accepted at least one move; the job is
-    restarted when a step accepts none.  Polls the move counter after every
-    step (a rank-k step is ~1 ms).  Returns moves/s, steps/s and the mean time
-    of the matrix-core update kernels."""
+    Reports moves/s and steps/s over the whole window (refreshes included), the
+    mean time of the matrix-core update kernel, the refresh time, the FOM after
+    every step against the cumulative number of flips, and at every refresh the
+    FOM error of the FP32/BF16 path: |FOM before - FOM after| / FOM after, the
+    refresh being the FP64 re-solve of the same structure."""
     import torch
     from paper_2202_05388_amd import _lib as L
     from paper_2202_05388_amd.hiprt import EventPool
     from paper_2202_05388_amd.job import Job
 
     prec = L.GFO_FP32 if precision == "fp32" else L.GFO_BF16
-    job = Job(problem, device="cuda:0", kmax=0)
+    re = problem.refresh_every
+    kmax = min(problem.n, problem.rank_k * max(steps, warmup))
+    job = Job(problem, device="cuda:0", kmax=kmax)
 
     def run(n, events):
         job.init()
-        done = moves = restarts = 0
-        durations_ok = []
+        done = moves = restarts = in_run = 0
+        durations_ok, curve, errs, refresh_s = [], [(0, job.fom())], [], 0.0
         last = 0
         while done < n:
             if events is not None:
@@ -465,33 +536,85 @@ def time_rank_k(problem, steps, warmup, precision):
             if now == last:
                 job.init()
                 restarts += 1
-                last = 0
+                last = in_run = 0
                 continue
             moves += now - last
             last = now
             done += 1
-        return moves, restarts, durations_ok
+            in_run += 1
+            curve.append((moves, job.fom()))
+            if re and in_run % re == 0:
+                f0 = job.fom()
+                t0 = time.perf_counter()
+                job.refresh()
+                f1 = job.fom()                     # synchronises
+                refresh_s += time.perf_counter() - t0
+                errs.append(abs(f0 - f1) / f1)
+        return moves, restarts, durations_ok, curve, errs, refresh_s
 
     run(warmup, None)
     torch.cuda.synchronize()
     ev = EventPool(4 * steps + 16)
     t0 = time.perf_counter()
-    moves, restarts, ok = run(steps, ev)
+    moves, restarts, ok, curve, errs, refresh_s = run(steps, ev)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     d = [x for x, f in zip(ev.elapsed_ms(), ok) if f]
     ev.close()
     N, R = problem.n, problem.rows
     k_ms = sum(d) / len(d)
+    flipped = int((job.eps_idx.cpu().numpy() != 0).sum())
+    best = max(curve, key=lambda c: c[1])
     out = dict(precision=precision, rank=problem.rank_k, min_spacing=problem.min_spacing,
-               steps=steps, moves=moves, restarts=restarts, moves_per_s=moves / dt,
-               steps_per_s=steps / dt, update_us=k_ms * 1e3,
-               update_gbs=16 * N * R / (k_ms * 1e-3) / 1e9,
-               update_tflops=8 * N * R * problem.rank_k / (k_ms * 1e-3) / 1e12,
-               fom_last=job.fom(), status=job.status())
+               refresh_every_steps=re, kmax=kmax, steps=steps, moves=moves, restarts=restarts,
+               moves_per_s=moves / dt, steps_per_s=steps / dt, seconds=dt,
+               refreshes=len(errs), refresh_seconds=refresh_s, flipped_at_end=flipped,
+               update_us=k_ms * 1e3, update_gbs=16 * N * R / (k_ms * 1e-3) / 1e9,
+               update_hbm_frac=16 * N * R / (k_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+               fom_last=job.fom(), fom_best=best[1], flips_at_best=best[0],
+               fom_err_at_refresh_max=max(errs) if errs else None,
+               fom_err_at_refresh_mean=sum(errs) / len(errs) if errs else None,
+               fom_vs_flips=_sample_curve(curve), status=job.status())
     del job
     torch.cuda.empty_cache()
     return out
+
+
+def _sample_curve(curve, n=25):
+    """At most n (flips, FOM) points of a curve, its ends included."""
+    if len(curve) <= n:
+        return [[int(a), float(b)] for a, b in curve]
+    idx = sorted({round(i * (len(curve) - 1) / (n - 1)) for i in range(n)})
+    return [[int(curve[i][0]), float(curve[i][1])] for i in idx]
+
+
+def greedy_fom_curve(problem):
+    """FOM after every move of one rank-1 greedy trajectory to its end (the
+    predicted FOM each pick records, which the move reaches exactly)."""
+    import torch
+    from paper_2202_05388_amd import _lib as L
+    from paper_2202_05388_amd.job import Job
+
+    job = Job(problem, device="cuda:0", kmax=2 * problem.refresh_every, delay=64)
+    job.init()
+    cap = 4096
+    buf = torch.zeros(cap * L.PICK_BYTES, dtype=torch.uint8, device="cuda:0")
+    curve, done = [(0, job.fom())], 0
+    while done < cap:
+        n = min(64, cap - done)
+        job.greedy_steps(n, out=buf.data_ptr() + done * L.PICK_BYTES)
+        raw = buf[done * L.PICK_BYTES:(done + n) * L.PICK_BYTES].cpu().numpy().tobytes()
+        recs = (L.Pick * n).from_buffer_copy(raw)
+        made = [r for r in recs if r.pixel >= 0]
+        curve.extend((done + i + 1, float(r.fom_new)) for i, r in enumerate(made))
+        done += n
+        if len(made) < n:
+            break
+    job.flush()
+    torch.cuda.synchronize()
+    del job
+    torch.cuda.empty_cache()
+    return curve
 
 
 def time_refresh(problem):
@@ -515,24 +638,61 @@ def time_refresh(problem):
     return out
 
 
-def cpu_baseline(problem, max_steps):
-    """The FP64 oracle (flipped-set tier) on the same workload, host cores."""
-    import numpy as np
-    from oracle import greedy as og
-
+def host_info():
+    """CPU model, logical CPUs, RAM and the BLAS library numpy uses (threadpoolctl)."""
+    info = dict(cpu_model=None, logical_cpus=os.cpu_count(), ram_gb=None, blas=None,
+                blas_threads=None)
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["ram_gb"] = round(int(line.split()[1]) / 1024**2, 1)
+                    break
+    except OSError:
+        pass
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+        blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if blas:
+            info["blas"] = f"{blas[0].get('internal_api')} {blas[0].get('version')}"
+            info["blas_threads"] = int(blas[0].get("num_threads", 1))
     except Exception:  # pragma: no cover
-        threads = os.cpu_count()
+        pass
+    return info
+
+
+def cpu_baseline(problem, max_steps):
+    """The FP64 oracle (flipped-set tier) on the same workload, host cores."""
+    from oracle import greedy as og
+
+    host = host_info()
     t0 = time.perf_counter()
     tr = og.greedy(problem.replace(tau=1e-9), steps=max_steps, tier="T2")
     dt = time.perf_counter() - t0
     n = len(tr.steps)
-    return dict(value=n / dt, unit="steps/s", cores=int(threads), kind="oracle",
+    return dict(value=n / dt, unit="steps/s", cores=int(host["blas_threads"] or os.cpu_count()),
+                kind="oracle",
                 sample=f"oracle greedy trajectory, flipped-set tier (FP64), {n} steps "
                        f"({'to termination' if tr.stopped else 'capped'}) of {problem.name}, "
-                       f"{dt:.1f} s"), [s.pixel for s in tr.steps], tr
+                       f"{dt:.1f} s", host=host), [s.pixel for s in tr.steps], tr
+
+
+def cpu_dense_resolve_baseline(steps=10):
+    """The oracle's dense re-solve tier (T1: one direct solve of the 1024-pixel
+    system per step) on the 32x32 FP64 workload, its first `steps` steps."""
+    import workloads as W
+    from oracle import greedy as og
+    p = W.SMALL_32
+    t0 = time.perf_counter()
+    tr = og.greedy(p, steps=steps, tier="T1")
+    dt = time.perf_counter() - t0
+    return dict(kind="oracle", tier="T1", workload=p.name, value=len(tr.steps) / dt,
+                unit="steps/s", sample=f"first {len(tr.steps)} greedy steps, {dt:.1f} s")
 
 
 def main():
@@ -623,6 +783,8 @@ def main():
     if not args.no_cpu_baseline:
         _log("[bench] cpu baseline (oracle)")
         cpu, ref_pixels, tr = cpu_baseline(problem, max_steps=200)
+        if problem.name == "square128_c64":
+            cpu["dense_resolve_square32"] = cpu_dense_resolve_baseline()
         gpu_pixels = res["last_run_pixels"]
         n = min(len(ref_pixels), len(gpu_pixels))
         match = sum(1 for a, b in zip(ref_pixels, gpu_pixels) if a == b)
@@ -658,8 +820,15 @@ def main():
         rank_k = {}
         for prec in ("fp32", "bf16"):
             _log(f"[bench] rank-{rk.rank_k} steps ({prec})")
-            rank_k[prec] = time_rank_k(rk, steps=100, warmup=10, precision=prec)
+            rank_k[prec] = time_rank_k(rk, steps=rk.steps, warmup=16, precision=prec)
             _log(f"[bench] rank-{rk.rank_k} {prec}: {rank_k[prec]}")
+        g = greedy_fom_curve(problem)
+        rank_k["rank1_greedy"] = dict(moves=len(g) - 1, fom_last=g[-1][1],
+                                      fom_vs_flips=_sample_curve(g))
+        # flips the rank-16 form needs to reach the greedy trajectory's final FOM
+        for prec in ("fp32", "bf16"):
+            reach = [f for f, v in rank_k[prec]["fom_vs_flips"] if v >= g[-1][1]]
+            rank_k[prec]["flips_to_greedy_fom"] = reach[0] if reach else None
 
     eps_greedy = None
     if not args.no_eps_greedy and problem.name == "square128_c64":
@@ -704,37 +873,21 @@ def main():
     eager = dict(value=value, unit="steps/s", ms_per_step=1e3 * res["seconds"] / res["accepted"],
                  restarts=res["restarts"], roofline=eager_roof)
     d = (deferred or {}).get(problem.name)
-    if d is not None and d.get("flush_us"):
+    if d is not None and d.get("flush_roofline"):
         mode = (f"deferred rank-1 updates, flush every {d['delay']} moves, "
                 f"{'fused greedy loop (gfo_greedy_steps)' if d['fused'] else 'per-call'}")
         head_value = d["steps_per_s"]
         head_ms = d["ms_per_step"]
-        flops = 8.0 * N * ld * d["delay"]            # complex rank-r update, 8 real flops per MAC
-        peak = MFMA_PEAK_TFLOPS[problem.dtype]
-        tri = flush_triangle(d["flush_variant"])
-        # issued matrix work: three real products per complex one (_3m variants),
-        # on the tiles on and above the diagonal only (the design block is symmetric)
-        issued = flops * (0.75 if "3m" in str(d["flush_variant"]) else 1.0) * (0.5 if tri else 1.0)
-        if flush_covers_monitors(d["flush_variant"]):
-            issued += 8.0 * problem.n_mon * ld * d["delay"] * 0.75     # the monitor rows' tiles
-        alg_bytes = flush_alg_bytes(d["flush_variant"], problem.dtype, N, ld, problem.n_mon)
-        t_mfma, t_hbm = issued / (peak * 1e12), alg_bytes / (HBM_PEAK_GBS * 1e9)
-        secs = d["flush_us"] * 1e-6
-        common = {"kernel": f"flush of the deferred updates, FP32 MFMA, variant {d['flush_variant']}",
-                  "traffic": pmc_traffic("k_flush_c64", problem.name, d["flush_variant"]),
-                  "traffic_unit": "bytes/launch", "avg_launch_us": d["flush_us"],
-                  "flops_per_launch": flops, "issued_flops_per_launch": issued,
-                  "algorithmic_bytes_per_launch": alg_bytes, "variant": d["flush_variant"],
-                  "complex_update_tflops": flops / secs / 1e12}
-        if t_hbm >= t_mfma:
-            achieved = alg_bytes / secs / 1e9
-            roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, **common}
-        else:
-            # the matrix work the kernel issues per second against the dense peak
-            achieved = issued / secs / 1e12
-            roofline = {"bound": "mfma", "achieved": achieved, "peak": peak,
-                        "unit": "TFLOP/s", "frac": achieved / peak, **common}
+        kind = "FP32" if problem.dtype == "c64" else "FP64"
+        roofline = dict(d["flush_roofline"])
+        # the counters were taken on flushes of a full term buffer: they stand
+        # for this window only if its flushes ran the same term bucket
+        full = all(2 * r > d["delay"] for r in d["flush_terms"])
+        roofline.update(kernel=f"flush of the deferred updates, {kind} MFMA, variant "
+                               f"{d['flush_variant']}",
+                        traffic=pmc_traffic("k_flush_c64", problem.name, d["flush_variant"])
+                        if full else None,
+                        traffic_unit="bytes/launch")
         pix = d["last_run_pixels"]
     else:
         mode = "eager rank-1 updates"
