@@ -32,7 +32,8 @@
  *   - Return value: GFO_OK (0) or a negative error detected on the host:
  *     GFO_EINVAL (bad sizes or null pointers), GFO_EHIP (a HIP call failed),
  *     GFO_ENOSPC (workspace too small), GFO_ERANGE (refresh_G: more flipped
- *     pixels than kmax).  Conditions met on the device are OR-ed
+ *     pixels than kmax), GFO_ESCRATCH (score_candidates_static: problem
+ *     larger than the static scratch).  Conditions met on the device are OR-ed
  *     into *state->status (GFO_STATUS_*), to be read by the caller when it
  *     synchronises.  The library never aborts the process.
  */
@@ -49,7 +50,8 @@ extern "C" {
 
 enum { GFO_C64 = 0, GFO_C128 = 1 };            /* storage type of G and E */
 enum { GFO_FP32 = 0, GFO_BF16 = 1 };           /* MFMA input type of the rank-k update */
-enum { GFO_OK = 0, GFO_EINVAL = -1, GFO_EHIP = -2, GFO_ENOSPC = -3, GFO_ERANGE = -4 };
+enum { GFO_OK = 0, GFO_EINVAL = -1, GFO_EHIP = -2, GFO_ENOSPC = -3, GFO_ERANGE = -4,
+       GFO_ESCRATCH = -5 };
 enum {                                         /* bits of the device status word */
   GFO_STATUS_SINGULAR = 1,      /* |1 - alpha G_jj| < 1e-12: move refused */
   GFO_STATUS_NONFINITE = 2,     /* a candidate score was NaN or infinite */
@@ -59,6 +61,7 @@ enum {                                         /* bits of the device status word
 #define GFO_MAX_EPS 8                          /* permittivity table entries */
 #define GFO_MAX_RANK_K 32                      /* largest k of apply_flips_rank_k */
 #define GFO_MAX_DELAY 128                      /* largest number of deferred rank-1 moves */
+#define GFO_STATIC_SCRATCH_BYTES (8u << 20)    /* device scratch of score_candidates_static */
 
 /* Problem description, read during a call, not retained. */
 typedef struct {
@@ -158,6 +161,24 @@ int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 int score_candidates(const gfo_problem* prob, const gfo_state* st, uint32_t cand_mask,
                      double tau, int32_t topk, int32_t min_spacing, gfo_pick* d_out,
                      hipStream_t stream);
+
+/* score_candidates_static - score_candidates for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same scores and the same records in d_out, bit
+ * for bit, but st->work is not used (it may be NULL, as may work_bytes be 0).
+ * Its scratch (N x n_eps FP64 scores and the score workgroups' summaries, at
+ * most GFO_STATIC_SCRATCH_BYTES = 8 MiB: N * n_eps <= 1,047,040) lives in a
+ * device array of the library, one per GPU, held until the process ends; its
+ * address is taken on the first call on each device.  Allocates nothing, and
+ * calls no allocating routine.  Every call on one GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (other streams, other threads) race
+ * and must be ordered by the caller.  Returns GFO_ESCRATCH, before any launch,
+ * for a problem whose scratch would not fit; GFO_EINVAL as score_candidates;
+ * GFO_EHIP if the scratch address cannot be taken or a launch fails.
+ * Asynchronous on `stream`. */
+int score_candidates_static(const gfo_problem* prob, const gfo_state* st, uint32_t cand_mask,
+                            double tau, int32_t topk, int32_t min_spacing, gfo_pick* d_out,
+                            hipStream_t stream);
 
 /* apply_flip - apply one move as a rank-1 Dyson update (paper Sec. II B,
  * eqs. form10-form14 with a one-pixel region; field by eqs. form4-form9).

@@ -14,12 +14,13 @@ LIB_PATH = os.path.join(_HERE, "libgfo.so")
 
 GFO_C64, GFO_C128 = 0, 1
 GFO_FP32, GFO_BF16 = 0, 1
-GFO_OK, GFO_EINVAL, GFO_EHIP, GFO_ENOSPC, GFO_ERANGE = 0, -1, -2, -3, -4
+GFO_OK, GFO_EINVAL, GFO_EHIP, GFO_ENOSPC, GFO_ERANGE, GFO_ESCRATCH = 0, -1, -2, -3, -4, -5
 GFO_STATUS_SINGULAR, GFO_STATUS_NONFINITE = 1, 2
 GFO_STATUS_HISTORY_FULL, GFO_STATUS_REFRESH_OVERFLOW = 4, 8
 GFO_MAX_EPS = 8
 GFO_MAX_RANK_K = 32
 GFO_MAX_DELAY = 128
+GFO_STATIC_SCRATCH_BYTES = 8 << 20
 
 # every entry point that include/gfo.h declares
 EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "gfo_scores_offset",
@@ -29,7 +30,7 @@ EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "g
            "gfo_flush_variant_name", "gfo_flush_set_variant", "gfo_flush_get_variant",
            "gfo_loop_set_form", "gfo_loop_get_form",
            "gfo_greedy_steps", "gfo_choose_eps_greedy", "score_regions", "gfo_region_pixels",
-           "gfo_sync_lower")
+           "gfo_sync_lower", "score_candidates_static")
 
 
 class Problem(C.Structure):
@@ -83,6 +84,7 @@ def lib():
     L.gfo_scores_offset.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
     L.init_G0.argtypes = [P, S, V]
     L.score_candidates.argtypes = [P, S, C.c_uint32, C.c_double, C.c_int32, C.c_int32, V, V]
+    L.score_candidates_static.argtypes = [P, S, C.c_uint32, C.c_double, C.c_int32, C.c_int32, V, V]
     L.apply_flip.argtypes = [P, S, V, V]
     L.apply_flips_rank_k.argtypes = [P, S, V, C.c_int32, C.c_int32, V]
     L.refresh_G.argtypes = [P, S, V]
@@ -141,6 +143,11 @@ def init_G0(prob: Problem, st: State, stream: int) -> None:
 def score_candidates(prob, st, cand_mask, tau, topk, min_spacing, d_out, stream) -> None:
     check(lib().score_candidates(C.byref(prob), C.byref(st), cand_mask, tau, topk, min_spacing,
                                  d_out, stream), "score_candidates")
+
+
+def score_candidates_static(prob, st, cand_mask, tau, topk, min_spacing, d_out, stream) -> None:
+    check(lib().score_candidates_static(C.byref(prob), C.byref(st), cand_mask, tau, topk,
+                                        min_spacing, d_out, stream), "score_candidates_static")
 
 
 def apply_flip(prob, st, d_pick, stream) -> None:

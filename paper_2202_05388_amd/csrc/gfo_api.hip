@@ -111,15 +111,22 @@ static int64_t min_ld(const gfo_problem* p) {
   return (N + 63) / 64 * 64;
 }
 
-static int validate_state(const gfo_problem* p, const gfo_state* st, Layout* L) {
-  if (!st || !st->G || !st->E || !st->diag64 || !st->eps_idx || !st->n_flips || !st->status ||
-      !st->work)
+// Every field of a job's state except the workspace.
+int validate_state_fields(const gfo_problem* p, const gfo_state* st) {
+  if (!st || !st->G || !st->E || !st->diag64 || !st->eps_idx || !st->n_flips || !st->status)
     return GFO_EINVAL;
   if (st->flip_cap < 0 || (st->flip_cap > 0 && !st->flips) || st->kmax < 0) return GFO_EINVAL;
   if (st->delay < 0 || st->delay > GFO_MAX_DELAY || st->pending_calls < 0) return GFO_EINVAL;
   if (st->lower_stale != 0 && st->lower_stale != 1) return GFO_EINVAL;
   if (st->ldG < min_ld(p) || st->ldG % 64 != 0) return GFO_EINVAL;
-  if (((uintptr_t)st->work & 255) != 0 || ((uintptr_t)st->G & 15) != 0) return GFO_EINVAL;
+  if (((uintptr_t)st->G & 15) != 0) return GFO_EINVAL;
+  return GFO_OK;
+}
+
+static int validate_state(const gfo_problem* p, const gfo_state* st, Layout* L) {
+  int rc = validate_state_fields(p, st);
+  if (rc) return rc;
+  if (!st->work || ((uintptr_t)st->work & 255) != 0) return GFO_EINVAL;
   *L = make_layout(p, st->ldG, st->kmax);
   if (st->work_bytes < L->total) return GFO_ENOSPC;
   return GFO_OK;
@@ -140,6 +147,7 @@ const char* gfo_strerror(int code) {
     case GFO_EHIP: return "a HIP runtime call or kernel launch failed";
     case GFO_ENOSPC: return "workspace too small";
     case GFO_ERANGE: return "more flipped pixels than the refresh workspace holds (kmax)";
+    case GFO_ESCRATCH: return "problem too large for the library's static scratch";
     default: return "unknown error";
   }
 }

@@ -376,6 +376,21 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 hipError_t launch_init(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
 hipError_t launch_score(const Geo& g, const gfo_state* st, const Layout& L, uint32_t mask,
                         double tau, int topk, int spacing, gfo_pick* out, hipStream_t s);
+// Scratch of score_candidates: N x n_eps scores, then per score workgroup its
+// best score and the lowest index within the tie band of that best.
+struct ScoreBufs {
+  double* scores;
+  double* partial;
+  int* pfirst;
+};
+// workgroups of the score kernel (one pixel per thread, at most kScoreMaxBlocks)
+inline int score_blocks(const Geo& g) {
+  const int n = (g.N + kScoreThreads - 1) / kScoreThreads;
+  return n < kScoreMaxBlocks ? n : kScoreMaxBlocks;
+}
+hipError_t launch_score_into(const Geo& g, const gfo_state* st, const ScoreBufs& b, uint32_t mask,
+                             double tau, int topk, int spacing, gfo_pick* out, hipStream_t s);
+int validate_state_fields(const gfo_problem* p, const gfo_state* st);
 hipError_t launch_apply(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* pick,
                         hipStream_t s);
 hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* picks,

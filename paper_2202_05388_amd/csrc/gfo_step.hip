@@ -238,28 +238,31 @@ __global__ void k_gather(Geo g, const Snap* __restrict__ snap, const T* __restri
 
 // ------------------------------------------------------------------ launchers
 template <typename T>
-static hipError_t score_typed(const Geo& g, const gfo_state* st, const Layout& L, uint32_t mask,
+static hipError_t score_typed(const Geo& g, const gfo_state* st, const ScoreBufs& b, uint32_t mask,
                               double tau, int topk, int spacing, gfo_pick* out, hipStream_t s) {
-  char* w = (char*)st->work;
-  int nblk = (g.N + kScoreThreads - 1) / kScoreThreads;
-  if (nblk > kScoreMaxBlocks) nblk = kScoreMaxBlocks;
+  const int nblk = score_blocks(g);
   hipLaunchKernelGGL(k_score<T>, dim3(nblk), dim3(kScoreThreads), 0, s, g, (const T*)st->G,
                      (const T*)st->E, (const double2*)st->diag64, (const uint8_t*)st->eps_idx, mask,
-                     tau, (double*)(w + L.scores), (double*)(w + L.partial), (int*)(w + L.pfirst),
-                     st->status);
+                     tau, b.scores, b.partial, b.pfirst, st->status);
   // the greedy pick reads the workgroup summaries (one wave); the spaced top-k
   // rescans every score after each pick
   const int sel_threads = topk == 1 ? 64 : kSelectThreads;
-  hipLaunchKernelGGL(k_select<T>, dim3(1), dim3(sel_threads), 0, s, g, (const T*)st->E,
-                     (double*)(w + L.scores), (const double*)(w + L.partial),
-                     (const int*)(w + L.pfirst), nblk, tau, topk, spacing, out);
+  hipLaunchKernelGGL(k_select<T>, dim3(1), dim3(sel_threads), 0, s, g, (const T*)st->E, b.scores,
+                     (const double*)b.partial, (const int*)b.pfirst, nblk, tau, topk, spacing, out);
   return hipGetLastError();
+}
+
+hipError_t launch_score_into(const Geo& g, const gfo_state* st, const ScoreBufs& b, uint32_t mask,
+                             double tau, int topk, int spacing, gfo_pick* out, hipStream_t s) {
+  if (g.dtype == GFO_C64) return score_typed<float2>(g, st, b, mask, tau, topk, spacing, out, s);
+  return score_typed<double2>(g, st, b, mask, tau, topk, spacing, out, s);
 }
 
 hipError_t launch_score(const Geo& g, const gfo_state* st, const Layout& L, uint32_t mask,
                         double tau, int topk, int spacing, gfo_pick* out, hipStream_t s) {
-  if (g.dtype == GFO_C64) return score_typed<float2>(g, st, L, mask, tau, topk, spacing, out, s);
-  return score_typed<double2>(g, st, L, mask, tau, topk, spacing, out, s);
+  char* w = (char*)st->work;
+  const ScoreBufs b{(double*)(w + L.scores), (double*)(w + L.partial), (int*)(w + L.pfirst)};
+  return launch_score_into(g, st, b, mask, tau, topk, spacing, out, s);
 }
 
 template <typename T>

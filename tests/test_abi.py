@@ -184,3 +184,36 @@ def test_loop_form_hook_validates_and_round_trips():
     finally:
         L.loop_set_form(old)
     assert L.loop_get_form() == 0
+
+
+def test_static_score_rejects_oversize_and_bad_arguments_on_host():
+    """score_candidates_static refuses a problem whose scores would not fit its
+    8 MiB device scratch (GFO_ESCRATCH) and invalid arguments (GFO_EINVAL),
+    before any HIP call; it needs no workspace (work may be NULL)."""
+    lib = L.lib()
+    fake = 1 << 20                                 # aligned, never dereferenced
+    out = C.c_void_p(fake)
+
+    def state(pr):
+        return L.State(G=fake, ldG=L.min_ld(pr), E=fake, diag64=fake, eps_idx=fake, flips=fake,
+                       flip_cap=16, n_flips=fake, kmax=0, work=None, work_bytes=0, status=fake)
+
+    # 1024 x 1024 pixels with two materials: 16 MiB of scores
+    big, keep = _problem(W.tiny(1024, 1024, n_mon=4))
+    st = state(big)
+    assert lib.score_candidates_static(C.byref(big), C.byref(st), 3, 1e-9, 1, 0, out,
+                                       None) == L.GFO_ESCRATCH
+    assert lib.gfo_strerror(L.GFO_ESCRATCH) == b"problem too large for the library's static scratch"
+    # the largest grid that fits: N * n_eps * 8 bytes + 12 KiB of summaries <= 8 MiB
+    assert (L.GFO_STATIC_SCRATCH_BYTES - 12288) // 16 == 523_520
+    small, keep2 = _problem(W.tiny(8, 8, n_mon=4))
+    st = state(small)
+    for mask, tau, topk, spacing in ((0, 1e-9, 1, 0), (3, -1.0, 1, 0), (3, 1e-9, 0, 0),
+                                     (3, 1e-9, 33, 0), (3, 1e-9, 4, -1)):
+        assert lib.score_candidates_static(C.byref(small), C.byref(st), mask, tau, topk, spacing,
+                                           out, None) == L.GFO_EINVAL
+    assert lib.score_candidates_static(C.byref(small), C.byref(st), 3, 1e-9, 1, 0, None,
+                                       None) == L.GFO_EINVAL
+    st.G = None
+    assert lib.score_candidates_static(C.byref(small), C.byref(st), 3, 1e-9, 1, 0, out,
+                                       None) == L.GFO_EINVAL
