@@ -515,10 +515,16 @@ def time_rank_k(problem, steps, warmup, precision):
     from paper_2202_05388_amd.hiprt import EventPool
     from paper_2202_05388_amd.job import Job
 
+    from paper_2202_05388_amd import autotune as at
+
     prec = L.GFO_FP32 if precision == "fp32" else L.GFO_BF16
     re = problem.refresh_every
     kmax = min(problem.n, problem.rank_k * max(steps, warmup))
     job = Job(problem, device="cuda:0", kmax=kmax)
+    job.init()
+    tuned = at.tune_rank_k(job, rank=problem.rank_k, precision=prec, save=False)
+    _log(f"[bench] rank-k update autotune ({precision}): "
+         + ", ".join(f"{r['name']} {r['us']:.0f} us" for r in tuned["all"]))
 
     def run(n, events):
         job.init()
@@ -574,7 +580,9 @@ def time_rank_k(problem, steps, warmup, precision):
                fom_last=job.fom(), fom_best=best[1], flips_at_best=best[0],
                fom_err_at_refresh_max=max(errs) if errs else None,
                fom_err_at_refresh_mean=sum(errs) / len(errs) if errs else None,
-               fom_vs_flips=_sample_curve(curve), status=job.status())
+               fom_vs_flips=_sample_curve(curve), update_variant=tuned["name"],
+               update_variants_us={r["name"]: round(r["us"], 1) for r in tuned["all"]},
+               status=job.status())
     del job
     torch.cuda.empty_cache()
     return out

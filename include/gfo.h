@@ -320,6 +320,15 @@ const char* gfo_k1_variant_name(int32_t dtype, int32_t idx);   /* NULL if out of
 int gfo_k1_set_variant(int32_t dtype, int32_t idx);           /* GFO_EINVAL if out of range */
 int gfo_k1_get_variant(int32_t dtype);
 
+/* Autotuner hooks for the matrix-core update of apply_flips_rank_k: tile and
+ * epilogue variants of the same rank-k product (the streaming variants agree
+ * with each other bit for bit; the accumulating one, "acc64", differs from
+ * them by FP32 rounding).  Selection is process-wide; host only. */
+int gfo_rk_variant_count(void);
+const char* gfo_rk_variant_name(int32_t idx);                 /* NULL if out of range */
+int gfo_rk_set_variant(int32_t idx);                          /* GFO_EINVAL if out of range */
+int gfo_rk_get_variant(void);
+
 /* Autotuner hooks for the complex64 deferred-mode flush: tile variants of the
  * same rank-r matrix-core product (bit-identical results are not guaranteed
  * across variants: the FP32 summation order differs).  Host only. */

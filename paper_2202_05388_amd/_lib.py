@@ -30,7 +30,8 @@ EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "g
            "gfo_flush_variant_name", "gfo_flush_set_variant", "gfo_flush_get_variant",
            "gfo_loop_set_form", "gfo_loop_get_form",
            "gfo_greedy_steps", "gfo_choose_eps_greedy", "score_regions", "gfo_region_pixels",
-           "gfo_sync_lower", "score_candidates_static")
+           "gfo_sync_lower", "score_candidates_static", "gfo_rk_variant_count",
+           "gfo_rk_variant_name", "gfo_rk_set_variant", "gfo_rk_get_variant")
 
 
 class Problem(C.Structure):
@@ -94,6 +95,9 @@ def lib():
     L.gfo_choose_eps_greedy.argtypes = [V, C.c_int32, C.c_double, C.c_double, C.c_double, V, V]
     L.score_regions.argtypes = [P, S, C.c_int32, C.c_uint32, C.c_double, V, V]
     L.gfo_region_pixels.argtypes = [P, S, C.c_int32, V, V, V]
+    L.gfo_rk_variant_name.argtypes = [C.c_int32]
+    L.gfo_rk_variant_name.restype = C.c_char_p
+    L.gfo_rk_set_variant.argtypes = [C.c_int32]
     L.gfo_flush_variant_name.argtypes = [C.c_int32]
     L.gfo_flush_variant_name.restype = C.c_char_p
     L.gfo_flush_set_variant.argtypes = [C.c_int32]
@@ -206,6 +210,19 @@ def k1_get_variant(dtype: int) -> int:
 
 def time_next_k1(before: int, after: int) -> None:
     check(lib().gfo_time_next_k1(before, after), "gfo_time_next_k1")
+
+
+def rk_variants():
+    L = lib()
+    return [L.gfo_rk_variant_name(i).decode() for i in range(L.gfo_rk_variant_count())]
+
+
+def rk_set_variant(idx: int) -> None:
+    check(lib().gfo_rk_set_variant(idx), "gfo_rk_set_variant")
+
+
+def rk_get_variant() -> int:
+    return lib().gfo_rk_get_variant()
 
 
 def flush_variants():

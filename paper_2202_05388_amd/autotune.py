@@ -146,6 +146,79 @@ def tune_flush(job, reps: int = 2) -> dict:
     return dict(variant=best["variant"], name=best["name"], us=best["us"], all=res)
 
 
+def time_rk_variants(job, rank: int = 16, precision: int = None, reps: int = 4,
+                     warm: int = 2) -> list:
+    """Mean time (us) of the matrix-core update of apply_flips_rank_k for each
+    variant on `job`'s shape (complex64, eager).  Each measurement applies
+    `rank` spaced pixels to material 1 and then back to their material, so the
+    structure is unchanged after every pair (G up to FP32 rounding)."""
+    import torch
+    from .hiprt import EventPool
+
+    if job.dtype_name != "c64" or job.delay:
+        raise L.GfoError("rank-k tuning needs a complex64 job in eager mode")
+    precision = L.GFO_FP32 if precision is None else precision
+    p = job.problem
+    N = job.N
+    cur = job.eps_idx.cpu().numpy()
+    step = max(1, N // rank)
+    pix = [min(N - 1, i * step + (i * 7) % max(step, 1)) for i in range(rank)]
+    there = [(j, 1 if int(cur[j]) == 0 else 0) for j in pix]
+    back = [(j, int(cur[j])) for j in pix]
+    base = job.picks.data_ptr()
+
+    def apply(moves):
+        for t, (j, e) in enumerate(moves):
+            job.set_pick(j, e, slot=t)
+        job.apply_rank_k(rank, precision=precision, pick_ptr=base)
+
+    names = L.rk_variants()
+    old = L.rk_get_variant()
+    out = []
+    try:
+        for vi in range(len(names)):
+            L.rk_set_variant(vi)
+            for i in range(warm):
+                apply(there if i % 2 == 0 else back)
+            if warm % 2:
+                apply(back)
+            ev = EventPool(2 * reps)
+            for i in range(2 * reps):
+                a, b = ev.next()
+                L.time_next_k1(a, b)
+                apply(there if i % 2 == 0 else back)
+            ms = ev.elapsed_ms()
+            ev.close()
+            out.append(dict(variant=vi, name=names[vi], us=1e3 * sum(ms) / len(ms),
+                            us_min=1e3 * min(ms)))
+    finally:
+        L.rk_set_variant(old)
+    torch.cuda.synchronize()
+    return out
+
+
+def tune_rank_k(job, rank: int = 16, precision: int = None, reps: int = 4,
+                save: bool = True) -> dict:
+    """Time the rank-k update variants on this job's shape, select and cache the
+    fastest (key: shape, rank padding, input precision)."""
+    t0 = time.time()
+    precision = L.GFO_FP32 if precision is None else precision
+    res = time_rk_variants(job, rank=rank, precision=precision, reps=reps)
+    bytes_per = 16 * job.N * job.R
+    for r in res:
+        r["gbs"] = bytes_per / (r["us"] * 1e-6) / 1e9
+    best = min(res, key=lambda r: r["us"])
+    L.rk_set_variant(best["variant"])
+    prec = "fp32" if precision == L.GFO_FP32 else "bf16"
+    entry = dict(variant=best["variant"], name=best["name"], us=best["us"], gbs=best["gbs"],
+                 seconds=time.time() - t0, all=res)
+    if save:
+        d = load_cache()
+        d[f"{_key(job.N, job.R, job.dtype_name)}/rk{16 if rank <= 16 else 32}/{prec}"] = entry
+        save_cache(d)
+    return entry
+
+
 def apply_cached(job) -> bool:
     """Select the cached variant for this job's shape, if any.  Returns True if found."""
     e = load_cache().get(_key(job.N, job.R, job.dtype_name))

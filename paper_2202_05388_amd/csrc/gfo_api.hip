@@ -432,6 +432,11 @@ const char* gfo_k1_variant_name(int32_t dtype, int32_t idx) { return k1_variant_
 int gfo_k1_set_variant(int32_t dtype, int32_t idx) { return k1_set_variant(dtype, idx); }
 int gfo_k1_get_variant(int32_t dtype) { return k1_get_variant(dtype); }
 
+int gfo_rk_variant_count(void) { return rk_variant_count(); }
+const char* gfo_rk_variant_name(int32_t idx) { return rk_variant_name(idx); }
+int gfo_rk_set_variant(int32_t idx) { return rk_set_variant(idx); }
+int gfo_rk_get_variant(void) { return rk_get_variant(); }
+
 int gfo_flush_variant_count(void) { return flush_variant_count(); }
 const char* gfo_flush_variant_name(int32_t idx) { return flush_variant_name(idx); }
 int gfo_flush_set_variant(int32_t idx) { return flush_set_variant(idx); }

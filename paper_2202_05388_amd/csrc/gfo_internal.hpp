@@ -442,6 +442,10 @@ void k1_take_timing(hipEvent_t* before, hipEvent_t* after);   // consumes the pe
 // the streaming rank-1 update of G with the selected tile variant (timed if requested)
 hipError_t launch_rank1(const Geo& g, const Snap* snap, const void* cu, const void* v, void* G,
                         hipStream_t s);
+int rk_variant_count();
+const char* rk_variant_name(int idx);
+int rk_set_variant(int idx);
+int rk_get_variant();
 int flush_variant_count();
 const char* flush_variant_name(int idx);
 int flush_set_variant(int idx);

@@ -186,3 +186,47 @@ def test_rank16_square128_follows_oracle_policy():
         assert np.array_equal(job.eps_idx.cpu().numpy(), idx)
     print(f"rank-16 at 128x128: sets equal to the oracle's for {same} of {steps} steps", flush=True)
     assert job.status() == 0
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("s", [16, 24])
+def test_rank_k_update_variants(precision, s):
+    """Every matrix-core update variant gives the dense re-solve's G; the
+    streaming variants (products summed from zero, G added once) agree bit for
+    bit.  30 x 70 pixels: ld = 2112 leaves a 64-column remainder of the
+    128-column workgroup tiles, and R = 2108 rows a ragged last row block."""
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(30, 70, n_mon=8, dtype="c64")
+    N = p.n
+    idx = W.random_eps_idx(p, 0.15, 6)
+    G, E = ost.dense_state(p, ost.eps_of(p, idx))
+    pix = np.random.default_rng(s).choice(N, s, replace=False)
+    idx2 = idx.copy()
+    idx2[pix] = 1 - idx2[pix]
+    Gd, Ed = ost.dense_state(p, ost.eps_of(p, idx2))
+    prec = L.GFO_FP32 if precision == "fp32" else L.GFO_BF16
+    names = L.rk_variants()
+    old = L.rk_get_variant()
+    out = {}
+    try:
+        for vi, name in enumerate(names):
+            L.rk_set_variant(vi)
+            job = _job(p)
+            job.upload_state(G, E, np.diagonal(G[:N]), idx)
+            for t, j in enumerate(pix):
+                job.set_pick(int(j), int(idx2[j]), slot=t)
+            job.apply_rank_k(s, precision=prec)
+            G1, E1, d1, i1 = job.host_state()
+            assert np.array_equal(i1, idx2) and job.status() == 0
+            if precision == "fp32":
+                assert _rel(G1, Gd) <= c64_drift_tol(s), name
+            else:
+                assert _rel(G1 - G, Gd - G, floor=1.0) <= 1e-2, name
+            assert _rel(E1, Ed) <= 5e-6, name
+            out[name] = G1
+    finally:
+        L.rk_set_variant(old)
+    streaming = [n for n in names if n != "acc64"]
+    assert len(streaming) >= 2
+    for n in streaming[1:]:
+        assert np.array_equal(out[n], out[streaming[0]]), n
