@@ -867,8 +867,9 @@ def main():
         from paper_2202_05388_amd.serve import serve_benchmark
         _log(f"[bench] serving {args.serve_jobs} jobs at {args.serve_rate}/s (mix, then one at a time)")
         serving = serve_benchmark(n_jobs=args.serve_jobs, rate=args.serve_rate, delay=args.delay)
-        _log(f"[bench] serving mix {serving['mix']}")
-        _log(f"[bench] serving one-at-a-time {serving['one_at_a_time']}")
+        for k in ("mix", "mix_grouped", "one_at_a_time", "burst_mix", "burst_mix_grouped",
+                  "burst_one_at_a_time"):
+            _log(f"[bench] serving {k} {serving[k]}")
 
     N, R, ld = problem.n, problem.rows, (problem.n + 63) // 64 * 64
     eager_roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

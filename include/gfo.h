@@ -247,6 +247,40 @@ int gfo_sync_lower(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 int gfo_greedy_steps(const gfo_problem* prob, gfo_state* st, int32_t n_steps,
                      uint32_t cand_mask, double tau, gfo_pick* d_picks, hipStream_t stream);
 
+/* Grouped greedy steps of many resident jobs (the served form: continuous
+ * batching of small jobs, whose moves are latency bound).  A job table holds,
+ * per job, its geometry, buffers and workspace offsets in caller-owned device
+ * memory; gfo_greedy_steps_table then runs n_steps greedy moves of every job
+ * of the table with one launch per move for all of them (plus each job's own
+ * flush when its term buffer is full), with the results of one
+ * gfo_greedy_steps(n_steps, d_picks = NULL) call per job, bit for bit.  Jobs
+ * share no memory; a job that stops (no improving move) makes no-op moves.
+ * Requirements: 1 <= n_jobs <= 64, every job in deferred mode (delay > 0),
+ * served by the one-kernel loop (at most 65,536 pixels), and alike in storage
+ * type, term batch (delay <= 64 or not) and summary size (at most 16,384
+ * pixels or not); else GFO_EINVAL. */
+
+/* Bytes of device memory a table of n_jobs jobs needs (0 if n_jobs is out of
+ * range).  Host only. */
+size_t gfo_job_table_bytes(int32_t n_jobs);
+
+/* Write the table of the jobs (probs[i], states[i]) with their candidate masks
+ * and tie bands (host arrays) into d_table (256-byte aligned, at least
+ * gfo_job_table_bytes(n_jobs) bytes, else GFO_ENOSPC).  The table holds the
+ * jobs' device pointers: it stays valid while their buffers do, and must be
+ * rebuilt when the set of jobs changes.  Exception to asynchrony: synchronises
+ * `stream` once (the table is copied from host memory). */
+int gfo_job_table_build(const gfo_problem* probs, const gfo_state* states, int32_t n_jobs,
+                        const uint32_t* h_cand_masks, const double* h_taus, void* d_table,
+                        size_t table_bytes, hipStream_t stream);
+
+/* n_steps greedy moves of every job of a table built from these same probs and
+ * states, in the same order (the host-side pending counts in states[] are kept
+ * up to date as by gfo_greedy_steps).  Each job's picks go to its workspace.
+ * Asynchronous on `stream`. */
+int gfo_greedy_steps_table(const gfo_problem* probs, gfo_state* states, int32_t n_jobs,
+                           int32_t n_steps, const void* d_table, hipStream_t stream);
+
 /* score_regions - greedy pick among multi-pixel region moves (paper Sec. II
  * with a flipped region V of N_V = 4 pixels; Sec. IV flips 2x2-pixel pillars).
  * Square regions of side `region` (= 2) tile the design grid (ny, nx even);

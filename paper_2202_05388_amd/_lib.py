@@ -31,7 +31,8 @@ EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "g
            "gfo_loop_set_form", "gfo_loop_get_form",
            "gfo_greedy_steps", "gfo_choose_eps_greedy", "score_regions", "gfo_region_pixels",
            "gfo_sync_lower", "score_candidates_static", "gfo_rk_variant_count",
-           "gfo_rk_variant_name", "gfo_rk_set_variant", "gfo_rk_get_variant")
+           "gfo_rk_variant_name", "gfo_rk_set_variant", "gfo_rk_get_variant",
+           "gfo_job_table_bytes", "gfo_job_table_build", "gfo_greedy_steps_table")
 
 
 class Problem(C.Structure):
@@ -95,6 +96,11 @@ def lib():
     L.gfo_choose_eps_greedy.argtypes = [V, C.c_int32, C.c_double, C.c_double, C.c_double, V, V]
     L.score_regions.argtypes = [P, S, C.c_int32, C.c_uint32, C.c_double, V, V]
     L.gfo_region_pixels.argtypes = [P, S, C.c_int32, V, V, V]
+    L.gfo_job_table_bytes.argtypes = [C.c_int32]
+    L.gfo_job_table_bytes.restype = C.c_size_t
+    L.gfo_job_table_build.argtypes = [P, S, C.c_int32, C.POINTER(C.c_uint32),
+                                      C.POINTER(C.c_double), V, C.c_size_t, V]
+    L.gfo_greedy_steps_table.argtypes = [P, S, C.c_int32, C.c_int32, V, V]
     L.gfo_rk_variant_name.argtypes = [C.c_int32]
     L.gfo_rk_variant_name.restype = C.c_char_p
     L.gfo_rk_set_variant.argtypes = [C.c_int32]
@@ -210,6 +216,24 @@ def k1_get_variant(dtype: int) -> int:
 
 def time_next_k1(before: int, after: int) -> None:
     check(lib().gfo_time_next_k1(before, after), "gfo_time_next_k1")
+
+
+def job_table_bytes(n_jobs: int) -> int:
+    return lib().gfo_job_table_bytes(n_jobs)
+
+
+def job_table_build(probs, states, masks, taus, d_table, table_bytes, stream) -> None:
+    """probs, states: ctypes arrays (Problem * n, State * n); masks, taus: sequences."""
+    n = len(probs)
+    m = (C.c_uint32 * n)(*[int(x) for x in masks])
+    t = (C.c_double * n)(*[float(x) for x in taus])
+    check(lib().gfo_job_table_build(probs, states, n, m, t, d_table, table_bytes, stream),
+          "gfo_job_table_build")
+
+
+def greedy_steps_table(probs, states, n_steps, d_table, stream) -> None:
+    check(lib().gfo_greedy_steps_table(probs, states, len(probs), n_steps, d_table, stream),
+          "gfo_greedy_steps_table")
 
 
 def rk_variants():

@@ -132,6 +132,13 @@ static int validate_state(const gfo_problem* p, const gfo_state* st, Layout* L) 
   return GFO_OK;
 }
 
+// validate_state for other sources of the library
+int validate_job(const gfo_problem* p, const gfo_state* st, Layout* L) {
+  int rc = validate_problem(p);
+  if (rc) return rc;
+  return validate_state(p, st, L);
+}
+
 }  // namespace gfo
 
 using namespace gfo;

@@ -332,8 +332,8 @@ __global__ void k_mon_dl(Geo g, const Snap* __restrict__ snap, const T* __restri
 // The expressions are those of k_mon_dl and k_score, so the state and the scores
 // are bit for bit those of the per-call path.
 template <typename T>
-__global__ __launch_bounds__(kScoreThreads) void k_mon_score(
-    Geo g, int apply_prev, const Snap* __restrict__ snap, const T* __restrict__ cu,
+__device__ __forceinline__ void mon_score_body(
+    const Geo& g, int apply_prev, const Snap* __restrict__ snap, const T* __restrict__ cu,
     const T* __restrict__ v, const T* __restrict__ emon, T* __restrict__ G, T* __restrict__ E,
     double2* __restrict__ diag64, uint8_t* __restrict__ eps_idx, int32_t* __restrict__ flips,
     int flip_cap, int32_t* __restrict__ n_flips, int32_t* __restrict__ status,
@@ -393,6 +393,18 @@ __global__ __launch_bounds__(kScoreThreads) void k_mon_score(
   if (moved && q == 0) record_move(sn, flips, flip_cap, n_flips, status, count);
 }
 
+template <typename T>
+__global__ __launch_bounds__(kScoreThreads) void k_mon_score(
+    Geo g, int apply_prev, const Snap* __restrict__ snap, const T* __restrict__ cu,
+    const T* __restrict__ v, const T* __restrict__ emon, T* __restrict__ G, T* __restrict__ E,
+    double2* __restrict__ diag64, uint8_t* __restrict__ eps_idx, int32_t* __restrict__ flips,
+    int flip_cap, int32_t* __restrict__ n_flips, int32_t* __restrict__ status,
+    int32_t* __restrict__ count, uint32_t mask, double tau, double* __restrict__ scores,
+    double* __restrict__ partial, int* __restrict__ pfirst, int nblk) {
+  mon_score_body<T>(g, apply_prev, snap, cu, v, emon, G, E, diag64, eps_idx, flips, flip_cap,
+                    n_flips, status, count, mask, tau, scores, partial, pfirst, nblk);
+}
+
 __global__ void k_dl_reset(int32_t* count) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *count = 0;
 }
@@ -420,8 +432,8 @@ hipError_t launch_dl_reset(const Geo&, gfo_state* st, const Layout& L, hipStream
 // snapshots, scores and summaries alternate between two sets of buffers.  The expressions are those of the per-call path (k_gather_dl,
 // k_mon_dl, k_score), so the state and the picks are bit for bit the same.
 template <typename T, int PPL, int B>
-__global__ __launch_bounds__(256) void k_move(
-    Geo g, int has_prev, int flushed, const Snap* __restrict__ snap_prev,
+__device__ __forceinline__ void move_body(
+    const Geo& g, int has_prev, int flushed, const Snap* __restrict__ snap_prev,
     Snap* __restrict__ snap_out, const double* __restrict__ scores_prev,
     const double* __restrict__ partial_prev, const int* __restrict__ pfirst_prev, int nblk_prev,
     int bpix_prev, double* __restrict__ scores_next, double* __restrict__ partial_next,
@@ -600,13 +612,32 @@ __global__ __launch_bounds__(256) void k_move(
   }
 }
 
+template <typename T, int PPL, int B>
+__global__ __launch_bounds__(256) void k_move(
+    Geo g, int has_prev, int flushed, const Snap* __restrict__ snap_prev,
+    Snap* __restrict__ snap_out, const double* __restrict__ scores_prev,
+    const double* __restrict__ partial_prev, const int* __restrict__ pfirst_prev, int nblk_prev,
+    int bpix_prev, double* __restrict__ scores_next, double* __restrict__ partial_next,
+    int* __restrict__ pfirst_next, const T* __restrict__ emon_prev, T* __restrict__ emon_next,
+    uint32_t mask, double tau, gfo_pick* __restrict__ pick_out, T* __restrict__ G,
+    T* __restrict__ E, double2* __restrict__ diag64, uint8_t* __restrict__ eps_idx,
+    const int32_t* __restrict__ count, int32_t* __restrict__ flips, int flip_cap,
+    int32_t* __restrict__ n_flips, int32_t* __restrict__ status, T* __restrict__ CUs,
+    T* __restrict__ Vs) {
+  move_body<T, PPL, B>(g, has_prev, flushed, snap_prev, snap_out, scores_prev, partial_prev,
+                       pfirst_prev, nblk_prev, bpix_prev, scores_next, partial_next, pfirst_next,
+                       emon_prev, emon_next, mask, tau, pick_out, G, E, diag64, eps_idx, count,
+                       flips, flip_cap, n_flips, status, CUs, Vs);
+}
+
 // After move t of a one-kernel loop (its last, or before a flush): the move's
 // pivot values, the fields at the monitors and the term count reach memory.
 template <typename T>
-__global__ void k_move_finish(Geo g, const Snap* __restrict__ snap_last,
-                              const T* __restrict__ emon_last, T* __restrict__ G,
-                              T* __restrict__ E, double2* __restrict__ diag64,
-                              uint8_t* __restrict__ eps_idx, int32_t* __restrict__ count) {
+__device__ __forceinline__ void move_finish_body(const Geo& g, const Snap* __restrict__ snap_last,
+                                                 const T* __restrict__ emon_last, T* __restrict__ G,
+                                                 T* __restrict__ E, double2* __restrict__ diag64,
+                                                 uint8_t* __restrict__ eps_idx,
+                                                 int32_t* __restrict__ count) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < g.nmon) E[g.N + t] = emon_last[t];
   if (t == 0) {
@@ -619,6 +650,14 @@ __global__ void k_move_finish(Geo g, const Snap* __restrict__ snap_last,
       G[(int64_t)(g.N + g.m0) * g.ld + sn.j] = St<T>::from_d(sn.gm0_new);
     }
   }
+}
+
+template <typename T>
+__global__ void k_move_finish(Geo g, const Snap* __restrict__ snap_last,
+                              const T* __restrict__ emon_last, T* __restrict__ G,
+                              T* __restrict__ E, double2* __restrict__ diag64,
+                              uint8_t* __restrict__ eps_idx, int32_t* __restrict__ count) {
+  move_finish_body<T>(g, snap_last, emon_last, G, E, diag64, eps_idx, count);
 }
 
 template <typename T>
@@ -752,6 +791,142 @@ hipError_t launch_move_scores(const Geo& g, gfo_state* st, const Layout& L, uint
                      (double*)(w + L.scores), (double*)(w + L.partial), (int*)(w + L.pfirst), nblk);
   return hipGetLastError();
 }
+
+// ------------------------------------------------------------------ grouped launches
+// The one-kernel loop of many jobs at once: workgroup (x, y) runs workgroup x
+// of job y's own kernel with job y's arguments from the table (the same bodies,
+// so every job's moves and state are bit for bit those of its own calls);
+// workgroups past a job's count return at once.
+int gather_move_workgroups(const Geo& g) {
+  const int64_t n = (int64_t)gather_mpad(g) + g.ld;
+  return (int)((n + kGatherElems - 1) / kGatherElems);
+}
+
+bool move_small_grid(const Geo& g) { return (g.N + kGatherElems - 1) / kGatherElems <= 4 * 64; }
+
+JobEntry make_job_entry(const Geo& g, const gfo_state* st, const Layout& L, uint32_t mask,
+                        double tau) {
+  JobEntry je = {};
+  je.g = g;
+  je.G = st->G;
+  je.E = st->E;
+  je.diag64 = (double2*)st->diag64;
+  je.eps_idx = st->eps_idx;
+  je.flips = st->flips;
+  je.n_flips = st->n_flips;
+  je.status = st->status;
+  je.work = (char*)st->work;
+  je.snap = L.snap;
+  je.snap2 = L.snap2;
+  je.emon = L.emon;
+  je.emon2 = L.emon2;
+  je.scores = L.scores;
+  je.scores2 = L.scores2;
+  je.partial = L.partial;
+  je.partial2 = L.partial2;
+  je.pfirst = L.pfirst;
+  je.pfirst2 = L.pfirst2;
+  je.cu = L.cu;
+  je.v = L.v;
+  je.dl_hdr = L.dl_hdr;
+  je.dl_CUs = L.dl_CUs;
+  je.dl_Vs = L.dl_Vs;
+  je.picks = L.picks;
+  je.tau = tau;
+  je.mask = mask;
+  je.flip_cap = st->flip_cap;
+  const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
+  je.n_score_wg = (int)((nx + kScoreThreads - 1) / kScoreThreads);
+  je.n_move_wg = gather_move_workgroups(g);
+  je.n_finish_wg = (g.nmon + 255) / 256;
+  je.nblk0 = (g.N + kScoreThreads - 1) / kScoreThreads;
+  je.nblkg = (g.N + kGatherElems - 1) / kGatherElems;
+  return je;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScoreThreads) void k_mon_score_table(const JobEntry* __restrict__ tab) {
+  const JobEntry* je = tab + blockIdx.y;
+  if ((int)blockIdx.x >= je->n_score_wg) return;
+  const Geo g = je->g;
+  char* w = je->work;
+  mon_score_body<T>(g, 0, (const Snap*)(w + je->snap), (const T*)(w + je->cu),
+                    (const T*)(w + je->v), (const T*)(w + je->emon), (T*)je->G, (T*)je->E,
+                    je->diag64, je->eps_idx, je->flips, je->flip_cap, je->n_flips, je->status,
+                    (int32_t*)(w + je->dl_hdr), je->mask, je->tau, (double*)(w + je->scores),
+                    (double*)(w + je->partial), (int*)(w + je->pfirst), je->nblk0);
+}
+
+template <typename T, int PPL, int B>
+__global__ __launch_bounds__(256) void k_move_table(const JobEntry* __restrict__ tab, int t,
+                                                    uint64_t flushed_mask) {
+  const JobEntry* je = tab + blockIdx.y;
+  if ((int)blockIdx.x >= je->n_move_wg) return;
+  const Geo g = je->g;
+  char* w = je->work;
+  const int a = t & 1;
+  const int64_t snap_a = a ? je->snap2 : je->snap, snap_b = a ? je->snap : je->snap2;
+  const int64_t emon_a = a ? je->emon2 : je->emon, emon_b = a ? je->emon : je->emon2;
+  const int64_t sc_a = a ? je->scores2 : je->scores, sc_b = a ? je->scores : je->scores2;
+  const int64_t pa_a = a ? je->partial2 : je->partial, pa_b = a ? je->partial : je->partial2;
+  const int64_t pf_a = a ? je->pfirst2 : je->pfirst, pf_b = a ? je->pfirst : je->pfirst2;
+  move_body<T, PPL, B>(g, t > 0 ? 1 : 0, (int)((flushed_mask >> blockIdx.y) & 1u),
+                       (const Snap*)(w + snap_b), (Snap*)(w + snap_a), (const double*)(w + sc_a),
+                       (const double*)(w + pa_a), (const int*)(w + pf_a),
+                       t == 0 ? je->nblk0 : je->nblkg, t == 0 ? kScoreThreads : kGatherElems,
+                       (double*)(w + sc_b), (double*)(w + pa_b), (int*)(w + pf_b),
+                       (const T*)(w + emon_b), (T*)(w + emon_a), je->mask, je->tau,
+                       (gfo_pick*)(w + je->picks), (T*)je->G, (T*)je->E, je->diag64, je->eps_idx,
+                       (const int32_t*)(w + je->dl_hdr), je->flips, je->flip_cap, je->n_flips,
+                       je->status, (T*)(w + je->dl_CUs), (T*)(w + je->dl_Vs));
+}
+
+template <typename T>
+__global__ void k_move_finish_table(const JobEntry* __restrict__ tab, int t) {
+  const JobEntry* je = tab + blockIdx.y;
+  if ((int)blockIdx.x >= je->n_finish_wg) return;
+  const Geo g = je->g;
+  char* w = je->work;
+  const int a = t & 1;
+  move_finish_body<T>(g, (const Snap*)(w + (a ? je->snap2 : je->snap)),
+                      (const T*)(w + (a ? je->emon2 : je->emon)), (T*)je->G, (T*)je->E,
+                      je->diag64, je->eps_idx, (int32_t*)(w + je->dl_hdr));
+}
+
+template <typename T>
+hipError_t launch_table_scores(const JobEntry* tab, int n_jobs, int max_wg, hipStream_t s) {
+  hipLaunchKernelGGL(k_mon_score_table<T>, dim3((unsigned)max_wg, (unsigned)n_jobs),
+                     dim3(kScoreThreads), 0, s, tab);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_table_move(const JobEntry* tab, int n_jobs, int max_wg, int t, uint64_t flushed,
+                             bool small, int batch, hipStream_t s) {
+  const dim3 grid((unsigned)max_wg, (unsigned)n_jobs);
+  const bool b16 = batch == 16;
+  hipLaunchKernelGGL((small ? (b16 ? k_move_table<T, 4, 16> : k_move_table<T, 4, 32>)
+                            : (b16 ? k_move_table<T, kPickPerLane, 16>
+                                   : k_move_table<T, kPickPerLane, 32>)),
+                     grid, dim3(256), 0, s, tab, t, flushed);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_table_finish(const JobEntry* tab, int n_jobs, int max_wg, int t, hipStream_t s) {
+  hipLaunchKernelGGL(k_move_finish_table<T>, dim3((unsigned)max_wg, (unsigned)n_jobs), dim3(256), 0,
+                     s, tab, t);
+  return hipGetLastError();
+}
+
+template hipError_t launch_table_scores<float2>(const JobEntry*, int, int, hipStream_t);
+template hipError_t launch_table_scores<double2>(const JobEntry*, int, int, hipStream_t);
+template hipError_t launch_table_move<float2>(const JobEntry*, int, int, int, uint64_t, bool, int,
+                                              hipStream_t);
+template hipError_t launch_table_move<double2>(const JobEntry*, int, int, int, uint64_t, bool, int,
+                                               hipStream_t);
+template hipError_t launch_table_finish<float2>(const JobEntry*, int, int, int, hipStream_t);
+template hipError_t launch_table_finish<double2>(const JobEntry*, int, int, int, hipStream_t);
 
 template hipError_t launch_move<float2>(const Geo&, gfo_state*, const Layout&, int, int, uint32_t,
                                         double, gfo_pick*, hipStream_t);

@@ -391,6 +391,7 @@ inline int score_blocks(const Geo& g) {
 hipError_t launch_score_into(const Geo& g, const gfo_state* st, const ScoreBufs& b, uint32_t mask,
                              double tau, int topk, int spacing, gfo_pick* out, hipStream_t s);
 int validate_state_fields(const gfo_problem* p, const gfo_state* st);
+int validate_job(const gfo_problem* p, const gfo_state* st, Layout* L);
 hipError_t launch_apply(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* pick,
                         hipStream_t s);
 hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* picks,
@@ -431,6 +432,46 @@ hipError_t launch_fused_move(const Geo& g, gfo_state* st, const Layout& L, int a
                              hipStream_t s);
 template <typename T>
 hipError_t launch_fused_finish(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
+
+// ------------------------------------------------------------------ job table
+// One entry per job of a grouped launch (gfo_greedy_steps_table): its geometry,
+// its buffers and the workspace offsets the one-kernel loop uses, and the
+// workgroup counts of its kernels.  Built on the host, read by the table
+// kernels (workgroup (x, y) works for job y as workgroup x of its own launch).
+struct JobEntry {
+  Geo g;
+  void* G;
+  void* E;
+  double2* diag64;
+  uint8_t* eps_idx;
+  int32_t* flips;
+  int32_t* n_flips;
+  int32_t* status;
+  char* work;
+  int64_t snap, snap2, emon, emon2, scores, scores2, partial, partial2, pfirst, pfirst2;
+  int64_t cu, v, dl_hdr, dl_CUs, dl_Vs, picks;
+  double tau;
+  uint32_t mask;
+  int32_t flip_cap;
+  int32_t n_score_wg;   // workgroups of the scoring kernel (kScoreThreads indices each)
+  int32_t n_move_wg;    // workgroups of the move kernel (kGatherElems elements each)
+  int32_t n_finish_wg;  // workgroups of the finishing kernel
+  int32_t nblk0;        // score summaries of the scoring kernel (kScoreThreads pixels each)
+  int32_t nblkg;        // score summaries of the move kernel (kGatherElems pixels each)
+  int32_t pad[3];
+};
+JobEntry make_job_entry(const Geo& g, const gfo_state* st, const Layout& L, uint32_t mask,
+                        double tau);
+// the grouped kernels: every job of the table, one launch each
+template <typename T>
+hipError_t launch_table_scores(const JobEntry* tab, int n_jobs, int max_wg, hipStream_t s);
+template <typename T>
+hipError_t launch_table_move(const JobEntry* tab, int n_jobs, int max_wg, int t, uint64_t flushed,
+                             bool small, int batch, hipStream_t s);
+template <typename T>
+hipError_t launch_table_finish(const JobEntry* tab, int n_jobs, int max_wg, int t, hipStream_t s);
+int gather_move_workgroups(const Geo& g);
+bool move_small_grid(const Geo& g);
 
 // K1 variant selection (autotuner); returns number of variants
 int k1_variant_count(int dtype);

@@ -330,3 +330,51 @@ class Job:
             if refresh_every and acc % refresh_every == 0:
                 self.refresh()
         return acc - start
+
+
+class JobGroup:
+    """Resident jobs stepped together: one launch per move for all of them
+    (gfo_greedy_steps_table) instead of one per job.  Every job must be in
+    deferred mode, and the jobs alike in storage type, term batch and grid class
+    (the library refuses other groups).  The device job table is rebuilt by
+    `build` whenever the set of jobs changes."""
+
+    def __init__(self, jobs, device="cuda"):
+        self.device = torch.device(device)
+        self.jobs = []
+        self.table = None
+        self._probs = None
+        self.set_jobs(jobs)
+
+    def set_jobs(self, jobs):
+        self.jobs = list(jobs)
+        self._probs = None
+        self.table = None
+
+    def __len__(self):
+        return len(self.jobs)
+
+    def build(self, stream=None):
+        """Write the device table of the current jobs (synchronises `stream`)."""
+        n = len(self.jobs)
+        if n == 0:
+            self.table = None
+            return
+        self._probs = (L.Problem * n)(*[j.prob for j in self.jobs])
+        nbytes = L.job_table_bytes(n)
+        self.table = torch.empty((nbytes,), dtype=torch.uint8, device=self.device)
+        states = (L.State * n)(*[j.state for j in self.jobs])
+        L.job_table_build(self._probs, states, [j.problem.cand_mask for j in self.jobs],
+                          [j.problem.tau for j in self.jobs], self.table.data_ptr(), nbytes,
+                          _stream_handle(stream))
+
+    def steps(self, n, stream=None):
+        """n greedy moves of every job: per job, bit for bit the results of one
+        greedy_steps(n) call."""
+        if self.table is None:
+            raise L.GfoError("JobGroup.build() must run after the set of jobs changes")
+        states = (L.State * len(self.jobs))(*[j.state for j in self.jobs])
+        L.greedy_steps_table(self._probs, states, n, self.table.data_ptr(), _stream_handle(stream))
+        for j, st in zip(self.jobs, states):
+            j.state.pending_calls = st.pending_calls
+            j.steps_issued += n
