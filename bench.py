@@ -59,11 +59,6 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-# Flush interval of workloads whose trajectories run for hundreds of moves: 128
-# pending terms share each flush's pass over G among twice the moves (48x2048:
-# 2,731 against 2,373 steps/s); the 190-move trajectories of 128x128 keep 64.
-LONG_TRAJECTORY_DELAY = {"strip48x2048_c64": 128}
-
 # extra columns of G beyond the minimum leading dimension (--ld-pad)
 LD_PAD = 0
 
@@ -326,9 +321,18 @@ def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True):
     from paper_2202_05388_amd.hiprt import EventPool
     from paper_2202_05388_amd.job import Job
 
+    from paper_2202_05388_amd import autotune as at
+
     kmax = 2 * problem.refresh_every if problem.refresh_every else 0
-    job = Job(problem, device="cuda:0", kmax=kmax, delay=delay, ld_pad=LD_PAD)
+    job = Job(problem, device="cuda:0", kmax=kmax, delay=delay or 64, ld_pad=LD_PAD)
     job.init()
+    delay_tuned = None
+    if delay is None:
+        # the flush interval from the trajectory this workload runs (autotuner)
+        delay_tuned = at.tune_delay(job, moves=256, refresh_every=problem.refresh_every,
+                                    save=False)
+        delay = job.delay
+        _log(f"[bench] flush interval autotune {problem.name}: {delay_tuned}")
     flush_tuned = None
     if problem.dtype == "c64":
         from paper_2202_05388_amd import _lib as L
@@ -357,7 +361,8 @@ def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True):
     ld = (N + 63) // 64 * 64
     variant = None if flush_tuned is None else flush_tuned["name"]
     roof = flush_roofline(variant, problem.dtype, N, ld, problem.n_mon, terms, fl)
-    out = dict(delay=delay, fused=fused, storage=problem.dtype, accepted=acc, restarts=restarts,
+    out = dict(delay=delay, delay_autotune=None if delay_tuned is None else delay_tuned["all"],
+               fused=fused, storage=problem.dtype, accepted=acc, restarts=restarts,
                steps_per_s=acc / dt, ms_per_step=1e3 * dt / acc, flushes_timed=len(fl),
                flush_terms=terms, flush_variant=variant,
                flush_us=None if not fl else 1e3 * sum(fl) / len(fl),
@@ -718,8 +723,8 @@ def main():
     ap.add_argument("--no-rank-k", action="store_true")
     ap.add_argument("--no-deferred", action="store_true")
     ap.add_argument("--delay", type=int, default=None,
-                    help="deferred-mode flush interval (default: 128 for the long trajectories of the "
-                         "48x2048 strip, 64 otherwise)")
+                    help="deferred-mode flush interval (default: chosen by the autotuner from the "
+                         "workload's trajectory)")
     ap.add_argument("--no-refresh-timing", action="store_true")
     ap.add_argument("--no-eps-greedy", action="store_true")
     ap.add_argument("--no-regions", action="store_true")
@@ -741,8 +746,6 @@ def main():
     global LD_PAD
     LD_PAD = args.ld_pad
     problem = W.WORKLOADS[args.workload]
-    if args.delay is None:
-        args.delay = LONG_TRAJECTORY_DELAY.get(problem.name, 64)
     _log(f"[bench] {problem.name}: {problem.ny}x{problem.nx}, {problem.n_mon} monitors, "
          f"{problem.dtype}, steps={args.steps} warmup={args.warmup}")
     copy_gbs = None
@@ -811,16 +814,20 @@ def main():
         if problem.name == "square128_c64":
             forms.append(W.SQUARE_128_FP64)
         for pf in forms:
-            _log(f"[bench] deferred updates, {pf.name}, delay {args.delay}")
+            _log(f"[bench] deferred updates, {pf.name}, delay {args.delay or 'autotuned'}")
             deferred[pf.name] = time_deferred(pf, args.steps, args.warmup, args.poll, args.delay)
             _log(f"[bench] deferred {pf.name}: {deferred[pf.name]}")
+            d_pf = deferred[pf.name]["delay"]
             key = pf.name + "_per_call"
-            deferred[key] = time_deferred(pf, args.steps, args.warmup, args.poll, args.delay,
+            deferred[key] = time_deferred(pf, args.steps, args.warmup, args.poll, d_pf,
                                           fused=False, tune=False)
             _log(f"[bench] deferred {key}: {deferred[key]}")
             key = pf.name + "_graph"
-            deferred[key] = time_deferred_graph(pf, args.steps, args.warmup, args.delay)
+            deferred[key] = time_deferred_graph(pf, args.steps, args.warmup, d_pf)
             _log(f"[bench] deferred {key}: {deferred[key]}")
+    if args.delay is None:
+        # the other deferred legs use the interval chosen for the headline workload
+        args.delay = deferred[problem.name]["delay"] if deferred else 64
 
     rank_k = None
     if not args.no_rank_k and problem.name == "square128_c64":

@@ -1,10 +1,14 @@
-"""Autotuner for the streaming rank-1 kernel of apply_flip.
+"""Autotuner: kernel variants and the deferred-update schedule, on the live shape.
 
-Times every tile variant the library exposes on the real problem shape with HIP
-events recorded around the kernel alone, picks the fastest, and caches the
-choice as JSON keyed by (architecture, N, R, storage type).  All variants
-compute bit-identical results (tests/test_gpu_step.py checks this), so the
-choice affects speed only.
+  * the streaming rank-1 kernel of apply_flip (tile variants, bit-identical);
+  * the complex64 flush of the deferred terms (tile variants);
+  * the matrix-core update of apply_flips_rank_k (tile and epilogue variants),
+    per input precision;
+  * the flush interval of deferred mode, from the trajectory the job runs.
+
+Kernels are timed with HIP events recorded around the kernel alone; the flush
+interval by the wall clock of the fused greedy loop.  Choices are cached as JSON
+keyed by (architecture, N, R, storage type, ...).
 
 Cache path: $GFO_AUTOTUNE_CACHE, else ~/.cache/gfo/autotune.json.
 """
@@ -215,6 +219,46 @@ def tune_rank_k(job, rank: int = 16, precision: int = None, reps: int = 4,
     if save:
         d = load_cache()
         d[f"{_key(job.N, job.R, job.dtype_name)}/rk{16 if rank <= 16 else 32}/{prec}"] = entry
+        save_cache(d)
+    return entry
+
+
+def tune_delay(job, moves: int = 256, candidates=(32, 64, 128), chunk: int = 32,
+               refresh_every: int = 0, save: bool = True) -> dict:
+    """Choose the flush interval (pending terms per flush) of a deferred-mode
+    job from its own trajectory: for each candidate, start from init_G0 and time
+    the fused greedy loop (gfo_greedy_steps in chunks of `chunk` moves, the
+    flushes it launches and a final one) over the first `moves` moves, or to the
+    trajectory's end if it ends earlier.  Longer trajectories favour more terms
+    per flush (a flush is one pass over the design block, shared by more
+    moves); short ones pay for a partial last flush.  Sets the fastest on the
+    job (job.delay and its state) and caches it by shape and trajectory length."""
+    import torch
+
+    if job.dtype_name not in ("c64", "c128"):
+        raise L.GfoError("unknown storage type")
+    res = []
+    for d in candidates:
+        if not 1 <= d <= L.GFO_MAX_DELAY:
+            continue
+        job.delay = d
+        job.state.delay = d
+        job.init()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = job.run_greedy(moves, poll_every=chunk, refresh_every=refresh_every, fused=True)
+        job.flush()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res.append(dict(delay=d, moves=n, us_per_move=1e6 * dt / max(n, 1)))
+    best = min(res, key=lambda r: r["us_per_move"])
+    job.delay = best["delay"]
+    job.state.delay = best["delay"]
+    job.init()
+    entry = dict(delay=best["delay"], moves=best["moves"], all=res)
+    if save:
+        d = load_cache()
+        d[f"{_key(job.N, job.R, job.dtype_name)}/delay/{best['moves']}"] = entry
         save_cache(d)
     return entry
 

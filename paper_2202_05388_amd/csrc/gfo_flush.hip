@@ -16,53 +16,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // reads past the range return zero).
 constexpr int kBufferDword3 = 0x00020000;
 
-// FP32 flush for complex64 storage: G[m, n] += sum_{s < count} CU[s][m] V[s][n]
-// for design rows m < N and all ld columns, as complex FP32 on the matrix cores
-// (v_mfma_f32_32x32x2_f32; re += Ar Br - Ai Bi, im += Ar Bi + Ai Br).  The G tile
-// is loaded into the accumulators, so G is read and written once.  Workgroup of
-// 4 waves = 64 x 64 outputs, each wave 32 x 32.  Lane layout of the instruction:
-// A(i, k): i = lane % 32, k = lane / 32; B(k, j): j = lane % 32, k = lane / 32;
-// accumulator element e: row 8*(e/4) + 4*(lane/32) + e%4, column lane % 32.
-__global__ __launch_bounds__(256) void k_flush_c64(int M, int R, int64_t ld,
-                                                   const int32_t* __restrict__ count,
-                                                   const float2* __restrict__ CU,
-                                                   const float2* __restrict__ V,
-                                                   float2* __restrict__ G) {
-  const int K = *count;
-  if (K == 0) return;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = blockIdx.y * 64 + (w >> 1) * 32;
-  const int n = blockIdx.x * 64 + (w & 1) * 32 + (lane & 31);
-  const int h = lane >> 5;
-  f32x16 accr, acci;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int row = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    const float2 gv = row < M ? G[(int64_t)row * ld + n] : make_float2(0.f, 0.f);
-    accr[e] = gv.x;
-    acci[e] = gv.y;
-  }
-  const int am = m0 + (lane & 31);
-#pragma unroll 4
-  for (int k0 = 0; k0 < K; k0 += 2) {
-    const int kk = k0 + h;
-    float2 a = make_float2(0.f, 0.f), b = make_float2(0.f, 0.f);
-    if (kk < K) {
-      if (am < M) a = CU[(int64_t)kk * R + am];
-      b = V[(int64_t)kk * ld + n];
-    }
-    accr = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, accr, 0, 0, 0);
-    accr = __builtin_amdgcn_mfma_f32_32x32x2f32(-a.y, b.y, accr, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, acci, 0, 0, 0);
-    acci = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.x, acci, 0, 0, 0);
-  }
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int row = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    if (row < M) G[(int64_t)row * ld + n] = make_float2(accr[e], acci[e]);
-  }
-}
-
 // Variants with TM row tiles of 32 per wave (a 32*TM x 32 output tile; the TM
 // tiles share each B value) and 64*TM x 64 per workgroup.  The accumulators of
 // different row tiles are independent, so consecutive matrix instructions do not
@@ -175,12 +128,6 @@ __device__ __forceinline__ void tri_tile(int t, int nb, int& r, int& c) {
 // uses this form only when GFO_MAX_DELAY * max(R, ld) * 8 < 2^31.  THREE_MULT
 // as in k_flush_c64_tm.
 //
-// XCD: a one-dimensional grid numbered for the chip's eight XCDs (consecutive
-// workgroup ids go to different XCDs, id b to XCD b % 8).  XCD x takes the row
-// blocks [x * bpx, (x + 1) * bpx) and walks them column block by column block:
-// its band of CU rows stays in its own L2 and each V column block is reused
-// across the band.  nby = row blocks, bpx = ceil(nby / 8), grid = 8 * bpx * nbx.
-//
 // SYM: the design block is symmetric (reciprocity: G_D = G_D^T, and each pending
 // term restricted to it, c_s v_s v_s^T, is symmetric too), so only the tiles on
 // and above the diagonal are computed: a one-dimensional grid of nby (nby + 1) / 2
@@ -197,7 +144,7 @@ __device__ __forceinline__ void tri_tile(int t, int nb, int& r, int& c) {
 // triangle is out of date, and readers take design entries from the upper
 // one).  Diagonal tiles are computed whole, their lower halves from the old
 // values.
-template <bool THREE_MULT, int H, bool XCD, bool SYM = false, bool NT = false, bool MIRROR = true,
+template <bool THREE_MULT, int H, bool SYM = false, bool NT = false, bool MIRROR = true,
           int P = GFO_MAX_DELAY / 2>
 __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld,
                                                         const int32_t* __restrict__ count,
@@ -207,12 +154,6 @@ __global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld
   const int K = *count;
   if (K == 0) return;
   int bx = blockIdx.x, by = blockIdx.y;
-  if (XCD) {
-    const int bpx = (nby + 7) / 8, xcd = (int)(blockIdx.x & 7), local = (int)(blockIdx.x >> 3);
-    bx = local / bpx;
-    by = xcd * bpx + local % bpx;
-    if (by >= nby) return;
-  }
   if (SYM) tri_tile((int)blockIdx.x, nby, by, bx);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = by * 64 + (w >> 1) * 32;
@@ -439,173 +380,14 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
   }
 }
 
-// Warp-specialised persistent flush: one workgroup of 8 waves per CU walks the
-// 64 x 64 output tiles (tile id = blockIdx.x + i * gridDim.x; bx = id % nbx,
-// by = id / nbx).  Waves 0-3 only stream CU/V operands and issue matrix
-// instructions (32 x 32 outputs each, three real products per complex one, an
-// operand ring of H instruction steps that runs on into the next tile); waves
-// 4-7 move G: they bring the next tile's G into one of two LDS buffers while the
-// current tile computes, and store the finished tile from LDS.  The matrix waves
-// thus never wait on G traffic (vector memory operations of a wave complete in
-// issue order).  Per tile, every wave passes the same two barriers:
-//   X: the matrix waves hold the tile's products, G_in[t % 2] is loaded, the
-//      movers have read the previous finished tile out of G_out;
-//   Y: G_out holds tile t (G + products), G_in[(t + 1) % 2] holds tile t + 1.
-// Same operand loads and 32-bit offset limit as k_flush_c64_pipe.
-constexpr int kWsPitch = 66;                     // float2 per LDS row (16-B aligned rows)
-constexpr int kWsTile = 64 * kWsPitch;
-
-template <int H>
-__global__ __launch_bounds__(512) void k_flush_c64_ws(int M, int R, int64_t ld,
-                                                      const int32_t* __restrict__ count,
-                                                      const float2* __restrict__ CU,
-                                                      const float2* __restrict__ V,
-                                                      float2* __restrict__ G, int nbx, int nby) {
-  __shared__ __align__(16) float2 lds[3 * kWsTile];     // G_in[0], G_in[1], G_out
-  const int K = *count;
-  if (K == 0) return;
-  const int ntiles = nbx * nby;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  constexpr int P = GFO_MAX_DELAY / 2;
-  static_assert(P % H == 0 && H < P, "ring depth");
-  if (w >= 4) {
-    // ---------------------------------------------------------------- movers
-    const int mt = threadIdx.x - 256;             // 0..255: 8 x 16 B of a 32 KB tile each
-    auto tile_rc = [&](int id, int j, int& r, int& c) {
-      const int idx = (j * 256 + mt) * 2;         // float2 index within the 64 x 64 tile
-      r = idx >> 6;
-      c = idx & 63;
-      (void)id;
-    };
-    f32x4 buf[8];
-    auto load_tile = [&](int id) {
-      const int bx = id % nbx, by = id / nbx;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        int r, c;
-        tile_rc(id, j, r, c);
-        const int row = by * 64 + r;
-        buf[j] = row < M ? *(const f32x4*)(G + (int64_t)row * ld + bx * 64 + c) : f32x4{0.f, 0.f, 0.f, 0.f};
-      }
-    };
-    auto put_in = [&](int slot) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        int r, c;
-        tile_rc(0, j, r, c);
-        *(f32x4*)(lds + slot * kWsTile + r * kWsPitch + c) = buf[j];
-      }
-    };
-    auto store_out = [&](int id) {
-      const int bx = id % nbx, by = id / nbx;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        int r, c;
-        tile_rc(id, j, r, c);
-        const f32x4 v = *(const f32x4*)(lds + 2 * kWsTile + r * kWsPitch + c);
-        const int row = by * 64 + r;
-        if (row < M) *(f32x4*)(G + (int64_t)row * ld + bx * 64 + c) = v;
-      }
-    };
-    int id = blockIdx.x;
-    if (id < ntiles) {
-      load_tile(id);
-      put_in(0);
-    }
-    __syncthreads();                              // prologue: G_in[0] holds the first tile
-    int it = 0;
-    for (; id < ntiles; id += gridDim.x, ++it) {
-      if (it > 0) store_out(id - (int)gridDim.x);            // the previous finished tile
-      const int nid = id + (int)gridDim.x;
-      if (nid < ntiles) load_tile(nid);
-      __syncthreads();                            // X
-      if (nid < ntiles) put_in((it + 1) & 1);
-      __syncthreads();                            // Y
-    }
-    if (it > 0) store_out(id - (int)gridDim.x);
-    return;
-  }
-  // ---------------------------------------------------------------- matrix waves
-  const int h = lane >> 5;
-  const __amdgpu_buffer_rsrc_t ra =
-      __builtin_amdgcn_make_buffer_rsrc((void*)CU, (short)0, K * R * 8, kBufferDword3);
-  const __amdgpu_buffer_rsrc_t rb =
-      __builtin_amdgcn_make_buffer_rsrc((void*)V, (short)0, (int)(K * ld * 8), kBufferDword3);
-  const unsigned a_step = 2u * (unsigned)R * 8u, b_step = 2u * (unsigned)ld * 8u;
-  // operand offsets of a tile (an id past the end gives offsets past the range: zeros)
-  auto offsets = [&](int id, unsigned& ao, unsigned& bo) {
-    if (id >= ntiles) {
-      ao = bo = 0xFFFFFFF0u;
-      return;
-    }
-    const int bx = id % nbx, by = id / nbx;
-    const int am = by * 64 + (w >> 1) * 32 + (lane & 31);
-    const int n = bx * 64 + (w & 1) * 32 + (lane & 31);
-    ao = am < M ? (unsigned)(h * R + am) * 8u : 0xFFFFFFF0u;
-    bo = (unsigned)(h * ld + n) * 8u;
-  };
-  auto ld_a = [&](unsigned base, int step) {
-    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(
-                                         ra, base == 0xFFFFFFF0u ? base : base + step * a_step, 0, 0));
-  };
-  auto ld_b = [&](unsigned base, int step) {
-    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(
-                                         rb, base == 0xFFFFFFF0u ? base : base + step * b_step, 0, 0));
-  };
-  int id = blockIdx.x;
-  unsigned a_off, b_off;
-  offsets(id, a_off, b_off);
-  f32x2 ra_[H], rb_[H];
-#pragma unroll
-  for (int i = 0; i < H; ++i) {
-    ra_[i] = ld_a(a_off, i);
-    rb_[i] = ld_b(b_off, i);
-  }
-  __syncthreads();                                // prologue
-  const int lr0 = (w >> 1) * 32 + 4 * h, lc = (w & 1) * 32 + (lane & 31);
-  for (int it = 0; id < ntiles; id += gridDim.x, ++it) {
-    unsigned na, nb;
-    offsets(id + (int)gridDim.x, na, nb);
-    f32x16 X, Y, Z;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) X[e] = Y[e] = Z[e] = 0.f;
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const f32x2 ai = ra_[i % H], bi = rb_[i % H];
-      if (i + H < P) {
-        ra_[i % H] = ld_a(a_off, i + H);
-        rb_[i % H] = ld_b(b_off, i + H);
-      } else {
-        ra_[i % H] = ld_a(na, i + H - P);
-        rb_[i % H] = ld_b(nb, i + H - P);
-      }
-      X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
-      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[1], bi[1], Y, 0, 0, 0);
-      Z = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0] + ai[1], bi[0] + bi[1], Z, 0, 0, 0);
-    }
-    __syncthreads();                              // X
-    const float2* gin = lds + (it & 1) * kWsTile;
-    float2* gout = lds + 2 * kWsTile;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int r = lr0 + 8 * (e >> 2) + (e & 3);
-      const float2 gv = gin[r * kWsPitch + lc];
-      gout[r * kWsPitch + lc] = make_float2(gv.x + (X[e] - Y[e]), gv.y + (Z[e] - X[e] - Y[e]));
-    }
-    __syncthreads();                              // Y
-    a_off = na;
-    b_off = nb;
-  }
-}
 
 // flush variants for complex64 storage (selected by the autotuner; all give the
 // eager results to FP32 rounding, tests/test_gpu_deferred.py)
-static const char* const kFlushNames[] = {"w32", "w32_3m", "w32_pipe16_3m", "w32_pipe8",
-                                          "w32_pipe8_3m", "w32_pipe8_3m_xcd", "ws8_3m",
-                                          "ws16_3m", "sym_pipe8_3m", "sym_pipe8_3m_nt",
-                                          "sym_pipe4_3m_nt", "up_pipe8_3m_nt", "up_pair4_3m_nt"};
+static const char* const kFlushNames[] = {"w32_3m",          "w32_pipe8_3m",   "sym_pipe8_3m",
+                                          "sym_pipe8_3m_nt", "sym_pipe4_3m_nt", "up_pipe8_3m_nt",
+                                          "up_pair4_3m_nt"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
-constexpr int kFlushDefault = 12;
+constexpr int kFlushDefault = 6;
 static std::atomic<int> g_flush_sel{kFlushDefault};
 int flush_variant_count() { return kFlushCount; }
 const char* flush_variant_name(int i) { return i >= 0 && i < kFlushCount ? kFlushNames[i] : nullptr; }
@@ -628,72 +410,38 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
     bool monitors_done = false;
     // the pipelined forms address the term buffers with 32-bit byte offsets
     const bool off32 = (int64_t)GFO_MAX_DELAY * (g.ld > g.R ? g.ld : g.R) * 8 < ((int64_t)1 << 31);
-    if (fv >= 2 && !off32) fv = 1;
+    if (fv >= 1 && !off32) fv = 0;
     const float2* cu = (const float2*)(w + L.dl_CUs);
     const float2* vv = (const float2*)(w + L.dl_Vs);
     float2* G = (float2*)st->G;
     const dim3 grid((unsigned)(g.ld / 64), (unsigned)((g.N + 63) / 64)), blk(256);
     switch (fv) {
       case 0:
-        hipLaunchKernelGGL(k_flush_c64, grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G);
-        break;
-      case 1:
         hipLaunchKernelGGL((k_flush_c64_tm<1, true>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G,
                            0);
         break;
+      case 1:
+        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8>), grid, blk, 0, s, g.N, g.R, g.ld, count,
+                           cu, vv, G, (int)grid.y);
+        break;
       case 2:
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 16, false>), grid, blk, 0, s, g.N, g.R, g.ld, count,
-                           cu, vv, G, (int)grid.y);
-        break;
       case 3:
-        hipLaunchKernelGGL((k_flush_c64_pipe<false, 8, false>), grid, blk, 0, s, g.N, g.R, g.ld, count,
-                           cu, vv, G, (int)grid.y);
-        break;
-      case 4:
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false>), grid, blk, 0, s, g.N, g.R, g.ld, count,
-                           cu, vv, G, (int)grid.y);
-        break;
-      case 6:
-      case 7: {
-        // one persistent workgroup per CU (its LDS allows no second one)
-        static std::atomic<int> n_cu_cache{0};
-        int n_cu = n_cu_cache.load();
-        if (n_cu == 0) {
-          int dev = 0;
-          if (hipGetDevice(&dev) != hipSuccess ||
-              hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-              n_cu <= 0)
-            return hipErrorUnknown;
-          n_cu_cache.store(n_cu);
-        }
-        const int nbx = (int)grid.x, nby = (int)grid.y;
-        const int nwg = n_cu < nbx * nby ? n_cu : nbx * nby;
-        if (fv == 6)
-          hipLaunchKernelGGL((k_flush_c64_ws<8>), dim3(nwg), dim3(512), 0, s, g.N, g.R, g.ld, count, cu,
-                             vv, G, nbx, nby);
-        else
-          hipLaunchKernelGGL((k_flush_c64_ws<16>), dim3(nwg), dim3(512), 0, s, g.N, g.R, g.ld, count,
-                             cu, vv, G, nbx, nby);
-        break;
-      }
-      case 8:
-      case 9:
-      case 10: {
+      case 4: {
         // design-block triangle only (symmetric flush)
         const int nb = (g.N + 63) / 64;
         const dim3 tri((unsigned)(nb * (nb + 1) / 2));
-        if (fv == 8)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true>), tri, blk, 0, s, g.N, g.R, g.ld,
+        if (fv == 2)
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true>), tri, blk, 0, s, g.N, g.R, g.ld,
                              count, cu, vv, G, nb);
-        else if (fv == 9)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true>), tri, blk, 0, s, g.N, g.R,
+        else if (fv == 3)
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true, true>), tri, blk, 0, s, g.N, g.R,
                              g.ld, count, cu, vv, G, nb);
         else
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 4, false, true, true>), tri, blk, 0, s, g.N, g.R,
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 4, true, true>), tri, blk, 0, s, g.N, g.R,
                              g.ld, count, cu, vv, G, nb);
         break;
       }
-      case 11: {
+      case 5: {
         // upper triangle only; the lower one is out of date from here on.  The
         // calls since the last flush bound the term count (a refused move
         // records none), so a partial flush runs fewer steps.
@@ -701,21 +449,21 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         const dim3 tri((unsigned)(nb * (nb + 1) / 2));
         const int bound = st->pending_calls;
         if (bound <= 16)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false, 8>), tri, blk, 0, s,
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true, true, false, 8>), tri, blk, 0, s,
                              g.N, g.R, g.ld, count, cu, vv, G, nb);
         else if (bound <= 32)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false, 16>), tri, blk, 0, s,
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true, true, false, 16>), tri, blk, 0, s,
                              g.N, g.R, g.ld, count, cu, vv, G, nb);
         else if (bound <= 64)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false, 32>), tri, blk, 0, s,
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true, true, false, 32>), tri, blk, 0, s,
                              g.N, g.R, g.ld, count, cu, vv, G, nb);
         else
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, false, true, true, false, 64>), tri, blk, 0, s,
+          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true, true, false, 64>), tri, blk, 0, s,
                              g.N, g.R, g.ld, count, cu, vv, G, nb);
         st->lower_stale = 1;
         break;
       }
-      case 12: {
+      default: {
         // upper triangle only, pair-interleaved terms in the unused halves of
         // the term buffers (complex64 slots take 8 of their 16 bytes)
         const int nb = (g.N + 63) / 64;
@@ -741,12 +489,6 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
           hipLaunchKernelGGL((k_flush_c64_pair<4, 32>), tri, blk, 0, s, g.N, g.R, g.ld, count,
                              (const f32x4*)cu2, (const f32x4*)vv2, G, nb);
         st->lower_stale = 1;
-        break;
-      }
-      default: {
-        const unsigned nby = grid.y, bpx = (nby + 7) / 8;
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true>), dim3(8 * bpx * grid.x), blk, 0, s, g.N,
-                           g.R, g.ld, count, cu, vv, G, (int)nby);
         break;
       }
     }

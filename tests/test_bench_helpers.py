@@ -32,12 +32,6 @@ def test_counter_traffic_lookup():
         assert os.path.exists(os.path.join(bench.ROOT, rec["source"]))
 
 
-def test_long_trajectory_workloads_flush_every_128():
-    import workloads as W
-    assert bench.LONG_TRAJECTORY_DELAY == {"strip48x2048_c64": 128}
-    assert "strip48x2048_c64" in W.WORKLOADS
-
-
 def test_flush_flops_count_the_folded_terms_only():
     N, ld, n_mon = 16384, 16384, 64
     nb = N // 64
@@ -45,8 +39,8 @@ def test_flush_flops_count_the_folded_terms_only():
     f64 = bench.flush_mfma_flops("up_pair4_3m_nt", "c64", N, ld, n_mon, 64)
     assert f64 == 6.0 * 4096 * tiles * 64            # three real products of 2 flops each
     assert bench.flush_mfma_flops("up_pair4_3m_nt", "c64", N, ld, n_mon, 20) == f64 * 20 / 64
-    # four real products in the plain form, every tile of the block
-    assert bench.flush_mfma_flops("w32", "c64", N, ld, n_mon, 1) == 8.0 * 4096 * nb * (ld // 64)
+    # the non-symmetric form computes every tile of the block
+    assert bench.flush_mfma_flops("w32_pipe8_3m", "c64", N, ld, n_mon, 1) == 6.0 * 4096 * nb * (ld // 64)
 
 
 def test_flush_roofline_bound_follows_the_terms():
