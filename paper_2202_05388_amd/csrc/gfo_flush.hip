@@ -301,7 +301,9 @@ __global__ __launch_bounds__(256) void k_flush_pack(int R, int64_t ld,
 // The workgroups past the nby (nby + 1) / 2 triangle tiles take the monitor
 // rows [M, R) in 64 x 64 tiles over all ld columns (the FOM monitor's terms
 // are zeros, and G is added in the epilogue, so its row is rewritten unchanged).
-template <int HP, int PP>
+// XORD: the XCD tile order (xcd_tile): the grid is 8 x the largest per-XCD
+// tile count, and workgroups without a tile return at once.
+template <int HP, int PP, bool XORD = false>
 __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld,
                                                         const int32_t* __restrict__ count,
                                                         const f32x4* __restrict__ CU2,
@@ -311,7 +313,14 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
   if (K == 0) return;
   const int ntri = nby * (nby + 1) / 2;
   int by, bx, lim, rbase;
-  if ((int)blockIdx.x < ntri) {
+  if constexpr (XORD) {
+    const int nbx = (int)(ld / 64), nmb = (R - M + 63) / 64;
+    bool mon = false;
+    if (!xcd_tile((int)blockIdx.x, nby, nbx, nmb, &by, &bx, &mon)) return;
+    if (bx < 0 || bx >= nbx || by < 0 || by >= (mon ? nmb : nby)) return;
+    lim = mon ? R : M;
+    rbase = mon ? M + by * 64 : by * 64;
+  } else if ((int)blockIdx.x < ntri) {
     tri_tile((int)blockIdx.x, nby, by, bx);
     lim = M;
     rbase = by * 64;
@@ -385,7 +394,7 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
 // eager results to FP32 rounding, tests/test_gpu_deferred.py)
 static const char* const kFlushNames[] = {"w32_3m",          "w32_pipe8_3m",   "sym_pipe8_3m",
                                           "sym_pipe8_3m_nt", "sym_pipe4_3m_nt", "up_pipe8_3m_nt",
-                                          "up_pair4_3m_nt"};
+                                          "up_pair4_3m_nt",  "up_pair4_3m_nt_x8"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
 constexpr int kFlushDefault = 6;
 static std::atomic<int> g_flush_sel{kFlushDefault};
@@ -473,21 +482,35 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         hipLaunchKernelGGL(k_flush_pack, dim3((unsigned)((nx + 255) / 256), GFO_MAX_DELAY / 2), blk, 0, s,
                            g.R, g.ld, count, cu, vv, cu2, vv2);
         // the triangle's tiles, then the monitor rows' (no separate monitor kernel)
-        const dim3 tri((unsigned)(nb * (nb + 1) / 2 + (g.nmon + 63) / 64 * (g.ld / 64)));
+        const int nmb = (g.nmon + 63) / 64, nbx = (int)(g.ld / 64);
+        unsigned ntiles = (unsigned)(nb * (nb + 1) / 2 + nmb * nbx);
+        const bool xord = fv == 7;
+        if (xord) {
+          int mx = 0;
+          for (int x = 0; x < 8; ++x) {
+            const int c = xcd_tile_count(nb, nbx, nmb, x);
+            mx = c > mx ? c : mx;
+          }
+          ntiles = 8u * (unsigned)mx;
+        }
+        const dim3 tri(ntiles);
         monitors_done = true;
         const int bound = st->pending_calls;
-        if (bound <= 16)
-          hipLaunchKernelGGL((k_flush_c64_pair<4, 4>), tri, blk, 0, s, g.N, g.R, g.ld, count,
-                             (const f32x4*)cu2, (const f32x4*)vv2, G, nb);
-        else if (bound <= 32)
-          hipLaunchKernelGGL((k_flush_c64_pair<4, 8>), tri, blk, 0, s, g.N, g.R, g.ld, count,
-                             (const f32x4*)cu2, (const f32x4*)vv2, G, nb);
-        else if (bound <= 64)
-          hipLaunchKernelGGL((k_flush_c64_pair<4, 16>), tri, blk, 0, s, g.N, g.R, g.ld, count,
-                             (const f32x4*)cu2, (const f32x4*)vv2, G, nb);
-        else
-          hipLaunchKernelGGL((k_flush_c64_pair<4, 32>), tri, blk, 0, s, g.N, g.R, g.ld, count,
-                             (const f32x4*)cu2, (const f32x4*)vv2, G, nb);
+        const f32x4* c2 = (const f32x4*)cu2;
+        const f32x4* v2 = (const f32x4*)vv2;
+        if (bound <= 16) {
+          if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 4, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+          else hipLaunchKernelGGL((k_flush_c64_pair<4, 4>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+        } else if (bound <= 32) {
+          if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 8, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+          else hipLaunchKernelGGL((k_flush_c64_pair<4, 8>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+        } else if (bound <= 64) {
+          if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 16, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+          else hipLaunchKernelGGL((k_flush_c64_pair<4, 16>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+        } else {
+          if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 32, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+          else hipLaunchKernelGGL((k_flush_c64_pair<4, 32>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+        }
         st->lower_stale = 1;
         break;
       }

@@ -433,6 +433,59 @@ hipError_t launch_fused_move(const Geo& g, gfo_state* st, const Layout& L, int a
 template <typename T>
 hipError_t launch_fused_finish(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s);
 
+// ------------------------------------------------------------------ XCD tile order
+// Tiles of an upper-triangle flush (nb x nb design tiles on and above the
+// diagonal, then nmb rows of nbx monitor tiles), numbered so that workgroup b
+// (the dispatcher sends workgroup b to XCD b % 8) takes tiles of the column
+// blocks bx with bx % 8 == b % 8 only: XCD x walks its own tiles row by row
+// (triangle rows first, then monitor rows), so its L2 holds just the operand
+// panels of its eighth of the columns, while the eight XCDs sweep the same rows
+// of G together.  Returns false when workgroup b has no tile (the grid is 8
+// times the largest per-XCD count).
+__host__ __device__ inline int xcd_cols_below(int n, int x) {   // #{c < n : c % 8 == x}
+  return n > x ? (n - x + 7) / 8 : 0;
+}
+__host__ __device__ inline int xcd_tri_before(int by, int nb, int x) {
+  // XCD x's triangle tiles in rows [0, by): sum over rows i < by of
+  // #{c in [i, nb) : c % 8 == x} = by * cols(nb) - sum_{i < by} cols(i)
+  const int m = by - 1 - x;
+  int lower = 0;
+  if (m > 0) {
+    const int q = m / 8, r = m % 8;
+    lower = 4 * q * (q + 1) + r * (q + 1);
+  }
+  return by * xcd_cols_below(nb, x) - lower;
+}
+__host__ __device__ inline int xcd_tile_count(int nb, int nbx, int nmb, int x) {
+  return xcd_tri_before(nb, nb, x) + nmb * xcd_cols_below(nbx, x);
+}
+__host__ __device__ inline bool xcd_tile(int b, int nb, int nbx, int nmb, int* by, int* bx,
+                                         bool* mon) {
+  const int x = b & 7, local = b >> 3;
+  const int ntri = xcd_tri_before(nb, nb, x);
+  if (local < ntri) {
+    int lo = 0, hi = nb - 1;                 // the last row whose start is <= local
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (xcd_tri_before(mid, nb, x) <= local) lo = mid; else hi = mid - 1;
+    }
+    const int k = local - xcd_tri_before(lo, nb, x);
+    const int c0 = lo + ((x - lo % 8) + 8) % 8;   // first column >= lo with c % 8 == x
+    *by = lo;
+    *bx = c0 + 8 * k;
+    *mon = false;
+    return *bx < nb;
+  }
+  const int per = xcd_cols_below(nbx, x);
+  if (per == 0) return false;
+  const int l2 = local - ntri, mby = l2 / per;
+  if (mby >= nmb) return false;
+  *by = mby;
+  *bx = x + 8 * (l2 - mby * per);
+  *mon = true;
+  return *bx < nbx;
+}
+
 // ------------------------------------------------------------------ job table
 // One entry per job of a grouped launch (gfo_greedy_steps_table): its geometry,
 // its buffers and the workspace offsets the one-kernel loop uses, and the
