@@ -390,11 +390,188 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
 }
 
 
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+// Persistent form of the pair flush (same operands, same matrix steps in the same
+// order, so the same results bit for bit): workgroup b takes a contiguous run of
+// the tile list (triangle tiles row by row, then the monitor rows' tiles; runs in
+// XCD order, workgroup b on XCD b % 8 taking run (b % 8) P/8 + b / 8).  Per wave:
+// the CU operands of its 32 rows of the current row band stay in registers
+// (reloaded when the run enters a new band); the V operands of a tile go
+// through LDS, one copy per workgroup; the G tile is read two tiles ahead, in
+// two register sets that alternate between tiles.  Per tile the loads are
+// issued in the order V(t+1), G(t+1), so the wait for V(t+1) at the end of tile
+// t leaves G(t+1) in flight and the matrix loop never waits on memory.  G is
+// read and written through a buffer whose range ends at the tile's last row
+// (rows past the matrix read zero, their stores are dropped).  Odd runs start
+// by sleeping for about half a tile, so that the two workgroups sharing a
+// compute unit reach their epilogues at different times.
+template <int PP>
+__global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld,
+                                                        const int32_t* __restrict__ count,
+                                                        const f32x4* __restrict__ CU2,
+                                                        const f32x4* __restrict__ V2,
+                                                        float2* __restrict__ G, int nby, int chunk) {
+  const int K = *count;
+  if (K == 0) return;
+  const int ntri = nby * (nby + 1) / 2;
+  const int nbx = (int)(ld / 64), nmb = (R - M + 63) / 64;
+  const int T = ntri + nmb * nbx;
+  const int P = (int)gridDim.x, b = (int)blockIdx.x;
+  const int run = (P & 7) == 0 ? (b & 7) * (P >> 3) + (b >> 3) : b;
+  const int t0 = run * chunk;
+  const int t1 = t0 + chunk < T ? t0 + chunk : T;
+  if (t0 >= t1) return;
+  __shared__ f32x4 Vsh[2 * PP][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const int np = (K + 1) / 2;
+  const __amdgpu_buffer_rsrc_t ra =
+      __builtin_amdgcn_make_buffer_rsrc((void*)CU2, (short)0, np * R * 16, kBufferDword3);
+  const __amdgpu_buffer_rsrc_t rb =
+      __builtin_amdgcn_make_buffer_rsrc((void*)V2, (short)0, (int)(np * ld * 16), kBufferDword3);
+  const int q = (w >> 1) * 32 + (lane & 31);   // row of the band (CU operand)
+  const int cc = (w & 1) * 32 + (lane & 31);  // column of the tile (V operand)
+  const unsigned g_lane = (unsigned)(((w >> 1) * 32 + 4 * h) * ld + cc) * 8u;
+  f32x4 aR[PP];
+  auto load_A = [&](int lim, int rbase) {
+    const int am = rbase + q;
+    const unsigned off = am < lim ? (unsigned)(h * R + am) * 16u : 0xFFFFFFF0u;
+    const unsigned st = am < lim ? 2u * (unsigned)R * 16u : 0u;
+#pragma unroll
+    for (int i = 0; i < PP; ++i)
+      aR[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, off + i * st, 0, 0));
+  };
+  constexpr int NB = (2 * PP * 64) / 256;
+  f32x4 bs[NB];
+  auto load_B = [&](int bx) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int e = j * 256 + (int)threadIdx.x;
+      const unsigned off = (unsigned)((e >> 6) * ld + bx * 64 + (e & 63)) * 16u;
+      bs[j] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb, off, 0, 0));
+    }
+  };
+  auto stage_B = [&]() {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int e = j * 256 + (int)threadIdx.x;
+      Vsh[e >> 6][e & 63] = bs[j];
+    }
+  };
+  auto g_rsrc = [&](int bx, int lim, int rbase) {
+    const int rows = lim - rbase < 64 ? lim - rbase : 64;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(G + (int64_t)rbase * ld + bx * 64), (short)0,
+                                             (int)((int64_t)rows * ld * 8), kBufferDword3);
+  };
+  auto load_G = [&](__amdgpu_buffer_rsrc_t rg, float2(&gv)[16]) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const unsigned off = g_lane + (unsigned)((8 * (e >> 2) + (e & 3)) * ld) * 8u;
+      gv[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, off, 0, 2));
+    }
+  };
+  // tile t of the list: row band, column tile, row limit, first row
+  int band, bx, lim, rbase;
+  if (t0 < ntri) {
+    tri_tile(t0, nby, band, bx);
+    lim = M;
+    rbase = band * 64;
+  } else {
+    const int u = t0 - ntri;
+    bx = u % nbx;
+    band = nby + u / nbx;
+    lim = R;
+    rbase = M + (u / nbx) * 64;
+  }
+  float2 gA[16], gB[16];
+  load_A(lim, rbase);
+  load_B(bx);
+  __amdgpu_buffer_rsrc_t rcur = g_rsrc(bx, lim, rbase);
+  load_G(rcur, gA);
+  stage_B();
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the operands are in registers on every path
+  __syncthreads();
+  if ((run & 1) && (P & 7) == 0) __builtin_amdgcn_s_sleep(48);
+  auto tile = [&](int t, float2(&gc)[16], float2(&gn)[16]) {
+    // the next tile of the run: along the band, else the next band's first tile
+    int nband = band, nbxx = bx, nlim = lim, nrbase = rbase;
+    if (t + 1 < t1) {
+      if (band < nby) {
+        if (bx + 1 < nby) {
+          nbxx = bx + 1;
+        } else if (band + 1 < nby) {
+          nband = band + 1;
+          nbxx = band + 1;
+          nrbase = nband * 64;
+        } else {
+          nband = nby;
+          nbxx = 0;
+          nlim = R;
+          nrbase = M;
+        }
+      } else if (bx + 1 < nbx) {
+        nbxx = bx + 1;
+      } else {
+        nband = band + 1;
+        nbxx = 0;
+        nrbase = rbase + 64;
+      }
+    }
+    load_B(nbxx);
+    const __amdgpu_buffer_rsrc_t rnext = g_rsrc(nbxx, nlim, nrbase);
+    load_G(rnext, gn);
+    __builtin_amdgcn_sched_barrier(0);
+    f32x16 X, Y, Z;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) X[e] = Y[e] = Z[e] = 0.f;
+    f32x4 br[2];
+    br[0] = Vsh[h][cc];
+    br[1] = Vsh[2 + h][cc];
+#pragma unroll
+    for (int i = 0; i < PP; ++i) {
+      const f32x4 ai = aR[i], bi = br[i & 1];
+      if (i + 2 < PP) br[i & 1] = Vsh[2 * (i + 2) + h][cc];
+      X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
+      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[1], bi[1], Y, 0, 0, 0);
+      Z = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0] + ai[1], bi[0] + bi[1], Z, 0, 0, 0);
+      X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[2], bi[2], X, 0, 0, 0);
+      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[3], bi[3], Y, 0, 0, 0);
+      Z = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[2] + ai[3], bi[2] + bi[3], Z, 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const unsigned off = g_lane + (unsigned)((8 * (e >> 2) + (e & 3)) * ld) * 8u;
+      const f32x2 o = {gc[e].x + (X[e] - Y[e]), gc[e].y + (Z[e] - X[e] - Y[e])};
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, o), rcur, off, 0, 2);
+    }
+    __syncthreads();  // every wave is done with this tile's V operands
+    stage_B();
+    __syncthreads();
+    if (nband != band) {
+      load_A(nlim, nrbase);
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+    }
+    band = nband;
+    bx = nbxx;
+    lim = nlim;
+    rbase = nrbase;
+    rcur = rnext;
+  };
+  for (int t = t0; t < t1; t += 2) {
+    tile(t, gA, gB);
+    if (t + 1 >= t1) break;
+    tile(t + 1, gB, gA);
+  }
+}
+
+
 // flush variants for complex64 storage (selected by the autotuner; all give the
 // eager results to FP32 rounding, tests/test_gpu_deferred.py)
 static const char* const kFlushNames[] = {"w32_3m",          "w32_pipe8_3m",   "sym_pipe8_3m",
                                           "sym_pipe8_3m_nt", "sym_pipe4_3m_nt", "up_pipe8_3m_nt",
-                                          "up_pair4_3m_nt",  "up_pair4_3m_nt_x8"};
+                                          "up_pair4_3m_nt",  "up_pair4_3m_nt_x8", "up_band4_3m_nt"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
 constexpr int kFlushDefault = 6;
 static std::atomic<int> g_flush_sel{kFlushDefault};
@@ -406,6 +583,24 @@ int flush_set_variant(int i) {
   return GFO_OK;
 }
 int flush_get_variant() { return g_flush_sel.load(); }
+
+// Workgroups of the persistent band flush: two per compute unit (its occupancy),
+// a multiple of 8 so that every XCD gets the same number of runs.
+static int band_workgroups() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int n = cache[dev].load();
+  if (n == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    n = (2 * cus) / 8 * 8;
+    if (n < 8) n = 8;
+    cache[dev].store(n);
+  }
+  return n;
+}
 
 hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {
   char* w = (char*)st->work;
@@ -485,6 +680,8 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         const int nmb = (g.nmon + 63) / 64, nbx = (int)(g.ld / 64);
         unsigned ntiles = (unsigned)(nb * (nb + 1) / 2 + nmb * nbx);
         const bool xord = fv == 7;
+        // the band form addresses a 64-row G tile with 32-bit byte offsets
+        const bool band = fv == 8 && g.ld * 64 * 8 < ((int64_t)1 << 31);
         if (xord) {
           int mx = 0;
           for (int x = 0; x < 8; ++x) {
@@ -506,7 +703,12 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
           else hipLaunchKernelGGL((k_flush_c64_pair<4, 8>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
         } else if (bound <= 64) {
           if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 16, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
-          else hipLaunchKernelGGL((k_flush_c64_pair<4, 16>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+          else if (band) {
+            const int P = band_workgroups();
+            const int T = nb * (nb + 1) / 2 + nmb * nbx;
+            hipLaunchKernelGGL((k_flush_c64_band<16>), dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G,
+                               nb, (T + P - 1) / P);
+          } else hipLaunchKernelGGL((k_flush_c64_pair<4, 16>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
         } else {
           if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 32, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
           else hipLaunchKernelGGL((k_flush_c64_pair<4, 32>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);

@@ -172,6 +172,42 @@ def test_flush_variants_agree(delay):
     assert len(states) == len(names)
 
 
+
+@pytest.mark.parametrize("ny,nx,n_mon,steps", [(60, 62, 20, 50), (64, 64, 70, 40), (24, 26, 8, 60)])
+def test_band_flush_equals_pair_flush_bitwise(ny, nx, n_mon, steps):
+    """The persistent band flush (33 to 64 pending terms) runs the pair flush's
+    matrix steps in the same order: after the same moves, G (upper triangle and
+    monitor rows, then the mirrored block) is bit for bit that of the pair
+    flush.  Cases: runs of several tiles that cross row bands, a ragged last
+    band, one and two monitor bands (the second ragged), fewer tiles than
+    workgroups."""
+    import torch
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(ny, nx, n_mon=n_mon, dtype="c64", cand_mask=W.MASK_BOTH, tau=1e-6)
+    names = L.flush_variants()
+    old = L.flush_get_variant()
+    out = {}
+    try:
+        for name in ("up_pair4_3m_nt", "up_band4_3m_nt"):
+            L.flush_set_variant(names.index(name))
+            print(f"[case] {ny}x{nx} n_mon {n_mon}: {steps} pending terms, flush {name}", flush=True)
+            job = _job(p, delay=64)
+            job.init()
+            n = job.run_greedy(steps, poll_every=steps)
+            assert 33 <= job.state.pending_calls <= 64, (n, job.state.pending_calls)
+            job.flush()
+            torch.cuda.synchronize()
+            N = p.n
+            G = job.G[:, :N].cpu().numpy()
+            iu = np.triu_indices(N)
+            out[name] = (G[:N][iu].copy(), G[N:].copy(), job.host_state())
+    finally:
+        L.flush_set_variant(old)
+    (ua, ma, sa), (ub, mb, sb) = out["up_pair4_3m_nt"], out["up_band4_3m_nt"]
+    assert np.array_equal(ua, ub) and np.array_equal(ma, mb)
+    for x, y in zip(sa, sb):
+        assert np.array_equal(x, y)
+
 @pytest.mark.parametrize("dtype,delay,poll,form,n_mon", [
     ("c128", 16, 25, 0, 8), ("c64", 64, 32, 0, 8), ("c64", 7, 10, 0, 8), ("c64", 0, 20, 0, 8),
     ("c128", 16, 25, 1, 8), ("c64", 64, 32, 1, 8), ("c64", 7, 10, 1, 8),
