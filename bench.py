@@ -142,28 +142,26 @@ def run_steps(job, target, poll, events=None, refresh_every=0, flush_events=None
 
 
 def flush_triangle(variant):
-    """'sym': tiles on and above the diagonal, stored in place and mirrored;
-    'up': the upper triangle alone is kept current; None: every tile."""
-    v = str(variant)
-    return "sym" if v.startswith("sym") else ("up" if v.startswith("up") else None)
+    """'up': the upper triangle alone is kept current; None: every tile."""
+    return "up" if str(variant).startswith("up") else None
 
 
 def flush_covers_monitors(variant):
-    """The pair-interleaved flush updates the monitor rows in the same kernel."""
-    return str(variant).startswith("up_pair")
+    """The pair-interleaved flushes (pair and band forms) update the monitor rows
+    in the same kernel."""
+    return str(variant).startswith(("up_pair", "up_band"))
 
 
 def flush_alg_bytes(variant, dtype, N, ld, n_mon=0):
     """Minimal HBM bytes of one flush of the N x ld design block.  complex64:
-    symmetric variants read half of it and write all of it (12 N ld) or, keeping
-    only the upper triangle, read and write half of it (8 N ld); plus the
-    monitor rows (16 n_mon ld) for a variant that updates them in the same
-    kernel.  complex128 (FP64 flush of the upper triangle and the monitor rows):
-    16 N ld + 32 n_mon ld."""
+    the whole block read and written (16 N ld) or, keeping only the upper
+    triangle, half of it (8 N ld); plus the monitor rows (16 n_mon ld) for a
+    variant that updates them in the same kernel.  complex128 (FP64 flush of the
+    upper triangle and the monitor rows): 16 N ld + 32 n_mon ld."""
     if dtype != "c64":
         return 16 * N * ld + 32 * n_mon * ld
     mon = 16 * n_mon * ld if flush_covers_monitors(variant) else 0
-    return {"sym": 12, "up": 8, None: 16}[flush_triangle(variant)] * N * ld + mon
+    return {"up": 8, None: 16}[flush_triangle(variant)] * N * ld + mon
 
 
 def flush_mfma_flops(variant, dtype, N, ld, n_mon, terms):

@@ -108,20 +108,22 @@ def tune(job, reps: int = 10, save: bool = True) -> dict:
     return entry
 
 
-def time_flush_variants(job, reps: int = 2) -> list:
+def time_flush_variants(job, reps: int = 2, variants=None) -> list:
     """Mean flush-kernel time (us) of each complex64 flush variant on `job`'s shape
     (deferred job, delay d): each measurement runs d greedy steps, whose last apply
-    ends with the flush; the job restarts when its trajectory ends."""
+    ends with the flush; the job restarts when its trajectory ends.  `variants`:
+    names to time (default all)."""
     import torch
     from .hiprt import EventPool
 
     if not job.delay or job.dtype_name != "c64":
         raise L.GfoError("flush tuning needs a complex64 job in deferred mode")
     names = L.flush_variants()
+    idxs = range(len(names)) if variants is None else [names.index(v) for v in variants]
     old = L.flush_get_variant()
     out = []
     try:
-        for vi in range(len(names)):
+        for vi in idxs:
             L.flush_set_variant(vi)
             ev = EventPool(reps + 1)
             for rep in range(reps + 1):
@@ -151,7 +153,7 @@ def tune_flush(job, reps: int = 2) -> dict:
 
 
 def time_rk_variants(job, rank: int = 16, precision: int = None, reps: int = 4,
-                     warm: int = 2) -> list:
+                     warm: int = 2, variants=None) -> list:
     """Mean time (us) of the matrix-core update of apply_flips_rank_k for each
     variant on `job`'s shape (complex64, eager).  Each measurement applies
     `rank` spaced pixels to material 1 and then back to their material, so the
@@ -177,10 +179,11 @@ def time_rk_variants(job, rank: int = 16, precision: int = None, reps: int = 4,
         job.apply_rank_k(rank, precision=precision, pick_ptr=base)
 
     names = L.rk_variants()
+    idxs = range(len(names)) if variants is None else [names.index(v) for v in variants]
     old = L.rk_get_variant()
     out = []
     try:
-        for vi in range(len(names)):
+        for vi in idxs:
             L.rk_set_variant(vi)
             for i in range(warm):
                 apply(there if i % 2 == 0 else back)
@@ -277,6 +280,10 @@ def apply_cached(job) -> bool:
 
 
 if __name__ == "__main__":
+    # Times the variants of one kernel family on a named workload and prints one
+    # line per variant (mean kernel time from HIP events), e.g.
+    #   python -m paper_2202_05388_amd.autotune --kernel flush --delay 64
+    #   python -m paper_2202_05388_amd.autotune --kernel rank-k --variants pre128_r4
     import argparse
     import sys
 
@@ -286,12 +293,39 @@ if __name__ == "__main__":
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="square128_c64")
+    ap.add_argument("--kernel", choices=["k1", "flush", "rank-k"], default="k1")
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--delay", type=int, default=64, help="pending terms per flush (--kernel flush)")
+    ap.add_argument("--rank", type=int, default=16, help="pixels per move (--kernel rank-k)")
+    ap.add_argument("--bf16", action="store_true", help="BF16 operands (--kernel rank-k)")
+    ap.add_argument("--variants", default=None, help="comma-separated variant names (default all)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy 2 GiB device to device (a kernel of known traffic, to scale counters)")
     args = ap.parse_args()
+    if args.calib_copy:
+        import torch
+        src = torch.empty(1 << 29, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        del src
     p = W.WORKLOADS[args.workload]
-    job = Job(p, device="cuda:0")
-    job.init()
-    e = tune(job, reps=args.reps)
-    for r in sorted(e["all"], key=lambda r: r["us"]):
-        print(f"{r['name']:>16s} {r['us']:9.1f} us {r['gbs']:7.0f} GB/s", flush=True)
-    print(json.dumps({k: v for k, v in e.items() if k != "all"}))
+    sel = args.variants.split(",") if args.variants else None
+    if args.kernel == "k1":
+        job = Job(p, device="cuda:0")
+        job.init()
+        e = tune(job, reps=args.reps, save=False)
+        for r in sorted(e["all"], key=lambda r: r["us"]):
+            print(f"{r['name']:>20s} {r['us']:9.1f} us {r['gbs']:7.0f} GB/s", flush=True)
+        print(json.dumps({k: v for k, v in e.items() if k != "all"}))
+    elif args.kernel == "flush":
+        job = Job(p, device="cuda:0", delay=args.delay)
+        job.init()
+        for r in time_flush_variants(job, reps=args.reps, variants=sel):
+            print(f"{r['name']:>20s} {r['us']:9.1f} us", flush=True)
+    else:
+        job = Job(p, device="cuda:0")
+        job.init()
+        prec = L.GFO_BF16 if args.bf16 else L.GFO_FP32
+        for r in time_rk_variants(job, rank=args.rank, precision=prec, reps=args.reps, variants=sel):
+            gbs = 16 * job.N * job.R / (r["us"] * 1e-6) / 1e9
+            print(f"{r['name']:>20s} {r['us']:9.1f} us {gbs:7.0f} GB/s", flush=True)

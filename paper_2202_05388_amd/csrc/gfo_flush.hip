@@ -113,154 +113,6 @@ __device__ __forceinline__ void tri_tile(int t, int nb, int& r, int& c) {
   c = i + (t - start(i));
 }
 
-// Software-pipelined flush, 32 x 32 outputs per wave and 64 x 64 per workgroup.
-// The CU and V operands come through buffer loads whose range ends at the
-// pending count, so slots past it (and rows past the end, given an offset
-// beyond the range) read as zero without a branch or a select.  Registers hold
-// the operands of H instruction steps (a ring); the wave's G tile is requested
-// after the first H, and each ring entry is reloaded with the operands H steps
-// ahead as soon as its step is consumed.  The products accumulate from zero and
-// G is added in the epilogue: vector loads complete in issue order, so no
-// product waits for the G loads.  A launch runs P steps of two terms (terms
-// past the count read as zeros): GFO_MAX_DELAY / 2, or for the upper-only
-// default the fewest of 8, 16, 32 and 64 that cover the caller's bound on the
-// count.  Byte offsets are 32-bit: the launcher
-// uses this form only when GFO_MAX_DELAY * max(R, ld) * 8 < 2^31.  THREE_MULT
-// as in k_flush_c64_tm.
-//
-// SYM: the design block is symmetric (reciprocity: G_D = G_D^T, and each pending
-// term restricted to it, c_s v_s v_s^T, is symmetric too), so only the tiles on
-// and above the diagonal are computed: a one-dimensional grid of nby (nby + 1) / 2
-// workgroups, tile t in row-major order over that triangle (nby = design blocks).
-// An off-diagonal tile is written twice, in place and mirrored (the mirrored
-// copy replaces the lower tile, whose old values are not read).  Only design
-// columns are covered, and the mirrored rows are design rows.
-//
-// NT: G is read and written with non-temporal (streaming) loads and stores;
-// the operand terms, which every workgroup re-reads, keep the normal policy.
-//
-// MIRROR = false (with SYM): the upper triangle alone is brought up to date;
-// the lower tiles are left as they are (the caller records that the lower
-// triangle is out of date, and readers take design entries from the upper
-// one).  Diagonal tiles are computed whole, their lower halves from the old
-// values.
-template <bool THREE_MULT, int H, bool SYM = false, bool NT = false, bool MIRROR = true,
-          int P = GFO_MAX_DELAY / 2>
-__global__ __launch_bounds__(256) void k_flush_c64_pipe(int M, int R, int64_t ld,
-                                                        const int32_t* __restrict__ count,
-                                                        const float2* __restrict__ CU,
-                                                        const float2* __restrict__ V,
-                                                        float2* __restrict__ G, int nby) {
-  const int K = *count;
-  if (K == 0) return;
-  int bx = blockIdx.x, by = blockIdx.y;
-  if (SYM) tri_tile((int)blockIdx.x, nby, by, bx);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int m0 = by * 64 + (w >> 1) * 32;
-  const int n = bx * 64 + (w & 1) * 32 + (lane & 31);
-  const int h = lane >> 5;
-  const int am = m0 + (lane & 31);
-  static_assert(P % H == 0, "ring depth divides the step count");
-  const __amdgpu_buffer_rsrc_t ra =
-      __builtin_amdgcn_make_buffer_rsrc((void*)CU, (short)0, K * R * 8, kBufferDword3);
-  const __amdgpu_buffer_rsrc_t rb =
-      __builtin_amdgcn_make_buffer_rsrc((void*)V, (short)0, (int)(K * ld * 8), kBufferDword3);
-  const unsigned a_off = am < M ? (unsigned)(h * R + am) * 8u : 0xFFFFFFF0u;
-  const unsigned a_step = am < M ? 2u * (unsigned)R * 8u : 0u;
-  const unsigned b_off = (unsigned)(h * ld + n) * 8u, b_step = 2u * (unsigned)ld * 8u;
-  f32x2 a[H], b[H];
-#pragma unroll
-  for (int i = 0; i < H; ++i) {
-    a[i] = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(ra, a_off + i * a_step, 0, 0));
-    b[i] = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rb, b_off + i * b_step, 0, 0));
-  }
-  __builtin_amdgcn_sched_barrier(0);
-  float2 gv[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    const float2* src = G + (int64_t)(r < M ? r : M - 1) * ld + n;
-    gv[e] = NT ? __builtin_bit_cast(float2, __builtin_nontemporal_load((const f32x2*)src)) : *src;
-  }
-  __builtin_amdgcn_sched_barrier(0);
-  f32x16 X, Y, Z;
-#pragma unroll
-  for (int e = 0; e < 16; ++e) X[e] = Y[e] = Z[e] = 0.f;
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const f32x2 ai = a[i % H], bi = b[i % H];
-    if (i + H < P) {
-      a[i % H] = __builtin_bit_cast(
-          f32x2, __builtin_amdgcn_raw_buffer_load_b64(ra, a_off + (i + H) * a_step, 0, 0));
-      b[i % H] = __builtin_bit_cast(
-          f32x2, __builtin_amdgcn_raw_buffer_load_b64(rb, b_off + (i + H) * b_step, 0, 0));
-    }
-    if (THREE_MULT) {
-      X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
-      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[1], bi[1], Y, 0, 0, 0);
-      Z = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0] + ai[1], bi[0] + bi[1], Z, 0, 0, 0);
-    } else {
-      X = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[0], X, 0, 0, 0);
-      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[0], bi[1], Y, 0, 0, 0);
-      X = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai[1], bi[1], X, 0, 0, 0);
-      Y = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[1], bi[0], Y, 0, 0, 0);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  float2 out[16];
-#pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    out[e] = THREE_MULT ? make_float2(gv[e].x + (X[e] - Y[e]), gv[e].y + (Z[e] - X[e] - Y[e]))
-                        : make_float2(gv[e].x + X[e], gv[e].y + Y[e]);
-    const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    if (r < M) {
-      float2* dst = G + (int64_t)r * ld + n;
-      if (NT)
-        __builtin_nontemporal_store(f32x2{out[e].x, out[e].y}, (f32x2*)dst);
-      else
-        *dst = out[e];
-    }
-  }
-  if (SYM && MIRROR && bx != by) {
-    // Mirrored copy, transposed through LDS (33-float2 rows against bank
-    // conflicts): lane (h, c) holds column n0 + c of the wave's tile, which is
-    // row n0 + c of the lower tile.  After the transpose, store i of lane l
-    // writes 16 bytes of lower row n0 + 4 i + l / 16 at columns
-    // m0 + 2 (l % 16) and m0 + 2 (l % 16) + 1, so each store covers four whole
-    // 256-byte row segments (the untransposed stores cover 16-byte pieces of
-    // 32 rows, which costs a third more time per byte).
-    __shared__ float2 tsh[SYM ? 4 : 1][32][33];
-    float2 (*T)[33] = tsh[SYM ? w : 0];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) T[8 * (e >> 2) + 4 * h + (e & 3)][lane & 31] = out[e];
-    // only this wave reads its tile: its LDS operations complete in order
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int n0 = n - (lane & 31), rr = 2 * (lane & 15), c = m0 + rr;
-    float2 v0[8], v1[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      v0[i] = T[rr][4 * i + (lane >> 4)];
-      v1[i] = T[rr + 1][4 * i + (lane >> 4)];
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int nr = n0 + 4 * i + (lane >> 4);
-      float2* __restrict__ p = G + (int64_t)nr * ld + c;
-      if (nr < M && c + 1 < M) {
-        const f32x4 q = f32x4{v0[i].x, v0[i].y, v1[i].x, v1[i].y};
-        if (NT)
-          __builtin_nontemporal_store(q, (f32x4*)p);
-        else
-          *(f32x4*)p = q;
-      } else if (nr < M && c < M) {
-        *p = v0[i];
-      }
-    }
-  }
-}
-
 // Pair-interleaved copy of the pending terms (complex64): slots 2p and 2p + 1 of
 // index i side by side, CU2[p R + i] = (CU_2p[i], CU_2p+1[i]) and likewise V2
 // with ld, zero past the count, so that one 16-byte load brings a lane the
@@ -287,16 +139,36 @@ __global__ __launch_bounds__(256) void k_flush_pack(int R, int64_t ld,
   }
 }
 
-// The upper-only three-product flush (k_flush_c64_pipe with SYM, NT, no
-// MIRROR) on the pair-interleaved terms: in pair step m, lane (row or column,
-// h) loads pair 2m + h, i.e. slots 4m + 2h and 4m + 2h + 1, and feeds them to
-// two matrix steps (the instruction sums its two k lanes, here slots 4m + 2h'
-// for h' = 0, 1 in the first step and 4m + 2h' + 1 in the second).  Half the
-// operand load instructions for the same bytes.  HP pair steps of operands in
-// registers; PP pair steps per launch (the count rounded up to 4 terms, as in
-// the P-step form).  The default complex64 flush: ring depths of 2 and 8 pair
-// steps measured no faster (8 drops to two waves per SIMD), nor did moving the
-// G tile in 16-byte pieces (adjacent lanes exchanging halves).
+// Upper-triangle flush of the design block, three real products per complex
+// one (as in k_flush_c64_tm), 32 x 32 outputs per wave, 64 x 64 per workgroup.
+//
+// Symmetry: the design block is symmetric (reciprocity: G_D = G_D^T, and each
+// pending term restricted to it, c_s v_s v_s^T, is symmetric too), so only the
+// tiles on and above the diagonal are computed: a one-dimensional grid, tile t
+// in row-major order over that triangle (nby = design blocks).  The upper
+// triangle alone is brought up to date; the lower tiles are left as they are
+// (the caller records that the lower triangle is out of date, and readers take
+// design entries from the upper one).  Diagonal tiles are computed whole,
+// their lower halves from the old values.
+//
+// Operands: pair-interleaved terms (k_flush_pack).  In pair step m, lane (row
+// or column, h) loads pair 2m + h, i.e. slots 4m + 2h and 4m + 2h + 1, and
+// feeds them to two matrix steps (the instruction sums its two k lanes, here
+// slots 4m + 2h' for h' = 0, 1 in the first step and 4m + 2h' + 1 in the
+// second).  The operands come through buffer loads whose range ends at the
+// pending count, so slots past it (and rows past the end, given an offset
+// beyond the range) read as zero without a branch or a select.  HP pair steps
+// of operands in registers (a ring, each entry reloaded HP steps ahead); PP
+// pair steps per launch, the fewest of 4, 8, 16 and 32 (16 to 128 terms) that
+// cover the caller's bound on the count.  Byte offsets are 32-bit: the
+// launcher uses this form only when GFO_MAX_DELAY * max(R, ld) * 8 < 2^31.
+//
+// G is read and written with non-temporal (streaming) loads and stores; the
+// operand terms, which every workgroup re-reads, keep the normal policy.  The
+// products accumulate from zero and G is added in the epilogue.  Ring depths
+// of 2 and 8 pair steps measured no faster (8 drops to two waves per SIMD),
+// nor did moving the G tile in 16-byte pieces (adjacent lanes exchanging
+// halves).
 //
 // The workgroups past the nby (nby + 1) / 2 triangle tiles take the monitor
 // rows [M, R) in 64 x 64 tiles over all ld columns (the FOM monitor's terms
@@ -406,7 +278,13 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 // (rows past the matrix read zero, their stores are dropped).  Odd runs start
 // by sleeping for about half a tile, so that the two workgroups sharing a
 // compute unit reach their epilogues at different times.
-template <int PP>
+//
+// SEGO: the tile list in column segments of 32 tiles (segment j: columns
+// [32 j, 32 j + 32)), inside a segment the triangle rows top to bottom, then the
+// monitor bands, each row left to right.  The runs of one XCD then share a
+// segment's V operands (1 MB at 64 terms), which stay in its L2; the CU operands
+// change at each row, once per at most 32 tiles.
+template <int PP, bool SEGO>
 __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld,
                                                         const int32_t* __restrict__ count,
                                                         const f32x4* __restrict__ CU2,
@@ -471,9 +349,51 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
       gv[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, off, 0, 2));
     }
   };
-  // tile t of the list: row band, column tile, row limit, first row
-  int band, bx, lim, rbase;
-  if (t0 < ntri) {
+  // tiles of segment j: triangle rows, then monitor bands
+  auto seg_tri = [&](int j) {
+    const int s0 = 32 * j;
+    if (s0 >= nby) return 0;
+    const int wd = (s0 + 32 < nby ? s0 + 32 : nby) - s0;
+    return s0 * wd + wd * (wd + 1) / 2;
+  };
+  auto seg_mon = [&](int j) {
+    const int s0 = 32 * j;
+    return nmb * ((s0 + 32 < nbx ? s0 + 32 : nbx) - s0);
+  };
+  // tile t of the list: row band, column tile, row limit, first row (and segment)
+  int band, bx, lim, rbase, seg = 0;
+  if (SEGO) {
+    int u = t0;
+    while (u >= seg_tri(seg) + seg_mon(seg)) {
+      u -= seg_tri(seg) + seg_mon(seg);
+      ++seg;
+    }
+    const int s0 = 32 * seg, nt = seg_tri(seg);
+    if (u < nt) {
+      const int e = s0 + 32 < nby ? s0 + 32 : nby, wd = e - s0;
+      if (u < s0 * wd) {
+        band = u / wd;
+        bx = s0 + u % wd;
+      } else {
+        u -= s0 * wd;
+        band = s0;
+        while (u >= e - band) {
+          u -= e - band;
+          ++band;
+        }
+        bx = band + u;
+      }
+      lim = M;
+      rbase = band * 64;
+    } else {
+      u -= nt;
+      const int wd = (s0 + 32 < nbx ? s0 + 32 : nbx) - s0;
+      band = nby + u / wd;
+      bx = s0 + u % wd;
+      lim = R;
+      rbase = M + (u / wd) * 64;
+    }
+  } else if (t0 < ntri) {
     tri_tile(t0, nby, band, bx);
     lim = M;
     rbase = band * 64;
@@ -495,8 +415,52 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
   if ((run & 1) && (P & 7) == 0) __builtin_amdgcn_s_sleep(48);
   auto tile = [&](int t, float2(&gc)[16], float2(&gn)[16]) {
     // the next tile of the run: along the band, else the next band's first tile
-    int nband = band, nbxx = bx, nlim = lim, nrbase = rbase;
-    if (t + 1 < t1) {
+    int nband = band, nbxx = bx, nlim = lim, nrbase = rbase, nseg = seg;
+    if (SEGO && t + 1 < t1) {
+      const int s0 = 32 * seg;
+      bool next_seg = false;
+      if (band < nby) {
+        const int e = s0 + 32 < nby ? s0 + 32 : nby;
+        if (bx + 1 < e) {
+          nbxx = bx + 1;
+        } else if (band + 1 < e) {
+          nband = band + 1;
+          nbxx = nband > s0 ? nband : s0;
+          nrbase = nband * 64;
+        } else if (nmb > 0) {
+          nband = nby;
+          nbxx = s0;
+          nlim = R;
+          nrbase = M;
+        } else {
+          next_seg = true;
+        }
+      } else {
+        const int f = s0 + 32 < nbx ? s0 + 32 : nbx;
+        if (bx + 1 < f) {
+          nbxx = bx + 1;
+        } else if (band + 1 < nby + nmb) {
+          nband = band + 1;
+          nbxx = s0;
+          nrbase = rbase + 64;
+        } else {
+          next_seg = true;
+        }
+      }
+      if (next_seg) {
+        nseg = seg + 1;
+        nbxx = s0 + 32;
+        if (nbxx < nby) {
+          nband = 0;
+          nlim = M;
+          nrbase = 0;
+        } else {
+          nband = nby;
+          nlim = R;
+          nrbase = M;
+        }
+      }
+    } else if (t + 1 < t1) {
       if (band < nby) {
         if (bx + 1 < nby) {
           nbxx = bx + 1;
@@ -557,6 +521,7 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
     bx = nbxx;
     lim = nlim;
     rbase = nrbase;
+    seg = nseg;
     rcur = rnext;
   };
   for (int t = t0; t < t1; t += 2) {
@@ -569,11 +534,10 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
 
 // flush variants for complex64 storage (selected by the autotuner; all give the
 // eager results to FP32 rounding, tests/test_gpu_deferred.py)
-static const char* const kFlushNames[] = {"w32_3m",          "w32_pipe8_3m",   "sym_pipe8_3m",
-                                          "sym_pipe8_3m_nt", "sym_pipe4_3m_nt", "up_pipe8_3m_nt",
-                                          "up_pair4_3m_nt",  "up_pair4_3m_nt_x8", "up_band4_3m_nt"};
+static const char* const kFlushNames[] = {"w32_3m", "up_pair4_3m_nt", "up_pair4_3m_nt_x8", "up_band4_3m_nt",
+                                          "up_bandseg4_3m_nt"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
-constexpr int kFlushDefault = 6;
+constexpr int kFlushDefault = 4;
 static std::atomic<int> g_flush_sel{kFlushDefault};
 int flush_variant_count() { return kFlushCount; }
 const char* flush_variant_name(int i) { return i >= 0 && i < kFlushCount ? kFlushNames[i] : nullptr; }
@@ -612,7 +576,7 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
     if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
     int fv = flush_get_variant();
     bool monitors_done = false;
-    // the pipelined forms address the term buffers with 32-bit byte offsets
+    // the pair and band forms address the term buffers with 32-bit byte offsets
     const bool off32 = (int64_t)GFO_MAX_DELAY * (g.ld > g.R ? g.ld : g.R) * 8 < ((int64_t)1 << 31);
     if (fv >= 1 && !off32) fv = 0;
     const float2* cu = (const float2*)(w + L.dl_CUs);
@@ -624,49 +588,6 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         hipLaunchKernelGGL((k_flush_c64_tm<1, true>), grid, blk, 0, s, g.N, g.R, g.ld, count, cu, vv, G,
                            0);
         break;
-      case 1:
-        hipLaunchKernelGGL((k_flush_c64_pipe<true, 8>), grid, blk, 0, s, g.N, g.R, g.ld, count,
-                           cu, vv, G, (int)grid.y);
-        break;
-      case 2:
-      case 3:
-      case 4: {
-        // design-block triangle only (symmetric flush)
-        const int nb = (g.N + 63) / 64;
-        const dim3 tri((unsigned)(nb * (nb + 1) / 2));
-        if (fv == 2)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true>), tri, blk, 0, s, g.N, g.R, g.ld,
-                             count, cu, vv, G, nb);
-        else if (fv == 3)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true, true>), tri, blk, 0, s, g.N, g.R,
-                             g.ld, count, cu, vv, G, nb);
-        else
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 4, true, true>), tri, blk, 0, s, g.N, g.R,
-                             g.ld, count, cu, vv, G, nb);
-        break;
-      }
-      case 5: {
-        // upper triangle only; the lower one is out of date from here on.  The
-        // calls since the last flush bound the term count (a refused move
-        // records none), so a partial flush runs fewer steps.
-        const int nb = (g.N + 63) / 64;
-        const dim3 tri((unsigned)(nb * (nb + 1) / 2));
-        const int bound = st->pending_calls;
-        if (bound <= 16)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true, true, false, 8>), tri, blk, 0, s,
-                             g.N, g.R, g.ld, count, cu, vv, G, nb);
-        else if (bound <= 32)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true, true, false, 16>), tri, blk, 0, s,
-                             g.N, g.R, g.ld, count, cu, vv, G, nb);
-        else if (bound <= 64)
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true, true, false, 32>), tri, blk, 0, s,
-                             g.N, g.R, g.ld, count, cu, vv, G, nb);
-        else
-          hipLaunchKernelGGL((k_flush_c64_pipe<true, 8, true, true, false, 64>), tri, blk, 0, s,
-                             g.N, g.R, g.ld, count, cu, vv, G, nb);
-        st->lower_stale = 1;
-        break;
-      }
       default: {
         // upper triangle only, pair-interleaved terms in the unused halves of
         // the term buffers (complex64 slots take 8 of their 16 bytes)
@@ -679,9 +600,9 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         // the triangle's tiles, then the monitor rows' (no separate monitor kernel)
         const int nmb = (g.nmon + 63) / 64, nbx = (int)(g.ld / 64);
         unsigned ntiles = (unsigned)(nb * (nb + 1) / 2 + nmb * nbx);
-        const bool xord = fv == 7;
+        const bool xord = fv == 2;
         // the band form addresses a 64-row G tile with 32-bit byte offsets
-        const bool band = fv == 8 && g.ld * 64 * 8 < ((int64_t)1 << 31);
+        const bool band = (fv == 3 || fv == 4) && g.ld * 64 * 8 < ((int64_t)1 << 31);
         if (xord) {
           int mx = 0;
           for (int x = 0; x < 8; ++x) {
@@ -706,8 +627,12 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
           else if (band) {
             const int P = band_workgroups();
             const int T = nb * (nb + 1) / 2 + nmb * nbx;
-            hipLaunchKernelGGL((k_flush_c64_band<16>), dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G,
-                               nb, (T + P - 1) / P);
+            if (fv == 4)
+              hipLaunchKernelGGL((k_flush_c64_band<16, true>), dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count, c2,
+                                 v2, G, nb, (T + P - 1) / P);
+            else
+              hipLaunchKernelGGL((k_flush_c64_band<16, false>), dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count, c2,
+                                 v2, G, nb, (T + P - 1) / P);
           } else hipLaunchKernelGGL((k_flush_c64_pair<4, 16>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
         } else {
           if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 32, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);

@@ -10,17 +10,16 @@ import bench  # noqa: E402
 
 def test_flush_minimal_bytes_per_variant():
     N, ld, n_mon = 16384, 16384, 64
-    # whole block read and written once; symmetric mirrored: half read, all written;
+    # whole block read and written once (the monitor rows by a kernel of their own);
     # upper triangle alone: half read, half written; complex128: 16-byte entries
-    assert bench.flush_alg_bytes("w32_pipe8_3m", "c64", N, ld) == 16 * N * ld
-    assert bench.flush_alg_bytes("sym_pipe8_3m_nt", "c64", N, ld) == 12 * N * ld
-    assert bench.flush_alg_bytes("up_pipe8_3m_nt", "c64", N, ld, n_mon) == 8 * N * ld
+    assert bench.flush_alg_bytes("w32_3m", "c64", N, ld, n_mon) == 16 * N * ld
     # complex128: the FP64 flush of the upper triangle and the monitor rows
     assert bench.flush_alg_bytes(None, "c128", N, ld, n_mon) == 16 * N * ld + 32 * n_mon * ld
-    # the pair flush also updates the monitor rows (read and written once)
-    assert bench.flush_covers_monitors("up_pair4_3m_nt")
-    assert not bench.flush_covers_monitors("up_pipe8_3m_nt")
-    assert bench.flush_alg_bytes("up_pair4_3m_nt", "c64", N, ld, n_mon) == 8 * N * ld + 16 * n_mon * ld
+    # the pair and band flushes also update the monitor rows (read and written once)
+    for v in ("up_pair4_3m_nt", "up_pair4_3m_nt_x8", "up_band4_3m_nt", "up_bandseg4_3m_nt"):
+        assert bench.flush_covers_monitors(v)
+        assert bench.flush_alg_bytes(v, "c64", N, ld, n_mon) == 8 * N * ld + 16 * n_mon * ld
+    assert not bench.flush_covers_monitors("w32_3m")
 
 
 def test_counter_traffic_lookup():
@@ -40,7 +39,7 @@ def test_flush_flops_count_the_folded_terms_only():
     assert f64 == 6.0 * 4096 * tiles * 64            # three real products of 2 flops each
     assert bench.flush_mfma_flops("up_pair4_3m_nt", "c64", N, ld, n_mon, 20) == f64 * 20 / 64
     # the non-symmetric form computes every tile of the block
-    assert bench.flush_mfma_flops("w32_pipe8_3m", "c64", N, ld, n_mon, 1) == 6.0 * 4096 * nb * (ld // 64)
+    assert bench.flush_mfma_flops("w32_3m", "c64", N, ld, n_mon, 1) == 6.0 * 4096 * nb * (ld // 64)
 
 
 def test_flush_roofline_bound_follows_the_terms():

@@ -175,11 +175,12 @@ def test_flush_variants_agree(delay):
 
 @pytest.mark.parametrize("ny,nx,n_mon,steps", [(60, 62, 20, 50), (64, 64, 70, 40), (24, 26, 8, 60)])
 def test_band_flush_equals_pair_flush_bitwise(ny, nx, n_mon, steps):
-    """The persistent band flush (33 to 64 pending terms) runs the pair flush's
-    matrix steps in the same order: after the same moves, G (upper triangle and
-    monitor rows, then the mirrored block) is bit for bit that of the pair
-    flush.  Cases: runs of several tiles that cross row bands, a ragged last
-    band, one and two monitor bands (the second ragged), fewer tiles than
+    """The persistent band flushes (33 to 64 pending terms; row-major and
+    column-segment tile orders) run the pair flush's matrix steps in the same
+    order: after the same moves, G (upper triangle and monitor rows, then the
+    mirrored block) is bit for bit that of the pair flush.  Cases: runs of
+    several tiles that cross row bands and column segments, a ragged last band,
+    one and two monitor bands (the second ragged), fewer tiles than
     workgroups."""
     import torch
     from paper_2202_05388_amd import _lib as L
@@ -188,7 +189,7 @@ def test_band_flush_equals_pair_flush_bitwise(ny, nx, n_mon, steps):
     old = L.flush_get_variant()
     out = {}
     try:
-        for name in ("up_pair4_3m_nt", "up_band4_3m_nt"):
+        for name in ("up_pair4_3m_nt", "up_band4_3m_nt", "up_bandseg4_3m_nt"):
             L.flush_set_variant(names.index(name))
             print(f"[case] {ny}x{nx} n_mon {n_mon}: {steps} pending terms, flush {name}", flush=True)
             job = _job(p, delay=64)
@@ -203,10 +204,12 @@ def test_band_flush_equals_pair_flush_bitwise(ny, nx, n_mon, steps):
             out[name] = (G[:N][iu].copy(), G[N:].copy(), job.host_state())
     finally:
         L.flush_set_variant(old)
-    (ua, ma, sa), (ub, mb, sb) = out["up_pair4_3m_nt"], out["up_band4_3m_nt"]
-    assert np.array_equal(ua, ub) and np.array_equal(ma, mb)
-    for x, y in zip(sa, sb):
-        assert np.array_equal(x, y)
+    ua, ma, sa = out["up_pair4_3m_nt"]
+    for name in ("up_band4_3m_nt", "up_bandseg4_3m_nt"):
+        ub, mb, sb = out[name]
+        assert np.array_equal(ua, ub) and np.array_equal(ma, mb), name
+        for x, y in zip(sa, sb):
+            assert np.array_equal(x, y), name
 
 @pytest.mark.parametrize("dtype,delay,poll,form,n_mon", [
     ("c128", 16, 25, 0, 8), ("c64", 64, 32, 0, 8), ("c64", 7, 10, 0, 8), ("c64", 0, 20, 0, 8),
@@ -302,7 +305,7 @@ def test_upper_only_flush_then_sync_lower():
     eager.init()
     n_ref = eager.run_greedy(150, poll_every=25)
     Ge, Ee, de, ie = eager.host_state()
-    assert L.flush_variants()[L.flush_get_variant()] == "up_pair4_3m_nt"
+    assert L.flush_variants()[L.flush_get_variant()] == "up_bandseg4_3m_nt"
     job = _job(p, delay=64)
     job.init()
     assert job.state.lower_stale == 1               # init_G0 filled the upper triangle only
