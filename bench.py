@@ -37,22 +37,46 @@ FETCH_SCALE = 2097152.0 / 1048599.75
 WRITE_SCALE = 1.0
 PMC_TRAFFIC = [
     {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_rank1.hip", "sha256": "ce1af5cc48984ca588038afcb039097a02bee46cd883c6fd06b0ef5a615e2c8d", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053784.0, "write_kib": 2105344.0},
-    # the flush of up_pair4_3m_nt is two kernels (k_flush_pack, then k_flush_c64_pair, which also
-    # updates the monitor rows): their sum
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "515a365d7ed52b926e1719505684a52a05bce9063db027bd574a93ede389ffd0", "workload": "square128_c64", "variant": "up_pair4_3m_nt", "fetch_kib": 826184.56 + 8221.0, "write_kib": 1060864.0 + 16416.0},
+    # complex64 flush records: one per term bucket (the launcher's kernel for up to 16, 32, 64
+    # or 128 pending terms) of the default variant, each taken on full flushes: the tile
+    # kernel, then the pack kernel
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "1a60e809185c92df6351811eece726586e982d71df1ee23e5a9de2e3fb35443f", "workload": "square128_c64", "variant": "up_bandseg4_3m_nt", "bucket": 16, "tile_kernel": "k_flush_c64_pair<4, 4, true>", "fetch_kib": 539644.0 + 2059.0, "write_kib": 1060896.0 + 4104.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "1a60e809185c92df6351811eece726586e982d71df1ee23e5a9de2e3fb35443f", "workload": "square128_c64", "variant": "up_bandseg4_3m_nt", "bucket": 32, "tile_kernel": "k_flush_c64_pair<4, 8, true>", "fetch_kib": 549316.0 + 4111.0, "write_kib": 1060867.0 + 8208.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "1a60e809185c92df6351811eece726586e982d71df1ee23e5a9de2e3fb35443f", "workload": "square128_c64", "variant": "up_bandseg4_3m_nt", "bucket": 64, "tile_kernel": "k_flush_c64_band<16, true>", "fetch_kib": 579270.0 + 8215.5, "write_kib": 1060873.0 + 16416.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "1a60e809185c92df6351811eece726586e982d71df1ee23e5a9de2e3fb35443f", "workload": "square128_c64", "variant": "up_bandseg4_3m_nt", "bucket": 128, "tile_kernel": "k_flush_c64_pair<4, 32, true>", "fetch_kib": 610541.5 + 16423.5, "write_kib": 1060864.0 + 32832.0},
 ]
 
 
-def pmc_traffic(kernel, workload, variant):
+def pmc_traffic(kernel, workload, variant, bucket=None):
     import hashlib
     for rec in PMC_TRAFFIC:
         if (rec["kernel"], rec["workload"], rec["variant"]) != (kernel, workload, variant):
+            continue
+        if rec.get("bucket") != bucket:
             continue
         with open(os.path.join(ROOT, rec["source"]), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
                 return None
         return 1024.0 * (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE)
     return None
+
+
+def flush_bucket(terms):
+    """Term bucket of a complex64 flush: the launcher runs one kernel for up to
+    16, 32, 64 and 128 pending terms."""
+    for b in (16, 32, 64):
+        if terms <= b:
+            return b
+    return 128
+
+
+def flush_traffic(workload, variant, terms):
+    """Mean counter traffic per flush over flushes folding `terms` terms each,
+    from the bucket records; None if a bucket has no current record."""
+    if not terms:
+        return None
+    vals = [pmc_traffic("k_flush_c64", workload, variant, flush_bucket(t)) for t in terms]
+    return None if any(v is None for v in vals) else sum(vals) / len(vals)
 
 
 def _log(msg):
@@ -894,13 +918,11 @@ def main():
         head_ms = d["ms_per_step"]
         kind = "FP32" if problem.dtype == "c64" else "FP64"
         roofline = dict(d["flush_roofline"])
-        # the counters were taken on flushes of a full term buffer: they stand
-        # for this window only if its flushes ran the same term bucket
-        full = all(2 * r > d["delay"] for r in d["flush_terms"])
+        # counters per term bucket, averaged over the flushes of the window
         roofline.update(kernel=f"flush of the deferred updates, {kind} MFMA, variant "
                                f"{d['flush_variant']}",
-                        traffic=pmc_traffic("k_flush_c64", problem.name, d["flush_variant"])
-                        if full else None,
+                        traffic=flush_traffic(problem.name, d["flush_variant"], d["flush_terms"])
+                        if problem.dtype == "c64" else None,
                         traffic_unit="bytes/launch")
         pix = d["last_run_pixels"]
     else:

@@ -600,7 +600,10 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         // the triangle's tiles, then the monitor rows' (no separate monitor kernel)
         const int nmb = (g.nmon + 63) / 64, nbx = (int)(g.ld / 64);
         unsigned ntiles = (unsigned)(nb * (nb + 1) / 2 + nmb * nbx);
-        const bool xord = fv == 2;
+        // the default keeps every operand re-read in the XCD's L2: the band form
+        // (column segments) for 33 to 64 terms, the XCD tile order otherwise (at
+        // 128 terms: 1.05x the minimal HBM traffic instead of 1.8x, 2 % slower)
+        const bool xord = fv == 2 || fv == 4;
         // the band form addresses a 64-row G tile with 32-bit byte offsets
         const bool band = (fv == 3 || fv == 4) && g.ld * 64 * 8 < ((int64_t)1 << 31);
         if (xord) {
@@ -623,8 +626,7 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
           if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 8, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
           else hipLaunchKernelGGL((k_flush_c64_pair<4, 8>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
         } else if (bound <= 64) {
-          if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 16, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
-          else if (band) {
+          if (band) {
             const int P = band_workgroups();
             const int T = nb * (nb + 1) / 2 + nmb * nbx;
             if (fv == 4)
@@ -633,7 +635,11 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
             else
               hipLaunchKernelGGL((k_flush_c64_band<16, false>), dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count, c2,
                                  v2, G, nb, (T + P - 1) / P);
-          } else hipLaunchKernelGGL((k_flush_c64_pair<4, 16>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+          } else if (xord) {
+            hipLaunchKernelGGL((k_flush_c64_pair<4, 16, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+          } else {
+            hipLaunchKernelGGL((k_flush_c64_pair<4, 16>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+          }
         } else {
           if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 32, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
           else hipLaunchKernelGGL((k_flush_c64_pair<4, 32>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
