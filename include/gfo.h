@@ -77,7 +77,8 @@ typedef struct {
 
 /* Caller-owned device buffers of one optimisation job. */
 typedef struct {
-  void* G; int64_t ldG;         /* R x N, ldG >= N and a multiple of 64 */
+  void* G; int64_t ldG;         /* R x N, ldG >= N and a multiple of 64 (row stride; with
+                                   packed, see below), gfo_g_elems() entries */
   void* E;                      /* R */
   double* diag64;               /* 2*N doubles */
   uint8_t* eps_idx;             /* N */
@@ -95,6 +96,15 @@ typedef struct {
                                    set 0, or 1 to keep the upper triangle alone in eager
                                    mode too: the rank-1 update then skips the tiles below
                                    the diagonal, about half its HBM traffic */
+  int32_t packed;               /* 0: dense R x ldG rows.  1: band-packed upper triangle of the
+                                   design block (it is symmetric: Sec. II, reciprocity), about
+                                   half the entries: design rows in bands of 64, the rows of
+                                   band b holding columns [64 b, ldG) only and ldG - 64 b
+                                   entries apart, band b starting at entry
+                                   64 (b ldG - 32 b (b - 1)); then the N_m monitor rows, ldG
+                                   apart.  Needs deferred updates (delay >= 1; else every call
+                                   returns GFO_EINVAL); apply_flips_rank_k and gfo_sync_lower
+                                   refuse it (GFO_EINVAL).  Set before init_G0, kept after */
 } gfo_state;
 
 /* One selected move.  pixel = -1 is the sentinel "no move improves the FOM". */
@@ -117,6 +127,12 @@ int gfo_workspace_size(const gfo_problem* prob, int64_t ldG, int32_t kmax, size_
 
 /* Smallest valid leading dimension of G for this problem (N rounded up to 64). */
 int64_t gfo_min_ld(const gfo_problem* prob);
+
+/* Entries of G (of the problem's storage type) that a state with leading
+ * dimension ldG (0: gfo_min_ld) needs: R x ldG dense (packed = 0), or the
+ * band-packed design triangle and the monitor rows (packed = 1, see
+ * gfo_state.packed).  Host only; GFO_EINVAL on a bad ldG or packed value. */
+int gfo_g_elems(const gfo_problem* prob, int64_t ldG, int32_t packed, int64_t* h_elems);
 
 /* Byte offset, inside the workspace, of the FP64 score array that
  * score_candidates fills: N x n_eps values in (pixel, eps_idx) row-major
@@ -228,7 +244,7 @@ int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
  * applied (call gfo_flush first for a current matrix).  In deferred mode
  * init_G0 and refresh_G (they write the upper triangle only), the complex128
  * flush and the complex64 upper-only flush set the flag.  Asynchronous on
- * `stream`. */
+ * `stream`.  GFO_EINVAL for band-packed storage (no lower triangle is stored). */
 int gfo_sync_lower(const gfo_problem* prob, gfo_state* st, hipStream_t stream);
 
 /* gfo_greedy_steps - n_steps greedy moves (paper Sec. II: score every
@@ -323,7 +339,8 @@ int gfo_choose_eps_greedy(const gfo_pick* d_top, int32_t k, double eps, double u
  *   M = (I - B_S G[S,S])^-1 B_S  (k x k, FP64, B_S = diag(alpha)),
  *   G += G[:, S] M G[S, :],  E += G[:, S] M E[S],  diag64 updated in FP64.
  * The R x N update is a rank-k product on the matrix cores with FP32 or BF16
- * inputs (gemm_precision) and FP32 accumulation; requires GFO_C64 storage.
+ * inputs (gemm_precision) and FP32 accumulation; requires GFO_C64 storage,
+ * dense (GFO_EINVAL when state.packed).
  * Sentinel records (pixel < 0) are skipped; 1 <= k <= GFO_MAX_RANK_K. */
 int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_picks,
                        int32_t k, int32_t gemm_precision, hipStream_t stream);

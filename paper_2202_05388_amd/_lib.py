@@ -23,7 +23,7 @@ GFO_MAX_DELAY = 128
 GFO_STATIC_SCRATCH_BYTES = 8 << 20
 
 # every entry point that include/gfo.h declares
-EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "gfo_scores_offset",
+EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "gfo_g_elems", "gfo_scores_offset",
            "init_G0", "score_candidates", "apply_flip", "apply_flips_rank_k", "refresh_G",
            "gfo_k1_variant_count", "gfo_k1_variant_name", "gfo_k1_set_variant",
            "gfo_k1_get_variant", "gfo_time_next_k1", "gfo_flush", "gfo_flush_variant_count",
@@ -47,7 +47,8 @@ class State(C.Structure):
                 ("diag64", C.c_void_p), ("eps_idx", C.c_void_p), ("flips", C.c_void_p),
                 ("flip_cap", C.c_int32), ("n_flips", C.c_void_p), ("kmax", C.c_int32),
                 ("work", C.c_void_p), ("work_bytes", C.c_size_t), ("status", C.c_void_p),
-                ("delay", C.c_int32), ("pending_calls", C.c_int32), ("lower_stale", C.c_int32)]
+                ("delay", C.c_int32), ("pending_calls", C.c_int32), ("lower_stale", C.c_int32),
+                ("packed", C.c_int32)]
 
 
 class Pick(C.Structure):
@@ -83,6 +84,7 @@ def lib():
     L.gfo_workspace_size.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
     L.gfo_min_ld.argtypes = [P]
     L.gfo_min_ld.restype = C.c_int64
+    L.gfo_g_elems.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(C.c_int64)]
     L.gfo_scores_offset.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
     L.init_G0.argtypes = [P, S, V]
     L.score_candidates.argtypes = [P, S, C.c_uint32, C.c_double, C.c_int32, C.c_int32, V, V]
@@ -144,6 +146,13 @@ def min_ld(prob: Problem) -> int:
     if ld < 0:
         raise GfoError("invalid problem")
     return ld
+
+
+def g_elems(prob: Problem, ld: int = 0, packed: bool = False) -> int:
+    """Entries of G for this problem: R x ld dense, or band-packed."""
+    out = C.c_int64(0)
+    check(lib().gfo_g_elems(C.byref(prob), ld, int(bool(packed)), C.byref(out)), "gfo_g_elems")
+    return out.value
 
 
 def init_G0(prob: Problem, st: State, stream: int) -> None:

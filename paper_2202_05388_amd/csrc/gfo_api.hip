@@ -52,12 +52,15 @@ Geo make_geo(const gfo_problem* p, int64_t ld) {
   g.bg_idx = find_bg(p);
   g.m0 = p->fom_monitor;
   g.dtype = p->dtype;
+  g.mon_base = (int64_t)g.N * ld;
   return g;
 }
 
 Geo make_geo(const gfo_problem* p, const gfo_state* st) {
   Geo g = make_geo(p, st->ldG);
-  g.upper = st->delay > 0 || st->lower_stale ? 1 : 0;
+  g.packed = st->packed;
+  g.upper = st->packed || st->delay > 0 || st->lower_stale ? 1 : 0;
+  g.mon_base = g_elems(g.packed, g.N, 0, g.ld);
   return g;
 }
 
@@ -118,6 +121,9 @@ int validate_state_fields(const gfo_problem* p, const gfo_state* st) {
   if (st->flip_cap < 0 || (st->flip_cap > 0 && !st->flips) || st->kmax < 0) return GFO_EINVAL;
   if (st->delay < 0 || st->delay > GFO_MAX_DELAY || st->pending_calls < 0) return GFO_EINVAL;
   if (st->lower_stale != 0 && st->lower_stale != 1) return GFO_EINVAL;
+  // band-packed storage holds the upper triangle alone: deferred updates only
+  if (st->packed != 0 && st->packed != 1) return GFO_EINVAL;
+  if (st->packed && st->delay == 0) return GFO_EINVAL;
   if (st->ldG < min_ld(p) || st->ldG % 64 != 0) return GFO_EINVAL;
   if (((uintptr_t)st->G & 15) != 0) return GFO_EINVAL;
   return GFO_OK;
@@ -186,6 +192,15 @@ int gfo_scores_offset(const gfo_problem* prob, int64_t ldG, int32_t kmax, size_t
 int64_t gfo_min_ld(const gfo_problem* prob) {
   if (validate_problem(prob)) return -1;
   return min_ld(prob);
+}
+
+int gfo_g_elems(const gfo_problem* prob, int64_t ldG, int32_t packed, int64_t* h_elems) {
+  int rc = validate_problem(prob);
+  if (rc) return rc;
+  const int64_t ld = query_ld(prob, ldG);
+  if (!h_elems || ld < 0 || (packed != 0 && packed != 1)) return GFO_EINVAL;
+  *h_elems = g_elems(packed, (int64_t)prob->ny * prob->nx, prob->n_mon, ld);
+  return GFO_OK;
 }
 
 int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
@@ -259,6 +274,7 @@ int gfo_sync_lower(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   if (rc) return rc;
   Layout L;
   if ((rc = validate_state(prob, st, &L))) return rc;
+  if (st->packed) return GFO_EINVAL;   // no lower triangle is stored
   if (!st->lower_stale) return GFO_OK;
   const Geo g = make_geo(prob, st);
   if (launch_sync_lower(g, st, stream) != hipSuccess) return GFO_EHIP;
@@ -401,6 +417,7 @@ int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d
   if (!d_picks || k < 1 || k > GFO_MAX_RANK_K || prob->dtype != GFO_C64 ||
       (gemm_precision != GFO_FP32 && gemm_precision != GFO_BF16))
     return GFO_EINVAL;
+  if (st->packed) return GFO_EINVAL;   // the rank-k update streams whole rows
   const Geo g = make_geo(prob, st);
   if (st->delay > 0 && st->pending_calls > 0) {
     if (launch_flush(g, st, L, stream) != hipSuccess) return GFO_EHIP;

@@ -168,7 +168,7 @@ __device__ __forceinline__ void gather_finish(const Geo& g, const gfo_pick pk,
   const double2 dj = diag64[jc];
   const T Ej = E[jc];
   T base = St<T>::from_d(make_double2(0.0, 0.0));
-  if (w == 0) base = mon ? G[i * g.ld + jc] : G[g_at(g, jc, q)];
+  if (w == 0) base = mon ? G[g_off(g, i, jc)] : G[g_at(g, jc, q)];
   if (threadIdx.x < cnt) yj[0][threadIdx.x] = Vs[(int64_t)threadIdx.x * g.ld + jc];
   if (threadIdx.x >= 64 && threadIdx.x - 64 < cnt)
     yj[1][threadIdx.x - 64] = CUs[(int64_t)(threadIdx.x - 64) * g.R + jc];
@@ -285,7 +285,7 @@ __device__ __forceinline__ void elementwise_move(const Geo& g, const Snap& sn, i
     }
   }
   if (q >= g.ld) return;
-  T* p = G + (int64_t)(g.N + g.m0) * g.ld + q;
+  T* p = G + g_off(g, g.N + g.m0, q);
   *p = axpy_st<T>(*p, cu[g.N + g.m0], St<T>::to_d(v[q]));
 }
 
@@ -351,7 +351,7 @@ __device__ __forceinline__ void mon_score_body(
   double2 dq = diag64[qc];
   int cur = eps_idx[qc];
   const T cuq = cu[qc], vq = v[ql], emq = emon[qm];
-  T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
+  T* __restrict__ grow = G + g_off(g, g.N + g.m0, 0);
   T grow_q = grow[ql];
   const T em0 = emon[g.m0], e0 = E[g.N + g.m0], cum0 = cu[g.N + g.m0];
   __builtin_amdgcn_sched_barrier(0);
@@ -450,7 +450,7 @@ __device__ __forceinline__ void move_body(
   const GatherElem el = gather_elem(g);
   const int64_t e = el.e, i = el.i, q = el.q;
   const bool mon = el.mon, live = el.live;
-  T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
+  T* __restrict__ grow = G + g_off(g, g.N + g.m0, 0);
   // loads that need nothing else: the summaries first, then the lane's operand
   // of every slot of its wave's terms (those past the term count, not known
   // yet, are not used), then this lane's own values (its pixel, or its
@@ -490,7 +490,7 @@ __device__ __forceinline__ void move_body(
     gm0j = St<T>::from_d(sp.gm0_new);
   }
   T base = zero;
-  if (w == 0) base = mon ? (e == g.m0 ? gm0j : G[i * g.ld + jc]) : G[g_at(g, jc, q)];
+  if (w == 0) base = mon ? (e == g.m0 ? gm0j : G[g_off(g, i, jc)]) : G[g_at(g, jc, q)];
   if (threadIdx.x < cnt) yj[0][threadIdx.x] = Vs[(int64_t)threadIdx.x * g.ld + jc];
   if (threadIdx.x >= 64 && threadIdx.x - 64 < cnt)
     yj[1][threadIdx.x - 64] = CUs[(int64_t)(threadIdx.x - 64) * g.R + jc];
@@ -647,7 +647,7 @@ __device__ __forceinline__ void move_finish_body(const Geo& g, const Snap* __res
       E[sn.j] = St<T>::from_d(sn.Ej_new);
       diag64[sn.j] = sn.dj_new;
       eps_idx[sn.j] = (uint8_t)sn.e_new;
-      G[(int64_t)(g.N + g.m0) * g.ld + sn.j] = St<T>::from_d(sn.gm0_new);
+      G[g_off(g, g.N + g.m0, sn.j)] = St<T>::from_d(sn.gm0_new);
     }
   }
 }

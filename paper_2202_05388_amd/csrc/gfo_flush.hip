@@ -139,6 +139,20 @@ __global__ __launch_bounds__(256) void k_flush_pack(int R, int64_t ld,
   }
 }
 
+// Base offset and row stride of the 64-row tile at rows [rbase, rbase + 64),
+// columns [64 bx, 64 bx + 64): a design tile (rbase < M, rbase a multiple of
+// 64) in dense or band-packed storage (g_off), or a monitor tile (rows from
+// M on, ld apart after mon_base).
+struct TileAt {
+  int64_t base, stride;
+};
+__device__ __forceinline__ TileAt tile_at(int packed, int M, int64_t ld, int64_t mon_base, int rbase,
+                                          int bx) {
+  if (rbase >= M) return TileAt{mon_base + (int64_t)(rbase - M) * ld + 64 * (int64_t)bx, ld};
+  const int64_t b = rbase >> 6;
+  return TileAt{g_band_start(packed, ld, b) + 64 * (bx - (packed ? b : 0)), g_band_stride(packed, ld, b)};
+}
+
 // Upper-triangle flush of the design block, three real products per complex
 // one (as in k_flush_c64_tm), 32 x 32 outputs per wave, 64 x 64 per workgroup.
 //
@@ -180,7 +194,8 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
                                                         const int32_t* __restrict__ count,
                                                         const f32x4* __restrict__ CU2,
                                                         const f32x4* __restrict__ V2,
-                                                        float2* __restrict__ G, int nby) {
+                                                        float2* __restrict__ G, int nby,
+                                                        int packed, int64_t mon_base) {
   const int K = *count;
   if (K == 0) return;
   const int ntri = nby * (nby + 1) / 2;
@@ -223,11 +238,14 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
     b[i] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb, b_off + i * b_step, 0, 0));
   }
   __builtin_amdgcn_sched_barrier(0);
+  // the tile in G (dense or band-packed design rows, monitor rows)
+  const TileAt ta = tile_at(packed, M, ld, mon_base, rbase, bx);
+  float2* __restrict__ Gt = G + ta.base + (n - bx * 64);
   float2 gv[16];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
-    const float2* src = G + (int64_t)(r < lim ? r : lim - 1) * ld + n;
+    const float2* src = Gt + (int64_t)((r < lim ? r : lim - 1) - rbase) * ta.stride;
     gv[e] = __builtin_bit_cast(float2, __builtin_nontemporal_load((const f32x2*)src));
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -256,7 +274,7 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
     const int r = m0 + 8 * (e >> 2) + 4 * h + (e & 3);
     if (r < lim) {
       const float2 out = make_float2(gv[e].x + (X[e] - Y[e]), gv[e].y + (Z[e] - X[e] - Y[e]));
-      __builtin_nontemporal_store(f32x2{out.x, out.y}, (f32x2*)(G + (int64_t)r * ld + n));
+      __builtin_nontemporal_store(f32x2{out.x, out.y}, (f32x2*)(Gt + (int64_t)(r - rbase) * ta.stride));
     }
   }
 }
@@ -289,7 +307,8 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
                                                         const int32_t* __restrict__ count,
                                                         const f32x4* __restrict__ CU2,
                                                         const f32x4* __restrict__ V2,
-                                                        float2* __restrict__ G, int nby, int chunk) {
+                                                        float2* __restrict__ G, int nby, int chunk,
+                                                        int packed, int64_t mon_base) {
   const int K = *count;
   if (K == 0) return;
   const int ntri = nby * (nby + 1) / 2;
@@ -310,7 +329,7 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
       __builtin_amdgcn_make_buffer_rsrc((void*)V2, (short)0, (int)(np * ld * 16), kBufferDword3);
   const int q = (w >> 1) * 32 + (lane & 31);   // row of the band (CU operand)
   const int cc = (w & 1) * 32 + (lane & 31);  // column of the tile (V operand)
-  const unsigned g_lane = (unsigned)(((w >> 1) * 32 + 4 * h) * ld + cc) * 8u;
+  const int lrow = (w >> 1) * 32 + 4 * h;     // the lane's first row within a tile
   f32x4 aR[PP];
   auto load_A = [&](int lim, int rbase) {
     const int am = rbase + q;
@@ -337,17 +356,23 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
       Vsh[e >> 6][e & 63] = bs[j];
     }
   };
-  auto g_rsrc = [&](int bx, int lim, int rbase) {
+  // the tile's G through a buffer resource whose range ends at its last row
+  // (dense or band-packed design rows: tile_at gives the row stride)
+  auto g_rsrc = [&](int bx, int lim, int rbase, int64_t& stride) {
     const int rows = lim - rbase < 64 ? lim - rbase : 64;
-    return __builtin_amdgcn_make_buffer_rsrc((void*)(G + (int64_t)rbase * ld + bx * 64), (short)0,
-                                             (int)((int64_t)rows * ld * 8), kBufferDword3);
+    const TileAt ta = tile_at(packed, M, ld, mon_base, rbase, bx);
+    stride = ta.stride;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(G + ta.base), (short)0,
+                                             (int)((int64_t)rows * ta.stride * 8), kBufferDword3);
   };
-  auto load_G = [&](__amdgpu_buffer_rsrc_t rg, float2(&gv)[16]) {
+  // byte offsets: the lane's (vector) and element e's row (uniform, a scalar offset)
+  auto lane_off = [&](int64_t stride) { return (unsigned)((int64_t)lrow * stride + cc) * 8u; };
+  auto row_off = [&](int64_t stride, int e) { return (int)((int64_t)(8 * (e >> 2) + (e & 3)) * stride * 8); };
+  auto load_G = [&](__amdgpu_buffer_rsrc_t rg, int64_t stride, float2(&gv)[16]) {
+    const unsigned vo = lane_off(stride);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const unsigned off = g_lane + (unsigned)((8 * (e >> 2) + (e & 3)) * ld) * 8u;
-      gv[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, off, 0, 2));
-    }
+    for (int e = 0; e < 16; ++e)
+      gv[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, vo, row_off(stride, e), 2));
   };
   // tiles of segment j: triangle rows, then monitor bands
   auto seg_tri = [&](int j) {
@@ -407,8 +432,9 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
   float2 gA[16], gB[16];
   load_A(lim, rbase);
   load_B(bx);
-  __amdgpu_buffer_rsrc_t rcur = g_rsrc(bx, lim, rbase);
-  load_G(rcur, gA);
+  int64_t scur;
+  __amdgpu_buffer_rsrc_t rcur = g_rsrc(bx, lim, rbase, scur);
+  load_G(rcur, scur, gA);
   stage_B();
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the operands are in registers on every path
   __syncthreads();
@@ -483,8 +509,9 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
       }
     }
     load_B(nbxx);
-    const __amdgpu_buffer_rsrc_t rnext = g_rsrc(nbxx, nlim, nrbase);
-    load_G(rnext, gn);
+    int64_t snext;
+    const __amdgpu_buffer_rsrc_t rnext = g_rsrc(nbxx, nlim, nrbase, snext);
+    load_G(rnext, snext, gn);
     __builtin_amdgcn_sched_barrier(0);
     f32x16 X, Y, Z;
 #pragma unroll
@@ -504,11 +531,11 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
       Z = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[2] + ai[3], bi[2] + bi[3], Z, 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
     }
+    const unsigned vo = lane_off(scur);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      const unsigned off = g_lane + (unsigned)((8 * (e >> 2) + (e & 3)) * ld) * 8u;
       const f32x2 o = {gc[e].x + (X[e] - Y[e]), gc[e].y + (Z[e] - X[e] - Y[e])};
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, o), rcur, off, 0, 2);
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, o), rcur, vo, row_off(scur, e), 2);
     }
     __syncthreads();  // every wave is done with this tile's V operands
     stage_B();
@@ -523,6 +550,7 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
     rbase = nrbase;
     seg = nseg;
     rcur = rnext;
+    scur = snext;
   };
   for (int t = t0; t < t1; t += 2) {
     tile(t, gA, gB);
@@ -579,6 +607,12 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
     // the pair and band forms address the term buffers with 32-bit byte offsets
     const bool off32 = (int64_t)GFO_MAX_DELAY * (g.ld > g.R ? g.ld : g.R) * 8 < ((int64_t)1 << 31);
     if (fv >= 1 && !off32) fv = 0;
+    // band-packed storage: the pair and band forms only (they address tiles
+    // through tile_at); sizes beyond their 32-bit offsets are refused
+    if (g.packed) {
+      if (!off32) return hipErrorInvalidValue;
+      if (fv == 0) fv = 1;
+    }
     const float2* cu = (const float2*)(w + L.dl_CUs);
     const float2* vv = (const float2*)(w + L.dl_Vs);
     float2* G = (float2*)st->G;
@@ -620,29 +654,29 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         const f32x4* c2 = (const f32x4*)cu2;
         const f32x4* v2 = (const f32x4*)vv2;
         if (bound <= 16) {
-          if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 4, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
-          else hipLaunchKernelGGL((k_flush_c64_pair<4, 4>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+          if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 4, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb, g.packed, g.mon_base);
+          else hipLaunchKernelGGL((k_flush_c64_pair<4, 4>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb, g.packed, g.mon_base);
         } else if (bound <= 32) {
-          if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 8, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
-          else hipLaunchKernelGGL((k_flush_c64_pair<4, 8>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+          if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 8, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb, g.packed, g.mon_base);
+          else hipLaunchKernelGGL((k_flush_c64_pair<4, 8>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb, g.packed, g.mon_base);
         } else if (bound <= 64) {
           if (band) {
             const int P = band_workgroups();
             const int T = nb * (nb + 1) / 2 + nmb * nbx;
             if (fv == 4)
               hipLaunchKernelGGL((k_flush_c64_band<16, true>), dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count, c2,
-                                 v2, G, nb, (T + P - 1) / P);
+                                 v2, G, nb, (T + P - 1) / P, g.packed, g.mon_base);
             else
               hipLaunchKernelGGL((k_flush_c64_band<16, false>), dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count, c2,
-                                 v2, G, nb, (T + P - 1) / P);
+                                 v2, G, nb, (T + P - 1) / P, g.packed, g.mon_base);
           } else if (xord) {
-            hipLaunchKernelGGL((k_flush_c64_pair<4, 16, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+            hipLaunchKernelGGL((k_flush_c64_pair<4, 16, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb, g.packed, g.mon_base);
           } else {
-            hipLaunchKernelGGL((k_flush_c64_pair<4, 16>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+            hipLaunchKernelGGL((k_flush_c64_pair<4, 16>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb, g.packed, g.mon_base);
           }
         } else {
-          if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 32, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
-          else hipLaunchKernelGGL((k_flush_c64_pair<4, 32>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb);
+          if (xord) hipLaunchKernelGGL((k_flush_c64_pair<4, 32, true>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb, g.packed, g.mon_base);
+          else hipLaunchKernelGGL((k_flush_c64_pair<4, 32>), tri, blk, 0, s, g.N, g.R, g.ld, count, c2, v2, G, nb, g.packed, g.mon_base);
         }
         st->lower_stale = 1;
         break;

@@ -74,7 +74,7 @@ __global__ void k_fill_design(Geo g, T* __restrict__ G, const double2* __restric
       d[v] = make_double2(0.0, 0.0);
       if (q0 + v < g.N) d[v] = table[abs(iyp - iyq[v]) * g.nx + abs(ixp - ixq[v])];
     }
-    T* dst = G + (int64_t)p * g.ld + q0;
+    T* dst = G + g_off(g, p, q0);   // packed: q0 >= 64 (p / 64) here (upper)
     if constexpr (VN == 2) {
       const float2 a = St<T>::from_d(d[0]), b = St<T>::from_d(d[1]);
       __builtin_nontemporal_store(f32x4{a.x, a.y, b.x, b.y}, (f32x4*)dst);
@@ -100,7 +100,7 @@ __global__ void k_fill_monitors(Geo g, T* __restrict__ G, const double* __restri
     } else {
       out = St<T>::from_d(make_double2(0.0, 0.0));
     }
-    G[(int64_t)(g.N + m) * g.ld + q] = out;
+    G[g_off(g, g.N + m, q)] = out;
   }
 }
 

@@ -22,12 +22,42 @@ struct Geo {
   // column).  The block is symmetric (reciprocity of the medium), and in
   // deferred mode a flush may bring only the upper triangle up to date.
   int upper;
+  // 1: band-packed storage of the design block's upper triangle (see g_off);
+  // implies upper.  mon_base: offset of the first monitor row.
+  int packed;
+  int64_t mon_base;
 };
+
+// Band-packed storage: design rows in bands of 64; the rows of band b store the
+// columns [64 b, ld) only (the tiles on and above the diagonal), band b starts
+// at 64 (b ld - 32 b (b - 1)) and its rows are ld - 64 b apart; every row
+// starts on a 64-entry boundary.  The monitor rows follow, ld apart.  Dense
+// storage: row r at r ld.
+__host__ __device__ __forceinline__ int64_t g_band_start(int packed, int64_t ld, int64_t b) {
+  return packed ? 64 * (b * ld - 32 * b * (b - 1)) : 64 * b * ld;
+}
+__host__ __device__ __forceinline__ int64_t g_band_stride(int packed, int64_t ld, int64_t b) {
+  return packed ? ld - 64 * b : ld;
+}
+// Entries of G for a problem of N design pixels: packed, the design bands and
+// the monitor rows; dense, R x ld.
+__host__ __device__ __forceinline__ int64_t g_elems(int packed, int64_t N, int64_t nmon, int64_t ld) {
+  return packed ? g_band_start(1, ld, (N + 63) / 64) + nmon * ld : (N + nmon) * ld;
+}
+
+// Offset of entry (r, c) of G as stored (packed: design entries need
+// c >= 64 (r / 64)).
+__host__ __device__ __forceinline__ int64_t g_off(const Geo& g, int64_t r, int64_t c) {
+  if (!g.packed) return r * g.ld + c;
+  if (r >= g.N) return g.mon_base + (r - g.N) * g.ld + c;
+  const int64_t b = r >> 6;
+  return g_band_start(1, g.ld, b) + (r & 63) * (g.ld - 64 * b) + (c - 64 * b);
+}
 
 // Offset of entry (p, q) of G; design-block entries (p, q < N) come from the
 // upper triangle when g.upper.
 __device__ __forceinline__ int64_t g_at(const Geo& g, int64_t p, int64_t q) {
-  return g.upper && p > q && p < g.N ? q * g.ld + p : p * g.ld + q;
+  return g.upper && p > q && p < g.N ? g_off(g, q, p) : g_off(g, p, q);
 }
 
 // ------------------------------------------------------------------ complex FP64

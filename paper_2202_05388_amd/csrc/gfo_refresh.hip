@@ -226,18 +226,21 @@ struct EpiG0 {
   T* G;
   double2* diag64;
   __device__ void operator()(int m, int n, double2 v) const {
+    // band-packed storage holds no entry left of a design row's band
+    if (g.packed && m < g.N && n < (m & ~63)) return;
     const double2 g0 = g0_entry(g, table, mon_xy, m, n);
     const double2 val = make_double2(g0.x + v.x, g0.y + v.y);
-    G[(int64_t)m * g.ld + n] = St<T>::from_d(val);
+    G[g_off(g, m, n)] = St<T>::from_d(val);
     if (m == n) diag64[m] = val;
   }
 };
 
 struct EpiAddG {
-  int64_t ld;
+  Geo g;
   double2* G;
   __device__ void operator()(int m, int n, double2 v) const {
-    double2* p = G + (int64_t)m * ld + n;
+    if (g.packed && m < g.N && n < (m & ~63)) return;
+    double2* p = G + g_off(g, m, n);
     *p = cadd(*p, v);
   }
 };
@@ -403,7 +406,7 @@ hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const dou
   // slot-major terms: A(m, k) = CU[k * R + m], B(k, n) = V[k * ld + n]; all R
   // rows (the design block and the monitor rows; the FOM monitor's terms are
   // zeros)
-  EpiAddG ep{g.ld, G};
+  EpiAddG ep{g, G};
   hipLaunchKernelGGL((k_zgemm_f64<true, false, EpiAddG>), dim3((g.N + 63) / 64, (g.R + 63) / 64),
                      dim3(256), 0, s, g.R, g.N, GFO_MAX_DELAY, CU, (int64_t)g.R, V, g.ld, count, ep, g.N);
   return hipGetLastError();

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_regions(
     region_pixels(g, k, V);
     double2 Gvv[kRegionPix][kRegionPix], EV[kRegionPix], gm[kRegionPix];
     int cur[kRegionPix];
-    const T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
+    const T* __restrict__ grow = G + g_off(g, g.N + g.m0, 0);
 #pragma unroll
     for (int i = 0; i < kRegionPix; ++i) {
       cur[i] = eps_idx[V[i]];

@@ -22,7 +22,7 @@ __global__ __launch_bounds__(kScoreThreads) void k_score(
   __shared__ double sh[kScoreThreads / 64];
   __shared__ int shi[kScoreThreads / 64];
   const double2 Em0 = St<T>::to_d(E[g.N + g.m0]);
-  const T* __restrict__ grow = G + (int64_t)(g.N + g.m0) * g.ld;
+  const T* __restrict__ grow = G + g_off(g, g.N + g.m0, 0);
   double best = -INFINITY;
   bool bad = false;
   double F[GFO_MAX_EPS];

@@ -26,7 +26,8 @@ class Job:
     """Device state of one greedy optimisation."""
 
     def __init__(self, problem, device="cuda", kmax: int = 0, flip_cap: int = None,
-                 dtype: str = None, delay: int = 0, ld_pad: int = 0, upper: bool = False):
+                 dtype: str = None, delay: int = 0, ld_pad: int = 0, upper: bool = False,
+                 packed: bool = False):
         if not torch.cuda.is_available():
             raise L.GfoError("libgfo needs a GPU; torch.cuda is not available")
         L.lib()
@@ -51,7 +52,15 @@ class Job:
         self.flip_cap = int(flip_cap if flip_cap is not None else max(4 * self.N, 16))
         work_bytes = L.workspace_size(self.prob, self.kmax, self.ld)
         dev = self.device
-        self.G = torch.empty((self.R, self.ld), dtype=tdtype, device=dev)
+        # band-packed storage (the design block's upper triangle and the monitor
+        # rows, about half of G) works with deferred updates only
+        self.packed = bool(packed)
+        if self.packed and int(delay) < 1:
+            raise L.GfoError("band-packed storage needs deferred updates (delay >= 1)")
+        if self.packed:
+            self.G = torch.empty((L.g_elems(self.prob, self.ld, True),), dtype=tdtype, device=dev)
+        else:
+            self.G = torch.empty((self.R, self.ld), dtype=tdtype, device=dev)
         self.E = torch.empty((self.R,), dtype=tdtype, device=dev)
         self.diag64 = torch.empty((self.N,), dtype=torch.complex128, device=dev)
         self.eps_idx = torch.empty((self.N,), dtype=torch.uint8, device=dev)
@@ -64,7 +73,7 @@ class Job:
             eps_idx=self.eps_idx.data_ptr(), flips=self.flips.data_ptr(), flip_cap=self.flip_cap,
             n_flips=self.counters.data_ptr(), kmax=self.kmax, work=self.work.data_ptr(),
             work_bytes=work_bytes, status=self.counters.data_ptr() + 4, delay=int(delay),
-            pending_calls=0, lower_stale=0)
+            pending_calls=0, lower_stale=0, packed=int(self.packed))
         self.delay = int(delay)
         # keep only the upper triangle of the (symmetric) design block current,
         # in eager mode too: init_G0 and refresh_G are called with lower_stale = 1
@@ -104,8 +113,41 @@ class Job:
 
     def sync_lower(self, stream=None):
         """Copy the upper triangle of the design block into the lower one if a
-        flush left the lower one out of date."""
-        L.sync_lower(self.prob, self.state, _stream_handle(stream))
+        flush left the lower one out of date (band-packed storage keeps no lower
+        triangle: a no-op)."""
+        if not self.packed:
+            L.sync_lower(self.prob, self.state, _stream_handle(stream))
+
+    def _bands(self):
+        """(first row, rows, first column, packed offset, row stride) of each
+        64-row band of the design block in band-packed storage, then the monitor
+        rows' (N, N_m, 0, offset, ld)."""
+        ld, N = self.ld, self.N
+        out = []
+        for b in range((N + 63) // 64):
+            r0 = 64 * b
+            out.append((r0, min(64, N - r0), r0, 64 * (b * ld - 32 * b * (b - 1)), ld - r0))
+        nb = (N + 63) // 64
+        out.append((N, self.R - N, 0, 64 * (nb * ld - 32 * nb * (nb - 1)), ld))
+        return out
+
+    def dense_G(self):
+        """G as an R x ld device tensor.  Band-packed storage: the stored
+        entries in place, the design block's lower triangle from its upper one
+        (entries left of a row's band and the stale lower halves of the diagonal
+        tiles are not used)."""
+        if not self.packed:
+            return self.G
+        D = torch.zeros((self.R, self.ld), dtype=self.G.dtype, device=self.device)
+        for r0, nr, c0, off, stride in self._bands():
+            if nr <= 0:
+                continue
+            blk = self.G[off: off + nr * stride].view(nr, stride)
+            D[r0: r0 + nr, c0:] = blk[:, : self.ld - c0]
+        N = self.N
+        up = torch.triu(D[:N, :N])
+        D[:N, :N] = up + torch.triu(up, 1).transpose(0, 1)
+        return D
 
     def step(self, stream=None):
         """One greedy step: score + select + rank-1 apply, no host synchronisation."""
@@ -233,7 +275,7 @@ class Job:
         self.flush()
         self.sync_lower()
         torch.cuda.synchronize(self.device)
-        G = self.G[:, : self.N].cpu().to(torch.complex128).numpy()
+        G = self.dense_G()[:, : self.N].cpu().to(torch.complex128).numpy()
         return (G, self.E.cpu().to(torch.complex128).numpy(), self.diag64.cpu().numpy(),
                 self.eps_idx.cpu().numpy())
 
@@ -243,7 +285,13 @@ class Job:
         Gt = torch.zeros((self.R, self.ld), dtype=torch.complex128)
         # np.array copies: read-only views (np.diagonal) are not valid tensor storage
         Gt[:, : self.N] = torch.from_numpy(np.array(G, np.complex128))
-        self.G.copy_(Gt.to(tdtype))
+        if self.packed:
+            for r0, nr, c0, off, stride in self._bands():
+                if nr > 0:
+                    self.G[off: off + nr * stride].view(nr, stride).copy_(
+                        Gt[r0: r0 + nr, c0: c0 + stride].to(tdtype))
+        else:
+            self.G.copy_(Gt.to(tdtype))
         self.E.copy_(torch.from_numpy(np.array(E, np.complex128)).to(tdtype))
         self.diag64.copy_(torch.from_numpy(np.array(diag, np.complex128)))
         self.eps_idx.copy_(torch.from_numpy(np.array(eps_idx, np.uint8)))

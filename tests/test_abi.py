@@ -50,7 +50,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(L.State) == 112
     assert L.State.work.offset == 72 and L.State.status.offset == 88
     assert L.State.delay.offset == 96 and L.State.pending_calls.offset == 100
-    assert L.State.lower_stale.offset == 104
+    assert L.State.lower_stale.offset == 104 and L.State.packed.offset == 108
     assert C.sizeof(L.Pick) == 24
 
 
@@ -216,3 +216,43 @@ def test_static_score_rejects_oversize_and_bad_arguments_on_host():
     st.G = None
     assert lib.score_candidates_static(C.byref(small), C.byref(st), 3, 1e-9, 1, 0, out,
                                        None) == L.GFO_EINVAL
+
+
+def test_packed_storage_sizes_and_refusals():
+    """Band-packed G: the entry count (the design bands on and above the
+    diagonal, then the monitor rows), and the calls that refuse it before any
+    launch: eager updates (delay 0), the rank-k update and gfo_sync_lower (the
+    pointers here are never dereferenced)."""
+    lib = L.lib()
+    for ny, nx, nmon, pad in ((128, 128, 64, 0), (60, 62, 20, 64), (1, 3, 1, 0), (8, 8, 70, 0)):
+        pr, keep = _problem(W.tiny(ny, nx, n_mon=nmon))
+        N, R = ny * nx, ny * nx + nmon
+        ld = L.min_ld(pr) + pad
+        assert L.g_elems(pr, ld, False) == R * ld
+        # band b holds 64 rows of ld - 64 b entries (the last band's rows past N too)
+        nb = (N + 63) // 64
+        want = sum(64 * (ld - 64 * b) for b in range(nb)) + nmon * ld
+        assert L.g_elems(pr, ld, True) == want
+        assert L.g_elems(pr, ld, True) < R * ld or N <= 64
+    pr, keep = _problem(W.SQUARE_128, dtype=L.GFO_C64)
+    assert L.g_elems(pr, 0, True) * 8 / 1e9 < 0.55 * L.g_elems(pr, 0, False) * 8 / 1e9
+    out = C.c_int64(0)
+    assert lib.gfo_g_elems(C.byref(pr), 0, 2, C.byref(out)) == L.GFO_EINVAL
+    assert lib.gfo_g_elems(C.byref(pr), 17, 1, C.byref(out)) == L.GFO_EINVAL
+    pr, keep = _problem(W.tiny(8, 8, n_mon=4), dtype=L.GFO_C64)
+    ld = L.min_ld(pr)
+    fake = 1 << 20
+    st = L.State(G=fake, ldG=ld, E=fake, diag64=fake, eps_idx=fake, flips=fake, flip_cap=16,
+                 n_flips=fake, kmax=0, work=fake, work_bytes=L.workspace_size(pr, 0), status=fake,
+                 delay=0, pending_calls=0, lower_stale=0, packed=1)
+    picks = C.c_void_p(fake)
+    # packed needs deferred updates: every call validates that
+    assert lib.init_G0(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
+    assert lib.apply_flip(C.byref(pr), C.byref(st), picks, None) == L.GFO_EINVAL
+    assert lib.gfo_greedy_steps(C.byref(pr), C.byref(st), 4, 3, 1e-6, None, None) == L.GFO_EINVAL
+    st.packed = 2
+    st.delay = 16
+    assert lib.init_G0(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
+    st.packed = 1
+    assert lib.apply_flips_rank_k(C.byref(pr), C.byref(st), picks, 4, L.GFO_FP32, None) == L.GFO_EINVAL
+    assert lib.gfo_sync_lower(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
