@@ -333,7 +333,7 @@ def time_deferred_graph(problem, steps, warmup, delay, fused=True):
     return out
 
 
-def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True):
+def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True, packed=False):
     """Greedy steps with deferred rank-1 updates: E, the FP64 diagonal and the monitor
     rows every step, the design block by one rank-`delay` matrix-core product per
     `delay` steps.  fused: gfo_greedy_steps (one kernel per move), else
@@ -346,8 +346,9 @@ def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True):
     from paper_2202_05388_amd import autotune as at
 
     kmax = 2 * problem.refresh_every if problem.refresh_every else 0
-    job = Job(problem, device="cuda:0", kmax=kmax, delay=delay or 64, ld_pad=LD_PAD)
+    job = Job(problem, device="cuda:0", kmax=kmax, delay=delay or 64, ld_pad=LD_PAD, packed=packed)
     job.init()
+    g_bytes = job.G.numel() * job.G.element_size()
     delay_tuned = None
     if delay is None:
         # the flush interval from the trajectory this workload runs (autotuner)
@@ -392,6 +393,7 @@ def time_deferred(problem, steps, warmup, poll, delay, fused=True, tune=True):
                flush_variants_us=None if flush_tuned is None else flush_tuned.get("variants_us"),
                flush_us=None if not fl else 1e3 * sum(fl) / len(fl),
                flush_roofline=roof, fom_last=job.fom(), status=job.status(),
+               storage_layout="band-packed" if packed else "dense", g_bytes=g_bytes,
                last_run_pixels=[int(x) for x in hist[:, 0]])
     del job
     torch.cuda.empty_cache()
@@ -849,6 +851,11 @@ def main():
             _log(f"[bench] deferred {key}: {deferred[key]}")
             key = pf.name + "_graph"
             deferred[key] = time_deferred_graph(pf, args.steps, args.warmup, d_pf)
+            _log(f"[bench] deferred {key}: {deferred[key]}")
+            # the same fused loop on band-packed storage (about half of G's bytes)
+            key = pf.name + "_packed"
+            deferred[key] = time_deferred(pf, args.steps, args.warmup, args.poll, d_pf,
+                                          tune=False, packed=True)
             _log(f"[bench] deferred {key}: {deferred[key]}")
     if args.delay is None:
         # the other deferred legs use the interval chosen for the headline workload
