@@ -161,3 +161,57 @@ def test_packed_footprint_at_128():
         j.run_greedy(200, poll_every=32, fused=True)
     torch.cuda.synchronize()
     _same(dense, packed)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_packed_two_kernel_loop_equals_dense(dtype):
+    """The fused loop's two-kernel form (grids above 65,536 pixels; forced here
+    on a small grid) on packed storage, bit for bit as dense."""
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(40, 42, n_mon=30, dtype=dtype, cand_mask=W.MASK_BOTH,
+               tau=1e-6 if dtype == "c64" else 1e-9)
+    L.loop_set_form(1)
+    try:
+        dense, packed = _pair(p, 64)
+        for n in (33, 70, 5):
+            for j in (dense, packed):
+                j.greedy_steps(n)
+        _same(dense, packed)
+    finally:
+        L.loop_set_form(0)
+
+
+def test_packed_strip_equals_dense_at_sampled_entries():
+    """The 48 x 2048 strip (98,304 pixels, 256 monitors): packed G takes 38.9 GB
+    beside the dense 77.5 GB.  120 fused moves at 128 terms per flush (the
+    two-kernel loop), then a flush: the same moves, fields, diagonal and FOM
+    monitor row, and the same upper-triangle entries at 4096 sampled positions,
+    bit for bit."""
+    import torch
+    p = W.STRIP_48x2048
+    dense, packed = _pair(p, 128)
+    assert packed.G.numel() * packed.G.element_size() < 39.0e9
+    for j in (dense, packed):
+        j.greedy_steps(60)
+        j.greedy_steps(60)
+        j.flush()
+    torch.cuda.synchronize()
+    assert np.array_equal(dense.history(), packed.history())
+    assert dense.status() == packed.status() == 0
+    for a, b in ((dense.E, packed.E), (dense.diag64, packed.diag64), (dense.eps_idx, packed.eps_idx)):
+        assert torch.equal(a, b)
+    N, ld = p.n, dense.ld
+    rng = np.random.default_rng(0)
+    r = rng.integers(0, N, 4096)
+    c = rng.integers(0, N, 4096)
+    r, c = np.minimum(r, c), np.maximum(r, c)                 # upper-triangle positions
+    b = r // 64
+    off = 64 * (b * ld - 32 * b * (b - 1)) + (r % 64) * (ld - 64 * b) + (c - 64 * b)
+    idx = torch.from_numpy(off.astype(np.int64)).to(packed.G.device)
+    got = packed.G[idx]
+    want = dense.G[torch.from_numpy(r).to(dense.G.device), torch.from_numpy(c).to(dense.G.device)]
+    assert torch.equal(got, want)
+    nb = (N + 63) // 64
+    mon0 = 64 * (nb * ld - 32 * nb * (nb - 1))
+    m0 = p.fom_monitor
+    assert torch.equal(packed.G[mon0 + m0 * ld: mon0 + (m0 + 1) * ld], dense.G[N + m0])
