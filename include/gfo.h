@@ -36,6 +36,10 @@
  *     larger than the static scratch).  Conditions met on the device are OR-ed
  *     into *state->status (GFO_STATUS_*), to be read by the caller when it
  *     synchronises.  The library never aborts the process.
+ *   - GFO_EHIP names a failure of the call's own HIP calls or launches
+ *     (gfo_last_hip_error gives the HIP code).  An entry point that launches
+ *     kernels first reads and drops the thread's pending HIP error, one left
+ *     by an earlier failed call of the caller or of another library.
  */
 #ifndef GFO_H
 #define GFO_H
@@ -119,6 +123,12 @@ const char* gfo_version(void);
 
 /* Human-readable text of a return code. */
 const char* gfo_strerror(int code);
+
+/* The HIP result behind the calling thread's most recent GFO_EHIP: the code of
+ * the last HIP runtime call or kernel launch of the library that failed on
+ * this thread (0 = none since the previous query), and its name in *h_name
+ * (a static string; h_name may be NULL).  Clears the record.  Host only. */
+int32_t gfo_last_hip_error(const char** h_name);
 
 /* Bytes of workspace that a job of this problem needs with leading dimension
  * ldG (0: gfo_min_ld; else at least that and a multiple of 64) when refresh_G

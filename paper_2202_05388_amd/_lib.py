@@ -23,7 +23,7 @@ GFO_MAX_DELAY = 128
 GFO_STATIC_SCRATCH_BYTES = 8 << 20
 
 # every entry point that include/gfo.h declares
-EXPORTS = ("gfo_version", "gfo_strerror", "gfo_workspace_size", "gfo_min_ld", "gfo_g_elems", "gfo_scores_offset",
+EXPORTS = ("gfo_version", "gfo_strerror", "gfo_last_hip_error", "gfo_workspace_size", "gfo_min_ld", "gfo_g_elems", "gfo_scores_offset",
            "init_G0", "score_candidates", "apply_flip", "apply_flips_rank_k", "refresh_G",
            "gfo_k1_variant_count", "gfo_k1_variant_name", "gfo_k1_set_variant",
            "gfo_k1_get_variant", "gfo_time_next_k1", "gfo_flush", "gfo_flush_variant_count",
@@ -76,11 +76,18 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise GfoError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # torch first: its wheel carries its own HIP runtime under the same soname,
+    # and libgfo must bind to that one (the runtime that owns torch's device
+    # memory and streams).  Loaded first, libgfo would pull in the system copy and
+    # torch a second runtime beside it, whose launches then fail.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P, S, V = C.POINTER(Problem), C.POINTER(State), C.c_void_p
     L.gfo_version.restype = C.c_char_p
     L.gfo_strerror.restype = C.c_char_p
     L.gfo_strerror.argtypes = [C.c_int]
+    L.gfo_last_hip_error.restype = C.c_int32
+    L.gfo_last_hip_error.argtypes = [C.POINTER(C.c_char_p)]
     L.gfo_workspace_size.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(C.c_size_t)]
     L.gfo_min_ld.argtypes = [P]
     L.gfo_min_ld.restype = C.c_int64
@@ -122,7 +129,12 @@ def lib():
 
 def check(rc: int, what: str) -> None:
     if rc != GFO_OK:
-        raise GfoError(f"{what} failed: {rc} ({lib().gfo_strerror(rc).decode()})", code=rc)
+        msg = f"{what} failed: {rc} ({lib().gfo_strerror(rc).decode()})"
+        if rc == GFO_EHIP:
+            name = C.c_char_p()
+            code = lib().gfo_last_hip_error(C.byref(name))
+            msg += f" [HIP error {code}: {(name.value or b'').decode()}]"
+        raise GfoError(msg, code=rc)
 
 
 def version() -> str:

@@ -145,6 +145,18 @@ int validate_job(const gfo_problem* p, const gfo_state* st, Layout* L) {
   return validate_state(p, st, L);
 }
 
+static thread_local hipError_t t_last_hip = hipSuccess;
+
+hipError_t note_hip(hipError_t e) {
+  if (e != hipSuccess) t_last_hip = e;
+  return e;
+}
+
+// The runtime keeps a failed call's error until it is read; one left by a call
+// made before the entry point (by the caller or another library) is dropped
+// here, so that the checks after this call's own launches report only them.
+void discard_stale_hip() { (void)hipGetLastError(); }
+
 }  // namespace gfo
 
 using namespace gfo;
@@ -152,6 +164,13 @@ using namespace gfo;
 extern "C" {
 
 const char* gfo_version(void) { return "libgfo 0.1 gfx950"; }
+
+int32_t gfo_last_hip_error(const char** h_name) {
+  const hipError_t e = t_last_hip;
+  t_last_hip = hipSuccess;
+  if (h_name) *h_name = hipGetErrorName(e);
+  return (int32_t)e;
+}
 
 const char* gfo_strerror(int code) {
   switch (code) {
@@ -204,6 +223,7 @@ int gfo_g_elems(const gfo_problem* prob, int64_t ldG, int32_t packed, int64_t* h
 }
 
 int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
+  discard_stale_hip();
   int rc = validate_problem(prob);
   if (rc) return rc;
   Layout L;
@@ -212,8 +232,8 @@ int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   char* w = (char*)st->work;
   // monitor coordinates travel with the call; wait for the copy so that the
   // caller's host array need not outlive it
-  if (hipMemcpyAsync(w + L.mon_xy, prob->h_mon_xy, (size_t)prob->n_mon * 2 * sizeof(double),
-                     hipMemcpyHostToDevice, stream) != hipSuccess)
+  if (note_hip(hipMemcpyAsync(w + L.mon_xy, prob->h_mon_xy, (size_t)prob->n_mon * 2 * sizeof(double),
+                              hipMemcpyHostToDevice, stream)) != hipSuccess)
     return GFO_EHIP;
   if (launch_init(g, st, L, stream) != hipSuccess) return GFO_EHIP;
   if (launch_dl_reset(g, st, L, stream) != hipSuccess) return GFO_EHIP;
@@ -221,12 +241,13 @@ int init_G0(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
   // deferred mode, or a caller that asked for it (lower_stale = 1 on entry),
   // keeps the upper triangle of the design block alone
   st->lower_stale = g.upper;
-  if (hipStreamSynchronize(stream) != hipSuccess) return GFO_EHIP;
+  if (note_hip(hipStreamSynchronize(stream)) != hipSuccess) return GFO_EHIP;
   return GFO_OK;
 }
 
 int score_candidates(const gfo_problem* prob, const gfo_state* st, uint32_t cand_mask, double tau,
                      int32_t topk, int32_t min_spacing, gfo_pick* d_out, hipStream_t stream) {
+  discard_stale_hip();
   int rc = validate_problem(prob);
   if (rc) return rc;
   Layout L;
@@ -243,6 +264,7 @@ int score_candidates(const gfo_problem* prob, const gfo_state* st, uint32_t cand
 }
 
 int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick, hipStream_t stream) {
+  discard_stale_hip();
   int rc = validate_problem(prob);
   if (rc) return rc;
   Layout L;
@@ -258,6 +280,7 @@ int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick, h
 }
 
 int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
+  discard_stale_hip();
   int rc = validate_problem(prob);
   if (rc) return rc;
   Layout L;
@@ -270,6 +293,7 @@ int gfo_flush(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
 }
 
 int gfo_sync_lower(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
+  discard_stale_hip();
   int rc = validate_problem(prob);
   if (rc) return rc;
   Layout L;
@@ -284,6 +308,7 @@ int gfo_sync_lower(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
 
 int gfo_greedy_steps(const gfo_problem* prob, gfo_state* st, int32_t n_steps, uint32_t cand_mask,
                      double tau, gfo_pick* d_picks, hipStream_t stream) {
+  discard_stale_hip();
   int rc = validate_problem(prob);
   if (rc) return rc;
   Layout L;
@@ -372,6 +397,7 @@ static int validate_regions(const gfo_problem* prob, int32_t region) {
 
 int score_regions(const gfo_problem* prob, const gfo_state* st, int32_t region,
                   uint32_t cand_mask, double tau, gfo_pick* d_out, hipStream_t stream) {
+  discard_stale_hip();
   int rc = validate_problem(prob);
   if (rc) return rc;
   Layout L;
@@ -387,6 +413,7 @@ int score_regions(const gfo_problem* prob, const gfo_state* st, int32_t region,
 
 int gfo_region_pixels(const gfo_problem* prob, const gfo_state* st, int32_t region,
                       const gfo_pick* d_region, gfo_pick* d_pixels, hipStream_t stream) {
+  discard_stale_hip();
   int rc = validate_problem(prob);
   if (rc) return rc;
   Layout L;
@@ -400,6 +427,7 @@ int gfo_region_pixels(const gfo_problem* prob, const gfo_state* st, int32_t regi
 
 int gfo_choose_eps_greedy(const gfo_pick* d_top, int32_t k, double eps, double u_explore,
                           double u_choice, gfo_pick* d_out, hipStream_t stream) {
+  discard_stale_hip();
   if (!d_top || !d_out || k < 1 || k > GFO_MAX_RANK_K || !(eps >= 0.0 && eps <= 1.0) ||
       !(u_explore >= 0.0 && u_explore < 1.0) || !(u_choice >= 0.0 && u_choice < 1.0))
     return GFO_EINVAL;
@@ -410,6 +438,7 @@ int gfo_choose_eps_greedy(const gfo_pick* d_top, int32_t k, double eps, double u
 
 int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_picks, int32_t k,
                        int32_t gemm_precision, hipStream_t stream) {
+  discard_stale_hip();
   int rc = validate_problem(prob);
   if (rc) return rc;
   Layout L;
@@ -428,6 +457,7 @@ int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d
 }
 
 int refresh_G(const gfo_problem* prob, gfo_state* st, hipStream_t stream) {
+  discard_stale_hip();
   int rc = validate_problem(prob);
   if (rc) return rc;
   Layout L;

@@ -411,7 +411,7 @@ __global__ void k_dl_reset(int32_t* count) {
 
 hipError_t launch_dl_reset(const Geo&, gfo_state* st, const Layout& L, hipStream_t s) {
   hipLaunchKernelGGL(k_dl_reset, dim3(1), dim3(64), 0, s, (int32_t*)((char*)st->work + L.dl_hdr));
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 // One kernel per move (fused greedy loop, deferred mode, when the pixels fit
@@ -686,7 +686,7 @@ hipError_t launch_fused_finish(const Geo& g, gfo_state* st, const Layout& L, hip
                      (const T*)(w + L.cu), (const T*)(w + L.v), (const T*)(w + L.emon), (T*)st->G,
                      (T*)st->E, (double2*)st->diag64, st->eps_idx, st->flips, st->flip_cap,
                      st->n_flips, st->status, (int32_t*)(w + L.dl_hdr));
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 template <typename T>
@@ -722,7 +722,7 @@ hipError_t launch_fused_move(const Geo& g, gfo_state* st, const Layout& L, int a
                      (const T*)st->G, (const T*)st->E, (const double2*)st->diag64,
                      (const uint8_t*)st->eps_idx, (const int32_t*)count, snap, (T*)(w + L.dl_CUs),
                      (T*)(w + L.dl_Vs), cu, v, emon);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 // The one-kernel loop serves shapes whose pixels fit kScoreMaxBlocks summaries
@@ -759,7 +759,7 @@ hipError_t launch_move(const Geo& g, gfo_state* st, const Layout& L, int t, int 
                      pick_out, (T*)st->G, (T*)st->E, (double2*)st->diag64, st->eps_idx,
                      (const int32_t*)(w + L.dl_hdr), st->flips, st->flip_cap, st->n_flips,
                      st->status, (T*)(w + L.dl_CUs), (T*)(w + L.dl_Vs));
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 // After move t of a one-kernel loop: its last, or one before a flush.
@@ -772,7 +772,7 @@ hipError_t launch_move_finish(const Geo& g, gfo_state* st, const Layout& L, int 
   hipLaunchKernelGGL(k_move_finish<T>, dim3((unsigned)((g.nmon + 255) / 256)), dim3(256), 0, s, g,
                      snap, emon, (T*)st->G, (T*)st->E, (double2*)st->diag64, st->eps_idx,
                      (int32_t*)(w + L.dl_hdr));
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 // Scores of the current state into the first buffer set (the start of a
@@ -789,7 +789,7 @@ hipError_t launch_move_scores(const Geo& g, gfo_state* st, const Layout& L, uint
                      (T*)st->E, (double2*)st->diag64, st->eps_idx, st->flips, st->flip_cap,
                      st->n_flips, st->status, (int32_t*)(w + L.dl_hdr), mask, tau,
                      (double*)(w + L.scores), (double*)(w + L.partial), (int*)(w + L.pfirst), nblk);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ grouped launches
@@ -897,7 +897,7 @@ template <typename T>
 hipError_t launch_table_scores(const JobEntry* tab, int n_jobs, int max_wg, hipStream_t s) {
   hipLaunchKernelGGL(k_mon_score_table<T>, dim3((unsigned)max_wg, (unsigned)n_jobs),
                      dim3(kScoreThreads), 0, s, tab);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 template <typename T>
@@ -909,14 +909,14 @@ hipError_t launch_table_move(const JobEntry* tab, int n_jobs, int max_wg, int t,
                             : (b16 ? k_move_table<T, kPickPerLane, 16>
                                    : k_move_table<T, kPickPerLane, 32>)),
                      grid, dim3(256), 0, s, tab, t, flushed);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 template <typename T>
 hipError_t launch_table_finish(const JobEntry* tab, int n_jobs, int max_wg, int t, hipStream_t s) {
   hipLaunchKernelGGL(k_move_finish_table<T>, dim3((unsigned)max_wg, (unsigned)n_jobs), dim3(256), 0,
                      s, tab, t);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 template hipError_t launch_table_scores<float2>(const JobEntry*, int, int, hipStream_t);

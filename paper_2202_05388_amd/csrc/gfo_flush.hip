@@ -601,7 +601,7 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
   k1_take_timing(&before, &after);
   hipError_t e;
   if (g.dtype == GFO_C64) {
-    if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
+    if (hipError_t er = record_event(before, s)) return note_hip(er);
     int fv = flush_get_variant();
     bool monitors_done = false;
     // the pair and band forms address the term buffers with 32-bit byte offsets
@@ -610,7 +610,7 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
     // band-packed storage: the pair and band forms only (they address tiles
     // through tile_at); sizes beyond their 32-bit offsets are refused
     if (g.packed) {
-      if (!off32) return hipErrorInvalidValue;
+      if (!off32) return note_hip(hipErrorInvalidValue);
       if (fv == 0) fv = 1;
     }
     const float2* cu = (const float2*)(w + L.dl_CUs);
@@ -683,21 +683,22 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
       }
     }
     e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess) return note_hip(e);
     // the timed interval is the design-block kernel alone
-    if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
+    if (hipError_t er = record_event(after, s)) return note_hip(er);
     // the monitor rows (the FOM monitor's terms are stored as zeros)
     if (!monitors_done) {
       hipLaunchKernelGGL((k_flush_c64_tm<1, true>),
                          dim3((unsigned)((g.N + 63) / 64), (unsigned)((g.nmon + 63) / 64)), blk, 0, s,
                          g.R, g.R, g.ld, count, cu, vv, G, g.N);
-      e = hipGetLastError();
+      e = note_hip(hipGetLastError());
     }
   } else {
-    if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
+    if (hipError_t er = record_event(before, s)) return note_hip(er);
     e = launch_zgemm_update_f64(g, count, (const double2*)(w + L.dl_CUs),
                                 (const double2*)(w + L.dl_Vs), (double2*)st->G, s);
-    if (e == hipSuccess && after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
+    if (e == hipSuccess) e = record_event(after, s);
+    if (e != hipSuccess) return note_hip(e);
     st->lower_stale = 1;
   }
   if (e != hipSuccess) return e;
@@ -734,7 +735,7 @@ hipError_t launch_sync_lower(const Geo& g, gfo_state* st, hipStream_t s) {
     hipLaunchKernelGGL(k_sync_lower<float2>, grid, dim3(256), 0, s, g.N, g.ld, (float2*)st->G, nb);
   else
     hipLaunchKernelGGL(k_sync_lower<double2>, grid, dim3(256), 0, s, g.N, g.ld, (double2*)st->G, nb);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 }  // namespace gfo

@@ -154,7 +154,7 @@ static hipError_t init_typed(const Geo& g, gfo_state* st, const Layout& L, hipSt
   hipLaunchKernelGGL(k_init_vectors<T>, dim3((g.R + 255) / 256), dim3(256), 0, s, g, (T*)st->E,
                      (double2*)st->diag64, st->eps_idx, (const double*)mon, (const double2*)table,
                      st->n_flips, st->status);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 hipError_t launch_init(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {

@@ -10,6 +10,17 @@
 
 namespace gfo {
 
+// Keeps e as the calling thread's last failed HIP result (read back through
+// gfo_last_hip_error) when it is not hipSuccess; returns e.
+hipError_t note_hip(hipError_t e);
+// Drops a HIP error left by calls made before the entry point (called first
+// in every entry point that launches kernels).
+void discard_stale_hip();
+// Records ev on s when ev is set (the autotuner's timing events).
+inline hipError_t record_event(hipEvent_t ev, hipStream_t s) {
+  return ev ? hipEventRecord(ev, s) : hipSuccess;
+}
+
 // Geometry and material data passed by value to every kernel.
 struct Geo {
   int ny, nx, nmon, N, R;

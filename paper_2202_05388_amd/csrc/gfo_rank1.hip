@@ -244,10 +244,10 @@ hipError_t launch_rank1(const Geo& g, const Snap* snap, const void* cu, const vo
   const K1Variant* tab = k1_table(g.dtype, &nv);
   hipEvent_t before, after;
   k1_take_timing(&before, &after);
-  if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
+  if (hipError_t er = record_event(before, s)) return note_hip(er);
   tab[k1_get_variant(g.dtype)].launch(g.R, g.ld, g.N, g.upper, snap, cu, v, G, s);
-  if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
-  return hipGetLastError();
+  if (hipError_t er = record_event(after, s)) return note_hip(er);
+  return note_hip(hipGetLastError());
 }
 
 }  // namespace gfo

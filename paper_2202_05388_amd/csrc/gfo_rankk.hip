@@ -419,8 +419,11 @@ __global__ __launch_bounds__(256) void k_rk_mfma(int R, int64_t ld,
 //   LDSEPI = true: the 32 x 128 product goes through LDS and G streams in
 //     16-byte pieces (1 KB row segments per wave), two barriers per row block.
 // G is read and written with non-temporal (streaming) loads and stores.
+// The launch bound keeps the FP32 rank-16 forms with one row tile within 128
+// registers (about 120 needed): three to four waves per SIMD, as LDS allows, and
+// more loads of G in flight than at two.
 template <int KP, bool BF16, int RB, bool LDSEPI, int TM = 1>
-__global__ __launch_bounds__(256) void k_rk_stream(int R, int64_t ld,
+__global__ __launch_bounds__(256, (!BF16 && TM == 1 && KP == 16) ? 3 : 1) void k_rk_stream(int R, int64_t ld,
                                                    const int32_t* __restrict__ gate_count,
                                                    const int32_t* __restrict__ gate_kp,
                                                    const float* __restrict__ Af,
@@ -606,7 +609,7 @@ static void launch_rk_stream(const Geo& g, RkHdr* hdr, const float* Af, const fl
 
 hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo_pick* picks, int k,
                          int precision, hipStream_t s) {
-  if (g.dtype != GFO_C64) return hipErrorInvalidValue;
+  if (g.dtype != GFO_C64) return note_hip(hipErrorInvalidValue);
   char* w = (char*)st->work;
   RkHdr* hdr = (RkHdr*)(w + L.rk_S);
   double2* M = (double2*)(w + L.rk_M);
@@ -628,7 +631,7 @@ hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo
                      (double2*)st->diag64, (const double2*)U64, Bf, Bbf, bf);
   hipEvent_t before, after;
   k1_take_timing(&before, &after);
-  if (before && hipEventRecord(before, s) != hipSuccess) return hipErrorUnknown;
+  if (hipError_t er = record_event(before, s)) return note_hip(er);
   // the rank padding (16 or 32) is decided on the device; both instantiations are
   // launched and the one that does not match exits at once
   const float* cAf = Af;
@@ -678,8 +681,8 @@ hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo
       break;
     }
   }
-  if (after && hipEventRecord(after, s) != hipSuccess) return hipErrorUnknown;
-  return hipGetLastError();
+  if (hipError_t er = record_event(after, s)) return note_hip(er);
+  return note_hip(hipGetLastError());
 }
 
 }  // namespace gfo

@@ -341,15 +341,15 @@ int launch_refresh_count(const Geo& g, gfo_state* st, const Layout& L, hipStream
   int32_t* V = (int32_t*)((char*)st->work + L.rf_V);
   hipLaunchKernelGGL(k_rf_list, dim3(1), dim3(1024), 0, s, g, (const uint8_t*)st->eps_idx, V);
   *k = 0;
-  if (hipMemcpyAsync(k, V + g.N, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
+  if (note_hip(hipMemcpyAsync(k, V + g.N, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      note_hip(hipStreamSynchronize(s)) != hipSuccess)
     return GFO_EHIP;
   return GFO_OK;
 }
 
 hipError_t launch_refresh_overflow(gfo_state* st, hipStream_t s) {
   hipLaunchKernelGGL(k_rf_overflow, dim3(1), dim3(64), 0, s, st->status);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 template <typename T>
@@ -394,7 +394,7 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, int32_t k
                      dim3(256), 0, s, g.R, g.N, kp, (const double2*)Z, (int64_t)kp,
                      (const double2*)U, (int64_t)kp, (const int32_t*)nullptr, eg,
                      g.upper ? g.N : 0);
-  return hipGetLastError() == hipSuccess ? GFO_OK : GFO_EHIP;
+  return note_hip(hipGetLastError()) == hipSuccess ? GFO_OK : GFO_EHIP;
 }
 
 // Deferred-mode flush for complex128 storage: G[r, 0:N] += CU V^T over the
@@ -409,7 +409,7 @@ hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const dou
   EpiAddG ep{g, G};
   hipLaunchKernelGGL((k_zgemm_f64<true, false, EpiAddG>), dim3((g.N + 63) / 64, (g.R + 63) / 64),
                      dim3(256), 0, s, g.R, g.N, GFO_MAX_DELAY, CU, (int64_t)g.R, V, g.ld, count, ep, g.N);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 int launch_refresh(const Geo& g, gfo_state* st, const Layout& L, int32_t k, hipStream_t s) {

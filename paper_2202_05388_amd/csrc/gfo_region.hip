@@ -229,14 +229,14 @@ hipError_t launch_score_regions(const Geo& g, const gfo_state* st, const Layout&
                        (const double2*)st->E, (const double*)scores, (const double*)partial,
                        (const int*)pfirst, tau, out);
   }
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 hipError_t launch_region_pixels(const Geo& g, const gfo_state* st, const gfo_pick* region,
                                 gfo_pick* out, hipStream_t s) {
   hipLaunchKernelGGL(k_region_pixels, dim3(1), dim3(64), 0, s, g, region,
                      (const uint8_t*)st->eps_idx, out);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 }  // namespace gfo

@@ -31,7 +31,7 @@ static std::mutex g_scratch_mu;
 // Device address of `scratch` on the current device (taken on first use).
 static int scratch_address(unsigned char** out) {
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return GFO_EHIP;
+  if (note_hip(hipGetDevice(&dev)) != hipSuccess) return GFO_EHIP;
   if (dev < 0 || dev >= kMaxDevices) return GFO_EINVAL;
   unsigned char* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
   if (!p) {
@@ -39,7 +39,8 @@ static int scratch_address(unsigned char** out) {
     p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
     if (!p) {
       void* addr = nullptr;
-      if (hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch)) != hipSuccess || !addr) return GFO_EHIP;
+      if (note_hip(hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch))) != hipSuccess || !addr)
+        return GFO_EHIP;
       p = (unsigned char*)addr;
       g_scratch_ptr[dev].store(p, std::memory_order_release);
     }
@@ -59,6 +60,7 @@ using namespace gfo;
 extern "C" int score_candidates_static(const gfo_problem* prob, const gfo_state* st,
                                        uint32_t cand_mask, double tau, int32_t topk,
                                        int32_t min_spacing, gfo_pick* d_out, hipStream_t stream) {
+  discard_stale_hip();
   int rc = validate_problem(prob);
   if (rc) return rc;
   if ((rc = validate_state_fields(prob, st))) return rc;

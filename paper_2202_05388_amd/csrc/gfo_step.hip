@@ -153,7 +153,7 @@ hipError_t launch_choose_eps_greedy(const gfo_pick* top, int k, double eps, doub
                                     double u_choice, gfo_pick* out, hipStream_t s) {
   hipLaunchKernelGGL(k_choose_eps_greedy, dim3(1), dim3(64), 0, s, top, k, eps, u_explore, u_choice,
                      out);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ K2a: snapshot
@@ -249,7 +249,7 @@ static hipError_t score_typed(const Geo& g, const gfo_state* st, const ScoreBufs
   const int sel_threads = topk == 1 ? 64 : kSelectThreads;
   hipLaunchKernelGGL(k_select<T>, dim3(1), dim3(sel_threads), 0, s, g, (const T*)st->E, b.scores,
                      (const double*)b.partial, (const int*)b.pfirst, nblk, tau, topk, spacing, out);
-  return hipGetLastError();
+  return note_hip(hipGetLastError());
 }
 
 hipError_t launch_score_into(const Geo& g, const gfo_state* st, const ScoreBufs& b, uint32_t mask,

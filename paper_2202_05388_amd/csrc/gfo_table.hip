@@ -46,6 +46,7 @@ extern "C" int gfo_job_table_build(const gfo_problem* probs, const gfo_state* st
                                    int32_t n_jobs, const uint32_t* h_cand_masks,
                                    const double* h_taus, void* d_table, size_t table_bytes,
                                    hipStream_t stream) {
+  discard_stale_hip();
   std::vector<Geo> geos;
   std::vector<Layout> lays;
   int rc = check_group(probs, states, n_jobs, &geos, &lays);
@@ -59,15 +60,16 @@ extern "C" int gfo_job_table_build(const gfo_problem* probs, const gfo_state* st
     if (mask == 0 || !(tau >= 0.0) || !(tau < 1.0)) return GFO_EINVAL;
     tab[i] = make_job_entry(geos[i], &states[i], lays[i], mask, tau);
   }
-  if (hipMemcpyAsync(d_table, tab.data(), tab.size() * sizeof(JobEntry), hipMemcpyHostToDevice,
-                     stream) != hipSuccess ||
-      hipStreamSynchronize(stream) != hipSuccess)
+  if (note_hip(hipMemcpyAsync(d_table, tab.data(), tab.size() * sizeof(JobEntry),
+                              hipMemcpyHostToDevice, stream)) != hipSuccess ||
+      note_hip(hipStreamSynchronize(stream)) != hipSuccess)
     return GFO_EHIP;
   return GFO_OK;
 }
 
 extern "C" int gfo_greedy_steps_table(const gfo_problem* probs, gfo_state* states, int32_t n_jobs,
                                       int32_t n_steps, const void* d_table, hipStream_t stream) {
+  discard_stale_hip();
   std::vector<Geo> geos;
   std::vector<Layout> lays;
   int rc = check_group(probs, states, n_jobs, &geos, &lays);

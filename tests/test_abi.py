@@ -121,6 +121,8 @@ def test_k1_variants_listed():
     assert L.flush_get_variant() == 4
     assert L.rk_variants()[0] == "acc64" and len(set(L.rk_variants())) == len(L.rk_variants())
     assert L.lib().gfo_strerror(L.GFO_ENOSPC) == b"workspace too small"
+    # no HIP call of the library has failed on this thread
+    assert L.lib().gfo_last_hip_error(None) == 0
 
 
 def test_choose_eps_greedy_rejects_bad_arguments_on_host():
@@ -256,3 +258,20 @@ def test_packed_storage_sizes_and_refusals():
     st.packed = 1
     assert lib.apply_flips_rank_k(C.byref(pr), C.byref(st), picks, 4, L.GFO_FP32, None) == L.GFO_EINVAL
     assert lib.gfo_sync_lower(C.byref(pr), C.byref(st), None) == L.GFO_EINVAL
+
+
+def test_one_hip_runtime_when_the_library_loads_first():
+    """Loaded before torch is imported, libgfo still binds to the HIP runtime of
+    torch's wheel: the process maps one libamdhip64."""
+    import subprocess
+    import sys
+    script = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2202_05388_amd import _lib as L\n"
+        "L.lib()\n"
+        "import torch\n"
+        "maps = open('/proc/self/maps').read().splitlines()\n"
+        "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", script], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().splitlines()[-1] == "1"
