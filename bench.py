@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 MFMA_PEAK_TFLOPS = {"c64": 157.3, "c128": 78.6}     # dense FP32 / FP64 matrix peaks
+BF16_PEAK_TFLOPS = 2500.0                           # dense BF16 matrix peak
 
 # HBM traffic per launch from rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE in KiB
 # per dispatch), each scaled by what the same counter reports for a device copy of
@@ -188,14 +189,23 @@ def flush_alg_bytes(variant, dtype, N, ld, n_mon=0):
     return {"up": 8, None: 16}[flush_triangle(variant)] * N * ld + mon
 
 
+def flush_split(variant, dtype, terms):
+    """True when the flush of `terms` terms runs the split-product kernel (FP32
+    products as six BF16 part products; the launcher takes it for 17 to 64
+    terms and the pair flush otherwise)."""
+    return dtype == "c64" and str(variant) == "up_bandseg_s3" and 16 < terms <= 64
+
+
 def flush_mfma_flops(variant, dtype, N, ld, n_mon, terms):
     """Matrix-core flops of one flush that folds `terms` pending terms: real
     flops of the complex products over the 64 x 64 tiles the kernel computes
     (for the triangle variants and the complex128 flush, the tiles on and above
     the diagonal of the design block, plus the monitor rows where the kernel
     covers them), 2 flops per real product and three real products per complex
-    one in the _3m variants (four otherwise).  Only the terms actually folded
-    count, not the zero padding up to the kernel's term bucket."""
+    one in the _3m variants (four otherwise); the split-product kernel issues
+    four real products per complex one, each as six BF16 part products.  Only
+    the terms actually folded count, not the zero padding up to the kernel's
+    term bucket."""
     nb = (N + 63) // 64
     if dtype != "c64":
         tiles = nb * (nb + 1) // 2 + (n_mon + 63) // 64 * (ld // 64)
@@ -205,8 +215,15 @@ def flush_mfma_flops(variant, dtype, N, ld, n_mon, terms):
         tiles = nb * (nb + 1) // 2 if tri else nb * (ld // 64)
         if flush_covers_monitors(variant):
             tiles += (n_mon + 63) // 64 * (ld // 64)
-        per = 6 if "3m" in str(variant) else 8
+        # the split variant runs the three-product pair flush outside 17 to 64 terms
+        three = "3m" in str(variant) or str(variant) == "up_bandseg_s3"
+        per = 48 if flush_split(variant, dtype, terms) else 6 if three else 8
     return float(per) * 64 * 64 * tiles * terms
+
+
+def flush_mfma_peak(variant, dtype, terms):
+    """Dense matrix peak (TFLOP/s) of the instructions the flush of `terms` terms issues."""
+    return BF16_PEAK_TFLOPS if flush_split(variant, dtype, terms) else MFMA_PEAK_TFLOPS[dtype]
 
 
 def flush_roofline(variant, dtype, N, ld, n_mon, terms, ms):
@@ -215,11 +232,14 @@ def flush_roofline(variant, dtype, N, ld, n_mon, terms, ms):
     summed kernel time; the bound is the larger of the two ideal times."""
     if not ms:
         return None
-    flops = sum(flush_mfma_flops(variant, dtype, N, ld, n_mon, r) for r in terms)
+    fl = [flush_mfma_flops(variant, dtype, N, ld, n_mon, r) for r in terms]
+    flops = sum(fl)
     nbytes = flush_alg_bytes(variant, dtype, N, ld, n_mon) * len(ms)
     secs = sum(ms) * 1e-3
-    peak = MFMA_PEAK_TFLOPS[dtype]
-    t_mfma, t_hbm = flops / (peak * 1e12), nbytes / (HBM_PEAK_GBS * 1e9)
+    # each flush's matrix work at the peak of the instructions it issues
+    t_mfma = sum(f / (flush_mfma_peak(variant, dtype, r) * 1e12) for f, r in zip(fl, terms))
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    peak = flops / t_mfma / 1e12 if t_mfma > 0 else MFMA_PEAK_TFLOPS[dtype]
     common = dict(avg_launch_us=1e6 * secs / len(ms), launches=len(ms),
                   mean_terms=sum(terms) / len(terms), mfma_flops_per_launch=flops / len(ms),
                   algorithmic_bytes_per_launch=nbytes / len(ms), variant=variant)
@@ -926,7 +946,9 @@ def main():
                 f"{'fused greedy loop (gfo_greedy_steps)' if d['fused'] else 'per-call'}")
         head_value = d["steps_per_s"]
         head_ms = d["ms_per_step"]
-        kind = "FP32" if problem.dtype == "c64" else "FP64"
+        kind = ("FP64" if problem.dtype != "c64" else
+                "FP32 products as BF16 part products on the" if d["flush_variant"] == "up_bandseg_s3"
+                else "FP32")
         roofline = dict(d["flush_roofline"])
         # counters per term bucket, averaged over the flushes of the window
         roofline.update(kernel=f"flush of the deferred updates, {kind} MFMA, variant "

@@ -560,12 +560,337 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
 }
 
 
+// ---------------------------------------------------------------------------
+// Split-product flush: the FP32 products on the BF16 matrix cores.  Each FP32
+// operand x is split into three BF16 parts, x = x0 + x1 + x2 + r with |r| at
+// most about 2^-26 |x| (x0 the nearest BF16 to x, x1 to x - x0, x2 to
+// x - x0 - x1; every difference is exact in FP32), and a product a b is summed
+// from the six part products a_i b_j with i + j <= 2.  Each part product is
+// exact in FP32 and the matrix core accumulates in FP32; the three dropped ones
+// are below 2^-26 |a||b|, so the sum has the accuracy of an FP32 product (the
+// split itself is the standard error-free splitting of a floating-point number
+// into shorter ones).  v_mfma_f32_32x32x16_bf16 takes 16 terms in 32 cycles
+// where v_mfma_f32_32x32x2f32 takes 2 in 64: with six part products and four
+// real products per complex one, a term costs half the matrix-core cycles of
+// the three-product FP32 form.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split3(float x, __bf16& x0, __bf16& x1, __bf16& x2) {
+  x0 = (__bf16)x;
+  const float r1 = x - (float)x0;
+  x1 = (__bf16)r1;
+  x2 = (__bf16)(r1 - (float)x1);
+}
+
+// Split planes of the pending terms.  Unit u = 6 (2 c + h) + p holds, for each
+// index i, slots 16 c + 8 h + j (j < 8) of plane p: 0-2 the parts of the real
+// part, 3-5 those of the imaginary part; 16 bytes, zero past the count.
+// A3[u R + i] from CU (i < R), V3[u ld + i] from V (i < ld).  Grid: x over
+// max(R, ld) / 256, y over the 2 KC (c, h) groups.
+template <int KC>
+__global__ __launch_bounds__(256) void k_flush_pack_s3(int R, int64_t ld,
+                                                       const int32_t* __restrict__ count,
+                                                       const float2* __restrict__ CU,
+                                                       const float2* __restrict__ V,
+                                                       bf16x8* __restrict__ A3, bf16x8* __restrict__ V3) {
+  const int K = *count;
+  const int ch = (int)blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  auto emit = [&](const float2* src, int64_t n, bf16x8* dst) {
+    if (i >= n) return;
+    bf16x8 pl[6];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int s = 8 * ch + j;
+      const float2 z = s < K ? src[(int64_t)s * n + i] : make_float2(0.f, 0.f);
+      __bf16 a, b, c;
+      split3(z.x, a, b, c);
+      pl[0][j] = a;
+      pl[1][j] = b;
+      pl[2][j] = c;
+      split3(z.y, a, b, c);
+      pl[3][j] = a;
+      pl[4][j] = b;
+      pl[5][j] = c;
+    }
+#pragma unroll
+    for (int p = 0; p < 6; ++p) dst[(int64_t)(6 * ch + p) * n + i] = pl[p];
+  };
+  emit(CU, R, A3);
+  emit(V, ld, V3);
+}
+
+// Position of a persistent flush run in the tile list in column segments of 32
+// tiles (segment j: columns [32 j, 32 j + 32)); inside a segment the triangle's
+// rows top to bottom, then the monitor bands, each row left to right.
+struct SegTile {
+  int band, bx, lim, rbase, seg;
+};
+struct SegWalk {
+  int M, R, nby, nbx, nmb;
+  __device__ int seg_tri(int j) const {
+    const int s0 = 32 * j;
+    if (s0 >= nby) return 0;
+    const int wd = (s0 + 32 < nby ? s0 + 32 : nby) - s0;
+    return s0 * wd + wd * (wd + 1) / 2;
+  }
+  __device__ int seg_mon(int j) const {
+    const int s0 = 32 * j;
+    return nmb * ((s0 + 32 < nbx ? s0 + 32 : nbx) - s0);
+  }
+  __device__ SegTile at(int t) const {
+    SegTile c{0, 0, M, 0, 0};
+    int u = t;
+    while (u >= seg_tri(c.seg) + seg_mon(c.seg)) {
+      u -= seg_tri(c.seg) + seg_mon(c.seg);
+      ++c.seg;
+    }
+    const int s0 = 32 * c.seg, nt = seg_tri(c.seg);
+    if (u < nt) {
+      const int e = s0 + 32 < nby ? s0 + 32 : nby, wd = e - s0;
+      if (u < s0 * wd) {
+        c.band = u / wd;
+        c.bx = s0 + u % wd;
+      } else {
+        u -= s0 * wd;
+        c.band = s0;
+        while (u >= e - c.band) {
+          u -= e - c.band;
+          ++c.band;
+        }
+        c.bx = c.band + u;
+      }
+      c.rbase = c.band * 64;
+    } else {
+      u -= nt;
+      const int wd = (s0 + 32 < nbx ? s0 + 32 : nbx) - s0;
+      c.band = nby + u / wd;
+      c.bx = s0 + u % wd;
+      c.lim = R;
+      c.rbase = M + (u / wd) * 64;
+    }
+    return c;
+  }
+  // the tile after c (c itself when the list ends there)
+  __device__ SegTile next(const SegTile& c) const {
+    SegTile n = c;
+    const int s0 = 32 * c.seg;
+    bool next_seg = false;
+    if (c.band < nby) {
+      const int e = s0 + 32 < nby ? s0 + 32 : nby;
+      if (c.bx + 1 < e) {
+        n.bx = c.bx + 1;
+      } else if (c.band + 1 < e) {
+        n.band = c.band + 1;
+        n.bx = n.band > s0 ? n.band : s0;
+        n.rbase = n.band * 64;
+      } else if (nmb > 0) {
+        n.band = nby;
+        n.bx = s0;
+        n.lim = R;
+        n.rbase = M;
+      } else {
+        next_seg = true;
+      }
+    } else {
+      const int f = s0 + 32 < nbx ? s0 + 32 : nbx;
+      if (c.bx + 1 < f) {
+        n.bx = c.bx + 1;
+      } else if (c.band + 1 < nby + nmb) {
+        n.band = c.band + 1;
+        n.bx = s0;
+        n.rbase = c.rbase + 64;
+      } else {
+        next_seg = true;
+      }
+    }
+    if (next_seg) {
+      if (s0 + 32 >= nbx) return c;
+      n.seg = c.seg + 1;
+      n.bx = s0 + 32;
+      if (n.bx < nby) {
+        n.band = 0;
+        n.lim = M;
+        n.rbase = 0;
+      } else {
+        n.band = nby;
+        n.lim = R;
+        n.rbase = M;
+      }
+    }
+    return n;
+  }
+};
+
+// Persistent band flush with split products (KC chunks of 16 terms: 2 for up to
+// 32 terms, 4 for up to 64).  Same tile list, run assignment, G buffers and
+// epilogue layout as k_flush_c64_band in column-segment order; per wave the
+// output is the 32 x 32 block (rows 32 (w >> 1), columns 32 (w & 1)) of the
+// tile, accumulated as XR = sum Ar Br, XI = sum Ai Bi, Z = sum (Ar Bi + Ai Br).
+// Operands:
+//   - A (the row band's split CU planes, 6 KC x 16 bytes per lane) stays in
+//     registers while the run stays in the band;
+//   - B (the tile's split V planes, 12 KC units x 64 columns) sits in LDS in two
+//     halves, chunks [0, KC/2) and [KC/2, KC); each half of the next tile is
+//     read into registers while the current tile's matrix steps run on the
+//     other half, and written into its half after a barrier;
+//   - G(t+1) is read into registers after tile t's epilogue, in flight during
+//     tile t+1's matrix steps.
+// Global loads of one wave retire in order; the order per tile, B(t+2) first
+// half, then G(t+1), lets the first-half write of the next tile wait for its
+// B loads while G(t+1) is still in flight.  Rows past the matrix read zero and
+// their stores are dropped (buffer ranges), so every load and store is
+// unconditional.
+template <int KC>
+__global__ __launch_bounds__(256, 2) void k_flush_c64_s3(int M, int R, int64_t ld,
+                                                      const int32_t* __restrict__ count,
+                                                      const bf16x8* __restrict__ A3,
+                                                      const bf16x8* __restrict__ V3,
+                                                      float2* __restrict__ G, int nby, int chunk,
+                                                      int packed, int64_t mon_base) {
+  constexpr int NU = 12 * KC;         // split units per index
+  constexpr int HU = NU / 2;          // units per LDS half
+  constexpr int NS = HU * 64 / 256;   // 16-byte staging loads per thread per half
+  const int K = *count;
+  if (K == 0) return;
+  const SegWalk walk{M, R, nby, (int)(ld / 64), (R - M + 63) / 64};
+  const int T = nby * (nby + 1) / 2 + walk.nmb * walk.nbx;
+  const int P = (int)gridDim.x, b = (int)blockIdx.x;
+  const int run = (P & 7) == 0 ? (b & 7) * (P >> 3) + (b >> 3) : b;
+  const int t0 = run * chunk;
+  const int t1 = t0 + chunk < T ? t0 + chunk : T;
+  if (t0 >= t1) return;
+  __shared__ bf16x8 Bsh[NU][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const __amdgpu_buffer_rsrc_t ra =
+      __builtin_amdgcn_make_buffer_rsrc((void*)A3, (short)0, NU * R * 16, kBufferDword3);
+  const __amdgpu_buffer_rsrc_t rb =
+      __builtin_amdgcn_make_buffer_rsrc((void*)V3, (short)0, (int)(NU * ld * 16), kBufferDword3);
+  const int q = (w >> 1) * 32 + (lane & 31);   // row of the band (A operand)
+  const int cc = (w & 1) * 32 + (lane & 31);  // column of the tile (B operand)
+  const int lrow = (w >> 1) * 32 + 4 * h;     // the lane's first output row within a tile
+  bf16x8 aR[6 * KC];
+  auto load_A = [&](const SegTile& c) {
+    const int am = c.rbase + q;
+    const unsigned off = am < c.lim ? (unsigned)am * 16u : 0xFFFFFFF0u;
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+#pragma unroll
+      for (int p = 0; p < 6; ++p) {
+        const unsigned u = (unsigned)(6 * (2 * k + h) + p);
+        aR[6 * k + p] = __builtin_bit_cast(
+            bf16x8, __builtin_amdgcn_raw_buffer_load_b128(ra, am < c.lim ? off + u * (unsigned)R * 16u : off, 0, 0));
+      }
+  };
+  bf16x8 S[NS];
+  auto load_S = [&](int bx, int half) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int e = j * 256 + (int)threadIdx.x;
+      const unsigned off = (unsigned)((int64_t)(half * HU + (e >> 6)) * ld + bx * 64 + (e & 63)) * 16u;
+      S[j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb, off, 0, 0));
+    }
+  };
+  auto write_S = [&](int half) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int e = j * 256 + (int)threadIdx.x;
+      Bsh[half * HU + (e >> 6)][e & 63] = S[j];
+    }
+  };
+  auto g_rsrc = [&](const SegTile& c, int64_t& stride) {
+    const int rows = c.lim - c.rbase < 64 ? c.lim - c.rbase : 64;
+    const TileAt ta = tile_at(packed, M, ld, mon_base, c.rbase, c.bx);
+    stride = ta.stride;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(G + ta.base), (short)0,
+                                             (int)((int64_t)rows * ta.stride * 8), kBufferDword3);
+  };
+  auto lane_off = [&](int64_t stride) { return (unsigned)((int64_t)lrow * stride + cc) * 8u; };
+  auto row_off = [&](int64_t stride, int e) { return (int)((int64_t)(8 * (e >> 2) + (e & 3)) * stride * 8); };
+  float2 gG[16];
+  auto load_G = [&](__amdgpu_buffer_rsrc_t rg, int64_t stride) {
+    const unsigned vo = lane_off(stride);
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      gG[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, vo, row_off(stride, e), 2));
+  };
+  f32x16 XR, XI, Z;
+  // the matrix steps of chunks [k0, k1) against the B units in LDS
+  auto steps = [&](int k0, int k1) {
+#pragma unroll
+    for (int k = k0; k < k1; ++k) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const bf16x8 br = Bsh[6 * (2 * k + h) + j][cc];
+        const bf16x8 bi = Bsh[6 * (2 * k + h) + 3 + j][cc];
+#pragma unroll
+        for (int i = 0; i + j < 3; ++i) {
+          const bf16x8 ar = aR[6 * k + i], ai = aR[6 * k + 3 + i];
+          XR = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, br, XR, 0, 0, 0);
+          Z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, bi, Z, 0, 0, 0);
+          XI = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai, bi, XI, 0, 0, 0);
+          Z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai, br, Z, 0, 0, 0);
+        }
+      }
+    }
+  };
+  // prologue: tile t0's operands and B, then the next tile's first half and G(t0)
+  SegTile cur = walk.at(t0);
+  SegTile nxt = t0 + 1 < t1 ? walk.next(cur) : cur;
+  load_A(cur);
+  load_S(cur.bx, 0);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  write_S(0);
+  load_S(cur.bx, 1);
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  write_S(1);
+  load_S(nxt.bx, 0);
+  int64_t scur;
+  __amdgpu_buffer_rsrc_t rcur = g_rsrc(cur, scur);
+  load_G(rcur, scur);
+  __syncthreads();
+  if ((run & 1) && (P & 7) == 0) __builtin_amdgcn_s_sleep(48);
+  for (int t = t0; t < t1; ++t) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) XR[e] = XI[e] = Z[e] = 0.f;
+    steps(0, KC / 2);
+    __syncthreads();  // every wave is done with the first half
+    write_S(0);       // the next tile's first half (waits for its loads, not for G)
+    load_S(nxt.bx, 1);
+    steps(KC / 2, KC);
+    if (nxt.band != cur.band) {
+      load_A(nxt);
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+    }
+    __syncthreads();  // every wave is done with the second half
+    write_S(1);
+    __builtin_amdgcn_sched_barrier(0);
+    const unsigned vo = lane_off(scur);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const f32x2 o = {gG[e].x + (XR[e] - XI[e]), gG[e].y + Z[e]};
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, o), rcur, vo, row_off(scur, e), 2);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // B(t+2) first half, then G(t+1)
+    const SegTile nn = t + 2 < t1 ? walk.next(nxt) : nxt;
+    load_S(nn.bx, 0);
+    cur = nxt;
+    nxt = nn;
+    rcur = g_rsrc(cur, scur);
+    load_G(rcur, scur);
+  }
+}
+
 // flush variants for complex64 storage (selected by the autotuner; all give the
-// eager results to FP32 rounding, tests/test_gpu_deferred.py)
+// eager results to FP32 rounding, tests/test_gpu_deferred.py).  The default,
+// up_bandseg_s3: the split-product band flush for 17 to 64 terms, the pair
+// flush in XCD tile order otherwise.
 static const char* const kFlushNames[] = {"w32_3m", "up_pair4_3m_nt", "up_pair4_3m_nt_x8", "up_band4_3m_nt",
-                                          "up_bandseg4_3m_nt"};
+                                          "up_bandseg4_3m_nt", "up_bandseg_s3"};
 constexpr int kFlushCount = (int)(sizeof(kFlushNames) / sizeof(kFlushNames[0]));
-constexpr int kFlushDefault = 4;
+constexpr int kFlushDefault = 5;
 static std::atomic<int> g_flush_sel{kFlushDefault};
 int flush_variant_count() { return kFlushCount; }
 const char* flush_variant_name(int i) { return i >= 0 && i < kFlushCount ? kFlushNames[i] : nullptr; }
@@ -623,6 +948,32 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
                            0);
         break;
       default: {
+        const int bound = st->pending_calls;
+        // split products: 17 to 64 terms (the matrix work of up to 16 terms hides
+        // behind the G stream in the pair form); 32-bit offsets into G tiles
+        if (fv == 5 && bound > 16 && bound <= 64 && g.ld * 64 * 8 < ((int64_t)1 << 31)) {
+          const int nb = (g.N + 63) / 64;
+          const int nmb = (g.nmon + 63) / 64, nbx = (int)(g.ld / 64);
+          bf16x8* a3 = (bf16x8*)(w + L.dl_CUs + (size_t)GFO_MAX_DELAY * g.R * 8);
+          bf16x8* v3 = (bf16x8*)(w + L.dl_Vs + (size_t)GFO_MAX_DELAY * g.ld * 8);
+          const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
+          const dim3 pg((unsigned)((nx + 255) / 256), bound <= 32 ? 4u : 8u);
+          const int P = band_workgroups();
+          const int T = nb * (nb + 1) / 2 + nmb * nbx;
+          if (bound <= 32) {
+            hipLaunchKernelGGL(k_flush_pack_s3<2>, pg, blk, 0, s, g.R, g.ld, count, cu, vv, a3, v3);
+            hipLaunchKernelGGL(k_flush_c64_s3<2>, dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count,
+                               (const bf16x8*)a3, (const bf16x8*)v3, G, nb, (T + P - 1) / P, g.packed,
+                               g.mon_base);
+          } else {
+            hipLaunchKernelGGL(k_flush_pack_s3<4>, pg, blk, 0, s, g.R, g.ld, count, cu, vv, a3, v3);
+            hipLaunchKernelGGL(k_flush_c64_s3<4>, dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count,
+                               (const bf16x8*)a3, (const bf16x8*)v3, G, nb, (T + P - 1) / P, g.packed,
+                               g.mon_base);
+          }
+          monitors_done = true;
+          break;
+        }
         // upper triangle only, pair-interleaved terms in the unused halves of
         // the term buffers (complex64 slots take 8 of their 16 bytes)
         const int nb = (g.N + 63) / 64;
@@ -634,10 +985,10 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         // the triangle's tiles, then the monitor rows' (no separate monitor kernel)
         const int nmb = (g.nmon + 63) / 64, nbx = (int)(g.ld / 64);
         unsigned ntiles = (unsigned)(nb * (nb + 1) / 2 + nmb * nbx);
-        // the default keeps every operand re-read in the XCD's L2: the band form
-        // (column segments) for 33 to 64 terms, the XCD tile order otherwise (at
-        // 128 terms: 1.05x the minimal HBM traffic instead of 1.8x, 2 % slower)
-        const bool xord = fv == 2 || fv == 4;
+        // the XCD tile order keeps every operand re-read in the XCD's L2 (at 128
+        // terms: 1.05x the minimal HBM traffic instead of 1.8x, 2 % slower); the
+        // band form in column segments does for 33 to 64 terms
+        const bool xord = fv == 2 || fv >= 4;
         // the band form addresses a 64-row G tile with 32-bit byte offsets
         const bool band = (fv == 3 || fv == 4) && g.ld * 64 * 8 < ((int64_t)1 << 31);
         if (xord) {
@@ -650,7 +1001,6 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         }
         const dim3 tri(ntiles);
         monitors_done = true;
-        const int bound = st->pending_calls;
         const f32x4* c2 = (const f32x4*)cu2;
         const f32x4* v2 = (const f32x4*)vv2;
         if (bound <= 16) {

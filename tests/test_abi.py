@@ -117,8 +117,8 @@ def test_k1_variants_listed():
         assert len(names) >= 4 and len(set(names)) == len(names)
     assert L.lib().gfo_k1_set_variant(L.GFO_C64, 999) == L.GFO_EINVAL
     assert L.flush_variants() == ["w32_3m", "up_pair4_3m_nt", "up_pair4_3m_nt_x8", "up_band4_3m_nt",
-                                  "up_bandseg4_3m_nt"]
-    assert L.flush_get_variant() == 4
+                                  "up_bandseg4_3m_nt", "up_bandseg_s3"]
+    assert L.flush_get_variant() == 5
     assert L.rk_variants()[0] == "acc64" and len(set(L.rk_variants())) == len(L.rk_variants())
     assert L.lib().gfo_strerror(L.GFO_ENOSPC) == b"workspace too small"
     # no HIP call of the library has failed on this thread

@@ -16,7 +16,7 @@ def test_flush_minimal_bytes_per_variant():
     # complex128: the FP64 flush of the upper triangle and the monitor rows
     assert bench.flush_alg_bytes(None, "c128", N, ld, n_mon) == 16 * N * ld + 32 * n_mon * ld
     # the pair and band flushes also update the monitor rows (read and written once)
-    for v in ("up_pair4_3m_nt", "up_pair4_3m_nt_x8", "up_band4_3m_nt", "up_bandseg4_3m_nt"):
+    for v in ("up_pair4_3m_nt", "up_pair4_3m_nt_x8", "up_band4_3m_nt", "up_bandseg4_3m_nt", "up_bandseg_s3"):
         assert bench.flush_covers_monitors(v)
         assert bench.flush_alg_bytes(v, "c64", N, ld, n_mon) == 8 * N * ld + 16 * n_mon * ld
     assert not bench.flush_covers_monitors("w32_3m")
@@ -63,6 +63,26 @@ def test_flush_roofline_bound_follows_the_terms():
     r = bench.flush_roofline(v, "c64", N, ld, n_mon, [20], [0.40])
     assert r["bound"] == "hbm" and r["achieved"] == r["algorithmic_bytes_per_launch"] / 0.40e-3 / 1e9
     assert bench.flush_roofline(v, "c64", N, ld, n_mon, [], []) is None
+
+
+def test_split_flush_counts_bf16_part_products():
+    N, ld, n_mon = 16384, 16384, 64
+    v = "up_bandseg_s3"
+    # 17 to 64 terms: four real products per complex one, six BF16 part products each
+    f = bench.flush_mfma_flops(v, "c64", N, ld, n_mon, 64)
+    assert f == 8 * bench.flush_mfma_flops("up_pair4_3m_nt", "c64", N, ld, n_mon, 64)
+    assert bench.flush_mfma_peak(v, "c64", 64) == bench.BF16_PEAK_TFLOPS
+    # outside that range the launcher runs the FP32 pair flush
+    for t in (16, 65, 128):
+        assert bench.flush_mfma_flops(v, "c64", N, ld, n_mon, t) == bench.flush_mfma_flops(
+            "up_pair4_3m_nt", "c64", N, ld, n_mon, t)
+        assert bench.flush_mfma_peak(v, "c64", t) == bench.MFMA_PEAK_TFLOPS["c64"]
+    # at 64 terms in 0.46 ms the bytes bind (0.17 ms of BF16 matrix work at peak)
+    r = bench.flush_roofline(v, "c64", N, ld, n_mon, [64], [0.46])
+    assert r["bound"] == "hbm" and 0.55 < r["frac"] < 0.65
+    # a window that mixes kernels: each flush's matrix time at its own peak
+    r = bench.flush_roofline(v, "c64", N, ld, n_mon, [128, 128], [1.0, 1.0])
+    assert r["bound"] == "mfma" and abs(r["peak"] - bench.MFMA_PEAK_TFLOPS["c64"]) < 1e-9
 
 
 def test_host_info_fields():

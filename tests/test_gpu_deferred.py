@@ -173,6 +173,51 @@ def test_flush_variants_agree(delay):
 
 
 
+
+@pytest.mark.parametrize("ny,nx,n_mon,steps", [(60, 62, 20, 20), (60, 62, 20, 50), (64, 64, 70, 40),
+                                               (24, 26, 8, 60), (64, 64, 70, 64)])
+def test_split_flush_matches_pair_flush(ny, nx, n_mon, steps):
+    """The split-product flush (17 to 64 pending terms; each FP32 product summed
+    from six BF16 part products on the matrix cores) against the FP32 pair flush
+    after the same moves.  Both sum the same K terms onto G in FP32, each within
+    about K u max|G| of the exact sum (a term reaches at most max|G|), so the
+    upper triangle and the monitor rows agree to 4 K u max|G|; the fields,
+    diagonal and materials are not touched by the flush and agree bit for bit.
+    Cases: 20 terms (two chunks of 16) and 40 to 64 (four); ragged last band, one
+    and two monitor bands, fewer tiles than workgroups."""
+    import torch
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(ny, nx, n_mon=n_mon, dtype="c64", cand_mask=W.MASK_BOTH, tau=1e-6)
+    names = L.flush_variants()
+    old = L.flush_get_variant()
+    out = {}
+    try:
+        for name in ("up_pair4_3m_nt", "up_bandseg_s3"):
+            L.flush_set_variant(names.index(name))
+            print(f"[case] {ny}x{nx} n_mon {n_mon}: {steps} pending terms, flush {name}", flush=True)
+            job = _job(p, delay=128)
+            job.init()
+            job.run_greedy(steps, poll_every=steps)
+            K = job.state.pending_calls
+            assert 17 <= K <= 64, K
+            job.flush()
+            torch.cuda.synchronize()
+            N = p.n
+            G = job.G[:, :N].cpu().numpy()
+            iu = np.triu_indices(N)
+            out[name] = (K, G[:N][iu].copy(), G[N:].copy(), job.history(), job.host_state()[1:])
+    finally:
+        L.flush_set_variant(old)
+    Ka, ua, ma, ha, sa = out["up_pair4_3m_nt"]
+    Kb, ub, mb, hb, sb = out["up_bandseg_s3"]
+    assert Ka == Kb and np.array_equal(ha, hb)
+    tol = 4 * Ka * 2.0 ** -24
+    assert _rel(ub, ua, floor=1.0) <= tol
+    assert _rel(mb, ma, floor=1.0) <= tol
+    for x, y in zip(sa, sb):
+        assert np.array_equal(x, y)
+
+
 @pytest.mark.parametrize("ny,nx,n_mon,steps", [(60, 62, 20, 50), (64, 64, 70, 40), (24, 26, 8, 60),
                                                (60, 62, 20, 100)])
 def test_band_flush_equals_pair_flush_bitwise(ny, nx, n_mon, steps):
@@ -307,7 +352,7 @@ def test_upper_only_flush_then_sync_lower():
     eager.init()
     n_ref = eager.run_greedy(150, poll_every=25)
     Ge, Ee, de, ie = eager.host_state()
-    assert L.flush_variants()[L.flush_get_variant()] == "up_bandseg4_3m_nt"
+    assert L.flush_variants()[L.flush_get_variant()] == "up_bandseg_s3"
     job = _job(p, delay=64)
     job.init()
     assert job.state.lower_stale == 1               # init_G0 filled the upper triangle only

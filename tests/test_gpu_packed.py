@@ -64,7 +64,7 @@ def test_packed_equals_dense_bitwise(ny, nx, n_mon, dtype, delay):
 
 
 @pytest.mark.parametrize("variant", ["up_pair4_3m_nt", "up_pair4_3m_nt_x8", "up_band4_3m_nt",
-                                     "up_bandseg4_3m_nt", "w32_3m"])
+                                     "up_bandseg4_3m_nt", "up_bandseg_s3", "w32_3m"])
 def test_packed_flush_variants(variant):
     """Every complex64 flush variant on packed storage (the non-symmetric one
     falls back to the pair kernel there) gives the dense result of the same
