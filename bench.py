@@ -37,14 +37,14 @@ BF16_PEAK_TFLOPS = 2500.0                           # dense BF16 matrix peak
 FETCH_SCALE = 2097152.0 / 1048599.75
 WRITE_SCALE = 1.0
 PMC_TRAFFIC = [
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_rank1.hip", "sha256": "ce1af5cc48984ca588038afcb039097a02bee46cd883c6fd06b0ef5a615e2c8d", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053784.0, "write_kib": 2105344.0},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_rank1.hip", "sha256": "a79143cebd95fd21cd0b1947163a604110a9ea7aa74dcfa84733f42172133799", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053784.0, "write_kib": 2105344.0},
     # complex64 flush records: one per term bucket (the launcher's kernel for up to 16, 32, 64
-    # or 128 pending terms) of the default variant, each taken on full flushes: the tile
-    # kernel, then the pack kernel
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "1a60e809185c92df6351811eece726586e982d71df1ee23e5a9de2e3fb35443f", "workload": "square128_c64", "variant": "up_bandseg4_3m_nt", "bucket": 16, "tile_kernel": "k_flush_c64_pair<4, 4, true>", "fetch_kib": 539644.0 + 2059.0, "write_kib": 1060896.0 + 4104.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "1a60e809185c92df6351811eece726586e982d71df1ee23e5a9de2e3fb35443f", "workload": "square128_c64", "variant": "up_bandseg4_3m_nt", "bucket": 32, "tile_kernel": "k_flush_c64_pair<4, 8, true>", "fetch_kib": 549316.0 + 4111.0, "write_kib": 1060867.0 + 8208.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "1a60e809185c92df6351811eece726586e982d71df1ee23e5a9de2e3fb35443f", "workload": "square128_c64", "variant": "up_bandseg4_3m_nt", "bucket": 64, "tile_kernel": "k_flush_c64_band<16, true>", "fetch_kib": 579270.0 + 8215.5, "write_kib": 1060873.0 + 16416.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "1a60e809185c92df6351811eece726586e982d71df1ee23e5a9de2e3fb35443f", "workload": "square128_c64", "variant": "up_bandseg4_3m_nt", "bucket": 128, "tile_kernel": "k_flush_c64_pair<4, 32, true>", "fetch_kib": 610541.5 + 16423.5, "write_kib": 1060864.0 + 32832.0},
+    # or 128 pending terms) of the default variant, each taken on flushes that fold the
+    # bucket's full term count: the tile kernel, then the pack kernel
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "76612e234509950bcc76980789a441479b373296ecd318cb6383560e1a2c2498", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 16, "tile_kernel": "k_flush_c64_pair<4, 4, true>", "fetch_kib": 539638.5 + 2063.0, "write_kib": 1060873.4 + 4104.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "76612e234509950bcc76980789a441479b373296ecd318cb6383560e1a2c2498", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 32, "tile_kernel": "k_flush_c64_s3<2>", "fetch_kib": 562283.6 + 4131.0, "write_kib": 1060888.6 + 12312.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "76612e234509950bcc76980789a441479b373296ecd318cb6383560e1a2c2498", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 64, "tile_kernel": "k_flush_c64_s3<4>", "fetch_kib": 634001.5 + 8235.0, "write_kib": 1060874.6 + 24624.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "76612e234509950bcc76980789a441479b373296ecd318cb6383560e1a2c2498", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 128, "tile_kernel": "k_flush_c64_pair<4, 32, true>", "fetch_kib": 610572.9 + 16428.0, "write_kib": 1060864.1 + 32832.0},
 ]
 
 

@@ -88,16 +88,18 @@ def time_k1_variants(job, reps: int = 10, warm: int = 2, variants=None) -> list:
     return out
 
 
-def tune(job, reps: int = 10, save: bool = True) -> dict:
-    """Time all variants on this job's shape, select and cache the fastest."""
+def tune(job, reps: int = 10, save: bool = True, variants=None) -> dict:
+    """Time the variants (default all; else a list of names) on this job's
+    shape, select and cache the fastest."""
     t0 = time.time()
-    res = time_k1_variants(job, reps=reps)
+    code = L.GFO_C64 if job.dtype_name == "c64" else L.GFO_C128
+    idxs = None if variants is None else [L.k1_variants(code).index(v) for v in variants]
+    res = time_k1_variants(job, reps=reps, variants=idxs)
     elem = 8 if job.dtype_name == "c64" else 16
     bytes_per = 2 * elem * job.N * job.R
     for r in res:
         r["gbs"] = bytes_per / (r["us"] * 1e-6) / 1e9
     best = min(res, key=lambda r: r["us"])
-    code = L.GFO_C64 if job.dtype_name == "c64" else L.GFO_C128
     L.k1_set_variant(code, best["variant"])
     entry = dict(variant=best["variant"], name=best["name"], us=best["us"], gbs=best["gbs"],
                  seconds=time.time() - t0, all=res)
@@ -313,7 +315,7 @@ if __name__ == "__main__":
     if args.kernel == "k1":
         job = Job(p, device="cuda:0")
         job.init()
-        e = tune(job, reps=args.reps, save=False)
+        e = tune(job, reps=args.reps, save=False, variants=sel)
         for r in sorted(e["all"], key=lambda r: r["us"]):
             print(f"{r['name']:>20s} {r['us']:9.1f} us {r['gbs']:7.0f} GB/s", flush=True)
         print(json.dumps({k: v for k, v in e.items() if k != "all"}))

@@ -419,11 +419,11 @@ __global__ __launch_bounds__(256) void k_rk_mfma(int R, int64_t ld,
 //   LDSEPI = true: the 32 x 128 product goes through LDS and G streams in
 //     16-byte pieces (1 KB row segments per wave), two barriers per row block.
 // G is read and written with non-temporal (streaming) loads and stores.
-// The launch bound keeps the FP32 rank-16 forms with one row tile within 128
-// registers (about 120 needed): three to four waves per SIMD, as LDS allows, and
-// more loads of G in flight than at two.
+// The launch bound keeps the FP32 rank-16 forms with one row tile and four row
+// blocks within 128 registers (about 120 needed): three to four waves per SIMD,
+// as LDS allows, and more loads of G in flight than at two.
 template <int KP, bool BF16, int RB, bool LDSEPI, int TM = 1>
-__global__ __launch_bounds__(256, (!BF16 && TM == 1 && KP == 16) ? 3 : 1) void k_rk_stream(int R, int64_t ld,
+__global__ __launch_bounds__(256, (!BF16 && TM == 1 && KP == 16 && RB <= 4) ? 3 : 1) void k_rk_stream(int R, int64_t ld,
                                                    const int32_t* __restrict__ gate_count,
                                                    const int32_t* __restrict__ gate_kp,
                                                    const float* __restrict__ Af,

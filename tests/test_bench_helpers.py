@@ -26,12 +26,12 @@ def test_counter_traffic_lookup():
     # unrecorded kernels, workloads, variants or buckets give no traffic figure
     assert bench.pmc_traffic("k_flush_c64", "square128_c64", "w32") is None
     assert bench.pmc_traffic("k_rank1", "strip48x2048_c64", "2x1x1_nt") is None
-    assert bench.flush_traffic("square128_c64", "up_bandseg4_3m_nt", []) is None
+    assert bench.flush_traffic("square128_c64", "up_bandseg_s3", []) is None
     assert bench.flush_traffic("square128_c64", "w32_3m", [64]) is None
     # a window's figure is the mean of its flushes' bucket records
-    per = {b: bench.pmc_traffic("k_flush_c64", "square128_c64", "up_bandseg4_3m_nt", b) for b in (16, 32, 64, 128)}
+    per = {b: bench.pmc_traffic("k_flush_c64", "square128_c64", "up_bandseg_s3", b) for b in (16, 32, 64, 128)}
     if all(v is not None for v in per.values()):
-        got = bench.flush_traffic("square128_c64", "up_bandseg4_3m_nt", [128, 62, 3])
+        got = bench.flush_traffic("square128_c64", "up_bandseg_s3", [128, 62, 3])
         assert abs(got - (per[128] + per[64] + per[16]) / 3) < 1.0
         # at least the tiles read and written once (the minimal 2.164 GB), within 1.15x
         assert all(2.16e9 < v < 1.15 * 2.165e9 for v in per.values())
