@@ -41,10 +41,10 @@ PMC_TRAFFIC = [
     # complex64 flush records: one per term bucket (the launcher's kernel for up to 16, 32, 64
     # or 128 pending terms) of the default variant, each taken on flushes that fold the
     # bucket's full term count: the tile kernel, then the pack kernel
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "76612e234509950bcc76980789a441479b373296ecd318cb6383560e1a2c2498", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 16, "tile_kernel": "k_flush_c64_pair<4, 4, true>", "fetch_kib": 539638.5 + 2063.0, "write_kib": 1060873.4 + 4104.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "76612e234509950bcc76980789a441479b373296ecd318cb6383560e1a2c2498", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 32, "tile_kernel": "k_flush_c64_s3<2>", "fetch_kib": 562283.6 + 4131.0, "write_kib": 1060888.6 + 12312.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "76612e234509950bcc76980789a441479b373296ecd318cb6383560e1a2c2498", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 64, "tile_kernel": "k_flush_c64_s3<4>", "fetch_kib": 634001.5 + 8235.0, "write_kib": 1060874.6 + 24624.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "76612e234509950bcc76980789a441479b373296ecd318cb6383560e1a2c2498", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 128, "tile_kernel": "k_flush_c64_pair<4, 32, true>", "fetch_kib": 610572.9 + 16428.0, "write_kib": 1060864.1 + 32832.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "ebc87557a26db2fe0297ddf4e3297d09fd9a055983e368e09957001ffd9935b0", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 16, "tile_kernel": "k_flush_c64_pair<4, 4, true>", "fetch_kib": 539636.2 + 2063.0, "write_kib": 1060869.2 + 4104.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "ebc87557a26db2fe0297ddf4e3297d09fd9a055983e368e09957001ffd9935b0", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 32, "tile_kernel": "k_flush_c64_s3<2>", "fetch_kib": 562331.2 + 4131.0, "write_kib": 1060891.8 + 12312.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "ebc87557a26db2fe0297ddf4e3297d09fd9a055983e368e09957001ffd9935b0", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 64, "tile_kernel": "k_flush_c64_s3<4>", "fetch_kib": 633296.6 + 8235.0, "write_kib": 1060867.1 + 24624.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "ebc87557a26db2fe0297ddf4e3297d09fd9a055983e368e09957001ffd9935b0", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 128, "tile_kernel": "k_flush_c64_pair<4, 32, true>", "fetch_kib": 610556.1 + 16428.0, "write_kib": 1060864.0 + 32832.0},
 ]
 
 

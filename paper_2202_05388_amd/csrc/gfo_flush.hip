@@ -6,6 +6,7 @@
 #include "gfo_internal.hpp"
 
 #include <atomic>
+#include <type_traits>
 
 namespace gfo {
 
@@ -281,6 +282,154 @@ __global__ __launch_bounds__(256) void k_flush_c64_pair(int M, int R, int64_t ld
 
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
+// Position of a persistent flush run in the tile list in column segments of sw
+// tiles (segment j: columns [sw j, sw j + sw)); inside a segment the triangle's
+// rows top to bottom, then the monitor bands, each row left to right.
+struct SegTile {
+  int band, bx, lim, rbase, seg;
+};
+struct SegWalk {
+  int M, R, nby, nbx, nmb, sw;   // sw: segment width in tiles
+  __device__ int seg_tri(int j) const {
+    const int s0 = sw * j;
+    if (s0 >= nby) return 0;
+    const int wd = (s0 + sw < nby ? s0 + sw : nby) - s0;
+    return s0 * wd + wd * (wd + 1) / 2;
+  }
+  __device__ int seg_mon(int j) const {
+    const int s0 = sw * j;
+    return nmb * ((s0 + sw < nbx ? s0 + sw : nbx) - s0);
+  }
+  __device__ SegTile at(int t) const {
+    SegTile c{0, 0, M, 0, 0};
+    int u = t;
+    while (u >= seg_tri(c.seg) + seg_mon(c.seg)) {
+      u -= seg_tri(c.seg) + seg_mon(c.seg);
+      ++c.seg;
+    }
+    const int s0 = sw * c.seg, nt = seg_tri(c.seg);
+    if (u < nt) {
+      const int e = s0 + sw < nby ? s0 + sw : nby, wd = e - s0;
+      if (u < s0 * wd) {
+        c.band = u / wd;
+        c.bx = s0 + u % wd;
+      } else {
+        u -= s0 * wd;
+        c.band = s0;
+        while (u >= e - c.band) {
+          u -= e - c.band;
+          ++c.band;
+        }
+        c.bx = c.band + u;
+      }
+      c.rbase = c.band * 64;
+    } else {
+      u -= nt;
+      const int wd = (s0 + sw < nbx ? s0 + sw : nbx) - s0;
+      c.band = nby + u / wd;
+      c.bx = s0 + u % wd;
+      c.lim = R;
+      c.rbase = M + (u / wd) * 64;
+    }
+    return c;
+  }
+  // the tile after c (c itself when the list ends there)
+  __device__ SegTile next(const SegTile& c) const {
+    SegTile n = c;
+    const int s0 = sw * c.seg;
+    bool next_seg = false;
+    if (c.band < nby) {
+      const int e = s0 + sw < nby ? s0 + sw : nby;
+      if (c.bx + 1 < e) {
+        n.bx = c.bx + 1;
+      } else if (c.band + 1 < e) {
+        n.band = c.band + 1;
+        n.bx = n.band > s0 ? n.band : s0;
+        n.rbase = n.band * 64;
+      } else if (nmb > 0) {
+        n.band = nby;
+        n.bx = s0;
+        n.lim = R;
+        n.rbase = M;
+      } else {
+        next_seg = true;
+      }
+    } else {
+      const int f = s0 + sw < nbx ? s0 + sw : nbx;
+      if (c.bx + 1 < f) {
+        n.bx = c.bx + 1;
+      } else if (c.band + 1 < nby + nmb) {
+        n.band = c.band + 1;
+        n.bx = s0;
+        n.rbase = c.rbase + 64;
+      } else {
+        next_seg = true;
+      }
+    }
+    if (next_seg) {
+      if (s0 + sw >= nbx) return c;
+      n.seg = c.seg + 1;
+      n.bx = s0 + sw;
+      if (n.bx < nby) {
+        n.band = 0;
+        n.lim = M;
+        n.rbase = 0;
+      } else {
+        n.band = nby;
+        n.lim = R;
+        n.rbase = M;
+      }
+    }
+    return n;
+  }
+};
+
+// The same list in row-major order: the triangle's rows top to bottom, each
+// left to right, then the monitor bands.
+struct RowWalk {
+  int M, R, nby, nbx, nmb;
+  __device__ SegTile at(int t) const {
+    SegTile c{0, 0, M, 0, 0};
+    const int ntri = nby * (nby + 1) / 2;
+    if (t < ntri) {
+      tri_tile(t, nby, c.band, c.bx);
+      c.rbase = c.band * 64;
+    } else {
+      const int u = t - ntri;
+      c.bx = u % nbx;
+      c.band = nby + u / nbx;
+      c.lim = R;
+      c.rbase = M + (u / nbx) * 64;
+    }
+    return c;
+  }
+  // the tile after c (the caller asks only while one follows)
+  __device__ SegTile next(const SegTile& c) const {
+    SegTile n = c;
+    if (c.band < nby) {
+      if (c.bx + 1 < nby) {
+        n.bx = c.bx + 1;
+      } else if (c.band + 1 < nby) {
+        n.band = c.band + 1;
+        n.bx = n.band;
+        n.rbase = n.band * 64;
+      } else {
+        n.band = nby;
+        n.bx = 0;
+        n.lim = R;
+        n.rbase = M;
+      }
+    } else if (c.bx + 1 < nbx) {
+      n.bx = c.bx + 1;
+    } else {
+      n.band = c.band + 1;
+      n.bx = 0;
+      n.rbase = c.rbase + 64;
+    }
+    return n;
+  }
+};
+
 // Persistent form of the pair flush (same operands, same matrix steps in the same
 // order, so the same results bit for bit): workgroup b takes a contiguous run of
 // the tile list (triangle tiles row by row, then the monitor rows' tiles; runs in
@@ -373,61 +522,13 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
     for (int e = 0; e < 16; ++e)
       gv[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, vo, row_off(stride, e), 2));
   };
-  // tiles of segment j: triangle rows, then monitor bands
-  auto seg_tri = [&](int j) {
-    const int s0 = 32 * j;
-    if (s0 >= nby) return 0;
-    const int wd = (s0 + 32 < nby ? s0 + 32 : nby) - s0;
-    return s0 * wd + wd * (wd + 1) / 2;
-  };
-  auto seg_mon = [&](int j) {
-    const int s0 = 32 * j;
-    return nmb * ((s0 + 32 < nbx ? s0 + 32 : nbx) - s0);
-  };
-  // tile t of the list: row band, column tile, row limit, first row (and segment)
-  int band, bx, lim, rbase, seg = 0;
-  if (SEGO) {
-    int u = t0;
-    while (u >= seg_tri(seg) + seg_mon(seg)) {
-      u -= seg_tri(seg) + seg_mon(seg);
-      ++seg;
-    }
-    const int s0 = 32 * seg, nt = seg_tri(seg);
-    if (u < nt) {
-      const int e = s0 + 32 < nby ? s0 + 32 : nby, wd = e - s0;
-      if (u < s0 * wd) {
-        band = u / wd;
-        bx = s0 + u % wd;
-      } else {
-        u -= s0 * wd;
-        band = s0;
-        while (u >= e - band) {
-          u -= e - band;
-          ++band;
-        }
-        bx = band + u;
-      }
-      lim = M;
-      rbase = band * 64;
-    } else {
-      u -= nt;
-      const int wd = (s0 + 32 < nbx ? s0 + 32 : nbx) - s0;
-      band = nby + u / wd;
-      bx = s0 + u % wd;
-      lim = R;
-      rbase = M + (u / wd) * 64;
-    }
-  } else if (t0 < ntri) {
-    tri_tile(t0, nby, band, bx);
-    lim = M;
-    rbase = band * 64;
-  } else {
-    const int u = t0 - ntri;
-    bx = u % nbx;
-    band = nby + u / nbx;
-    lim = R;
-    rbase = M + (u / nbx) * 64;
-  }
+  // the run's tiles: column segments of 32 tiles (SEGO) or row-major order
+  using Walk = typename std::conditional<SEGO, SegWalk, RowWalk>::type;
+  Walk walk;
+  if constexpr (SEGO) walk = SegWalk{M, R, nby, nbx, nmb, 32};
+  else walk = RowWalk{M, R, nby, nbx, nmb};
+  const SegTile c0 = walk.at(t0);
+  int band = c0.band, bx = c0.bx, lim = c0.lim, rbase = c0.rbase, seg = c0.seg;
   float2 gA[16], gB[16];
   load_A(lim, rbase);
   load_B(bx);
@@ -439,74 +540,9 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
   __syncthreads();
   if ((run & 1) && (P & 7) == 0) __builtin_amdgcn_s_sleep(48);
   auto tile = [&](int t, float2(&gc)[16], float2(&gn)[16]) {
-    // the next tile of the run: along the band, else the next band's first tile
-    int nband = band, nbxx = bx, nlim = lim, nrbase = rbase, nseg = seg;
-    if (SEGO && t + 1 < t1) {
-      const int s0 = 32 * seg;
-      bool next_seg = false;
-      if (band < nby) {
-        const int e = s0 + 32 < nby ? s0 + 32 : nby;
-        if (bx + 1 < e) {
-          nbxx = bx + 1;
-        } else if (band + 1 < e) {
-          nband = band + 1;
-          nbxx = nband > s0 ? nband : s0;
-          nrbase = nband * 64;
-        } else if (nmb > 0) {
-          nband = nby;
-          nbxx = s0;
-          nlim = R;
-          nrbase = M;
-        } else {
-          next_seg = true;
-        }
-      } else {
-        const int f = s0 + 32 < nbx ? s0 + 32 : nbx;
-        if (bx + 1 < f) {
-          nbxx = bx + 1;
-        } else if (band + 1 < nby + nmb) {
-          nband = band + 1;
-          nbxx = s0;
-          nrbase = rbase + 64;
-        } else {
-          next_seg = true;
-        }
-      }
-      if (next_seg) {
-        nseg = seg + 1;
-        nbxx = s0 + 32;
-        if (nbxx < nby) {
-          nband = 0;
-          nlim = M;
-          nrbase = 0;
-        } else {
-          nband = nby;
-          nlim = R;
-          nrbase = M;
-        }
-      }
-    } else if (t + 1 < t1) {
-      if (band < nby) {
-        if (bx + 1 < nby) {
-          nbxx = bx + 1;
-        } else if (band + 1 < nby) {
-          nband = band + 1;
-          nbxx = band + 1;
-          nrbase = nband * 64;
-        } else {
-          nband = nby;
-          nbxx = 0;
-          nlim = R;
-          nrbase = M;
-        }
-      } else if (bx + 1 < nbx) {
-        nbxx = bx + 1;
-      } else {
-        nband = band + 1;
-        nbxx = 0;
-        nrbase = rbase + 64;
-      }
-    }
+    // the next tile of the run (this one at the run's end)
+    const SegTile nt = t + 1 < t1 ? walk.next(SegTile{band, bx, lim, rbase, seg}) : SegTile{band, bx, lim, rbase, seg};
+    const int nband = nt.band, nbxx = nt.bx, nlim = nt.lim, nrbase = nt.rbase, nseg = nt.seg;
     load_B(nbxx);
     int64_t snext;
     const __amdgpu_buffer_rsrc_t rnext = g_rsrc(nbxx, nlim, nrbase, snext);
@@ -618,108 +654,6 @@ __global__ __launch_bounds__(256) void k_flush_pack_s3(int R, int64_t ld,
   emit(CU, R, A3);
   emit(V, ld, V3);
 }
-
-// Position of a persistent flush run in the tile list in column segments of sw
-// tiles (segment j: columns [sw j, sw j + sw)); inside a segment the triangle's
-// rows top to bottom, then the monitor bands, each row left to right.
-struct SegTile {
-  int band, bx, lim, rbase, seg;
-};
-struct SegWalk {
-  int M, R, nby, nbx, nmb, sw;   // sw: segment width in tiles
-  __device__ int seg_tri(int j) const {
-    const int s0 = sw * j;
-    if (s0 >= nby) return 0;
-    const int wd = (s0 + sw < nby ? s0 + sw : nby) - s0;
-    return s0 * wd + wd * (wd + 1) / 2;
-  }
-  __device__ int seg_mon(int j) const {
-    const int s0 = sw * j;
-    return nmb * ((s0 + sw < nbx ? s0 + sw : nbx) - s0);
-  }
-  __device__ SegTile at(int t) const {
-    SegTile c{0, 0, M, 0, 0};
-    int u = t;
-    while (u >= seg_tri(c.seg) + seg_mon(c.seg)) {
-      u -= seg_tri(c.seg) + seg_mon(c.seg);
-      ++c.seg;
-    }
-    const int s0 = sw * c.seg, nt = seg_tri(c.seg);
-    if (u < nt) {
-      const int e = s0 + sw < nby ? s0 + sw : nby, wd = e - s0;
-      if (u < s0 * wd) {
-        c.band = u / wd;
-        c.bx = s0 + u % wd;
-      } else {
-        u -= s0 * wd;
-        c.band = s0;
-        while (u >= e - c.band) {
-          u -= e - c.band;
-          ++c.band;
-        }
-        c.bx = c.band + u;
-      }
-      c.rbase = c.band * 64;
-    } else {
-      u -= nt;
-      const int wd = (s0 + sw < nbx ? s0 + sw : nbx) - s0;
-      c.band = nby + u / wd;
-      c.bx = s0 + u % wd;
-      c.lim = R;
-      c.rbase = M + (u / wd) * 64;
-    }
-    return c;
-  }
-  // the tile after c (c itself when the list ends there)
-  __device__ SegTile next(const SegTile& c) const {
-    SegTile n = c;
-    const int s0 = sw * c.seg;
-    bool next_seg = false;
-    if (c.band < nby) {
-      const int e = s0 + sw < nby ? s0 + sw : nby;
-      if (c.bx + 1 < e) {
-        n.bx = c.bx + 1;
-      } else if (c.band + 1 < e) {
-        n.band = c.band + 1;
-        n.bx = n.band > s0 ? n.band : s0;
-        n.rbase = n.band * 64;
-      } else if (nmb > 0) {
-        n.band = nby;
-        n.bx = s0;
-        n.lim = R;
-        n.rbase = M;
-      } else {
-        next_seg = true;
-      }
-    } else {
-      const int f = s0 + sw < nbx ? s0 + sw : nbx;
-      if (c.bx + 1 < f) {
-        n.bx = c.bx + 1;
-      } else if (c.band + 1 < nby + nmb) {
-        n.band = c.band + 1;
-        n.bx = s0;
-        n.rbase = c.rbase + 64;
-      } else {
-        next_seg = true;
-      }
-    }
-    if (next_seg) {
-      if (s0 + sw >= nbx) return c;
-      n.seg = c.seg + 1;
-      n.bx = s0 + sw;
-      if (n.bx < nby) {
-        n.band = 0;
-        n.lim = M;
-        n.rbase = 0;
-      } else {
-        n.band = nby;
-        n.lim = R;
-        n.rbase = M;
-      }
-    }
-    return n;
-  }
-};
 
 // Persistent band flush with split products (KC chunks of 16 terms: 2 for up to
 // 32 terms, 4 for up to 64).  Same tile list, run assignment, G buffers and
