@@ -191,9 +191,9 @@ def flush_alg_bytes(variant, dtype, N, ld, n_mon=0):
 
 def flush_split(variant, dtype, terms):
     """True when the flush of `terms` terms runs the split-product kernel (FP32
-    products as six BF16 part products; the launcher takes it for 17 to 64
-    terms and the pair flush otherwise)."""
-    return dtype == "c64" and str(variant) == "up_bandseg_s3" and 16 < terms <= 64
+    products as six BF16 part products; the launcher takes it for 17 to 128
+    terms and the pair flush for up to 16)."""
+    return dtype == "c64" and str(variant) == "up_bandseg_s3" and 16 < terms <= 128
 
 
 def flush_mfma_flops(variant, dtype, N, ld, n_mon, terms):
@@ -215,7 +215,7 @@ def flush_mfma_flops(variant, dtype, N, ld, n_mon, terms):
         tiles = nb * (nb + 1) // 2 if tri else nb * (ld // 64)
         if flush_covers_monitors(variant):
             tiles += (n_mon + 63) // 64 * (ld // 64)
-        # the split variant runs the three-product pair flush outside 17 to 64 terms
+        # the split variant runs the three-product pair flush for up to 16 terms
         three = "3m" in str(variant) or str(variant) == "up_bandseg_s3"
         per = 48 if flush_split(variant, dtype, terms) else 6 if three else 8
     return float(per) * 64 * 64 * tiles * terms

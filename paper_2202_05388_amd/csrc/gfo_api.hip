@@ -105,6 +105,7 @@ Layout make_layout(const gfo_problem* p, int64_t ld, int32_t kmax) {
   L.rf_piv = take(k * 16 + 64);
   L.rf_Z = take(R * k * 16);
   L.rf_x = take(k * 16 + 64);
+  L.dl_split = p->dtype == GFO_C64 ? take((size_t)kSplitUnits * (R + (size_t)ld) * 16) : 0;
   L.total = o;
   return L;
 }

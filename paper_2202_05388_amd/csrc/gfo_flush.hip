@@ -656,7 +656,9 @@ __global__ __launch_bounds__(256) void k_flush_pack_s3(int R, int64_t ld,
 }
 
 // Persistent band flush with split products (KC chunks of 16 terms: 2 for up to
-// 32 terms, 4 for up to 64).  Same tile list, run assignment, G buffers and
+// 32 terms, 4 for up to 64 at two workgroups per compute unit; 8 for up to 128
+// at one, its A parts taking 192 registers of a wave, its B halves 96 KB of
+// LDS).  Same tile list, run assignment, G buffers and
 // epilogue layout as k_flush_c64_band in column-segment order; per wave the
 // output is the 32 x 32 block (rows 32 (w >> 1), columns 32 (w & 1)) of the
 // tile, accumulated as XR = sum Ar Br, XI = sum Ai Bi, Z = sum (Ar Bi + Ai Br).
@@ -668,14 +670,16 @@ __global__ __launch_bounds__(256) void k_flush_pack_s3(int R, int64_t ld,
 //     read into registers while the current tile's matrix steps run on the
 //     other half, and written into its half after a barrier;
 //   - G(t+1) is read into registers after tile t's epilogue, in flight during
-//     tile t+1's matrix steps.
+//     tile t+1's matrix steps (at one workgroup per compute unit a second G
+//     register set, G(t+2) in flight, measured slower: 903 against 854 us at
+//     128 terms on the 128 x 128 grid).
 // Global loads of one wave retire in order; the order per tile, B(t+2) first
 // half, then G(t+1), lets the first-half write of the next tile wait for its
 // B loads while G(t+1) is still in flight.  Rows past the matrix read zero and
 // their stores are dropped (buffer ranges), so every load and store is
 // unconditional.
 template <int KC>
-__global__ __launch_bounds__(256, 2) void k_flush_c64_s3(int M, int R, int64_t ld,
+__global__ __launch_bounds__(256, KC == 8 ? 1 : 2) void k_flush_c64_s3(int M, int R, int64_t ld,
                                                       const int32_t* __restrict__ count,
                                                       const bf16x8* __restrict__ A3,
                                                       const bf16x8* __restrict__ V3,
@@ -704,7 +708,7 @@ __global__ __launch_bounds__(256, 2) void k_flush_c64_s3(int M, int R, int64_t l
   const int cc = (w & 1) * 32 + (lane & 31);  // column of the tile (B operand)
   const int lrow = (w >> 1) * 32 + 4 * h;     // the lane's first output row within a tile
   bf16x8 aR[6 * KC];
-  auto load_A = [&](const SegTile& c) {
+  auto load_A = [&](const SegTile& c) __attribute__((always_inline)) {
     const int am = c.rbase + q;
     const unsigned off = am < c.lim ? (unsigned)am * 16u : 0xFFFFFFF0u;
 #pragma unroll
@@ -717,7 +721,7 @@ __global__ __launch_bounds__(256, 2) void k_flush_c64_s3(int M, int R, int64_t l
       }
   };
   bf16x8 S[NS];
-  auto load_S = [&](int bx, int half) {
+  auto load_S = [&](int bx, int half) __attribute__((always_inline)) {
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       const int e = j * 256 + (int)threadIdx.x;
@@ -725,14 +729,14 @@ __global__ __launch_bounds__(256, 2) void k_flush_c64_s3(int M, int R, int64_t l
       S[j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rb, off, 0, 0));
     }
   };
-  auto write_S = [&](int half) {
+  auto write_S = [&](int half) __attribute__((always_inline)) {
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       const int e = j * 256 + (int)threadIdx.x;
       Bsh[half * HU + (e >> 6)][e & 63] = S[j];
     }
   };
-  auto g_rsrc = [&](const SegTile& c, int64_t& stride) {
+  auto g_rsrc = [&](const SegTile& c, int64_t& stride) __attribute__((always_inline)) {
     const int rows = c.lim - c.rbase < 64 ? c.lim - c.rbase : 64;
     const TileAt ta = tile_at(packed, M, ld, mon_base, c.rbase, c.bx);
     stride = ta.stride;
@@ -742,15 +746,17 @@ __global__ __launch_bounds__(256, 2) void k_flush_c64_s3(int M, int R, int64_t l
   auto lane_off = [&](int64_t stride) { return (unsigned)((int64_t)lrow * stride + cc) * 8u; };
   auto row_off = [&](int64_t stride, int e) { return (int)((int64_t)(8 * (e >> 2) + (e & 3)) * stride * 8); };
   float2 gG[16];
-  auto load_G = [&](__amdgpu_buffer_rsrc_t rg, int64_t stride) {
+  auto load_G = [&](const SegTile& c, float2(&gv)[16]) __attribute__((always_inline)) {
+    int64_t stride;
+    const __amdgpu_buffer_rsrc_t rg = g_rsrc(c, stride);
     const unsigned vo = lane_off(stride);
 #pragma unroll
     for (int e = 0; e < 16; ++e)
-      gG[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, vo, row_off(stride, e), 2));
+      gv[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(rg, vo, row_off(stride, e), 2));
   };
   f32x16 XR, XI, Z;
   // the matrix steps of chunks [k0, k1) against the B units in LDS
-  auto steps = [&](int k0, int k1) {
+  auto steps = [&](int k0, int k1) __attribute__((always_inline)) {
 #pragma unroll
     for (int k = k0; k < k1; ++k) {
 #pragma unroll
@@ -779,11 +785,9 @@ __global__ __launch_bounds__(256, 2) void k_flush_c64_s3(int M, int R, int64_t l
   __builtin_amdgcn_s_waitcnt(0x0F70);
   write_S(1);
   load_S(nxt.bx, 0);
-  int64_t scur;
-  __amdgpu_buffer_rsrc_t rcur = g_rsrc(cur, scur);
-  load_G(rcur, scur);
+  load_G(cur, gG);
   __syncthreads();
-  if ((run & 1) && (P & 7) == 0) __builtin_amdgcn_s_sleep(48);
+  if (KC < 8 && (run & 1) && (P & 7) == 0) __builtin_amdgcn_s_sleep(48);
   for (int t = t0; t < t1; ++t) {
 #pragma unroll
     for (int e = 0; e < 16; ++e) XR[e] = XI[e] = Z[e] = 0.f;
@@ -799,6 +803,8 @@ __global__ __launch_bounds__(256, 2) void k_flush_c64_s3(int M, int R, int64_t l
     __syncthreads();  // every wave is done with the second half
     write_S(1);
     __builtin_amdgcn_sched_barrier(0);
+    int64_t scur;
+    const __amdgpu_buffer_rsrc_t rcur = g_rsrc(cur, scur);
     const unsigned vo = lane_off(scur);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -809,10 +815,9 @@ __global__ __launch_bounds__(256, 2) void k_flush_c64_s3(int M, int R, int64_t l
     // B(t+2) first half, then G(t+1)
     const SegTile nn = t + 2 < t1 ? walk.next(nxt) : nxt;
     load_S(nn.bx, 0);
+    load_G(nxt, gG);
     cur = nxt;
     nxt = nn;
-    rcur = g_rsrc(cur, scur);
-    load_G(rcur, scur);
   }
 }
 
@@ -836,20 +841,18 @@ int flush_get_variant() { return g_flush_sel.load(); }
 
 // Workgroups of the persistent band flush: two per compute unit (its occupancy),
 // a multiple of 8 so that every XCD gets the same number of runs.
-static int band_workgroups() {
+static int band_workgroups(int per_cu = 2) {
   static std::atomic<int> cache[64];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-  int n = cache[dev].load();
-  if (n == 0) {
-    int cus = 0;
+  int cus = cache[dev].load();
+  if (cus == 0) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
       cus = 256;
-    n = (2 * cus) / 8 * 8;
-    if (n < 8) n = 8;
-    cache[dev].store(n);
+    cache[dev].store(cus);
   }
-  return n;
+  const int n = (per_cu * cus) / 8 * 8;
+  return n < 8 ? 8 : n;
 }
 
 hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_t s) {
@@ -884,28 +887,34 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         const int bound = st->pending_calls;
         // split products: 17 to 64 terms (the matrix work of up to 16 terms hides
         // behind the G stream in the pair form); 32-bit offsets into G tiles
-        if (fv == 5 && bound > 16 && bound <= 64 && g.ld * 64 * 8 < ((int64_t)1 << 31)) {
+        // split products: 17 to 128 terms (the matrix work of up to 16 terms hides
+        // behind the G stream in the pair form); 32-bit offsets into G tiles and
+        // into the part planes
+        const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
+        if (fv == 5 && bound > 16 && g.ld * 64 * 8 < ((int64_t)1 << 31) &&
+            (int64_t)kSplitUnits * 16 * nx < ((int64_t)1 << 31)) {
           // segments of 32 tiles (16: 0.4 % less traffic, 1 % slower; 64: 3.5 % more traffic)
           const int sw = 32;
           const int nb = (g.N + 63) / 64;
           const int nmb = (g.nmon + 63) / 64, nbx = (int)(g.ld / 64);
-          bf16x8* a3 = (bf16x8*)(w + L.dl_CUs + (size_t)GFO_MAX_DELAY * g.R * 8);
-          bf16x8* v3 = (bf16x8*)(w + L.dl_Vs + (size_t)GFO_MAX_DELAY * g.ld * 8);
-          const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
-          const dim3 pg((unsigned)((nx + 255) / 256), bound <= 32 ? 4u : 8u);
-          const int P = band_workgroups();
+          bf16x8* a3 = (bf16x8*)(w + L.dl_split);
+          bf16x8* v3 = a3 + (size_t)kSplitUnits * g.R;
           const int T = nb * (nb + 1) / 2 + nmb * nbx;
-          if (bound <= 32) {
-            hipLaunchKernelGGL(k_flush_pack_s3<2>, pg, blk, 0, s, g.R, g.ld, count, cu, vv, a3, v3);
-            hipLaunchKernelGGL(k_flush_c64_s3<2>, dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count,
+          const unsigned gx = (unsigned)((nx + 255) / 256);
+          auto run = [&](auto kc) {
+            constexpr int KC = decltype(kc)::value;
+            // two workgroups per compute unit up to 64 terms, one (one wave per SIMD,
+            // the 128 terms' A parts in 192 registers) beyond
+            const int P = band_workgroups(KC == 8 ? 1 : 2);
+            hipLaunchKernelGGL(k_flush_pack_s3<KC>, dim3(gx, 2 * KC), blk, 0, s, g.R, g.ld, count, cu, vv,
+                               a3, v3);
+            hipLaunchKernelGGL(k_flush_c64_s3<KC>, dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count,
                                (const bf16x8*)a3, (const bf16x8*)v3, G, nb, (T + P - 1) / P, g.packed,
                                g.mon_base, sw);
-          } else {
-            hipLaunchKernelGGL(k_flush_pack_s3<4>, pg, blk, 0, s, g.R, g.ld, count, cu, vv, a3, v3);
-            hipLaunchKernelGGL(k_flush_c64_s3<4>, dim3((unsigned)P), blk, 0, s, g.N, g.R, g.ld, count,
-                               (const bf16x8*)a3, (const bf16x8*)v3, G, nb, (T + P - 1) / P, g.packed,
-                               g.mon_base, sw);
-          }
+          };
+          if (bound <= 32) run(std::integral_constant<int, 2>{});
+          else if (bound <= 64) run(std::integral_constant<int, 4>{});
+          else run(std::integral_constant<int, 8>{});
           monitors_done = true;
           break;
         }
@@ -914,7 +923,6 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         const int nb = (g.N + 63) / 64;
         f32x4* cu2 = (f32x4*)(w + L.dl_CUs + (size_t)GFO_MAX_DELAY * g.R * 8);
         f32x4* vv2 = (f32x4*)(w + L.dl_Vs + (size_t)GFO_MAX_DELAY * g.ld * 8);
-        const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
         hipLaunchKernelGGL(k_flush_pack, dim3((unsigned)((nx + 255) / 256), GFO_MAX_DELAY / 2), blk, 0, s,
                            g.R, g.ld, count, cu, vv, cu2, vv2);
         // the triangle's tiles, then the monitor rows' (no separate monitor kernel)

@@ -145,6 +145,9 @@ struct Snap {
 
 constexpr int kScoreThreads = 256;
 constexpr int kScoreMaxBlocks = 1024;
+// 16-byte units per index of the split-product flush's operands: 12 per 16
+// pending terms, up to GFO_MAX_DELAY terms.
+constexpr int kSplitUnits = 12 * (GFO_MAX_DELAY / 16);
 constexpr int kSelectThreads = 1024;
 
 // ------------------------------------------------------------------ workspace layout
@@ -182,6 +185,10 @@ struct Layout {
   size_t rf_piv;    // kp double2: pivot column of the current Gauss-Jordan step
   size_t rf_Z;      // R x kp double2: G0[:, V] M
   size_t rf_x;      // kp double2: M Einc[V]
+  // split-product flush (complex64 storage only): the pending terms as BF16
+  // parts, kSplitUnits units of 16 bytes per row (R rows of CU) and per column
+  // (ld columns of V)
+  size_t dl_split;
   size_t total;
 };
 

@@ -68,21 +68,27 @@ def test_flush_roofline_bound_follows_the_terms():
 def test_split_flush_counts_bf16_part_products():
     N, ld, n_mon = 16384, 16384, 64
     v = "up_bandseg_s3"
-    # 17 to 64 terms: four real products per complex one, six BF16 part products each
+    # 17 to 128 terms: four real products per complex one, six BF16 part products each
     f = bench.flush_mfma_flops(v, "c64", N, ld, n_mon, 64)
     assert f == 8 * bench.flush_mfma_flops("up_pair4_3m_nt", "c64", N, ld, n_mon, 64)
     assert bench.flush_mfma_peak(v, "c64", 64) == bench.BF16_PEAK_TFLOPS
-    # outside that range the launcher runs the FP32 pair flush
-    for t in (16, 65, 128):
+    # up to 16 terms the launcher runs the FP32 pair flush
+    for t in (1, 16):
         assert bench.flush_mfma_flops(v, "c64", N, ld, n_mon, t) == bench.flush_mfma_flops(
             "up_pair4_3m_nt", "c64", N, ld, n_mon, t)
         assert bench.flush_mfma_peak(v, "c64", t) == bench.MFMA_PEAK_TFLOPS["c64"]
     # at 64 terms in 0.46 ms the bytes bind (0.17 ms of BF16 matrix work at peak)
     r = bench.flush_roofline(v, "c64", N, ld, n_mon, [64], [0.46])
     assert r["bound"] == "hbm" and 0.55 < r["frac"] < 0.65
-    # a window that mixes kernels: each flush's matrix time at its own peak
-    r = bench.flush_roofline(v, "c64", N, ld, n_mon, [128, 128], [1.0, 1.0])
-    assert r["bound"] == "mfma" and abs(r["peak"] - bench.MFMA_PEAK_TFLOPS["c64"]) < 1e-9
+    assert bench.flush_mfma_peak(v, "c64", 128) == bench.BF16_PEAK_TFLOPS
+    # a window that mixes the two kernels: each flush's matrix work at its own
+    # instructions' peak (both far below the bytes' time here)
+    r = bench.flush_roofline(v, "c64", N, ld, n_mon, [16, 128], [0.4, 0.6])
+    f16 = bench.flush_mfma_flops(v, "c64", N, ld, n_mon, 16)
+    f128 = bench.flush_mfma_flops(v, "c64", N, ld, n_mon, 128)
+    assert r["bound"] == "hbm" and r["mfma_flops_per_launch"] == (f16 + f128) / 2
+    t_mfma = f16 / (bench.MFMA_PEAK_TFLOPS["c64"] * 1e12) + f128 / (bench.BF16_PEAK_TFLOPS * 1e12)
+    assert t_mfma < 2 * r["algorithmic_bytes_per_launch"] / (bench.HBM_PEAK_GBS * 1e9)
 
 
 def test_host_info_fields():
