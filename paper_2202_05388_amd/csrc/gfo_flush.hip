@@ -893,8 +893,9 @@ hipError_t launch_flush(const Geo& g, gfo_state* st, const Layout& L, hipStream_
         const int64_t nx = g.R > g.ld ? (int64_t)g.R : g.ld;
         if (fv == 5 && bound > 16 && g.ld * 64 * 8 < ((int64_t)1 << 31) &&
             (int64_t)kSplitUnits * 16 * nx < ((int64_t)1 << 31)) {
-          // segments of 32 tiles (16: 0.4 % less traffic, 1 % slower; 64: 3.5 % more traffic)
-          const int sw = 32;
+          // segments of 32 tiles up to 64 terms (16: 0.4 % less traffic, 1 % slower;
+          // 64: 3.5 % more traffic), of 16 beyond (twice the V parts per column)
+          const int sw = bound <= 64 ? 32 : 16;
           const int nb = (g.N + 63) / 64;
           const int nmb = (g.nmon + 63) / 64, nbx = (int)(g.ld / 64);
           bf16x8* a3 = (bf16x8*)(w + L.dl_split);
