@@ -41,10 +41,10 @@ PMC_TRAFFIC = [
     # complex64 flush records: one per term bucket (the launcher's kernel for up to 16, 32, 64
     # or 128 pending terms) of the default variant, each taken on flushes that fold the
     # bucket's full term count: the tile kernel, then the pack kernel
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "ebc87557a26db2fe0297ddf4e3297d09fd9a055983e368e09957001ffd9935b0", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 16, "tile_kernel": "k_flush_c64_pair<4, 4, true>", "fetch_kib": 539636.2 + 2063.0, "write_kib": 1060869.2 + 4104.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "ebc87557a26db2fe0297ddf4e3297d09fd9a055983e368e09957001ffd9935b0", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 32, "tile_kernel": "k_flush_c64_s3<2>", "fetch_kib": 562331.2 + 4131.0, "write_kib": 1060891.8 + 12312.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "ebc87557a26db2fe0297ddf4e3297d09fd9a055983e368e09957001ffd9935b0", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 64, "tile_kernel": "k_flush_c64_s3<4>", "fetch_kib": 633296.6 + 8235.0, "write_kib": 1060867.1 + 24624.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "ebc87557a26db2fe0297ddf4e3297d09fd9a055983e368e09957001ffd9935b0", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 128, "tile_kernel": "k_flush_c64_pair<4, 32, true>", "fetch_kib": 610556.1 + 16428.0, "write_kib": 1060864.0 + 32832.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "972763ff34d84328f3dfb3e404f30992ad6bb4e1903dd657c351c8cd3a6185c9", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 16, "tile_kernel": "k_flush_c64_pair<4, 4, true>", "fetch_kib": 539642.0 + 2065.0, "write_kib": 1060921.4 + 4104.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "972763ff34d84328f3dfb3e404f30992ad6bb4e1903dd657c351c8cd3a6185c9", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 32, "tile_kernel": "k_flush_c64_s3<2>", "fetch_kib": 562021.2 + 4135.0, "write_kib": 1060888.1 + 12312.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "972763ff34d84328f3dfb3e404f30992ad6bb4e1903dd657c351c8cd3a6185c9", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 64, "tile_kernel": "k_flush_c64_s3<4>", "fetch_kib": 620708.7 + 8237.0, "write_kib": 1060870.4 + 24624.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "972763ff34d84328f3dfb3e404f30992ad6bb4e1903dd657c351c8cd3a6185c9", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 128, "tile_kernel": "k_flush_c64_s3<8>", "fetch_kib": 1014278.6 + 16452.1, "write_kib": 1060904.5 + 49248.0},
 ]
 
 

@@ -33,8 +33,11 @@ def test_counter_traffic_lookup():
     if all(v is not None for v in per.values()):
         got = bench.flush_traffic("square128_c64", "up_bandseg_s3", [128, 62, 3])
         assert abs(got - (per[128] + per[64] + per[16]) / 3) < 1.0
-        # at least the tiles read and written once (the minimal 2.164 GB), within 1.15x
-        assert all(2.16e9 < v < 1.15 * 2.165e9 for v in per.values())
+        # at least the tiles read and written once (the minimal 2.164 GB): within
+        # 1.15x up to 64 terms; the 128-term form (one workgroup per compute unit,
+        # twice the operand parts per tile) re-reads its operands, within 1.6x
+        assert all(2.16e9 < per[b] < 1.15 * 2.165e9 for b in (16, 32, 64))
+        assert 2.16e9 < per[128] < 1.6 * 2.165e9
     # the launcher's term buckets
     assert [bench.flush_bucket(t) for t in (1, 16, 17, 32, 33, 64, 65, 128)] == [16, 16, 32, 32, 64, 64, 128, 128]
     for rec in bench.PMC_TRAFFIC:
