@@ -226,15 +226,17 @@ int apply_flip(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_pick,
  * monitor's row of G at once.  score_candidates reads only those, so the move
  * sequence is the one of eager mode.  After r apply_flip calls since the
  * last flush, the design block and the other monitor rows are brought up to
- * date by one rank-r product on the matrix cores (FP32 for GFO_C64, FP64 for
- * GFO_C128); gfo_flush does the same on demand.  Until then those rows hold
+ * date by one rank-r product on the matrix cores (FP64 for GFO_C128; for
+ * GFO_C64 FP32 products, which the default flush for 17 to 128 terms computes
+ * as the six leading products of three-part BF16 splits of each FP32 operand,
+ * at FP32 accuracy); gfo_flush does the same on demand.  Until then those rows hold
  * their base values only.  refresh_G
  * discards pending terms (it rebuilds G from G0); apply_flips_rank_k flushes
  * first.
  * The design block G_D is symmetric at every step (reciprocity of the medium,
  * and each pending term restricted to it is c v v^T), so in deferred mode the
  * library reads its entries from the upper triangle (row <= column) only, and
- * the flushes (complex128, and the complex64 default "up_pair4_3m_nt"),
+ * the flushes (complex128, and every complex64 variant but "w32_3m"),
  * init_G0 and refresh_G bring only that triangle up to date; they then set
  * state.lower_stale.  In eager mode the same holds when state.lower_stale is 1
  * on entry to init_G0 or refresh_G: the rank-1 update of apply_flip then skips
@@ -392,7 +394,8 @@ int gfo_rk_get_variant(void);
 
 /* Autotuner hooks for the complex64 deferred-mode flush: tile variants of the
  * same rank-r matrix-core product (bit-identical results are not guaranteed
- * across variants: the FP32 summation order differs).  Host only. */
+ * across variants: the FP32 summation order, and for "up_bandseg_s3" the
+ * product's arithmetic, differ).  Host only. */
 int gfo_flush_variant_count(void);
 const char* gfo_flush_variant_name(int32_t idx);              /* NULL if out of range */
 int gfo_flush_set_variant(int32_t idx);                       /* GFO_EINVAL if out of range */
