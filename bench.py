@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -32,32 +33,42 @@ BF16_PEAK_TFLOPS = 2500.0                           # dense BF16 matrix peak
 # per dispatch), each scaled by what the same counter reports for a device copy of
 # exactly 2 GiB (FETCH 1048599.75 KiB -> factor 2.0; WRITE 2097152 KiB -> factor
 # 1.0).  A record is valid only for the kernel source and variant it was measured
-# on: any change to that source file voids it (traffic is then reported as null).
+# on: any change to that source's code (comments and whitespace aside) voids it
+# (traffic is then reported as null).
 # Counters: profiles/k_rank1_square128_c64.md and profiles/deferred_step_square128_c64.md.
 FETCH_SCALE = 2097152.0 / 1048599.75
 WRITE_SCALE = 1.0
 PMC_TRAFFIC = [
-    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_rank1.hip", "sha256": "a79143cebd95fd21cd0b1947163a604110a9ea7aa74dcfa84733f42172133799", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053784.0, "write_kib": 2105344.0},
+    {"kernel": "k_rank1", "source": "paper_2202_05388_amd/csrc/gfo_rank1.hip", "code_sha256": "a6b6efb2897f6b048c0d7845fc1fb0c76a7153786a46e94aefbd8df1e5a847d9", "workload": "square128_c64", "variant": "2x1x1_nt", "fetch_kib": 1053784.0, "write_kib": 2105344.0},
     # complex64 flush records: one per term bucket (the launcher's kernel for up to 16, 32, 64
     # or 128 pending terms) of the default variant, each taken on flushes that fold the
     # bucket's full term count: the tile kernel, then the pack kernel
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "972763ff34d84328f3dfb3e404f30992ad6bb4e1903dd657c351c8cd3a6185c9", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 16, "tile_kernel": "k_flush_c64_pair<4, 4, true>", "fetch_kib": 539642.0 + 2065.0, "write_kib": 1060921.4 + 4104.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "972763ff34d84328f3dfb3e404f30992ad6bb4e1903dd657c351c8cd3a6185c9", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 32, "tile_kernel": "k_flush_c64_s3<2>", "fetch_kib": 562021.2 + 4135.0, "write_kib": 1060888.1 + 12312.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "972763ff34d84328f3dfb3e404f30992ad6bb4e1903dd657c351c8cd3a6185c9", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 64, "tile_kernel": "k_flush_c64_s3<4>", "fetch_kib": 620708.7 + 8237.0, "write_kib": 1060870.4 + 24624.0},
-    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "sha256": "972763ff34d84328f3dfb3e404f30992ad6bb4e1903dd657c351c8cd3a6185c9", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 128, "tile_kernel": "k_flush_c64_s3<8>", "fetch_kib": 1014278.6 + 16452.1, "write_kib": 1060904.5 + 49248.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "code_sha256": "467dc02667036d6a9a06a30b399e3413a41a0aeebbb56137dcf67f5f431dbc44", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 16, "tile_kernel": "k_flush_c64_pair<4, 4, true>", "fetch_kib": 539642.0 + 2065.0, "write_kib": 1060921.4 + 4104.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "code_sha256": "467dc02667036d6a9a06a30b399e3413a41a0aeebbb56137dcf67f5f431dbc44", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 32, "tile_kernel": "k_flush_c64_s3<2>", "fetch_kib": 562021.2 + 4135.0, "write_kib": 1060888.1 + 12312.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "code_sha256": "467dc02667036d6a9a06a30b399e3413a41a0aeebbb56137dcf67f5f431dbc44", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 64, "tile_kernel": "k_flush_c64_s3<4>", "fetch_kib": 620708.7 + 8237.0, "write_kib": 1060870.4 + 24624.0},
+    {"kernel": "k_flush_c64", "source": "paper_2202_05388_amd/csrc/gfo_flush.hip", "code_sha256": "467dc02667036d6a9a06a30b399e3413a41a0aeebbb56137dcf67f5f431dbc44", "workload": "square128_c64", "variant": "up_bandseg_s3", "bucket": 128, "tile_kernel": "k_flush_c64_s3<8>", "fetch_kib": 1014278.6 + 16452.1, "write_kib": 1060904.5 + 49248.0},
 ]
 
 
-def pmc_traffic(kernel, workload, variant, bucket=None):
+def code_hash(path):
+    """SHA-256 of a C++/HIP source with its comments and whitespace removed: the
+    code a record was measured on, whatever its comments say since."""
     import hashlib
+    with open(path, encoding="utf-8") as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()
+
+
+def pmc_traffic(kernel, workload, variant, bucket=None):
     for rec in PMC_TRAFFIC:
         if (rec["kernel"], rec["workload"], rec["variant"]) != (kernel, workload, variant):
             continue
         if rec.get("bucket") != bucket:
             continue
-        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != rec["sha256"]:
-                return None
+        if code_hash(os.path.join(ROOT, rec["source"])) != rec["code_sha256"]:
+            return None
         return 1024.0 * (rec["fetch_kib"] * FETCH_SCALE + rec["write_kib"] * WRITE_SCALE)
     return None
 

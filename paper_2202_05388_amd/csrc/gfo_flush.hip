@@ -597,14 +597,14 @@ __global__ __launch_bounds__(256) void k_flush_c64_band(int M, int R, int64_t ld
 
 // ---------------------------------------------------------------------------
 // Split-product flush: the FP32 products on the BF16 matrix cores.  Each FP32
-// operand x is split into three BF16 parts, x = x0 + x1 + x2 + r with |r| at
-// most about 2^-26 |x| (x0 the nearest BF16 to x, x1 to x - x0, x2 to
-// x - x0 - x1; every difference is exact in FP32), and a product a b is summed
-// from the six part products a_i b_j with i + j <= 2.  Each part product is
-// exact in FP32 and the matrix core accumulates in FP32; the three dropped ones
-// are below 2^-26 |a||b|, so the sum has the accuracy of an FP32 product (the
-// split itself is the standard error-free splitting of a floating-point number
-// into shorter ones).  v_mfma_f32_32x32x16_bf16 takes 16 terms in 32 cycles
+// operand x is split into three BF16 parts, x = x0 + x1 + x2 + r (x0 the
+// nearest BF16 to x, x1 to x - x0, x2 to x - x0 - x1; every difference is exact
+// in FP32; with u = 2^-8 the unit roundoff of BF16, |x1| <= u |x|, |x2| <= u^2 |x|
+// and |r| <= u^3 |x| = 2^-24 |x|), and a product a b is summed from the six part
+// products a_i b_j with i + j <= 2.  Each part product is exact in FP32 and the
+// matrix core accumulates in FP32; the dropped part products and the residuals
+// come to about 4 u^3 |a||b|, a few units of FP32 rounding, so the sum has FP32
+// accuracy.  v_mfma_f32_32x32x16_bf16 takes 16 terms in 32 cycles
 // where v_mfma_f32_32x32x2f32 takes 2 in 64: with six part products and four
 // real products per complex one, a term costs half the matrix-core cycles of
 // the three-product FP32 form.

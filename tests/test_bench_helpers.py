@@ -98,3 +98,15 @@ def test_host_info_fields():
     h = bench.host_info()
     assert set(h) == {"cpu_model", "logical_cpus", "ram_gb", "blas", "blas_threads"}
     assert h["logical_cpus"] >= 1
+
+
+def test_code_hash_ignores_comments_only(tmp_path):
+    """A counter record stays valid across comment and whitespace edits of its
+    source, and not across a code change."""
+    a = tmp_path / "a.hip"
+    a.write_text("// note\nint f(int x) {  /* twice */ return 2 * x; }\n")
+    h = bench.code_hash(str(a))
+    a.write_text("int f(int x) {\n  return 2 * x;  // doubled\n}\n")
+    assert bench.code_hash(str(a)) == h
+    a.write_text("int f(int x) { return 3 * x; }\n")
+    assert bench.code_hash(str(a)) != h
