@@ -68,14 +68,15 @@ def test_packed_equals_dense_bitwise(ny, nx, n_mon, dtype, delay):
 def test_packed_flush_variants(variant):
     """Every complex64 flush variant on packed storage (the non-symmetric one
     falls back to the pair kernel there) gives the dense result of the same
-    variant bit for bit, at 64 and 128 terms."""
+    variant bit for bit, at 32, 64 and 128 terms (for the split-product default,
+    its two-, four- and eight-chunk forms)."""
     from paper_2202_05388_amd import _lib as L
     names = L.flush_variants()
     old = L.flush_get_variant()
     try:
         L.flush_set_variant(names.index(variant))
         p = W.tiny(40, 44, n_mon=40, dtype="c64", cand_mask=W.MASK_BOTH, tau=1e-6)
-        for delay in (64, 128):
+        for delay in (32, 64, 128):
             dense, packed = _pair(p, delay)
             for j in (dense, packed):
                 j.greedy_steps(delay + 10)
