@@ -560,7 +560,7 @@ def regions_cpu_baseline(problem, steps=20):
                 cores=os.cpu_count())
 
 
-def time_rank_k(problem, steps, warmup, precision):
+def time_rank_k(problem, steps, warmup, precision, upper=False):
     """Rank-k steps as the batched workload specifies them: score with top-k and
     the spacing rule, one joint Woodbury update, and the FP64 refresh after every
     `problem.refresh_every` rank-k steps (kmax covers every pixel those steps can
@@ -572,7 +572,12 @@ def time_rank_k(problem, steps, warmup, precision):
     mean time of the matrix-core update kernel, the refresh time, the FOM after
     every step against the cumulative number of flips, and at every refresh the
     FOM error of the FP32/BF16 path: |FOM before - FOM after| / FOM after, the
-    refresh being the FP64 re-solve of the same structure."""
+    refresh being the FP64 re-solve of the same structure.
+
+    upper: keep only the upper triangle of the symmetric design block current
+    (state.lower_stale): the refresh's product and the rank-k update leave out
+    the blocks wholly below the diagonal, and the update's bytes are those of
+    the triangle with its diagonal and the monitor rows."""
     import torch
     from paper_2202_05388_amd import _lib as L
     from paper_2202_05388_amd.hiprt import EventPool
@@ -583,7 +588,7 @@ def time_rank_k(problem, steps, warmup, precision):
     prec = L.GFO_FP32 if precision == "fp32" else L.GFO_BF16
     re = problem.refresh_every
     kmax = min(problem.n, problem.rank_k * max(steps, warmup))
-    job = Job(problem, device="cuda:0", kmax=kmax)
+    job = Job(problem, device="cuda:0", kmax=kmax, upper=upper)
     job.init()
     tuned = at.tune_rank_k(job, rank=problem.rank_k, precision=prec, save=False)
     _log(f"[bench] rank-k update autotune ({precision}): "
@@ -631,15 +636,19 @@ def time_rank_k(problem, steps, warmup, precision):
     d = [x for x, f in zip(ev.elapsed_ms(), ok) if f]
     ev.close()
     N, R = problem.n, problem.rows
+    # algorithmic bytes of one update: G read and written once (complex64), the
+    # whole block or the upper triangle with its diagonal plus the monitor rows
+    nbytes = 8 * N * job.ld + 16 * (R - N) * job.ld if upper else 16 * N * R
     k_ms = sum(d) / len(d)
     flipped = int((job.eps_idx.cpu().numpy() != 0).sum())
     best = max(curve, key=lambda c: c[1])
     out = dict(precision=precision, rank=problem.rank_k, min_spacing=problem.min_spacing,
-               refresh_every_steps=re, kmax=kmax, steps=steps, moves=moves, restarts=restarts,
+               storage="upper triangle" if upper else "full", refresh_every_steps=re, kmax=kmax,
+               steps=steps, moves=moves, restarts=restarts,
                moves_per_s=moves / dt, steps_per_s=steps / dt, seconds=dt,
                refreshes=len(errs), refresh_seconds=refresh_s, flipped_at_end=flipped,
-               update_us=k_ms * 1e3, update_gbs=16 * N * R / (k_ms * 1e-3) / 1e9,
-               update_hbm_frac=16 * N * R / (k_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+               update_us=k_ms * 1e3, update_bytes=nbytes, update_gbs=nbytes / (k_ms * 1e-3) / 1e9,
+               update_hbm_frac=nbytes / (k_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
                fom_last=job.fom(), fom_best=best[1], flips_at_best=best[0],
                fom_err_at_refresh_max=max(errs) if errs else None,
                fom_err_at_refresh_mean=sum(errs) / len(errs) if errs else None,
@@ -900,11 +909,14 @@ def main():
             _log(f"[bench] rank-{rk.rank_k} steps ({prec})")
             rank_k[prec] = time_rank_k(rk, steps=rk.steps, warmup=16, precision=prec)
             _log(f"[bench] rank-{rk.rank_k} {prec}: {rank_k[prec]}")
+        # the same steps keeping the design block's upper triangle alone
+        rank_k["fp32_upper"] = time_rank_k(rk, steps=rk.steps, warmup=16, precision="fp32", upper=True)
+        _log(f"[bench] rank-{rk.rank_k} fp32, upper triangle: {rank_k['fp32_upper']}")
         g = greedy_fom_curve(problem)
         rank_k["rank1_greedy"] = dict(moves=len(g) - 1, fom_last=g[-1][1],
                                       fom_vs_flips=_sample_curve(g))
         # flips the rank-16 form needs to reach the greedy trajectory's final FOM
-        for prec in ("fp32", "bf16"):
+        for prec in ("fp32", "bf16", "fp32_upper"):
             reach = [f for f, v in rank_k[prec]["fom_vs_flips"] if v >= g[-1][1]]
             rank_k[prec]["flips_to_greedy_fom"] = reach[0] if reach else None
 

@@ -352,7 +352,10 @@ int gfo_choose_eps_greedy(const gfo_pick* d_top, int32_t k, double eps, double u
  *   G += G[:, S] M G[S, :],  E += G[:, S] M E[S],  diag64 updated in FP64.
  * The R x N update is a rank-k product on the matrix cores with FP32 or BF16
  * inputs (gemm_precision) and FP32 accumulation; requires GFO_C64 storage,
- * dense (GFO_EINVAL when state.packed).
+ * dense (GFO_EINVAL when state.packed).  In deferred mode, or with
+ * state.lower_stale set, the update leaves out the blocks of design rows
+ * wholly below the diagonal (about half of the design block's traffic): only
+ * the upper triangle is read there.
  * Sentinel records (pixel < 0) are skipped; 1 <= k <= GFO_MAX_RANK_K. */
 int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d_picks,
                        int32_t k, int32_t gemm_precision, hipStream_t stream);

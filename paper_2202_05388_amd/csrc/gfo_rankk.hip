@@ -304,6 +304,15 @@ __global__ __launch_bounds__(64) void k_rk_cols(Geo g, const RkHdr* __restrict__
 }
 
 // ------------------------------------------------------------------ RK4: MFMA update
+// A workgroup of rows [r0, r0 + nr) and columns below c_end is left out when it
+// lies wholly in design rows (r0 + nr <= skip_below = N) and strictly below the
+// diagonal tiles (c_end <= r0, r0 a multiple of 64): with the design block's
+// upper triangle kept alone (deferred mode, or state.lower_stale), those
+// entries are never read.  skip_below = 0 updates every entry.
+__device__ __forceinline__ bool rk_below_diagonal(int r0, int nr, int64_t c_end, int skip_below) {
+  return skip_below > 0 && r0 + nr <= skip_below && c_end <= r0;
+}
+
 // Workgroup: 4 waves over a 64 x 64 complex tile per iteration (wave w: column
 // tile w & 1, row tile w >> 1), RBLK row blocks of 64 rows per workgroup.  The
 // A rows of the iteration are staged in LDS and shared by the two column waves;
@@ -313,7 +322,7 @@ __global__ __launch_bounds__(64) void k_rk_cols(Geo g, const RkHdr* __restrict__
 constexpr int kRkRowBlocks = 8;
 
 template <int KP, bool BF16>
-__global__ __launch_bounds__(256) void k_rk_mfma(int R, int64_t ld,
+__global__ __launch_bounds__(256) void k_rk_mfma(int R, int64_t ld, int skip_below,
                                                  const int32_t* __restrict__ gate_count,
                                                  const int32_t* __restrict__ gate_kp,
                                                  const float* __restrict__ Af,
@@ -330,6 +339,7 @@ __global__ __launch_bounds__(256) void k_rk_mfma(int R, int64_t ld,
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int ncg = (int)(ld / 64);
   const int cg = blockIdx.x % ncg, rg = blockIdx.x / ncg;
+  if (rk_below_diagonal(rg * 64 * kRkRowBlocks, 64 * kRkRowBlocks, cg * 64 + 64, skip_below)) return;
   const int q = cg * 64 + (w & 1) * 32 + (lane & 31);
   const int h = lane >> 5;
   // B fragments for this lane's column
@@ -423,7 +433,7 @@ __global__ __launch_bounds__(256) void k_rk_mfma(int R, int64_t ld,
 // blocks within 128 registers (about 120 needed): three to four waves per SIMD,
 // as LDS allows, and more loads of G in flight than at two.
 template <int KP, bool BF16, int RB, bool LDSEPI, int TM = 1>
-__global__ __launch_bounds__(256, (!BF16 && TM == 1 && KP == 16 && RB <= 4) ? 3 : 1) void k_rk_stream(int R, int64_t ld,
+__global__ __launch_bounds__(256, (!BF16 && TM == 1 && KP == 16 && RB <= 4) ? 3 : 1) void k_rk_stream(int R, int64_t ld, int skip_below,
                                                    const int32_t* __restrict__ gate_count,
                                                    const int32_t* __restrict__ gate_kp,
                                                    const float* __restrict__ Af,
@@ -446,6 +456,7 @@ __global__ __launch_bounds__(256, (!BF16 && TM == 1 && KP == 16 && RB <= 4) ? 3 
   const int cg = blockIdx.x % ncg, rg = blockIdx.x / ncg;
   const int64_t c0 = (int64_t)cg * 128;
   const int rbase = rg * RB * BR;
+  if (rk_below_diagonal(rbase, RB * BR, c0 + 128, skip_below)) return;
   const int64_t q = c0 + 32 * w + (lane & 31);
   const bool qok = q < ld;
   // A rows of the workgroup
@@ -601,9 +612,10 @@ static void launch_rk_stream(const Geo& g, RkHdr* hdr, const float* Af, const fl
   const int ncg = (int)((g.ld + 127) / 128);
   const int nrg = (g.R + 32 * TM * RB - 1) / (32 * TM * RB);
   const dim3 grid((unsigned)(ncg * nrg));
-  hipLaunchKernelGGL((k_rk_stream<16, BF16, RB, LDSEPI, TM>), grid, dim3(256), 0, s, g.R, g.ld,
+  const int skip = g.upper ? g.N : 0;
+  hipLaunchKernelGGL((k_rk_stream<16, BF16, RB, LDSEPI, TM>), grid, dim3(256), 0, s, g.R, g.ld, skip,
                      &hdr->s, &hdr->kp, Af, Bf, Abf, Bbf, G);
-  hipLaunchKernelGGL((k_rk_stream<32, BF16, RB, LDSEPI, TM>), grid, dim3(256), 0, s, g.R, g.ld,
+  hipLaunchKernelGGL((k_rk_stream<32, BF16, RB, LDSEPI, TM>), grid, dim3(256), 0, s, g.R, g.ld, skip,
                      &hdr->s, &hdr->kp, Af, Bf, Abf, Bbf, G);
 }
 
@@ -667,15 +679,16 @@ hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo
       const int ncg = (int)(g.ld / 64);
       const int nrg = (g.R + 64 * kRkRowBlocks - 1) / (64 * kRkRowBlocks);
       const dim3 grid((unsigned)(ncg * nrg));
+      const int skip = g.upper ? g.N : 0;
       if (bf) {
-        hipLaunchKernelGGL((k_rk_mfma<16, true>), grid, dim3(256), 0, s, g.R, g.ld, &hdr->s, &hdr->kp,
-                           cAf, cBf, cAbf, cBbf, G);
-        hipLaunchKernelGGL((k_rk_mfma<32, true>), grid, dim3(256), 0, s, g.R, g.ld, &hdr->s, &hdr->kp,
-                           cAf, cBf, cAbf, cBbf, G);
-      } else {
-        hipLaunchKernelGGL((k_rk_mfma<16, false>), grid, dim3(256), 0, s, g.R, g.ld, &hdr->s,
+        hipLaunchKernelGGL((k_rk_mfma<16, true>), grid, dim3(256), 0, s, g.R, g.ld, skip, &hdr->s,
                            &hdr->kp, cAf, cBf, cAbf, cBbf, G);
-        hipLaunchKernelGGL((k_rk_mfma<32, false>), grid, dim3(256), 0, s, g.R, g.ld, &hdr->s,
+        hipLaunchKernelGGL((k_rk_mfma<32, true>), grid, dim3(256), 0, s, g.R, g.ld, skip, &hdr->s,
+                           &hdr->kp, cAf, cBf, cAbf, cBbf, G);
+      } else {
+        hipLaunchKernelGGL((k_rk_mfma<16, false>), grid, dim3(256), 0, s, g.R, g.ld, skip, &hdr->s,
+                           &hdr->kp, cAf, cBf, cAbf, cBbf, G);
+        hipLaunchKernelGGL((k_rk_mfma<32, false>), grid, dim3(256), 0, s, g.R, g.ld, skip, &hdr->s,
                            &hdr->kp, cAf, cBf, cAbf, cBbf, G);
       }
       break;

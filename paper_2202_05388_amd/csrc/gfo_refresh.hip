@@ -312,6 +312,126 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
 }
 
+// The same product with a 128 x 128 output tile per workgroup of 512 threads
+// (8 waves in 2 x 4, each 64 x 32 = 4 x 2 tiles of the 16x16x4 instruction),
+// for the refresh, whose k is the flipped set (hundreds to thousands).  The
+// operands pass through LDS in chunks of 8 k with two buffers: the next chunk
+// is loaded into registers while the current one is multiplied, and a wave
+// waits on global memory only when it stores that chunk to LDS, 64 matrix
+// instructions later.  Each operand element is fetched once per workgroup
+// (1/32 byte per flop, against 1/8 for the 64 x 64 tile, whose waves each load
+// their own rows and columns).  It holds one workgroup per compute unit (two
+// waves per SIMD), so its epilogue does not overlap other tiles' products: the
+// 64 x 64 kernel stays the faster one for the flush's k <= 128, whose
+// epilogue reads and writes G.
+// Every accumulator takes the same instructions on the same operands in the
+// same order as in k_zgemm_f64, and the epilogue covers the same entries (the
+// 64 x 64 tiles wholly below the diagonal within rows < skip_below are left
+// alone), so the two kernels give bitwise equal results.
+constexpr int kZgT = 128, kZgKC = 8, kZgPitch = kZgT + 1;  // pitch: one pad entry per k row
+
+template <bool AT, bool BT, typename Epi>
+__global__ __launch_bounds__(512) void k_zgemm_f64_t128(int M, int N, int K, const double2* __restrict__ A,
+                                                        int64_t lda, const double2* __restrict__ B,
+                                                        int64_t ldb, const int32_t* __restrict__ kdev,
+                                                        Epi epi, int skip_below) {
+  if (skip_below > 0 && blockIdx.y > blockIdx.x && ((int64_t)blockIdx.y + 1) * kZgT <= skip_below) return;
+  __shared__ double2 As[2][kZgKC][kZgPitch], Bs[2][kZgKC][kZgPitch];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tm0 = blockIdx.y * kZgT, tn0 = blockIdx.x * kZgT;
+  const int wm = (w >> 2) * 64, wn = (w & 3) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  // the wave's rows and columns lie in one 64 x 64 tile; a skipped one idles
+  const int ty = (tm0 + wm) >> 6, tx = (tn0 + wn) >> 6;
+  const bool idle = skip_below > 0 && ty > tx && ((int64_t)ty + 1) * 64 <= skip_below;
+  if (kdev != nullptr) K = min(K, *kdev);
+  f64x4 re[4][2], im[4][2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      re[t][u] = (f64x4){0.0, 0.0, 0.0, 0.0};
+      im[t][u] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    }
+  // staging: thread tid moves elements tid and tid + 512 of each 128 x 8 chunk,
+  // consecutive threads along the operand's contiguous index
+  auto a_pos = [](int e, int& r, int& kk) {
+    if (AT) { r = e & 127; kk = e >> 7; } else { r = e >> 3; kk = e & 7; }
+  };
+  auto b_pos = [](int e, int& c, int& kk) {
+    if (BT) { c = e >> 3; kk = e & 7; } else { c = e & 127; kk = e >> 7; }
+  };
+  double2 pa[2], pb[2];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int r, c, ka, kb;
+      a_pos(tid + 512 * i, r, ka);
+      b_pos(tid + 512 * i, c, kb);
+      const int row = tm0 + r, col = tn0 + c;
+      ka += k0;
+      kb += k0;
+      pa[i] = row < M && ka < K ? (AT ? A[(int64_t)ka * lda + row] : A[(int64_t)row * lda + ka])
+                                : make_double2(0.0, 0.0);
+      pb[i] = col < N && kb < K ? (BT ? B[(int64_t)col * ldb + kb] : B[(int64_t)kb * ldb + col])
+                                : make_double2(0.0, 0.0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int r, c, ka, kb;
+      a_pos(tid + 512 * i, r, ka);
+      b_pos(tid + 512 * i, c, kb);
+      As[buf][ka][r] = pa[i];
+      Bs[buf][kb][c] = pb[i];
+    }
+  };
+  const int nch = (K + kZgKC - 1) / kZgKC;
+  if (nch > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) load((ch + 1) * kZgKC);
+    if (!idle) {
+#pragma unroll
+      for (int st = 0; st < kZgKC / 4; ++st) {
+        if (ch * kZgKC + 4 * st >= K) break;
+        double2 a[4], b[2];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = As[buf][4 * st + lk][wm + 16 * t + li];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) b[u] = Bs[buf][4 * st + lk][wn + 16 * u + li];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            re[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t].x, b[u].x, re[t][u], 0, 0, 0);
+            re[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[t].y, b[u].y, re[t][u], 0, 0, 0);
+            im[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t].x, b[u].y, im[t][u], 0, 0, 0);
+            im[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t].y, b[u].x, im[t][u], 0, 0, 0);
+          }
+      }
+    }
+    if (ch + 1 < nch) store(buf ^ 1);
+    __syncthreads();
+  }
+  if (idle) return;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = tm0 + wm + 16 * t + lk + 4 * e;
+        const int col = tn0 + wn + 16 * u + li;
+        if (row < M && col < N) epi(row, col, make_double2(re[t][u][e], im[t][u][e]));
+      }
+}
+
 // x = M Einc[V] (k-vector), then E[r] = Einc[r] + sum_i U[r, i] x_i.
 __global__ void k_rf_xE(Geo g, const double* __restrict__ mon_xy, const int32_t* __restrict__ V,
                         const double2* __restrict__ Aug, int k, int kp, double2* __restrict__ x) {
@@ -378,8 +498,8 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, int32_t k
     }
     // Z = U M, M = right half of Aug (row-major, ld 2kp)
     EpiStoreZ ez{Z, kp};
-    hipLaunchKernelGGL((k_zgemm_f64<false, false, EpiStoreZ>), dim3((kp + 63) / 64, (g.R + 63) / 64),
-                       dim3(256), 0, s, g.R, kp, kp, (const double2*)U, (int64_t)kp,
+    hipLaunchKernelGGL((k_zgemm_f64_t128<false, false, EpiStoreZ>),
+                       dim3((kp + kZgT - 1) / kZgT, (g.R + kZgT - 1) / kZgT), dim3(512), 0, s, g.R, kp, kp, (const double2*)U, (int64_t)kp,
                        (const double2*)(Aug + kp), (int64_t)2 * kp, (const int32_t*)nullptr, ez, 0);
     hipLaunchKernelGGL(k_rf_xE, dim3((kp + 255) / 256), dim3(256), 0, s, g, mon, (const int32_t*)V,
                        (const double2*)Aug, k, kp, x);
@@ -390,8 +510,8 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, int32_t k
   // deferred mode, or when the caller keeps the upper triangle alone, the
   // design block on and above its diagonal only
   EpiG0<T> eg{g, table, mon, (T*)st->G, (double2*)st->diag64};
-  hipLaunchKernelGGL((k_zgemm_f64<false, true, EpiG0<T>>), dim3((g.N + 63) / 64, (g.R + 63) / 64),
-                     dim3(256), 0, s, g.R, g.N, kp, (const double2*)Z, (int64_t)kp,
+  hipLaunchKernelGGL((k_zgemm_f64_t128<false, true, EpiG0<T>>),
+                     dim3((g.N + kZgT - 1) / kZgT, (g.R + kZgT - 1) / kZgT), dim3(512), 0, s, g.R, g.N, kp, (const double2*)Z, (int64_t)kp,
                      (const double2*)U, (int64_t)kp, (const int32_t*)nullptr, eg,
                      g.upper ? g.N : 0);
   return note_hip(hipGetLastError()) == hipSuccess ? GFO_OK : GFO_EHIP;

@@ -230,3 +230,56 @@ def test_rank_k_update_variants(precision, s):
     assert len(streaming) >= 2
     for n in streaming[1:]:
         assert np.array_equal(out[n], out[streaming[0]]), n
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_rank_k_upper_triangle_equals_full(precision):
+    """With state.lower_stale set the rank-k update leaves out the blocks of
+    design rows wholly below the diagonal; every entry it keeps (the upper
+    triangle with its diagonal, the monitor rows), E and the FP64 diagonal equal
+    the full update's bit for bit, in every variant, and the state with its lower
+    triangle copied back is the dense re-solve's."""
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(30, 70, n_mon=8, dtype="c64")
+    N, s = p.n, 16
+    idx = W.random_eps_idx(p, 0.15, 6)
+    G, E = ost.dense_state(p, ost.eps_of(p, idx))
+    pix = np.random.default_rng(3).choice(N, s, replace=False)
+    idx2 = idx.copy()
+    idx2[pix] = 1 - idx2[pix]
+    Gd, Ed = ost.dense_state(p, ost.eps_of(p, idx2))
+    prec = L.GFO_FP32 if precision == "fp32" else L.GFO_BF16
+    upper = np.triu(np.ones((N, N), bool))
+    old = L.rk_get_variant()
+    try:
+        for vi, name in enumerate(L.rk_variants()):
+            L.rk_set_variant(vi)
+            out = []
+            for lower_stale in (0, 1):
+                job = _job(p)
+                job.upload_state(G, E, np.diagonal(G[:N]), idx)
+                job.state.lower_stale = lower_stale
+                for t, j in enumerate(pix):
+                    job.set_pick(int(j), int(idx2[j]), slot=t)
+                job.apply_rank_k(s, precision=prec)
+                assert job.status() == 0 and job.state.lower_stale == lower_stale
+                raw = job.dense_G()[:, :N].cpu().numpy()
+                out.append((job, raw, job.E.cpu().numpy(), job.diag64.cpu().numpy()))
+            (_, Gf, Ef, df), (up, Gu, Eu, du) = out
+            assert np.array_equal(Gu[:N][upper], Gf[:N][upper]), name
+            assert np.array_equal(Gu[N:], Gf[N:]), name
+            assert np.array_equal(Eu, Ef) and np.array_equal(du, df), name
+            # rows 1920..2047 x columns 0..127 lie below the diagonal in every
+            # variant's row groups (128, 256 or 512 rows): left as uploaded
+            G64 = G[:N].astype(np.complex64)
+            assert np.array_equal(Gu[1920:2048, :128], G64[1920:2048, :128]), name
+            assert not np.array_equal(Gf[1920:2048, :128], G64[1920:2048, :128]), name
+            G1, E1, d1, i1 = up.host_state()
+            assert np.array_equal(i1, idx2)
+            if precision == "fp32":
+                assert _rel(G1, Gd) <= c64_drift_tol(s), name
+            else:
+                assert _rel(G1 - G, Gd - G, floor=1.0) <= 1e-2, name
+            assert _rel(E1, Ed) <= 5e-6, name
+    finally:
+        L.rk_set_variant(old)
