@@ -181,8 +181,9 @@ struct Layout {
   // (kp = kmax rounded up to a multiple of 4)
   size_t rf_V;      // N + 1 int32: flipped list, then its length
   size_t rf_U;      // R x kp double2: G0[:, V]
-  size_t rf_A;      // kp x 2kp double2: Gauss-Jordan on [diag(1/alpha) - G0[V,V] | I]
-  size_t rf_piv;    // kp double2: pivot column of the current Gauss-Jordan step
+  size_t rf_A;      // 2 kp^2 double2: two kp x kp buffers of the in-place Gauss-Jordan inverse
+                    // of diag(1/alpha) - G0[V,V], then M
+  size_t rf_piv;    // 16 kp + 64 bytes: the steps' pivot candidates, the pivots, the used rows
   size_t rf_Z;      // R x kp double2: G0[:, V] M
   size_t rf_x;      // kp double2: M Einc[V]
   // split-product flush (complex64 storage only): the pending terms as BF16

@@ -6,8 +6,8 @@
 //     M = (I - B_V G0[V,V])^-1 B_V = (diag(1/alpha) - G0[V,V])^-1,
 //     G = G0 + U M U_D^T,   E = Einc + U M Einc[V],
 // where U_D^T = G0[V, :] by reciprocity of the free-space kernel.
-// Steps: flipped list -> U gather (FP64 table / direct Hankel) -> Gauss-Jordan
-// inverse with partial pivoting -> Z = U M (FP64 MFMA) -> E -> G = G0 + Z U_D^T
+// Steps: flipped list -> U gather (FP64 table / direct Hankel) -> in-place
+// Gauss-Jordan inverse with partial pivoting -> Z = U M (FP64 MFMA) -> E -> G = G0 + Z U_D^T
 // (FP64 MFMA, G0 added in the epilogue, one rounding to the storage type).
 #include "gfo_internal.hpp"
 
@@ -96,111 +96,158 @@ __global__ void k_rf_gather_U(Geo g, const double2* __restrict__ table,
   U[t] = (i < k) ? g0_entry(g, table, mon_xy, r, V[i]) : make_double2(0.0, 0.0);
 }
 
-// Augmented [D - G0[V,V] | I] of size kp x 2kp, D = diag(1 / alpha); identity padding.
-__global__ void k_rf_build_aug(Geo g, const uint8_t* __restrict__ eps_idx,
-                               const int32_t* __restrict__ V, const double2* __restrict__ U, int k,
-                               int kp, double2* __restrict__ Aug) {
+// ------------------------------------------------------------------ Gauss-Jordan inverse
+// The k x k core A = D - G0[V,V], D = diag(1 / alpha), is inverted in place,
+// kp x kp with identity padding.  Step c takes as pivot p_c the row of largest
+// modulus in column c among the rows not yet used (lowest row on ties), scales
+// it by 1 / a[p][c] (its entry in column c becomes 1 / a[p][c]) and eliminates
+// column c from every other row (their entry in column c becomes
+// -a[r][c] / a[p][c]).  Rows are never swapped: after the kp steps the
+// inverse is read back through the pivots, A^-1[c][p_d] = X[p_c][d].  Each step
+// reads one buffer and writes the other, so no workgroup reads an entry that
+// another one of the same step writes.
+struct GjPart {
+  double m;   // |a[r][c + 1]|^2 of the workgroup's best unused row, -1 if none
+  int row;
+  int pad;
+};
+constexpr int kGjRows = 8;   // rows per workgroup of a step
+
+// Core A in W (row-major, ld kp) and the pivot flags cleared.
+__global__ void k_rf_build_core(Geo g, const uint8_t* __restrict__ eps_idx,
+                                const int32_t* __restrict__ V, const double2* __restrict__ U, int k,
+                                int kp, double2* __restrict__ W, int32_t* __restrict__ used) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)kp * 2 * kp) return;
-  const int a = (int)(t / (2 * kp)), b = (int)(t - (int64_t)a * 2 * kp);
+  if (t < kp) used[t] = 0;
+  if (t >= (int64_t)kp * kp) return;
+  const int a = (int)(t / kp), b = (int)(t - (int64_t)a * kp);
   double2 v = make_double2(0.0, 0.0);
-  if (b < kp) {
-    if (a < k && b < k) {
-      const double2 gab = U[(int64_t)V[a] * kp + b];   // G0[V_a, V_b]
-      v = make_double2(-gab.x, -gab.y);
-      if (a == b) {
-        const double alpha = g.k0sq * (g.eps[eps_idx[V[a]]] - g.eps[g.bg_idx]);
-        v.x += 1.0 / alpha;
-      }
-    } else if (a == b) {
-      v.x = 1.0;
+  if (a < k && b < k) {
+    const double2 gab = U[(int64_t)V[a] * kp + b];   // G0[V_a, V_b]
+    v = make_double2(-gab.x, -gab.y);
+    if (a == b) {
+      const double alpha = g.k0sq * (g.eps[eps_idx[V[a]]] - g.eps[g.bg_idx]);
+      v.x += 1.0 / alpha;
     }
-  } else if (b - kp == a) {
+  } else if (a == b) {
     v.x = 1.0;
   }
-  Aug[t] = v;
+  W[t] = v;
 }
 
-// Gauss-Jordan column c: pivot search (largest modulus, lowest row on ties),
-// row swap, scaling of the pivot row; saves column c of every row in f.
-__global__ __launch_bounds__(1024) void k_gj_pivot(double2* __restrict__ Aug, int kp, int c,
-                                                   double2* __restrict__ f, int32_t* status) {
-  __shared__ double smax[16];
-  __shared__ int sidx[16];
-  __shared__ int piv;
-  const int w2 = 2 * kp;
-  double best = -1.0;
-  int bi = 0x7fffffff;
-  for (int r = c + threadIdx.x; r < kp; r += blockDim.x) {
-    const double2 v = Aug[(int64_t)r * w2 + c];
-    const double m = v.x * v.x + v.y * v.y;
-    if (m > best) {
-      best = m;
-      bi = r;
-    }
-  }
-  // block arg-max (ties -> lowest row)
+// Block-wide arg-max of (m, row), largest m and lowest row on ties; every
+// thread returns the result.  256 threads.
+__device__ __forceinline__ void gj_argmax(double& m, int& row) {
+  __shared__ double sm[4];
+  __shared__ int sr[4];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    double ob = __shfl_xor(best, o, 64);
-    int oi = __shfl_xor(bi, o, 64);
-    if (ob > best || (ob == best && oi < bi)) {
-      best = ob;
-      bi = oi;
+    const double om = __shfl_xor(m, o, 64);
+    const int orow = __shfl_xor(row, o, 64);
+    if (om > m || (om == m && orow < row)) {
+      m = om;
+      row = orow;
     }
   }
   if (lane == 0) {
-    smax[w] = best;
-    sidx[w] = bi;
+    sm[w] = m;
+    sr[w] = row;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double b = -1.0;
-    int i = 0x7fffffff;
-    for (int q = 0; q < (int)(blockDim.x >> 6); ++q)
-      if (smax[q] > b || (smax[q] == b && sidx[q] < i)) {
-        b = smax[q];
-        i = sidx[q];
-      }
-    if (!(b > 0.0)) {
-      atomicOr(status, GFO_STATUS_SINGULAR);
-      i = c;
+  m = sm[0];
+  row = sr[0];
+#pragma unroll
+  for (int q = 1; q < 4; ++q)
+    if (sm[q] > m || (sm[q] == m && sr[q] < row)) {
+      m = sm[q];
+      row = sr[q];
     }
-    piv = i;
-  }
   __syncthreads();
-  const int p = piv;
-  if (p != c) {
-    for (int j = threadIdx.x; j < w2; j += blockDim.x) {
-      const double2 t = Aug[(int64_t)c * w2 + j];
-      Aug[(int64_t)c * w2 + j] = Aug[(int64_t)p * w2 + j];
-      Aug[(int64_t)p * w2 + j] = t;
-    }
-  }
-  __syncthreads();
-  const double2 d = Aug[(int64_t)c * w2 + c];
-  const double n = d.x * d.x + d.y * d.y;
-  const double2 inv = n > 0.0 ? make_double2(d.x / n, -d.y / n) : make_double2(1.0, 0.0);
-  __syncthreads();
-  for (int j = threadIdx.x; j < w2; j += blockDim.x) {
-    const int64_t o = (int64_t)c * w2 + j;
-    Aug[o] = cmul(Aug[o], inv);
-  }
-  for (int r = threadIdx.x; r < kp; r += blockDim.x) f[r] = Aug[(int64_t)r * w2 + c];
 }
 
-// Gauss-Jordan column c: eliminate column c from every other row.
-__global__ void k_gj_elim(double2* __restrict__ Aug, int kp, int c, const double2* __restrict__ f) {
-  const int w2 = 2 * kp;
+// Step c: S -> D.  Grid: kGjRows rows (blockIdx.x) x 256 columns (blockIdx.y)
+// per workgroup, one column per thread.  The pivot of column c comes from the
+// previous step's candidates, one per row group (part_in, n_in), or for c = 0
+// from column 0 itself.  The thread that holds column c + 1 leaves its row
+// group's best unused row for the next step; the workgroup (group of p_c, 0)
+// records the pivot (piv[c], used).
+__global__ __launch_bounds__(256) void k_gj_step(const double2* __restrict__ S, double2* __restrict__ D,
+                                                 int kp, int c, const GjPart* __restrict__ part_in,
+                                                 int n_in, GjPart* __restrict__ part_out,
+                                                 int32_t* __restrict__ piv, int32_t* __restrict__ used,
+                                                 int32_t* __restrict__ status) {
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  if (part_in != nullptr) {
+    for (int q = threadIdx.x; q < n_in; q += blockDim.x) {
+      const GjPart pq = part_in[q];
+      if (pq.m > best || (pq.m == best && pq.row < bi)) {
+        best = pq.m;
+        bi = pq.row;
+      }
+    }
+  } else {
+    for (int r = threadIdx.x; r < kp; r += blockDim.x) {
+      const double2 v = S[(int64_t)r * kp + c];
+      double m = v.x * v.x + v.y * v.y;
+      if (!(m >= 0.0)) m = 0.0;   // a NaN row stays a candidate: some row is always chosen
+      if (m > best) {
+        best = m;
+        bi = r;
+      }
+    }
+  }
+  gj_argmax(best, bi);
+  const int p = bi;
+  const int r0 = blockIdx.x * kGjRows;
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
+    if (blockIdx.x == 0 && !(best > 0.0)) atomicOr(status, GFO_STATUS_SINGULAR);
+    if (p >= r0 && p < r0 + kGjRows) {
+      piv[c] = p;
+      used[p] = 1;
+    }
+  }
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  if (j >= kp) return;
+  const double2 d = S[(int64_t)p * kp + c];
+  const double n = d.x * d.x + d.y * d.y;
+  const double2 inv = n > 0.0 ? make_double2(d.x / n, -d.y / n) : make_double2(1.0, 0.0);
+  const double2 pc = j == c ? inv : cmul(S[(int64_t)p * kp + j], inv);
+  double nb = -1.0;
+  int ni = 0x7fffffff;
+#pragma unroll
+  for (int rr = 0; rr < kGjRows; ++rr) {
+    const int r = r0 + rr;
+    if (r < kp) {
+      double2 out = pc;
+      if (r != p) {
+        const double2 fr = S[(int64_t)r * kp + c];
+        const double2 v = j == c ? make_double2(0.0, 0.0) : S[(int64_t)r * kp + j];
+        out = make_double2(v.x - (fr.x * pc.x - fr.y * pc.y), v.y - (fr.x * pc.y + fr.y * pc.x));
+      }
+      D[(int64_t)r * kp + j] = out;
+      // a candidate pivot of column c + 1: not p, not used before this step
+      if (j == c + 1 && r != p && used[r] == 0) {
+        double m = out.x * out.x + out.y * out.y;
+        if (!(m >= 0.0)) m = 0.0;
+        if (m > nb) {   // rows in increasing order: the lowest row wins ties
+          nb = m;
+          ni = r;
+        }
+      }
+    }
+  }
+  if (j == c + 1) part_out[blockIdx.x] = GjPart{nb, ni, 0};
+}
+
+// M = A^-1 from the in-place result X: M[c][p_d] = X[p_c][d].
+__global__ void k_gj_unpermute(const double2* __restrict__ X, double2* __restrict__ M,
+                               const int32_t* __restrict__ piv, int kp) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)kp * w2) return;
-  const int r = (int)(t / w2), j = (int)(t - (int64_t)r * w2);
-  if (r == c) return;
-  const double2 fr = f[r];
-  const double2 pc = Aug[(int64_t)c * w2 + j];
-  const double2 v = Aug[t];
-  Aug[t] = make_double2(v.x - (fr.x * pc.x - fr.y * pc.y), v.y - (fr.x * pc.y + fr.y * pc.x));
+  if (t >= (int64_t)kp * kp) return;
+  const int c = (int)(t / kp), d = (int)(t - (int64_t)c * kp);
+  M[(int64_t)c * kp + piv[d]] = X[(int64_t)piv[c] * kp + d];
 }
 
 // ------------------------------------------------------------------ FP64 MFMA complex GEMM
@@ -434,13 +481,13 @@ __global__ __launch_bounds__(512) void k_zgemm_f64_t128(int M, int N, int K, con
 
 // x = M Einc[V] (k-vector), then E[r] = Einc[r] + sum_i U[r, i] x_i.
 __global__ void k_rf_xE(Geo g, const double* __restrict__ mon_xy, const int32_t* __restrict__ V,
-                        const double2* __restrict__ Aug, int k, int kp, double2* __restrict__ x) {
+                        const double2* __restrict__ M, int k, int kp, double2* __restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= kp) return;
   double2 s = make_double2(0.0, 0.0);
   if (i < k)
     for (int j = 0; j < k; ++j)
-      s = cadd(s, cmul(Aug[(int64_t)i * 2 * kp + kp + j], incident(g, mon_xy, V[j])));
+      s = cadd(s, cmul(M[(int64_t)i * kp + j], incident(g, mon_xy, V[j])));
   x[i] = s;
 }
 
@@ -479,30 +526,42 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, int32_t k
   const double* mon = (const double*)(w + L.mon_xy);
   int32_t* V = (int32_t*)(w + L.rf_V);
   double2* U = (double2*)(w + L.rf_U);
-  double2* Aug = (double2*)(w + L.rf_A);
-  double2* f = (double2*)(w + L.rf_piv);
   double2* Z = (double2*)(w + L.rf_Z);
   double2* x = (double2*)(w + L.rf_x);
   const int kp = (k + 3) / 4 * 4;
+  double2* M = nullptr;
   if (kp > 0) {
     const int64_t nu = (int64_t)g.R * kp;
     hipLaunchKernelGGL(k_rf_gather_U, dim3((unsigned)((nu + 255) / 256)), dim3(256), 0, s, g, table,
                        mon, (const int32_t*)V, k, kp, U);
-    const int64_t na = (int64_t)kp * 2 * kp;
-    hipLaunchKernelGGL(k_rf_build_aug, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, g,
-                       (const uint8_t*)st->eps_idx, (const int32_t*)V, (const double2*)U, k, kp, Aug);
-    for (int c = 0; c < kp; ++c) {
-      hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, Aug, kp, c, f, st->status);
-      hipLaunchKernelGGL(k_gj_elim, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, Aug, kp, c,
-                         (const double2*)f);
-    }
-    // Z = U M, M = right half of Aug (row-major, ld 2kp)
+    // two kp x kp buffers in the 2 kp^2 entries of rf_A; in rf_piv (16 kp + 64
+    // bytes): the per-workgroup candidates of two steps, the pivots, the flags
+    const int nb = (kp + kGjRows - 1) / kGjRows;
+    double2* W[2] = {(double2*)(w + L.rf_A), (double2*)(w + L.rf_A) + (int64_t)kp * kp};
+    GjPart* part[2] = {(GjPart*)(w + L.rf_piv), (GjPart*)(w + L.rf_piv) + nb};
+    int32_t* piv = (int32_t*)(part[1] + nb);
+    int32_t* used = piv + kp;
+    const int64_t na = (int64_t)kp * kp;
+    hipLaunchKernelGGL(k_rf_build_core, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, g,
+                       (const uint8_t*)st->eps_idx, (const int32_t*)V, (const double2*)U, k, kp, W[0],
+                       used);
+    const dim3 gj_grid((unsigned)nb, (unsigned)((kp + 255) / 256));
+    for (int c = 0; c < kp; ++c)
+      hipLaunchKernelGGL(k_gj_step, gj_grid, dim3(256), 0, s, (const double2*)W[c & 1],
+                         W[(c + 1) & 1], kp, c, c == 0 ? (const GjPart*)nullptr : (const GjPart*)part[(c + 1) & 1],
+                         nb, part[c & 1], piv, used, st->status);
+    // after kp steps the in-place result is in W[kp & 1]; M goes to the other
+    M = W[(kp + 1) & 1];
+    hipLaunchKernelGGL(k_gj_unpermute, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s,
+                       (const double2*)W[kp & 1], M, (const int32_t*)piv, kp);
+    // Z = U M
     EpiStoreZ ez{Z, kp};
     hipLaunchKernelGGL((k_zgemm_f64_t128<false, false, EpiStoreZ>),
-                       dim3((kp + kZgT - 1) / kZgT, (g.R + kZgT - 1) / kZgT), dim3(512), 0, s, g.R, kp, kp, (const double2*)U, (int64_t)kp,
-                       (const double2*)(Aug + kp), (int64_t)2 * kp, (const int32_t*)nullptr, ez, 0);
+                       dim3((kp + kZgT - 1) / kZgT, (g.R + kZgT - 1) / kZgT), dim3(512), 0, s, g.R, kp, kp,
+                       (const double2*)U, (int64_t)kp, (const double2*)M, (int64_t)kp,
+                       (const int32_t*)nullptr, ez, 0);
     hipLaunchKernelGGL(k_rf_xE, dim3((kp + 255) / 256), dim3(256), 0, s, g, mon, (const int32_t*)V,
-                       (const double2*)Aug, k, kp, x);
+                       (const double2*)M, k, kp, x);
   }
   hipLaunchKernelGGL(k_rf_field<T>, dim3((g.R + 255) / 256), dim3(256), 0, s, g, mon,
                      (const double2*)U, (const double2*)x, k, kp, (T*)st->E);
