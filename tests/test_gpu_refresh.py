@@ -47,6 +47,48 @@ def test_refresh_equals_dense_resolve(dtype, fill, seed):
     assert np.array_equal(idx, idx2) and job.status() == 0
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("upper", [False, True])
+def test_refresh_large_flipped_set_equals_dense_resolve(dtype, upper):
+    """301 flipped pixels of 624 (kp = 304): each Gauss-Jordan step spans two
+    256-column chunks and 38 row groups, the products have ragged 128-row tiles
+    and a partial chunk of 8 terms.  With the upper triangle kept alone the
+    product leaves out the tiles below the diagonal; the lower triangle copied
+    back gives the same state.
+
+    Tolerance: two FP64 solves of one system differ by up to a modest multiple
+    of u kappa, u = 2^-53 and kappa the 2-norm condition number of the core
+    diag(1/alpha) - G0[V,V] (here about 1.1e3).  LAPACK's own inverse put
+    through the same Woodbury formula lands 21 u kappa from the dense solve;
+    the bound is 100 u kappa (complex64: plus one rounding)."""
+    p = W.tiny(24, 26, n_mon=6, dtype=dtype)
+    N = p.n
+    rng = np.random.default_rng(7)
+    idx = np.zeros(N, np.uint8)
+    idx[rng.choice(N, 301, replace=False)] = 1
+    job = _job(p, kmax=301, upper=upper)
+    job.init()
+    junk = rng.standard_normal((p.rows, N)) + 1j * rng.standard_normal((p.rows, N))
+    job.upload_state(junk, junk[:, 0], junk[:N, 1], idx)
+    job.state.lower_stale = int(upper)
+    job.refresh()
+    assert job.state.lower_stale == int(upper)
+    G, E, d, idx2 = job.host_state()
+    eps = ost.eps_of(p, idx)
+    Gd, Ed = ost.dense_state(p, eps)
+    G0 = greens.build_G0(p)
+    alpha = greens.alpha_of(p, eps)
+    V = np.nonzero(alpha != 0)[0]
+    kappa = np.linalg.cond(np.diag(1.0 / alpha[V]) - G0[np.ix_(V, V)])
+    tol64 = max(1e-12, 100 * 2.0 ** -53 * kappa)
+    tol = tol64 if dtype == "c128" else 3e-7 + tol64
+    print(f"kappa {kappa:.3g}: G {_rel(G, Gd):.3g}, E {_rel(E, Ed):.3g} (bound {tol:.3g})", flush=True)
+    assert _rel(G, Gd) <= tol
+    assert _rel(E, Ed) <= tol
+    assert _rel(d, np.diagonal(Gd[:N])) <= tol64
+    assert np.array_equal(idx, idx2) and job.status() == 0
+
+
 def test_refresh_overflow_sets_status_and_changes_nothing():
     """More flipped pixels than kmax: GFO_ERANGE, the status bit, and the state
     exactly as it was."""
