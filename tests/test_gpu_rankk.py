@@ -121,6 +121,34 @@ def test_rank_k_trajectory_matches_oracle_policy():
         assert abs(fom - group[0].fom) <= 1e-4 * group[0].fom
 
 
+def test_rank_k_upper_triangle_trajectory_with_refresh():
+    """The rank-16 trajectory with only the upper triangle kept (state.lower_stale:
+    the rank-k update and the refresh's product leave out the blocks below the
+    diagonal, every read goes to the upper triangle) and an FP64 refresh after
+    every two steps: the chosen sets and the FOM follow the oracle's policy, and
+    the final state with its lower triangle copied back is the dense re-solve's."""
+    from paper_2202_05388_amd import _lib as L
+    p = W.tiny(40, 40, n_mon=8, dtype="c64", cand_mask=W.MASK_BOTH, rank_k=16, min_spacing=3,
+               steps=6, tau=1e-6)
+    ref = og.rank_k_trajectory(p, steps=6, tier="T2")
+    job = _job(p, kmax=256, upper=True)
+    job.init()
+    assert job.state.lower_stale == 1
+    for t, group in enumerate(ref.steps):
+        job.score(topk=16, min_spacing=3, tau=1e-6)
+        got = [(a, b) for a, b, _, _ in job.read_picks(16) if a >= 0]
+        assert got == [(s.pixel, s.eps_idx) for s in group], t
+        job.apply_rank_k(16, precision=L.GFO_FP32)
+        if t % 2 == 1:
+            job.refresh()
+        assert job.state.lower_stale == 1
+        assert abs(job.fom() - group[0].fom) <= 1e-4 * group[0].fom, t
+    G1, E1, d1, idx1 = job.host_state()
+    Gd, Ed = ost.dense_state(p, ost.eps_of(p, idx1))
+    assert _rel(G1, Gd) <= 3e-7 and _rel(E1, Ed) <= 3e-7   # the last step was refreshed
+    assert job.status() == 0
+
+
 def test_rank_k_three_materials_follows_oracle_policy():
     """Spaced top-k over (pixel, material) with a three-entry table: at most one
     move per pixel, the chosen sets and the FOM follow the oracle's policy."""
