@@ -59,66 +59,176 @@ __global__ __launch_bounds__(kSelectThreads) void k_select(
   const int total = g.N * g.n_eps;
   const int win = spacing > 1 ? spacing - 1 : 0;
   int t = 0;
-  for (; t < topk; ++t) {
-    double m = -INFINITY;
-    if (t == 0) {
-      for (int i = threadIdx.x; i < nblk; i += blockDim.x) m = fmax(m, partial[i]);
-    } else {
-      for (int i = threadIdx.x; i < total; i += blockDim.x) m = fmax(m, scores[i]);
+  if (nblk * kScoreThreads >= g.N && blockDim.x == kSelectThreads) {
+    // One pixel per score thread: workgroup b's scores are [b span, b span + span),
+    // partial[b] their maximum and pfirst[b] the lowest index within the tie band
+    // of that maximum.  Both summaries stay in LDS.  A pick takes the first chunk
+    // whose maximum reaches the band; if that chunk holds the global maximum its
+    // summary is the winner (the same decision as greedy_pick_block), otherwise
+    // (a near-tie across chunks) the chunk is scanned.  After the exclusion the
+    // chunks it touched are summarised again, two at a time, 512 threads and at
+    // most kSelVals scores per thread each.
+    static_assert(kSelectThreads == 1024, "two groups of eight waves");
+    constexpr int kSelVals = kScoreThreads * GFO_MAX_EPS / 512;
+    __shared__ double spart[kScoreMaxBlocks];
+    __shared__ int sfirst[kScoreMaxBlocks];
+    __shared__ double gm[kSelectThreads / 64];
+    __shared__ int gf[kSelectThreads / 64];
+    const int span = kScoreThreads * g.n_eps;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+      spart[i] = partial[i];
+      sfirst[i] = pfirst[i];
     }
-    m = block_max(m, shd);
-    if (!(m > fom * (1.0 + tau))) break;
-    const double thr = m - tau * m;
-    int first = 0x7fffffff;
-    if (t == 0 && nblk * kScoreThreads >= g.N) {
-      // score workgroup b covered pixels [b*256, b*256 + 256): only workgroups whose
-      // maximum reaches the tie threshold can hold the winner; visit them in order
-      const int span = kScoreThreads * g.n_eps;
-      for (int b = 0; b < nblk; ++b) {
-        if (!(partial[b] >= thr)) continue;          // uniform across the workgroup
-        const int lo = b * span, hi = min(lo + span, total);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int grp = threadIdx.x >> 9, gi = threadIdx.x & 511;   // two groups of eight waves
+    for (; t < topk; ++t) {
+      double m = -INFINITY;
+      for (int i = threadIdx.x; i < nblk; i += blockDim.x) m = fmax(m, spart[i]);
+      m = block_max(m, shd);
+      if (!(m > fom * (1.0 + tau))) break;
+      const double thr = tie_threshold(m, tau);
+      int bq = 0x7fffffff;
+      for (int i = threadIdx.x; i < nblk; i += blockDim.x)
+        if (spart[i] >= thr) {
+          bq = i;
+          break;
+        }
+      bq = block_min(bq, shi);
+      if (bq == 0x7fffffff) break;                    // non-finite scores
+      int first = sfirst[bq];
+      if (!(spart[bq] == m) || first == 0x7fffffff) {
+        const int lo = bq * span, hi = min(lo + span, total);
         int f = 0x7fffffff;
-        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        for (int i = lo + threadIdx.x; i < hi; i += blockDim.x)
           if (scores[i] >= thr) {
             f = i;
             break;
           }
-        }
-        f = block_min(f, shi);
-        if (f != 0x7fffffff) {
-          first = f;
-          break;
-        }
+        first = block_min(f, shi);
       }
-    } else {
-      for (int i = threadIdx.x; i < total; i += blockDim.x) {
-        if (scores[i] >= thr) {
-          first = i;
-          break;
-        }
+      if (first == 0x7fffffff) break;
+      const int j = first / g.n_eps;
+      if (threadIdx.x == 0) {
+        gfo_pick pk;
+        pk.pixel = j;
+        pk.eps_idx = first - j * g.n_eps;
+        pk.fom_new = scores[first];
+        pk.dfom = pk.fom_new - fom;
+        out[t] = pk;
       }
-      first = block_min(first, shi);
+      if (t + 1 < topk) {   // exclude the pick's window, then summarise the chunks it touched
+        const int iy = j / g.nx, ix = j - (j / g.nx) * g.nx;
+        const int w = 2 * win + 1;
+        __syncthreads();
+        for (int k = threadIdx.x; k < w * w * g.n_eps; k += blockDim.x) {
+          const int e = k % g.n_eps, cell = k / g.n_eps;
+          const int yy = iy - win + cell / w, xx = ix - win + cell % w;
+          if (yy >= 0 && yy < g.ny && xx >= 0 && xx < g.nx)
+            scores[(int64_t)(yy * g.nx + xx) * g.n_eps + e] = -INFINITY;
+        }
+        __syncthreads();
+        const int b_lo = (max(iy - win, 0) * g.nx + max(ix - win, 0)) / kScoreThreads;
+        const int b_hi = min((min(iy + win, g.ny - 1) * g.nx + min(ix + win, g.nx - 1)) / kScoreThreads, nblk - 1);
+        for (int b0 = b_lo; b0 <= b_hi; b0 += 2) {       // uniform
+          const int b = b0 + grp;
+          const bool live = b <= b_hi;
+          const int lo = b * span, hi = live ? min(lo + span, total) : lo;
+          double v[kSelVals];
+          double mb = -INFINITY;
+#pragma unroll
+          for (int q = 0; q < kSelVals; ++q) {
+            const int i = lo + gi + 512 * q;
+            v[q] = i < hi ? scores[i] : -INFINITY;
+            mb = fmax(mb, v[q]);
+          }
+          mb = wave_max(mb);
+          if (lane == 0) gm[wv] = mb;
+          __syncthreads();
+          mb = -INFINITY;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) mb = fmax(mb, gm[8 * grp + q]);
+          const double tb = tie_threshold(mb, tau);
+          int fb = 0x7fffffff;
+#pragma unroll
+          for (int q = kSelVals - 1; q >= 0; --q)
+            if (mb > -INFINITY && v[q] >= tb) fb = lo + gi + 512 * q;
+          fb = wave_min(fb);
+          if (lane == 0) gf[wv] = fb;
+          __syncthreads();
+          if (live && gi == 0) {
+            int f = 0x7fffffff;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) f = min(f, gf[8 * grp + q]);
+            spart[b] = mb;
+            sfirst[b] = f;
+          }
+        }
+        __syncthreads();
+      }
     }
-    const int j = first / g.n_eps;
-    if (threadIdx.x == 0) {
-      gfo_pick pk;
-      pk.pixel = j;
-      pk.eps_idx = first - j * g.n_eps;
-      pk.fom_new = scores[first];
-      pk.dfom = pk.fom_new - fom;
-      out[t] = pk;
-    }
-    if (t + 1 < topk) {
-      __syncthreads();
-      const int iy = j / g.nx, ix = j - (j / g.nx) * g.nx;
-      const int w = 2 * win + 1;
-      for (int k = threadIdx.x; k < w * w * g.n_eps; k += blockDim.x) {
-        const int e = k % g.n_eps, cell = k / g.n_eps;
-        const int yy = iy - win + cell / w, xx = ix - win + cell % w;
-        if (yy >= 0 && yy < g.ny && xx >= 0 && xx < g.nx)
-          scores[(int64_t)(yy * g.nx + xx) * g.n_eps + e] = -INFINITY;
+  } else {
+    for (; t < topk; ++t) {
+      double m = -INFINITY;
+      if (t == 0) {
+        for (int i = threadIdx.x; i < nblk; i += blockDim.x) m = fmax(m, partial[i]);
+      } else {
+        for (int i = threadIdx.x; i < total; i += blockDim.x) m = fmax(m, scores[i]);
       }
-      __syncthreads();
+      m = block_max(m, shd);
+      if (!(m > fom * (1.0 + tau))) break;
+      const double thr = m - tau * m;
+      int first = 0x7fffffff;
+      if (t == 0 && nblk * kScoreThreads >= g.N) {
+        // score workgroup b covered pixels [b*256, b*256 + 256): only workgroups whose
+        // maximum reaches the tie threshold can hold the winner; visit them in order
+        const int span = kScoreThreads * g.n_eps;
+        for (int b = 0; b < nblk; ++b) {
+          if (!(partial[b] >= thr)) continue;          // uniform across the workgroup
+          const int lo = b * span, hi = min(lo + span, total);
+          int f = 0x7fffffff;
+          for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            if (scores[i] >= thr) {
+              f = i;
+              break;
+            }
+          }
+          f = block_min(f, shi);
+          if (f != 0x7fffffff) {
+            first = f;
+            break;
+          }
+        }
+      } else {
+        for (int i = threadIdx.x; i < total; i += blockDim.x) {
+          if (scores[i] >= thr) {
+            first = i;
+            break;
+          }
+        }
+        first = block_min(first, shi);
+      }
+      const int j = first / g.n_eps;
+      if (threadIdx.x == 0) {
+        gfo_pick pk;
+        pk.pixel = j;
+        pk.eps_idx = first - j * g.n_eps;
+        pk.fom_new = scores[first];
+        pk.dfom = pk.fom_new - fom;
+        out[t] = pk;
+      }
+      if (t + 1 < topk) {
+        __syncthreads();
+        const int iy = j / g.nx, ix = j - (j / g.nx) * g.nx;
+        const int w = 2 * win + 1;
+        for (int k = threadIdx.x; k < w * w * g.n_eps; k += blockDim.x) {
+          const int e = k % g.n_eps, cell = k / g.n_eps;
+          const int yy = iy - win + cell / w, xx = ix - win + cell % w;
+          if (yy >= 0 && yy < g.ny && xx >= 0 && xx < g.nx)
+            scores[(int64_t)(yy * g.nx + xx) * g.n_eps + e] = -INFINITY;
+        }
+        __syncthreads();
+      }
     }
   }
   if (threadIdx.x == 0) {
