@@ -483,23 +483,25 @@ def eps_greedy_study(runs=20, eps_list=(0.0, 0.1, 0.2, 0.3), with_oracle=True):
                 gpu_moves_per_s=steps_total / t_total, cpu_baseline=cpu)
 
 
-def time_eps_greedy(problem, steps, eps, delay):
+def time_eps_greedy(problem, steps, eps, delay, fused=True):
     """Epsilon-greedy steps (top-4 scores, drawn choice, rank-1 apply; deferred
-    updates when delay > 0) until `steps` moves, restarting finished trajectories."""
+    updates when delay > 0) until `steps` moves, restarting finished trajectories.
+    fused: the steps that do not explore run through gfo_greedy_steps; otherwise
+    every step takes the top-4 path (the same moves and state)."""
     import torch
     import workloads as W
     from paper_2202_05388_amd.job import Job
 
     job = Job(problem, device="cuda:0", delay=delay, ld_pad=LD_PAD)
     job.init()
-    job.run_eps_greedy(eps, W.eps_greedy_draws(64, 99), poll_every=64)   # warm-up
+    job.run_eps_greedy(eps, W.eps_greedy_draws(64, 99), poll_every=64, fused=fused)   # warm-up
     job.init()
     torch.cuda.synchronize()
     moves, restarts, seed = 0, 0, 0
     t0 = time.perf_counter()
     while moves < steps:
         n = job.run_eps_greedy(eps, W.eps_greedy_draws(min(2000, steps - moves), seed),
-                               poll_every=32)
+                               poll_every=32, fused=fused)
         moves += n
         seed += 1
         if job.delay:
@@ -510,8 +512,8 @@ def time_eps_greedy(problem, steps, eps, delay):
     dt = time.perf_counter() - t0
     del job
     torch.cuda.empty_cache()
-    return dict(eps=eps, delay=delay, moves=moves, restarts=restarts, moves_per_s=moves / dt,
-                ms_per_move=1e3 * dt / moves)
+    return dict(eps=eps, delay=delay, fused=fused, moves=moves, restarts=restarts,
+                moves_per_s=moves / dt, ms_per_move=1e3 * dt / moves)
 
 
 def time_regions(problem, steps, delay, apply):
@@ -925,7 +927,9 @@ def main():
         _log("[bench] epsilon-greedy study (21x21 lens) and rate at 128^2")
         eps_greedy = dict(study=eps_greedy_study(with_oracle=not args.no_cpu_baseline),
                           square128_c64=time_eps_greedy(problem, min(args.steps, 1000), 0.1,
-                                                        args.delay))
+                                                        args.delay),
+                          square128_c64_per_step=time_eps_greedy(problem, min(args.steps, 1000),
+                                                                 0.1, args.delay, fused=False))
         _log(f"[bench] epsilon-greedy {eps_greedy}")
 
     regions = None

@@ -174,19 +174,33 @@ class Job:
         self.apply(pick_ptr=chosen, stream=stream)
         self.steps_issued += 1
 
-    def run_eps_greedy(self, eps, draws, max_steps=None, poll_every=32, stream=None):
+    def run_eps_greedy(self, eps, draws, max_steps=None, poll_every=32, fused=True, stream=None):
         """Epsilon-greedy trajectory; step t uses draws[t] = (u_explore, u_choice).
         Polls the move counter every poll_every steps and stops once a step made no
         move (every earlier step moved: the policy only takes improving moves).
+
+        fused: a step whose draw does not explore (u_explore >= eps) takes the
+        greedy pick, the first record of the top-n selection, so runs of such
+        steps go through gfo_greedy_steps (one kernel per move in deferred mode);
+        the exploring steps take the top-4 scores and the drawn choice.  Bit for
+        bit the per-step path's moves and state (fused=False: every step through
+        eps_greedy_step).
         Returns the number of moves made by this call."""
         start = self.n_flips()
         n = len(draws) if max_steps is None else min(max_steps, len(draws))
         t = 0
         while t < n:
-            chunk = min(poll_every, n - t)
-            for i in range(chunk):
-                self.eps_greedy_step(eps, draws[t + i][0], draws[t + i][1], stream=stream)
-            t += chunk
+            end = min(t + poll_every, n)
+            while t < end:
+                if not fused or draws[t][0] < eps:
+                    self.eps_greedy_step(eps, draws[t][0], draws[t][1], stream=stream)
+                    t += 1
+                else:
+                    u = t
+                    while u < end and not draws[u][0] < eps:
+                        u += 1
+                    self.greedy_steps(u - t, stream=stream)
+                    t = u
             if self.n_flips() - start < t:
                 break
         return self.n_flips() - start

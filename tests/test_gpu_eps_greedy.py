@@ -81,3 +81,25 @@ def test_eps_greedy_three_materials_matches_oracle(eps, seed):
     E = job.E.cpu().numpy()
     assert rel_elem(E, ref.E) <= 1e-9
     assert job.status() == 0
+
+
+@pytest.mark.parametrize("dtype,delay,eps", [("c128", 0, 0.3), ("c64", 8, 0.3), ("c64", 16, 0.1),
+                                             ("c64", 0, 0.5)])
+def test_eps_greedy_fused_runs_equal_per_step_path(dtype, delay, eps):
+    """Steps whose draw does not explore go through gfo_greedy_steps in runs; the
+    moves and the whole state equal, bit for bit, those of every step taken
+    through the top-4 selection, the drawn choice and apply_flip."""
+    p = W.tiny(40, 40, n_mon=8, dtype=dtype, cand_mask=W.MASK_BOTH,
+               tau=1e-9 if dtype == "c128" else 1e-6)
+    draws = W.eps_greedy_draws(600, 11)
+    out = []
+    for fused in (False, True):
+        job = _job(p, delay=delay)
+        job.init()
+        n = job.run_eps_greedy(eps, draws, poll_every=24, fused=fused)
+        G, E, d, idx = job.host_state()
+        out.append((n, job.history(), G, E, d, idx, job.status()))
+    (n0, h0, G0, E0, d0, i0, s0), (n1, h1, G1, E1, d1, i1, s1) = out
+    assert n0 == n1 > 50 and np.array_equal(h0, h1)
+    assert np.array_equal(G0, G1) and np.array_equal(E0, E1) and np.array_equal(d0, d1)
+    assert np.array_equal(i0, i1) and s0 == s1 == 0
