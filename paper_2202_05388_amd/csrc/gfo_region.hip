@@ -65,18 +65,34 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_regions(
         Gvv[i][j] = i == j ? diag64[V[i]] : St<T>::to_d(G[g_at(g, V[i], V[j])]);
     }
     const int K = count ? *count : 0;
-    for (int s = 0; s < K; ++s) {
-      double2 cu[kRegionPix], v[kRegionPix];
+    // terms in groups of kTermBatch: every load of a group is issued before its
+    // first use (each term is an L2 round trip), the sums in term order
+    constexpr int kTermBatch = 4;
+    for (int s0 = 0; s0 < K; s0 += kTermBatch) {
+      T cuw[kTermBatch][kRegionPix], vw[kTermBatch][kRegionPix];
 #pragma unroll
-      for (int i = 0; i < kRegionPix; ++i) {
-        cu[i] = St<T>::to_d(CUs[(int64_t)s * g.R + V[i]]);
-        v[i] = St<T>::to_d(Vs[(int64_t)s * g.ld + V[i]]);
+      for (int u = 0; u < kTermBatch; ++u)
+#pragma unroll
+        for (int i = 0; i < kRegionPix; ++i)
+          if (s0 + u < K) {
+            cuw[u][i] = CUs[(int64_t)(s0 + u) * g.R + V[i]];
+            vw[u][i] = Vs[(int64_t)(s0 + u) * g.ld + V[i]];
+          }
+#pragma unroll
+      for (int u = 0; u < kTermBatch; ++u) {
+        if (s0 + u >= K) break;
+        double2 cu[kRegionPix], v[kRegionPix];
+#pragma unroll
+        for (int i = 0; i < kRegionPix; ++i) {
+          cu[i] = St<T>::to_d(cuw[u][i]);
+          v[i] = St<T>::to_d(vw[u][i]);
+        }
+#pragma unroll
+        for (int i = 0; i < kRegionPix; ++i)
+#pragma unroll
+          for (int j = 0; j < kRegionPix; ++j)
+            if (i != j) Gvv[i][j] = cadd(Gvv[i][j], cmul(cu[i], v[j]));
       }
-#pragma unroll
-      for (int i = 0; i < kRegionPix; ++i)
-#pragma unroll
-        for (int j = 0; j < kRegionPix; ++j)
-          if (i != j) Gvv[i][j] = cadd(Gvv[i][j], cmul(cu[i], v[j]));
     }
     const double2 Em0 = St<T>::to_d(E[g.N + g.m0]);
 #pragma unroll
