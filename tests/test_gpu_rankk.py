@@ -45,6 +45,30 @@ def test_topk_selection_matches_oracle(k, spacing, seed):
     assert all(a < 0 for a, _, _, _ in got[len(ref):])
 
 
+@pytest.mark.parametrize("n_eps", [3, 8])
+@pytest.mark.parametrize("k,spacing,seed", [(12, 0, 3), (20, 2, 4)])
+def test_topk_selection_many_materials_matches_oracle(n_eps, k, spacing, seed):
+    """The spaced top-k selection over (pixel, material) with 3- and 8-entry
+    tables on 624 pixels: three score chunks of 256 pixels, up to 2048 scores per
+    chunk, each pick's excluded window summarised again; equal to the oracle's
+    rule, sentinels after the last improving move."""
+    table = {3: (1.0, 12.25, 2.25), 8: (1.0, 12.25, 2.25, 4.0, 6.25, 9.0, 3.0, 1.5)}[n_eps]
+    p = W.tiny(24, 26, n_mon=8, dtype="c64", cand_mask=(1 << n_eps) - 1, eps_table=table)
+    N = p.n
+    idx = W.random_material_idx(p, seed)
+    G, E = ost.dense_state(p, ost.eps_of(p, idx))
+    job = _job(p)
+    job.upload_state(G, E, np.diagonal(G[:N]), idx)
+    job.score(topk=k, min_spacing=spacing, tau=1e-6)
+    got = job.read_picks(k)
+    F = og.scores_closed_form(p, E, np.diagonal(G[:N]), G[N + p.fom_monitor], idx)
+    ref = og.select_rank_k(F, ost.fom_of_state(p, E), 1e-6, k, spacing, p.nx)
+    assert len(ref) >= 4
+    gp = [(a, b) for a, b, _, _ in got if a >= 0]
+    assert gp == [(r.pixel, r.eps_idx) for r in ref]
+    assert all(a < 0 for a, _, _, _ in got[len(ref):])
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("s", [1, 7, 16, 24])
 def test_rank_k_update_equals_resolve(precision, s):
