@@ -371,8 +371,10 @@ int apply_flips_rank_k(const gfo_problem* prob, gfo_state* st, const gfo_pick* d
  * and |V| <= kmax.  |V| is counted first: with |V| > kmax the call returns
  * GFO_ERANGE and sets GFO_STATUS_REFRESH_OVERFLOW, and nothing else changes
  * (G, E, diag64, the pending deferred terms and state.pending_calls are left
- * as they were).  In deferred mode the design block is written on and above
- * its diagonal only (state.lower_stale set).  Exception to asynchrony:
+ * as they were).  The design block is computed on and above its diagonal (it
+ * is symmetric); in deferred mode, or with state.lower_stale set, only that
+ * triangle is written (state.lower_stale set), otherwise the lower triangle is
+ * written as its mirror.  Exception to asynchrony:
  * synchronises `stream` once, to read |V|, before any of the rebuild is
  * enqueued. */
 int refresh_G(const gfo_problem* prob, gfo_state* st, hipStream_t stream);

@@ -565,15 +565,17 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, int32_t k
   }
   hipLaunchKernelGGL(k_rf_field<T>, dim3((g.R + 255) / 256), dim3(256), 0, s, g, mon,
                      (const double2*)U, (const double2*)x, k, kp, (T*)st->E);
-  // G = G0 + Z U_D^T over the N design columns (padding columns stay zero); in
-  // deferred mode, or when the caller keeps the upper triangle alone, the
-  // design block on and above its diagonal only
+  // G = G0 + Z U_D^T over the N design columns (padding columns stay zero):
+  // the monitor rows whole and the design block on and above its diagonal (the
+  // block is symmetric); when the caller keeps the whole block, its lower
+  // triangle is then the mirror of the upper one (half the product's work)
   EpiG0<T> eg{g, table, mon, (T*)st->G, (double2*)st->diag64};
   hipLaunchKernelGGL((k_zgemm_f64_t128<false, true, EpiG0<T>>),
                      dim3((g.N + kZgT - 1) / kZgT, (g.R + kZgT - 1) / kZgT), dim3(512), 0, s, g.R, g.N, kp, (const double2*)Z, (int64_t)kp,
-                     (const double2*)U, (int64_t)kp, (const int32_t*)nullptr, eg,
-                     g.upper ? g.N : 0);
-  return note_hip(hipGetLastError()) == hipSuccess ? GFO_OK : GFO_EHIP;
+                     (const double2*)U, (int64_t)kp, (const int32_t*)nullptr, eg, g.N);
+  if (note_hip(hipGetLastError()) != hipSuccess) return GFO_EHIP;
+  if (!g.upper && launch_sync_lower(g, st, s) != hipSuccess) return GFO_EHIP;   // dense storage
+  return GFO_OK;
 }
 
 // Deferred-mode flush for complex128 storage: G[r, 0:N] += CU V^T over the
