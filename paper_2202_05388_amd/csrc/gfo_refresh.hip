@@ -8,7 +8,9 @@
 // where U_D^T = G0[V, :] by reciprocity of the free-space kernel.
 // Steps: flipped list -> U gather (FP64 table / direct Hankel) -> in-place
 // Gauss-Jordan inverse with partial pivoting -> Z = U M (FP64 MFMA) -> E -> G = G0 + Z U_D^T
-// (FP64 MFMA, G0 added in the epilogue, one rounding to the storage type).
+// (FP64 MFMA, G0 added in the epilogue, one rounding to the storage type) on
+// the monitor rows and the symmetric design block's upper triangle, whose
+// mirror gives the lower triangle when the state keeps it.
 #include "gfo_internal.hpp"
 
 namespace gfo {
