@@ -713,8 +713,13 @@ def time_refresh(problem):
     dt = time.perf_counter() - t0
     N, R = problem.n, problem.rows
     flips = int((job.eps_idx.cpu().numpy() != 0).sum())
-    out = dict(flipped_pixels=flips, ms=dt * 1e3,
-               gemm_tflops=8.0 * R * N * flips / dt / 1e12, status=job.status())
+    kp = (flips + 3) // 4 * 4
+    # FP64 flops of the two products as computed: G = G0 + Z U_D^T on the design
+    # block's upper triangle and the monitor rows, Z = U M (R x kp x kp); the
+    # rate is over the whole refresh (the inverse and the gathers included)
+    product_flops = 8.0 * kp * (N * (N + 1) / 2 + (R - N) * N) + 8.0 * R * kp * kp
+    out = dict(flipped_pixels=flips, ms=dt * 1e3, product_flops=product_flops,
+               product_tflops_over_refresh=product_flops / dt / 1e12, status=job.status())
     del job
     torch.cuda.empty_cache()
     return out
