@@ -191,6 +191,7 @@ __global__ __launch_bounds__(256) void k_gj_step(const double2* __restrict__ S, 
     }
   } else {
     for (int r = threadIdx.x; r < kp; r += blockDim.x) {
+      if (used[r] != 0) continue;
       const double2 v = S[(int64_t)r * kp + c];
       double m = v.x * v.x + v.y * v.y;
       if (!(m >= 0.0)) m = 0.0;   // a NaN row stays a candidate: some row is always chosen
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(256) void k_gj_step(const double2* __restrict__ S, 
     if (blockIdx.x == 0 && !(best > 0.0)) atomicOr(status, GFO_STATUS_SINGULAR);
     if (p >= r0 && p < r0 + kGjRows) {
       piv[c] = p;
-      used[p] = 1;
+      used[p] = c + 1;
     }
   }
   const int j = blockIdx.y * blockDim.x + threadIdx.x;
@@ -251,6 +252,119 @@ __global__ void k_gj_unpermute(const double2* __restrict__ X, double2* __restric
   const int c = (int)(t / kp), d = (int)(t - (int64_t)c * kp);
   M[(int64_t)c * kp + piv[d]] = X[(int64_t)piv[c] * kp + d];
 }
+
+// Blocked form (k > 64): panels of kGjPanel columns.  A panel's columns are
+// copied to a k x kGjPanel buffer and its steps run there (the same pivot rule,
+// the same updates restricted to the panel's columns, two buffers); the
+// panel's transformation T = prod of its steps then reaches every other
+// column j at once: X'[:, j] = X[:, j] + (T[:, P] - I[:, P]) X[P, j], P the
+// panel's pivot rows, whose columns T[:, P] the panel buffer now holds (column
+// c for pivot p_c).  That is a rank-kGjPanel FP64 product on the matrix cores,
+// its pivot rows read from a copy taken before; in the pivot rows the -1
+// cancels the old value.  used[r] = c + 1 records the column r pivoted.
+constexpr int kGjPanel = 32;
+
+__global__ void k_gj_panel_copy(const double2* __restrict__ X, double2* __restrict__ Pn, int kp, int c0,
+                                int qn) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)kp * kGjPanel) return;
+  const int r = (int)(t / kGjPanel), i = (int)(t - (int64_t)r * kGjPanel);
+  if (i < qn) Pn[t] = X[(int64_t)r * kp + c0 + i];
+}
+
+// Panel step c (local column ci = c - c0): S -> D, 8 rows x 32 columns per
+// workgroup; the pivot from the previous step's candidates (part_in) or, for
+// the panel's first column, from a scan of the unused rows.
+__global__ __launch_bounds__(256) void k_gj_panel_step(const double2* __restrict__ S, double2* __restrict__ D,
+                                                       int kp, int c0, int qn, int c,
+                                                       const GjPart* __restrict__ part_in, int n_in,
+                                                       GjPart* __restrict__ part_out, int32_t* __restrict__ piv,
+                                                       int32_t* __restrict__ used, int32_t* __restrict__ status) {
+  const int ci = c - c0;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  if (part_in != nullptr) {
+    for (int q = threadIdx.x; q < n_in; q += blockDim.x) {
+      const GjPart pq = part_in[q];
+      if (pq.m > best || (pq.m == best && pq.row < bi)) {
+        best = pq.m;
+        bi = pq.row;
+      }
+    }
+  } else {
+    for (int r = threadIdx.x; r < kp; r += blockDim.x) {
+      if (used[r] != 0) continue;
+      const double2 v = S[(int64_t)r * kGjPanel + ci];
+      double m = v.x * v.x + v.y * v.y;
+      if (!(m >= 0.0)) m = 0.0;
+      if (m > best) {
+        best = m;
+        bi = r;
+      }
+    }
+  }
+  gj_argmax(best, bi);
+  const int p = bi;
+  const int r0 = blockIdx.x * kGjRows;
+  if (threadIdx.x == 0) {
+    if (blockIdx.x == 0 && !(best > 0.0)) atomicOr(status, GFO_STATUS_SINGULAR);
+    if (p >= r0 && p < r0 + kGjRows) {
+      piv[c] = p;
+      used[p] = c + 1;
+    }
+  }
+  const int r = r0 + (int)(threadIdx.x >> 5), i = (int)(threadIdx.x & 31);
+  double nb = -1.0;
+  int ni = 0x7fffffff;
+  if (r < kp && i < qn) {
+    const double2 d = S[(int64_t)p * kGjPanel + ci];
+    const double n = d.x * d.x + d.y * d.y;
+    const double2 inv = n > 0.0 ? make_double2(d.x / n, -d.y / n) : make_double2(1.0, 0.0);
+    const double2 pc = i == ci ? inv : cmul(S[(int64_t)p * kGjPanel + i], inv);
+    double2 out = pc;
+    if (r != p) {
+      const double2 fr = S[(int64_t)r * kGjPanel + ci];
+      const double2 v = i == ci ? make_double2(0.0, 0.0) : S[(int64_t)r * kGjPanel + i];
+      out = make_double2(v.x - (fr.x * pc.x - fr.y * pc.y), v.y - (fr.x * pc.y + fr.y * pc.x));
+    }
+    D[(int64_t)r * kGjPanel + i] = out;
+    if (i == ci + 1 && r != p && used[r] == 0) {
+      double m = out.x * out.x + out.y * out.y;
+      if (!(m >= 0.0)) m = 0.0;
+      nb = m;
+      ni = r;
+    }
+  }
+  gj_argmax(nb, ni);
+  if (threadIdx.x == 0) part_out[blockIdx.x] = GjPart{nb, ni, 0};
+}
+
+// The pivot rows of the panel before it: Prow[i][j] = X[p_(c0 + i)][j].
+__global__ void k_gj_pivot_rows(const double2* __restrict__ X, double2* __restrict__ Prow,
+                                const int32_t* __restrict__ piv, int kp, int c0, int qn) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)qn * kp) return;
+  const int i = (int)(t / kp), j = (int)(t - (int64_t)i * kp);
+  Prow[t] = X[(int64_t)piv[c0 + i] * kp + j];
+}
+
+// Epilogue of the panel's product v = (T[:, P] X[P, :])[m][n]: the panel's
+// columns take T[:, P]; a pivot row of the panel takes v; every other entry adds v.
+struct EpiGJ {
+  double2* X;
+  const double2* Pn;
+  const int32_t* used;
+  int kp, c0, qn;
+  __device__ void operator()(int m, int n, double2 v) const {
+    double2* x = X + (int64_t)m * kp + n;
+    if (n >= c0 && n < c0 + qn) {
+      *x = Pn[(int64_t)m * kGjPanel + (n - c0)];
+    } else {
+      const int u = used[m];
+      *x = (u > c0 && u <= c0 + qn) ? v : cadd(*x, v);
+    }
+  }
+};
 
 // ------------------------------------------------------------------ FP64 MFMA complex GEMM
 // C(m, n) = sum_k A(m, k) B(k, n), complex FP64, A row-major (lda).
@@ -547,15 +661,43 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, int32_t k
     hipLaunchKernelGGL(k_rf_build_core, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, g,
                        (const uint8_t*)st->eps_idx, (const int32_t*)V, (const double2*)U, k, kp, W[0],
                        used);
-    const dim3 gj_grid((unsigned)nb, (unsigned)((kp + 255) / 256));
-    for (int c = 0; c < kp; ++c)
-      hipLaunchKernelGGL(k_gj_step, gj_grid, dim3(256), 0, s, (const double2*)W[c & 1],
-                         W[(c + 1) & 1], kp, c, c == 0 ? (const GjPart*)nullptr : (const GjPart*)part[(c + 1) & 1],
-                         nb, part[c & 1], piv, used, st->status);
-    // after kp steps the in-place result is in W[kp & 1]; M goes to the other
-    M = W[(kp + 1) & 1];
-    hipLaunchKernelGGL(k_gj_unpermute, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s,
-                       (const double2*)W[kp & 1], M, (const int32_t*)piv, kp);
+    const double2* X = nullptr;   // the in-place result
+    if (kp > 2 * kGjPanel && g.R >= 3 * kGjPanel) {
+      // blocked: the panel buffers and the pivot rows' copy in Z's workspace
+      // (R x kp entries, free until Z = U M), X in place in W[0]
+      double2* Pn[2] = {Z, Z + (int64_t)kp * kGjPanel};
+      double2* Prow = Z + 2 * (int64_t)kp * kGjPanel;
+      const unsigned np = (unsigned)(((int64_t)kp * kGjPanel + 255) / 256);
+      for (int c0 = 0; c0 < kp; c0 += kGjPanel) {
+        const int qn = min(kGjPanel, kp - c0);
+        hipLaunchKernelGGL(k_gj_panel_copy, dim3(np), dim3(256), 0, s, (const double2*)W[0], Pn[0], kp, c0,
+                           qn);
+        for (int l = 0; l < qn; ++l)
+          hipLaunchKernelGGL(k_gj_panel_step, dim3((unsigned)nb), dim3(256), 0, s, (const double2*)Pn[l & 1],
+                             Pn[(l + 1) & 1], kp, c0, qn, c0 + l,
+                             l == 0 ? (const GjPart*)nullptr : (const GjPart*)part[(l + 1) & 1], nb,
+                             part[l & 1], piv, used, st->status);
+        hipLaunchKernelGGL(k_gj_pivot_rows, dim3((unsigned)(((int64_t)qn * kp + 255) / 256)), dim3(256), 0, s,
+                           (const double2*)W[0], Prow, (const int32_t*)piv, kp, c0, qn);
+        EpiGJ eg{W[0], Pn[qn & 1], used, kp, c0, qn};
+        hipLaunchKernelGGL((k_zgemm_f64<false, false, EpiGJ>), dim3((kp + 63) / 64, (kp + 63) / 64), dim3(256),
+                           0, s, kp, kp, qn, (const double2*)Pn[qn & 1], (int64_t)kGjPanel,
+                           (const double2*)Prow, (int64_t)kp, (const int32_t*)nullptr, eg, 0);
+      }
+      X = W[0];
+      M = W[1];
+    } else {
+      const dim3 gj_grid((unsigned)nb, (unsigned)((kp + 255) / 256));
+      for (int c = 0; c < kp; ++c)
+        hipLaunchKernelGGL(k_gj_step, gj_grid, dim3(256), 0, s, (const double2*)W[c & 1],
+                           W[(c + 1) & 1], kp, c, c == 0 ? (const GjPart*)nullptr : (const GjPart*)part[(c + 1) & 1],
+                           nb, part[c & 1], piv, used, st->status);
+      // after kp steps the in-place result is in W[kp & 1]; M goes to the other
+      X = W[kp & 1];
+      M = W[(kp + 1) & 1];
+    }
+    hipLaunchKernelGGL(k_gj_unpermute, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, s, X, M,
+                       (const int32_t*)piv, kp);
     // Z = U M
     EpiStoreZ ez{Z, kp};
     hipLaunchKernelGGL((k_zgemm_f64_t128<false, false, EpiStoreZ>),
