@@ -184,7 +184,7 @@ struct Layout {
   size_t rf_A;      // 2 kp^2 double2: two kp x kp buffers of the in-place Gauss-Jordan inverse
                     // of diag(1/alpha) - G0[V,V], then M
   size_t rf_piv;    // 16 kp + 64 bytes: the steps' pivot candidates, the pivots, the used rows
-  size_t rf_Z;      // R x kp double2: G0[:, V] M
+  size_t rf_Z;      // R x kp double2: G0[:, V] M; before it, the blocked inverse's panel buffers
   size_t rf_x;      // kp double2: M Einc[V]
   // split-product flush (complex64 storage only): the pending terms as BF16
   // parts, kSplitUnits units of 16 bytes per row (R rows of CU) and per column
