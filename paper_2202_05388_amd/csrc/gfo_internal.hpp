@@ -594,4 +594,40 @@ const char* flush_variant_name(int idx);
 int flush_set_variant(int idx);
 int flush_get_variant();
 
+// Updates of the design block's upper triangle alone launch only the workgroups
+// that write something (a workgroup that returned at once would still take a
+// dispatch slot).  Row groups of H rows, column groups of W columns (H and W
+// powers of two): a row group y below nskip = N / H (wholly in design rows)
+// keeps the column groups [lo(y), ncg), lo(y) = floor(y H / W), the groups that
+// reach column y H or beyond; later row groups keep every column group.  With
+// nskip = 0 this is the plain row-major mapping.
+__host__ __device__ inline int64_t ut_lo_sum(int64_t y, int H, int W) {   // sum of lo(i), i < y
+  if (H >= W) return (int64_t)(H / W) * y * (y - 1) / 2;
+  const int64_t d = W / H, q = y / d;
+  return d * q * (q - 1) / 2 + q * (y - q * d);
+}
+__host__ __device__ inline int64_t ut_first(int64_t y, int ncg, int H, int W) {  // launch index of row group y
+  return y * ncg - ut_lo_sum(y, H, W);
+}
+__host__ inline int64_t ut_group_count(int nrg, int ncg, int nskip, int H, int W) {
+  return ut_first(nskip, ncg, H, W) + (int64_t)(nrg - nskip) * ncg;
+}
+__device__ __forceinline__ void ut_group(int64_t t, int ncg, int nskip, int H, int W, int& rg, int& cg) {
+  const int64_t t1 = ut_first(nskip, ncg, H, W);
+  if (t >= t1) {
+    t -= t1;
+    rg = nskip + (int)(t / ncg);
+    cg = (int)(t % ncg);
+    return;
+  }
+  int lo = 0, hi = nskip - 1;   // the last row group whose first index is <= t
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ut_first(mid, ncg, H, W) <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  rg = lo;
+  cg = (int)((int64_t)lo * H / W + (t - ut_first(lo, ncg, H, W)));
+}
+
 }  // namespace gfo

@@ -53,8 +53,9 @@ __device__ __forceinline__ void k_rank1_tile(int R, int64_t ld, int ct, int64_t 
 // Tiles are visited grid-stride (tile = blockIdx.x, blockIdx.x + gridDim.x, ...), so
 // the launch can stay below the 2^32 work-item limit of one dispatch on any shape.
 // upper: only the upper triangle of the design block is kept current (the
-// block is symmetric; readers take (min, max)), so tiles of design rows that
-// lie wholly below its diagonal are skipped; monitor rows are always updated.
+// block is symmetric; readers take (min, max)), so the tiles of design rows that
+// lie wholly below its diagonal are left out of the enumeration (ntiles counts
+// the others); monitor rows are always updated.
 template <typename T, int RB, int U, int CPT, bool NT, bool PIPE>
 __global__ __launch_bounds__(kK1Threads) void k_rank1(int R, int64_t ld, int ncoltiles,
                                                       int64_t ntiles, int N, int upper,
@@ -65,9 +66,8 @@ __global__ __launch_bounds__(kK1Threads) void k_rank1(int R, int64_t ld, int nco
   constexpr int64_t cols = (int64_t)kK1Threads * Vec16<T>::n * CPT;
   if (snap->j < 0) return;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int ct = (int)(tile % ncoltiles);
-    const int64_t rt = tile / ncoltiles;
-    if (upper && rt * RB + RB <= N && rt * RB > ct * cols + cols - 1) continue;
+    int rt, ct;
+    ut_group(tile, ncoltiles, upper ? N / RB : 0, RB, (int)cols, rt, ct);
     k_rank1_tile<T, RB, U, CPT, NT, PIPE>(R, ld, ct, rt, cu, v, G);
   }
 }
@@ -158,7 +158,8 @@ static void launch_k1(int R, int64_t ld, int N, int upper, const Snap* snap, con
   constexpr int cols = kK1Threads * VN * CPT;
   const int ncol = (int)((ld + cols - 1) / cols);
   const int64_t nrow = (R + RB - 1) / RB;
-  const int64_t ntiles = (int64_t)ncol * nrow;
+  static_assert(cols % RB == 0 || RB % cols == 0, "tile rows and columns must be powers of two");
+  const int64_t ntiles = ut_group_count((int)nrow, ncol, upper ? N / RB : 0, RB, cols);
   const int64_t nblk = ntiles < MAXB ? ntiles : MAXB;
   hipLaunchKernelGGL((k_rank1<T, RB, U, CPT, NT, PIPE>), dim3((unsigned)nblk), dim3(kK1Threads), 0,
                      s, R, ld, ncol, ntiles, N, upper, snap, (const T*)cu, (const T*)v, (T*)G);

@@ -313,41 +313,6 @@ __device__ __forceinline__ bool rk_below_diagonal(int r0, int nr, int64_t c_end,
   return skip_below > 0 && r0 + nr <= skip_below && c_end <= r0;
 }
 
-// Only the workgroups that update something are launched (a workgroup that
-// returned at once would still take a dispatch slot).  Row groups of H rows,
-// column groups of W columns (H and W powers of two): a row group y below
-// nskip = skip_below / H keeps the column groups [lo(y), ncg), lo(y) =
-// floor(y H / W) (exactly those rk_below_diagonal does not leave out), later
-// row groups every column group.  With nskip = 0 this is the plain
-// row-major mapping.
-__host__ __device__ inline int64_t rk_lo_sum(int64_t y, int H, int W) {   // sum of lo(i), i < y
-  if (H >= W) return (int64_t)(H / W) * y * (y - 1) / 2;
-  const int64_t d = W / H, q = y / d;
-  return d * q * (q - 1) / 2 + q * (y - q * d);
-}
-__host__ __device__ inline int64_t rk_first(int64_t y, int ncg, int H, int W) {  // launch index of row group y
-  return y * ncg - rk_lo_sum(y, H, W);
-}
-__host__ inline int64_t rk_group_count(int nrg, int ncg, int nskip, int H, int W) {
-  return rk_first(nskip, ncg, H, W) + (int64_t)(nrg - nskip) * ncg;
-}
-__device__ __forceinline__ void rk_group(int64_t t, int ncg, int nskip, int H, int W, int& rg, int& cg) {
-  const int64_t t1 = rk_first(nskip, ncg, H, W);
-  if (t >= t1) {
-    t -= t1;
-    rg = nskip + (int)(t / ncg);
-    cg = (int)(t % ncg);
-    return;
-  }
-  int lo = 0, hi = nskip - 1;   // the last row group whose first index is <= t
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (rk_first(mid, ncg, H, W) <= t) lo = mid;
-    else hi = mid - 1;
-  }
-  rg = lo;
-  cg = (int)((int64_t)lo * H / W + (t - rk_first(lo, ncg, H, W)));
-}
 
 // Workgroup: 4 waves over a 64 x 64 complex tile per iteration (wave w: column
 // tile w & 1, row tile w >> 1), RBLK row blocks of 64 rows per workgroup.  The
@@ -375,7 +340,7 @@ __global__ __launch_bounds__(256) void k_rk_mfma(int R, int64_t ld, int skip_bel
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int ncg = (int)(ld / 64);
   int cg, rg;
-  rk_group(blockIdx.x, ncg, skip_below / (64 * kRkRowBlocks), 64 * kRkRowBlocks, 64, rg, cg);
+  ut_group(blockIdx.x, ncg, skip_below / (64 * kRkRowBlocks), 64 * kRkRowBlocks, 64, rg, cg);
   const int q = cg * 64 + (w & 1) * 32 + (lane & 31);
   const int h = lane >> 5;
   // B fragments for this lane's column
@@ -490,7 +455,7 @@ __global__ __launch_bounds__(256, (!BF16 && TM == 1 && KP == 16 && RB <= 4) ? 3 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, h = lane >> 5;
   const int ncg = (int)((ld + 127) / 128);
   int cg, rg;
-  rk_group(blockIdx.x, ncg, skip_below / (RB * BR), RB * BR, 128, rg, cg);
+  ut_group(blockIdx.x, ncg, skip_below / (RB * BR), RB * BR, 128, rg, cg);
   const int64_t c0 = (int64_t)cg * 128;
   const int rbase = rg * RB * BR;
   const int64_t q = c0 + 32 * w + (lane & 31);
@@ -648,7 +613,7 @@ static void launch_rk_stream(const Geo& g, RkHdr* hdr, const float* Af, const fl
   const int ncg = (int)((g.ld + 127) / 128);
   const int H = 32 * TM * RB, nrg = (g.R + H - 1) / H;
   const int skip = g.upper ? g.N : 0;
-  const dim3 grid((unsigned)rk_group_count(nrg, ncg, skip / H, H, 128));
+  const dim3 grid((unsigned)ut_group_count(nrg, ncg, skip / H, H, 128));
   hipLaunchKernelGGL((k_rk_stream<16, BF16, RB, LDSEPI, TM>), grid, dim3(256), 0, s, g.R, g.ld, skip,
                      &hdr->s, &hdr->kp, Af, Bf, Abf, Bbf, G);
   hipLaunchKernelGGL((k_rk_stream<32, BF16, RB, LDSEPI, TM>), grid, dim3(256), 0, s, g.R, g.ld, skip,
@@ -715,7 +680,7 @@ hipError_t launch_rank_k(const Geo& g, gfo_state* st, const Layout& L, const gfo
       const int ncg = (int)(g.ld / 64);
       const int H = 64 * kRkRowBlocks, nrg = (g.R + H - 1) / H;
       const int skip = g.upper ? g.N : 0;
-      const dim3 grid((unsigned)rk_group_count(nrg, ncg, skip / H, H, 64));
+      const dim3 grid((unsigned)ut_group_count(nrg, ncg, skip / H, H, 64));
       if (bf) {
         hipLaunchKernelGGL((k_rk_mfma<16, true>), grid, dim3(256), 0, s, g.R, g.ld, skip, &hdr->s,
                            &hdr->kp, cAf, cBf, cAbf, cBbf, G);
