@@ -408,37 +408,10 @@ struct EpiAddG {
   }
 };
 
-// Products that leave out the design block's tiles below the diagonal launch
-// only the tiles they compute: a workgroup that returned at once would still
-// wait for a compute unit's slot, and the in-order dispatch behind it (half the
-// grid) cost a fifth of the product's time.  Tile rows by < nskip (wholly in
-// rows < skip_below) hold the columns [by, nbx), later rows every column; launch
-// index t -> (by, bx), the row from the closed form of the cumulative counts,
-// corrected exactly.
-__host__ __device__ inline int64_t upper_tile_count(int nby, int nbx, int nskip) {
-  return (int64_t)nskip * nbx - (int64_t)nskip * (nskip - 1) / 2 + (int64_t)(nby - nskip) * nbx;
-}
-__device__ inline void upper_tile(int64_t t, int nbx, int nskip, int& by, int& bx) {
-  const int64_t t1 = (int64_t)nskip * nbx - (int64_t)nskip * (nskip - 1) / 2;
-  if (t >= t1) {
-    t -= t1;
-    by = nskip + (int)(t / nbx);
-    bx = (int)(t % nbx);
-    return;
-  }
-  auto first = [&](int64_t y) { return y * nbx - y * (y - 1) / 2; };   // index of row y's first tile
-  const double b = 2.0 * nbx + 1.0;
-  int r = (int)((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
-  r = r < 0 ? 0 : (r > nskip - 1 ? nskip - 1 : r);
-  while (r > 0 && first(r) > t) --r;
-  while (r + 1 < nskip && first(r + 1) <= t) ++r;
-  by = r;
-  bx = r + (int)(t - first(r));
-}
-
 // A(m, k) = A[m * lda + k], or A[k * lda + m] when AT; K is clamped to *kdev when given.
 // skip_below > 0: tiles wholly below the diagonal within rows < skip_below are
-// not computed (deferred mode keeps the design block's upper triangle only).
+// not computed (deferred mode keeps the design block's upper triangle only);
+// the launch is then a 1-D grid of the other tiles only (ut_group).
 // Four waves per SIMD requested: the accumulators then live in ordinary vector
 // registers and every instantiation fits 4-5 waves without spilling (left to
 // itself the compiler put them in accumulation registers at 2-3 waves, and the
@@ -449,7 +422,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                                    int64_t ldb, const int32_t* __restrict__ kdev,
                                                    Epi epi, int skip_below) {
   int by = (int)blockIdx.y, bx = (int)blockIdx.x;
-  if (skip_below > 0) upper_tile(blockIdx.x, (N + 63) / 64, skip_below / 64, by, bx);
+  if (skip_below > 0) ut_group(blockIdx.x, (N + 63) / 64, skip_below / 64, 64, 64, by, bx);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = by * 64 + (w >> 1) * 32;
   const int n0 = bx * 64 + (w & 1) * 32;
@@ -528,7 +501,7 @@ __global__ __launch_bounds__(512) void k_zgemm_f64_t128(int M, int N, int K, con
                                                         int64_t ldb, const int32_t* __restrict__ kdev,
                                                         Epi epi, int skip_below) {
   int by = (int)blockIdx.y, bx = (int)blockIdx.x;
-  if (skip_below > 0) upper_tile(blockIdx.x, (N + kZgT - 1) / kZgT, skip_below / kZgT, by, bx);
+  if (skip_below > 0) ut_group(blockIdx.x, (N + kZgT - 1) / kZgT, skip_below / kZgT, kZgT, kZgT, by, bx);
   __shared__ double2 As[2][kZgKC][kZgPitch], Bs[2][kZgKC][kZgPitch];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int tm0 = by * kZgT, tn0 = bx * kZgT;
@@ -746,7 +719,7 @@ static int refresh_typed(const Geo& g, gfo_state* st, const Layout& L, int32_t k
   EpiG0<T> eg{g, table, mon, (T*)st->G, (double2*)st->diag64};
   const int ty = (g.R + kZgT - 1) / kZgT, tx = (g.N + kZgT - 1) / kZgT;
   hipLaunchKernelGGL((k_zgemm_f64_t128<false, true, EpiG0<T>>),
-                     dim3((unsigned)upper_tile_count(ty, tx, g.N / kZgT)), dim3(512), 0, s, g.R, g.N, kp,
+                     dim3((unsigned)ut_group_count(ty, tx, g.N / kZgT, kZgT, kZgT)), dim3(512), 0, s, g.R, g.N, kp,
                      (const double2*)Z, (int64_t)kp,
                      (const double2*)U, (int64_t)kp, (const int32_t*)nullptr, eg, g.N);
   if (note_hip(hipGetLastError()) != hipSuccess) return GFO_EHIP;
@@ -765,7 +738,7 @@ hipError_t launch_zgemm_update_f64(const Geo& g, const int32_t* count, const dou
   // zeros)
   EpiAddG ep{g, G};
   const int ty = (g.R + 63) / 64, tx = (g.N + 63) / 64;
-  hipLaunchKernelGGL((k_zgemm_f64<true, false, EpiAddG>), dim3((unsigned)upper_tile_count(ty, tx, g.N / 64)),
+  hipLaunchKernelGGL((k_zgemm_f64<true, false, EpiAddG>), dim3((unsigned)ut_group_count(ty, tx, g.N / 64, 64, 64)),
                      dim3(256), 0, s, g.R, g.N, GFO_MAX_DELAY, CU, (int64_t)g.R, V, g.ld, count, ep, g.N);
   return note_hip(hipGetLastError());
 }
